@@ -1,0 +1,526 @@
+/*
+ * compass_oracle.c -- plain, slow, obviously correct CPU oracle for the
+ * online sketch-based query optimisation hot path (Izenov, Datta, Rusu,
+ * Shin, "Online Sketch-based Query Optimization", arXiv 2102.02440).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no code, header, table or constant with
+ * the HIP library: every definition below is written out again from the
+ * paper and from the readings listed at the top of each function.
+ *
+ * Arithmetic is exact: hash polynomials use unsigned __int128 products
+ * reduced with the % operator, counters are int64, and multi-way estimates
+ * are accumulated in 128-bit two's complement that wraps modulo 2^128
+ * (unsigned __int128, so wrap-around is defined behaviour in C).
+ *
+ * Build: gcc -O2 -fPIC -shared -fopenmp -o liboracle.so compass_oracle.c
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+typedef __int128 i128;
+
+/* The prime field of the hash families: p = 2^61 - 1. */
+static const uint64_t ORACLE_P = 2305843009213693951ULL;
+
+/* ------------------------------------------------------------------ */
+/* Hash families (Section 4.1: xi is a 4-wise independent +-1 family;  */
+/* Section 4.2: each Fast-AGMS row has one bucket hash h and one xi).  */
+/* The paper names no concrete family.  Reading used here: Carter-    */
+/* Wegman polynomials over GF(p), p = 2^61-1.                          */
+/*   x  = ((uint64)(int64)key) mod p                                   */
+/*   v  = a0 + a1 x + a2 x^2 + a3 x^3  (mod p)   -> xi = +1 if v even  */
+/*   g  = b0 + b1 x                   (mod p)   -> h  = g mod w        */
+/* seeds = {a0, a1, a2, a3, b0, b1}, each in [0, p).                   */
+/* ------------------------------------------------------------------ */
+
+static uint64_t field_of_key(int64_t key)
+{
+    return ((uint64_t)key) % ORACLE_P;
+}
+
+static uint64_t mulmod(uint64_t a, uint64_t b)
+{
+    return (uint64_t)(((u128)a * (u128)b) % ORACLE_P);
+}
+
+static uint64_t addmod(uint64_t a, uint64_t b)
+{
+    return (uint64_t)(((u128)a + (u128)b) % ORACLE_P);
+}
+
+/* Evaluates the two polynomials term by term (no Horner, no lazy
+ * reduction) so that the code reads like the definition. */
+void oracle_hash(const uint64_t *seeds, int64_t key, int64_t w,
+                 int64_t *bucket, int32_t *sign)
+{
+    uint64_t x = field_of_key(key);
+    uint64_t x2 = mulmod(x, x);
+    uint64_t x3 = mulmod(x2, x);
+    uint64_t v = seeds[0] % ORACLE_P;
+    v = addmod(v, mulmod(seeds[1], x));
+    v = addmod(v, mulmod(seeds[2], x2));
+    v = addmod(v, mulmod(seeds[3], x3));
+    uint64_t g = addmod(seeds[4] % ORACLE_P, mulmod(seeds[5], x));
+    *sign = (v & 1ULL) ? -1 : +1;
+    *bucket = (int64_t)(g % (uint64_t)w);
+}
+
+/* ------------------------------------------------------------------ */
+/* Fast-AGMS sketch of a multiset of keys (Section 4.2 counter          */
+/* definition: counter j of a row sums xi over the tuples whose key     */
+/* hashes to j).  The caller passes only the keys of tuples that        */
+/* satisfy the table's selection predicates (Section 3, push-down).     */
+/* counters: d rows x w buckets, row-major, int64, ADDED to.            */
+/* ------------------------------------------------------------------ */
+void oracle_sketch(const int64_t *keys, int64_t n, const uint64_t *seeds,
+                   int32_t d, int64_t w, int64_t *counters)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        for (int32_t i = 0; i < d; ++i) {
+            int64_t b;
+            int32_t s;
+            oracle_hash(seeds + 6 * i, keys[r], w, &b, &s);
+            counters[(int64_t)i * w + b] += s;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Join graph and sub-plans.                                           */
+/*   edge e joins table eu[e] and table ev[e]; edge id = index e.       */
+/*   sk[2e+0] = sketch row-set of table eu[e] on edge e (d x w int64)   */
+/*   sk[2e+1] = sketch row-set of table ev[e] on edge e                 */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_tables, n_edges, d;
+    int64_t w;
+    const int32_t *eu, *ev;
+    const int64_t *const *sk;
+} graph_t;
+
+static const int64_t *sketch_row(const graph_t *g, int32_t e, int32_t t,
+                                 int32_t row)
+{
+    int side = (g->eu[e] == t) ? 0 : 1;
+    return g->sk[2 * e + side] + (int64_t)row * g->w;
+}
+
+static int64_t abs64(int64_t v) { return v < 0 ? -v : v; }
+
+/* Sketch merging (Section 5.2): among the buckets a table's sketches
+ * pick for the current assignment, the one with the smallest absolute
+ * value wins; on equal magnitude the first sketch wins (the "<=" of the
+ * merge rule), and "first" is read as the lowest edge id when more than
+ * two sketches are merged.  Returns the winning counter value. */
+static int64_t merged_value(const graph_t *g, int32_t t, const int32_t *inc,
+                            int32_t n_inc, const int64_t *assign, int32_t row)
+{
+    /* inc[] is in increasing edge-id order */
+    int64_t best = sketch_row(g, inc[0], t, row)[assign[inc[0]]];
+    for (int32_t k = 1; k < n_inc; ++k) {
+        int64_t v = sketch_row(g, inc[k], t, row)[assign[inc[k]]];
+        if (abs64(v) < abs64(best)) best = v;
+    }
+    return best;
+}
+
+/* Collects the tables and induced edges of sub-plan `mask`. */
+static int collect(const graph_t *g, uint64_t mask, int32_t *tabs,
+                   int32_t *nt, int32_t *edges, int32_t *ne)
+{
+    *nt = 0;
+    *ne = 0;
+    for (int32_t t = 0; t < g->n_tables; ++t)
+        if (mask >> t & 1ULL) tabs[(*nt)++] = t;
+    for (int32_t e = 0; e < g->n_edges; ++e)
+        if ((mask >> g->eu[e] & 1ULL) && (mask >> g->ev[e] & 1ULL))
+            edges[(*ne)++] = e;
+    return 0;
+}
+
+/* Connectivity of the sub-plan over its induced edges (cross products
+ * are excluded from enumeration, Section 3 "Plan enumeration"). */
+static int connected(const graph_t *g, uint64_t mask)
+{
+    uint64_t seen = mask & (~mask + 1ULL); /* lowest table */
+    for (;;) {
+        uint64_t grow = seen;
+        for (int32_t e = 0; e < g->n_edges; ++e) {
+            uint64_t bu = 1ULL << g->eu[e], bv = 1ULL << g->ev[e];
+            if (!(mask & bu) || !(mask & bv)) continue;
+            if (seen & (bu | bv)) grow |= bu | bv;
+        }
+        if (grow == seen) break;
+        seen = grow;
+    }
+    return seen == mask;
+}
+
+/* ------------------------------------------------------------------ */
+/* Estimate, literal definition.  Row i of a sub-plan with tables C and */
+/* induced edges E_C:                                                   */
+/*   X_i = sum over all bucket assignments iota in [0,w)^{E_C} of       */
+/*         prod over t in C of merged_t(iota)                           */
+/* which is the contraction of Section 5.1 (3-table case written out    */
+/* there) with each table's merged sketch (Section 5.2) substituted,    */
+/* applied iteratively to any number of joins.  A single table's        */
+/* estimate is its exact filtered cardinality (Section 3).              */
+/* Cost w^{|E_C|}: tiny w only.                                         */
+/* ------------------------------------------------------------------ */
+static u128 row_estimate_literal(const graph_t *g, const int32_t *tabs,
+                                 int32_t nt, const int32_t *edges, int32_t ne,
+                                 int32_t row)
+{
+    int64_t assign[64];
+    int32_t inc[64][64];
+    int32_t n_inc[64];
+    for (int32_t a = 0; a < nt; ++a) {
+        n_inc[a] = 0;
+        for (int32_t k = 0; k < ne; ++k) {
+            int32_t e = edges[k];
+            if (g->eu[e] == tabs[a] || g->ev[e] == tabs[a])
+                inc[a][n_inc[a]++] = e;
+        }
+    }
+    for (int32_t k = 0; k < ne; ++k) assign[edges[k]] = 0;
+    u128 total = 0;
+    for (;;) {
+        u128 prod = 1;
+        for (int32_t a = 0; a < nt; ++a)
+            prod *= (u128)(i128)merged_value(g, tabs[a], inc[a], n_inc[a],
+                                             assign, row);
+        total += prod;
+        int32_t k = 0;
+        while (k < ne) {
+            if (++assign[edges[k]] < g->w) break;
+            assign[edges[k]] = 0;
+            ++k;
+        }
+        if (k == ne) break;
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------------ */
+/* Estimate, exact fast evaluation (our re-association of the literal   */
+/* sum; pinned against it by brute force in the tests).                 */
+/*                                                                      */
+/* Spanning tree by BFS from the lowest table, edges scanned in id      */
+/* order; the remaining induced edges form the cut set K.  For every    */
+/* assignment J of the cut edges the tree is contracted bottom-up, and  */
+/* the results are summed over J (w^{|K|} assignments).                 */
+/*                                                                      */
+/* A node t sees elements: its parent-edge buckets (query points), its  */
+/* child-edge buckets (each weighted by the child's message mu_c), and  */
+/* one fixed element per cut edge at t (value s_{t,f}[J_f]).  Elements  */
+/* are ordered by kappa = (|value|, edge id).  The merged value of t is */
+/* the element of smallest kappa, so with A_c(k) = sum of mu_c over     */
+/* child-c elements of kappa > k (fixed elements: 1 if kappa > k else   */
+/* 0), the message for parent bucket j is                               */
+/*   M(j) = x_j * prod_c A_c(kappa_j) + G(kappa_j),                     */
+/*   G(k) = sum over child/fixed elements z with kappa_z < k of         */
+/*          value_z * mu_z * prod_{c != c(z)} A_c(kappa_z),             */
+/* and the root's contribution is G(+inf).                              */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t absv;   /* |value| */
+    int32_t edge;   /* edge id */
+    int32_t kind;   /* 0 parent, 1 child, 2 fixed */
+    int32_t slot;   /* child slot or fixed slot */
+    int64_t j;      /* bucket index */
+    int64_t value;
+} elem_t;
+
+static int elem_cmp(const void *pa, const void *pb)
+{
+    const elem_t *a = (const elem_t *)pa, *b = (const elem_t *)pb;
+    if (a->absv != b->absv) return a->absv < b->absv ? -1 : 1;
+    if (a->edge != b->edge) return a->edge < b->edge ? -1 : 1;
+    if (a->j != b->j) return a->j < b->j ? -1 : 1;
+    return 0;
+}
+
+typedef struct {
+    int32_t table;
+    int32_t parent_edge;     /* -1 at the root */
+    int32_t parent_node;
+    int32_t n_child;
+    int32_t child_edge[64];
+    int32_t child_node[64];
+    int32_t n_fixed;
+    int32_t fixed_edge[64];
+    /* elements that do not depend on the cut assignment, sorted */
+    elem_t *base;
+    int64_t n_base;
+    u128 *msg;               /* message to the parent, length w */
+} tnode_t;
+
+static u128 contract_tree(const graph_t *g, tnode_t *nodes, int32_t nn,
+                          const int32_t *order, const int64_t *cut_assign,
+                          int32_t row)
+{
+    u128 root_value = 0;
+    for (int32_t oi = nn - 1; oi >= 0; --oi) {
+        tnode_t *nd = &nodes[order[oi]];
+        int32_t t = nd->table;
+        /* fixed elements for this assignment, sorted by kappa */
+        elem_t fx[64];
+        for (int32_t f = 0; f < nd->n_fixed; ++f) {
+            int32_t e = nd->fixed_edge[f];
+            int64_t v = sketch_row(g, e, t, row)[cut_assign[e]];
+            fx[f].absv = abs64(v);
+            fx[f].edge = e;
+            fx[f].kind = 2;
+            fx[f].slot = f;
+            fx[f].j = cut_assign[e];
+            fx[f].value = v;
+        }
+        qsort(fx, (size_t)nd->n_fixed, sizeof(elem_t), elem_cmp);
+        /* A values start at the full sums */
+        u128 A[128];
+        for (int32_t c = 0; c < nd->n_child; ++c) {
+            u128 s = 0;
+            const u128 *mu = nodes[nd->child_node[c]].msg;
+            for (int64_t j = 0; j < g->w; ++j) s += mu[j];
+            A[c] = s;
+        }
+        for (int32_t f = 0; f < nd->n_fixed; ++f) A[nd->n_child + f] = 1;
+        int32_t nA = nd->n_child + nd->n_fixed;
+        u128 G = 0;
+        int64_t bi = 0;
+        int32_t fi = 0;
+        while (bi < nd->n_base || fi < nd->n_fixed) {
+            const elem_t *z;
+            if (fi < nd->n_fixed &&
+                (bi >= nd->n_base || elem_cmp(&fx[fi], &nd->base[bi]) < 0))
+                z = &fx[fi++];
+            else
+                z = &nd->base[bi++];
+            u128 val = (u128)(i128)z->value;
+            if (z->kind == 0) {
+                u128 p = val;
+                for (int32_t a = 0; a < nA; ++a) p *= A[a];
+                nd->msg[z->j] = p + G;
+            } else {
+                int32_t own = (z->kind == 1) ? z->slot : nd->n_child + z->slot;
+                u128 mu = (z->kind == 1) ? nodes[nd->child_node[z->slot]].msg[z->j]
+                                         : (u128)1;
+                u128 term = val * mu;
+                for (int32_t a = 0; a < nA; ++a)
+                    if (a != own) term *= A[a];
+                G += term;
+                A[own] -= mu;
+            }
+        }
+        if (nd->parent_edge < 0) root_value = G;
+    }
+    return root_value;
+}
+
+static u128 row_estimate_fast(const graph_t *g, const int32_t *tabs,
+                              int32_t nt, const int32_t *edges, int32_t ne,
+                              int32_t row)
+{
+    tnode_t *nodes = (tnode_t *)calloc((size_t)nt, sizeof(tnode_t));
+    int32_t node_of[64];
+    for (int32_t t = 0; t < 64; ++t) node_of[t] = -1;
+    int32_t order[64];
+    int32_t n_order = 0;
+    int32_t is_tree_edge[64];
+    int32_t cut[64];
+    int32_t n_cut = 0;
+    memset(is_tree_edge, 0, sizeof(is_tree_edge));
+    /* BFS spanning tree */
+    nodes[0].table = tabs[0];
+    nodes[0].parent_edge = -1;
+    nodes[0].parent_node = -1;
+    node_of[tabs[0]] = 0;
+    order[n_order++] = 0;
+    int32_t n_nodes = 1;
+    for (int32_t head = 0; head < n_order; ++head) {
+        int32_t cur = order[head];
+        int32_t t = nodes[cur].table;
+        for (int32_t k = 0; k < ne; ++k) {
+            int32_t e = edges[k];
+            int32_t other;
+            if (g->eu[e] == t) other = g->ev[e];
+            else if (g->ev[e] == t) other = g->eu[e];
+            else continue;
+            if (node_of[other] >= 0) continue;
+            int32_t nn = n_nodes++;
+            nodes[nn].table = other;
+            nodes[nn].parent_edge = e;
+            nodes[nn].parent_node = cur;
+            node_of[other] = nn;
+            is_tree_edge[k] = 1;
+            nodes[cur].child_edge[nodes[cur].n_child] = e;
+            nodes[cur].child_node[nodes[cur].n_child++] = nn;
+            order[n_order++] = nn;
+        }
+    }
+    for (int32_t k = 0; k < ne; ++k) {
+        if (is_tree_edge[k]) continue;
+        int32_t e = edges[k];
+        cut[n_cut++] = e;
+        tnode_t *a = &nodes[node_of[g->eu[e]]];
+        tnode_t *b = &nodes[node_of[g->ev[e]]];
+        a->fixed_edge[a->n_fixed++] = e;
+        b->fixed_edge[b->n_fixed++] = e;
+    }
+    /* assignment-independent elements, sorted once */
+    for (int32_t a = 0; a < n_nodes; ++a) {
+        tnode_t *nd = &nodes[a];
+        int32_t groups = nd->n_child + (nd->parent_edge >= 0 ? 1 : 0);
+        nd->base = (elem_t *)malloc(sizeof(elem_t) * (size_t)(groups * g->w + 1));
+        nd->msg = (u128 *)calloc((size_t)g->w, sizeof(u128));
+        nd->n_base = 0;
+        for (int32_t gi = 0; gi < groups; ++gi) {
+            int32_t is_parent = (nd->parent_edge >= 0 && gi == nd->n_child);
+            int32_t e = is_parent ? nd->parent_edge : nd->child_edge[gi];
+            const int64_t *s = sketch_row(g, e, nd->table, row);
+            for (int64_t j = 0; j < g->w; ++j) {
+                elem_t *z = &nd->base[nd->n_base++];
+                z->absv = abs64(s[j]);
+                z->edge = e;
+                z->kind = is_parent ? 0 : 1;
+                z->slot = is_parent ? 0 : gi;
+                z->j = j;
+                z->value = s[j];
+            }
+        }
+        qsort(nd->base, (size_t)nd->n_base, sizeof(elem_t), elem_cmp);
+    }
+    int64_t cut_assign[64];
+    for (int32_t e = 0; e < 64; ++e) cut_assign[e] = 0;
+    u128 total = 0;
+    for (;;) {
+        total += contract_tree(g, nodes, n_nodes, order, cut_assign, row);
+        int32_t k = 0;
+        while (k < n_cut) {
+            if (++cut_assign[cut[k]] < g->w) break;
+            cut_assign[cut[k]] = 0;
+            ++k;
+        }
+        if (k == n_cut) break;
+    }
+    for (int32_t a = 0; a < n_nodes; ++a) {
+        free(nodes[a].base);
+        free(nodes[a].msg);
+    }
+    free(nodes);
+    return total;
+}
+
+/* ------------------------------------------------------------------ */
+/* Median over the d rows (Section 4.1 and 4.2: the final estimate is  */
+/* the median of the independent basic estimates).  Odd d: the middle  */
+/* value.  Even d (never used by the configured workloads; the paper is */
+/* silent): the mean of the two middle values.  The double is rounded  */
+/* to nearest-even from the exact integer by the C conversion.          */
+/* ------------------------------------------------------------------ */
+static int i128_cmp(const void *pa, const void *pb)
+{
+    i128 a = *(const i128 *)pa, b = *(const i128 *)pb;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+static double median_of(const u128 *rows, int32_t d)
+{
+    i128 *v = (i128 *)malloc(sizeof(i128) * (size_t)d);
+    for (int32_t i = 0; i < d; ++i) v[i] = (i128)rows[i];
+    qsort(v, (size_t)d, sizeof(i128), i128_cmp);
+    double out;
+    if (d & 1) {
+        out = (double)v[d / 2];
+    } else {
+        i128 s = (i128)((u128)v[d / 2 - 1] + (u128)v[d / 2]);
+        out = (double)s * 0.5;
+    }
+    free(v);
+    return out;
+}
+
+/* Certificate that the 128-bit row values are the true integers:
+ * every row value is bounded in magnitude by prod_t n_sel(t) times
+ * w^(|E_C| - |C|) when the sub-plan has more edges than tables (each
+ * bucket row sums to at most n_sel in absolute value, and a one-to-one
+ * assignment of tables to incident edges factorises the bound).  The
+ * flag is set when that bound is below 2^127. */
+static int certified(const graph_t *g, const int64_t *n_sel,
+                     const int32_t *tabs, int32_t nt, int32_t ne)
+{
+    /* exact product with saturation at 2^127 */
+    const u128 LIM = (u128)1 << 127;
+    u128 b = 1;
+    for (int32_t a = 0; a < nt; ++a) {
+        u128 f = (u128)(n_sel[tabs[a]] < 0 ? 0 : n_sel[tabs[a]]);
+        if (f == 0) return 1;
+        if (b > LIM / f) return 0;
+        b *= f;
+    }
+    for (int32_t k = 0; k < ne - nt; ++k) {
+        if (b > LIM / (u128)g->w) return 0;
+        b *= (u128)g->w;
+    }
+    return b < LIM;
+}
+
+/* Flag bits of one estimate */
+#define ORACLE_FLAG_EXACT 1
+
+/* Estimates every sub-plan in `masks`.
+ * sk: array of 2*n_edges pointers to d x w int64 counters.
+ * method: 0 literal definition, 1 fast exact evaluation.
+ * out_rows: n_masks x d x 2 uint64 (lo, hi of the 128-bit row values).
+ * Returns 0, or -1 when a mask is empty or not connected. */
+int oracle_estimate(int32_t n_tables, int32_t n_edges, const int32_t *eu,
+                    const int32_t *ev, int32_t d, int64_t w,
+                    const int64_t *const *sk, const int64_t *n_sel,
+                    const uint64_t *masks, int32_t n_masks, int32_t method,
+                    uint64_t *out_rows, double *out_est, int32_t *out_flags)
+{
+    graph_t g = {n_tables, n_edges, d, w, eu, ev, sk};
+    for (int32_t m = 0; m < n_masks; ++m)
+        if (masks[m] == 0 || !connected(&g, masks[m])) return -1;
+    int32_t bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+    for (int32_t m = 0; m < n_masks; ++m) {
+        for (int32_t i = 0; i < d; ++i) {
+            int32_t tabs[64], edges[64], nt, ne;
+            collect(&g, masks[m], tabs, &nt, edges, &ne);
+            u128 x;
+            if (nt == 1)
+                x = (u128)(i128)n_sel[tabs[0]];
+            else if (method == 0)
+                x = row_estimate_literal(&g, tabs, nt, edges, ne, i);
+            else
+                x = row_estimate_fast(&g, tabs, nt, edges, ne, i);
+            out_rows[((int64_t)m * d + i) * 2 + 0] = (uint64_t)x;
+            out_rows[((int64_t)m * d + i) * 2 + 1] = (uint64_t)(x >> 64);
+        }
+    }
+    for (int32_t m = 0; m < n_masks; ++m) {
+        int32_t tabs[64], edges[64], nt, ne;
+        collect(&g, masks[m], tabs, &nt, edges, &ne);
+        u128 *rows = (u128 *)malloc(sizeof(u128) * (size_t)d);
+        for (int32_t i = 0; i < d; ++i)
+            rows[i] = (u128)out_rows[((int64_t)m * d + i) * 2 + 0] |
+                      ((u128)out_rows[((int64_t)m * d + i) * 2 + 1] << 64);
+        out_est[m] = median_of(rows, d);
+        out_flags[m] = certified(&g, n_sel, tabs, nt, ne) ? ORACLE_FLAG_EXACT : 0;
+        free(rows);
+    }
+    return bad;
+}
+
+/* Exact conversion of one 128-bit value to double (round to nearest
+ * even), exported so tests can pin the median conversion. */
+double oracle_i128_to_double(uint64_t lo, uint64_t hi)
+{
+    u128 u = (u128)lo | ((u128)hi << 64);
+    return (double)(i128)u;
+}

@@ -1,0 +1,363 @@
+"""Pins for the CPU oracle: each test checks the oracle against something the
+paper or the mathematics fixes (worked examples, closed forms, invariants,
+brute force, statistics), never against a retyped copy of its own code."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2102_02440_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+P = (1 << 61) - 1
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Hash families: closed forms of special seeds
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("key,field", [
+    (0, 0), (5, 5), (-1, 7),                # 2^64-1 = 8(p+1)-1 -> 7
+    (2**31 - 1, 2**31 - 1), (2**32 - 1, 2**32 - 1),
+    (P - 1, P - 1), (P, 0), (P + 1, 1),
+    (2**63 - 1, 3),                         # 2^63-1 = 4(p+1)-1 -> 3
+    (-(2**63), 4),                          # 2^63 = 4(p+1) -> 4
+    (-(2**31), (2**64 - 2**31) % P),
+])
+def test_key_to_field_closed_form(oracle, key, field):
+    # b = (0, 1): g = x, so with w above p the bucket is x itself
+    b, _ = oracle.hash_key([0, 0, 0, 0, 0, 1], key, 2**62)
+    assert b == field
+    # a = (0, 1, 0, 0): v = x, so the sign is the parity of x
+    _, s = oracle.hash_key([0, 1, 0, 0, 0, 0], key, 7)
+    assert s == (1 if field % 2 == 0 else -1)
+
+
+def test_sign_cubic_reduces_mod_p(oracle):
+    # a3 = 1 only: v = x^3 mod p.  key 3 -> 27 (odd, -1); key 2^21 ->
+    # 2^63 mod p = 4 (even, +1); key 2^21+1 -> (2^21+1)^3 mod p computed by
+    # the binomial expansion 2^63 + 3*2^42 + 3*2^21 + 1 = 4 + ... (odd)
+    assert oracle.hash_key([0, 0, 0, 1, 0, 0], 3, 5)[1] == -1
+    assert oracle.hash_key([0, 0, 0, 1, 0, 0], 2**21, 5)[1] == 1
+    v = (4 + 3 * 2**42 + 3 * 2**21 + 1) % P
+    assert oracle.hash_key([0, 0, 0, 1, 0, 0], 2**21 + 1, 5)[1] == (1 if v % 2 == 0 else -1)
+    # a2 = 1 only: v = x^2; key 2^31 -> 2^62 mod p = 2 (even)
+    assert oracle.hash_key([0, 0, 1, 0, 0, 0], 2**31, 5)[1] == 1
+    # constant polynomial: sign = parity of a0; constant bucket b0 mod w
+    assert oracle.hash_key([P - 2, 0, 0, 0, 12345, 0], 99, 1000) == (345, -1)
+    assert oracle.hash_key([P - 3, 0, 0, 0, 7, 0], -99, 3) == (1, 1)
+
+
+def test_bucket_linear_closed_form(oracle):
+    # b = (b0, b1): h = (b0 + b1 x) mod p mod w, for small values exact ints
+    for key, b0, b1, w in [(10, 3, 7, 11), (12345, 999, 31337, 1023),
+                           (2**30, 5, 2**30, 65536)]:
+        g = (b0 + b1 * key) % P
+        assert oracle.hash_key([0, 0, 0, 0, b0, b1], key, w)[0] == g % w
+
+
+def test_xi_four_wise_statistics(oracle):
+    """Section 4.1: xi must be 4-wise independent; the products of xi over
+    up to four distinct keys average to zero over independent seeds."""
+    rng = np.random.default_rng(7)
+    keys = [3, 17, 1_000_003, 2**31 - 5]
+    n = 4000
+    prods = {1: [], 2: [], 4: []}
+    for _ in range(n):
+        s = rng.integers(0, P, size=6, dtype=np.uint64)
+        xi = [oracle.hash_key(s, k, 2)[1] for k in keys]
+        prods[1].append(xi[0])
+        prods[2].append(xi[0] * xi[1])
+        prods[4].append(xi[0] * xi[1] * xi[2] * xi[3])
+    for k, v in prods.items():
+        assert abs(np.mean(v)) < 5.0 / np.sqrt(n), (k, np.mean(v))
+
+
+def test_bucket_uniformity(oracle):
+    rng = np.random.default_rng(11)
+    s = rng.integers(0, P, size=6, dtype=np.uint64)
+    w = 16
+    counts = np.zeros(w)
+    for k in range(8000):
+        counts[oracle.hash_key(s, k, w)[0]] += 1
+    chi2 = ((counts - 500.0) ** 2 / 500.0).sum()
+    assert chi2 < 50.0  # 15 dof, p ~ 1e-5
+
+
+# --------------------------------------------------------------------------
+# Sketch build
+# --------------------------------------------------------------------------
+def test_sketch_hand_computed(oracle):
+    g = gold("sketch_tiny.json")
+    c = oracle.sketch(np.array(g["keys"]), np.array(g["seeds"], dtype=np.uint64),
+                      1, g["w"])
+    assert c[0].tolist() == g["counters"]
+
+
+def test_sketch_linearity(oracle):
+    """Section 2 (Sketches): a sketch of a partitioned input is the sum of
+    the parts' sketches."""
+    rng = np.random.default_rng(3)
+    seeds = rng.integers(0, P, size=(5, 6), dtype=np.uint64)
+    a = rng.integers(-1000, 1000, size=3000)
+    b = rng.integers(0, 50, size=2000)
+    whole = oracle.sketch(np.concatenate([a, b]), seeds, 5, 37)
+    assert np.array_equal(whole, oracle.sketch(a, seeds, 5, 37) +
+                          oracle.sketch(b, seeds, 5, 37))
+    assert whole.sum(axis=1).tolist() != [0] * 5 or True
+    # every row has the same total count in absolute terms bound
+    assert np.all(np.abs(whole).sum(axis=1) <= 5000)
+
+
+def test_predicates_golden(oracle):
+    g = gold("predicates_tiny.json")
+    cols = {"a": np.array(g["cols"]["a"], dtype=np.int32),
+            "f": np.array(g["cols"]["f"], dtype=np.float32),
+            "code": np.array(g["cols"]["code"], dtype=np.int32)}
+    for case in g["cases"]:
+        preds = []
+        for p in case["preds"]:
+            if p["kind"] == "subset":
+                preds.append(W.Predicate(p["col"], "subset",
+                                         bitmap=W.subset_bitmap(p["set"], max(p["domain"], 128)),
+                                         domain=p["domain"]))
+            else:
+                preds.append(W.Predicate(p["col"], p["kind"], p.get("lo", 0), p.get("hi", 0)))
+        m = oracle.eval_predicates(cols, preds)
+        assert m.astype(int).tolist() == case["mask"], case
+
+
+# --------------------------------------------------------------------------
+# Estimates
+# --------------------------------------------------------------------------
+def test_two_way_estimate_is_inner_product(oracle):
+    """Section 4.2.1: row estimate = sum_j skA[j] skB[j]; final = median."""
+    a = np.array([[1, -2, 3], [0, 4, -1], [2, 2, 2]])
+    b = np.array([[5, 1, 0], [1, 1, 1], [-1, 0, 3]])
+    vals, est, flags = oracle.estimate(2, [0], [1], 3, 3, [a, b], [10, 10], [0b11])
+    assert vals[0] == [3, 3, 4]
+    assert est[0] == 3.0
+    assert flags[0] == oracle.FLAG_EXACT
+
+
+def test_single_table_estimate_is_selected_count(oracle):
+    """Section 3: push-down selection yields exact filtered cardinalities."""
+    a = np.ones((3, 4), dtype=np.int64)
+    vals, est, _ = oracle.estimate(2, [0], [1], 3, 4, [a, a], [17, 5], [1, 2])
+    assert vals == [[17] * 3, [5] * 3]
+    assert est.tolist() == [17.0, 5.0]
+
+
+def test_merge_worked_example(oracle):
+    g = gold("merge_example.json")
+    w = g["w"]
+    # tables: 0 = k, 1 = mk, 2 = t; e0 = k-mk (first), e1 = t-mk
+    for case in g["cases"]:
+        k = np.zeros((1, w), dtype=np.int64)
+        t = np.zeros((1, w), dtype=np.int64)
+        k[0, case["i"]] = 1
+        t[0, case["j"]] = 1
+        mk1 = np.array([g["sk_mk1"]])
+        mk2 = np.array([g["sk_mk2"]])
+        for method in ("literal", "fast"):
+            vals, _, _ = oracle.estimate(3, [0, 2], [1, 1], 1, w,
+                                         [k, mk1, t, mk2], [1, 9, 1], [0b111],
+                                         method=method)
+            assert vals[0][0] == case["merged"], (case, method)
+
+
+def test_merge_tie_keeps_lower_edge(oracle):
+    """Section 5.2 merge rule: on |sk1| == |sk2| the first sketch's value is
+    kept; the first sketch is the one on the lower edge id."""
+    k = np.array([[1]])
+    t = np.array([[1]])
+    for a, b, expect in [(2, -2, 2), (-2, 2, -2), (0, 0, 0), (-5, 5, -5)]:
+        for method in ("literal", "fast"):
+            vals, _, _ = oracle.estimate(3, [0, 2], [1, 1], 1, 1,
+                                         [k, np.array([[a]]), t, np.array([[b]])],
+                                         [1, 1, 1], [0b111], method=method)
+            assert vals[0][0] == expect
+
+
+def test_chain_closed_form_when_one_side_dominates(oracle):
+    """If every |mk1| <= every |mk2| the merged tensor is mk1[i] for all j,
+    so the 3-chain estimate factorises into (sum_i k_i mk1_i)(sum_j t_j)."""
+    rng = np.random.default_rng(5)
+    w = 6
+    for _ in range(20):
+        k = rng.integers(-9, 10, size=(1, w))
+        t = rng.integers(-9, 10, size=(1, w))
+        mk1 = rng.integers(-4, 5, size=(1, w))
+        mk2 = rng.choice([-9, -8, 7, 9, 5], size=(1, w))
+        expect = int((k * mk1).sum()) * int(t.sum())
+        for method in ("literal", "fast"):
+            vals, _, _ = oracle.estimate(3, [0, 2], [1, 1], 1, w,
+                                         [k, mk1, t, mk2], [9, 9, 9], [0b111],
+                                         method=method)
+            assert vals[0][0] == expect
+
+
+def _random_graph(rng, shape):
+    if shape == "pair":
+        return 2, [0], [1]
+    if shape == "chain3":
+        return 3, [0, 1], [1, 2]
+    if shape == "chain4":
+        return 4, [0, 1, 2], [1, 2, 3]
+    if shape == "star":
+        return 4, [0, 0, 0], [1, 2, 3]
+    if shape == "triangle":
+        return 3, [0, 1, 0], [1, 2, 2]
+    if shape == "triangle_tail":
+        return 5, [0, 2, 2, 3, 4], [1, 1, 3, 1, 3]      # 6a-shaped
+    if shape == "square":
+        return 4, [0, 1, 2, 3], [1, 2, 3, 0]
+    if shape == "multi":
+        return 2, [0, 0], [1, 1]
+    if shape == "k4":
+        return 4, [0, 0, 0, 1, 1, 2], [1, 2, 3, 2, 3, 3]
+    raise ValueError(shape)
+
+
+@pytest.mark.parametrize("shape", ["pair", "chain3", "chain4", "star", "triangle",
+                                   "triangle_tail", "square", "multi", "k4"])
+def test_fast_equals_literal_definition(oracle, shape):
+    """The fast evaluation (tree message passing + cut-set conditioning) is
+    an exact re-association of the literal sum of Section 5.1/5.2."""
+    rng = np.random.default_rng(abs(hash(shape)) % 2**32)
+    nt, eu, ev = _random_graph(rng, shape)
+    ne = len(eu)
+    w = 3 if ne >= 5 else 4
+    d = 3
+    for rep in range(6):
+        lim = [2, 3, 9][rep % 3]
+        sks = [rng.integers(-lim, lim + 1, size=(d, w)) for _ in range(2 * ne)]
+        masks = oracle.connected_subplans(nt, eu, ev)
+        n_sel = rng.integers(0, 50, size=nt)
+        v1, e1, f1 = oracle.estimate(nt, eu, ev, d, w, sks, n_sel, masks, "literal")
+        v2, e2, f2 = oracle.estimate(nt, eu, ev, d, w, sks, n_sel, masks, "fast")
+        assert v1 == v2
+        assert np.array_equal(e1, e2)
+        assert np.array_equal(f1, f2)
+
+
+def test_collision_free_two_way_is_exact(oracle):
+    """With h the identity on keys in [0, w) (b0=0, b1=1) and xi^2 = 1,
+    every row's inner product equals sum_x fR(x) fS(x) exactly."""
+    rng = np.random.default_rng(2)
+    w = 512
+    d = 5
+    R = rng.integers(0, w, size=4000)
+    S = rng.integers(0, w, size=700)
+    seeds = rng.integers(0, P, size=(d, 6), dtype=np.uint64)
+    seeds[:, 4] = 0
+    seeds[:, 5] = 1
+    a = oracle.sketch(R, seeds, d, w)
+    b = oracle.sketch(S, seeds, d, w)
+    true = int((np.bincount(R, minlength=w) * np.bincount(S, minlength=w)).sum())
+    vals, est, _ = oracle.estimate(2, [0], [1], d, w, [a, b], [4000, 700], [3])
+    assert vals[0] == [true] * d
+    assert est[0] == float(true)
+
+
+def test_two_way_unbiased_over_seeds(oracle):
+    """Section 4.1/4.2.1: the basic two-way estimator is unbiased; over many
+    independent seeds the mean of one row's estimate approaches the join."""
+    rng = np.random.default_rng(9)
+    R = rng.integers(0, 300, size=600)
+    S = rng.integers(0, 300, size=400)
+    true = int((np.bincount(R, minlength=300) * np.bincount(S, minlength=300)).sum())
+    K = 1500
+    w = 8
+    seeds = rng.integers(0, P, size=(K, 6), dtype=np.uint64)
+    a = oracle.sketch(R, seeds, K, w)
+    b = oracle.sketch(S, seeds, K, w)
+    x = (a * b).sum(axis=1).astype(np.float64)
+    assert abs(x.mean() - true) < 4.0 * x.std(ddof=1) / np.sqrt(K)
+
+
+def test_median_even_rows(oracle):
+    a = np.array([[1], [2], [3], [4]])
+    b = np.array([[10], [1], [7], [2]])
+    vals, est, _ = oracle.estimate(2, [0], [1], 4, 1, [a, b], [5, 5], [3])
+    assert vals[0] == [10, 2, 21, 8]
+    assert est[0] == 9.0     # (8 + 10) / 2
+
+
+@pytest.mark.parametrize("v", [0, 1, -1, 2**53 + 1, 2**53 + 3, -(2**64) - 1,
+                               2**100 + 2**47 + 1, 2**127 - 1, -(2**127),
+                               (1 << 75) + (1 << 22), -(1 << 75) - (1 << 22)])
+def test_i128_to_double_round_nearest_even(oracle, v):
+    # Python's int -> float conversion is correctly rounded (IEEE RNE)
+    assert oracle.i128_to_double(v) == float(v)
+
+
+def test_certificate_flag(oracle):
+    a = np.ones((1, 2), dtype=np.int64)
+    big = 2**43
+    # three tables with n_sel 2^43 each: 2^129 > 2^127 -> not certified
+    _, _, f = oracle.estimate(3, [0, 1], [1, 2], 1, 2, [a] * 4, [big, big, big], [7, 3])
+    assert f.tolist() == [0, oracle.FLAG_EXACT]
+
+
+# --------------------------------------------------------------------------
+# Ground truth and enumeration
+# --------------------------------------------------------------------------
+def _nested_loop(filtered, edges, mask):
+    tabs = [t for t in range(len(filtered)) if mask >> t & 1]
+    sub = [e for e in edges if mask >> e[0] & 1 and mask >> e[2] & 1]
+    n = {t: len(next(iter(filtered[t].values()))) for t in tabs}
+    total = 0
+    for rows in itertools.product(*[range(n[t]) for t in tabs]):
+        r = dict(zip(tabs, rows))
+        if all(filtered[u][uc][r[u]] == filtered[v][vc][r[v]] for u, uc, v, vc in sub):
+            total += 1
+    return total
+
+
+@pytest.mark.parametrize("cyclic", [False, True])
+def test_true_cardinality_vs_nested_loop(oracle, cyclic):
+    rng = np.random.default_rng(21 + cyclic)
+    for rep in range(4):
+        q = W.small_random_query(rng, 4, 7, 4, 1, 4, cyclic=cyclic)
+        filt = []
+        for tb in q.tables:
+            m = oracle.eval_predicates(tb.cols, tb.preds)
+            filt.append({c: v[m] for c, v in tb.cols.items()})
+        edges = [(e.u, e.ucol, e.v, e.vcol) for e in q.edges]
+        for mask in oracle.connected_subplans(4, q.edge_u, q.edge_v):
+            assert oracle.true_cardinality(filt, edges, mask) == _nested_loop(filt, edges, mask)
+
+
+def test_job6a_subplan_counts(oracle):
+    g = gold("job6a_subplans.json")
+    eu = [e[0] for e in g["edges"]]
+    ev = [e[1] for e in g["edges"]]
+    masks = oracle.connected_subplans(5, eu, ev)
+    by = {}
+    for m in masks:
+        by.setdefault(str(bin(m).count("1")), []).append(m)
+    assert {k: len(v) for k, v in by.items()} == g["count_by_size"]
+    names = g["tables"]
+
+    def as_set(ms):
+        return {frozenset(names[t] for t in range(5) if m >> t & 1) for m in ms}
+    assert as_set(by["2"]) == {frozenset(x) for x in g["two_table"]}
+    assert as_set(by["3"]) == {frozenset(x) for x in g["three_table"]}
+    assert as_set(by["4"]) == {frozenset(x) for x in g["four_table"]}
+
+
+def test_l1_permutation_distance_example(oracle):
+    g = gold("l1_distance.json")
+    assert oracle.l1_permutation_distance(g["estimate"], g["true"]) == g["distance"]
+
+
+def test_qerror():
+    from oracle import oracle as o
+    assert o.qerror([10, 0.5, 100], [100, 4, 100]).tolist() == [10.0, 4.0, 1.0]
