@@ -1,0 +1,200 @@
+/*
+ * compass.h -- C ABI of the MI355X (gfx950) hot path of online sketch-based
+ * query optimisation (Izenov, Datta, Rusu, Shin, "Online Sketch-based Query
+ * Optimization", arXiv 2102.02440).
+ *
+ * Two operations, as the paper splits them:
+ *   1. compass_sketch_build  -- push-down selection fused with Fast-AGMS
+ *      sketch building over the qualifying tuples (Section 3, "Workflow" and
+ *      "Partitioned query execution"; Section 4.2 counter definition).
+ *   2. compass_estimate      -- join-size estimates of sub-plans from the
+ *      two-way sketches only: inner product + median for two tables
+ *      (Section 4.2.1), min-abs sketch merging composed over the join graph
+ *      for more (Section 5.2 with the contraction of Section 5.1).
+ * Plus a batched build of many tables' sketches in one graph-captured
+ * persistent launch, and a small learned correction network.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns a compass_status and never throws.  On failure
+ *     compass_last_error() returns a message (thread-local, valid until the
+ *     next call on the same thread).
+ *   - Device pointers: column data, predicate bitmaps, counters, outputs.
+ *     Host pointers: seeds, graph arrays, sub-plan masks; they are copied
+ *     before the call returns.  The caller owns every buffer; the library
+ *     never frees caller memory.
+ *   - All GPU work is enqueued on `stream` (0 = the null stream) and is
+ *     asynchronous: outputs are valid once the stream has synchronised.
+ *   - Scratch memory is cached per device by the library and released by
+ *     compass_release().  Calls that share the library's scratch on one
+ *     device are serialised on their streams by the caller: two calls in
+ *     flight at once on different streams of the same device race on it.
+ *
+ * Hash families (the paper requires a 4-wise independent +-1 family xi and
+ * one bucket hash h per sketch row, Sections 4.1 and 4.2, and names no
+ * concrete family).  With p = 2^61 - 1 and seeds {a0,a1,a2,a3,b0,b1} in
+ * [0, p) for one row:
+ *     x  = ((uint64_t)(int64_t)key) mod p      (int32 keys sign-extended)
+ *     xi = +1 if (a0 + a1 x + a2 x^2 + a3 x^3 mod p) is even, else -1
+ *     h  = ((b0 + b1 x) mod p) mod w
+ * Both sketches of one join edge must use the same seeds (Section 4.1.1).
+ */
+#ifndef COMPASS_H
+#define COMPASS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    COMPASS_OK = 0,
+    COMPASS_E_ARG = 1,          /* null pointer, bad size / kind / dtype, seed >= p */
+    COMPASS_E_RANGE = 2,        /* a size exceeds what the exact arithmetic allows */
+    COMPASS_E_GRAPH = 3,        /* sub-plan empty / not connected / bad edge */
+    COMPASS_E_HIP = 4,          /* HIP runtime failure */
+    COMPASS_E_UNSUPPORTED = 5   /* valid request outside what this build runs */
+} compass_status;
+
+enum { COMPASS_I32 = 0, COMPASS_F32 = 1, COMPASS_I64 = 2 };
+enum { COMPASS_PRED_POINT = 0, COMPASS_PRED_RANGE = 1, COMPASS_PRED_SUBSET = 2 };
+
+/* One selection predicate on one column (Section 1: point, subset (LIKE over
+ * a dictionary) and range selections; Section 3: conjunctive, pushed down).
+ *   POINT : value == lo
+ *   RANGE : lo <= value <= hi           (inclusive; IEEE compares for F32,
+ *                                         so NaN fails, -0 == +0)
+ *   SUBSET: 0 <= value < domain and bit `value` of `bitmap` is set
+ *           (dtype must be I32; bitmap = device array of (domain+63)/64
+ *           uint64 words, bit k of word k/64 is code k) */
+typedef union {
+    int32_t i;
+    float f;
+} compass_scalar;
+
+typedef struct {
+    int32_t col;                 /* index into pred_cols */
+    int32_t kind;                /* COMPASS_PRED_* */
+    int32_t dtype;               /* COMPASS_I32 or COMPASS_F32 */
+    int32_t reserved;
+    compass_scalar lo, hi;
+    const uint64_t *bitmap;      /* SUBSET only, device */
+    int64_t domain;              /* SUBSET only */
+} compass_pred;
+
+/* One attribute sketch to build during the scan.  One table has as many
+ * sketches as joins it takes part in, even when two joins use the same
+ * column (Section 3, "Workflow"). */
+typedef struct {
+    const void *key_col;         /* device, n_rows keys */
+    int32_t key_dtype;           /* COMPASS_I32 or COMPASS_I64 */
+    int32_t reserved;
+    const uint64_t *seeds;       /* host, d x 6: a0 a1 a2 a3 b0 b1 per row */
+    void *counters;              /* device, d x w row-major, int32 or int64 */
+} compass_sketch_spec;
+
+/* compass_sketch_build -- one scan of one table: evaluates the conjunction
+ * of `preds` on every row and, for the rows that satisfy it, adds xi_i(key)
+ * to counter h_i(key) of row i of every sketch (Section 4.2 counter
+ * definition), and adds the number of qualifying rows to *n_selected (the
+ * exact selected cardinality of Section 3).
+ *   n_rows        rows of the table (0 allowed; < 2^47)
+ *   pred_cols     host array of n_pred_cols device column pointers
+ *   preds         host array of n_preds predicates (n_preds may be 0)
+ *   sketches      host array of n_sketches specs (1 <= n_sketches <= 16)
+ *   d, w          rows and buckets of every sketch (1 <= d <= 32, 1 <= w <= 2^20)
+ *   counter_bits  32 or 64 (int32 counters need n_rows < 2^31)
+ *   accumulate    0: counters and *n_selected are overwritten; 1: added to
+ *                 (sketches are mergeable by addition, Section 2)
+ *   n_selected    device int64 */
+compass_status compass_sketch_build(int64_t n_rows,
+                                    const void *const *pred_cols,
+                                    int32_t n_pred_cols,
+                                    const compass_pred *preds, int32_t n_preds,
+                                    const compass_sketch_spec *sketches,
+                                    int32_t n_sketches, int32_t d, int32_t w,
+                                    int32_t counter_bits, int32_t accumulate,
+                                    int64_t *n_selected, hipStream_t stream);
+
+/* A query join graph with its attribute sketches (Section 3, "Plan
+ * enumeration": estimates take only the two-way sketches as input).
+ * Edge e joins tables edge_u[e] and edge_v[e]; its id is e, and a lower id
+ * is "first" in the merge tie rule of Section 5.2.
+ * sketch[2e+0] = counters of table edge_u[e] on edge e, sketch[2e+1] = of
+ * table edge_v[e]; both built with the same seeds.  n_selected[t] = exact
+ * selected cardinality of table t (device). */
+typedef struct {
+    int32_t n_tables;            /* 1..64 */
+    int32_t n_edges;             /* 0..64 */
+    int32_t d, w;                /* sketch shape (w <= 65536) */
+    int32_t counter_bits;        /* 32 or 64 */
+    int32_t reserved;
+    const int32_t *edge_u;       /* host, n_edges */
+    const int32_t *edge_v;       /* host, n_edges */
+    const int64_t *n_selected;   /* device, n_tables */
+    const void *const *sketch;   /* host array of 2*n_edges device pointers */
+} compass_join_graph;
+
+typedef struct {
+    uint64_t lo;
+    int64_t hi;
+} compass_i128;
+
+/* Flag bits of one sub-plan estimate. */
+enum {
+    /* the row values are certified to be the true integers (no wrap):
+     * prod over the sub-plan's tables of n_selected, times w^(#edges -
+     * #tables) when positive, is below 2^127 */
+    COMPASS_FLAG_EXACT = 1,
+    /* the sub-plan's shape is outside what this build evaluates (more than
+     * one independent cycle, or a cycle longer than a triangle, or two
+     * edges between the same two tables); its outputs are zero / NaN */
+    COMPASS_FLAG_UNSUPPORTED = 2
+};
+
+/* compass_estimate -- for each sub-plan C (bitmask of tables, connected over
+ * the graph's edges between its tables) and each sketch row i:
+ *   |C| = 1 : X_i = n_selected of the table (Section 3)
+ *   |C| >= 2: X_i = sum over bucket assignments of C's induced edges of the
+ *             product over C's tables of the table's merged sketch, where
+ *             the merged value is the incident sketch bucket of smallest
+ *             absolute value, ties to the lower edge id (Section 5.2 merge
+ *             rule, generalised iteratively; Section 5.1 contraction;
+ *             Section 4.2.1 inner product for two tables).
+ * X_i is exact in 128-bit two's complement (wrapping mod 2^128), and the
+ * estimate is the median over rows (Section 4.2.1; even d: mean of the two
+ * middle values), converted to double with round-to-nearest-even.
+ *   masks      host, n_subplans bitmasks
+ *   row_est    device, n_subplans x d (may be NULL)
+ *   est        device, n_subplans doubles
+ *   flags      device, n_subplans int32 (COMPASS_FLAG_*)
+ * Supported shapes: any tree, and trees plus one edge that closes a
+ * triangle.  Others get COMPASS_FLAG_UNSUPPORTED and do not fail the call. */
+compass_status compass_estimate(const compass_join_graph *g,
+                                const uint64_t *masks, int32_t n_subplans,
+                                compass_i128 *row_est, double *est,
+                                int32_t *flags, hipStream_t stream);
+
+/* Kernel timing for measurement: while enabled, the library records a pair
+ * of HIP events on the launch stream around each kernel launch it makes.
+ * compass_profile_take(name) waits for the recorded events of kernel `name`
+ * ("scan_sketch", "fill_zero", "sort_rows", "node", "tri_lane", "finish"),
+ * returns their count and summed elapsed milliseconds, and forgets them. */
+compass_status compass_profile_enable(int32_t on);
+compass_status compass_profile_take(const char *name, int64_t *count,
+                                    double *total_ms);
+
+/* Frees the library's cached scratch memory on the current device. */
+compass_status compass_release(void);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *compass_last_error(void);
+
+/* Library version string. */
+const char *compass_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COMPASS_H */

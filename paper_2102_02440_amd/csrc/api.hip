@@ -1,0 +1,792 @@
+// api.hip -- host side of the C ABI declared in include/compass.h.
+//
+// Validation, work decomposition and launch sequencing for the fused
+// selection + sketch build and for the merged-sketch estimates.  All GPU
+// work goes to the caller's stream; nothing here computes a sketch or an
+// estimate on the host.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "build_params.hpp"
+#include "compass.h"
+#include "estimate_buffers.hpp"
+#include "estimate_params.hpp"
+
+namespace compass {
+// kernels (build_kernels.hip, estimate_kernels.hip)
+hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t st);
+hipError_t launch_scan_sketch(const BuildParams &P, int n_blocks,
+                              size_t lds_bytes, hipStream_t st);
+hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
+                            const EstBuffers &B, hipStream_t st);
+hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
+                       hipStream_t st);
+hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
+                           const EstBuffers &B, hipStream_t st);
+hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
+                         uint64_t *row_est, double *est, int32_t *flags,
+                         int32_t n_tables, hipStream_t st);
+}  // namespace compass
+
+using namespace compass;
+
+// ---------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static compass_status fail(compass_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_OK(expr)                                                       \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail(COMPASS_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
+// ---------------------------------------------------------------------
+// per-device state: scratch memory, pinned staging ring, kernel attrs
+// ---------------------------------------------------------------------
+struct DeviceState {
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  static constexpr int kRing = 4;
+  void *pinned[kRing] = {};
+  size_t pinned_bytes[kRing] = {};
+  hipEvent_t pinned_done[kRing] = {};
+  bool pinned_used[kRing] = {};
+  int ring_next = 0;
+  bool attrs_set = false;
+};
+
+static std::mutex g_mu;
+static std::map<int, DeviceState> g_dev;
+
+static compass_status device_state(DeviceState **out) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  DeviceState &ds = g_dev[dev];
+  if (!ds.attrs_set) {
+    for (int i = 0; i < DeviceState::kRing; ++i)
+      HIP_OK(hipEventCreateWithFlags(&ds.pinned_done[i],
+                                     hipEventDisableTiming));
+    ds.attrs_set = true;
+  }
+  *out = &ds;
+  return COMPASS_OK;
+}
+
+static compass_status ensure_scratch(DeviceState *ds, size_t bytes,
+                                     void **out) {
+  if (bytes > ds->scratch_bytes) {
+    if (ds->scratch) {
+      HIP_OK(hipDeviceSynchronize());
+      HIP_OK(hipFree(ds->scratch));
+      ds->scratch = nullptr;
+      ds->scratch_bytes = 0;
+    }
+    size_t want = std::max(bytes, ds->scratch_bytes * 2);
+    HIP_OK(hipMalloc(&ds->scratch, want));
+    ds->scratch_bytes = want;
+  }
+  *out = ds->scratch;
+  return COMPASS_OK;
+}
+
+// copies `bytes` of host data to `dst` (device) asynchronously through a
+// pinned staging buffer that is reused only once its copy has completed
+static compass_status upload(DeviceState *ds, void *dst, const void *src,
+                             size_t bytes, hipStream_t st) {
+  if (bytes == 0) return COMPASS_OK;
+  const int k = ds->ring_next;
+  ds->ring_next = (k + 1) % DeviceState::kRing;
+  if (ds->pinned_used[k]) HIP_OK(hipEventSynchronize(ds->pinned_done[k]));
+  if (ds->pinned_bytes[k] < bytes) {
+    if (ds->pinned[k]) HIP_OK(hipHostFree(ds->pinned[k]));
+    ds->pinned[k] = nullptr;
+    size_t want = std::max(bytes, (size_t)65536);
+    HIP_OK(hipHostMalloc(&ds->pinned[k], want, hipHostMallocDefault));
+    ds->pinned_bytes[k] = want;
+  }
+  memcpy(ds->pinned[k], src, bytes);
+  HIP_OK(hipMemcpyAsync(dst, ds->pinned[k], bytes, hipMemcpyHostToDevice, st));
+  HIP_OK(hipEventRecord(ds->pinned_done[k], st));
+  ds->pinned_used[k] = true;
+  return COMPASS_OK;
+}
+
+// ---------------------------------------------------------------------
+// kernel timing (HIP events around each launch, on the launch stream)
+// ---------------------------------------------------------------------
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+
+struct ProfScope {
+  ProfRec rec;
+  bool on;
+  hipStream_t st;
+  ProfScope(const char *name, hipStream_t s) : on(g_prof_on), st(s) {
+    if (!on) return;
+    rec.name = name;
+    (void)hipEventCreate(&rec.a);
+    (void)hipEventCreate(&rec.b);
+    (void)hipEventRecord(rec.a, st);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(rec.b, st);
+    g_prof.push_back(rec);
+  }
+};
+
+extern "C" compass_status compass_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof_on = on != 0;
+  return COMPASS_OK;
+}
+
+// Synchronises the recorded events and returns, for kernel `name`, the
+// number of launches and their total time in milliseconds; then forgets
+// every record of that name.
+extern "C" compass_status compass_profile_take(const char *name,
+                                               int64_t *count,
+                                               double *total_ms) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  *count = 0;
+  *total_ms = 0;
+  std::vector<ProfRec> keep;
+  for (auto &r : g_prof) {
+    if (r.name != name) {
+      keep.push_back(r);
+      continue;
+    }
+    HIP_OK(hipEventSynchronize(r.b));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+    *count += 1;
+    *total_ms += ms;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.swap(keep);
+  return COMPASS_OK;
+}
+
+// ---------------------------------------------------------------------
+// compass_sketch_build
+// ---------------------------------------------------------------------
+static BucketMod make_bucket_mod(uint32_t w) {
+  BucketMod m;
+  m.w = w;
+  m.pow2 = (w & (w - 1)) == 0;
+  m.mask = w - 1;
+  m.r32 = (uint32_t)((1ull << 32) % w);
+  m.inv = 1.0 / (double)w;
+  return m;
+}
+
+static int dtype_size(int dt) { return dt == COMPASS_I64 ? 8 : 4; }
+
+extern "C" compass_status compass_sketch_build(
+    int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
+    const compass_pred *preds, int32_t n_preds,
+    const compass_sketch_spec *sketches, int32_t n_sketches, int32_t d,
+    int32_t w, int32_t counter_bits, int32_t accumulate, int64_t *n_selected,
+    hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  if (n_rows < 0 || n_rows >= (1ll << 47))
+    return fail(COMPASS_E_RANGE, "n_rows %lld outside [0, 2^47)",
+                (long long)n_rows);
+  if (d < 1 || d > 32) return fail(COMPASS_E_ARG, "d=%d outside [1, 32]", d);
+  if (w < 1 || w > (1 << 20))
+    return fail(COMPASS_E_ARG, "w=%d outside [1, 2^20]", w);
+  if (counter_bits != 32 && counter_bits != 64)
+    return fail(COMPASS_E_ARG, "counter_bits must be 32 or 64");
+  if (counter_bits == 32 && n_rows > 0x7FFFFFFFll)
+    return fail(COMPASS_E_RANGE, "int32 counters need n_rows < 2^31");
+  if (n_sketches < 1 || n_sketches > kMaxSketches)
+    return fail(COMPASS_E_ARG, "n_sketches=%d outside [1, %d]", n_sketches,
+                kMaxSketches);
+  if (n_preds < 0 || n_preds > kMaxPreds)
+    return fail(COMPASS_E_ARG, "n_preds=%d outside [0, %d]", n_preds,
+                kMaxPreds);
+  if (!sketches || !n_selected || (n_preds > 0 && !preds))
+    return fail(COMPASS_E_ARG, "null pointer argument");
+  if (n_preds > 0 && n_rows > 0 && !pred_cols)
+    return fail(COMPASS_E_ARG, "null predicate column array");
+  if ((size_t)w * 4 > kLdsBudget)
+    return fail(COMPASS_E_UNSUPPORTED,
+                "w=%d: one sketch row of partial counters exceeds the LDS "
+                "budget of this build",
+                w);
+
+  BuildParams base;
+  memset(&base, 0, sizeof(base));
+  base.n_rows = n_rows;
+  base.n_preds = n_preds;
+  base.counter_bits = counter_bits;
+  base.n_selected = n_selected;
+  base.bm = make_bucket_mod((uint32_t)w);
+  for (int i = 0; i < n_preds; ++i) {
+    const compass_pred &p = preds[i];
+    if (p.col < 0 || p.col >= n_pred_cols ||
+        (n_rows > 0 && !pred_cols[p.col]))
+      return fail(COMPASS_E_ARG, "predicate %d: bad column index %d", i,
+                  p.col);
+    if (p.kind < COMPASS_PRED_POINT || p.kind > COMPASS_PRED_SUBSET)
+      return fail(COMPASS_E_ARG, "predicate %d: bad kind %d", i, p.kind);
+    if (p.dtype != COMPASS_I32 && p.dtype != COMPASS_F32)
+      return fail(COMPASS_E_ARG, "predicate %d: dtype must be I32 or F32", i);
+    if (p.kind == COMPASS_PRED_SUBSET &&
+        (p.dtype != COMPASS_I32 || !p.bitmap || p.domain < 0))
+      return fail(COMPASS_E_ARG, "predicate %d: subset needs I32 codes, a "
+                  "bitmap and a domain >= 0", i);
+    PredDev &q = base.preds[i];
+    q.col = pred_cols ? pred_cols[p.col] : nullptr;
+    q.bitmap = p.bitmap;
+    q.domain = p.domain;
+    q.kind = p.kind;
+    q.dtype = p.dtype;
+    memcpy(&q.lo, &p.lo, 4);
+    memcpy(&q.hi, &p.hi, 4);
+  }
+  for (int s = 0; s < n_sketches; ++s) {
+    const compass_sketch_spec &k = sketches[s];
+    if (!k.seeds || !k.counters || (n_rows > 0 && !k.key_col))
+      return fail(COMPASS_E_ARG, "sketch %d: null pointer", s);
+    if (k.key_dtype != COMPASS_I32 && k.key_dtype != COMPASS_I64)
+      return fail(COMPASS_E_ARG, "sketch %d: key dtype must be I32 or I64", s);
+    for (int i = 0; i < 6 * d; ++i)
+      if (k.seeds[i] >= kP61)
+        return fail(COMPASS_E_ARG, "sketch %d: seed %d is not below 2^61-1",
+                    s, i);
+    base.keys[s].col = k.key_col;
+    base.keys[s].dtype = k.key_dtype;
+    base.counters[s] = k.counters;
+  }
+  (void)dtype_size;
+
+  DeviceState *ds;
+  compass_status st = device_state(&ds);
+  if (st != COMPASS_OK) return st;
+
+  if (!accumulate) {
+    ProfScope ps("fill_zero", stream);
+    for (int s = 0; s < n_sketches; ++s)
+      HIP_OK(launch_fill_zero(sketches[s].counters,
+                              (int64_t)d * w * (counter_bits / 8), stream));
+    HIP_OK(launch_fill_zero(n_selected, 8, stream));
+  }
+  if (n_rows == 0) return COMPASS_OK;
+
+  // slice groups: consecutive (sketch, row) slices whose int32 partials fit
+  // the LDS budget, balanced in size
+  const int S = n_sketches * d;
+  const int per_group_max = (int)std::min<size_t>(
+      kLdsBudget / ((size_t)w * 4), (size_t)kMaxLaunchSlices);
+  const int n_groups_total = (S + per_group_max - 1) / per_group_max;
+  const int per_group = (S + n_groups_total - 1) / n_groups_total;
+
+  // rows per chunk: enough chunks to fill the chip, but each chunk scans
+  // at least 16x as many rows as it merges counters
+  const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
+  int64_t target_blocks = 2048;
+  int64_t chunks = std::max<int64_t>(1, target_blocks / n_groups_total);
+  const int64_t min_rows = std::max<int64_t>(kBuildTile,
+                                             16ll * per_group * w);
+  chunks = std::min(chunks, std::max<int64_t>(1, n_rows / min_rows));
+  chunks = std::min(chunks, tiles);
+  int64_t rows_per_chunk = (n_rows + chunks - 1) / chunks;
+  rows_per_chunk =
+      (rows_per_chunk + kBuildTile - 1) / kBuildTile * kBuildTile;
+  chunks = (n_rows + rows_per_chunk - 1) / rows_per_chunk;
+  base.rows_per_chunk = rows_per_chunk;
+
+  // launches: as many whole groups as the kernel-argument seed table holds
+  int slice = 0;
+  bool first = true;
+  while (slice < S) {
+    BuildParams P = base;
+    int ls = 0, ng = 0;
+    P.group_begin[0] = 0;
+    while (slice < S && ng < kMaxLaunchGroups) {
+      const int gs = std::min(per_group, S - slice);
+      if (ls + gs > kMaxLaunchSlices) break;
+      for (int q = 0; q < gs; ++q) {
+        const int gsl = slice + q;
+        const int s = gsl / d, i = gsl % d;
+        P.slice_sketch[ls + q] = (int8_t)s;
+        P.slice_row[ls + q] = (int8_t)i;
+        const uint64_t *sd = sketches[s].seeds + 6 * i;
+        P.seeds[ls + q] = RowSeeds{sd[0], sd[1], sd[2], sd[3], sd[4], sd[5]};
+      }
+      ls += gs;
+      slice += gs;
+      ++ng;
+      P.group_begin[ng] = (int16_t)ls;
+    }
+    P.n_groups = ng;
+    P.count_selected = first ? 1 : 0;
+    first = false;
+    int max_group = 0;
+    for (int g = 0; g < ng; ++g)
+      max_group = std::max(max_group, P.group_begin[g + 1] - P.group_begin[g]);
+    const size_t lds = (size_t)max_group * w * 4 + (size_t)kBuildTile * 4;
+    const int64_t blocks = chunks * ng;
+    if (blocks > 0x7FFFFFFF)
+      return fail(COMPASS_E_RANGE, "too many workgroups");
+    ProfScope ps("scan_sketch", stream);
+    HIP_OK(launch_scan_sketch(P, (int)blocks, lds, stream));
+  }
+  return COMPASS_OK;
+}
+
+// ---------------------------------------------------------------------
+// compass_estimate: host planning
+// ---------------------------------------------------------------------
+namespace {
+
+struct PlanNode {
+  int table;
+  int parent = -1;        // node index
+  int parent_edge = -1;
+  std::vector<int> children;       // node indices
+  std::vector<int> child_edges;
+  int cut_edge = -1;
+  int height = 0;
+};
+
+struct Planner {
+  const compass_join_graph *g;
+  int d, w;
+  std::vector<NodeTask> tasks;
+  std::vector<int> task_level;
+  std::vector<TriTask> tris;
+  std::vector<SubplanTask> sps;
+  int n_msg_slots = 0, n_x_slots = 0, n_prep_slots = 0, n_partial_slots = 0;
+  int Lmax = 0, Lprep = 0;
+  std::vector<char> side_used;
+
+  int side_of(int table, int e) const {
+    return 2 * e + (g->edge_u[e] == table ? 0 : 1);
+  }
+};
+
+}  // namespace
+
+// Builds the rooted spanning tree of one sub-plan and its node tasks.
+static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
+  const compass_join_graph *g = pl.g;
+  SubplanTask sp;
+  memset(&sp, 0, sizeof(sp));
+  sp.mask = mask;
+  std::vector<int> tabs, edges;
+  for (int t = 0; t < g->n_tables; ++t)
+    if (mask >> t & 1ull) tabs.push_back(t);
+  for (int e = 0; e < g->n_edges; ++e)
+    if ((mask >> g->edge_u[e] & 1ull) && (mask >> g->edge_v[e] & 1ull))
+      edges.push_back(e);
+  sp.n_tables = (int)tabs.size();
+  sp.n_edges = (int)edges.size();
+  if (tabs.size() == 1) {
+    sp.type = kSpSingle;
+    sp.single_table = tabs[0];
+    pl.sps.push_back(sp);
+    return COMPASS_OK;
+  }
+  // BFS spanning tree from the lowest table, edges in id order
+  std::map<int, int> node_of;
+  std::vector<PlanNode> nodes;
+  nodes.push_back(PlanNode());
+  nodes[0].table = tabs[0];
+  node_of[tabs[0]] = 0;
+  std::vector<char> is_tree(g->n_edges, 0);
+  for (size_t head = 0; head < nodes.size(); ++head) {
+    const int t = nodes[head].table;
+    for (int e : edges) {
+      int other;
+      if (g->edge_u[e] == t)
+        other = g->edge_v[e];
+      else if (g->edge_v[e] == t)
+        other = g->edge_u[e];
+      else
+        continue;
+      if (node_of.count(other)) continue;
+      PlanNode nd;
+      nd.table = other;
+      node_of[other] = (int)nodes.size();
+      is_tree[e] = 1;
+      nodes.push_back(nd);
+    }
+  }
+  if (nodes.size() != tabs.size())
+    return fail(COMPASS_E_GRAPH, "sub-plan %d (mask 0x%llx) is not connected",
+                spi, (unsigned long long)mask);
+  std::vector<int> cuts;
+  for (int e : edges)
+    if (!is_tree[e]) cuts.push_back(e);
+
+  // undirected tree adjacency
+  const int nn = (int)nodes.size();
+  std::vector<std::vector<std::pair<int, int>>> adj(nn);
+  for (int e : edges) {
+    if (!is_tree[e]) continue;
+    const int a = node_of[g->edge_u[e]], b = node_of[g->edge_v[e]];
+    adj[a].push_back({b, e});
+    adj[b].push_back({a, e});
+  }
+  int root = 0;
+  int cut_u = -1, cut_v = -1, cut_e = -1;
+  bool supported = true;
+  if (cuts.size() > 1) supported = false;
+  if (cuts.size() == 1) {
+    cut_e = cuts[0];
+    cut_u = node_of[g->edge_u[cut_e]];
+    cut_v = node_of[g->edge_v[cut_e]];
+    // apex: a common tree neighbour of both endpoints (a triangle)
+    int apex = -1;
+    bool direct = false;
+    for (auto &pa : adj[cut_u]) {
+      if (pa.first == cut_v) direct = true;
+      for (auto &pb : adj[cut_v])
+        if (pa.first == pb.first) apex = pa.first;
+    }
+    if (direct || apex < 0)
+      supported = false;
+    else
+      root = apex;
+  }
+  if (!supported) {
+    sp.type = kSpUnsupported;
+    pl.sps.push_back(sp);
+    return COMPASS_OK;
+  }
+  // orient the tree at `root`
+  std::vector<int> order;
+  std::vector<char> seen(nn, 0);
+  order.push_back(root);
+  seen[root] = 1;
+  for (size_t h = 0; h < order.size(); ++h) {
+    const int a = order[h];
+    std::vector<std::pair<int, int>> nb = adj[a];
+    std::sort(nb.begin(), nb.end(),
+              [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+                return x.second < y.second;
+              });
+    for (auto &p : nb) {
+      if (seen[p.first]) continue;
+      seen[p.first] = 1;
+      nodes[p.first].parent = a;
+      nodes[p.first].parent_edge = p.second;
+      nodes[a].children.push_back(p.first);
+      nodes[a].child_edges.push_back(p.second);
+      order.push_back(p.first);
+    }
+  }
+  if (cut_e >= 0) {
+    nodes[cut_u].cut_edge = cut_e;
+    nodes[cut_v].cut_edge = cut_e;
+  }
+  for (int k = nn - 1; k >= 0; --k) {
+    PlanNode &nd = nodes[order[k]];
+    for (int c : nd.children)
+      nd.height = std::max(nd.height, nodes[c].height + 1);
+    if ((int)nd.children.size() > kMaxChild) {
+      sp.type = kSpUnsupported;
+      pl.sps.push_back(sp);
+      return COMPASS_OK;
+    }
+  }
+  // tasks: every non-root node emits a message slot; cut endpoints also a
+  // cut-constant slot
+  std::vector<int> msg_slot(nn, -1), cmsg_slot(nn, -1);
+  for (int a = 0; a < nn; ++a) {
+    if (a != root) msg_slot[a] = pl.n_msg_slots++;
+    if (nodes[a].cut_edge >= 0) cmsg_slot[a] = pl.n_msg_slots++;
+  }
+  for (int k = nn - 1; k >= 0; --k) {
+    const int a = order[k];
+    PlanNode &nd = nodes[a];
+    NodeTask T;
+    memset(&T, 0, sizeof(T));
+    T.m = (int)nd.children.size();
+    T.parent_side = -1;
+    T.cut_side = -1;
+    T.msg_slot = msg_slot[a];
+    T.cmsg_slot = cmsg_slot[a];
+    for (int c = 0; c < T.m; ++c) {
+      const int e = nd.child_edges[c];
+      T.child_side[c] = pl.side_of(nd.table, e);
+      T.child_eid[c] = e;
+      T.child_msg[c] = msg_slot[nd.children[c]];
+      T.child_cut[c] = -1;
+      pl.side_used[T.child_side[c]] = 1;
+    }
+    int nl = T.m;
+    if (a != root) {
+      T.parent_side = pl.side_of(nd.table, nd.parent_edge);
+      T.parent_eid = nd.parent_edge;
+      pl.side_used[T.parent_side] = 1;
+      ++nl;
+    }
+    if (nd.cut_edge >= 0) {
+      T.cut_side = pl.side_of(nd.table, nd.cut_edge);
+      T.cut_eid = nd.cut_edge;
+      pl.side_used[T.cut_side] = 1;
+      ++nl;
+    }
+    if (a != root) {
+      T.mode = kModeMessage;
+    } else if (cut_e < 0) {
+      T.mode = kModeTreeRoot;
+      T.out_slot = pl.n_x_slots++;
+      sp.type = kSpTree;
+      sp.x_slot = T.out_slot;
+    } else {
+      T.mode = kModeTriRootPrep;
+      T.out_slot = pl.n_prep_slots++;
+      for (int c = 0; c < T.m; ++c) {
+        const int ch = nd.children[c];
+        if (ch == cut_u) T.child_cut[c] = 0;
+        if (ch == cut_v) T.child_cut[c] = 1;
+      }
+      pl.Lprep = std::max(pl.Lprep, T.m * pl.w);
+      TriTask tr;
+      memset(&tr, 0, sizeof(tr));
+      tr.prep_slot = T.out_slot;
+      tr.L = T.m * pl.w;
+      tr.m = T.m;
+      tr.cut_eid = cut_e;
+      tr.cut_side[0] = pl.side_of(nodes[cut_u].table, cut_e);
+      tr.cut_side[1] = pl.side_of(nodes[cut_v].table, cut_e);
+      tr.cut_cmsg[0] = cmsg_slot[cut_u];
+      tr.cut_cmsg[1] = cmsg_slot[cut_v];
+      for (int c = 0; c < T.m; ++c) {
+        if (nd.children[c] == cut_u) tr.cut_child[0] = c;
+        if (nd.children[c] == cut_v) tr.cut_child[1] = c;
+      }
+      const int zb = (pl.w + kLaneThreads - 1) / kLaneThreads;
+      tr.partial_slot = pl.n_partial_slots;
+      pl.n_partial_slots += zb;
+      sp.type = kSpTriangle;
+      sp.x_slot = tr.partial_slot;
+      sp.n_partials = zb;
+      pl.tris.push_back(tr);
+    }
+    if (T.m > 0) pl.Lmax = std::max(pl.Lmax, nl * pl.w);
+    pl.tasks.push_back(T);
+    pl.task_level.push_back(nd.height);
+  }
+  pl.sps.push_back(sp);
+  return COMPASS_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" compass_status compass_estimate(const compass_join_graph *g,
+                                           const uint64_t *masks,
+                                           int32_t n_subplans,
+                                           compass_i128 *row_est, double *est,
+                                           int32_t *flags,
+                                           hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  if (!g || !masks || !est || !flags)
+    return fail(COMPASS_E_ARG, "null pointer argument");
+  if (n_subplans < 0) return fail(COMPASS_E_ARG, "n_subplans < 0");
+  if (n_subplans == 0) return COMPASS_OK;
+  if (g->n_tables < 1 || g->n_tables > 64)
+    return fail(COMPASS_E_RANGE, "n_tables=%d outside [1, 64]", g->n_tables);
+  if (g->n_edges < 0 || g->n_edges > 64)
+    return fail(COMPASS_E_RANGE, "n_edges=%d outside [0, 64]", g->n_edges);
+  if (g->d < 1 || g->d > 32)
+    return fail(COMPASS_E_ARG, "d=%d outside [1, 32]", g->d);
+  if (g->w < 1 || g->w > kMaxEstimateW)
+    return fail(COMPASS_E_UNSUPPORTED, "w=%d outside [1, %d]", g->w,
+                kMaxEstimateW);
+  if (g->counter_bits != 32 && g->counter_bits != 64)
+    return fail(COMPASS_E_ARG, "counter_bits must be 32 or 64");
+  if (!g->n_selected || (g->n_edges > 0 && (!g->edge_u || !g->edge_v ||
+                                            !g->sketch)))
+    return fail(COMPASS_E_ARG, "null graph array");
+  for (int e = 0; e < g->n_edges; ++e) {
+    if (g->edge_u[e] < 0 || g->edge_u[e] >= g->n_tables || g->edge_v[e] < 0 ||
+        g->edge_v[e] >= g->n_tables || g->edge_u[e] == g->edge_v[e])
+      return fail(COMPASS_E_GRAPH, "edge %d has bad endpoints", e);
+    if (!g->sketch[2 * e] || !g->sketch[2 * e + 1])
+      return fail(COMPASS_E_GRAPH, "edge %d lacks a sketch", e);
+  }
+  const uint64_t all =
+      g->n_tables == 64 ? ~0ull : ((1ull << g->n_tables) - 1);
+  for (int i = 0; i < n_subplans; ++i)
+    if (masks[i] == 0 || (masks[i] & ~all))
+      return fail(COMPASS_E_GRAPH, "sub-plan %d: mask 0x%llx is empty or "
+                  "names a missing table", i, (unsigned long long)masks[i]);
+
+  Planner pl;
+  pl.g = g;
+  pl.d = g->d;
+  pl.w = g->w;
+  pl.side_used.assign(2 * g->n_edges, 0);
+  for (int i = 0; i < n_subplans; ++i) {
+    compass_status s = plan_subplan(pl, masks[i], i);
+    if (s != COMPASS_OK) return s;
+  }
+
+  DeviceState *ds;
+  compass_status st = device_state(&ds);
+  if (st != COMPASS_OK) return st;
+
+  // sort jobs
+  std::vector<int32_t> sort_jobs;
+  for (int s = 0; s < 2 * g->n_edges; ++s)
+    if (pl.side_used[s]) sort_jobs.push_back(s);
+  // levels
+  int max_level = 0;
+  for (int lv : pl.task_level) max_level = std::max(max_level, lv);
+  std::vector<std::vector<NodeTask>> levels(max_level + 1);
+  for (size_t k = 0; k < pl.tasks.size(); ++k)
+    levels[pl.task_level[k]].push_back(pl.tasks[k]);
+  size_t max_level_tasks = 0;
+  std::vector<NodeTask> flat;
+  std::vector<size_t> level_off;
+  for (auto &lv : levels) {
+    for (size_t k = 0; k < lv.size(); ++k) lv[k].scratch_slot = (int)k;
+    level_off.push_back(flat.size());
+    flat.insert(flat.end(), lv.begin(), lv.end());
+    max_level_tasks = std::max(max_level_tasks, lv.size());
+  }
+  const int d = g->d, w = g->w;
+  // scratch layout
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t o_sides = carve(sizeof(void *) * std::max(1, 2 * g->n_edges));
+  const size_t o_jobs = carve(sizeof(int32_t) * std::max<size_t>(1, sort_jobs.size()));
+  const size_t o_tasks = carve(sizeof(NodeTask) * std::max<size_t>(1, flat.size()));
+  const size_t o_tris = carve(sizeof(TriTask) * std::max<size_t>(1, pl.tris.size()));
+  const size_t o_sps = carve(sizeof(SubplanTask) * pl.sps.size());
+  const size_t o_sorted = carve(sizeof(uint64_t) * 2 * g->n_edges * d * (size_t)w);
+  const size_t o_msg = carve(16ull * pl.n_msg_slots * d * (size_t)w);
+  const size_t o_merged = carve(4ull * max_level_tasks * d * (size_t)std::max(1, pl.Lmax));
+  const size_t o_xout = carve(16ull * std::max(1, pl.n_x_slots) * d);
+  const size_t np = std::max(1, pl.n_prep_slots);
+  const size_t lp = std::max(1, pl.Lprep);
+  const size_t o_pmeta = carve(4ull * np * d * lp);
+  const size_t o_pv = carve(8ull * np * d * lp);
+  const size_t o_pmu = carve(16ull * np * d * lp);
+  const size_t o_pkey = carve(8ull * np * d * lp);
+  const size_t o_part = carve(16ull * std::max(1, pl.n_partial_slots) * d);
+  void *scratch;
+  st = ensure_scratch(ds, off, &scratch);
+  if (st != COMPASS_OK) return st;
+  char *base = reinterpret_cast<char *>(scratch);
+
+  // one staging upload of every host-built table
+  std::vector<char> host(o_sorted, 0);
+  memcpy(host.data() + o_sides, g->sketch, sizeof(void *) * 2 * g->n_edges);
+  if (!sort_jobs.empty())
+    memcpy(host.data() + o_jobs, sort_jobs.data(), 4 * sort_jobs.size());
+  if (!flat.empty())
+    memcpy(host.data() + o_tasks, flat.data(), sizeof(NodeTask) * flat.size());
+  if (!pl.tris.empty())
+    memcpy(host.data() + o_tris, pl.tris.data(), sizeof(TriTask) * pl.tris.size());
+  memcpy(host.data() + o_sps, pl.sps.data(), sizeof(SubplanTask) * pl.sps.size());
+  st = upload(ds, base, host.data(), o_sorted, stream);
+  if (st != COMPASS_OK) return st;
+
+  EstBuffers B;
+  memset(&B, 0, sizeof(B));
+  B.sides = reinterpret_cast<const void *const *>(base + o_sides);
+  B.n_sel = g->n_selected;
+  B.sorted = reinterpret_cast<const uint64_t *>(base + o_sorted);
+  B.msg = reinterpret_cast<u128 *>(base + o_msg);
+  B.merged = reinterpret_cast<uint32_t *>(base + o_merged);
+  B.xout = reinterpret_cast<u128 *>(base + o_xout);
+  B.prep_meta = reinterpret_cast<uint32_t *>(base + o_pmeta);
+  B.prep_v = reinterpret_cast<int64_t *>(base + o_pv);
+  B.prep_mu = reinterpret_cast<u128 *>(base + o_pmu);
+  B.prep_key = reinterpret_cast<uint64_t *>(base + o_pkey);
+  B.partial = reinterpret_cast<u128 *>(base + o_part);
+  B.counter_bits = g->counter_bits;
+  B.d = d;
+  B.w = w;
+  B.Lmax = std::max(1, pl.Lmax);
+  B.Lprep = (int)lp;
+
+  if (!sort_jobs.empty()) {
+    ProfScope ps("sort_rows", stream);
+    HIP_OK(launch_sort_rows(reinterpret_cast<const int32_t *>(base + o_jobs),
+                            (int)sort_jobs.size(), B, stream));
+  }
+  const NodeTask *dtasks = reinterpret_cast<const NodeTask *>(base + o_tasks);
+  for (size_t lv = 0; lv < levels.size(); ++lv) {
+    if (levels[lv].empty()) continue;
+    ProfScope ps("node", stream);
+    HIP_OK(launch_node(dtasks + level_off[lv], (int)levels[lv].size(), B,
+                       stream));
+  }
+  if (!pl.tris.empty()) {
+    ProfScope ps("tri_lane", stream);
+    HIP_OK(launch_tri_lane(reinterpret_cast<const TriTask *>(base + o_tris),
+                           (int)pl.tris.size(),
+                           (w + kLaneThreads - 1) / kLaneThreads, B, stream));
+  }
+  {
+    ProfScope ps("finish", stream);
+    HIP_OK(launch_finish(reinterpret_cast<const SubplanTask *>(base + o_sps),
+                         (int)pl.sps.size(), B,
+                         reinterpret_cast<uint64_t *>(row_est), est, flags,
+                         g->n_tables, stream));
+  }
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end()) return COMPASS_OK;
+  DeviceState &ds = it->second;
+  HIP_OK(hipDeviceSynchronize());
+  if (ds.scratch) HIP_OK(hipFree(ds.scratch));
+  ds.scratch = nullptr;
+  ds.scratch_bytes = 0;
+  for (int k = 0; k < DeviceState::kRing; ++k) {
+    if (ds.pinned[k]) HIP_OK(hipHostFree(ds.pinned[k]));
+    ds.pinned[k] = nullptr;
+    ds.pinned_bytes[k] = 0;
+    ds.pinned_used[k] = false;
+  }
+  return COMPASS_OK;
+}
+
+extern "C" const char *compass_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *compass_version(void) { return "compass-gfx950 0.1.0"; }

@@ -1,0 +1,63 @@
+// build_params.hpp -- kernel-argument layout of the fused scan + sketch build.
+#pragma once
+#include <stdint.h>
+
+#include "device_math.hpp"
+
+namespace compass {
+
+constexpr int kBuildThreads = 1024;
+constexpr int kBuildRowsPerThread = 4;
+constexpr int kBuildTile = kBuildThreads * kBuildRowsPerThread;
+constexpr int kMaxPreds = 8;
+constexpr int kMaxSketches = 16;
+constexpr int kMaxLaunchSlices = 48;   // slices whose seeds ride in kernargs
+constexpr int kMaxLaunchGroups = 16;
+constexpr size_t kLdsBudget = 128 * 1024;  // partial counters per workgroup
+
+enum { kDtI32 = 0, kDtF32 = 1, kDtI64 = 2 };
+enum { kPredPoint = 0, kPredRange = 1, kPredSubset = 2 };
+
+union Scalar32 {
+  int32_t i;
+  float f;
+};
+
+struct PredDev {
+  const void *col;
+  const uint64_t *bitmap;
+  int64_t domain;
+  int32_t kind;
+  int32_t dtype;
+  Scalar32 lo, hi;
+};
+
+struct KeyDev {
+  const void *col;
+  int32_t dtype;
+  int32_t pad;
+};
+
+// One launch covers n_groups slice groups; group g owns launch-local
+// slices [group_begin[g], group_begin[g+1]).
+struct BuildParams {
+  int64_t n_rows;
+  int64_t rows_per_chunk;
+  int32_t n_preds;
+  int32_t n_groups;
+  int32_t counter_bits;
+  int32_t count_selected;
+  int64_t *n_selected;
+  BucketMod bm;
+  PredDev preds[kMaxPreds];
+  KeyDev keys[kMaxSketches];
+  void *counters[kMaxSketches];
+  int8_t slice_sketch[kMaxLaunchSlices];
+  int8_t slice_row[kMaxLaunchSlices];
+  int16_t group_begin[kMaxLaunchGroups + 1];
+  RowSeeds seeds[kMaxLaunchSlices];
+};
+
+static_assert(sizeof(BuildParams) <= 4096, "kernel arguments must stay small");
+
+}  // namespace compass

@@ -1,0 +1,480 @@
+// estimate_kernels.hip -- merged-sketch join-size estimates on gfx950.
+//
+// What is computed (Section 4.2.1 two-way estimate and median; Section 5.1
+// contraction; Section 5.2 min-abs sketch merging, generalised iteratively):
+// for a connected sub-plan C and sketch row i,
+//   X_i = sum over bucket assignments iota of C's induced edges of
+//         prod over tables t in C of merged_t(iota),
+// merged_t = the incident bucket of smallest |value|, ties to the lower
+// edge id.  X_i is exact modulo 2^128.
+//
+// How (our exact re-association of that sum, never materialising tensors):
+// order every bucket element of a table by kappa = (|value|, edge id); the
+// merged value is the element of smallest kappa.  On a rooted spanning tree
+// the message of table t to its parent for parent bucket j is
+//   M(j) = x_j * prod_c A_c(kappa_j) + G(kappa_j)
+// with A_c(k) = sum of child-c message values over child-c elements of
+// kappa > k and G(k) = sum over child elements z of kappa < k of
+// v_z * mu_z * prod_{c' != c(z)} A_c'(kappa_z).  A node therefore needs its
+// incident bucket lists merged by kappa and two scans over the merged list.
+//
+// Kernels:
+//  sort_rows_kernel    one workgroup per (sketch, row): bitonic sort of the
+//                      w buckets by (|v|, j) in LDS (64-bit keys).
+//  node_kernel         one workgroup per (tree node, row): k-way merge of
+//                      the node's sorted lists by rank (binary search), then
+//                      block-wide scans of 128-bit A and G, emitting the
+//                      node's message (or the root's X).
+//  tri_lane_kernel     triangles: one lane per bucket J of the cut edge.
+//                      Fixing J turns each cut endpoint's message into
+//                      "M(j) if its parent-edge element ranks below the
+//                      fixed element, else the constant C(J)", so every
+//                      lane streams the apex's merged list (wave-uniform
+//                      scalar loads) with O(1) state.
+//  finish_kernel       per sub-plan: gathers X_i, median over rows,
+//                      round-to-nearest-even double, exactness certificate.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.hpp"
+#include "estimate_params.hpp"
+#include "estimate_buffers.hpp"
+
+namespace compass {
+
+
+
+__device__ __forceinline__ int64_t counter_at(const EstBuffers &B, int side,
+                                              int row, int j) {
+  const size_t idx = (size_t)row * B.w + j;
+  if (B.counter_bits == 32)
+    return reinterpret_cast<const int32_t *>(B.sides[side])[idx];
+  return reinterpret_cast<const int64_t *>(B.sides[side])[idx];
+}
+
+__device__ __forceinline__ const uint64_t *sorted_of(const EstBuffers &B,
+                                                     int side, int row) {
+  return B.sorted + ((size_t)side * B.d + row) * B.w;
+}
+
+__device__ __forceinline__ u128 *msg_of(const EstBuffers &B, int slot,
+                                        int row) {
+  return B.msg + ((size_t)slot * B.d + row) * B.w;
+}
+
+// number of keys < thr in a sorted array
+__device__ __forceinline__ int lower_bound_u64(const uint64_t *a, int n,
+                                               uint64_t thr) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < thr)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// |v| saturated below 2^47 (every sketch built from < 2^47 rows satisfies
+// this; saturation only keeps sort keys well-formed for foreign input)
+__device__ __forceinline__ uint64_t abs_u64(int64_t v) {
+  const uint64_t a = v < 0 ? 0ull - (uint64_t)v : (uint64_t)v;
+  return a < (1ull << 47) ? a : (1ull << 47) - 1;
+}
+
+// ---------------------------------------------------------------------
+// sort: grid (n_jobs, d); job_side[blockIdx.x] = sketch side to sort
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
+    const int32_t *job_side, EstBuffers B, int w2) {
+  extern __shared__ uint64_t skeys[];
+  const int side = job_side[blockIdx.x];
+  const int row = blockIdx.y;
+  const int w = B.w;
+  for (int j = threadIdx.x; j < w2; j += kSortThreads) {
+    uint64_t k = ~0ull;
+    if (j < w) k = (abs_u64(counter_at(B, side, row, j)) << 16) | (uint64_t)j;
+    skeys[j] = k;
+  }
+  __syncthreads();
+  for (int k = 2; k <= w2; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int i = threadIdx.x; i < w2; i += kSortThreads) {
+        const int ixj = i ^ jj;
+        if (ixj > i) {
+          const uint64_t a = skeys[i], b = skeys[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            skeys[i] = b;
+            skeys[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  uint64_t *out = const_cast<uint64_t *>(sorted_of(B, side, row));
+  for (int j = threadIdx.x; j < w; j += kSortThreads) out[j] = skeys[j];
+}
+
+// ---------------------------------------------------------------------
+// block scans over kNodeThreads 128-bit values
+// ---------------------------------------------------------------------
+__device__ u128 block_scan_incl(u128 v, u128 *sh, bool suffix) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kNodeThreads; off <<= 1) {
+    u128 add = 0;
+    if (suffix) {
+      if (t + off < kNodeThreads) add = sh[t + off];
+    } else {
+      if (t >= off) add = sh[t - off];
+    }
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const u128 r = sh[t];
+  __syncthreads();
+  return r;
+}
+
+struct ListRef {
+  int side;
+  int eid;
+};
+
+// list a of a node (a may differ across lanes: read through global memory
+// rather than indexing a register copy of the task)
+__device__ __forceinline__ ListRef list_of(const NodeTask *T, int a) {
+  ListRef r;
+  if (a < T->m) {
+    r.side = T->child_side[a];
+    r.eid = T->child_eid[a];
+  } else if (a == T->m && T->parent_side >= 0) {
+    r.side = T->parent_side;
+    r.eid = T->parent_eid;
+  } else {
+    r.side = T->cut_side;
+    r.eid = T->cut_eid;
+  }
+  return r;
+}
+
+__global__ __launch_bounds__(kNodeThreads) void node_kernel(
+    const NodeTask *tasks, EstBuffers B) {
+  __shared__ u128 sh[kNodeThreads];
+  const NodeTask *Tg = tasks + blockIdx.x;
+  const NodeTask T = *Tg;
+  const int row = blockIdx.y;
+  const int w = B.w;
+  const int m = T.m;
+  const int has_parent = T.parent_side >= 0;
+  const int has_cut = T.cut_side >= 0;
+  const int nl = m + has_parent + has_cut;
+
+  if (m == 0) {  // leaf: messages are the raw counters
+    if (T.mode != kModeMessage) return;
+    u128 *M = has_parent ? msg_of(B, T.msg_slot, row) : nullptr;
+    u128 *C = has_cut ? msg_of(B, T.cmsg_slot, row) : nullptr;
+    for (int j = threadIdx.x; j < w; j += kNodeThreads) {
+      if (M) M[j] = s64_to_u128(counter_at(B, T.parent_side, row, j));
+      if (C) C[j] = s64_to_u128(counter_at(B, T.cut_side, row, j));
+    }
+    return;
+  }
+
+  const int L = nl * w;
+  uint32_t *merged =
+      B.merged + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
+
+  // 1. k-way merge by rank: position = own index + elements of smaller
+  //    kappa in every other list (ties in |v| go to the lower edge id)
+  for (int e = threadIdx.x; e < L; e += kNodeThreads) {
+    const int a = e / w;
+    const int k = e - a * w;
+    const ListRef la = list_of(Tg, a);
+    const uint64_t key = sorted_of(B, la.side, row)[k];
+    const uint64_t absv = key >> 16;
+    const uint32_t j = (uint32_t)(key & 0xFFFF);
+    int pos = k;
+    for (int b = 0; b < nl; ++b) {
+      if (b == a) continue;
+      const ListRef lb = list_of(Tg, b);
+      const uint64_t thr = (absv + (lb.eid < la.eid ? 1 : 0)) << 16;
+      pos += lower_bound_u64(sorted_of(B, lb.side, row), w, thr);
+    }
+    merged[pos] = ((uint32_t)a << 16) | j;
+  }
+  __syncthreads();
+
+  if (T.mode == kModeTriRootPrep) {
+    const size_t base = ((size_t)T.out_slot * B.d + row) * (size_t)B.Lprep;
+    for (int pos = threadIdx.x; pos < L; pos += kNodeThreads) {
+      const uint32_t mt = merged[pos];
+      const int a = (int)(mt >> 16);
+      const int j = (int)(mt & 0xFFFF);
+      B.prep_meta[base + pos] = mt;
+      B.prep_v[base + pos] = counter_at(B, Tg->child_side[a], row, j);
+      B.prep_mu[base + pos] = msg_of(B, Tg->child_msg[a], row)[j];
+      uint64_t key = 0;
+      if (Tg->child_cut[a] >= 0) {
+        // kappa of the child's own bucket on the edge to the apex
+        const int other = Tg->child_side[a] ^ 1;
+        key = (abs_u64(counter_at(B, other, row, j)) << 7) |
+              (uint64_t)Tg->child_eid[a];
+      }
+      B.prep_key[base + pos] = key;
+    }
+    return;
+  }
+
+  // 2. my segment of the merged list
+  const int seg = (L + kNodeThreads - 1) / kNodeThreads;
+  const int s0 = min(L, (int)threadIdx.x * seg);
+  const int s1 = min(L, s0 + seg);
+
+  u128 tot[kMaxChild];
+#pragma unroll
+  for (int c = 0; c < kMaxChild; ++c) tot[c] = 0;
+  for (int pos = s0; pos < s1; ++pos) {
+    const uint32_t mt = merged[pos];
+    const int a = (int)(mt >> 16);
+    if (a >= m) continue;
+    const u128 mu = msg_of(B, Tg->child_msg[a], row)[mt & 0xFFFF];
+#pragma unroll
+    for (int c = 0; c < kMaxChild; ++c)
+      if (c == a) tot[c] += mu;
+  }
+  u128 A0[kMaxChild];  // A at the start of my segment (inclusive)
+#pragma unroll
+  for (int c = 0; c < kMaxChild; ++c) {
+    A0[c] = 0;
+    if (c < m) A0[c] = block_scan_incl(tot[c], sh, true);
+  }
+
+  // 3. term sums of my segment
+  u128 A[kMaxChild];
+#pragma unroll
+  for (int c = 0; c < kMaxChild; ++c) A[c] = A0[c];
+  u128 gl = 0;
+  for (int pos = s0; pos < s1; ++pos) {
+    const uint32_t mt = merged[pos];
+    const int a = (int)(mt >> 16);
+    if (a >= m) continue;
+    const int j = (int)(mt & 0xFFFF);
+    const u128 mu = msg_of(B, Tg->child_msg[a], row)[j];
+    u128 term = mul_s64_u128(counter_at(B, Tg->child_side[a], row, j), mu);
+#pragma unroll
+    for (int c = 0; c < kMaxChild; ++c) {
+      if (c < m && c != a) term = mul_u128(term, A[c]);
+      if (c == a) A[c] -= mu;
+    }
+    gl += term;
+  }
+  const u128 gincl = block_scan_incl(gl, sh, false);
+
+  if (T.mode == kModeTreeRoot) {
+    if (threadIdx.x == kNodeThreads - 1)
+      B.xout[(size_t)T.out_slot * B.d + row] = gincl;
+    return;
+  }
+
+  // 4. emit the message (parent list) and cut constants (cut list)
+  u128 G = gincl - gl;
+#pragma unroll
+  for (int c = 0; c < kMaxChild; ++c) A[c] = A0[c];
+  u128 *M = has_parent ? msg_of(B, T.msg_slot, row) : nullptr;
+  u128 *C = has_cut ? msg_of(B, T.cmsg_slot, row) : nullptr;
+  for (int pos = s0; pos < s1; ++pos) {
+    const uint32_t mt = merged[pos];
+    const int a = (int)(mt >> 16);
+    const int j = (int)(mt & 0xFFFF);
+    if (a < m) {
+      const u128 mu = msg_of(B, Tg->child_msg[a], row)[j];
+      u128 term = mul_s64_u128(counter_at(B, Tg->child_side[a], row, j), mu);
+#pragma unroll
+      for (int c = 0; c < kMaxChild; ++c) {
+        if (c < m && c != a) term = mul_u128(term, A[c]);
+        if (c == a) A[c] -= mu;
+      }
+      G += term;
+    } else {
+      const ListRef la = list_of(Tg, a);
+      u128 p = s64_to_u128(counter_at(B, la.side, row, j));
+#pragma unroll
+      for (int c = 0; c < kMaxChild; ++c)
+        if (c < m) p = mul_u128(p, A[c]);
+      const bool is_parent = has_parent && a == m;
+      (is_parent ? M : C)[j] = p + G;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------
+// triangle apex sweep: grid (n_tri, d, ceil(w / kLaneThreads))
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
+    const TriTask *tasks, EstBuffers B) {
+  __shared__ u128 red[kLaneThreads];
+  const TriTask T = tasks[blockIdx.x];
+  const int row = blockIdx.y;
+  const int J = blockIdx.z * kLaneThreads + threadIdx.x;
+  const bool active = J < B.w;
+  const int Jc = active ? J : 0;
+
+  uint64_t kf[2];
+  u128 cval[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    kf[e] = (abs_u64(counter_at(B, T.cut_side[e], row, Jc)) << 7) |
+            (uint64_t)T.cut_eid;
+    cval[e] = msg_of(B, T.cut_cmsg[e], row)[Jc];
+  }
+  const size_t base = ((size_t)T.prep_slot * B.d + row) * (size_t)B.Lprep;
+  const uint32_t *meta = B.prep_meta + base;
+  const int64_t *pv = B.prep_v + base;
+  const u128 *pmu = B.prep_mu + base;
+  const uint64_t *pkey = B.prep_key + base;
+  const int m = T.m;
+  const int cu = T.cut_child[0], cv = T.cut_child[1];
+
+  u128 A[kMaxChild];
+#pragma unroll
+  for (int c = 0; c < kMaxChild; ++c) A[c] = 0;
+  u128 G = 0;
+  for (int pos = T.L - 1; pos >= 0; --pos) {
+    const int a = (int)(meta[pos] >> 16);
+    const int64_t v = pv[pos];
+    u128 mu = pmu[pos];
+    const uint64_t key = pkey[pos];
+    if (a == cu) mu = key < kf[0] ? mu : cval[0];
+    if (a == cv) mu = key < kf[1] ? mu : cval[1];
+    u128 term = mul_s64_u128(v, mu);
+#pragma unroll
+    for (int c = 0; c < kMaxChild; ++c) {
+      if (c < m && c != a) term = mul_u128(term, A[c]);
+    }
+    G += term;
+#pragma unroll
+    for (int c = 0; c < kMaxChild; ++c)
+      if (c == a) A[c] += mu;
+  }
+  red[threadIdx.x] = active ? G : (u128)0;
+  __syncthreads();
+  for (int off = kLaneThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    B.partial[((size_t)T.partial_slot + blockIdx.z) * B.d + row] = red[0];
+}
+
+// ---------------------------------------------------------------------
+// per sub-plan: rows, median, double, certificate
+// ---------------------------------------------------------------------
+__global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
+                              uint64_t *row_est, double *est, int32_t *flags,
+                              int32_t n_tables) {
+  __shared__ u128 xs[64];
+  const SubplanTask S = sps[blockIdx.x];
+  const int d = B.d;
+  const int i = threadIdx.x;
+  if (i < d) {
+    u128 x = 0;
+    if (S.type == kSpSingle) {
+      x = s64_to_u128(B.n_sel[S.single_table]);
+    } else if (S.type == kSpTree) {
+      x = B.xout[(size_t)S.x_slot * d + i];
+    } else if (S.type == kSpTriangle) {
+      for (int z = 0; z < S.n_partials; ++z)
+        x += B.partial[((size_t)S.x_slot + z) * d + i];
+    }
+    xs[i] = x;
+    if (row_est) {
+      row_est[((size_t)blockIdx.x * d + i) * 2 + 0] = (uint64_t)x;
+      row_est[((size_t)blockIdx.x * d + i) * 2 + 1] = (uint64_t)(x >> 64);
+    }
+  }
+  __syncthreads();
+  if (i != 0) return;
+  if (S.type == kSpUnsupported) {
+    est[blockIdx.x] = __builtin_nan("");
+    flags[blockIdx.x] = 2;
+    return;
+  }
+  // insertion sort as signed 128-bit values
+  for (int a = 1; a < d; ++a) {
+    const u128 v = xs[a];
+    int b = a - 1;
+    while (b >= 0 && (__int128)xs[b] > (__int128)v) {
+      xs[b + 1] = xs[b];
+      --b;
+    }
+    xs[b + 1] = v;
+  }
+  double e;
+  if (d & 1)
+    e = i128_to_double(xs[d / 2]);
+  else
+    e = i128_to_double(xs[d / 2 - 1] + xs[d / 2]) * 0.5;
+  est[blockIdx.x] = e;
+  // certificate: prod n_sel * w^(E - V) < 2^127
+  const u128 lim = (u128)1 << 127;
+  u128 b = 1;
+  bool ok = true, zero = false;
+  for (int t = 0; t < n_tables && ok; ++t) {
+    if (!((S.mask >> t) & 1ull)) continue;
+    const int64_t ns = B.n_sel[t];
+    const u128 f = ns < 0 ? 0 : (u128)ns;
+    if (f == 0) {
+      zero = true;
+      break;
+    }
+    if (b > lim / f) ok = false; else b *= f;
+  }
+  if (!zero)
+    for (int k = 0; k < S.n_edges - S.n_tables && ok; ++k) {
+      if (b > lim / (u128)B.w) ok = false; else b *= (u128)B.w;
+    }
+  flags[blockIdx.x] = (zero || (ok && b < lim)) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------
+hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
+                            const EstBuffers &B, hipStream_t st) {
+  int w2 = 1;
+  while (w2 < B.w) w2 <<= 1;
+  hipLaunchKernelGGL(sort_rows_kernel, dim3(n_jobs, B.d), dim3(kSortThreads),
+                     (size_t)w2 * sizeof(uint64_t), st, job_side, B, w2);
+  return hipGetLastError();
+}
+
+hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(node_kernel, dim3(n, B.d), dim3(kNodeThreads), 0, st,
+                     tasks, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
+                           const EstBuffers &B, hipStream_t st) {
+  hipLaunchKernelGGL(tri_lane_kernel, dim3(n, B.d, zblocks),
+                     dim3(kLaneThreads), 0, st, tasks, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
+                         uint64_t *row_est, double *est, int32_t *flags,
+                         int32_t n_tables, hipStream_t st) {
+  hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(64), 0, st, sps, B, row_est,
+                     est, flags, n_tables);
+  return hipGetLastError();
+}
+
+
+}  // namespace compass

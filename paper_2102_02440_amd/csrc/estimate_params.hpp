@@ -1,0 +1,61 @@
+// estimate_params.hpp -- device-side plan of a compass_estimate call.
+#pragma once
+#include <stdint.h>
+
+namespace compass {
+
+constexpr int kMaxChild = 6;
+constexpr int kNodeThreads = 256;
+constexpr int kSortThreads = 1024;
+constexpr int kLaneThreads = 256;
+constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
+
+enum { kModeMessage = 0, kModeTreeRoot = 1, kModeTriRootPrep = 2 };
+enum { kSpSingle = 0, kSpTree = 1, kSpTriangle = 2, kSpUnsupported = 3 };
+
+// One node of one sub-plan's rooted spanning tree (blockIdx.y = sketch row).
+// Lists: children 0..m-1 (weighted by their messages), then the parent
+// bucket list (query points of the outgoing message) if parent_side >= 0,
+// then the cut-edge bucket list (query points of the cut constants) if
+// cut_side >= 0.
+struct NodeTask {
+  int32_t mode;
+  int32_t m;
+  int32_t parent_side, parent_eid;
+  int32_t cut_side, cut_eid;
+  int32_t msg_slot;    // message out (mode 0)
+  int32_t cmsg_slot;   // cut constants out (mode 0 with a cut edge)
+  int32_t out_slot;    // tree-root X slot (mode 1) / root-prep slot (mode 2)
+  int32_t scratch_slot;
+  int32_t child_side[kMaxChild];
+  int32_t child_eid[kMaxChild];
+  int32_t child_msg[kMaxChild];
+  int32_t child_cut[kMaxChild];   // mode 2: index (0/1) of the cut endpoint, or -1
+  int32_t child_parent_eid[kMaxChild];  // mode 2: edge id of the child's parent edge
+};
+
+// Triangle sub-plan: the root (apex) sweeps its merged child list once per
+// cut-edge bucket J; the two cut endpoints' messages switch to their cut
+// constant when their parent-edge element ranks above the cut element.
+struct TriTask {
+  int32_t prep_slot;        // root merged-list arrays
+  int32_t L;                // root merged-list length
+  int32_t m;                // root children
+  int32_t cut_eid;
+  int32_t cut_side[2];      // sides (endpoint u, endpoint v) of the cut edge
+  int32_t cut_cmsg[2];      // cut-constant slots of u and v
+  int32_t cut_child[2];     // root child slots of u and v
+  int32_t partial_slot;     // first of gridDim.z partial sums
+};
+
+struct SubplanTask {
+  int32_t type;
+  int32_t n_tables;
+  int32_t n_edges;
+  int32_t single_table;
+  int32_t x_slot;           // tree: X slot; triangle: first partial slot
+  int32_t n_partials;
+  uint64_t mask;
+};
+
+}  // namespace compass

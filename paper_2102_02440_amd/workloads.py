@@ -92,18 +92,22 @@ def draw_seeds(rng: np.random.Generator, n_edges: int, d: int) -> np.ndarray:
 
 
 class Zipf:
-    """Zipf(s) ranks over [0, n): P(rank k) proportional to (k+1)^-s."""
+    """Zipf(s) ranks over [0, n): P(rank k) proportional to (k+1)^-s.
+
+    A sample of ``size`` draws is taken as multinomial counts per rank,
+    expanded and shuffled (the same distribution as ``size`` independent
+    draws, at a fraction of the cost of inverse-CDF search)."""
 
     def __init__(self, n: int, s: float):
         w = np.arange(1, n + 1, dtype=np.float64) ** (-float(s))
-        cdf = np.cumsum(w)
-        self.cdf = cdf / cdf[-1]
+        self.p = w / w.sum()
         self.n = n
 
     def sample(self, rng: np.random.Generator, size: int) -> np.ndarray:
-        u = rng.random(size)
-        r = np.searchsorted(self.cdf, u, side="right")
-        return np.minimum(r, self.n - 1)
+        counts = rng.multinomial(size, self.p)
+        ranks = np.repeat(np.arange(self.n, dtype=np.int64), counts)
+        rng.shuffle(ranks)
+        return ranks
 
 
 def fk_column(rng, size, domain, s, perm, dtype=np.int32):
