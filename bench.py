@@ -34,6 +34,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=3_000_000,
                     help="cast_info rows in the oracle's timed sample")
+    ap.add_argument("--workload", default="job6a",
+                    choices=["job6a", "batch", "learned", "large"],
+                    help="job6a: the headline step (default); batch: 512 "
+                         "queries in one graph-captured persistent launch vs "
+                         "one launch per sketch; learned: train + evaluate "
+                         "the correction network")
+    ap.add_argument("--queries", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=30)
     return ap.parse_args()
 
 
@@ -90,6 +98,186 @@ def main():
               "the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "learned":
+        return run_learned(args)
+    if args.workload == "large":
+        return run_large(args)
+    return run_job6a(args)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_batch(args):
+    """512 queries (2..17 tables over a pool of 48 tables of 10k..36M rows,
+    ~4k attribute sketches, d in {5,7,11}, w in {1024..16384}): the batched
+    persistent graph-captured build vs the plain path (one launch per
+    sketch), same counters bit for bit."""
+    import torch
+    from paper_2102_02440_amd import compass as C
+    from paper_2102_02440_amd import workloads as W
+    seed = W.DEFAULT_SEED if args.seed is None else args.seed
+    t0 = time.time()
+    pool = W.schema_pool(seed)
+    qs = W.query_batch(pool, seed, n_queries=args.queries)
+    log("[bench] pool %d rows, %d queries in %.1fs" % (
+        sum(p.n_rows for p in pool), len(qs), time.time() - t0))
+    db = C.DeviceBatch(pool, qs)
+    n_sketch = sum(len(j["keys"]) for j in db.jobs)
+    rows = sum(j["n_rows"] for j in db.jobs)
+    t0 = time.time()
+    plan = db.plan()
+    info = plan.info()
+    log("[bench] plan %s in %.1fs" % (info, time.time() - t0))
+
+    def timed(fn, k):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / k
+
+    t_batch = timed(plan.launch, args.steps)
+    snap = [[x.clone() for x in sides] for sides in db.sides]
+    t_plain = timed(db.build_per_sketch, max(1, args.steps // 2))
+    same = all(torch.equal(a, b) for sa, sb in zip(snap, db.sides) for a, b in zip(sa, sb))
+    t_table = timed(db.build_per_table, max(1, args.steps // 2))
+    out = {"metric": "filtered rows sketched/s (% HBM roofline); subplan estimates/s at q-error",
+           "value": rows / t_batch, "unit": "rows/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": t_batch * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic",
+           "config": {"workload": "batched: %d queries, %d scan jobs, %d attribute "
+                                  "sketches over a 48-table pool (10k..36M rows)"
+                                  % (len(qs), len(db.jobs), n_sketch),
+                      "rows_per_step": rows, "parallelism": "single-gpu"},
+           "sketches_per_s": n_sketch / t_batch,
+           "plain_one_launch_per_sketch_ms": t_plain * 1e3,
+           "one_launch_per_table_ms": t_table * 1e3,
+           "speedup_vs_plain": t_plain / t_batch,
+           "bit_exact_vs_plain": bool(same), "plan": info}
+    print(json.dumps(out), flush=True)
+
+
+def run_learned(args):
+    """Trains the correction network with the library's kernels on ~213k
+    sub-plans (exact truths stored by tests/golden/make_learned_truth.py)
+    and evaluates it against the raw median estimate on ~21k held-out
+    sub-plans from disjoint seeds."""
+    import numpy as np
+    import torch
+    from paper_2102_02440_amd import learned as Lrn
+    from paper_2102_02440_amd import workloads as W
+    tp = os.path.join(ROOT, "tests", "golden", "learned_truth.npz")
+    tr = np.load(tp)
+    n_tr, n_te = int(tr["n_train_queries"]), int(tr["n_test_queries"])
+    t0 = time.time()
+    pool_tr, q_tr = W.learned_workload(W.LEARNED_TRAIN_SEED, n_tr)
+    pool_te, q_te = W.learned_workload(W.LEARNED_TEST_SEED, n_te)
+    s_tr = W.learned_subplans(q_tr, W.LEARNED_TRAIN_SEED)
+    s_te = W.learned_subplans(q_te, W.LEARNED_TEST_SEED)
+    assert sum(map(len, s_tr)) == tr["train_true"].size
+    assert sum(map(len, s_te)) == tr["test_true"].size
+    log("[bench] learned workloads in %.1fs" % (time.time() - t0))
+    t0 = time.time()
+    x, b, e, f = Lrn.build_features(pool_tr, q_tr, s_tr, log=log)
+    torch.cuda.synchronize()
+    t_feat = time.time() - t0
+    xt, bt, et, ft = Lrn.build_features(pool_te, q_te, s_te, log=log)
+    tgt = torch.from_numpy(np.log1p(tr["train_true"]).astype(np.float32)).cuda()
+    init = Lrn.init_params(0)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    mlp, hist = Lrn.train(x, b, tgt, init, epochs=args.epochs, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    res = Lrn.evaluate(mlp, xt, bt, et, tr["test_true"])
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(10):
+        mlp.forward(xt, bt)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - a) / 10
+    n = x.shape[0]
+    out = {"metric": "subplan estimates/s at q-error (learned correction)",
+           "value": xt.shape[0] / t_inf, "unit": "corrected estimates/s",
+           "n_gpus": 1, "steps": args.epochs, "warmup": 0,
+           "ms_per_step": t_train * 1e3 / max(1, args.epochs),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16 weights / fp32 accumulate", "data": "synthetic",
+           "config": {"workload": "learned correction: %d training and %d held-out "
+                                  "sub-plans, d=7 w=8192, MLP 20-64-64-64-1"
+                                  % (n, xt.shape[0]), "parallelism": "single-gpu"},
+           "train_samples_per_s": n * args.epochs / t_train,
+           "feature_build_s": t_feat, "mse_first_last": [hist[0], hist[-1]],
+           "qerror_heldout": res}
+    print(json.dumps(out), flush=True)
+
+
+def run_large(args):
+    """One 1B-row fact table: 4 range predicates (1% combined), 6 int64 key
+    sketches, d=11, w=65536, int64 counters, one fused scan."""
+    import torch
+    from paper_2102_02440_amd import compass as C
+    from paper_2102_02440_amd import workloads as W
+    seed = W.DEFAULT_SEED if args.seed is None else args.seed
+    n = int(os.environ.get("COMPASS_LARGE_ROWS", 1_000_000_000))
+    t0 = time.time()
+    cols, preds, seeds = W.large_scan_device(seed, n_rows=n)
+    torch.cuda.synchronize()
+    log("[bench] generated %d rows on the device in %.1fs" % (n, time.time() - t0))
+    names = ["i0", "i1", "f0", "f1"]
+    pd = [{"col": names.index(p.col), "kind": p.kind, "lo": p.lo, "hi": p.hi}
+          for p in preds]
+    keys = [cols["key%d" % k] for k in range(6)]
+    d, w = 11, 65536
+    cnt = [torch.zeros((d, w), dtype=torch.int64, device="cuda") for _ in keys]
+    nsel = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def step():
+        C.sketch_build(n, [cols[c] for c in names], pd, keys, list(seeds), cnt, nsel,
+                       d, w, counter_bits=64)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    C.profile_enable(True)
+    a = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / args.steps
+    C.profile_enable(False)
+    kn, kms = C.profile_take("scan_direct")
+    C.profile_take("fill_zero")
+    sel = int(nsel.item())
+    alg = 16 * n + sel * 6 * 8 + 6 * d * w * 8
+    k_s = kms / max(1, kn) / 1e3
+    gbs = alg / k_s / 1e9
+    out = {"metric": "filtered rows sketched/s (% HBM roofline); subplan estimates/s at q-error",
+           "value": n / dt, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "large scan: 1 table of %d rows, 4 range predicates "
+                                  "(1%% combined), 6 int64 key sketches d=11 w=65536 "
+                                  "int64" % n, "selected_rows": sel,
+                      "parallelism": "single-gpu"},
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "scan_direct", "alg_bytes_per_launch": alg,
+                        "kernel_ms": k_s * 1e3,
+                        "hash_updates_per_launch": sel * 6 * d}}
+    print(json.dumps(out), flush=True)
+
+
+def run_job6a(args):
     import numpy as np
     import torch
     from paper_2102_02440_amd import compass as C
@@ -140,7 +328,7 @@ def main():
     dt = time.perf_counter() - t0
     C.profile_enable(False)
     prof = {k: C.profile_take(k) for k in
-            ["fill_zero", "scan_sketch", "sort_rows", "node", "tri_lane", "finish"]}
+            ["fill_zero", "scan_sketch", "scan_direct", "sort_rows", "node", "tri_lane", "finish"]}
 
     ms_step = dt * 1e3 / args.steps
     rows_per_step = sum(tb.n_rows for tb in q.tables)

@@ -176,6 +176,106 @@ compass_status compass_estimate(const compass_join_graph *g,
                                 compass_i128 *row_est, double *est,
                                 int32_t *flags, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched build: the sketch builds of many tables (for instance every table
+ * of hundreds of queries) as ONE persistent launch captured in a HIP graph.
+ * Each job is exactly one compass_sketch_build call (same fields, same
+ * result, bit for bit); a launch overwrites every job's counters and
+ * n_selected (accumulate = 0).  Pointers in the jobs must stay valid for the
+ * life of the plan; seeds and predicates are copied at creation.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n_rows;
+    const void *const *pred_cols;        /* host array of device columns */
+    int32_t n_pred_cols;
+    int32_t n_preds;
+    const compass_pred *preds;           /* host */
+    const compass_sketch_spec *sketches; /* host */
+    int32_t n_sketches;
+    int32_t d, w;
+    int32_t reserved;
+    int64_t *n_selected;                 /* device */
+} compass_build_job;
+
+/* Tile parameters of the persistent kernel.  Zero fields = autotune: every
+ * candidate is timed on the batch itself (the plan's jobs run several times
+ * during creation) and the winner is cached per (gfx arch, shape class) in
+ * $COMPASS_AUTOTUNE_CACHE (default ~/.cache/compass_autotune.txt). */
+typedef struct {
+    int64_t rows_per_item;   /* table rows per work item */
+    int32_t lds_budget;      /* bytes of partial counters per workgroup */
+    int32_t blocks_per_cu;   /* persistent workgroups per compute unit */
+} compass_tune;
+
+typedef struct compass_batch_plan_s *compass_batch_plan;
+
+/* Validates the jobs (as compass_sketch_build), builds the work-item list,
+ * tunes, and captures "zero outputs + persistent kernel" into a graph.
+ * Synchronous; runs on `stream` when autotuning. */
+compass_status compass_batch_plan_create(const compass_build_job *jobs,
+                                         int32_t n_jobs, int32_t counter_bits,
+                                         const compass_tune *tune,
+                                         hipStream_t stream,
+                                         compass_batch_plan *plan);
+/* One hipGraphLaunch of the captured batch on `stream` (asynchronous). */
+compass_status compass_batch_plan_launch(compass_batch_plan plan,
+                                         hipStream_t stream);
+/* The tile parameters in use, the number of work items and the grid size. */
+compass_status compass_batch_plan_info(compass_batch_plan plan,
+                                       compass_tune *tune, int32_t *n_items,
+                                       int32_t *grid);
+compass_status compass_batch_plan_destroy(compass_batch_plan plan);
+
+/* ------------------------------------------------------------------------
+ * Learned correction (a small MLP; not in the paper).  Maps sub-plan
+ * features to y = ln(1 + max(raw, 0)) + net(x), raw = the median sketch
+ * estimate, so the zero network returns the raw estimate (the fallback).
+ * Layers n_in -> hidden (x n_hidden_layers, ReLU) -> 1; weights in fp32
+ * (master + Adam state) and bfloat16 (read by the products); each layer
+ * rounds its input activations to bfloat16 and accumulates in fp32.
+ * Flat parameter layout, per layer: W (out x in, row-major) then b (out).
+ * Training: loss = mean (y - target)^2, Adam (beta 0.9 / 0.999, eps 1e-8).
+ * ------------------------------------------------------------------------ */
+typedef struct compass_mlp_s *compass_mlp;
+
+/* init: host array of compass_mlp_n_params() floats.  1 <= n_in, hidden
+ * <= 64, 1 <= n_hidden_layers <= 7.  Synchronous. */
+compass_status compass_mlp_create(int32_t n_in, int32_t hidden,
+                                  int32_t n_hidden_layers, const float *init,
+                                  compass_mlp *out);
+int64_t compass_mlp_n_params(compass_mlp m);
+/* y[i] = base[i] + net(x[i]); x: device n x n_in fp32, base/y: device n. */
+compass_status compass_mlp_forward(compass_mlp m, const float *x,
+                                   const float *base, int32_t n, float *y,
+                                   hipStream_t stream);
+/* One Adam step on the mini-batch (x, base, target); *loss (device float)
+ * receives the batch's mean squared error before the update.  lr = 0
+ * computes loss and gradients without updating (and without advancing the
+ * Adam step count). */
+compass_status compass_mlp_train_step(compass_mlp m, const float *x,
+                                      const float *base, const float *target,
+                                      int32_t n, float lr, float *loss,
+                                      hipStream_t stream);
+/* Copies to host (synchronous): what = 0 parameters, 1 last gradients,
+ * 2 Adam first moments, 3 Adam second moments. */
+compass_status compass_mlp_read(compass_mlp m, int32_t what, float *host_out);
+/* Replaces parameters (and optionally Adam state and step count). */
+compass_status compass_mlp_write(compass_mlp m, const float *params,
+                                 const float *adam_m, const float *adam_v,
+                                 int64_t step);
+compass_status compass_mlp_destroy(compass_mlp m);
+/* Features of n sub-plans (device in, device out): x = n x 20 floats:
+ * 7 order statistics (positions round(k (d-1) / 6), k = 0..6) of
+ * sign(X) ln(1 + |X|) over the sorted row estimates; log2(1 + n_sel) of the
+ * sub-plan's tables, descending, first 8, zero padded; the 5 caller shape
+ * statistics (n x 5 device floats).  base = ln(1 + max(est, 0)). */
+compass_status compass_mlp_features(const compass_i128 *row_est, int32_t d,
+                                    const double *est, const uint64_t *masks,
+                                    const int64_t *n_selected,
+                                    int32_t n_tables, const float *shape,
+                                    int32_t n, float *x, float *base,
+                                    hipStream_t stream);
+
 /* Kernel timing for measurement: while enabled, the library records a pair
  * of HIP events on the launch stream around each kernel launch it makes.
  * compass_profile_take(name) waits for the recorded events of kernel `name`

@@ -353,3 +353,169 @@ def l1_permutation_distance(est, true) -> int:
     pos_t = {s: p for p, s in enumerate(by_true)}
     pos_e = {s: p for p, s in enumerate(by_est)}
     return sum(abs(pos_e[s] - pos_t[s]) for s in range(len(est)))
+
+
+# --------------------------------------------------------------------------
+# Learned correction network (not in the paper; spec addition).
+# Layers in -> 64 -> 64 -> 64 -> 1 with ReLU.  Every layer's input
+# activations and weights are rounded to bfloat16 (round to nearest even)
+# as a bfloat16 matrix product would see them; products and sums are exact
+# here (float64).  Output = base + network(x), base = ln(1 + max(raw, 0)),
+# so a zero network returns the raw sketch estimate.  Loss = mean squared
+# error against ln(1 + true).  Gradients treat the roundings as identity
+# (straight-through).  Parameter layout, per layer: W (out x in, row-major)
+# then b (out).
+# --------------------------------------------------------------------------
+MLP_DIMS = (20, 64, 64, 64, 1)
+
+
+def bf16_round(x) -> np.ndarray:
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = (u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mlp_unpack(params, dims=MLP_DIMS):
+    p = np.asarray(params, dtype=np.float64)
+    out, k = [], 0
+    for i in range(len(dims) - 1):
+        n_in, n_out = dims[i], dims[i + 1]
+        W = p[k:k + n_in * n_out].reshape(n_out, n_in)
+        k += n_in * n_out
+        b = p[k:k + n_out]
+        k += n_out
+        out.append((W, b))
+    assert k == p.size
+    return out
+
+
+def mlp_n_params(dims=MLP_DIMS) -> int:
+    return sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
+
+
+def mlp_forward(params, x, base, dims=MLP_DIMS, rounding=True):
+    """Returns (prediction, cache for the backward pass)."""
+    rnd = bf16_round if rounding else (lambda v: np.asarray(v, dtype=np.float64))
+    layers = mlp_unpack(params, dims)
+    a = np.asarray(x, dtype=np.float64)
+    cache = []
+    for li, (W, b) in enumerate(layers):
+        ar = rnd(a)
+        Wr = rnd(W)
+        z = ar @ Wr.T + b
+        cache.append((ar, Wr, z))
+        a = np.maximum(z, 0.0) if li < len(layers) - 1 else z
+    y = np.asarray(base, dtype=np.float64) + a[:, 0]
+    return y, cache
+
+
+def mlp_loss_grad(params, x, base, target, dims=MLP_DIMS, rounding=True):
+    """(loss, gradient w.r.t. params) of mean((y - target)^2)."""
+    y, cache = mlp_forward(params, x, base, dims, rounding)
+    t = np.asarray(target, dtype=np.float64)
+    n = y.size
+    loss = float(np.mean((y - t) ** 2))
+    dz = (2.0 * (y - t) / n)[:, None]
+    grads = []
+    for li in range(len(cache) - 1, -1, -1):
+        ar, Wr, z = cache[li]
+        if li < len(cache) - 1:
+            dz = dz * (z > 0)
+        dW = dz.T @ ar
+        db = dz.sum(axis=0)
+        grads.append((dW, db))
+        dz = dz @ Wr
+    flat = []
+    for dW, db in reversed(grads):
+        flat.append(dW.reshape(-1))
+        flat.append(db)
+    return loss, np.concatenate(flat)
+
+
+def adam_step(params, m, v, g, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba), bias-corrected; returns new p, m, v."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return params - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def mlp_init(seed: int, dims=MLP_DIMS) -> np.ndarray:
+    """He-uniform weights, zero biases, and a zero output layer (so the
+    untrained network returns the raw estimate)."""
+    rng = np.random.default_rng(seed)
+    flat = []
+    for i in range(len(dims) - 1):
+        n_in, n_out = dims[i], dims[i + 1]
+        lim = np.sqrt(6.0 / n_in)
+        W = rng.uniform(-lim, lim, size=(n_out, n_in))
+        if i == len(dims) - 2:
+            W[:] = 0.0
+        flat.append(W.reshape(-1))
+        flat.append(np.zeros(n_out))
+    return np.concatenate(flat)
+
+
+def true_cardinality_fk_tree(filtered_cols, edges, mask, domain_of):
+    """Exact join size of a tree-shaped sub-plan whose every edge joins a
+    foreign-key column to a dense primary key "id" in [0, domain) (the
+    batched/learned workloads).  Message passing toward the lowest table:
+    a child's message is the per-key count of its joining tuples, each
+    weighted by the product of the messages into it (numpy bincount).
+    Counts are float64 (exact to 2^53).  ``domain_of[t]`` = size of table
+    t's id domain.  Pinned against the hash-aggregation oracle."""
+    tabs = [t for t in range(len(filtered_cols)) if mask >> t & 1]
+    sub = [e for e in edges if (mask >> e[0] & 1) and (mask >> e[2] & 1)]
+    if len(sub) != len(tabs) - 1:
+        raise ValueError("not a tree")
+    adj = {t: [] for t in tabs}
+    for e in sub:
+        adj[e[0]].append(e)
+        adj[e[2]].append(e)
+    root = tabs[0]
+    order, parent_edge = [root], {root: None}
+    for a in order:
+        for e in adj[a]:
+            b = e[2] if e[0] == a else e[0]
+            if b not in parent_edge:
+                parent_edge[b] = e
+                order.append(b)
+    weight = {t: np.ones(len(filtered_cols[t]["id"]), dtype=np.float64)
+              for t in tabs}
+    for b in reversed(order[1:]):
+        e = parent_edge[b]
+        a = e[2] if e[0] == b else e[0]
+        bcol = e[1] if e[0] == b else e[3]
+        acol = e[3] if e[0] == b else e[1]
+        # b's tuples grouped by their join key, weighted; looked up by a
+        bkey = np.asarray(filtered_cols[b][bcol], dtype=np.int64)
+        akey = np.asarray(filtered_cols[a][acol], dtype=np.int64)
+        dom = int(max(domain_of[b] if bcol == "id" else 0,
+                      domain_of[a] if acol == "id" else 0,
+                      (bkey.max() + 1) if bkey.size else 0,
+                      (akey.max() + 1) if akey.size else 0))
+        msg = np.bincount(bkey, weights=weight[b], minlength=dom)
+        weight[a] = weight[a] * msg[akey]
+    return float(weight[root].sum())
+
+
+def mlp_features(rows, est, n_sel_sub, shape):
+    """Reference of the learned model's 20 features of one sub-plan (same
+    definition as compass_mlp_features): 7 order statistics (positions
+    round(k (d-1) / 6)) of sign(X) ln(1 + |X|) over the sorted exact row
+    values; log2(1 + n_sel) of the sub-plan's tables, descending, first 8,
+    zero padded; 5 shape statistics; base = ln(1 + max(est, 0))."""
+    d = len(rows)
+    v = sorted(i128_to_double(r) for r in rows)
+    x = []
+    for k in range(7):
+        r = v[(k * (d - 1) + 3) // 6]
+        x.append(-np.log1p(-r) if r < 0 else np.log1p(r))
+    ls = sorted((np.log2(1.0 + n) for n in n_sel_sub), reverse=True)[:8]
+    x += ls + [0.0] * (8 - len(ls))
+    x += list(shape)
+    return np.array(x, dtype=np.float64), float(np.log1p(max(est, 0.0)))

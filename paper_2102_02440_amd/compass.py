@@ -291,3 +291,354 @@ class DeviceQuery:
         return estimate(len(self.q.tables), self.q.edge_u, self.q.edge_v,
                         self.d, self.w, self.bits, self.n_selected,
                         self.sketch_of_side, masks, stream=stream)
+
+
+# --------------------------------------------------------------------------
+# Batched build (one persistent graph-captured launch for many tables)
+# --------------------------------------------------------------------------
+class BuildJob(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("pred_cols", ctypes.POINTER(ctypes.c_void_p)),
+                ("n_pred_cols", ctypes.c_int32), ("n_preds", ctypes.c_int32),
+                ("preds", ctypes.POINTER(Pred)), ("sketches", ctypes.POINTER(SketchSpec)),
+                ("n_sketches", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("w", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_selected", ctypes.c_void_p)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("rows_per_item", ctypes.c_int64), ("lds_budget", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+
+def _bind_batch(L):
+    if getattr(L, "_batch_bound", False):
+        return
+    vp = ctypes.c_void_p
+    L.compass_batch_plan_create.argtypes = [ctypes.POINTER(BuildJob), ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.POINTER(Tune), vp,
+                                            ctypes.POINTER(vp)]
+    L.compass_batch_plan_create.restype = ctypes.c_int32
+    L.compass_batch_plan_launch.argtypes = [vp, vp]
+    L.compass_batch_plan_launch.restype = ctypes.c_int32
+    L.compass_batch_plan_info.argtypes = [vp, ctypes.POINTER(Tune),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32)]
+    L.compass_batch_plan_info.restype = ctypes.c_int32
+    L.compass_batch_plan_destroy.argtypes = [vp]
+    L.compass_batch_plan_destroy.restype = ctypes.c_int32
+    L._batch_bound = True
+
+
+def _marshal_build(n_rows, pred_cols, preds, keys, seeds, counters):
+    """ctypes arrays for one table build; returns (arrays, keepalive)."""
+    ncol = len(pred_cols)
+    cols = (ctypes.c_void_p * max(1, ncol))(*[c.data_ptr() for c in pred_cols])
+    parr = (Pred * max(1, len(preds)))()
+    for i, p in enumerate(preds):
+        col = pred_cols[p["col"]]
+        q = parr[i]
+        q.col = p["col"]
+        q.kind = PRED_KIND[p["kind"]]
+        q.dtype = _dtype_code(col)
+        if q.dtype == F32:
+            q.lo.f = float(p.get("lo", 0))
+            q.hi.f = float(p.get("hi", 0))
+        else:
+            q.lo.i = int(p.get("lo", 0))
+            q.hi.i = int(p.get("hi", 0))
+        bm = p.get("bitmap")
+        q.bitmap = bm.data_ptr() if bm is not None else None
+        q.domain = int(p.get("domain", 0))
+    sarr = (SketchSpec * len(keys))()
+    keep = [cols, parr, sarr]
+    for i in range(len(keys)):
+        sd = np.ascontiguousarray(np.asarray(seeds[i], dtype=np.uint64).reshape(-1))
+        keep.append(sd)
+        sarr[i].key_col = keys[i].data_ptr()
+        sarr[i].key_dtype = _dtype_code(keys[i])
+        sarr[i].seeds = sd.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        sarr[i].counters = counters[i].data_ptr()
+    return cols, parr, sarr, keep
+
+
+class BatchPlan:
+    """A graph-captured persistent build of many tables' sketches.
+
+    jobs: list of dicts with the arguments of sketch_build (n_rows,
+    pred_cols, preds, keys, seeds, counters, n_selected, d, w).  tune: None
+    (autotune, cached) or (rows_per_item, lds_budget, blocks_per_cu)."""
+
+    def __init__(self, jobs, counter_bits=32, tune=None, stream=None):
+        L = lib()
+        _bind_batch(L)
+        self._keep = []
+        arr = (BuildJob * max(1, len(jobs)))()
+        for i, j in enumerate(jobs):
+            cols, parr, sarr, keep = _marshal_build(j["n_rows"], j["pred_cols"],
+                                                    j["preds"], j["keys"], j["seeds"],
+                                                    j["counters"])
+            self._keep.append(keep)
+            b = arr[i]
+            b.n_rows = int(j["n_rows"])
+            b.pred_cols = cols
+            b.n_pred_cols = len(j["pred_cols"])
+            b.n_preds = len(j["preds"])
+            b.preds = parr
+            b.sketches = sarr
+            b.n_sketches = len(j["keys"])
+            b.d = int(j["d"])
+            b.w = int(j["w"])
+            b.n_selected = j["n_selected"].data_ptr()
+        t = None
+        if tune is not None:
+            t = Tune(int(tune[0]), int(tune[1]), int(tune[2]))
+        h = ctypes.c_void_p()
+        _check(L.compass_batch_plan_create(arr, len(jobs), int(counter_bits),
+                                           ctypes.byref(t) if t is not None else None,
+                                           _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self._keep.append(arr)
+
+    def launch(self, stream=None):
+        _check(lib().compass_batch_plan_launch(self.h, _stream(stream)))
+
+    def info(self):
+        t = Tune()
+        n = ctypes.c_int32()
+        g = ctypes.c_int32()
+        _check(lib().compass_batch_plan_info(self.h, ctypes.byref(t), ctypes.byref(n),
+                                             ctypes.byref(g)))
+        return {"rows_per_item": t.rows_per_item, "lds_budget": t.lds_budget,
+                "blocks_per_cu": t.blocks_per_cu, "n_items": n.value, "grid": g.value}
+
+    def close(self):
+        if self.h:
+            lib().compass_batch_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def upload_pool(pool, device="cuda"):
+    """Device copies of every column of a table pool."""
+    return [{c: torch.from_numpy(np.ascontiguousarray(v)).to(device)
+             for c, v in pt.cols.items()} for pt in pool]
+
+
+class DeviceBatch:
+    """A pool of tables resident on the device and a batch of queries over
+    it: per (query, table) one build job with the query's selections and
+    one sketch per incident edge (d, w and seeds of the query)."""
+
+    def __init__(self, pool, queries, device="cuda", counter_bits=32,
+                 pool_cols=None):
+        self.pool, self.queries, self.device = pool, queries, device
+        self.bits = counter_bits
+        cdt = torch.int32 if counter_bits == 32 else torch.int64
+        self.cols = pool_cols if pool_cols is not None else upload_pool(pool, device)
+        self.jobs = []
+        self.sides = []       # per query: list of counters per side (2 * n_edges)
+        self.n_selected = []  # per query: int64 tensor (n_tables,)
+        for qi, pq in enumerate(queries):
+            nsel = torch.zeros(len(pq.tables), dtype=torch.int64, device=device)
+            sides = [None] * (2 * len(pq.edges))
+            for t, ptab in enumerate(pq.tables):
+                cols = self.cols[ptab]
+                inc = pq.incident(t)
+                if not inc:
+                    continue
+                names, preds = [], []
+                for p in pq.preds[t]:
+                    if p.col not in names:
+                        names.append(p.col)
+                    pd = {"col": names.index(p.col), "kind": p.kind, "lo": p.lo,
+                          "hi": p.hi, "domain": p.domain}
+                    if p.kind == "subset":
+                        pd["bitmap"] = torch.from_numpy(
+                            np.asarray(p.bitmap, dtype=np.uint64).view(np.int64)).to(device)
+                    preds.append(pd)
+                keys, seeds, counters = [], [], []
+                for (e, side, c) in inc:
+                    cnt = torch.zeros((pq.d, pq.w), dtype=cdt, device=device)
+                    sides[2 * e + side] = cnt
+                    keys.append(cols[c])
+                    seeds.append(pq.seeds[e])
+                    counters.append(cnt)
+                self.jobs.append({"n_rows": len(cols["id"]),
+                                  "pred_cols": [cols[c] for c in names],
+                                  "preds": preds, "keys": keys, "seeds": seeds,
+                                  "counters": counters,
+                                  "n_selected": nsel[t:t + 1], "d": pq.d, "w": pq.w,
+                                  "query": qi, "table": t})
+            self.sides.append(sides)
+            self.n_selected.append(nsel)
+
+    def plan(self, tune=None, stream=None):
+        return BatchPlan(self.jobs, self.bits, tune=tune, stream=stream)
+
+    def build_per_table(self, stream=None):
+        """One compass_sketch_build per (query, table): all its sketches."""
+        for j in self.jobs:
+            sketch_build(j["n_rows"], j["pred_cols"], j["preds"], j["keys"],
+                         j["seeds"], j["counters"], j["n_selected"], j["d"],
+                         j["w"], self.bits, stream=stream)
+
+    def build_per_sketch(self, stream=None):
+        """The plain path: one compass_sketch_build launch per sketch."""
+        for j in self.jobs:
+            for k in range(len(j["keys"])):
+                sketch_build(j["n_rows"], j["pred_cols"], j["preds"], [j["keys"][k]],
+                             [j["seeds"][k]], [j["counters"][k]], j["n_selected"],
+                             j["d"], j["w"], self.bits, stream=stream)
+
+    def estimate(self, qi, masks, stream=None):
+        pq = self.queries[qi]
+        return estimate(len(pq.tables), [e.u for e in pq.edges],
+                        [e.v for e in pq.edges], pq.d, pq.w, self.bits,
+                        self.n_selected[qi], self.sides[qi], masks, stream=stream)
+
+
+# --------------------------------------------------------------------------
+# Learned correction network
+# --------------------------------------------------------------------------
+def _bind_mlp(L):
+    if getattr(L, "_mlp_bound", False):
+        return
+    vp = ctypes.c_void_p
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.compass_mlp_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     fp, ctypes.POINTER(vp)]
+    L.compass_mlp_create.restype = ctypes.c_int32
+    L.compass_mlp_n_params.argtypes = [vp]
+    L.compass_mlp_n_params.restype = ctypes.c_int64
+    L.compass_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp]
+    L.compass_mlp_forward.restype = ctypes.c_int32
+    L.compass_mlp_train_step.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float,
+                                         vp, vp]
+    L.compass_mlp_train_step.restype = ctypes.c_int32
+    L.compass_mlp_read.argtypes = [vp, ctypes.c_int32, fp]
+    L.compass_mlp_read.restype = ctypes.c_int32
+    L.compass_mlp_write.argtypes = [vp, fp, fp, fp, ctypes.c_int64]
+    L.compass_mlp_write.restype = ctypes.c_int32
+    L.compass_mlp_destroy.argtypes = [vp]
+    L.compass_mlp_destroy.restype = ctypes.c_int32
+    L.compass_mlp_features.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32,
+                                       vp, ctypes.c_int32, vp, vp, vp]
+    L.compass_mlp_features.restype = ctypes.c_int32
+    L._mlp_bound = True
+
+
+def mlp_n_params(n_in=20, hidden=64, layers=3):
+    dims = [n_in] + [hidden] * layers + [1]
+    return sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
+
+
+class MLP:
+    """The learned correction network on the device (fp32 master weights,
+    bfloat16 copy, Adam state), driven by the library's HIP kernels."""
+
+    def __init__(self, init_params, n_in=20, hidden=64, layers=3):
+        L = lib()
+        _bind_mlp(L)
+        p = np.ascontiguousarray(np.asarray(init_params, dtype=np.float32))
+        assert p.size == mlp_n_params(n_in, hidden, layers)
+        h = ctypes.c_void_p()
+        _check(L.compass_mlp_create(n_in, hidden, layers,
+                                    p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                    ctypes.byref(h)))
+        self.h = h
+        self.n_in = n_in
+        self.n_params = int(L.compass_mlp_n_params(h))
+        self._loss = None
+
+    def forward(self, x, base, out=None, stream=None):
+        n = x.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(lib().compass_mlp_forward(self.h, x.data_ptr(), base.data_ptr(), n,
+                                         out.data_ptr(), _stream(stream)))
+        return out
+
+    def train_step(self, x, base, target, lr, stream=None):
+        """One Adam step; returns the device scalar holding the batch MSE."""
+        if self._loss is None or self._loss.device != x.device:
+            self._loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+        _check(lib().compass_mlp_train_step(self.h, x.data_ptr(), base.data_ptr(),
+                                            target.data_ptr(), x.shape[0],
+                                            float(lr), self._loss.data_ptr(),
+                                            _stream(stream)))
+        return self._loss
+
+    def read(self, what=0):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().compass_mlp_read(self.h, int(what),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def write(self, params, m=None, v=None, step=0):
+        fp = ctypes.POINTER(ctypes.c_float)
+        arrs = [None if a is None else np.ascontiguousarray(np.asarray(a, np.float32))
+                for a in (params, m, v)]
+        ptrs = [None if a is None else a.ctypes.data_as(fp) for a in arrs]
+        _check(lib().compass_mlp_write(self.h, ptrs[0], ptrs[1], ptrs[2], int(step)))
+
+    def close(self):
+        if self.h:
+            lib().compass_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def shape_stats(n_tables, edge_u, edge_v, masks):
+    """Per sub-plan (host): #tables, #edges, diameter, max degree and number
+    of independent cycles of the induced join graph (float32, n x 5)."""
+    out = np.zeros((len(masks), 5), dtype=np.float32)
+    for k, m in enumerate(masks):
+        m = int(m)
+        tabs = [t for t in range(n_tables) if m >> t & 1]
+        es = [(u, v) for u, v in zip(edge_u, edge_v) if m >> u & 1 and m >> v & 1]
+        adj = {t: [] for t in tabs}
+        for u, v in es:
+            adj[u].append(v)
+            adj[v].append(u)
+        diam = 0
+        for s in tabs:
+            dist = {s: 0}
+            frontier = [s]
+            while frontier:
+                nxt = []
+                for a in frontier:
+                    for b in adj[a]:
+                        if b not in dist:
+                            dist[b] = dist[a] + 1
+                            nxt.append(b)
+                frontier = nxt
+            diam = max(diam, max(dist.values()))
+        out[k] = (len(tabs), len(es), diam,
+                  max((len(v) for v in adj.values()), default=0),
+                  len(es) - len(tabs) + 1)
+    return out
+
+
+def features(row_est, est, masks_dev, n_selected, n_tables, shape_dev, stream=None):
+    """(x n x 20, base n) device float32 features of n sub-plans."""
+    L = lib()
+    _bind_mlp(L)
+    n, d = row_est.shape[0], row_est.shape[1]
+    dev = row_est.device
+    x = torch.empty((n, 20), dtype=torch.float32, device=dev)
+    base = torch.empty(n, dtype=torch.float32, device=dev)
+    _check(L.compass_mlp_features(row_est.data_ptr(), d, est.data_ptr(),
+                                  masks_dev.data_ptr(), n_selected.data_ptr(),
+                                  int(n_tables), shape_dev.data_ptr(), n,
+                                  x.data_ptr(), base.data_ptr(), _stream(stream)))
+    return x, base

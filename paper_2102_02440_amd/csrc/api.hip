@@ -26,6 +26,9 @@ namespace compass {
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t st);
 hipError_t launch_scan_sketch(const BuildParams &P, int n_blocks,
                               size_t lds_bytes, hipStream_t st);
+hipError_t launch_scan_direct(const BuildParams &P, const void *seeds,
+                              int n_slices, int d, int n_blocks,
+                              hipStream_t st);
 hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
                             const EstBuffers &B, hipStream_t st);
 hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
@@ -54,6 +57,10 @@ static compass_status fail(compass_status s, const char *fmt, ...) {
   return s;
 }
 
+namespace compass {
+void set_last_error(const std::string &s) { g_err = s; }
+}  // namespace compass
+
 #define HIP_OK(expr)                                                       \
   do {                                                                     \
     hipError_t e_ = (expr);                                                \
@@ -74,6 +81,9 @@ struct DeviceState {
   bool pinned_used[kRing] = {};
   int ring_next = 0;
   bool attrs_set = false;
+  int n_cu = 256;
+  void *dseeds = nullptr;      // seeds of wide sketches (direct kernel)
+  size_t dseeds_bytes = 0;
 };
 
 static std::mutex g_mu;
@@ -84,6 +94,9 @@ static compass_status device_state(DeviceState **out) {
   HIP_OK(hipGetDevice(&dev));
   DeviceState &ds = g_dev[dev];
   if (!ds.attrs_set) {
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, dev));
+    ds.n_cu = prop.multiProcessorCount;
     for (int i = 0; i < DeviceState::kRing; ++i)
       HIP_OK(hipEventCreateWithFlags(&ds.pinned_done[i],
                                      hipEventDisableTiming));
@@ -236,11 +249,6 @@ extern "C" compass_status compass_sketch_build(
     return fail(COMPASS_E_ARG, "null pointer argument");
   if (n_preds > 0 && n_rows > 0 && !pred_cols)
     return fail(COMPASS_E_ARG, "null predicate column array");
-  if ((size_t)w * 4 > kLdsBudget)
-    return fail(COMPASS_E_UNSUPPORTED,
-                "w=%d: one sketch row of partial counters exceeds the LDS "
-                "budget of this build",
-                w);
 
   BuildParams base;
   memset(&base, 0, sizeof(base));
@@ -301,23 +309,85 @@ extern "C" compass_status compass_sketch_build(
   }
   if (n_rows == 0) return COMPASS_OK;
 
-  // slice groups: consecutive (sketch, row) slices whose int32 partials fit
-  // the LDS budget, balanced in size
-  const int S = n_sketches * d;
-  const int per_group_max = (int)std::min<size_t>(
-      kLdsBudget / ((size_t)w * 4), (size_t)kMaxLaunchSlices);
-  const int n_groups_total = (S + per_group_max - 1) / per_group_max;
-  const int per_group = (S + n_groups_total - 1) / n_groups_total;
+  if ((size_t)w * 4 > kLdsBudget) {
+    // rows too wide for LDS-private partials: direct global atomics
+    const int S = n_sketches * d;
+    std::vector<RowSeeds> sd(S);
+    for (int s = 0; s < n_sketches; ++s)
+      for (int i = 0; i < d; ++i) {
+        const uint64_t *p = sketches[s].seeds + 6 * i;
+        sd[s * d + i] = RowSeeds{p[0], p[1], p[2], p[3], p[4], p[5]};
+      }
+    const size_t bytes = sizeof(RowSeeds) * S;
+    if (ds->dseeds_bytes < bytes) {
+      if (ds->dseeds) {
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipFree(ds->dseeds));
+      }
+      ds->dseeds = nullptr;
+      HIP_OK(hipMalloc(&ds->dseeds, std::max(bytes, (size_t)65536)));
+      ds->dseeds_bytes = std::max(bytes, (size_t)65536);
+    }
+    st = upload(ds, ds->dseeds, sd.data(), bytes, stream);
+    if (st != COMPASS_OK) return st;
+    const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
+    const int64_t blocks = std::min<int64_t>(tiles, 8ll * ds->n_cu);
+    int64_t rpc = (n_rows + blocks - 1) / blocks;
+    rpc = (rpc + kBuildTile - 1) / kBuildTile * kBuildTile;
+    BuildParams P = base;
+    P.rows_per_chunk = rpc;
+    P.count_selected = 1;
+    P.n_groups = 1;
+    for (int s = 0; s < n_sketches; ++s) {
+      P.keys[s].col = sketches[s].key_col;
+      P.keys[s].dtype = sketches[s].key_dtype;
+      P.counters[s] = sketches[s].counters;
+    }
+    ProfScope ps("scan_direct", stream);
+    HIP_OK(launch_scan_direct(P, ds->dseeds, S, d,
+                              (int)((n_rows + rpc - 1) / rpc), stream));
+    return COMPASS_OK;
+  }
 
-  // rows per chunk: enough chunks to fill the chip, but each chunk scans
-  // at least 16x as many rows as it merges counters
+  // slice groups: consecutive (sketch, row) slices whose int32 partials fit
+  // the LDS budget; among the group sizes that fit, prefer one that splits
+  // the slices into equal groups (every workgroup then does equal work)
+  const int S = n_sketches * d;
+  const int per_max = (int)std::min<size_t>(kLdsBudget / ((size_t)w * 4),
+                                            (size_t)kMaxLaunchSlices);
+  int per_group = std::min(per_max, S);
+  {
+    int best_waste = 1 << 30;
+    for (int g = per_group; g >= std::max(1, (per_group + 1) / 2); --g) {
+      const int ng = (S + g - 1) / g;
+      const int waste = ng * g - S;
+      if (waste < best_waste) {
+        best_waste = waste;
+        per_group = g;
+      }
+      if (waste == 0) break;
+    }
+  }
+  const int n_groups_total = (S + per_group - 1) / per_group;
+
+  // chunks: a multiple of the resident workgroup slots, so that equal-sized
+  // items fill the chip in whole waves; each chunk still scans at least 16x
+  // as many rows as it merges counters
+  const size_t lds_block = (size_t)per_group * w * 4 + (size_t)kBuildTile * 4;
+  const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / lds_block)));
+  const int64_t slots = (int64_t)ds->n_cu * per_cu;
   const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
-  int64_t target_blocks = 2048;
-  int64_t chunks = std::max<int64_t>(1, target_blocks / n_groups_total);
-  const int64_t min_rows = std::max<int64_t>(kBuildTile,
-                                             16ll * per_group * w);
-  chunks = std::min(chunks, std::max<int64_t>(1, n_rows / min_rows));
-  chunks = std::min(chunks, tiles);
+  const int64_t min_rows = std::max<int64_t>(kBuildTile, 16ll * per_group * w);
+  const int64_t max_chunks = std::max<int64_t>(1, std::min(tiles, n_rows / min_rows));
+  int64_t chunks = 1;
+  for (int64_t waves = 8; waves >= 1; waves /= 2) {
+    const int64_t c = (waves * slots + n_groups_total - 1) / n_groups_total;
+    if (c <= max_chunks) {
+      chunks = c;
+      break;
+    }
+  }
+  if (chunks == 1) chunks = max_chunks;
   int64_t rows_per_chunk = (n_rows + chunks - 1) / chunks;
   rows_per_chunk =
       (rows_per_chunk + kBuildTile - 1) / kBuildTile * kBuildTile;

@@ -1,0 +1,550 @@
+// batch.hip -- every attribute sketch of many tables (of many queries) in
+// one persistent, graph-captured launch.
+//
+// The batch is cut into work items (table job, row range, slice group).
+// A fixed grid of persistent workgroups pulls items from a device-side
+// counter until the list is exhausted (every workgroup reaches the exit:
+// the counter only grows), so uneven filtered sizes (10k..36M rows, 0.1%..
+// 100% selectivity) balance dynamically.  Items are ordered largest first.
+// Each item runs the same fused scan + LDS-private sketch + merge body as the
+// one-table kernel.  Plan creation captures "zero counters + reset queue +
+// persistent kernel" in a hipGraph; a launch is one hipGraphLaunch.
+//
+// The tile parameters (rows per item, LDS budget per workgroup, persistent
+// workgroups per CU) come from a small autotuner: it times every candidate
+// on the batch itself and caches the winner per (gfx arch, shape class).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "build_params.hpp"
+#include "compass.h"
+#include "device_math.hpp"
+#include "scan_common.hpp"
+
+namespace compass {
+
+struct BatchJob {
+  int64_t n_rows;
+  int64_t *n_selected;
+  int32_t n_preds;
+  int32_t n_sketch;
+  int32_t d;
+  int32_t counter_bits;
+  int32_t seed_base;   // first RowSeeds of this job (slice sl -> seed_base + sl)
+  int32_t pad;
+  BucketMod bm;
+  PredDev preds[kMaxPreds];
+  KeyDev keys[kMaxSketches];
+  void *counters[kMaxSketches];
+};
+
+struct BatchItem {
+  int64_t row0, row1;
+  int32_t job;
+  int32_t slice_begin, slice_end;
+  int32_t count_selected;
+};
+
+struct ZeroRegion {
+  void *p;
+  int64_t words;
+};
+
+struct GlobalJob {
+  const BatchJob *J;
+  const RowSeeds *seed_arr;
+  __device__ int n_preds() const { return J->n_preds; }
+  __device__ const PredDev &pred(int q) const { return J->preds[q]; }
+  __device__ KeyDev key(int s) const { return J->keys[s]; }
+  __device__ int slice_sketch(int sl) const { return sl / J->d; }
+  __device__ int slice_row(int sl) const { return sl % J->d; }
+  __device__ RowSeeds seeds(int sl) const { return seed_arr[J->seed_base + sl]; }
+  __device__ BucketMod bm() const { return J->bm; }
+  __device__ int counter_bits() const { return J->counter_bits; }
+  __device__ void *counters(int s) const { return J->counters[s]; }
+};
+
+__global__ __launch_bounds__(kBuildThreads) void batch_scan_kernel(
+    const BatchJob *jobs, const BatchItem *items, int32_t n_items,
+    int32_t *queue, const RowSeeds *seeds) {
+  extern __shared__ int32_t lds[];
+  __shared__ int32_t s_qn;
+  __shared__ int32_t s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;  // uniform across the workgroup
+    const BatchItem I = items[it];
+    const GlobalJob job{jobs + I.job, seeds};
+    const int w = (int)job.bm().w;
+    const int ns = I.slice_end - I.slice_begin;
+    int32_t *cnt = lds;
+    int32_t *queue_rows = lds + (size_t)ns * w;
+    for (int i = threadIdx.x; i < ns * w; i += kBuildThreads) cnt[i] = 0;
+    __syncthreads();
+    const uint64_t sel = scan_rows(job, I.row0, I.row1, I.slice_begin,
+                                   I.slice_end, cnt, queue_rows, &s_qn);
+    merge_slices(job, I.slice_begin, I.slice_end, cnt);
+    if (I.count_selected && threadIdx.x == 0 && sel)
+      atomicAdd(reinterpret_cast<unsigned long long *>(job.J->n_selected),
+                (unsigned long long)sel);
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+__global__ void zero_regions_kernel(const ZeroRegion *r, int32_t n) {
+  for (int k = blockIdx.y; k < n; k += gridDim.y) {
+    uint32_t *p = reinterpret_cast<uint32_t *>(r[k].p);
+    const int64_t words = r[k].words;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+      p[i] = 0;
+  }
+}
+
+}  // namespace compass
+
+using namespace compass;
+
+// ---------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------
+namespace compass {
+void set_last_error(const std::string &s);
+}
+
+static compass_status bfail(compass_status s, const std::string &msg) {
+  compass::set_last_error(msg);
+  return s;
+}
+
+#define BHIP(expr)                                                           \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return bfail(COMPASS_E_HIP,                                            \
+                   std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+struct compass_batch_plan_s {
+  int device = 0;
+  int counter_bits = 32;
+  std::vector<BatchJob> jobs;
+  std::vector<RowSeeds> seeds;
+  std::vector<ZeroRegion> zeros;
+  std::vector<int64_t> job_rows;
+  std::vector<int32_t> job_slices;
+  std::vector<int32_t> job_w;
+  compass_tune tune{};
+  // device copies
+  char *dmem = nullptr;
+  size_t dbytes = 0;
+  BatchJob *d_jobs = nullptr;
+  BatchItem *d_items = nullptr;
+  RowSeeds *d_seeds = nullptr;
+  ZeroRegion *d_zeros = nullptr;
+  int32_t *d_queue = nullptr;
+  int32_t n_items = 0;
+  size_t lds = 0;
+  int grid = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int n_cu = 0;
+};
+
+static BucketMod bmod(uint32_t w) {
+  BucketMod m;
+  m.w = w;
+  m.pow2 = (w & (w - 1)) == 0;
+  m.mask = w - 1;
+  m.r32 = (uint32_t)((1ull << 32) % w);
+  m.inv = 1.0 / (double)w;
+  return m;
+}
+
+// Work items for a tuning choice; returns the LDS bytes per workgroup.
+static size_t make_items(const compass_batch_plan_s &pl, const compass_tune &t,
+                         std::vector<BatchItem> &items) {
+  items.clear();
+  size_t lds_max = 0;
+  for (size_t j = 0; j < pl.jobs.size(); ++j) {
+    const int64_t n = pl.job_rows[j];
+    const int S = pl.job_slices[j];
+    const int w = pl.job_w[j];
+    if (n == 0 || S == 0) continue;
+    const int per_max = std::max(1, std::min<int>(
+        (int)(t.lds_budget / ((size_t)w * 4)), kMaxLaunchSlices));
+    const int ng = (S + per_max - 1) / per_max;
+    int64_t rpi = std::max<int64_t>(kBuildTile, t.rows_per_item);
+    rpi = (rpi + kBuildTile - 1) / kBuildTile * kBuildTile;
+    for (int g = 0; g < ng; ++g) {
+      const int sb = (int)((int64_t)S * g / ng);
+      const int se = (int)((int64_t)S * (g + 1) / ng);
+      lds_max = std::max(lds_max, (size_t)(se - sb) * w * 4);
+      for (int64_t r = 0; r < n; r += rpi) {
+        BatchItem it;
+        it.row0 = r;
+        it.row1 = std::min(n, r + rpi);
+        it.job = (int32_t)j;
+        it.slice_begin = sb;
+        it.slice_end = se;
+        it.count_selected = (g == 0) ? 1 : 0;
+        items.push_back(it);
+      }
+    }
+  }
+  // largest first (rows x slices; dense jobs weigh their full hashing)
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const BatchItem &a, const BatchItem &b) {
+                     const double ca = (double)(a.row1 - a.row0) *
+                                       (1 + (a.slice_end - a.slice_begin) *
+                                                (pl.jobs[a.job].n_preds ? 0.1 : 1.0));
+                     const double cb = (double)(b.row1 - b.row0) *
+                                       (1 + (b.slice_end - b.slice_begin) *
+                                                (pl.jobs[b.job].n_preds ? 0.1 : 1.0));
+                     return ca > cb;
+                   });
+  return lds_max + (size_t)kBuildTile * 4;
+}
+
+static compass_status upload_plan(compass_batch_plan_s &pl,
+                                  const std::vector<BatchItem> &items) {
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t b_jobs = al(sizeof(BatchJob) * pl.jobs.size());
+  const size_t b_items = al(sizeof(BatchItem) * std::max<size_t>(1, items.size()));
+  const size_t b_seeds = al(sizeof(RowSeeds) * std::max<size_t>(1, pl.seeds.size()));
+  const size_t b_zero = al(sizeof(ZeroRegion) * (pl.zeros.size() + 1));
+  const size_t b_queue = 256;
+  const size_t total = b_jobs + b_items + b_seeds + b_zero + b_queue;
+  if (total > pl.dbytes) {
+    if (pl.dmem) BHIP(hipFree(pl.dmem));
+    pl.dmem = nullptr;
+    BHIP(hipMalloc(&pl.dmem, total));
+    pl.dbytes = total;
+  }
+  size_t off = 0;
+  pl.d_jobs = reinterpret_cast<BatchJob *>(pl.dmem + off); off += b_jobs;
+  pl.d_items = reinterpret_cast<BatchItem *>(pl.dmem + off); off += b_items;
+  pl.d_seeds = reinterpret_cast<RowSeeds *>(pl.dmem + off); off += b_seeds;
+  pl.d_zeros = reinterpret_cast<ZeroRegion *>(pl.dmem + off); off += b_zero;
+  pl.d_queue = reinterpret_cast<int32_t *>(pl.dmem + off);
+  std::vector<ZeroRegion> z = pl.zeros;
+  z.push_back(ZeroRegion{pl.d_queue, 1});
+  BHIP(hipMemcpy(pl.d_jobs, pl.jobs.data(), sizeof(BatchJob) * pl.jobs.size(),
+                 hipMemcpyHostToDevice));
+  if (!items.empty())
+    BHIP(hipMemcpy(pl.d_items, items.data(), sizeof(BatchItem) * items.size(),
+                   hipMemcpyHostToDevice));
+  if (!pl.seeds.empty())
+    BHIP(hipMemcpy(pl.d_seeds, pl.seeds.data(),
+                   sizeof(RowSeeds) * pl.seeds.size(), hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(pl.d_zeros, z.data(), sizeof(ZeroRegion) * z.size(),
+                 hipMemcpyHostToDevice));
+  pl.n_items = (int32_t)items.size();
+  return COMPASS_OK;
+}
+
+static void enqueue(const compass_batch_plan_s &pl, hipStream_t st) {
+  const int nz = (int)pl.zeros.size() + 1;
+  hipLaunchKernelGGL(zero_regions_kernel, dim3(16, std::min(nz, 65535)),
+                     dim3(256), 0, st, pl.d_zeros, nz);
+  if (pl.n_items > 0)
+    hipLaunchKernelGGL(batch_scan_kernel, dim3(pl.grid), dim3(kBuildThreads),
+                       pl.lds, st, pl.d_jobs, pl.d_items, pl.n_items,
+                       pl.d_queue, pl.d_seeds);
+}
+
+static std::string cache_path() {
+  const char *p = getenv("COMPASS_AUTOTUNE_CACHE");
+  if (p && *p) return p;
+  const char *h = getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/compass_autotune.txt";
+}
+
+// shape class: arch, counter width, and a coarse histogram of the jobs
+static std::string shape_key(const compass_batch_plan_s &pl,
+                             const char *arch) {
+  std::map<std::string, int64_t> h;
+  int64_t rows = 0;
+  for (size_t j = 0; j < pl.jobs.size(); ++j) {
+    std::ostringstream k;
+    k << "w" << pl.job_w[j] << "d" << pl.jobs[j].d
+      << (pl.jobs[j].n_preds ? "s" : "x");
+    h[k.str()] += 1;
+    rows += pl.job_rows[j];
+  }
+  std::ostringstream o;
+  o << arch << "|c" << pl.counter_bits << "|r"
+    << (int)std::log2((double)std::max<int64_t>(1, rows)) << "|j"
+    << (int)std::log2((double)std::max<size_t>(1, pl.jobs.size()));
+  for (auto &kv : h)
+    o << "|" << kv.first << ":"
+      << (int)std::log2((double)std::max<int64_t>(1, kv.second));
+  return o.str();
+}
+
+static bool cache_lookup(const std::string &key, compass_tune *t) {
+  std::ifstream f(cache_path());
+  std::string k;
+  long long rpi;
+  int lb, bpc;
+  while (f >> k >> rpi >> lb >> bpc) {
+    if (k == key) {
+      t->rows_per_item = rpi;
+      t->lds_budget = lb;
+      t->blocks_per_cu = bpc;
+      return true;
+    }
+  }
+  return false;
+}
+
+static void cache_store(const std::string &key, const compass_tune &t) {
+  const std::string p = cache_path();
+  const size_t slash = p.rfind('/');
+  if (slash != std::string::npos) {
+    const std::string dir = p.substr(0, slash);
+    std::string cmd = "mkdir -p '" + dir + "'";
+    if (system(cmd.c_str()) != 0) return;
+  }
+  std::ofstream f(p, std::ios::app);
+  f << key << " " << (long long)t.rows_per_item << " " << t.lds_budget << " "
+    << t.blocks_per_cu << "\n";
+}
+
+static compass_status apply_tune(compass_batch_plan_s &pl,
+                                 const compass_tune &t) {
+  std::vector<BatchItem> items;
+  pl.lds = make_items(pl, t, items);
+  if (pl.lds > 160 * 1024)
+    return bfail(COMPASS_E_UNSUPPORTED, "LDS need exceeds 160 KiB");
+  compass_status s = upload_plan(pl, items);
+  if (s != COMPASS_OK) return s;
+  int bpc = std::max(1, t.blocks_per_cu);
+  if (pl.lds * bpc > 160 * 1024) bpc = 1;
+  pl.grid = std::max(1, pl.n_cu * bpc);
+  pl.tune = t;
+  return COMPASS_OK;
+}
+
+static compass_status autotune(compass_batch_plan_s &pl, hipStream_t st,
+                               compass_tune *best_out) {
+  const int64_t rpis[] = {65536, 262144, 1048576};
+  const int32_t budgets[] = {65536, 131072};
+  const int32_t bpcs[] = {1, 2};
+  hipEvent_t a, b;
+  BHIP(hipEventCreate(&a));
+  BHIP(hipEventCreate(&b));
+  float best = 1e30f;
+  compass_tune bt{};
+  for (int64_t rpi : rpis)
+    for (int32_t lb : budgets)
+      for (int32_t bpc : bpcs) {
+        if ((size_t)lb * bpc > 144 * 1024) continue;
+        compass_tune t{rpi, lb, bpc};
+        bool fits = true;
+        for (int w : pl.job_w)
+          if ((size_t)w * 4 > (size_t)lb) fits = false;
+        if (!fits) continue;
+        compass_status s = apply_tune(pl, t);
+        if (s != COMPASS_OK) continue;
+        enqueue(pl, st);  // warm
+        BHIP(hipEventRecord(a, st));
+        enqueue(pl, st);
+        BHIP(hipEventRecord(b, st));
+        BHIP(hipEventSynchronize(b));
+        float ms = 0;
+        BHIP(hipEventElapsedTime(&ms, a, b));
+        if (ms < best) {
+          best = ms;
+          bt = t;
+        }
+      }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (best >= 1e30f) return bfail(COMPASS_E_UNSUPPORTED, "no tile fits");
+  *best_out = bt;
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_batch_plan_create(
+    const compass_build_job *jobs, int32_t n_jobs, int32_t counter_bits,
+    const compass_tune *tune, hipStream_t stream, compass_batch_plan *out) {
+  if (!out || (n_jobs > 0 && !jobs))
+    return bfail(COMPASS_E_ARG, "null pointer argument");
+  *out = nullptr;
+  if (n_jobs < 0) return bfail(COMPASS_E_ARG, "n_jobs < 0");
+  if (counter_bits != 32 && counter_bits != 64)
+    return bfail(COMPASS_E_ARG, "counter_bits must be 32 or 64");
+  compass_batch_plan_s *pl = new compass_batch_plan_s();
+  pl->counter_bits = counter_bits;
+  auto cleanup = [&](compass_status s) {
+    if (pl->dmem) (void)hipFree(pl->dmem);
+    delete pl;
+    return s;
+  };
+  for (int j = 0; j < n_jobs; ++j) {
+    const compass_build_job &J = jobs[j];
+    char msg[256];
+    if (J.n_rows < 0 || J.n_rows >= (1ll << 47) ||
+        (counter_bits == 32 && J.n_rows > 0x7FFFFFFFll)) {
+      snprintf(msg, sizeof msg, "job %d: n_rows out of range", j);
+      return cleanup(bfail(COMPASS_E_RANGE, msg));
+    }
+    if (J.d < 1 || J.d > 32 || J.w < 1 || J.w > (1 << 20) ||
+        J.n_sketches < 1 || J.n_sketches > kMaxSketches || J.n_preds < 0 ||
+        J.n_preds > kMaxPreds || !J.sketches || !J.n_selected ||
+        (J.n_preds > 0 && !J.preds)) {
+      snprintf(msg, sizeof msg, "job %d: bad d/w/sketches/predicates", j);
+      return cleanup(bfail(COMPASS_E_ARG, msg));
+    }
+    if ((size_t)J.w * 4 > kLdsBudget) {
+      snprintf(msg, sizeof msg, "job %d: w=%d exceeds the LDS budget", j, J.w);
+      return cleanup(bfail(COMPASS_E_UNSUPPORTED, msg));
+    }
+    BatchJob b;
+    memset(&b, 0, sizeof b);
+    b.n_rows = J.n_rows;
+    b.n_selected = J.n_selected;
+    b.n_preds = J.n_preds;
+    b.n_sketch = J.n_sketches;
+    b.d = J.d;
+    b.counter_bits = counter_bits;
+    b.seed_base = (int32_t)pl->seeds.size();
+    b.bm = bmod((uint32_t)J.w);
+    for (int q = 0; q < J.n_preds; ++q) {
+      const compass_pred &p = J.preds[q];
+      if (p.col < 0 || p.col >= J.n_pred_cols || !J.pred_cols ||
+          (J.n_rows > 0 && !J.pred_cols[p.col]) || p.kind < 0 || p.kind > 2 ||
+          (p.dtype != COMPASS_I32 && p.dtype != COMPASS_F32) ||
+          (p.kind == COMPASS_PRED_SUBSET &&
+           (p.dtype != COMPASS_I32 || !p.bitmap || p.domain < 0))) {
+        snprintf(msg, sizeof msg, "job %d predicate %d is invalid", j, q);
+        return cleanup(bfail(COMPASS_E_ARG, msg));
+      }
+      PredDev &d = b.preds[q];
+      d.col = J.pred_cols[p.col];
+      d.bitmap = p.bitmap;
+      d.domain = p.domain;
+      d.kind = p.kind;
+      d.dtype = p.dtype;
+      memcpy(&d.lo, &p.lo, 4);
+      memcpy(&d.hi, &p.hi, 4);
+    }
+    for (int s = 0; s < J.n_sketches; ++s) {
+      const compass_sketch_spec &k = J.sketches[s];
+      if (!k.seeds || !k.counters || (J.n_rows > 0 && !k.key_col) ||
+          (k.key_dtype != COMPASS_I32 && k.key_dtype != COMPASS_I64)) {
+        snprintf(msg, sizeof msg, "job %d sketch %d is invalid", j, s);
+        return cleanup(bfail(COMPASS_E_ARG, msg));
+      }
+      for (int i = 0; i < J.d; ++i) {
+        const uint64_t *sd = k.seeds + 6 * i;
+        for (int c = 0; c < 6; ++c)
+          if (sd[c] >= kP61) {
+            snprintf(msg, sizeof msg, "job %d sketch %d: seed not below p", j, s);
+            return cleanup(bfail(COMPASS_E_ARG, msg));
+          }
+        pl->seeds.push_back(RowSeeds{sd[0], sd[1], sd[2], sd[3], sd[4], sd[5]});
+      }
+      b.keys[s].col = k.key_col;
+      b.keys[s].dtype = k.key_dtype;
+      b.counters[s] = k.counters;
+      pl->zeros.push_back(ZeroRegion{
+          k.counters, (int64_t)J.d * J.w * (counter_bits / 8) / 4});
+    }
+    pl->zeros.push_back(ZeroRegion{J.n_selected, 2});
+    pl->jobs.push_back(b);
+    pl->job_rows.push_back(J.n_rows);
+    pl->job_slices.push_back(J.n_sketches * J.d);
+    pl->job_w.push_back(J.w);
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&pl->device) != hipSuccess ||
+      hipGetDeviceProperties(&prop, pl->device) != hipSuccess)
+    return cleanup(bfail(COMPASS_E_HIP, "device query failed"));
+  pl->n_cu = prop.multiProcessorCount;
+  if (pl->jobs.empty()) {
+    *out = pl;
+    return COMPASS_OK;
+  }
+  compass_tune t{};
+  if (tune) t = *tune;
+  const std::string key = shape_key(*pl, prop.gcnArchName);
+  if (t.rows_per_item <= 0 || t.lds_budget <= 0 || t.blocks_per_cu <= 0) {
+    compass_tune found{};
+    if (cache_lookup(key, &found)) {
+      t = found;
+    } else {
+      compass_status s = autotune(*pl, stream, &found);
+      if (s != COMPASS_OK) return cleanup(s);
+      t = found;
+      cache_store(key, t);
+    }
+  }
+  compass_status s = apply_tune(*pl, t);
+  if (s != COMPASS_OK) return cleanup(s);
+  // capture zeroing + persistent kernel on a private stream (capture does
+  // not execute anything; the graph is launched on the caller's stream)
+  hipStream_t cap;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(bfail(COMPASS_E_HIP, "hipStreamCreate failed"));
+  if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) !=
+      hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return cleanup(bfail(COMPASS_E_HIP, "hipStreamBeginCapture failed"));
+  }
+  enqueue(*pl, cap);
+  const hipError_t ce = hipStreamEndCapture(cap, &pl->graph);
+  (void)hipStreamDestroy(cap);
+  if (ce != hipSuccess)
+    return cleanup(bfail(COMPASS_E_HIP, "hipStreamEndCapture failed"));
+  if (hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) !=
+      hipSuccess) {
+    (void)hipGraphDestroy(pl->graph);
+    return cleanup(bfail(COMPASS_E_HIP, "hipGraphInstantiate failed"));
+  }
+  *out = pl;
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_batch_plan_launch(compass_batch_plan pl,
+                                                    hipStream_t stream) {
+  if (!pl) return bfail(COMPASS_E_ARG, "null plan");
+  if (pl->jobs.empty()) return COMPASS_OK;
+  BHIP(hipGraphLaunch(pl->exec, stream));
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_batch_plan_info(compass_batch_plan pl,
+                                                  compass_tune *tune,
+                                                  int32_t *n_items,
+                                                  int32_t *grid) {
+  if (!pl) return bfail(COMPASS_E_ARG, "null plan");
+  if (tune) *tune = pl->tune;
+  if (n_items) *n_items = pl->n_items;
+  if (grid) *grid = pl->grid;
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_batch_plan_destroy(compass_batch_plan pl) {
+  if (!pl) return COMPASS_OK;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->dmem) (void)hipFree(pl->dmem);
+  delete pl;
+  return COMPASS_OK;
+}

@@ -31,40 +31,30 @@
 
 #include "build_params.hpp"
 #include "device_math.hpp"
+#include "scan_common.hpp"
 
 namespace compass {
 
-__device__ __forceinline__ bool eval_pred(const PredDev &p, int64_t row) {
-  if (p.dtype == kDtF32) {
-    const float v = reinterpret_cast<const float *>(p.col)[row];
-    if (p.kind == kPredPoint) return v == p.lo.f;
-    return (v >= p.lo.f) & (v <= p.hi.f);
-  }
-  const int32_t v = reinterpret_cast<const int32_t *>(p.col)[row];
-  if (p.kind == kPredPoint) return v == p.lo.i;
-  if (p.kind == kPredRange) return (v >= p.lo.i) & (v <= p.hi.i);
-  // subset: dictionary code must lie in [0, domain) and have its bit set
-  if (v < 0 || (int64_t)v >= p.domain) return false;
-  const uint64_t word = p.bitmap[v >> 6];
-  return (word >> (v & 63)) & 1ull;
-}
+// Job view over the kernel-argument parameter block of one table.
+struct ParamJob {
+  const BuildParams &P;
+  __device__ int n_preds() const { return P.n_preds; }
+  __device__ const PredDev &pred(int q) const { return P.preds[q]; }
+  __device__ KeyDev key(int s) const { return P.keys[s]; }
+  __device__ int slice_sketch(int sl) const { return P.slice_sketch[sl]; }
+  __device__ int slice_row(int sl) const { return P.slice_row[sl]; }
+  __device__ RowSeeds seeds(int sl) const { return P.seeds[sl]; }
+  __device__ BucketMod bm() const { return P.bm; }
+  __device__ int counter_bits() const { return P.counter_bits; }
+  __device__ void *counters(int s) const { return P.counters[s]; }
+};
 
-__device__ __forceinline__ uint64_t load_field(const KeyDev &k, int64_t row) {
-  if (k.dtype == kDtI32) {
-    const int32_t v = reinterpret_cast<const int32_t *>(k.col)[row];
-    return v >= 0 ? (uint64_t)v : key_field((int64_t)v);
-  }
-  const int64_t v = reinterpret_cast<const int64_t *>(k.col)[row];
-  return key_field(v);
-}
-
-template <int kRowsPerThread>
 __global__ __launch_bounds__(kBuildThreads) void scan_sketch_kernel(
     const BuildParams P) {
   extern __shared__ int32_t lds[];
   __shared__ int32_t s_qn;
-  __shared__ unsigned long long s_sel;
 
+  const ParamJob job{P};
   const int ngroups = P.n_groups;
   const int gi = blockIdx.x % ngroups;
   const int64_t chunk = blockIdx.x / ngroups;
@@ -73,113 +63,88 @@ __global__ __launch_bounds__(kBuildThreads) void scan_sketch_kernel(
   const int ns = se - sb;
   const int w = (int)P.bm.w;
   int32_t *cnt = lds;                       // ns * w partial counters
-  int32_t *queue = lds + (size_t)ns * w;    // kTile row offsets
+  int32_t *queue = lds + (size_t)ns * w;    // kBuildTile row offsets
 
   for (int i = threadIdx.x; i < ns * w; i += kBuildThreads) cnt[i] = 0;
-  if (threadIdx.x == 0) s_sel = 0;
-
+  __syncthreads();
   const int64_t row0 = chunk * P.rows_per_chunk;
   const int64_t row1 = min(row0 + P.rows_per_chunk, P.n_rows);
-  const bool dense = (P.n_preds == 0);
-  constexpr int kTile = kBuildThreads * kRowsPerThread;
+  const uint64_t sel = scan_rows(job, row0, row1, sb, se, cnt, queue, &s_qn);
+  merge_slices(job, sb, se, cnt);
+  if (P.count_selected && gi == 0 && threadIdx.x == 0 && sel)
+    atomicAdd(reinterpret_cast<unsigned long long *>(P.n_selected),
+              (unsigned long long)sel);
+}
+
+// Sketch rows too wide for LDS (w * 4 > the LDS budget, e.g. w = 65536):
+// the same fused scan + compaction, with every (survivor, slice) hash
+// update going straight to the global counters as one integer atomic.  The
+// counters of such sketches (d x w x 8 bytes, a few MB each) stay resident in
+// the L2 / Infinity Cache, and at the selective predicates this is meant
+// for, HBM traffic is the predicate columns.  Work of a tile is flattened
+// to (survivor, slice) tasks so that a handful of survivors still keeps
+// every lane busy; the slice seeds are staged in LDS.
+struct DirectJob {
+  const BuildParams &P;
+  __device__ int n_preds() const { return P.n_preds; }
+  __device__ const PredDev &pred(int q) const { return P.preds[q]; }
+};
+
+__global__ __launch_bounds__(kBuildThreads) void scan_direct_kernel(
+    const BuildParams P, const RowSeeds *__restrict__ seeds, int32_t n_slices,
+    int32_t d) {
+  extern __shared__ int32_t lds[];
+  __shared__ int32_t s_qn;
+  RowSeeds *sd = reinterpret_cast<RowSeeds *>(lds);
+  int32_t *queue = lds + (n_slices * sizeof(RowSeeds) + 3) / 4;
+  for (int i = threadIdx.x; i < n_slices; i += kBuildThreads) sd[i] = seeds[i];
   __syncthreads();
-
-  for (int64_t base = row0; base < row1; base += kTile) {
-    const int nt = (int)min((int64_t)kTile, row1 - base);
-    int qn;
-    if (dense) {
-      qn = nt;
-    } else {
-      if (threadIdx.x == 0) s_qn = 0;
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < kRowsPerThread; ++k) {
-        const int r = threadIdx.x + k * kBuildThreads;
-        bool pass = r < nt;
-        if (pass) {
-          for (int q = 0; q < P.n_preds; ++q) {
-            if (!eval_pred(P.preds[q], base + r)) {
-              pass = false;
-              break;
-            }
-          }
-        }
-        const uint64_t ballot = __ballot(pass);
-        const int lane = __lane_id();
-        const uint32_t before = __builtin_amdgcn_mbcnt_hi(
-            (uint32_t)(ballot >> 32),
-            __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
-        const int total = __popcll(ballot);
-        int off = 0;
-        if (lane == 0 && total) off = atomicAdd(&s_qn, total);
-        off = __shfl(off, 0);
-        if (pass) queue[off + before] = r;
-      }
-      __syncthreads();
-      qn = s_qn;
-    }
-    if (threadIdx.x == 0) s_sel += (unsigned long long)qn;
-
-    // survivors handled by this thread: entries threadIdx.x + k * threads
-    int ridx[kRowsPerThread];
-    bool valid[kRowsPerThread];
-#pragma unroll
-    for (int k = 0; k < kRowsPerThread; ++k) {
-      const int q = threadIdx.x + k * kBuildThreads;
-      valid[k] = q < qn;
-      ridx[k] = valid[k] ? (dense ? q : queue[q]) : 0;
-    }
-    uint64_t x[kRowsPerThread];
-    int cur_sketch = -1;
-    for (int sl = sb; sl < se; ++sl) {
-      const int s = P.slice_sketch[sl];
-      if (s != cur_sketch) {
-        cur_sketch = s;
-#pragma unroll
-        for (int k = 0; k < kRowsPerThread; ++k)
-          x[k] = valid[k] ? load_field(P.keys[s], base + ridx[k]) : 0;
-      }
-      const RowSeeds sd = P.seeds[sl];
-      int32_t *c = cnt + (size_t)(sl - sb) * w;
-#pragma unroll
-      for (int k = 0; k < kRowsPerThread; ++k) {
-        if (!valid[k]) continue;
-        int32_t sign;
-        uint32_t b;
-        if ((x[k] >> 32) == 0)
-          hash_xi_h<true>(x[k], sd, P.bm, sign, b);
-        else
-          hash_xi_h<false>(x[k], sd, P.bm, sign, b);
-        atomicAdd(&c[b], sign);
-      }
+  const DirectJob job{P};
+  const int64_t row0 = (int64_t)blockIdx.x * P.rows_per_chunk;
+  const int64_t row1 = min(row0 + P.rows_per_chunk, P.n_rows);
+  uint64_t sel = 0;
+  const int w = (int)P.bm.w;
+  for (int64_t base = row0; base < row1; base += kBuildTile) {
+    const int nt = (int)min((int64_t)kBuildTile, row1 - base);
+    const int qn = compact_tile<DirectJob, kBuildRowsPerThread>(
+        job, base, nt, P.n_preds, queue, &s_qn);
+    sel += (uint64_t)qn;
+    const int tasks = qn * n_slices;
+    for (int t = threadIdx.x; t < tasks; t += kBuildThreads) {
+      const int q = t / n_slices;
+      const int sl = t - q * n_slices;
+      const int s = sl / d, i = sl - s * d;
+      const int64_t row = base + (P.n_preds ? queue[q] : q);
+      const uint64_t x = load_field(P.keys[s], row);
+      int32_t sign;
+      uint32_t b;
+      if ((x >> 32) == 0)
+        hash_xi_h<true>(x, sd[sl], P.bm, sign, b);
+      else
+        hash_xi_h<false>(x, sd[sl], P.bm, sign, b);
+      const size_t idx = (size_t)i * w + b;
+      if (P.counter_bits == 32)
+        atomicAdd(reinterpret_cast<int32_t *>(P.counters[s]) + idx, sign);
+      else
+        atomicAdd(reinterpret_cast<unsigned long long *>(P.counters[s]) + idx,
+                  (unsigned long long)(int64_t)sign);
     }
     __syncthreads();  // queue and s_qn are reused by the next tile
   }
+  if (P.count_selected && threadIdx.x == 0 && sel)
+    atomicAdd(reinterpret_cast<unsigned long long *>(P.n_selected),
+              (unsigned long long)sel);
+}
 
-  // merge pass: LDS partials -> global counters (non-zero buckets only)
-  for (int l = 0; l < ns; ++l) {
-    const int sl = sb + l;
-    const int s = P.slice_sketch[sl];
-    const int row = P.slice_row[sl];
-    const int32_t *c = cnt + (size_t)l * w;
-    if (P.counter_bits == 32) {
-      int32_t *g = reinterpret_cast<int32_t *>(P.counters[s]) + (size_t)row * w;
-      for (int j = threadIdx.x; j < w; j += kBuildThreads) {
-        const int32_t v = c[j];
-        if (v) atomicAdd(&g[j], v);
-      }
-    } else {
-      unsigned long long *g =
-          reinterpret_cast<unsigned long long *>(P.counters[s]) +
-          (size_t)row * w;
-      for (int j = threadIdx.x; j < w; j += kBuildThreads) {
-        const int32_t v = c[j];
-        if (v) atomicAdd(&g[j], (unsigned long long)(int64_t)v);
-      }
-    }
-  }
-  if (P.count_selected && gi == 0 && threadIdx.x == 0 && s_sel)
-    atomicAdd(reinterpret_cast<unsigned long long *>(P.n_selected), s_sel);
+hipError_t launch_scan_direct(const BuildParams &P, const void *seeds,
+                              int n_slices, int d, int n_blocks,
+                              hipStream_t st) {
+  const size_t lds = ((size_t)n_slices * sizeof(RowSeeds) + 3) / 4 * 4 +
+                     (size_t)kBuildTile * 4;
+  hipLaunchKernelGGL(scan_direct_kernel, dim3((unsigned)n_blocks),
+                     dim3(kBuildThreads), lds, st, P,
+                     reinterpret_cast<const RowSeeds *>(seeds), n_slices, d);
+  return hipGetLastError();
 }
 
 // zero-fill used instead of hipMemsetAsync so that callers may capture the
@@ -202,7 +167,7 @@ hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t st) {
 
 hipError_t launch_scan_sketch(const BuildParams &P, int n_blocks,
                               size_t lds_bytes, hipStream_t st) {
-  hipLaunchKernelGGL(scan_sketch_kernel<kBuildRowsPerThread>,
+  hipLaunchKernelGGL(scan_sketch_kernel,
                      dim3((unsigned)n_blocks), dim3(kBuildThreads), lds_bytes,
                      st, P);
   return hipGetLastError();

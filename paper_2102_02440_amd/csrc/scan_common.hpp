@@ -1,0 +1,163 @@
+// scan_common.hpp -- the per-chunk body of the fused selection scan +
+// Fast-AGMS sketch update, shared by the one-table kernel and the batched
+// persistent kernel.  A "job view" J supplies the table's predicates, key
+// columns, slice -> (sketch, row) mapping, seeds and counters.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "build_params.hpp"
+#include "device_math.hpp"
+
+namespace compass {
+
+__device__ __forceinline__ bool eval_pred(const PredDev &p, int64_t row) {
+  if (p.dtype == kDtF32) {
+    const float v = reinterpret_cast<const float *>(p.col)[row];
+    if (p.kind == kPredPoint) return v == p.lo.f;
+    return (v >= p.lo.f) & (v <= p.hi.f);
+  }
+  const int32_t v = reinterpret_cast<const int32_t *>(p.col)[row];
+  if (p.kind == kPredPoint) return v == p.lo.i;
+  if (p.kind == kPredRange) return (v >= p.lo.i) & (v <= p.hi.i);
+  // subset: dictionary code must lie in [0, domain) and have its bit set
+  if (v < 0 || (int64_t)v >= p.domain) return false;
+  const uint64_t word = p.bitmap[v >> 6];
+  return (word >> (v & 63)) & 1ull;
+}
+
+__device__ __forceinline__ uint64_t load_field(const KeyDev &k, int64_t row) {
+  if (k.dtype == kDtI32) {
+    const int32_t v = reinterpret_cast<const int32_t *>(k.col)[row];
+    return v >= 0 ? (uint64_t)v : key_field((int64_t)v);
+  }
+  const int64_t v = reinterpret_cast<const int64_t *>(k.col)[row];
+  return key_field(v);
+}
+
+// Compacts the qualifying rows of tile [base, base + nt) into `queue`
+// (row offsets, unordered: the sums do not depend on order) and returns
+// their number; with no predicates every row qualifies and the queue is not
+// used.  Every thread of the block must call it.
+template <class J, int kRowsPerThread>
+__device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
+                            int32_t *queue, int32_t *s_qn) {
+  if (n_preds == 0) return nt;
+  if (threadIdx.x == 0) *s_qn = 0;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRowsPerThread; ++k) {
+    const int r = threadIdx.x + k * kBuildThreads;
+    bool pass = r < nt;
+    if (pass) {
+      for (int q = 0; q < n_preds; ++q) {
+        if (!eval_pred(job.pred(q), base + r)) {
+          pass = false;
+          break;
+        }
+      }
+    }
+    const uint64_t ballot = __ballot(pass);
+    const int lane = __lane_id();
+    const uint32_t before = __builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(ballot >> 32),
+        __builtin_amdgcn_mbcnt_lo((uint32_t)ballot, 0u));
+    const int total = __popcll(ballot);
+    int off = 0;
+    if (lane == 0 && total) off = atomicAdd(s_qn, total);
+    off = __shfl(off, 0);
+    if (pass) queue[off + before] = r;
+  }
+  __syncthreads();
+  return *s_qn;
+}
+
+// Scans rows [row0, row1) of job J into the LDS partial counters `cnt` of
+// slices [sb, se) (slice sl at cnt + (sl - sb) * w).  Returns, in thread 0,
+// the number of qualifying rows.  `queue` holds kBuildTile row offsets;
+// `s_qn` is a shared counter.  Every thread of the block must call it.
+template <class J>
+__device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
+                              int sb, int se, int32_t *cnt, int32_t *queue,
+                              int32_t *s_qn) {
+  constexpr int kRowsPerThread = kBuildRowsPerThread;
+  constexpr int kTile = kBuildTile;
+  const int w = (int)job.bm().w;
+  const int n_preds = job.n_preds();
+  const bool dense = (n_preds == 0);
+  uint64_t sel = 0;
+  for (int64_t base = row0; base < row1; base += kTile) {
+    const int nt = (int)min((int64_t)kTile, row1 - base);
+    const int qn = compact_tile<J, kRowsPerThread>(job, base, nt, n_preds,
+                                                   queue, s_qn);
+    sel += (uint64_t)qn;
+
+    // survivors handled by this thread: entries threadIdx.x + k * threads
+    int ridx[kRowsPerThread];
+    bool valid[kRowsPerThread];
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; ++k) {
+      const int q = threadIdx.x + k * kBuildThreads;
+      valid[k] = q < qn;
+      ridx[k] = valid[k] ? (dense ? q : queue[q]) : 0;
+    }
+    uint64_t x[kRowsPerThread];
+    int cur_sketch = -1;
+    for (int sl = sb; sl < se; ++sl) {
+      const int s = job.slice_sketch(sl);
+      if (s != cur_sketch) {
+        cur_sketch = s;
+        const KeyDev kd = job.key(s);
+#pragma unroll
+        for (int k = 0; k < kRowsPerThread; ++k)
+          x[k] = valid[k] ? load_field(kd, base + ridx[k]) : 0;
+      }
+      const RowSeeds sd = job.seeds(sl);
+      const BucketMod bm = job.bm();
+      int32_t *c = cnt + (size_t)(sl - sb) * w;
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        if (!valid[k]) continue;
+        int32_t sign;
+        uint32_t b;
+        if ((x[k] >> 32) == 0)
+          hash_xi_h<true>(x[k], sd, bm, sign, b);
+        else
+          hash_xi_h<false>(x[k], sd, bm, sign, b);
+        atomicAdd(&c[b], sign);
+      }
+    }
+    __syncthreads();  // queue and s_qn are reused by the next tile
+  }
+  return sel;
+}
+
+// Adds the non-zero LDS partials of slices [sb, se) into the job's global
+// counters (integer atomics: order-independent, hence exact).
+template <class J>
+__device__ void merge_slices(const J &job, int sb, int se,
+                             const int32_t *cnt) {
+  const int w = (int)job.bm().w;
+  for (int sl = sb; sl < se; ++sl) {
+    const int s = job.slice_sketch(sl);
+    const int row = job.slice_row(sl);
+    const int32_t *c = cnt + (size_t)(sl - sb) * w;
+    if (job.counter_bits() == 32) {
+      int32_t *g = reinterpret_cast<int32_t *>(job.counters(s)) + (size_t)row * w;
+      for (int j = threadIdx.x; j < w; j += kBuildThreads) {
+        const int32_t v = c[j];
+        if (v) atomicAdd(&g[j], v);
+      }
+    } else {
+      unsigned long long *g =
+          reinterpret_cast<unsigned long long *>(job.counters(s)) +
+          (size_t)row * w;
+      for (int j = threadIdx.x; j < w; j += kBuildThreads) {
+        const int32_t v = c[j];
+        if (v) atomicAdd(&g[j], (unsigned long long)(int64_t)v);
+      }
+    }
+  }
+}
+
+}  // namespace compass

@@ -1,0 +1,114 @@
+"""Learned correction of merged-sketch estimates, end to end on the GPU.
+
+Dataset: every query of a workload is sketched with the batched persistent
+build, its sampled sub-plans are estimated with compass_estimate, and the 20
+features per sub-plan are computed by the library's feature kernel.  The
+network (compass_mlp_*) is trained by the library's forward / backward /
+Adam kernels on ln(1 + true) targets supplied by the caller (exact join
+sizes from an independent counter), and evaluated against the raw median
+estimate on held-out sub-plans by q-error.  The raw estimate stays the
+fallback: the network predicts a correction on top of it.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import compass as C
+
+
+def init_params(seed: int, n_in=20, hidden=64, layers=3) -> np.ndarray:
+    """He-uniform hidden weights, zero biases, zero output layer (the
+    untrained network returns the raw estimate)."""
+    rng = np.random.default_rng(seed)
+    dims = [n_in] + [hidden] * layers + [1]
+    flat = []
+    for i in range(len(dims) - 1):
+        lim = np.sqrt(6.0 / dims[i])
+        W = rng.uniform(-lim, lim, size=(dims[i + 1], dims[i]))
+        if i == len(dims) - 2:
+            W[:] = 0.0
+        flat += [W.reshape(-1), np.zeros(dims[i + 1])]
+    return np.concatenate(flat).astype(np.float32)
+
+
+def build_features(pool, queries, subplans, device="cuda", group=1500,
+                   tune=(262144, 131072, 1), log=None):
+    """(x [N,20], base [N], est [N] float64, flags [N]) device tensors for the
+    sub-plans `subplans[q]` of every query q, in query order."""
+    pool_cols = C.upload_pool(pool, device)
+    xs, bases, ests, flags = [], [], [], []
+    t0 = time.time()
+    for g0 in range(0, len(queries), group):
+        qs = queries[g0:g0 + group]
+        db = C.DeviceBatch(pool, qs, device=device, pool_cols=pool_cols)
+        plan = db.plan(tune=tune)
+        plan.launch()
+        for k, pq in enumerate(qs):
+            masks = subplans[g0 + k]
+            if not masks:
+                continue
+            eu = [e.u for e in pq.edges]
+            ev = [e.v for e in pq.edges]
+            row_est, est, fl = db.estimate(k, masks)
+            shape = torch.from_numpy(C.shape_stats(len(pq.tables), eu, ev, masks)).to(device)
+            md = torch.from_numpy(np.asarray(masks, dtype=np.uint64).view(np.int64)).to(device)
+            x, base = C.features(row_est, est, md, db.n_selected[k], len(pq.tables), shape)
+            xs.append(x)
+            bases.append(base)
+            ests.append(est)
+            flags.append(fl)
+        torch.cuda.synchronize()
+        plan.close()
+        del db
+        if log:
+            log("[learned] features of queries %d..%d in %.1fs" %
+                (g0, g0 + len(qs), time.time() - t0))
+    return torch.cat(xs), torch.cat(bases), torch.cat(ests), torch.cat(flags)
+
+
+def train(x, base, target, init, epochs=30, batch=512, lr=1e-3, seed=0,
+          log=None):
+    """Adam on mean squared error of ln(1 + card); returns (mlp, losses)."""
+    mlp = C.MLP(init)
+    n = x.shape[0]
+    g = torch.Generator(device=x.device)
+    g.manual_seed(seed)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, device=x.device, generator=g)
+        tot = torch.zeros((), dtype=torch.float64, device=x.device)
+        steps = 0
+        for s in range(0, n - batch + 1, batch):
+            idx = perm[s:s + batch]
+            loss = mlp.train_step(x[idx].contiguous(), base[idx].contiguous(),
+                                  target[idx].contiguous(), lr)
+            tot += loss[0].double()
+            steps += 1
+        hist.append(float(tot.item()) / max(1, steps))
+        if log:
+            log("[learned] epoch %d mse %.4f" % (ep, hist[-1]))
+    return mlp, hist
+
+
+def qerror(est, true):
+    e = np.maximum(np.asarray(est, dtype=np.float64), 1.0)
+    t = np.maximum(np.asarray(true, dtype=np.float64), 1.0)
+    return np.maximum(e / t, t / e)
+
+
+def summarize(q):
+    return {"median": float(np.median(q)), "p90": float(np.percentile(q, 90)),
+            "p99": float(np.percentile(q, 99)), "max": float(np.max(q))}
+
+
+def evaluate(mlp, x, base, est, true):
+    """q-error of the raw median estimate and of the corrected estimate."""
+    y = mlp.forward(x, base)
+    learned = np.expm1(y.double().cpu().numpy())
+    raw = est.cpu().numpy()
+    return {"raw": summarize(qerror(raw, true)),
+            "learned": summarize(qerror(learned, true)),
+            "n": int(len(true))}

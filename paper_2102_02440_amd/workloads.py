@@ -243,3 +243,246 @@ def small_random_query(rng: np.random.Generator, n_tables: int, n_rows: int,
                 break
     seeds = draw_seeds(rng, len(edges), d)
     return Query(tables, edges, d, w, seeds, 32)
+
+
+# --------------------------------------------------------------------------
+# Batched workload: a pool of tables with primary keys and Zipf foreign keys,
+# and many queries over it, each with its own selections, sketch shape
+# (d, w) and hash seeds.  Shapes follow the 6a recipe above; table sizes are
+# log-uniform, so filtered sizes are very uneven across the batch.
+# --------------------------------------------------------------------------
+@dataclass
+class PoolTable:
+    name: str
+    cols: dict
+    fks: list          # [(column, referenced pool table)]
+
+    @property
+    def n_rows(self) -> int:
+        return len(self.cols["id"])
+
+
+def schema_pool(seed: int = DEFAULT_SEED, n_tables: int = 48,
+                size_range=(10_000, 36_000_000), scale: float = 1.0,
+                fk_range=(2, 3)):
+    rng = rng_of(seed, 30)
+    lo, hi = np.log(size_range[0]), np.log(size_range[1])
+    sizes = [max(64, int(np.exp(rng.uniform(lo, hi)) * scale))
+             for _ in range(n_tables)]
+    perms = [None] * n_tables
+    pool = []
+    for t in range(n_tables):
+        n = sizes[t]
+        cols = {"id": np.arange(n, dtype=np.int32),
+                "a_uni": rng.integers(0, 1_000_000, size=n, dtype=np.int64).astype(np.int32),
+                "a_cat": rng.integers(0, 1000, size=n, dtype=np.int64).astype(np.int32),
+                "a_f": rng.random(n, dtype=np.float32)}
+        fks = []
+        for k in range(int(rng.integers(fk_range[0], fk_range[1] + 1))):
+            ref = int(rng.integers(0, n_tables - 1))
+            ref = ref if ref < t else ref + 1
+            if perms[ref] is None:
+                perms[ref] = rng_of(seed, 31, ref).permutation(sizes[ref]).astype(np.int64)
+            s = float(rng.uniform(0.8, 1.2))
+            cols["fk%d" % k] = fk_column(rng, n, sizes[ref], s, perms[ref])
+            fks.append(("fk%d" % k, ref))
+        pool.append(PoolTable("p%d" % t, cols, fks))
+    return pool
+
+
+@dataclass
+class PoolQuery:
+    tables: list       # pool table indices (query-local order)
+    edges: list        # Edge over query-local indices
+    preds: list        # per query-local table: list of Predicate
+    d: int
+    w: int
+    seeds: np.ndarray  # (n_edges, d, 6)
+
+    def incident(self, t):
+        out = []
+        for i, e in enumerate(self.edges):
+            if e.u == t:
+                out.append((i, 0, e.ucol))
+            elif e.v == t:
+                out.append((i, 1, e.vcol))
+        return out
+
+
+def random_predicates(rng, pred_prob=0.7):
+    """None, or one selection of selectivity log-uniform in [0.1%, 20%]."""
+    if rng.random() >= pred_prob:
+        return []
+    sel = float(np.exp(rng.uniform(np.log(0.001), np.log(0.2))))
+    kind = ["range", "subset", "point", "frange"][int(rng.integers(0, 4))]
+    if kind == "range":
+        width = max(1, int(sel * 1_000_000))
+        lo = int(rng.integers(0, 1_000_000 - width + 1))
+        return [Predicate("a_uni", "range", lo, lo + width - 1)]
+    if kind == "subset":
+        k = max(1, int(round(sel * 1000)))
+        codes = rng.choice(1000, size=k, replace=False)
+        return [Predicate("a_cat", "subset", bitmap=subset_bitmap(codes, 1000),
+                          domain=1000)]
+    if kind == "point":
+        return [Predicate("a_cat", "point", int(rng.integers(0, 1000)))]
+    lo = float(rng.random() * (1.0 - sel))
+    return [Predicate("a_f", "range", lo, lo + sel)]
+
+
+def query_batch(pool, seed: int = DEFAULT_SEED, n_queries: int = 512,
+                max_tables: int = 17, mean_tables: float = 4.5,
+                d_choices=(5, 7, 11), w_choices=(1024, 2048, 4096, 8192, 16384),
+                tri_prob: float = 0.15, pred_prob: float = 0.7):
+    """Connected queries over the pool's foreign-key graph.  Each join edge
+    is a foreign key = primary key predicate; with probability tri_prob a
+    query also gets the transitive equality of two foreign keys that
+    reference the same table of the query (a triangle, as in 6a)."""
+    rng = rng_of(seed, 40)
+    links = []  # (a, acol, b): a.acol references b.id
+    for a, pt in enumerate(pool):
+        for (c, b) in pt.fks:
+            links.append((a, c, b))
+    out = []
+    for _ in range(n_queries):
+        target = int(min(max_tables, max(2, 1 + rng.geometric(1.0 / (mean_tables - 1)))))
+        start = int(rng.integers(0, len(pool)))
+        tabs = [start]
+        edges = []
+        while len(tabs) < target:
+            cand = [(a, c, b) for (a, c, b) in links
+                    if (a in tabs) != (b in tabs)]
+            if not cand:
+                break
+            a, c, b = cand[int(rng.integers(0, len(cand)))]
+            new = b if a in tabs else a
+            tabs.append(new)
+            edges.append(Edge(tabs.index(a), c, tabs.index(b), "id"))
+        if rng.random() < tri_prob:
+            # two foreign keys of the query referencing the same query table
+            by_ref = {}
+            for e in edges:
+                if e.vcol == "id":
+                    by_ref.setdefault(e.v, []).append(e)
+            for v, es in by_ref.items():
+                if len(es) >= 2:
+                    e1, e2 = es[0], es[1]
+                    edges.append(Edge(e1.u, e1.ucol, e2.u, e2.ucol))
+                    break
+        preds = [random_predicates(rng, pred_prob) for _ in tabs]
+        d = int(rng.choice(d_choices))
+        w = int(rng.choice(w_choices))
+        seeds = draw_seeds(rng, len(edges), d)
+        out.append(PoolQuery(tabs, edges, preds, d, w, seeds))
+    return out
+
+
+def pool_query_as_query(pool, pq: PoolQuery) -> Query:
+    """A standalone Query (tables with their columns and selections)."""
+    tables = [Table(pool[t].name, pool[t].cols, pq.preds[i])
+              for i, t in enumerate(pq.tables)]
+    return Query(tables, pq.edges, pq.d, pq.w, pq.seeds, 32)
+
+
+# --------------------------------------------------------------------------
+# Learned-correction workload: pools of tables of 10k..2M rows (so exact
+# join sizes stay affordable for the oracle), tree-shaped queries of up to 8
+# tables, d=7, w=8192; training and held-out sets come from disjoint seeds.
+# --------------------------------------------------------------------------
+LEARNED_TRAIN_SEED = 1001
+LEARNED_TEST_SEED = 2002
+
+
+def learned_workload(seed: int, n_queries: int, pool_tables: int = 48,
+                     size_range=(10_000, 2_000_000), max_tables: int = 8,
+                     d: int = 7, w: int = 8192, scale: float = 1.0):
+    pool = schema_pool(seed, n_tables=pool_tables, size_range=size_range,
+                       scale=scale)
+    queries = query_batch(pool, seed + 1, n_queries, max_tables=max_tables,
+                          d_choices=(d,), w_choices=(w,), tri_prob=0.0)
+    return pool, queries
+
+
+def connected_masks(n_tables, edge_u, edge_v, min_tables=1, max_tables=64):
+    adj = [0] * n_tables
+    for u, v in zip(edge_u, edge_v):
+        adj[u] |= 1 << v
+        adj[v] |= 1 << u
+    out = []
+    for m in range(1, 1 << n_tables):
+        k = bin(m).count("1")
+        if k < min_tables or k > max_tables:
+            continue
+        seen = m & -m
+        while True:
+            grow = seen
+            s, t = seen, 0
+            while s:
+                if s & 1:
+                    grow |= adj[t] & m
+                s >>= 1
+                t += 1
+            if grow == seen:
+                break
+            seen = grow
+        if seen == m:
+            out.append(m)
+    return out
+
+
+def learned_subplans(queries, seed: int, max_per_query: int = 24):
+    """Per query: its connected sub-plans of >= 2 tables, a seeded sample of
+    at most max_per_query of them."""
+    rng = rng_of(seed, 50)
+    out = []
+    for pq in queries:
+        ms = connected_masks(len(pq.tables), [e.u for e in pq.edges],
+                             [e.v for e in pq.edges], min_tables=2)
+        if len(ms) > max_per_query:
+            idx = rng.choice(len(ms), size=max_per_query, replace=False)
+            ms = [ms[i] for i in sorted(idx)]
+        out.append(ms)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Large scan: one fact table of 1B rows generated directly in device memory
+# (64 GB of columns; host generation would take minutes): six int64 join
+# keys Zipf(1.1) over a 50M-key domain (a seeded permutation per column),
+# two int32 columns uniform in [0, 1e6) and two float32 columns uniform in
+# [0, 1), four range predicates of ~31.6% each (1% combined), d=11,
+# w=65536, int64 counters.
+# --------------------------------------------------------------------------
+def large_scan_device(seed: int = DEFAULT_SEED, n_rows: int = 1_000_000_000,
+                      domain: int = 50_000_000, zipf_s: float = 1.1,
+                      n_keys: int = 6, d: int = 11, w: int = 65536,
+                      device="cuda", chunk: int = 1 << 26):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) * 7919 + 5)
+    ranks = torch.arange(1, domain + 1, dtype=torch.float64, device=device)
+    cdf = torch.cumsum(ranks.pow_(-float(zipf_s)), 0)
+    cdf /= cdf[-1].clone()
+    del ranks
+    cols = {}
+    for k in range(n_keys):
+        perm = torch.randperm(domain, generator=g, device=device)
+        out = torch.empty(n_rows, dtype=torch.int64, device=device)
+        for a in range(0, n_rows, chunk):
+            b = min(n_rows, a + chunk)
+            u = torch.rand(b - a, generator=g, device=device, dtype=torch.float64)
+            r = torch.searchsorted(cdf, u).clamp_(max=domain - 1)
+            out[a:b] = perm[r]
+        cols["key%d" % k] = out
+        del perm
+    for k in range(2):
+        cols["i%d" % k] = torch.randint(0, 1_000_000, (n_rows,), generator=g,
+                                        device=device, dtype=torch.int32)
+    for k in range(2):
+        cols["f%d" % k] = torch.rand(n_rows, generator=g, device=device,
+                                     dtype=torch.float32)
+    del cdf
+    preds = [Predicate("i0", "range", 0, 316_227), Predicate("i1", "range", 0, 316_227),
+             Predicate("f0", "range", 0.0, 0.316227), Predicate("f1", "range", 0.0, 0.316227)]
+    seeds = draw_seeds(rng_of(seed, 60), n_keys, d)
+    return cols, preds, seeds

@@ -46,7 +46,7 @@ def _spec(C, d, seeds):
 @pytest.mark.parametrize("kw,status", [
     (dict(d=0), 1), (dict(d=33), 1), (dict(w=0), 1), (dict(counter_bits=16), 1),
     (dict(n_rows=-1), 2), (dict(n_rows=2**31), 2), (dict(n_rows=2**47, counter_bits=64), 2),
-    (dict(w=1 << 16), 5), (dict(bad_seed=True), 1), (dict(n_sketches=0), 1),
+    (dict(w=(1 << 20) + 1), 1), (dict(bad_seed=True), 1), (dict(n_sketches=0), 1),
 ])
 def test_build_validation(C, kw, status):
     L = C.lib()

@@ -220,3 +220,117 @@ def test_collision_free_exact_two_way(oracle):
     assert C.row_values(row_est)[0] == [true] * 5
     assert est.item() == float(true)
     assert flags.item() == C.FLAG_EXACT
+
+
+@gpu
+def test_job6a_full_size(oracle):
+    """Full-size 6a-shaped workload (ci 36M, mk 4.5M, t 2.5M, n 4.2M, k 134k;
+    d=7, w=8192) in the launch configuration the benchmark times.
+    Exact oracle comparison for the sketches of k, mk, t, n and the selected
+    counts; for ci (756M hash updates) exact comparison on a 1M-row slice
+    plus properties that hold at any size: linearity across launches with a
+    different chunking, sum of a row == n_sel (mod 2), L1 of a row <= n_sel.
+    Estimates: every tree sub-plan on all rows; the four triangle sub-plans
+    on sampled rows 0 and 6 (the oracle costs ~w^2 per row there)."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    q = W.job6a()
+    _say("job6a full size", [tb.n_rows for tb in q.tables])
+    dq = C.DeviceQuery(q)
+    dq.build()
+    torch.cuda.synchronize()
+    n_sel = []
+    side_sk = [None] * (2 * len(q.edges))
+    for t, tb in enumerate(q.tables):
+        mask = oracle.eval_predicates(tb.cols, tb.preds)
+        n_sel.append(int(mask.sum()))
+        if tb.name == "ci":
+            continue
+        for (e, side, c) in q.incident(t):
+            side_sk[2 * e + side] = oracle.sketch(tb.cols[c][mask], q.seeds[e], q.d, q.w)
+            g = dq.sketch_of_side[2 * e + side].cpu().numpy().astype(np.int64)
+            assert np.array_equal(g, side_sk[2 * e + side]), (tb.name, e)
+    assert dq.n_selected.cpu().tolist() == n_sel
+    ci = 3
+    tb = q.tables[ci]
+    inc = q.incident(ci)
+    for (e, side, c) in inc:
+        g = dq.sketch_of_side[2 * e + side].cpu().numpy().astype(np.int64)
+        assert np.all(g.sum(axis=1) % 2 == n_sel[ci] % 2)
+        assert np.all(np.abs(g).sum(axis=1) <= n_sel[ci])
+        side_sk[2 * e + side] = g
+    # linearity across launches: three slices accumulated into new counters
+    keys = [dq.tables[ci]["keys"][k] for k in range(len(inc))]
+    acc = [torch.zeros_like(dq.tables[ci]["counters"][k]) for k in range(len(inc))]
+    nacc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cuts = [0, 1_000_000, 20_000_003, tb.n_rows]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        C.sketch_build(b - a, [], [], [k[a:b] for k in keys],
+                       [q.seeds[e] for (e, _, _) in inc], acc, nacc, q.d, q.w,
+                       accumulate=True)
+    torch.cuda.synchronize()
+    for k in range(len(inc)):
+        assert torch.equal(acc[k], dq.tables[ci]["counters"][k])
+    # exact oracle check of the first slice (1M rows), built alone
+    part = [torch.zeros_like(x) for x in acc]
+    C.sketch_build(1_000_000, [], [], [k[:1_000_000] for k in keys],
+                   [q.seeds[e] for (e, _, _) in inc], part, nacc, q.d, q.w)
+    torch.cuda.synchronize()
+    for k, (e, _, c) in enumerate(inc):
+        o = oracle.sketch(tb.cols[c][:1_000_000], q.seeds[e], q.d, q.w)
+        assert np.array_equal(part[k].cpu().numpy().astype(np.int64), o)
+    # estimates
+    masks = oracle.connected_subplans(5, q.edge_u, q.edge_v)
+    row_est, est, flags = dq.estimate(masks)
+    torch.cuda.synchronize()
+    got = C.row_values(row_est)
+    fl = flags.cpu().numpy()
+    assert not np.any(fl & C.FLAG_UNSUPPORTED)
+    tri = [m for m in masks if (m & 0b1110) == 0b1110]
+    trees = [m for m in masks if m not in tri]
+    vals, e_o, f_o = oracle.estimate(5, q.edge_u, q.edge_v, q.d, q.w, side_sk,
+                                     n_sel, trees)
+    for m, v in zip(trees, vals):
+        assert got[masks.index(m)] == [x & ((1 << 128) - 1) for x in v], hex(m)
+    for m, e in zip(trees, e_o):
+        assert est.cpu().numpy()[masks.index(m)] == e
+    for row in (0, q.d - 1):
+        sk1 = [s[row:row + 1] for s in side_sk]
+        v1, _, _ = oracle.estimate(5, q.edge_u, q.edge_v, 1, q.w, sk1, n_sel, tri)
+        for m, v in zip(tri, v1):
+            assert got[masks.index(m)][row] == v[0] & ((1 << 128) - 1), (hex(m), row)
+    assert np.array_equal(fl, np.asarray(
+        oracle.estimate(5, q.edge_u, q.edge_v, 1, 1,
+                        [np.zeros((1, 1), np.int64)] * 10, n_sel, masks)[2]))
+
+
+@gpu
+@pytest.mark.parametrize("w,bits", [(65536, 64), (40000, 32), (1 << 20, 64)])
+def test_wide_sketches_direct_path(oracle, w, bits):
+    """Rows too wide for LDS partials (w * 4 > 128 KiB) take the direct
+    global-atomic kernel: same counters as the oracle, int32 and int64."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(w)
+    n = 300_001
+    d = 11
+    keys = [rng.integers(-2**40, 2**40, n).astype(np.int64),
+            W.fk_column(rng, n, 50_000, 1.1, rng.permutation(50_000)).astype(np.int64)]
+    a = rng.integers(0, 1_000_000, n).astype(np.int32)
+    f = rng.random(n).astype(np.float32)
+    seeds = [W.draw_seeds(rng, 1, d)[0] for _ in keys]
+    preds = [{"col": 0, "kind": "range", "lo": 0, "hi": 316_227},
+             {"col": 1, "kind": "range", "lo": 0.0, "hi": 0.316227}]
+    cdt = torch.int64 if bits == 64 else torch.int32
+    cnt = [torch.full((d, w), 5, dtype=cdt, device="cuda") for _ in keys]
+    nsel = torch.zeros(1, dtype=torch.int64, device="cuda")
+    print("[case] wide", w, bits, flush=True)
+    C.sketch_build(n, [torch.from_numpy(a).cuda(), torch.from_numpy(f).cuda()], preds,
+                   [torch.from_numpy(k).cuda() for k in keys], seeds, cnt, nsel, d, w,
+                   counter_bits=bits)
+    torch.cuda.synchronize()
+    mask = (a <= 316_227) & (f >= np.float32(0.0)) & (f <= np.float32(0.316227))
+    assert nsel.item() == int(mask.sum())
+    for k, c in zip(keys, range(2)):
+        o = oracle.sketch(k[mask], seeds[c], d, w)
+        assert np.array_equal(cnt[c].cpu().numpy().astype(np.int64), o)

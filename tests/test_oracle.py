@@ -361,3 +361,31 @@ def test_l1_permutation_distance_example(oracle):
 def test_qerror():
     from oracle import oracle as o
     assert o.qerror([10, 0.5, 100], [100, 4, 100]).tolist() == [10.0, 4.0, 1.0]
+
+
+def test_fk_tree_truth_vs_hash_aggregation(oracle):
+    """The bincount message passing for foreign-key trees equals the hash
+    aggregation oracle (itself pinned by nested loops above)."""
+    pool = W.schema_pool(seed=5, n_tables=10, scale=0.0005, size_range=(10_000, 200_000))
+    qs = W.query_batch(pool, seed=6, n_queries=20, tri_prob=0.0, max_tables=6)
+    for pq in qs:
+        q = W.pool_query_as_query(pool, pq)
+        filt = []
+        for tb in q.tables:
+            m = oracle.eval_predicates(tb.cols, tb.preds)
+            filt.append({c: v[m] for c, v in tb.cols.items()})
+        edges = [(e.u, e.ucol, e.v, e.vcol) for e in q.edges]
+        dom = [pool[t].n_rows for t in pq.tables]
+        for mask in oracle.connected_subplans(len(q.tables), q.edge_u, q.edge_v)[:30]:
+            a = oracle.true_cardinality(filt, edges, mask)
+            b = oracle.true_cardinality_fk_tree(filt, edges, mask, dom)
+            assert a == b, (mask, a, b)
+
+
+def test_i128_rows_feature_reference(oracle):
+    x, base = oracle.mlp_features([5, -3, 100, 0, 7, 2**70, -2**65], 99.5,
+                                  [10, 1000, 3], [3, 2, 2, 2, 0])
+    assert x.shape == (20,)
+    assert x[0] == -np.log1p(2.0**65) and x[6] == np.log1p(2.0**70)
+    assert x[7] == np.log2(1001.0) and x[9] == np.log2(4.0) and x[10] == 0.0
+    assert base == np.log1p(99.5)
