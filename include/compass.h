@@ -276,6 +276,25 @@ compass_status compass_mlp_features(const compass_i128 *row_est, int32_t d,
                                     int32_t n, float *x, float *base,
                                     hipStream_t stream);
 
+/* Join order enumeration (Section 6, Algorithm 1), on the host: DFS over
+ * the join graph building left-deep orders without cross products; sources
+ * in increasing f(v) = alpha card(v)/max card + beta deg(v)/max deg;
+ * extensions in increasing estimate of the extended sub-plan; a branch is
+ * pruned when its running cost (sum of the estimates of all its prefixes)
+ * exceeds the best complete cost; at most max_plans complete plans per
+ * source (max_plans <= 0: exhaustive).  masks/est: host arrays of the
+ * estimates of (at least) every connected sub-plan the search visits, e.g.
+ * compass_estimate's output copied back; card: host, per table (the
+ * single-table estimates).  Outputs: the best order (n_tables ids), its
+ * cost and the number of complete plans reached. */
+compass_status compass_enumerate(int32_t n_tables, int32_t n_edges,
+                                 const int32_t *edge_u, const int32_t *edge_v,
+                                 const uint64_t *masks, const double *est,
+                                 int32_t n_masks, const double *card,
+                                 int32_t max_plans, double alpha, double beta,
+                                 int32_t *order_out, double *cost_out,
+                                 int64_t *n_plans_out);
+
 /* Kernel timing for measurement: while enabled, the library records a pair
  * of HIP events on the launch stream around each kernel launch it makes.
  * compass_profile_take(name) waits for the recorded events of kernel `name`

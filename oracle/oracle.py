@@ -519,3 +519,58 @@ def mlp_features(rows, est, n_sel_sub, shape):
     x += ls + [0.0] * (8 - len(ls))
     x += list(shape)
     return np.array(x, dtype=np.float64), float(np.log1p(max(est, 0.0)))
+
+
+# --------------------------------------------------------------------------
+# Plan enumeration (Section 6, Algorithm 1): DFS over the join graph that
+# builds left-deep orders without cross products, sources ordered by
+# f(v) = alpha card(v)/max card + beta deg(v)/max deg, children visited in
+# increasing order of the estimate of the extended sub-plan, pruning when
+# the running cost exceeds the best complete cost, at most max_plans
+# complete plans per source.  cost = sum of the estimates of every prefix
+# (the single table, each intermediate join and the full join).
+# --------------------------------------------------------------------------
+def plan_enumeration(n_tables, edge_u, edge_v, est_of, card, max_plans,
+                     alpha=0.5, beta=0.5):
+    """Returns (best order, best cost, complete plans reached)."""
+    deg = [0] * n_tables
+    adj = [set() for _ in range(n_tables)]
+    for u, v in zip(edge_u, edge_v):
+        deg[u] += 1
+        deg[v] += 1
+        adj[u].add(v)
+        adj[v].add(u)
+    mc = max(card) if max(card) > 0 else 1
+    md = max(deg) if max(deg) > 0 else 1
+    f = [alpha * card[v] / mc + beta * deg[v] / md for v in range(n_tables)]
+    sources = sorted(range(n_tables), key=lambda v: (f[v], v))
+    best = {"cost": float("inf"), "order": None}
+    total = [0]
+
+    class Abort(Exception):
+        pass
+
+    def dfs(order, mask, cost, p):
+        cost = cost + est_of[mask]
+        if cost > best["cost"]:
+            return
+        if len(order) == n_tables:
+            if cost < best["cost"]:
+                best["cost"] = cost
+                best["order"] = list(order)
+            p[0] += 1
+            total[0] += 1
+            if p[0] == max_plans:
+                raise Abort()
+            return
+        cand = sorted({b for a in order for b in adj[a]} - set(order))
+        ext = sorted(cand, key=lambda v: (est_of[mask | (1 << v)], v))
+        for v in ext:
+            dfs(order + [v], mask | (1 << v), cost, p)
+
+    for s in sources:
+        try:
+            dfs([s], 1 << s, 0.0, [0])
+        except Abort:
+            pass
+    return best["order"], best["cost"], total[0]

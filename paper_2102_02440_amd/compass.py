@@ -642,3 +642,32 @@ def features(row_est, est, masks_dev, n_selected, n_tables, shape_dev, stream=No
                                   int(n_tables), shape_dev.data_ptr(), n,
                                   x.data_ptr(), base.data_ptr(), _stream(stream)))
     return x, base
+
+
+def enumerate_plan(n_tables, edge_u, edge_v, masks, est, card, max_plans=10,
+                   alpha=0.5, beta=0.5):
+    """Algorithm 1 join-order search over host estimates; returns (order,
+    cost, complete plans reached)."""
+    L = lib()
+    if not getattr(L, "_enum_bound", False):
+        vp = ctypes.c_void_p
+        L.compass_enumerate.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp,
+                                        ctypes.c_int32, vp, ctypes.c_int32,
+                                        ctypes.c_double, ctypes.c_double, vp, vp, vp]
+        L.compass_enumerate.restype = ctypes.c_int32
+        L._enum_bound = True
+    ne = len(edge_u)
+    eu = np.ascontiguousarray(np.asarray(edge_u, dtype=np.int32))
+    ev = np.ascontiguousarray(np.asarray(edge_v, dtype=np.int32))
+    ms = np.ascontiguousarray(np.asarray(masks, dtype=np.uint64))
+    es = np.ascontiguousarray(np.asarray(est, dtype=np.float64))
+    cd = np.ascontiguousarray(np.asarray(card, dtype=np.float64))
+    order = np.zeros(n_tables, dtype=np.int32)
+    cost = np.zeros(1, dtype=np.float64)
+    npl = np.zeros(1, dtype=np.int64)
+    _check(L.compass_enumerate(int(n_tables), ne, eu.ctypes.data, ev.ctypes.data,
+                               ms.ctypes.data, es.ctypes.data, int(ms.size),
+                               cd.ctypes.data, int(max_plans), float(alpha),
+                               float(beta), order.ctypes.data, cost.ctypes.data,
+                               npl.ctypes.data))
+    return order.tolist(), float(cost[0]), int(npl[0])

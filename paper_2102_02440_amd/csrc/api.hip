@@ -767,10 +767,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_xout = carve(16ull * std::max(1, pl.n_x_slots) * d);
   const size_t np = std::max(1, pl.n_prep_slots);
   const size_t lp = std::max(1, pl.Lprep);
-  const size_t o_pmeta = carve(4ull * np * d * lp);
-  const size_t o_pv = carve(8ull * np * d * lp);
-  const size_t o_pmu = carve(16ull * np * d * lp);
-  const size_t o_pkey = carve(8ull * np * d * lp);
+  const size_t o_prep = carve(sizeof(TriElem) * np * d * lp);
   const size_t o_part = carve(16ull * std::max(1, pl.n_partial_slots) * d);
   void *scratch;
   st = ensure_scratch(ds, off, &scratch);
@@ -798,10 +795,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.msg = reinterpret_cast<u128 *>(base + o_msg);
   B.merged = reinterpret_cast<uint32_t *>(base + o_merged);
   B.xout = reinterpret_cast<u128 *>(base + o_xout);
-  B.prep_meta = reinterpret_cast<uint32_t *>(base + o_pmeta);
-  B.prep_v = reinterpret_cast<int64_t *>(base + o_pv);
-  B.prep_mu = reinterpret_cast<u128 *>(base + o_pmu);
-  B.prep_key = reinterpret_cast<uint64_t *>(base + o_pkey);
+  B.prep = reinterpret_cast<TriElem *>(base + o_prep);
   B.partial = reinterpret_cast<u128 *>(base + o_part);
   B.counter_bits = g->counter_bits;
   B.d = d;

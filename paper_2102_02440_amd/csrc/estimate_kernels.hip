@@ -211,22 +211,24 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
   __syncthreads();
 
   if (T.mode == kModeTriRootPrep) {
-    const size_t base = ((size_t)T.out_slot * B.d + row) * (size_t)B.Lprep;
+    TriElem *out = B.prep + ((size_t)T.out_slot * B.d + row) * (size_t)B.Lprep;
     for (int pos = threadIdx.x; pos < L; pos += kNodeThreads) {
       const uint32_t mt = merged[pos];
       const int a = (int)(mt >> 16);
       const int j = (int)(mt & 0xFFFF);
-      B.prep_meta[base + pos] = mt;
-      B.prep_v[base + pos] = counter_at(B, Tg->child_side[a], row, j);
-      B.prep_mu[base + pos] = msg_of(B, Tg->child_msg[a], row)[j];
-      uint64_t key = 0;
+      TriElem e;
+      e.v = counter_at(B, Tg->child_side[a], row, j);
+      e.mu = msg_of(B, Tg->child_msg[a], row)[j];
+      e.key = 0;
       if (Tg->child_cut[a] >= 0) {
         // kappa of the child's own bucket on the edge to the apex
         const int other = Tg->child_side[a] ^ 1;
-        key = (abs_u64(counter_at(B, other, row, j)) << 7) |
-              (uint64_t)Tg->child_eid[a];
+        e.key = (abs_u64(counter_at(B, other, row, j)) << 7) |
+                (uint64_t)Tg->child_eid[a];
       }
-      B.prep_key[base + pos] = key;
+      e.child = (uint32_t)a;
+      e.pad[0] = e.pad[1] = e.pad[2] = 0;
+      out[pos] = e;
     }
     return;
   }
@@ -333,11 +335,8 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
             (uint64_t)T.cut_eid;
     cval[e] = msg_of(B, T.cut_cmsg[e], row)[Jc];
   }
-  const size_t base = ((size_t)T.prep_slot * B.d + row) * (size_t)B.Lprep;
-  const uint32_t *meta = B.prep_meta + base;
-  const int64_t *pv = B.prep_v + base;
-  const u128 *pmu = B.prep_mu + base;
-  const uint64_t *pkey = B.prep_key + base;
+  const TriElem *el =
+      B.prep + ((size_t)T.prep_slot * B.d + row) * (size_t)B.Lprep;
   const int m = T.m;
   const int cu = T.cut_child[0], cv = T.cut_child[1];
 
@@ -345,18 +344,41 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
 #pragma unroll
   for (int c = 0; c < kMaxChild; ++c) A[c] = 0;
   u128 G = 0;
-  for (int pos = T.L - 1; pos >= 0; --pos) {
-    const int a = (int)(meta[pos] >> 16);
-    const int64_t v = pv[pos];
-    u128 mu = pmu[pos];
-    const uint64_t key = pkey[pos];
-    if (a == cu) mu = key < kf[0] ? mu : cval[0];
-    if (a == cv) mu = key < kf[1] ? mu : cval[1];
-    u128 term = mul_s64_u128(v, mu);
+  // descending kappa: A_c accumulates the elements already passed (larger
+  // kappa), so each element's term sees exactly the A of Section 5.2's
+  // "all other buckets rank above me" condition
+  constexpr int kUnroll = 4;
+  int pos = T.L - 1;
+  for (; pos >= kUnroll - 1; pos -= kUnroll) {
+    TriElem e[kUnroll];
 #pragma unroll
-    for (int c = 0; c < kMaxChild; ++c) {
-      if (c < m && c != a) term = mul_u128(term, A[c]);
+    for (int u = 0; u < kUnroll; ++u) e[u] = el[pos - u];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int a = (int)e[u].child;
+      u128 mu = e[u].mu;
+      if (a == cu) mu = e[u].key < kf[0] ? mu : cval[0];
+      if (a == cv) mu = e[u].key < kf[1] ? mu : cval[1];
+      u128 term = mul_s64_u128(e[u].v, mu);
+#pragma unroll
+      for (int c = 0; c < kMaxChild; ++c)
+        if (c < m && c != a) term = mul_u128(term, A[c]);
+      G += term;
+#pragma unroll
+      for (int c = 0; c < kMaxChild; ++c)
+        if (c == a) A[c] += mu;
     }
+  }
+  for (; pos >= 0; --pos) {
+    const TriElem e = el[pos];
+    const int a = (int)e.child;
+    u128 mu = e.mu;
+    if (a == cu) mu = e.key < kf[0] ? mu : cval[0];
+    if (a == cv) mu = e.key < kf[1] ? mu : cval[1];
+    u128 term = mul_s64_u128(e.v, mu);
+#pragma unroll
+    for (int c = 0; c < kMaxChild; ++c)
+      if (c < m && c != a) term = mul_u128(term, A[c]);
     G += term;
 #pragma unroll
     for (int c = 0; c < kMaxChild; ++c)

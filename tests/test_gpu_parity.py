@@ -334,3 +334,61 @@ def test_wide_sketches_direct_path(oracle, w, bits):
     for k, c in zip(keys, range(2)):
         o = oracle.sketch(k[mask], seeds[c], d, w)
         assert np.array_equal(cnt[c].cpu().numpy().astype(np.int64), o)
+
+
+@gpu
+def test_large_scan_full_size(oracle):
+    """1B-row fact table (6 int64 Zipf(1.1) keys over 50M, 4 range
+    predicates, 1% combined; d=11, w=65536, int64 counters) in the launch
+    configuration the benchmark times.  Exact oracle comparison on a 2M-row
+    slice built alone; on the whole table: the selected count against a
+    torch mask count, linearity across three launches with accumulate,
+    sum of a row == n_sel (mod 2), L1 of a row <= n_sel."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    n = 1_000_000_000
+    _say("large scan", n)
+    cols, preds, seeds = W.large_scan_device(n_rows=n)
+    names = ["i0", "i1", "f0", "f1"]
+    pd = [{"col": names.index(p.col), "kind": p.kind, "lo": p.lo, "hi": p.hi}
+          for p in preds]
+    keys = [cols["key%d" % k] for k in range(6)]
+    d, w = 11, 65536
+    cnt = [torch.zeros((d, w), dtype=torch.int64, device="cuda") for _ in keys]
+    nsel = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pc = [cols[c] for c in names]
+    C.sketch_build(n, pc, pd, keys, list(seeds), cnt, nsel, d, w, counter_bits=64)
+    torch.cuda.synchronize()
+    m = ((cols["i0"] <= 316_227) & (cols["i1"] <= 316_227) &
+         (cols["f0"] >= 0.0) & (cols["f0"] <= 0.316227) &
+         (cols["f1"] >= 0.0) & (cols["f1"] <= 0.316227))
+    ns = int(m.sum().item())
+    del m
+    assert nsel.item() == ns
+    for c in cnt:
+        assert torch.all(c.sum(dim=1) % 2 == ns % 2)
+        assert torch.all(c.abs().sum(dim=1) <= ns)
+    acc = [torch.zeros_like(c) for c in cnt]
+    n2 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cuts = [0, 333_333_331, 700_000_000, n]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        C.sketch_build(b - a, [x[a:b] for x in pc], pd, [k[a:b] for k in keys],
+                       list(seeds), acc, n2, d, w, counter_bits=64, accumulate=True)
+    torch.cuda.synchronize()
+    assert n2.item() == ns
+    for a_, c in zip(acc, cnt):
+        assert torch.equal(a_, c)
+    # exact oracle check of a 2M-row slice
+    a0, b0 = 123_456_789, 125_456_789
+    part = [torch.zeros_like(c) for c in cnt]
+    C.sketch_build(b0 - a0, [x[a0:b0] for x in pc], pd, [k[a0:b0] for k in keys],
+                   list(seeds), part, n2, d, w, counter_bits=64)
+    torch.cuda.synchronize()
+    host = {c: cols[c][a0:b0].cpu().numpy() for c in names}
+    mask = oracle.eval_predicates(host, preds)
+    assert n2.item() == int(mask.sum())
+    for k in range(6):
+        o = oracle.sketch(keys[k][a0:b0].cpu().numpy()[mask], seeds[k], d, w)
+        assert np.array_equal(part[k].cpu().numpy(), o)
+    del cols, keys, pc
+    torch.cuda.empty_cache()
