@@ -38,3 +38,13 @@ def build(verbose: bool = False) -> str:
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
+
+
+def build_microbench() -> str:
+    """Builds the roofline probes (paper_2102_02440_amd/microbench/micro)."""
+    src = os.path.join(PKG, "microbench", "micro.hip")
+    out = os.path.join(PKG, "microbench", "micro")
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
+                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           src, "-o", out])
+    return out

@@ -1,0 +1,134 @@
+// micro.hip -- roofline probes for gfx950: VALU rates of 32-bit ops and
+// v_mad_u64_u32, the sketch hash rate, LDS atomic rate, HBM stream read and
+// global atomic rate.  Every index is bounded by its buffer.
+#include <hip/hip_runtime.h>
+#include <cstdio>
+#include <cstdint>
+#include <vector>
+#include "../csrc/device_math.hpp"
+
+#define CK(x) do { hipError_t e = (x); if (e != hipSuccess) { printf("HIP error %s at %d\n", hipGetErrorString(e), __LINE__); return 1; } } while (0)
+
+__global__ void k_add32(uint32_t* out, int iters) {
+  uint32_t a = threadIdx.x, b = blockIdx.x, c = a ^ 0x1234, d = b + 7;
+  uint32_t e = a + 1, f = b + 2, g = a * 3, h = b * 5;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      a = a + b; c = c ^ d; e = e + f; g = g ^ h;
+      b = b + c; d = d ^ e; f = f + g; h = h ^ a;
+    }
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = a ^ b ^ c ^ d ^ e ^ f ^ g ^ h;
+}
+
+__global__ void k_mad64(uint64_t* out, int iters) {
+  uint64_t a = threadIdx.x, b = blockIdx.x + 1, c = a + 3, d = b + 5;
+  uint32_t x = threadIdx.x * 2654435761u, y = blockIdx.x * 40503u + 1;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      a = (uint64_t)(uint32_t)a * x + (uint32_t)(b >> 13);
+      b = (uint64_t)(uint32_t)b * y + (uint32_t)(c >> 11);
+      c = (uint64_t)(uint32_t)c * x + (uint32_t)(d >> 7);
+      d = (uint64_t)(uint32_t)d * y + (uint32_t)(a >> 5);
+    }
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = a ^ b ^ c ^ d;
+}
+
+__global__ void k_hash(uint32_t* out, int iters, compass::RowSeeds s, compass::BucketMod m) {
+  uint64_t x = (blockIdx.x * blockDim.x + threadIdx.x) & 0x7fffffff;
+  uint32_t acc = 0;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int32_t sg; uint32_t b;
+      compass::hash_xi_h<true>(x + k, s, m, sg, b);
+      acc += b + sg;
+    }
+    x += 7;
+  }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
+__global__ void k_lds_atomic(uint32_t* out, int iters, int w, int hot) {
+  extern __shared__ int32_t c[];
+  for (int i = threadIdx.x; i < w; i += blockDim.x) c[i] = 0;
+  __syncthreads();
+  uint32_t h = (blockIdx.x * blockDim.x + threadIdx.x) * 2654435761u;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      h = h * 1664525u + 1013904223u;
+      uint32_t idx = hot ? ((h >> 28) & 3) : ((h >> 8) & (w - 1));
+      atomicAdd(&c[idx], 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = c[0];
+}
+
+__global__ void k_stream(const uint4* __restrict__ in, size_t n, uint32_t* out) {
+  uint32_t acc = 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    uint4 v = in[i];
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+  if (acc == 0x12345678) out[0] = acc;
+}
+
+__global__ void k_gatomic(int32_t* c, size_t w, int iters) {
+  uint32_t h = (blockIdx.x * blockDim.x + threadIdx.x) * 2654435761u + 17;
+  for (int i = 0; i < iters; ++i) {
+    h = h * 1664525u + 1013904223u;
+    size_t idx = ((size_t)h * 7919u) % w;
+    atomicAdd(&c[idx], 1);
+  }
+}
+
+int main() {
+  hipDeviceProp_t p; CK(hipGetDeviceProperties(&p, 0));
+  printf("device %s CUs %d clock %d kHz l2 %d bytes sharedPerBlock %zu maxSharedPerMP %zu\n", p.name, p.multiProcessorCount, p.clockRate, p.l2CacheSize, p.sharedMemPerBlock, p.maxSharedMemoryPerMultiProcessor);
+  hipEvent_t a, b; CK(hipEventCreate(&a)); CK(hipEventCreate(&b));
+  float ms;
+  const int blocks = 256 * 8, threads = 256;
+  uint64_t* o64; CK(hipMalloc(&o64, (size_t)blocks * threads * 8));
+  uint32_t* o32 = (uint32_t*)o64;
+  int iters = 2000;
+  // add32: 16*8 ops per iter
+  hipLaunchKernelGGL(k_add32, dim3(blocks), dim3(threads), 0, 0, o32, 10); CK(hipDeviceSynchronize());
+  CK(hipEventRecord(a)); hipLaunchKernelGGL(k_add32, dim3(blocks), dim3(threads), 0, 0, o32, iters); CK(hipEventRecord(b)); CK(hipEventSynchronize(b)); CK(hipEventElapsedTime(&ms, a, b));
+  double ops = (double)blocks * threads * iters * 16 * 8;
+  printf("M1a add/xor32: %.1f Gop/s (lane-ops)\n", ops / ms / 1e6);
+  hipLaunchKernelGGL(k_mad64, dim3(blocks), dim3(threads), 0, 0, o64, 10); CK(hipDeviceSynchronize());
+  CK(hipEventRecord(a)); hipLaunchKernelGGL(k_mad64, dim3(blocks), dim3(threads), 0, 0, o64, iters); CK(hipEventRecord(b)); CK(hipEventSynchronize(b)); CK(hipEventElapsedTime(&ms, a, b));
+  ops = (double)blocks * threads * iters * 16 * 4;
+  printf("M1b mad_u64_u32 (+shift): %.1f Gmad/s\n", ops / ms / 1e6);
+  compass::RowSeeds s{123456789ull, 987654321ull, 555555555555ull, 77777777777ull, 31337ull, 2305843009213693000ull};
+  compass::BucketMod m{8192, 8191, 0, 1, 1.0 / 8192};
+  hipLaunchKernelGGL(k_hash, dim3(blocks), dim3(threads), 0, 0, o32, 10, s, m); CK(hipDeviceSynchronize());
+  CK(hipEventRecord(a)); hipLaunchKernelGGL(k_hash, dim3(blocks), dim3(threads), 0, 0, o32, 500, s, m); CK(hipEventRecord(b)); CK(hipEventSynchronize(b)); CK(hipEventElapsedTime(&ms, a, b));
+  ops = (double)blocks * threads * 500 * 4;
+  printf("M1c hash (xi+h, x<2^32): %.1f Ghash/s\n", ops / ms / 1e6);
+  for (int hot = 0; hot < 2; ++hot) {
+    int w = 8192;
+    hipLaunchKernelGGL(k_lds_atomic, dim3(blocks), dim3(threads), w * 4, 0, o32, 10, w, hot); CK(hipDeviceSynchronize());
+    CK(hipEventRecord(a)); hipLaunchKernelGGL(k_lds_atomic, dim3(blocks), dim3(threads), w * 4, 0, o32, 1000, w, hot); CK(hipEventRecord(b)); CK(hipEventSynchronize(b)); CK(hipEventElapsedTime(&ms, a, b));
+    ops = (double)blocks * threads * 1000 * 8;
+    printf("M2 LDS atomic add (%s): %.1f Gatomic/s\n", hot ? "4 hot addresses" : "uniform 8192", ops / ms / 1e6);
+  }
+  size_t bytes = (size_t)4 << 30;
+  uint4* big; CK(hipMalloc(&big, bytes)); CK(hipMemset(big, 1, bytes));
+  size_t n = bytes / 16;
+  for (int rep = 0; rep < 3; ++rep) {
+    CK(hipEventRecord(a)); hipLaunchKernelGGL(k_stream, dim3(256 * 16), dim3(256), 0, 0, big, n, o32); CK(hipEventRecord(b)); CK(hipEventSynchronize(b)); CK(hipEventElapsedTime(&ms, a, b));
+    printf("M3 stream read 4 GiB: %.1f GB/s\n", bytes / ms / 1e6);
+  }
+  int32_t* cnt; size_t w = 35u << 20; CK(hipMalloc(&cnt, w * 4)); CK(hipMemset(cnt, 0, w * 4));
+  CK(hipEventRecord(a)); hipLaunchKernelGGL(k_gatomic, dim3(256 * 16), dim3(256), 0, 0, cnt, w / 4, 1000); CK(hipEventRecord(b)); CK(hipEventSynchronize(b)); CK(hipEventElapsedTime(&ms, a, b));
+  printf("M4 global atomic add (int32, 35 MiB region): %.1f Gatomic/s\n", 256.0 * 16 * 256 * 1000 / ms / 1e6);
+  CK(hipEventRecord(a)); hipLaunchKernelGGL(k_gatomic, dim3(256 * 16), dim3(256), 0, 0, cnt, (size_t)(2u << 20) / 4, 1000); CK(hipEventRecord(b)); CK(hipEventSynchronize(b)); CK(hipEventElapsedTime(&ms, a, b));
+  printf("M4 global atomic add (int32, 2 MiB region): %.1f Gatomic/s\n", 256.0 * 16 * 256 * 1000 / ms / 1e6);
+  return 0;
+}
