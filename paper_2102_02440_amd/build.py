@@ -17,6 +17,7 @@ FLAGS = [
     # no packed-FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    "-Wl,-z,defs",  # every referenced symbol must resolve at link time
 ]
 
 

@@ -26,13 +26,23 @@ namespace compass {
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t st);
 hipError_t launch_scan_sketch(const BuildParams &P, int n_blocks,
                               size_t lds_bytes, hipStream_t st);
-hipError_t launch_scan_direct(const BuildParams &P, const void *seeds,
-                              int n_slices, int d, int n_blocks,
+hipError_t launch_wide_compact(const BuildParams &P, uint64_t *surv,
+                               int64_t cap, void *count, int64_t row_begin,
+                               int64_t row_end, int n_blocks, hipStream_t st);
+hipError_t launch_wide_hash(const uint64_t *surv, int64_t cap,
+                            const void *count, const void *seeds,
+                            const BucketMod &bm, int d, int n_slices,
+                            int ranges, int chunks, int32_t *slab,
+                            hipStream_t st);
+hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
+                              int n_slices, int d, int w,
+                              void *const *counters, int n_sketches,
+                              int counter_bits, int accumulate,
                               hipStream_t st);
 hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
                             const EstBuffers &B, hipStream_t st);
 hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
-                       hipStream_t st);
+                       int stage_bytes, hipStream_t st);
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
                            const EstBuffers &B, hipStream_t st);
 hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
@@ -300,16 +310,20 @@ extern "C" compass_status compass_sketch_build(
   compass_status st = device_state(&ds);
   if (st != COMPASS_OK) return st;
 
+  const bool wide = (size_t)w * 4 > kLdsBudget;
   if (!accumulate) {
     ProfScope ps("fill_zero", stream);
-    for (int s = 0; s < n_sketches; ++s)
-      HIP_OK(launch_fill_zero(sketches[s].counters,
-                              (int64_t)d * w * (counter_bits / 8), stream));
+    // the LDS path's reduction overwrites the counters itself, except
+    // for an empty table, which launches nothing else
+    if (wide || n_rows == 0)
+      for (int s = 0; s < n_sketches; ++s)
+        HIP_OK(launch_fill_zero(sketches[s].counters,
+                                (int64_t)d * w * (counter_bits / 8), stream));
     HIP_OK(launch_fill_zero(n_selected, 8, stream));
   }
   if (n_rows == 0) return COMPASS_OK;
 
-  if ((size_t)w * 4 > kLdsBudget) {
+  if (wide) {
     // rows too wide for LDS-private partials: direct global atomics
     const int S = n_sketches * d;
     std::vector<RowSeeds> sd(S);
@@ -330,22 +344,53 @@ extern "C" compass_status compass_sketch_build(
     }
     st = upload(ds, ds->dseeds, sd.data(), bytes, stream);
     if (st != COMPASS_OK) return st;
-    const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
-    const int64_t blocks = std::min<int64_t>(tiles, 8ll * ds->n_cu);
-    int64_t rpc = (n_rows + blocks - 1) / blocks;
-    rpc = (rpc + kBuildTile - 1) / kBuildTile * kBuildTile;
+    // batches of at most `cap` rows: phase A compacts the survivors' key
+    // field elements (so the buffer can never overflow), phase B hashes
+    // them into LDS counters over a bucket range per block, and the slab
+    // reduction adds the partials into the counters (zeroed above unless
+    // accumulating).
+    const int64_t cap = std::min<int64_t>(n_rows, (int64_t)1 << 25);
+    const int ranges = (int)(((size_t)w * 4 + kLdsBudget - 1) / kLdsBudget);
+    int chunks = std::max(1, (int)((4ll * ds->n_cu + S * ranges - 1) / (S * ranges)));
+    const size_t b_surv = (size_t)n_sketches * cap * 8;
+    const size_t b_slab = ((size_t)chunks * S * w * 4 + 255) & ~(size_t)255;
+    void *scr;
+    st = ensure_scratch(ds, b_surv + b_slab + 256, &scr);
+    if (st != COMPASS_OK) return st;
+    uint64_t *surv = reinterpret_cast<uint64_t *>(scr);
+    int32_t *wslab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(scr) + b_surv);
+    void *count = reinterpret_cast<char *>(scr) + b_surv + b_slab;
     BuildParams P = base;
-    P.rows_per_chunk = rpc;
     P.count_selected = 1;
-    P.n_groups = 1;
+    P.n_groups = n_sketches;
     for (int s = 0; s < n_sketches; ++s) {
       P.keys[s].col = sketches[s].key_col;
       P.keys[s].dtype = sketches[s].key_dtype;
       P.counters[s] = sketches[s].counters;
     }
-    ProfScope ps("scan_direct", stream);
-    HIP_OK(launch_scan_direct(P, ds->dseeds, S, d,
-                              (int)((n_rows + rpc - 1) / rpc), stream));
+    std::vector<void *> cp(n_sketches);
+    for (int s = 0; s < n_sketches; ++s) cp[s] = sketches[s].counters;
+    for (int64_t r0 = 0; r0 < n_rows; r0 += cap) {
+      const int64_t r1 = std::min(n_rows, r0 + cap);
+      const int64_t tiles = (r1 - r0 + kBuildTile - 1) / kBuildTile;
+      HIP_OK(launch_fill_zero(count, 8, stream));
+      {
+        ProfScope ps("wide_compact", stream);
+        HIP_OK(launch_wide_compact(P, surv, cap, count, r0, r1,
+                                   (int)std::min<int64_t>(tiles, 4ll * ds->n_cu),
+                                   stream));
+      }
+      {
+        ProfScope ps("wide_hash", stream);
+        HIP_OK(launch_wide_hash(surv, cap, count, ds->dseeds, base.bm, d, S,
+                                ranges, chunks, wslab, stream));
+      }
+      {
+        ProfScope ps("slab_reduce", stream);
+        HIP_OK(launch_slab_reduce(wslab, chunks, S, d, w, cp.data(), n_sketches,
+                                  counter_bits, 1, stream));
+      }
+    }
     return COMPASS_OK;
   }
 
@@ -370,29 +415,29 @@ extern "C" compass_status compass_sketch_build(
   }
   const int n_groups_total = (S + per_group - 1) / per_group;
 
-  // chunks: a multiple of the resident workgroup slots, so that equal-sized
-  // items fill the chip in whole waves; each chunk still scans at least 16x
-  // as many rows as it merges counters
+  // chunks: about four waves of the resident workgroup slots, so that
+  // equal-sized items fill the chip; at least one tile per chunk.  Each
+  // chunk writes its partial counters to a slab (summed by one reduction
+  // kernel), which is cheap next to the scan: bound the slab to 1 GiB.
   const size_t lds_block = (size_t)per_group * w * 4 + (size_t)kBuildTile * 4;
   const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / lds_block)));
   const int64_t slots = (int64_t)ds->n_cu * per_cu;
   const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
-  const int64_t min_rows = std::max<int64_t>(kBuildTile, 16ll * per_group * w);
-  const int64_t max_chunks = std::max<int64_t>(1, std::min(tiles, n_rows / min_rows));
-  int64_t chunks = 1;
-  for (int64_t waves = 8; waves >= 1; waves /= 2) {
-    const int64_t c = (waves * slots + n_groups_total - 1) / n_groups_total;
-    if (c <= max_chunks) {
-      chunks = c;
-      break;
-    }
-  }
-  if (chunks == 1) chunks = max_chunks;
+  int64_t chunks = std::max<int64_t>(1, (4 * slots + n_groups_total - 1) / n_groups_total);
+  chunks = std::min(chunks, tiles);
+  const size_t slab_row = (size_t)S * w * 4;
+  chunks = std::min<int64_t>(chunks, std::max<size_t>(1, ((size_t)1 << 30) / slab_row));
   int64_t rows_per_chunk = (n_rows + chunks - 1) / chunks;
   rows_per_chunk =
       (rows_per_chunk + kBuildTile - 1) / kBuildTile * kBuildTile;
   chunks = (n_rows + rows_per_chunk - 1) / rows_per_chunk;
   base.rows_per_chunk = rows_per_chunk;
+  void *slab;
+  st = ensure_scratch(ds, (size_t)chunks * slab_row, &slab);
+  if (st != COMPASS_OK) return st;
+  base.slab = reinterpret_cast<int32_t *>(slab);
+  base.d = d;
+  base.n_slices_total = S;
 
   // launches: as many whole groups as the kernel-argument seed table holds
   int slice = 0;
@@ -429,6 +474,13 @@ extern "C" compass_status compass_sketch_build(
       return fail(COMPASS_E_RANGE, "too many workgroups");
     ProfScope ps("scan_sketch", stream);
     HIP_OK(launch_scan_sketch(P, (int)blocks, lds, stream));
+  }
+  {
+    std::vector<void *> cp(n_sketches);
+    for (int s = 0; s < n_sketches; ++s) cp[s] = sketches[s].counters;
+    ProfScope ps("slab_reduce", stream);
+    HIP_OK(launch_slab_reduce(base.slab, chunks, S, d, w, cp.data(), n_sketches,
+                              counter_bits, accumulate, stream));
   }
   return COMPASS_OK;
 }
@@ -656,7 +708,18 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
       for (int c = 0; c < T.m; ++c) {
         if (nd.children[c] == cut_u) tr.cut_child[0] = c;
         if (nd.children[c] == cut_v) tr.cut_child[1] = c;
+        // tables of the child's subtree (bounds for narrow arithmetic)
+        uint64_t sub = 0;
+        std::vector<int> stack{nd.children[c]};
+        while (!stack.empty()) {
+          const int x = stack.back();
+          stack.pop_back();
+          sub |= 1ull << nodes[x].table;
+          for (int y : nodes[x].children) stack.push_back(y);
+        }
+        tr.child_tables[c] = sub;
       }
+      tr.root_table = nd.table;
       const int zb = (pl.w + kLaneThreads - 1) / kLaneThreads;
       tr.partial_slot = pl.n_partial_slots;
       pl.n_partial_slots += zb;
@@ -811,9 +874,19 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const NodeTask *dtasks = reinterpret_cast<const NodeTask *>(base + o_tasks);
   for (size_t lv = 0; lv < levels.size(); ++lv) {
     if (levels[lv].empty()) continue;
+    // LDS for the staged merge: the level's widest node, if it fits
+    int stage = 0;
+    if (g->counter_bits == 32) {
+      for (const NodeTask &t : levels[lv]) {
+        if (t.m == 0) continue;
+        const int nl = t.m + (t.parent_side >= 0) + (t.cut_side >= 0);
+        const int need = nl * w * 4;
+        if (need <= kNodeStageBytes) stage = std::max(stage, need);
+      }
+    }
     ProfScope ps("node", stream);
     HIP_OK(launch_node(dtasks + level_off[lv], (int)levels[lv].size(), B,
-                       stream));
+                       stage, stream));
   }
   if (!pl.tris.empty()) {
     ProfScope ps("tri_lane", stream);

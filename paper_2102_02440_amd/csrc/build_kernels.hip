@@ -70,80 +70,173 @@ __global__ __launch_bounds__(kBuildThreads) void scan_sketch_kernel(
   const int64_t row0 = chunk * P.rows_per_chunk;
   const int64_t row1 = min(row0 + P.rows_per_chunk, P.n_rows);
   const uint64_t sel = scan_rows(job, row0, row1, sb, se, cnt, queue, &s_qn);
-  merge_slices(job, sb, se, cnt);
+  // partial counters of this chunk -> its slab rows (plain coalesced
+  // stores; the reduction kernel sums the chunks in a fixed order)
+  const size_t S = (size_t)P.n_slices_total;
+  for (int l = 0; l < ns; ++l) {
+    const int sl = sb + l;
+    const size_t gs = (size_t)P.slice_sketch[sl] * P.d + P.slice_row[sl];
+    int32_t *dst = P.slab + ((size_t)chunk * S + gs) * w;
+    const int32_t *c = cnt + (size_t)l * w;
+    for (int j = threadIdx.x; j < w; j += kBuildThreads) dst[j] = c[j];
+  }
   if (P.count_selected && gi == 0 && threadIdx.x == 0 && sel)
     atomicAdd(reinterpret_cast<unsigned long long *>(P.n_selected),
               (unsigned long long)sel);
 }
 
-// Sketch rows too wide for LDS (w * 4 > the LDS budget, e.g. w = 65536):
-// the same fused scan + compaction, with every (survivor, slice) hash
-// update going straight to the global counters as one integer atomic.  The
-// counters of such sketches (d x w x 8 bytes, a few MB each) stay resident in
-// the L2 / Infinity Cache, and at the selective predicates this is meant
-// for, HBM traffic is the predicate columns.  Work of a tile is flattened
-// to (survivor, slice) tasks so that a handful of survivors still keeps
-// every lane busy; the slice seeds are staged in LDS.
+// Sketch rows too wide for LDS-private partials (w * 4 > the LDS budget,
+// e.g. w = 65536): two phases per batch of rows, no global atomic per
+// update (device-scope atomics run two orders of magnitude below LDS ones).
 struct DirectJob {
   const BuildParams &P;
   __device__ int n_preds() const { return P.n_preds; }
   __device__ const PredDev &pred(int q) const { return P.preds[q]; }
 };
 
-__global__ __launch_bounds__(kBuildThreads) void scan_direct_kernel(
-    const BuildParams P, const RowSeeds *__restrict__ seeds, int32_t n_slices,
-    int32_t d) {
-  extern __shared__ int32_t lds[];
+// Wide sketches, phase A: the fused scan compacts the qualifying rows of
+// [row_begin, row_end) and appends their key field elements, per sketch, to
+// surv[s * cap + ...] (one global atomic per tile reserves the space).
+__global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
+    const BuildParams P, uint64_t *__restrict__ surv, int64_t cap,
+    unsigned long long *__restrict__ count, int64_t row_begin,
+    int64_t row_end) {
+  __shared__ int32_t queue[kBuildTile];
   __shared__ int32_t s_qn;
-  RowSeeds *sd = reinterpret_cast<RowSeeds *>(lds);
-  int32_t *queue = lds + (n_slices * sizeof(RowSeeds) + 3) / 4;
-  for (int i = threadIdx.x; i < n_slices; i += kBuildThreads) sd[i] = seeds[i];
-  __syncthreads();
+  __shared__ unsigned long long s_off;
   const DirectJob job{P};
-  const int64_t row0 = (int64_t)blockIdx.x * P.rows_per_chunk;
-  const int64_t row1 = min(row0 + P.rows_per_chunk, P.n_rows);
   uint64_t sel = 0;
-  const int w = (int)P.bm.w;
-  for (int64_t base = row0; base < row1; base += kBuildTile) {
-    const int nt = (int)min((int64_t)kBuildTile, row1 - base);
+  for (int64_t base = row_begin + (int64_t)blockIdx.x * kBuildTile;
+       base < row_end; base += (int64_t)gridDim.x * kBuildTile) {
+    const int nt = (int)min((int64_t)kBuildTile, row_end - base);
     const int qn = compact_tile<DirectJob, kBuildRowsPerThread>(
         job, base, nt, P.n_preds, queue, &s_qn);
+    if (threadIdx.x == 0) s_off = qn ? atomicAdd(count, (unsigned long long)qn) : 0;
+    __syncthreads();
+    const int64_t off = (int64_t)s_off;
     sel += (uint64_t)qn;
-    const int tasks = qn * n_slices;
-    for (int t = threadIdx.x; t < tasks; t += kBuildThreads) {
-      const int q = t / n_slices;
-      const int sl = t - q * n_slices;
-      const int s = sl / d, i = sl - s * d;
-      const int64_t row = base + (P.n_preds ? queue[q] : q);
-      const uint64_t x = load_field(P.keys[s], row);
-      int32_t sign;
-      uint32_t b;
-      if ((x >> 32) == 0)
-        hash_xi_h<true>(x, sd[sl], P.bm, sign, b);
-      else
-        hash_xi_h<false>(x, sd[sl], P.bm, sign, b);
-      const size_t idx = (size_t)i * w + b;
-      if (P.counter_bits == 32)
-        atomicAdd(reinterpret_cast<int32_t *>(P.counters[s]) + idx, sign);
-      else
-        atomicAdd(reinterpret_cast<unsigned long long *>(P.counters[s]) + idx,
-                  (unsigned long long)(int64_t)sign);
+    for (int s = 0; s < P.n_groups; ++s) {  // n_groups = sketches here
+      const KeyDev kd = P.keys[s];
+      for (int q = threadIdx.x; q < qn; q += kBuildThreads) {
+        const int64_t row = base + (P.n_preds ? queue[q] : q);
+        surv[(int64_t)s * cap + off + q] = load_field(kd, row);
+      }
     }
-    __syncthreads();  // queue and s_qn are reused by the next tile
+    __syncthreads();  // queue, s_qn and s_off are reused by the next tile
   }
   if (P.count_selected && threadIdx.x == 0 && sel)
     atomicAdd(reinterpret_cast<unsigned long long *>(P.n_selected),
               (unsigned long long)sel);
 }
 
-hipError_t launch_scan_direct(const BuildParams &P, const void *seeds,
-                              int n_slices, int d, int n_blocks,
+// Wide sketches, phase B: block (slice, bucket range, chunk) hashes its
+// chunk of the compacted survivors of the slice's sketch and keeps the
+// buckets of its range in LDS, then writes them to its slab row.  Every
+// range block recomputes the hashes (the price of a range that fits LDS).
+__global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
+    const uint64_t *__restrict__ surv, int64_t cap,
+    const unsigned long long *__restrict__ count,
+    const RowSeeds *__restrict__ seeds, BucketMod bm, int32_t d,
+    int32_t n_slices, int32_t ranges, int32_t chunks,
+    int32_t *__restrict__ slab) {
+  extern __shared__ int32_t cnt[];
+  const int sl = blockIdx.x % n_slices;
+  const int r = (blockIdx.x / n_slices) % ranges;
+  const int k = blockIdx.x / (n_slices * ranges);
+  const int w = (int)bm.w;
+  const int wr = (w + ranges - 1) / ranges;
+  const int lo = r * wr, hi = min(w, lo + wr);
+  for (int j = threadIdx.x; j < hi - lo; j += kBuildThreads) cnt[j] = 0;
+  __syncthreads();
+  const int64_t n = (int64_t)*count;
+  const int64_t a = n * k / chunks, b = n * (k + 1) / chunks;
+  const int s = sl / d;
+  const RowSeeds sd = seeds[sl];
+  const uint64_t *x = surv + (int64_t)s * cap;
+  for (int64_t i = a + threadIdx.x; i < b; i += kBuildThreads) {
+    const uint64_t xi = x[i];
+    int32_t sign;
+    uint32_t bk;
+    if ((xi >> 32) == 0)
+      hash_xi_h<true>(xi, sd, bm, sign, bk);
+    else
+      hash_xi_h<false>(xi, sd, bm, sign, bk);
+    if ((int)bk >= lo && (int)bk < hi) atomicAdd(&cnt[bk - lo], sign);
+  }
+  __syncthreads();
+  int32_t *dst = slab + ((int64_t)k * n_slices + sl) * w + lo;
+  for (int j = threadIdx.x; j < hi - lo; j += kBuildThreads) dst[j] = cnt[j];
+}
+
+hipError_t launch_wide_compact(const BuildParams &P, uint64_t *surv,
+                               int64_t cap, void *count, int64_t row_begin,
+                               int64_t row_end, int n_blocks, hipStream_t st) {
+  hipLaunchKernelGGL(wide_compact_kernel, dim3(n_blocks), dim3(kBuildThreads),
+                     0, st, P, surv, cap,
+                     reinterpret_cast<unsigned long long *>(count), row_begin,
+                     row_end);
+  return hipGetLastError();
+}
+
+hipError_t launch_wide_hash(const uint64_t *surv, int64_t cap,
+                            const void *count, const void *seeds,
+                            const BucketMod &bm, int d, int n_slices,
+                            int ranges, int chunks, int32_t *slab,
+                            hipStream_t st) {
+  const int w = (int)bm.w;
+  const size_t lds = (size_t)((w + ranges - 1) / ranges) * 4;
+  hipLaunchKernelGGL(wide_hash_kernel, dim3(n_slices * ranges * chunks),
+                     dim3(kBuildThreads), lds, st, surv, cap,
+                     reinterpret_cast<const unsigned long long *>(count),
+                     reinterpret_cast<const RowSeeds *>(seeds), bm, d,
+                     n_slices, ranges, chunks, slab);
+  return hipGetLastError();
+}
+
+// counters[s][row][j] = (accumulate ? counters : 0) + sum over chunks of
+// slab[chunk][s * d + row][j]: one thread per counter, chunks summed in
+// order (integer sums: exact and order-independent anyway).
+struct CounterList {
+  void *p[kMaxSketches];
+};
+
+__global__ void slab_reduce_kernel(const int32_t *__restrict__ slab,
+                                   int64_t chunks, int32_t n_slices, int32_t d,
+                                   int32_t w, CounterList cl,
+                                   int32_t counter_bits, int32_t accumulate) {
+  const int64_t total = (int64_t)n_slices * w;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t acc = 0;
+    for (int64_t c = 0; c < chunks; ++c) acc += slab[c * total + k];
+    const int gs = (int)(k / w);
+    const int j = (int)(k - (int64_t)gs * w);
+    const int s = gs / d, row = gs - s * d;
+    const size_t idx = (size_t)row * w + j;
+    if (counter_bits == 32) {
+      int32_t *g = reinterpret_cast<int32_t *>(cl.p[s]);
+      g[idx] = (accumulate ? g[idx] : 0) + (int32_t)acc;
+    } else {
+      int64_t *g = reinterpret_cast<int64_t *>(cl.p[s]);
+      g[idx] = (accumulate ? g[idx] : 0) + acc;
+    }
+  }
+}
+
+hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
+                              int n_slices, int d, int w,
+                              void *const *counters, int n_sketches,
+                              int counter_bits, int accumulate,
                               hipStream_t st) {
-  const size_t lds = ((size_t)n_slices * sizeof(RowSeeds) + 3) / 4 * 4 +
-                     (size_t)kBuildTile * 4;
-  hipLaunchKernelGGL(scan_direct_kernel, dim3((unsigned)n_blocks),
-                     dim3(kBuildThreads), lds, st, P,
-                     reinterpret_cast<const RowSeeds *>(seeds), n_slices, d);
+  CounterList cl;
+  for (int s = 0; s < kMaxSketches; ++s)
+    cl.p[s] = s < n_sketches ? counters[s] : nullptr;
+  const int64_t total = (int64_t)n_slices * w;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(slab_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                     st, slab, chunks, n_slices, d, w, cl, counter_bits,
+                     accumulate);
   return hipGetLastError();
 }
 

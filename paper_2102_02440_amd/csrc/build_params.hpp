@@ -48,6 +48,9 @@ struct BuildParams {
   int32_t counter_bits;
   int32_t count_selected;
   int64_t *n_selected;
+  int32_t *slab;        // [chunk][sketch * d + row][w] partial counters
+  int32_t d;
+  int32_t n_slices_total;  // n_sketches * d of the call (slab row count)
   BucketMod bm;
   PredDev preds[kMaxPreds];
   KeyDev keys[kMaxSketches];

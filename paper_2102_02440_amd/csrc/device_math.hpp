@@ -144,6 +144,24 @@ __device__ __forceinline__ u128 mul_u128(u128 a, u128 b) {
   return r + ((u128)cross << 64);
 }
 
+// signed 64 x signed 64 -> exact signed 128-bit product
+__device__ __forceinline__ u128 mul_s64_s64(int64_t a, int64_t b) {
+  const u128 r = mul_u64_full((uint64_t)a, (uint64_t)b);
+  uint64_t hi = (uint64_t)(r >> 64);
+  if (a < 0) hi -= (uint64_t)b;
+  if (b < 0) hi -= (uint64_t)a;
+  return ((u128)hi << 64) | (uint64_t)r;
+}
+
+// 128-bit value times signed 64-bit value (sign-extended), mod 2^128
+__device__ __forceinline__ u128 mul_u128_s64(u128 t, int64_t b) {
+  const uint64_t tl = (uint64_t)t, th = (uint64_t)(t >> 64);
+  const u128 r = mul_u64_full(tl, (uint64_t)b);
+  uint64_t hi = (uint64_t)(r >> 64) + th * (uint64_t)b;
+  if (b < 0) hi -= tl;
+  return ((u128)hi << 64) | (uint64_t)r;
+}
+
 // signed 64-bit value times 128-bit value, mod 2^128
 __device__ __forceinline__ u128 mul_s64_u128(int64_t a, u128 b) {
   return mul_u128(s64_to_u128(a), b);

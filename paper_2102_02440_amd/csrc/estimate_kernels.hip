@@ -164,7 +164,7 @@ __device__ __forceinline__ ListRef list_of(const NodeTask *T, int a) {
 }
 
 __global__ __launch_bounds__(kNodeThreads) void node_kernel(
-    const NodeTask *tasks, EstBuffers B) {
+    const NodeTask *tasks, EstBuffers B, int32_t stage_bytes) {
   __shared__ u128 sh[kNodeThreads];
   const NodeTask *Tg = tasks + blockIdx.x;
   const NodeTask T = *Tg;
@@ -191,7 +191,20 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
       B.merged + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
 
   // 1. k-way merge by rank: position = own index + elements of smaller
-  //    kappa in every other list (ties in |v| go to the lower edge id)
+  //    kappa in every other list (ties in |v| go to the lower edge id).
+  //    With int32 counters every |v| < 2^32: the lists' sorted magnitudes
+  //    are staged in LDS as 32-bit values and the rank searches run there.
+  extern __shared__ uint32_t mags[];  // nl * w when staged
+  const bool staged = B.counter_bits == 32 &&
+                      (size_t)nl * w * 4 <= (size_t)stage_bytes;
+  if (staged) {
+    for (int e = threadIdx.x; e < L; e += kNodeThreads) {
+      const int a = e / w;
+      const int k = e - a * w;
+      mags[e] = (uint32_t)(sorted_of(B, list_of(Tg, a).side, row)[k] >> 16);
+    }
+    __syncthreads();
+  }
   for (int e = threadIdx.x; e < L; e += kNodeThreads) {
     const int a = e / w;
     const int k = e - a * w;
@@ -203,8 +216,18 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
     for (int b = 0; b < nl; ++b) {
       if (b == a) continue;
       const ListRef lb = list_of(Tg, b);
-      const uint64_t thr = (absv + (lb.eid < la.eid ? 1 : 0)) << 16;
-      pos += lower_bound_u64(sorted_of(B, lb.side, row), w, thr);
+      const uint64_t t = absv + (lb.eid < la.eid ? 1 : 0);  // count |v_b| < t
+      if (staged) {
+        const uint32_t *m = mags + (size_t)b * w;
+        int lo = 0, hi = w;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if ((uint64_t)m[mid] < t) lo = mid + 1; else hi = mid;
+        }
+        pos += lo;
+      } else {
+        pos += lower_bound_u64(sorted_of(B, lb.side, row), w, t << 16);
+      }
     }
     merged[pos] = ((uint32_t)a << 16) | j;
   }
@@ -340,26 +363,101 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
   const int m = T.m;
   const int cu = T.cut_child[0], cv = T.cut_child[1];
 
-  u128 A[kMaxChild];
-#pragma unroll
-  for (int c = 0; c < kMaxChild; ++c) A[c] = 0;
+  // Narrow arithmetic when it is exact: every message value of child c is
+  // bounded by B_c = prod of n_sel over c's subtree (the L1 norm of a
+  // sketch row is at most n_sel), each A_c by (w + 1) B_c, and the apex's
+  // counters by n_sel(apex).  When all of these stay below 2^62, messages
+  // and A are int64 and only the running sum G needs 128 bits.
+  bool narrow = true;
+  {
+    const u128 lim = (u128)1 << 62;
+    const u128 nroot = (u128)(B.n_sel[T.root_table] < 0 ? 0 : B.n_sel[T.root_table]);
+    for (int c = 0; c < m && narrow; ++c) {
+      u128 bc = 1;
+      for (int t = 0; t < 64; ++t) {
+        if (!((T.child_tables[c] >> t) & 1ull)) continue;
+        const int64_t ns = B.n_sel[t];
+        const u128 f = (u128)(ns < 0 ? 0 : ns);
+        if (f != 0 && bc > lim / f) {
+          narrow = false;
+          break;
+        }
+        bc *= f;
+      }
+      if (!narrow) break;
+      if (bc != 0 && ((u128)(B.w + 1) > lim / bc || nroot > lim / bc)) narrow = false;
+    }
+  }
   u128 G = 0;
-  // descending kappa: A_c accumulates the elements already passed (larger
-  // kappa), so each element's term sees exactly the A of Section 5.2's
-  // "all other buckets rank above me" condition
   constexpr int kUnroll = 4;
-  int pos = T.L - 1;
-  for (; pos >= kUnroll - 1; pos -= kUnroll) {
-    TriElem e[kUnroll];
+  if (narrow) {
+    int64_t A[kMaxChild];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) e[u] = el[pos - u];
+    for (int c = 0; c < kMaxChild; ++c) A[c] = 0;
+    const int64_t c0 = (int64_t)(uint64_t)cval[0], c1 = (int64_t)(uint64_t)cval[1];
+    int pos = T.L - 1;
+    for (; pos >= 0; pos -= kUnroll) {
+      TriElem e[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int a = (int)e[u].child;
-      u128 mu = e[u].mu;
-      if (a == cu) mu = e[u].key < kf[0] ? mu : cval[0];
-      if (a == cv) mu = e[u].key < kf[1] ? mu : cval[1];
-      u128 term = mul_s64_u128(e[u].v, mu);
+      for (int u = 0; u < kUnroll; ++u) e[u] = el[max(pos - u, 0)];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (pos - u < 0) break;
+        const int a = (int)e[u].child;
+        int64_t mu = (int64_t)(uint64_t)e[u].mu;
+        if (a == cu) mu = e[u].key < kf[0] ? mu : c0;
+        if (a == cv) mu = e[u].key < kf[1] ? mu : c1;
+        const int64_t vm = e[u].v * mu;
+        u128 term = 0;
+        bool first = true;
+#pragma unroll
+        for (int c = 0; c < kMaxChild; ++c) {
+          if (c < m && c != a) {
+            term = first ? mul_s64_s64(vm, A[c]) : mul_u128_s64(term, A[c]);
+            first = false;
+          }
+        }
+        if (first) term = s64_to_u128(vm);
+        G += term;
+#pragma unroll
+        for (int c = 0; c < kMaxChild; ++c)
+          if (c == a) A[c] += mu;
+      }
+    }
+  } else {
+    u128 A[kMaxChild];
+#pragma unroll
+    for (int c = 0; c < kMaxChild; ++c) A[c] = 0;
+    // descending kappa: A_c accumulates the elements already passed (larger
+    // kappa), i.e. exactly the elements a term's bucket must rank below
+    int pos = T.L - 1;
+    for (; pos >= kUnroll - 1; pos -= kUnroll) {
+      TriElem e[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) e[u] = el[pos - u];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int a = (int)e[u].child;
+        u128 mu = e[u].mu;
+        if (a == cu) mu = e[u].key < kf[0] ? mu : cval[0];
+        if (a == cv) mu = e[u].key < kf[1] ? mu : cval[1];
+        u128 term = mul_s64_u128(e[u].v, mu);
+#pragma unroll
+        for (int c = 0; c < kMaxChild; ++c)
+          if (c < m && c != a) term = mul_u128(term, A[c]);
+        G += term;
+#pragma unroll
+        for (int c = 0; c < kMaxChild; ++c)
+          if (c == a) A[c] += mu;
+      }
+    }
+    for (; pos >= 0; --pos) {
+      const TriElem e = el[pos];
+      const int a = (int)e.child;
+      u128 mu = e.mu;
+      if (a == cu) mu = e.key < kf[0] ? mu : cval[0];
+      if (a == cv) mu = e.key < kf[1] ? mu : cval[1];
+      u128 term = mul_s64_u128(e.v, mu);
 #pragma unroll
       for (int c = 0; c < kMaxChild; ++c)
         if (c < m && c != a) term = mul_u128(term, A[c]);
@@ -368,21 +466,6 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
       for (int c = 0; c < kMaxChild; ++c)
         if (c == a) A[c] += mu;
     }
-  }
-  for (; pos >= 0; --pos) {
-    const TriElem e = el[pos];
-    const int a = (int)e.child;
-    u128 mu = e.mu;
-    if (a == cu) mu = e.key < kf[0] ? mu : cval[0];
-    if (a == cv) mu = e.key < kf[1] ? mu : cval[1];
-    u128 term = mul_s64_u128(e.v, mu);
-#pragma unroll
-    for (int c = 0; c < kMaxChild; ++c)
-      if (c < m && c != a) term = mul_u128(term, A[c]);
-    G += term;
-#pragma unroll
-    for (int c = 0; c < kMaxChild; ++c)
-      if (c == a) A[c] += mu;
   }
   red[threadIdx.x] = active ? G : (u128)0;
   __syncthreads();
@@ -477,9 +560,9 @@ hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
 }
 
 hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(node_kernel, dim3(n, B.d), dim3(kNodeThreads), 0, st,
-                     tasks, B);
+                       int stage_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(node_kernel, dim3(n, B.d), dim3(kNodeThreads),
+                     (size_t)stage_bytes, st, tasks, B, stage_bytes);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@ constexpr int kNodeThreads = 256;
 constexpr int kSortThreads = 1024;
 constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
+constexpr int kNodeStageBytes = 96 * 1024;  // node merge: staged magnitudes
 
 enum { kModeMessage = 0, kModeTreeRoot = 1, kModeTriRootPrep = 2 };
 enum { kSpSingle = 0, kSpTree = 1, kSpTriangle = 2, kSpUnsupported = 3 };
@@ -46,6 +47,8 @@ struct TriTask {
   int32_t cut_cmsg[2];      // cut-constant slots of u and v
   int32_t cut_child[2];     // root child slots of u and v
   int32_t partial_slot;     // first of gridDim.z partial sums
+  int32_t root_table;
+  uint64_t child_tables[kMaxChild];  // tables of each child's subtree
 };
 
 struct SubplanTask {

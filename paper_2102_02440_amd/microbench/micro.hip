@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <cstdint>
+#include <string>
 #include <vector>
 #include "../csrc/device_math.hpp"
 
@@ -87,7 +88,30 @@ __global__ void k_gatomic(int32_t* c, size_t w, int iters) {
   }
 }
 
-int main() {
+__global__ void k_copy(const uint4 *__restrict__ in, uint4 *__restrict__ out,
+                       size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = in[i];
+}
+
+// `micro copy`: one plain copy of exactly 1 GiB (read 1 GiB, write 1 GiB),
+// the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters.
+static int copy_probe() {
+  const size_t bytes = (size_t)1 << 30, n = bytes / 16;
+  uint4 *a, *b;
+  CK(hipMalloc(&a, bytes));
+  CK(hipMalloc(&b, bytes));
+  CK(hipMemset(a, 1, bytes));
+  CK(hipDeviceSynchronize());
+  hipLaunchKernelGGL(k_copy, dim3(256 * 16), dim3(256), 0, 0, a, b, n);
+  CK(hipDeviceSynchronize());
+  printf("copied %zu bytes\n", bytes);
+  return 0;
+}
+
+int main(int argc, char **argv) {
+  if (argc > 1 && std::string(argv[1]) == "copy") return copy_probe();
   hipDeviceProp_t p; CK(hipGetDeviceProperties(&p, 0));
   printf("device %s CUs %d clock %d kHz l2 %d bytes sharedPerBlock %zu maxSharedPerMP %zu\n", p.name, p.multiProcessorCount, p.clockRate, p.l2CacheSize, p.sharedMemPerBlock, p.maxSharedMemoryPerMultiProcessor);
   hipEvent_t a, b; CK(hipEventCreate(&a)); CK(hipEventCreate(&b));

@@ -307,8 +307,10 @@ def test_job6a_full_size(oracle):
 @gpu
 @pytest.mark.parametrize("w,bits", [(65536, 64), (40000, 32), (1 << 20, 64)])
 def test_wide_sketches_direct_path(oracle, w, bits):
-    """Rows too wide for LDS partials (w * 4 > 128 KiB) take the direct
-    global-atomic kernel: same counters as the oracle, int32 and int64."""
+    """Rows too wide for LDS partials (w * 4 > 128 KiB) take the two-phase
+    path (survivor compaction, bucket-range LDS hashing, slab reduction):
+    same counters as the oracle, int32 and int64, pre-filled counters
+    overwritten."""
     torch = _torch()
     from paper_2102_02440_amd import compass as C
     rng = np.random.default_rng(w)
