@@ -64,6 +64,40 @@ def algorithmic_work(q, n_sel):
     return total_bytes, updates
 
 
+SCAN_SOURCES = ["scan_common.hpp", "build_kernels.hip", "build_params.hpp",
+                "device_math.hpp"]
+
+
+def source_hash(names):
+    """sha256 over the given kernel sources (identifies the kernel build)."""
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2102_02440_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(profile, names):
+    """HBM bytes per step of the dominant kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy kernel),
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != source_hash(names):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_step"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(q, sample_rows):
     """The oracle, as it stands, on a bounded sample of the same workload:
     every table but cast_info in full plus the first `sample_rows` rows of
@@ -353,7 +387,9 @@ def run_job6a(args):
     upd_rate = updates / scan_s_step
     roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved_gbs / HBM_PEAK_GBS,
-                "traffic": None, "kernel": "scan_sketch",
+                "traffic": measured_traffic("scan_sketch_traffic_job6a.md",
+                                            SCAN_SOURCES),
+                "kernel": "scan_sketch",
                 "launches_per_step": scan_n / args.steps,
                 "alg_bytes_per_step": alg_bytes,
                 "hash_updates_per_step": updates,

@@ -415,15 +415,16 @@ extern "C" compass_status compass_sketch_build(
   }
   const int n_groups_total = (S + per_group - 1) / per_group;
 
-  // chunks: about four waves of the resident workgroup slots, so that
-  // equal-sized items fill the chip; at least one tile per chunk.  Each
+  // chunks: about eight waves of the resident workgroup slots, so that
+  // equal-sized items fill the chip with a short tail; at least one tile
+  // per chunk.  Each
   // chunk writes its partial counters to a slab (summed by one reduction
   // kernel), which is cheap next to the scan: bound the slab to 1 GiB.
   const size_t lds_block = (size_t)per_group * w * 4 + (size_t)kBuildTile * 4;
   const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / lds_block)));
   const int64_t slots = (int64_t)ds->n_cu * per_cu;
   const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
-  int64_t chunks = std::max<int64_t>(1, (4 * slots + n_groups_total - 1) / n_groups_total);
+  int64_t chunks = std::max<int64_t>(1, (8 * slots + n_groups_total - 1) / n_groups_total);
   chunks = std::min(chunks, tiles);
   const size_t slab_row = (size_t)S * w * 4;
   chunks = std::min<int64_t>(chunks, std::max<size_t>(1, ((size_t)1 << 30) / slab_row));

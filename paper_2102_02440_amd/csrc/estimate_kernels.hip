@@ -344,7 +344,10 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
 __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
     const TriTask *tasks, EstBuffers B) {
   __shared__ u128 red[kLaneThreads];
-  const TriTask T = tasks[blockIdx.x];
+  // the task is the same for every lane: read it through the constant
+  // address space so its fields live in scalar registers
+  typedef const __attribute__((address_space(4))) TriTask ConstTask;
+  ConstTask &T = *((ConstTask *)tasks + blockIdx.x);
   const int row = blockIdx.y;
   const int J = blockIdx.z * kLaneThreads + threadIdx.x;
   const bool active = J < B.w;
@@ -358,8 +361,12 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
             (uint64_t)T.cut_eid;
     cval[e] = msg_of(B, T.cut_cmsg[e], row)[Jc];
   }
-  const TriElem *el =
-      B.prep + ((size_t)T.prep_slot * B.d + row) * (size_t)B.Lprep;
+  // read-only during this kernel and the same for every lane: read through
+  // the constant address space so the loads are scalar (s_load) and the
+  // child index is a scalar, making the per-child branches uniform
+  typedef const __attribute__((address_space(4))) TriElem ConstElem;
+  ConstElem *el = (ConstElem *)(B.prep + ((size_t)T.prep_slot * B.d + row) *
+                                             (size_t)B.Lprep);
   const int m = T.m;
   const int cu = T.cut_child[0], cv = T.cut_child[1];
 
@@ -399,7 +406,13 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
     for (; pos >= 0; pos -= kUnroll) {
       TriElem e[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) e[u] = el[max(pos - u, 0)];
+      for (int u = 0; u < kUnroll; ++u) {
+        ConstElem &r = el[max(pos - u, 0)];
+        e[u].v = r.v;
+        e[u].key = r.key;
+        e[u].mu = r.mu;
+        e[u].child = r.child;
+      }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         if (pos - u < 0) break;
@@ -434,7 +447,13 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
     for (; pos >= kUnroll - 1; pos -= kUnroll) {
       TriElem e[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) e[u] = el[pos - u];
+      for (int u = 0; u < kUnroll; ++u) {
+        ConstElem &r = el[pos - u];
+        e[u].v = r.v;
+        e[u].key = r.key;
+        e[u].mu = r.mu;
+        e[u].child = r.child;
+      }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int a = (int)e[u].child;
@@ -452,7 +471,11 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
       }
     }
     for (; pos >= 0; --pos) {
-      const TriElem e = el[pos];
+      TriElem e;
+      e.v = el[pos].v;
+      e.key = el[pos].key;
+      e.mu = el[pos].mu;
+      e.child = el[pos].child;
       const int a = (int)e.child;
       u128 mu = e.mu;
       if (a == cu) mu = e.key < kf[0] ? mu : cval[0];

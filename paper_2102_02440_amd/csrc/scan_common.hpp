@@ -26,6 +26,16 @@ __device__ __forceinline__ bool eval_pred(const PredDev &p, int64_t row) {
   return (word >> (v & 63)) & 1ull;
 }
 
+// raw key as int64 (int32 keys sign-extended)
+__device__ __forceinline__ int64_t load_raw_key(const KeyDev &k, int64_t row) {
+  if (k.dtype == kDtI32) return reinterpret_cast<const int32_t *>(k.col)[row];
+  return reinterpret_cast<const int64_t *>(k.col)[row];
+}
+
+__device__ __forceinline__ uint64_t field_of_raw(int64_t v) {
+  return (v >= 0 && (uint64_t)v < kP61) ? (uint64_t)v : key_field(v);
+}
+
 __device__ __forceinline__ uint64_t load_field(const KeyDev &k, int64_t row) {
   if (k.dtype == kDtI32) {
     const int32_t v = reinterpret_cast<const int32_t *>(k.col)[row];
@@ -86,6 +96,12 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
   const int n_preds = job.n_preds();
   const bool dense = (n_preds == 0);
   uint64_t sel = 0;
+  // Dense tables: the keys of the group's first sketch for the next tile
+  // are loaded while the current tile is hashed (software prefetch).
+  const int s_first = job.slice_sketch(sb);
+  const KeyDev kd_first = job.key(s_first);
+  int64_t pre[kRowsPerThread];
+  bool have_pre = false;
   for (int64_t base = row0; base < row1; base += kTile) {
     const int nt = (int)min((int64_t)kTile, row1 - base);
     const int qn = compact_tile<J, kRowsPerThread>(job, base, nt, n_preds,
@@ -103,6 +119,22 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
     }
     uint64_t x[kRowsPerThread];
     int cur_sketch = -1;
+    if (dense) {
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        if (!have_pre) pre[k] = valid[k] ? load_raw_key(kd_first, base + ridx[k]) : 0;
+        x[k] = field_of_raw(pre[k]);
+      }
+      cur_sketch = s_first;
+      const int64_t nb = base + kTile;
+      const int nt2 = (int)max((int64_t)0, min((int64_t)kTile, row1 - nb));
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        const int q = threadIdx.x + k * kBuildThreads;
+        pre[k] = q < nt2 ? load_raw_key(kd_first, nb + q) : 0;
+      }
+      have_pre = true;
+    }
     for (int sl = sb; sl < se; ++sl) {
       const int s = job.slice_sketch(sl);
       if (s != cur_sketch) {
