@@ -707,8 +707,14 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
       tr.cut_cmsg[0] = cmsg_slot[cut_u];
       tr.cut_cmsg[1] = cmsg_slot[cut_v];
       for (int c = 0; c < T.m; ++c) {
-        if (nd.children[c] == cut_u) tr.cut_child[0] = c;
-        if (nd.children[c] == cut_v) tr.cut_child[1] = c;
+        if (nd.children[c] == cut_u) {
+          tr.cut_child[0] = c;
+          tr.cut_peid[0] = nd.child_edges[c];
+        }
+        if (nd.children[c] == cut_v) {
+          tr.cut_child[1] = c;
+          tr.cut_peid[1] = nd.child_edges[c];
+        }
         // tables of the child's subtree (bounds for narrow arithmetic)
         uint64_t sub = 0;
         std::vector<int> stack{nd.children[c]};
@@ -832,6 +838,8 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t np = std::max(1, pl.n_prep_slots);
   const size_t lp = std::max(1, pl.Lprep);
   const size_t o_prep = carve(sizeof(TriElem) * np * d * lp);
+  const size_t o_prepn = carve(sizeof(TriElemN) * np * d * lp);
+  const size_t o_prepz = carve(sizeof(int32_t) * np * d);
   const size_t o_part = carve(16ull * std::max(1, pl.n_partial_slots) * d);
   void *scratch;
   st = ensure_scratch(ds, off, &scratch);
@@ -860,6 +868,8 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.merged = reinterpret_cast<uint32_t *>(base + o_merged);
   B.xout = reinterpret_cast<u128 *>(base + o_xout);
   B.prep = reinterpret_cast<TriElem *>(base + o_prep);
+  B.prepn = reinterpret_cast<TriElemN *>(base + o_prepn);
+  B.prep_z = reinterpret_cast<int32_t *>(base + o_prepz);
   B.partial = reinterpret_cast<u128 *>(base + o_part);
   B.counter_bits = g->counter_bits;
   B.d = d;

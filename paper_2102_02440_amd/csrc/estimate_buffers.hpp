@@ -16,6 +16,16 @@ struct TriElem {
   uint32_t pad[3];
 };
 
+// Compact element of a two-child apex (both children are the cut edge's
+// endpoints), used when every magnitude involved is below 2^30 and every
+// message and product fits in 64 bits.
+struct TriElemN {
+  int32_t v;        // the apex's counter on the child's edge
+  uint32_t kc;      // child slot << 31 | |child's own bucket on that edge|
+  int64_t mu;       // the child's unconditioned message M
+  int64_t vm;       // v * M
+};
+
 struct EstBuffers {
   const void *const *sides;   // [2 * n_edges] counter arrays (d x w)
   const int64_t *n_sel;       // [n_tables]
@@ -24,6 +34,8 @@ struct EstBuffers {
   uint32_t *merged;           // [scratch slot][row][Lmax]
   u128 *xout;                 // [slot][row]
   TriElem *prep;              // [prep slot][row][Lprep]
+  TriElemN *prepn;            // [prep slot][row][Lprep] (two-child apexes)
+  int32_t *prep_z;            // [prep slot][row] leading zero-counter run
   u128 *partial;              // [slot][row]
   int32_t counter_bits;
   int32_t d;

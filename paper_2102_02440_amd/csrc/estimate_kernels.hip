@@ -234,7 +234,9 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
   __syncthreads();
 
   if (T.mode == kModeTriRootPrep) {
-    TriElem *out = B.prep + ((size_t)T.out_slot * B.d + row) * (size_t)B.Lprep;
+    const size_t slot_row = (size_t)T.out_slot * B.d + row;
+    TriElem *out = B.prep + slot_row * (size_t)B.Lprep;
+    TriElemN *outn = B.prepn + slot_row * (size_t)B.Lprep;
     for (int pos = threadIdx.x; pos < L; pos += kNodeThreads) {
       const uint32_t mt = merged[pos];
       const int a = (int)(mt >> 16);
@@ -243,15 +245,37 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
       e.v = counter_at(B, Tg->child_side[a], row, j);
       e.mu = msg_of(B, Tg->child_msg[a], row)[j];
       e.key = 0;
+      uint64_t own = 0;
       if (Tg->child_cut[a] >= 0) {
         // kappa of the child's own bucket on the edge to the apex
         const int other = Tg->child_side[a] ^ 1;
-        e.key = (abs_u64(counter_at(B, other, row, j)) << 7) |
-                (uint64_t)Tg->child_eid[a];
+        own = abs_u64(counter_at(B, other, row, j));
+        e.key = (own << 7) | (uint64_t)Tg->child_eid[a];
       }
       e.child = (uint32_t)a;
       e.pad[0] = e.pad[1] = e.pad[2] = 0;
       out[pos] = e;
+      if (m == 2) {
+        // truncating copy; the sweep reads it only when the bounds hold
+        TriElemN n;
+        n.v = (int32_t)e.v;
+        n.kc = ((uint32_t)a << 31) | (uint32_t)(own & 0x7FFFFFFFull);
+        n.mu = (int64_t)(uint64_t)e.mu;
+        n.vm = (int64_t)((uint64_t)e.v * (uint64_t)e.mu);
+        outn[pos] = n;
+      }
+      // the list is ascending in |v|: its zero counters form a prefix, and
+      // they add nothing to the sweep (it ends there)
+      if (e.v != 0) {
+        bool first = pos == 0;
+        if (!first) {
+          const uint32_t pt = merged[pos - 1];
+          first = counter_at(B, Tg->child_side[pt >> 16], row, pt & 0xFFFF) == 0;
+        }
+        if (first) B.prep_z[slot_row] = pos;
+      } else if (pos == L - 1) {
+        B.prep_z[slot_row] = L;
+      }
     }
     return;
   }
@@ -341,6 +365,54 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
 // ---------------------------------------------------------------------
 // triangle apex sweep: grid (n_tri, d, ceil(w / kLaneThreads))
 // ---------------------------------------------------------------------
+
+// min(a * b, 2^63) for a <= 2^63, b < 2^63
+__device__ __forceinline__ u128 sat_mul63(u128 a, uint64_t b) {
+  const u128 r = a * (u128)b;
+  const u128 cap = (u128)1 << 63;
+  return r > cap ? cap : r;
+}
+
+// Two-child apex, all magnitudes below 2^30, messages in 64 bits.  Sweeping
+// in descending kappa, a maximal run of one child's elements sees the other
+// child's running sum fixed, so the run's terms collapse to
+// (sum over the run of v * mu) * A_other: one 64 x 64 -> 128-bit product per
+// run instead of one per element.  Within a run the lane's conditioned
+// message is mu = M if the element ranks below the cut element, else the
+// constant C(J), so the run sum is (sum of v*M over the elements below) +
+// C(J) * (sum of v over the others): no multiply per element.  The child of
+// an element is wave-uniform; its per-child state is picked with selects
+// (no branch per element, no indexed registers).
+struct FastState {
+  int64_t A0, At;    // running sums: child 0's messages, both children's
+  int64_t C0, C1;    // cut constants C(J) of child slots 0 and 1
+  uint32_t kf0, kf1; // element below the cut element iff its key < kf
+  int64_t xl;        // run: sum of v*M over the elements below
+  int32_t vh;        // run: sum of v over the others
+  uint32_t prev;     // child slot of the current run (uniform)
+};
+
+__device__ __forceinline__ void fast_step(FastState &s, int32_t v, uint32_t kc,
+                                          int64_t mu0, int64_t vm, u128 &G) {
+  const uint32_t c = kc >> 31;
+  if (c != s.prev) {  // the run of child `prev` ends; A_other = A_c
+    const int64_t cown = s.prev ? s.C1 : s.C0;
+    const int64_t Ac = c ? s.At - s.A0 : s.A0;
+    G += mul_s64_s64(s.xl + cown * (int64_t)s.vh, Ac);
+    s.xl = 0;
+    s.vh = 0;
+    s.prev = c;
+  }
+  const uint32_t kf = c ? s.kf1 : s.kf0;
+  const int64_t cc = c ? s.C1 : s.C0;
+  const bool below = (kc & 0x7FFFFFFFu) < kf;
+  const int64_t mu = below ? mu0 : cc;
+  s.At += mu;
+  s.A0 += c ? 0 : mu;
+  s.xl += below ? vm : 0;
+  s.vh += below ? 0 : v;
+}
+
 __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
     const TriTask *tasks, EstBuffers B) {
   __shared__ u128 red[kLaneThreads];
@@ -352,58 +424,109 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
   const int J = blockIdx.z * kLaneThreads + threadIdx.x;
   const bool active = J < B.w;
   const int Jc = active ? J : 0;
+  const size_t slot_row = (size_t)T.prep_slot * B.d + row;
+  const int z = B.prep_z[slot_row];  // the sweep ends at the zero prefix
+  const int m = T.m;
+  const int cu = T.cut_child[0], cv = T.cut_child[1];
 
-  uint64_t kf[2];
+  uint64_t qabs[2];
   u128 cval[2];
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    kf[e] = (abs_u64(counter_at(B, T.cut_side[e], row, Jc)) << 7) |
-            (uint64_t)T.cut_eid;
+    qabs[e] = abs_u64(counter_at(B, T.cut_side[e], row, Jc));
     cval[e] = msg_of(B, T.cut_cmsg[e], row)[Jc];
   }
-  // read-only during this kernel and the same for every lane: read through
-  // the constant address space so the loads are scalar (s_load) and the
-  // child index is a scalar, making the per-child branches uniform
-  typedef const __attribute__((address_space(4))) TriElem ConstElem;
-  ConstElem *el = (ConstElem *)(B.prep + ((size_t)T.prep_slot * B.d + row) *
-                                             (size_t)B.Lprep);
-  const int m = T.m;
-  const int cu = T.cut_child[0], cv = T.cut_child[1];
 
   // Narrow arithmetic when it is exact: every message value of child c is
   // bounded by B_c = prod of n_sel over c's subtree (the L1 norm of a
   // sketch row is at most n_sel), each A_c by (w + 1) B_c, and the apex's
   // counters by n_sel(apex).  When all of these stay below 2^62, messages
-  // and A are int64 and only the running sum G needs 128 bits.
-  bool narrow = true;
+  // and A are int64 and only the running sum G needs 128 bits.  The compact
+  // two-child sweep also needs every table's n_sel below 2^30 (counters,
+  // keys and thresholds then fit 32 bits).
+  bool narrow = true, small = true;
   {
     const u128 lim = (u128)1 << 62;
-    const u128 nroot = (u128)(B.n_sel[T.root_table] < 0 ? 0 : B.n_sel[T.root_table]);
-    for (int c = 0; c < m && narrow; ++c) {
+    const int64_t nr = B.n_sel[T.root_table];
+    const uint64_t nroot = nr < 0 ? 0 : (uint64_t)nr;
+    small = nroot < (1ull << 30);
+    for (int c = 0; c < m; ++c) {
       u128 bc = 1;
-      for (int t = 0; t < 64; ++t) {
-        if (!((T.child_tables[c] >> t) & 1ull)) continue;
-        const int64_t ns = B.n_sel[t];
-        const u128 f = (u128)(ns < 0 ? 0 : ns);
-        if (f != 0 && bc > lim / f) {
-          narrow = false;
-          break;
-        }
-        bc *= f;
+      for (uint64_t s = T.child_tables[c]; s; s &= s - 1) {
+        const int64_t ns = B.n_sel[__builtin_ctzll(s)];
+        const uint64_t f = ns < 0 ? 0 : (uint64_t)ns;
+        small = small && f < (1ull << 30);
+        bc = sat_mul63(bc, f);
       }
-      if (!narrow) break;
-      if (bc != 0 && ((u128)(B.w + 1) > lim / bc || nroot > lim / bc)) narrow = false;
+      if (bc * (u128)(B.w + 1) >= lim || bc * (u128)nroot >= lim) narrow = false;
     }
   }
+
   u128 G = 0;
   constexpr int kUnroll = 4;
-  if (narrow) {
+  if (narrow && small && m == 2) {
+    typedef const __attribute__((address_space(4))) TriElemN ConstElemN;
+    ConstElemN *el = (ConstElemN *)(B.prepn + slot_row * (size_t)B.Lprep);
+    // child slot -> its side state; key < kf  <=>  kappa below the cut
+    // element's (ties in |v| go to the lower edge id)
+    FastState fs;
+    {
+      uint32_t kf[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        kf[e] = (uint32_t)qabs[e] + (T.cut_peid[e] < T.cut_eid ? 1u : 0u);
+      const int e0 = cu == 0 ? 0 : 1;  // cut endpoint in child slot 0
+      fs.kf0 = kf[e0];
+      fs.kf1 = kf[1 - e0];
+      fs.C0 = (int64_t)(uint64_t)cval[e0];
+      fs.C1 = (int64_t)(uint64_t)cval[1 - e0];
+    }
+    fs.A0 = fs.At = 0;
+    fs.xl = 0;
+    fs.vh = 0;
+    fs.prev = 0;
+    constexpr int kGroup = 8;
+    int pos = T.L - 1;
+    for (; pos - (kGroup - 1) >= z; pos -= kGroup) {
+      int32_t v[kGroup];
+      uint32_t kc[kGroup];
+      int64_t mu[kGroup], vm[kGroup];
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        ConstElemN &r = el[pos - u];
+        v[u] = r.v;
+        kc[u] = r.kc;
+        mu[u] = r.mu;
+        vm[u] = r.vm;
+      }
+      // issue the whole group's scalar loads before the first use
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u)
+        __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) fast_step(fs, v[u], kc[u], mu[u], vm[u], G);
+    }
+    for (; pos >= z; --pos) {
+      ConstElemN &r = el[pos];
+      fast_step(fs, r.v, r.kc, r.mu, r.vm, G);
+    }
+    {  // close the last run
+      const int64_t cown = fs.prev ? fs.C1 : fs.C0;
+      const int64_t Aoth = fs.prev ? fs.A0 : fs.At - fs.A0;
+      G += mul_s64_s64(fs.xl + cown * (int64_t)fs.vh, Aoth);
+    }
+  } else if (narrow) {
+    typedef const __attribute__((address_space(4))) TriElem ConstElem;
+    ConstElem *el = (ConstElem *)(B.prep + slot_row * (size_t)B.Lprep);
+    uint64_t kf[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) kf[e] = (qabs[e] << 7) | (uint64_t)T.cut_eid;
     int64_t A[kMaxChild];
 #pragma unroll
     for (int c = 0; c < kMaxChild; ++c) A[c] = 0;
     const int64_t c0 = (int64_t)(uint64_t)cval[0], c1 = (int64_t)(uint64_t)cval[1];
     int pos = T.L - 1;
-    for (; pos >= 0; pos -= kUnroll) {
+    for (; pos >= z; pos -= kUnroll) {
       TriElem e[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -415,7 +538,7 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        if (pos - u < 0) break;
+        if (pos - u < z) break;
         const int a = (int)e[u].child;
         int64_t mu = (int64_t)(uint64_t)e[u].mu;
         if (a == cu) mu = e[u].key < kf[0] ? mu : c0;
@@ -438,13 +561,18 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
       }
     }
   } else {
+    typedef const __attribute__((address_space(4))) TriElem ConstElem;
+    ConstElem *el = (ConstElem *)(B.prep + slot_row * (size_t)B.Lprep);
+    uint64_t kf[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) kf[e] = (qabs[e] << 7) | (uint64_t)T.cut_eid;
     u128 A[kMaxChild];
 #pragma unroll
     for (int c = 0; c < kMaxChild; ++c) A[c] = 0;
     // descending kappa: A_c accumulates the elements already passed (larger
     // kappa), i.e. exactly the elements a term's bucket must rank below
     int pos = T.L - 1;
-    for (; pos >= kUnroll - 1; pos -= kUnroll) {
+    for (; pos - (kUnroll - 1) >= z; pos -= kUnroll) {
       TriElem e[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
@@ -470,7 +598,7 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
           if (c == a) A[c] += mu;
       }
     }
-    for (; pos >= 0; --pos) {
+    for (; pos >= z; --pos) {
       TriElem e;
       e.v = el[pos].v;
       e.key = el[pos].key;

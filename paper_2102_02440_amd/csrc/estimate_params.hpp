@@ -46,6 +46,7 @@ struct TriTask {
   int32_t cut_side[2];      // sides (endpoint u, endpoint v) of the cut edge
   int32_t cut_cmsg[2];      // cut-constant slots of u and v
   int32_t cut_child[2];     // root child slots of u and v
+  int32_t cut_peid[2];      // edge ids joining u and v to the apex
   int32_t partial_slot;     // first of gridDim.z partial sums
   int32_t root_table;
   uint64_t child_tables[kMaxChild];  // tables of each child's subtree

@@ -222,6 +222,62 @@ def test_collision_free_exact_two_way(oracle):
     assert flags.item() == C.FLAG_EXACT
 
 
+def _triangle_query(seed, extra_child):
+    """Triangle 0-1-2 closed by edge (1, 2); table 0 is the apex.  With
+    extra_child a fourth table hangs off the apex (three apex children)."""
+    rng = np.random.default_rng(seed)
+    n = [3000, 2500, 2000, 1500]
+    tables = []
+    for t in range(4 if extra_child else 3):
+        cols = {"k0": rng.integers(0, 300, n[t]).astype(np.int32),
+                "k1": rng.integers(0, 300, n[t]).astype(np.int32)}
+        tables.append(W.Table("t%d" % t, cols, []))
+    edges = [W.Edge(0, "k0", 1, "k0"), W.Edge(0, "k1", 2, "k0"),
+             W.Edge(1, "k1", 2, "k1")]
+    if extra_child:
+        edges.append(W.Edge(0, "k0", 3, "k1"))
+    return W.Query(tables, edges, 3, 512, W.draw_seeds(rng, len(edges), 3), 32)
+
+
+@gpu
+@pytest.mark.parametrize("extra_child", [False, True])
+@pytest.mark.parametrize("inflate", ["none", "above_2^30", "above_2^62"])
+def test_triangle_sweep_paths(oracle, extra_child, inflate):
+    """The triangle sweep picks its arithmetic from the selected counts (they
+    bound every counter and message): compact 64-bit for a two-child apex
+    with all counts below 2^30, general 64-bit, or 128-bit.  Raising the
+    counts keeps them valid bounds and forces each path on the same
+    sketches; the oracle gets the same counts."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    q = _triangle_query(91 + extra_child, extra_child)
+    _say("triangle paths", "extra_child", extra_child, "inflate", inflate)
+    dq = C.DeviceQuery(q)
+    dq.build()
+    torch.cuda.synchronize()
+    side_sk, n_sel = oracle_query(oracle, q)
+    assert dq.n_selected.cpu().tolist() == n_sel
+    add = {"none": 0, "above_2^30": 1 << 30, "above_2^62": 1 << 40}[inflate]
+    n_sel = [x + add for x in n_sel]
+    dq.n_selected.copy_(torch.tensor(n_sel, dtype=torch.int64))
+    masks = oracle.connected_subplans(len(q.tables), q.edge_u, q.edge_v)
+    row_est, est, flags = dq.estimate(masks)
+    torch.cuda.synchronize()
+    vals_o, est_o, flags_o = oracle.estimate(len(q.tables), q.edge_u, q.edge_v,
+                                             q.d, q.w, side_sk, n_sel, masks)
+    vals_g = C.row_values(row_est)
+    fl = flags.cpu().numpy()
+    n_tri = 0
+    for m in range(len(masks)):
+        assert not fl[m] & C.FLAG_UNSUPPORTED, "mask 0x%x" % masks[m]
+        n_tri += (masks[m] & 7) == 7
+        go = [v & ((1 << 128) - 1) for v in vals_o[m]]
+        assert vals_g[m] == go, "mask 0x%x" % masks[m]
+        assert fl[m] == flags_o[m], "mask 0x%x" % masks[m]
+        assert est.cpu().numpy()[m] == est_o[m], "mask 0x%x" % masks[m]
+    assert n_tri == (2 if extra_child else 1)
+
+
 @gpu
 def test_job6a_full_size(oracle):
     """Full-size 6a-shaped workload (ci 36M, mk 4.5M, t 2.5M, n 4.2M, k 134k;
