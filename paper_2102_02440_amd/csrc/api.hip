@@ -349,7 +349,10 @@ extern "C" compass_status compass_sketch_build(
     // them into LDS counters over a bucket range per block, and the slab
     // reduction adds the partials into the counters (zeroed above unless
     // accumulating).
-    const int64_t cap = std::min<int64_t>(n_rows, (int64_t)1 << 25);
+    // (survivor buffer at most 4 GiB: 8 bytes per sketch per row)
+    const int64_t cap = std::min<int64_t>(
+        n_rows, std::max<int64_t>((int64_t)1 << 25,
+                                  ((int64_t)1 << 32) / (8 * n_sketches)));
     const int ranges = (int)(((size_t)w * 4 + kLdsBudget - 1) / kLdsBudget);
     int chunks = std::max(1, (int)((4ll * ds->n_cu + S * ranges - 1) / (S * ranges)));
     const size_t b_surv = (size_t)n_sketches * cap * 8;
@@ -377,7 +380,7 @@ extern "C" compass_status compass_sketch_build(
       {
         ProfScope ps("wide_compact", stream);
         HIP_OK(launch_wide_compact(P, surv, cap, count, r0, r1,
-                                   (int)std::min<int64_t>(tiles, 4ll * ds->n_cu),
+                                   (int)std::min<int64_t>(tiles, 2ll * ds->n_cu),
                                    stream));
       }
       {

@@ -96,33 +96,63 @@ struct DirectJob {
 
 // Wide sketches, phase A: the fused scan compacts the qualifying rows of
 // [row_begin, row_end) and appends their key field elements, per sketch, to
-// surv[s * cap + ...] (one global atomic per tile reserves the space).
+// surv[s * cap + ...].  Each block strides over tiles, buffers the offsets
+// of its survivors in LDS across tiles, and only when the buffer is nearly
+// full (or its tiles are done) reserves space with one global atomic and
+// gathers the keys of every (sketch, survivor) pair, four loads in flight
+// per thread.
+constexpr int kWideQueue = 16384;
+
 __global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
     const BuildParams P, uint64_t *__restrict__ surv, int64_t cap,
     unsigned long long *__restrict__ count, int64_t row_begin,
     int64_t row_end) {
-  __shared__ int32_t queue[kBuildTile];
+  __shared__ int32_t queue[kWideQueue];
   __shared__ int32_t s_qn;
   __shared__ unsigned long long s_off;
   const DirectJob job{P};
   uint64_t sel = 0;
+  int qtot = 0;  // block-uniform
+  const int64_t stride = (int64_t)gridDim.x * kBuildTile;
   for (int64_t base = row_begin + (int64_t)blockIdx.x * kBuildTile;
-       base < row_end; base += (int64_t)gridDim.x * kBuildTile) {
+       base < row_end; base += stride) {
     const int nt = (int)min((int64_t)kBuildTile, row_end - base);
-    const int qn = compact_tile<DirectJob, kBuildRowsPerThread>(
-        job, base, nt, P.n_preds, queue, &s_qn);
-    if (threadIdx.x == 0) s_off = qn ? atomicAdd(count, (unsigned long long)qn) : 0;
-    __syncthreads();
-    const int64_t off = (int64_t)s_off;
-    sel += (uint64_t)qn;
-    for (int s = 0; s < P.n_groups; ++s) {  // n_groups = sketches here
-      const KeyDev kd = P.keys[s];
-      for (int q = threadIdx.x; q < qn; q += kBuildThreads) {
-        const int64_t row = base + (P.n_preds ? queue[q] : q);
-        surv[(int64_t)s * cap + off + q] = load_field(kd, row);
-      }
+    const int bias = (int)(base - row_begin);
+    if (P.n_preds == 0) {
+      for (int r = threadIdx.x; r < nt; r += kBuildThreads)
+        queue[qtot + r] = bias + r;
+      qtot += nt;
+    } else {
+      qtot = compact_tile<DirectJob, kBuildRowsPerThread>(
+          job, base, nt, P.n_preds, queue, &s_qn, qtot, bias);
     }
-    __syncthreads();  // queue, s_qn and s_off are reused by the next tile
+    const bool last = base + stride >= row_end;
+    if (qtot > kWideQueue - kBuildTile || (last && qtot > 0)) {
+      __syncthreads();  // queue complete
+      if (threadIdx.x == 0) s_off = atomicAdd(count, (unsigned long long)qtot);
+      __syncthreads();
+      const int64_t off = (int64_t)s_off;
+      for (int s = 0; s < P.n_groups; ++s) {  // n_groups = sketches here
+        const KeyDev kd = P.keys[s];
+        uint64_t *dst = surv + (int64_t)s * cap + off;
+        for (int q0 = threadIdx.x; q0 < qtot; q0 += 4 * kBuildThreads) {
+          uint64_t v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * kBuildThreads;
+            v[u] = q < qtot ? load_field(kd, row_begin + queue[q]) : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * kBuildThreads;
+            if (q < qtot) dst[q] = v[u];
+          }
+        }
+      }
+      sel += (uint64_t)qtot;
+      qtot = 0;
+    }
+    __syncthreads();  // queue, s_qn and s_off are reused
   }
   if (P.count_selected && threadIdx.x == 0 && sel)
     atomicAdd(reinterpret_cast<unsigned long long *>(P.n_selected),

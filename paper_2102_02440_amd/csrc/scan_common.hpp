@@ -11,13 +11,19 @@
 
 namespace compass {
 
-__device__ __forceinline__ bool eval_pred(const PredDev &p, int64_t row) {
+// predicate columns are int32 or float32: their 32-bit patterns
+__device__ __forceinline__ uint32_t load_pred_raw(const PredDev &p,
+                                                  int64_t row) {
+  return reinterpret_cast<const uint32_t *>(p.col)[row];
+}
+
+__device__ __forceinline__ bool eval_pred_raw(const PredDev &p, uint32_t raw) {
   if (p.dtype == kDtF32) {
-    const float v = reinterpret_cast<const float *>(p.col)[row];
+    const float v = __uint_as_float(raw);
     if (p.kind == kPredPoint) return v == p.lo.f;
     return (v >= p.lo.f) & (v <= p.hi.f);
   }
-  const int32_t v = reinterpret_cast<const int32_t *>(p.col)[row];
+  const int32_t v = (int32_t)raw;
   if (p.kind == kPredPoint) return v == p.lo.i;
   if (p.kind == kPredRange) return (v >= p.lo.i) & (v <= p.hi.i);
   // subset: dictionary code must lie in [0, domain) and have its bit set
@@ -46,28 +52,49 @@ __device__ __forceinline__ uint64_t load_field(const KeyDev &k, int64_t row) {
 }
 
 // Compacts the qualifying rows of tile [base, base + nt) into `queue`
-// (row offsets, unordered: the sums do not depend on order) and returns
-// their number; with no predicates every row qualifies and the queue is not
-// used.  Every thread of the block must call it.
+// (entries start .. start + count - 1, each the row offset plus `bias`;
+// unordered: the sums do not depend on order) and returns start + their
+// number.  Each predicate column is loaded for all of the thread's rows,
+// and before it is evaluated the next one is loaded too, so loads overlap
+// instead of waiting on the previous predicate's outcome.  With no
+// predicates every row qualifies; the queue is then not used and nt is
+// returned.  Every thread of the block must call it.
 template <class J, int kRowsPerThread>
 __device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
-                            int32_t *queue, int32_t *s_qn) {
+                            int32_t *queue, int32_t *s_qn, int start = 0,
+                            int bias = 0) {
   if (n_preds == 0) return nt;
-  if (threadIdx.x == 0) *s_qn = 0;
-  __syncthreads();
+  if (threadIdx.x == 0) *s_qn = start;
+  // predicate q + 1 is loaded before predicate q is evaluated
+  uint32_t cur[kRowsPerThread], nxt[kRowsPerThread];
+  bool pass[kRowsPerThread];
 #pragma unroll
   for (int k = 0; k < kRowsPerThread; ++k) {
     const int r = threadIdx.x + k * kBuildThreads;
-    bool pass = r < nt;
-    if (pass) {
-      for (int q = 0; q < n_preds; ++q) {
-        if (!eval_pred(job.pred(q), base + r)) {
-          pass = false;
-          break;
-        }
+    pass[k] = r < nt;
+    cur[k] = pass[k] ? load_pred_raw(job.pred(0), base + r) : 0u;
+  }
+  for (int q = 0; q < n_preds; ++q) {
+    if (q + 1 < n_preds) {
+      const PredDev &pn = job.pred(q + 1);
+#pragma unroll
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        const int r = threadIdx.x + k * kBuildThreads;
+        nxt[k] = r < nt ? load_pred_raw(pn, base + r) : 0u;
       }
     }
-    const uint64_t ballot = __ballot(pass);
+    const PredDev &p = job.pred(q);
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; ++k) {
+      pass[k] = pass[k] && eval_pred_raw(p, cur[k]);
+      cur[k] = nxt[k];
+    }
+  }
+  __syncthreads();  // s_qn initialised
+#pragma unroll
+  for (int k = 0; k < kRowsPerThread; ++k) {
+    const int r = threadIdx.x + k * kBuildThreads;
+    const uint64_t ballot = __ballot(pass[k]);
     const int lane = __lane_id();
     const uint32_t before = __builtin_amdgcn_mbcnt_hi(
         (uint32_t)(ballot >> 32),
@@ -76,7 +103,7 @@ __device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
     int off = 0;
     if (lane == 0 && total) off = atomicAdd(s_qn, total);
     off = __shfl(off, 0);
-    if (pass) queue[off + before] = r;
+    if (pass[k]) queue[off + before] = r + bias;
   }
   __syncthreads();
   return *s_qn;
