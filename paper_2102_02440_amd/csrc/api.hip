@@ -418,17 +418,18 @@ extern "C" compass_status compass_sketch_build(
   }
   const int n_groups_total = (S + per_group - 1) / per_group;
 
-  // chunks: about eight waves of the resident workgroup slots, so that
-  // equal-sized items fill the chip with a short tail; at least one tile
-  // per chunk.  Each
-  // chunk writes its partial counters to a slab (summed by one reduction
-  // kernel), which is cheap next to the scan: bound the slab to 1 GiB.
+  // chunks: up to eight waves of the resident workgroup slots (whole
+  // waves, so that no slot runs one more workgroup than the others), but at
+  // least eight tiles per workgroup, which keeps zeroing and writing back
+  // its LDS partials small next to its scan.  Each chunk writes its partial
+  // counters to a slab (summed by one reduction kernel), which is cheap next
+  // to the scan: bound the slab to 1 GiB.
   const size_t lds_block = (size_t)per_group * w * 4 + (size_t)kBuildTile * 4;
   const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / lds_block)));
   const int64_t slots = (int64_t)ds->n_cu * per_cu;
   const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
-  int64_t chunks = std::max<int64_t>(1, (8 * slots + n_groups_total - 1) / n_groups_total);
-  chunks = std::min(chunks, tiles);
+  int64_t chunks = std::max<int64_t>(1, 8 * slots / n_groups_total);
+  chunks = std::min(chunks, std::max<int64_t>(1, tiles / 8));
   const size_t slab_row = (size_t)S * w * 4;
   chunks = std::min<int64_t>(chunks, std::max<size_t>(1, ((size_t)1 << 30) / slab_row));
   int64_t rows_per_chunk = (n_rows + chunks - 1) / chunks;
@@ -449,6 +450,7 @@ extern "C" compass_status compass_sketch_build(
   while (slice < S) {
     BuildParams P = base;
     int ls = 0, ng = 0;
+    P.slice_base = slice;
     P.group_begin[0] = 0;
     while (slice < S && ng < kMaxLaunchGroups) {
       const int gs = std::min(per_group, S - slice);
@@ -456,15 +458,13 @@ extern "C" compass_status compass_sketch_build(
       for (int q = 0; q < gs; ++q) {
         const int gsl = slice + q;
         const int s = gsl / d, i = gsl % d;
-        P.slice_sketch[ls + q] = (int8_t)s;
-        P.slice_row[ls + q] = (int8_t)i;
         const uint64_t *sd = sketches[s].seeds + 6 * i;
         P.seeds[ls + q] = RowSeeds{sd[0], sd[1], sd[2], sd[3], sd[4], sd[5]};
       }
       ls += gs;
       slice += gs;
       ++ng;
-      P.group_begin[ng] = (int16_t)ls;
+      P.group_begin[ng] = ls;
     }
     P.n_groups = ng;
     P.count_selected = first ? 1 : 0;
@@ -599,10 +599,45 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
       for (auto &pb : adj[cut_v])
         if (pa.first == pb.first) apex = pa.first;
     }
-    if (direct || apex < 0)
+    if (direct || apex < 0) {
       supported = false;
-    else
-      root = apex;
+    } else {
+      // Any triangle edge may be the cut one (the estimate is the same
+      // number); cut the edge opposite the vertex of fewest sub-plan edges,
+      // so that the apex sweep has as few children as possible (two, when
+      // no other edge meets that vertex).
+      auto degree = [&](int node) {
+        int k = 0;
+        for (int e : edges)
+          k += g->edge_u[e] == nodes[node].table || g->edge_v[e] == nodes[node].table;
+        return k;
+      };
+      auto tree_edge = [&](int a, int b) {
+        for (auto &p : adj[a])
+          if (p.first == b) return p.second;
+        return -1;
+      };
+      int best = apex;
+      if (degree(cut_u) < degree(best)) best = cut_u;
+      if (degree(cut_v) < degree(best)) best = cut_v;
+      if (best != apex) {
+        const int other = best == cut_u ? cut_v : cut_u;
+        const int new_cut = tree_edge(apex, other);
+        is_tree[cut_e] = 1;
+        is_tree[new_cut] = 0;
+        for (auto &v : adj) v.clear();
+        for (int e : edges) {
+          if (!is_tree[e]) continue;
+          const int a = node_of[g->edge_u[e]], b = node_of[g->edge_v[e]];
+          adj[a].push_back({b, e});
+          adj[b].push_back({a, e});
+        }
+        cut_e = new_cut;
+        cut_u = node_of[g->edge_u[new_cut]];
+        cut_v = node_of[g->edge_v[new_cut]];
+      }
+      root = best;
+    }
   }
   if (!supported) {
     sp.type = kSpUnsupported;

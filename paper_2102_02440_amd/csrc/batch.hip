@@ -61,18 +61,53 @@ struct ZeroRegion {
   int64_t words;
 };
 
+// Job view over the device-resident job and seed tables.  They are read-only
+// while the kernel runs and every lane reads the same entry, so they are
+// read through the constant address space (scalar loads, uniform values).
+typedef const __attribute__((address_space(4))) BatchJob KJob;
+typedef const __attribute__((address_space(4))) BatchItem KItem;
+typedef const __attribute__((address_space(4))) RowSeeds KSeeds;
+
 struct GlobalJob {
-  const BatchJob *J;
-  const RowSeeds *seed_arr;
+  KJob *J;
+  KSeeds *seed_arr;
   __device__ int n_preds() const { return J->n_preds; }
-  __device__ const PredDev &pred(int q) const { return J->preds[q]; }
-  __device__ KeyDev key(int s) const { return J->keys[s]; }
+  __device__ PredDev pred(int q) const {
+    PredDev p;
+    p.col = J->preds[q].col;
+    p.bitmap = J->preds[q].bitmap;
+    p.domain = J->preds[q].domain;
+    p.kind = J->preds[q].kind;
+    p.dtype = J->preds[q].dtype;
+    p.lo.i = J->preds[q].lo.i;
+    p.hi.i = J->preds[q].hi.i;
+    return p;
+  }
+  __device__ KeyDev key(int s) const {
+    KeyDev k;
+    k.col = J->keys[s].col;
+    k.dtype = J->keys[s].dtype;
+    k.pad = 0;
+    return k;
+  }
   __device__ int slice_sketch(int sl) const { return sl / J->d; }
   __device__ int slice_row(int sl) const { return sl % J->d; }
-  __device__ RowSeeds seeds(int sl) const { return seed_arr[J->seed_base + sl]; }
-  __device__ BucketMod bm() const { return J->bm; }
+  __device__ RowSeeds seeds(int sl) const {
+    KSeeds &x = seed_arr[J->seed_base + sl];
+    return RowSeeds{x.a0, x.a1, x.a2, x.a3, x.b0, x.b1};
+  }
+  __device__ BucketMod bm() const {
+    BucketMod m;
+    m.w = J->bm.w;
+    m.mask = J->bm.mask;
+    m.r32 = J->bm.r32;
+    m.pow2 = J->bm.pow2;
+    m.inv = J->bm.inv;
+    return m;
+  }
   __device__ int counter_bits() const { return J->counter_bits; }
   __device__ void *counters(int s) const { return J->counters[s]; }
+  __device__ int64_t *n_selected() const { return J->n_selected; }
 };
 
 __global__ __launch_bounds__(kBuildThreads) void batch_scan_kernel(
@@ -84,11 +119,18 @@ __global__ __launch_bounds__(kBuildThreads) void batch_scan_kernel(
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= n_items) break;  // uniform across the workgroup
-    const BatchItem I = items[it];
-    const GlobalJob job{jobs + I.job, seeds};
+    KItem &KI = ((KItem *)items)[it];
+    BatchItem I;
+    I.row0 = KI.row0;
+    I.row1 = KI.row1;
+    I.job = KI.job;
+    I.slice_begin = KI.slice_begin;
+    I.slice_end = KI.slice_end;
+    I.count_selected = KI.count_selected;
+    const GlobalJob job{(KJob *)jobs + I.job, (KSeeds *)seeds};
     const int w = (int)job.bm().w;
     const int ns = I.slice_end - I.slice_begin;
     int32_t *cnt = lds;
@@ -99,7 +141,7 @@ __global__ __launch_bounds__(kBuildThreads) void batch_scan_kernel(
                                    I.slice_end, cnt, queue_rows, &s_qn);
     merge_slices(job, I.slice_begin, I.slice_end, cnt);
     if (I.count_selected && threadIdx.x == 0 && sel)
-      atomicAdd(reinterpret_cast<unsigned long long *>(job.J->n_selected),
+      atomicAdd(reinterpret_cast<unsigned long long *>(job.n_selected()),
                 (unsigned long long)sel);
     __syncthreads();  // LDS is reused by the next item
   }

@@ -19,10 +19,11 @@
 //  * Each survivor's key is turned into its field element once per sketch;
 //    the d row hashes then use wave-uniform seeds (scalar registers) and a
 //    fire-and-forget ds_add into LDS.
-//  * The merge pass adds each non-zero LDS partial into the global counters
-//    with one integer atomic; integer addition is order-independent, so the
-//    result is bit-exact whatever the schedule (Section 2: sketches of
-//    partitions add up to the sketch of the whole).
+//  * Each workgroup writes its LDS partials to its own slab row (plain
+//    stores); one reduction kernel sums the chunks per counter.  Integer
+//    addition is order-independent, so the result is bit-exact whatever
+//    the schedule (Section 2: sketches of partitions add up to the sketch
+//    of the whole).
 //  * Block -> (chunk, group) with the group varying fastest, so the groups
 //    that re-read one chunk's columns are dispatched together and share it
 //    through the Infinity Cache.
@@ -41,8 +42,8 @@ struct ParamJob {
   __device__ int n_preds() const { return P.n_preds; }
   __device__ const PredDev &pred(int q) const { return P.preds[q]; }
   __device__ KeyDev key(int s) const { return P.keys[s]; }
-  __device__ int slice_sketch(int sl) const { return P.slice_sketch[sl]; }
-  __device__ int slice_row(int sl) const { return P.slice_row[sl]; }
+  __device__ int slice_sketch(int sl) const { return (P.slice_base + sl) / P.d; }
+  __device__ int slice_row(int sl) const { return (P.slice_base + sl) % P.d; }
   __device__ RowSeeds seeds(int sl) const { return P.seeds[sl]; }
   __device__ BucketMod bm() const { return P.bm; }
   __device__ int counter_bits() const { return P.counter_bits; }
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(kBuildThreads) void scan_sketch_kernel(
   const size_t S = (size_t)P.n_slices_total;
   for (int l = 0; l < ns; ++l) {
     const int sl = sb + l;
-    const size_t gs = (size_t)P.slice_sketch[sl] * P.d + P.slice_row[sl];
+    const size_t gs = (size_t)(P.slice_base + sl);
     int32_t *dst = P.slab + ((size_t)chunk * S + gs) * w;
     const int32_t *c = cnt + (size_t)l * w;
     for (int j = threadIdx.x; j < w; j += kBuildThreads) dst[j] = c[j];

@@ -55,9 +55,9 @@ struct BuildParams {
   PredDev preds[kMaxPreds];
   KeyDev keys[kMaxSketches];
   void *counters[kMaxSketches];
-  int8_t slice_sketch[kMaxLaunchSlices];
-  int8_t slice_row[kMaxLaunchSlices];
-  int16_t group_begin[kMaxLaunchGroups + 1];
+  int32_t slice_base;   // launch-local slice l is the call's slice
+                        // slice_base + l = sketch * d + row
+  int32_t group_begin[kMaxLaunchGroups + 1];  // 32-bit: scalar loads
   RowSeeds seeds[kMaxLaunchSlices];
 };
 

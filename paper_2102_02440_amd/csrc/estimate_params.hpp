@@ -5,7 +5,7 @@
 namespace compass {
 
 constexpr int kMaxChild = 6;
-constexpr int kNodeThreads = 256;
+constexpr int kNodeThreads = 1024;
 constexpr int kSortThreads = 1024;
 constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS

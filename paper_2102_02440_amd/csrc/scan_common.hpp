@@ -51,6 +51,30 @@ __device__ __forceinline__ uint64_t load_field(const KeyDev &k, int64_t row) {
   return key_field(v);
 }
 
+// Field elements of the keys of rows base + ridx[k] (every such row lies in
+// the table): all loads are issued before the first is used.
+template <int R>
+__device__ __forceinline__ void load_fields(const KeyDev &kd, int64_t base,
+                                            const int (&ridx)[R],
+                                            uint64_t (&x)[R]) {
+  if (kd.dtype == kDtI32) {
+    int32_t raw[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      raw[k] = reinterpret_cast<const int32_t *>(kd.col)[base + ridx[k]];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      x[k] = raw[k] >= 0 ? (uint64_t)raw[k] : key_field((int64_t)raw[k]);
+  } else {
+    int64_t raw[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      raw[k] = reinterpret_cast<const int64_t *>(kd.col)[base + ridx[k]];
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = key_field(raw[k]);
+  }
+}
+
 // Compacts the qualifying rows of tile [base, base + nt) into `queue`
 // (entries start .. start + count - 1, each the row offset plus `bias`;
 // unordered: the sums do not depend on order) and returns start + their
@@ -119,6 +143,11 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
                               int32_t *s_qn) {
   constexpr int kRowsPerThread = kBuildRowsPerThread;
   constexpr int kTile = kBuildTile;
+  // the slice range is the same in every lane: say so, so that the slice
+  // tables and seeds are read with scalar loads and the per-slice branches
+  // stay uniform
+  sb = __builtin_amdgcn_readfirstlane(sb);
+  se = __builtin_amdgcn_readfirstlane(se);
   const int w = (int)job.bm().w;
   const int n_preds = job.n_preds();
   const bool dense = (n_preds == 0);
@@ -162,14 +191,14 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
       }
       have_pre = true;
     }
-    for (int sl = sb; sl < se; ++sl) {
+    for (int sl0 = sb; sl0 < se; ++sl0) {
+      const int sl = __builtin_amdgcn_readfirstlane(sl0);
       const int s = job.slice_sketch(sl);
       if (s != cur_sketch) {
         cur_sketch = s;
-        const KeyDev kd = job.key(s);
-#pragma unroll
-        for (int k = 0; k < kRowsPerThread; ++k)
-          x[k] = valid[k] ? load_field(kd, base + ridx[k]) : 0;
+        // rows of invalid entries are row `base` (in the table); their
+        // values are never used
+        load_fields<kRowsPerThread>(job.key(s), base, ridx, x);
       }
       const RowSeeds sd = job.seeds(sl);
       const BucketMod bm = job.bm();
