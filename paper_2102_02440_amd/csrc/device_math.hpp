@@ -33,18 +33,19 @@ __device__ __forceinline__ uint64_t canon61(uint64_t r) {
 
 // acc < 2^63, x < 2^32, c < 2^61:
 // returns a value < 2^63 congruent to acc * x + c (mod p).
-//   acc * x + c = P1 * 2^32 + P0 with
-//   P0 = lo32(acc) * x + lo32(c)   (< 2^64)
-//   P1 = hi32(acc) * x + hi32(c)   (< 2^63 + 2^29)
-//   P1 * 2^32 = (P1 >> 29) * 2^61 + (P1 mod 2^29) * 2^32,  2^61 == 1 (mod p)
-//   P0        = (P0 >> 61) * 2^61 + (P0 mod 2^61)
+//   t0 = lo32(acc) * x                       (< 2^64)
+//   t1 = hi32(acc) * x + hi32(t0)            (< 2^63 + 2^32)
+//   acc * x = t1 * 2^32 + lo32(t0)
+//   t1 * 2^32 = (t1 >> 29) * 2^61 + (t1 mod 2^29) * 2^32,  2^61 == 1 (mod p)
+// so acc * x + c == (t1 mod 2^29) * 2^32 + lo32(t0) + (t1 >> 29) + c, a sum
+// below 2^61 + 2^35 + 2^61.  Two v_mad_u64_u32 (the second takes hi32(t0)
+// as its addend), one AND, one 64-bit shift and two 64-bit adds.
 __device__ __forceinline__ uint64_t madd61_x32(uint64_t acc, uint32_t x,
                                                uint64_t c) {
-  const uint64_t p0 = (uint64_t)(uint32_t)acc * x + (uint32_t)c;
-  const uint64_t p1 =
-      (uint64_t)(uint32_t)(acc >> 32) * x + (uint32_t)(c >> 32);
-  return (p0 & kP61) + (p0 >> 61) + (p1 >> 29) +
-         ((p1 & 0x1FFFFFFFull) << 32);
+  const uint64_t t0 = (uint64_t)(uint32_t)acc * x;
+  const uint64_t t1 = (uint64_t)(uint32_t)(acc >> 32) * x + (t0 >> 32);
+  const uint64_t low = ((t1 & 0x1FFFFFFFull) << 32) | (uint32_t)t0;
+  return low + (t1 >> 29) + c;
 }
 
 // acc < 2^63, x < 2^61, c < 2^61: value < 2^63 congruent to acc * x + c.

@@ -32,12 +32,6 @@ __device__ __forceinline__ bool eval_pred_raw(const PredDev &p, uint32_t raw) {
   return (word >> (v & 63)) & 1ull;
 }
 
-// raw key as int64 (int32 keys sign-extended)
-__device__ __forceinline__ int64_t load_raw_key(const KeyDev &k, int64_t row) {
-  if (k.dtype == kDtI32) return reinterpret_cast<const int32_t *>(k.col)[row];
-  return reinterpret_cast<const int64_t *>(k.col)[row];
-}
-
 __device__ __forceinline__ uint64_t field_of_raw(int64_t v) {
   return (v >= 0 && (uint64_t)v < kP61) ? (uint64_t)v : key_field(v);
 }
@@ -153,10 +147,13 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
   const bool dense = (n_preds == 0);
   uint64_t sel = 0;
   // Dense tables: the keys of the group's first sketch for the next tile
-  // are loaded while the current tile is hashed (software prefetch).
+  // are loaded while the current tile is hashed (software prefetch).  They
+  // are kept as raw 32-bit words (no sign extension at the load, which
+  // would make the load wait at once).
   const int s_first = job.slice_sketch(sb);
   const KeyDev kd_first = job.key(s_first);
-  int64_t pre[kRowsPerThread];
+  const bool first_i32 = kd_first.dtype == kDtI32;
+  uint32_t pre_lo[kRowsPerThread], pre_hi[kRowsPerThread];
   bool have_pre = false;
   for (int64_t base = row0; base < row1; base += kTile) {
     const int nt = (int)min((int64_t)kTile, row1 - base);
@@ -176,18 +173,36 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
     uint64_t x[kRowsPerThread];
     int cur_sketch = -1;
     if (dense) {
+      if (!have_pre) load_fields<kRowsPerThread>(kd_first, base, ridx, x);
+      if (have_pre) {
 #pragma unroll
-      for (int k = 0; k < kRowsPerThread; ++k) {
-        if (!have_pre) pre[k] = valid[k] ? load_raw_key(kd_first, base + ridx[k]) : 0;
-        x[k] = field_of_raw(pre[k]);
+        for (int k = 0; k < kRowsPerThread; ++k) {
+          const int64_t raw =
+              first_i32 ? (int64_t)(int32_t)pre_lo[k]
+                        : (int64_t)(((uint64_t)pre_hi[k] << 32) | pre_lo[k]);
+          x[k] = field_of_raw(raw);
+        }
       }
       cur_sketch = s_first;
       const int64_t nb = base + kTile;
       const int nt2 = (int)max((int64_t)0, min((int64_t)kTile, row1 - nb));
+      if (first_i32) {
+        const uint32_t *col = reinterpret_cast<const uint32_t *>(kd_first.col);
 #pragma unroll
-      for (int k = 0; k < kRowsPerThread; ++k) {
-        const int q = threadIdx.x + k * kBuildThreads;
-        pre[k] = q < nt2 ? load_raw_key(kd_first, nb + q) : 0;
+        for (int k = 0; k < kRowsPerThread; ++k) {
+          const int q = threadIdx.x + k * kBuildThreads;
+          pre_lo[k] = q < nt2 ? col[nb + q] : 0u;
+          pre_hi[k] = 0u;
+        }
+      } else {
+        const uint64_t *col = reinterpret_cast<const uint64_t *>(kd_first.col);
+#pragma unroll
+        for (int k = 0; k < kRowsPerThread; ++k) {
+          const int q = threadIdx.x + k * kBuildThreads;
+          const uint64_t v = q < nt2 ? col[nb + q] : 0ull;
+          pre_lo[k] = (uint32_t)v;
+          pre_hi[k] = (uint32_t)(v >> 32);
+        }
       }
       have_pre = true;
     }
