@@ -18,12 +18,14 @@ struct TriElem {
 
 // Compact element of a two-child apex (both children are the cut edge's
 // endpoints), used when every magnitude involved is below 2^30 and every
-// message and product fits in 64 bits.
+// message and product fits in 64 bits.  32 bytes: one scalar x8 load.
 struct TriElemN {
   int32_t v;        // the apex's counter on the child's edge
   uint32_t kc;      // child slot << 31 | |child's own bucket on that edge|
   int64_t mu;       // the child's unconditioned message M
   int64_t vm;       // v * M
+  int32_t run_lo;   // lowest position of the same-child run holding it
+  int32_t pad;
 };
 
 struct EstBuffers {

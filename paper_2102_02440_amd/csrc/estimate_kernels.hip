@@ -262,6 +262,8 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
         n.kc = ((uint32_t)a << 31) | (uint32_t)(own & 0x7FFFFFFFull);
         n.mu = (int64_t)(uint64_t)e.mu;
         n.vm = (int64_t)((uint64_t)e.v * (uint64_t)e.mu);
+        n.run_lo = 0;  // set below
+        n.pad = 0;
         outn[pos] = n;
       }
       // the list is ascending in |v|: its zero counters form a prefix, and
@@ -275,6 +277,34 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
         if (first) B.prep_z[slot_row] = pos;
       } else if (pos == L - 1) {
         B.prep_z[slot_row] = L;
+      }
+    }
+    if (m == 2) {
+      // runs of equal child: each element gets the lowest position of its
+      // run (a max-scan of run starts over contiguous thread segments)
+      __syncthreads();
+      int *shi = reinterpret_cast<int *>(sh);
+      const int seg = (L + kNodeThreads - 1) / kNodeThreads;
+      const int s0 = min(L, (int)threadIdx.x * seg);
+      const int s1 = min(L, s0 + seg);
+      auto starts_run = [&](int p) {
+        return p == 0 || (merged[p] >> 16) != (merged[p - 1] >> 16);
+      };
+      int last = -1;
+      for (int p = s0; p < s1; ++p)
+        if (starts_run(p)) last = p;
+      shi[threadIdx.x] = last;
+      __syncthreads();
+      for (int off = 1; off < kNodeThreads; off <<= 1) {
+        const int o = threadIdx.x >= off ? shi[threadIdx.x - off] : -1;
+        __syncthreads();
+        shi[threadIdx.x] = max(shi[threadIdx.x], o);
+        __syncthreads();
+      }
+      int cur = threadIdx.x > 0 ? shi[threadIdx.x - 1] : -1;
+      for (int p = s0; p < s1; ++p) {
+        if (starts_run(p)) cur = p;
+        outn[p].run_lo = cur;
       }
     }
     return;
@@ -377,40 +407,37 @@ __device__ __forceinline__ u128 sat_mul63(u128 a, uint64_t b) {
 // in descending kappa, a maximal run of one child's elements sees the other
 // child's running sum fixed, so the run's terms collapse to
 // (sum over the run of v * mu) * A_other: one 64 x 64 -> 128-bit product per
-// run instead of one per element.  Within a run the lane's conditioned
-// message is mu = M if the element ranks below the cut element, else the
-// constant C(J), so the run sum is (sum of v*M over the elements below) +
-// C(J) * (sum of v over the others): no multiply per element.  The child of
-// an element is wave-uniform; its per-child state is picked with selects
-// (no branch per element, no indexed registers).
-struct FastState {
-  int64_t A0, At;    // running sums: child 0's messages, both children's
-  int64_t C0, C1;    // cut constants C(J) of child slots 0 and 1
-  uint32_t kf0, kf1; // element below the cut element iff its key < kf
-  int64_t xl;        // run: sum of v*M over the elements below
-  int32_t vh;        // run: sum of v over the others
-  uint32_t prev;     // child slot of the current run (uniform)
+// run instead of one per element (counters of the apex take few distinct
+// magnitudes, and ties go to the lower edge id, so runs are long).  The
+// runs are found once by the merge (run_lo), so the sweep loops over runs
+// and, inside one, over elements with no per-element branch.  Within a run
+// the lane's conditioned message is mu = M if the element ranks below the
+// cut element, else the constant C(J); with a lane mask m for "below", the
+// run keeps sum(m & M), sum(m & v*M), sum(m & v) and count(m), next to the
+// run's plain sum of v and length (wave-uniform, scalar), and rebuilds
+//   sum of v * mu = sum(m & v*M) + C * (sum v - sum(m & v))
+//   sum of mu     = sum(m & M)   + C * (length - count(m))
+// at its end: per element one compare, and AND / add operations only.
+struct FastRun {
+  int64_t mb, xb;      // sums of M and of v*M over the elements below
+  int32_t vb, nb;      // sum of v and count over the elements below
+  int32_t vrun, nrun;  // sum of v and length (uniform)
 };
 
-__device__ __forceinline__ void fast_step(FastState &s, int32_t v, uint32_t kc,
-                                          int64_t mu0, int64_t vm, u128 &G) {
-  const uint32_t c = kc >> 31;
-  if (c != s.prev) {  // the run of child `prev` ends; A_other = A_c
-    const int64_t cown = s.prev ? s.C1 : s.C0;
-    const int64_t Ac = c ? s.At - s.A0 : s.A0;
-    G += mul_s64_s64(s.xl + cown * (int64_t)s.vh, Ac);
-    s.xl = 0;
-    s.vh = 0;
-    s.prev = c;
-  }
-  const uint32_t kf = c ? s.kf1 : s.kf0;
-  const int64_t cc = c ? s.C1 : s.C0;
-  const bool below = (kc & 0x7FFFFFFFu) < kf;
-  const int64_t mu = below ? mu0 : cc;
-  s.At += mu;
-  s.A0 += c ? 0 : mu;
-  s.xl += below ? vm : 0;
-  s.vh += below ? 0 : v;
+__device__ __forceinline__ void fast_elem(FastRun &r, uint32_t kf, int32_t v,
+                                          uint32_t kc, int64_t mu0,
+                                          int64_t vm) {
+  // all-ones iff key < kf (both below 2^31); opaque, so that the masking
+  // stays AND instead of becoming per-lane selects of scalar operands
+  int32_t m = (int32_t)((kc & 0x7FFFFFFFu) - kf) >> 31;
+  __asm__("" : "+v"(m));
+  const uint64_t m64 = ((uint64_t)(uint32_t)m << 32) | (uint32_t)m;
+  r.mb += (int64_t)((uint64_t)mu0 & m64);
+  r.xb += (int64_t)((uint64_t)vm & m64);
+  r.vb += (int32_t)((uint32_t)v & (uint32_t)m);
+  r.nb -= m;
+  r.vrun += v;
+  r.nrun += 1;
 }
 
 __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
@@ -469,51 +496,63 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
     ConstElemN *el = (ConstElemN *)(B.prepn + slot_row * (size_t)B.Lprep);
     // child slot -> its side state; key < kf  <=>  kappa below the cut
     // element's (ties in |v| go to the lower edge id)
-    FastState fs;
+    int64_t C0, C1, A0 = 0, A1 = 0;
+    uint32_t kf0, kf1;
     {
       uint32_t kf[2];
 #pragma unroll
       for (int e = 0; e < 2; ++e)
         kf[e] = (uint32_t)qabs[e] + (T.cut_peid[e] < T.cut_eid ? 1u : 0u);
       const int e0 = cu == 0 ? 0 : 1;  // cut endpoint in child slot 0
-      fs.kf0 = kf[e0];
-      fs.kf1 = kf[1 - e0];
-      fs.C0 = (int64_t)(uint64_t)cval[e0];
-      fs.C1 = (int64_t)(uint64_t)cval[1 - e0];
+      kf0 = kf[e0];
+      kf1 = kf[1 - e0];
+      C0 = (int64_t)(uint64_t)cval[e0];
+      C1 = (int64_t)(uint64_t)cval[1 - e0];
     }
-    fs.A0 = fs.At = 0;
-    fs.xl = 0;
-    fs.vh = 0;
-    fs.prev = 0;
     constexpr int kGroup = 8;
     int pos = T.L - 1;
-    for (; pos - (kGroup - 1) >= z; pos -= kGroup) {
-      int32_t v[kGroup];
-      uint32_t kc[kGroup];
-      int64_t mu[kGroup], vm[kGroup];
+    while (pos >= z) {
+      const uint32_t c = el[pos].kc >> 31;  // the run's child (uniform)
+      const int lo = max(el[pos].run_lo, z);
+      const uint32_t kf = c ? kf1 : kf0;
+      FastRun r;
+      r.mb = r.xb = 0;
+      r.vb = r.nb = 0;
+      r.vrun = r.nrun = 0;
+      for (; pos - (kGroup - 1) >= lo; pos -= kGroup) {
+        int32_t v[kGroup];
+        uint32_t kc[kGroup];
+        int64_t mu[kGroup], vm[kGroup];
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u) {
-        ConstElemN &r = el[pos - u];
-        v[u] = r.v;
-        kc[u] = r.kc;
-        mu[u] = r.mu;
-        vm[u] = r.vm;
+        for (int u = 0; u < kGroup; ++u) {
+          ConstElemN &e = el[pos - u];
+          v[u] = e.v;
+          kc[u] = e.kc;
+          mu[u] = e.mu;
+          vm[u] = e.vm;
+        }
+        // issue the whole group's scalar loads before the first use
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+          __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) fast_elem(r, kf, v[u], kc[u], mu[u], vm[u]);
       }
-      // issue the whole group's scalar loads before the first use
-#pragma unroll
-      for (int u = 0; u < kGroup; ++u)
-        __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
-#pragma unroll
-      for (int u = 0; u < kGroup; ++u) fast_step(fs, v[u], kc[u], mu[u], vm[u], G);
-    }
-    for (; pos >= z; --pos) {
-      ConstElemN &r = el[pos];
-      fast_step(fs, r.v, r.kc, r.mu, r.vm, G);
-    }
-    {  // close the last run
-      const int64_t cown = fs.prev ? fs.C1 : fs.C0;
-      const int64_t Aoth = fs.prev ? fs.A0 : fs.At - fs.A0;
-      G += mul_s64_s64(fs.xl + cown * (int64_t)fs.vh, Aoth);
+      for (; pos >= lo; --pos) {
+        ConstElemN &e = el[pos];
+        fast_elem(r, kf, e.v, e.kc, e.mu, e.vm);
+      }
+      // close the run: its terms times the other child's running sum
+      const int64_t cc = c ? C1 : C0;
+      const int64_t x = r.xb + cc * (int64_t)(r.vrun - r.vb);
+      const int64_t arun = r.mb + cc * (int64_t)(r.nrun - r.nb);
+      if (c) {
+        G += mul_s64_s64(x, A0);
+        A1 += arun;
+      } else {
+        G += mul_s64_s64(x, A1);
+        A0 += arun;
+      }
     }
   } else if (narrow) {
     typedef const __attribute__((address_space(4))) TriElem ConstElem;
