@@ -440,13 +440,179 @@ __device__ __forceinline__ void fast_elem(FastRun &r, uint32_t kf, int32_t v,
   r.nrun += 1;
 }
 
+typedef const __attribute__((address_space(4))) TriTask ConstTask;
+typedef const __attribute__((address_space(4))) TriElemN ConstElemN;
+
+enum { kTriFast = 0, kTriNarrow = 1, kTriWide = 2 };
+
+// Arithmetic of one triangle task (the same in every lane and block).
+// Narrow arithmetic is exact when: every message value of child c is
+// bounded by B_c = prod of n_sel over c's subtree (the L1 norm of a sketch
+// row is at most n_sel), each A_c by (w + 1) B_c, and the apex's counters by
+// n_sel(apex); when all of these stay below 2^62, messages and A are int64
+// and only the running sum G needs 128 bits.  The compact two-child sweep
+// also needs every table's n_sel below 2^30 (counters, keys and thresholds
+// then fit 32 bits).
+__device__ int tri_path(ConstTask &T, const EstBuffers &B) {
+  bool narrow = true, small = true;
+  const u128 lim = (u128)1 << 62;
+  const int64_t nr = B.n_sel[T.root_table];
+  const uint64_t nroot = nr < 0 ? 0 : (uint64_t)nr;
+  small = nroot < (1ull << 30);
+  for (int c = 0; c < T.m; ++c) {
+    u128 bc = 1;
+    for (uint64_t s = T.child_tables[c]; s; s &= s - 1) {
+      const int64_t ns = B.n_sel[__builtin_ctzll(s)];
+      const uint64_t f = ns < 0 ? 0 : (uint64_t)ns;
+      small = small && f < (1ull << 30);
+      bc = sat_mul63(bc, f);
+    }
+    if (bc * (u128)(B.w + 1) >= lim || bc * (u128)nroot >= lim) narrow = false;
+  }
+  if (!narrow) return kTriWide;
+  return small && T.m == 2 ? kTriFast : kTriNarrow;
+}
+
+// Two-child apexes: grid (n_tri, d, ceil(w / kLaneThreads)), kFastSegs
+// segments of the sweep per block (segment s = threads s * kLaneThreads ..).
+// Cutting the descending sweep into segments is exact: a segment's runs see
+// the other child's running sum of the earlier segments plus their own, so
+//   G = sum_s [ G_s + A0(before s) * X1_s + A1(before s) * X0_s ]
+// with X_c the segment's sum of the run terms of child c (v * mu summed).
+constexpr int kFastSegs = 4;
+
+struct SegOut {
+  u128 G;
+  int64_t A0, A1, X0, X1;
+};
+
+__global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
+    const TriTask *tasks, EstBuffers B) {
+  __shared__ SegOut so[kFastSegs][kLaneThreads];
+  ConstTask &T = *((ConstTask *)tasks + blockIdx.x);
+  if (tri_path(T, B) != kTriFast) return;  // uniform: tri_lane_kernel's block
+  const int row = blockIdx.y;
+  const int lane = threadIdx.x % kLaneThreads;
+  const int seg = threadIdx.x / kLaneThreads;
+  const int J = blockIdx.z * kLaneThreads + lane;
+  const bool active = J < B.w;
+  const int Jc = active ? J : 0;
+  const size_t slot_row = (size_t)T.prep_slot * B.d + row;
+  const int z = B.prep_z[slot_row];  // the sweep ends at the zero prefix
+  const int len = T.L - z;
+  const int top = T.L - 1 - (int)((int64_t)len * seg / kFastSegs);
+  const int bottom = T.L - (int)((int64_t)len * (seg + 1) / kFastSegs);
+
+  // child slot 0 / 1 state; key < kf  <=>  kappa below the cut element's
+  // (ties in |v| go to the lower edge id)
+  uint32_t kf0, kf1;
+  int64_t C0, C1;
+  {
+    uint32_t kf[2];
+    int64_t cv[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      kf[e] = (uint32_t)abs_u64(counter_at(B, T.cut_side[e], row, Jc)) +
+              (T.cut_peid[e] < T.cut_eid ? 1u : 0u);
+      cv[e] = (int64_t)(uint64_t)msg_of(B, T.cut_cmsg[e], row)[Jc];
+    }
+    const int e0 = T.cut_child[0] == 0 ? 0 : 1;  // cut endpoint in slot 0
+    kf0 = kf[e0];
+    kf1 = kf[1 - e0];
+    C0 = cv[e0];
+    C1 = cv[1 - e0];
+  }
+  ConstElemN *el = (ConstElemN *)(B.prepn + slot_row * (size_t)B.Lprep);
+  int64_t A0 = 0, A1 = 0, X0 = 0, X1 = 0;
+  u128 G = 0;
+  constexpr int kGroup = 4;
+  int pos = top;
+  while (pos >= bottom) {
+    const uint32_t c = el[pos].kc >> 31;  // the run's child (uniform)
+    const int lo = max(el[pos].run_lo, bottom);
+    const uint32_t kf = c ? kf1 : kf0;
+    FastRun r;
+    r.mb = r.xb = 0;
+    r.vb = r.nb = 0;
+    r.vrun = r.nrun = 0;
+    for (; pos - (kGroup - 1) >= lo; pos -= kGroup) {
+      int32_t v[kGroup];
+      uint32_t kc[kGroup];
+      int64_t mu[kGroup], vm[kGroup];
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        ConstElemN &e = el[pos - u];
+        v[u] = e.v;
+        kc[u] = e.kc;
+        mu[u] = e.mu;
+        vm[u] = e.vm;
+      }
+      // issue the whole group's scalar loads before the first use
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u)
+        __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) fast_elem(r, kf, v[u], kc[u], mu[u], vm[u]);
+    }
+    for (; pos >= lo; --pos) {
+      ConstElemN &e = el[pos];
+      fast_elem(r, kf, e.v, e.kc, e.mu, e.vm);
+    }
+    // close the run: its terms times the other child's running sum
+    const int64_t cc = c ? C1 : C0;
+    const int64_t x = r.xb + cc * (int64_t)(r.vrun - r.vb);
+    const int64_t arun = r.mb + cc * (int64_t)(r.nrun - r.nb);
+    if (c) {
+      G += mul_s64_s64(x, A0);
+      A1 += arun;
+      X1 += x;
+    } else {
+      G += mul_s64_s64(x, A1);
+      A0 += arun;
+      X0 += x;
+    }
+  }
+  SegOut &mine = so[seg][lane];
+  mine.G = G;
+  mine.A0 = A0;
+  mine.A1 = A1;
+  mine.X0 = X0;
+  mine.X1 = X1;
+  __syncthreads();
+  u128 *red = reinterpret_cast<u128 *>(&so[1][0]);  // free once combined
+  u128 g = 0;
+  if (seg == 0) {
+    int64_t a0 = 0, a1 = 0;
+    for (int s2 = 0; s2 < kFastSegs; ++s2) {
+      const SegOut &o = so[s2][lane];
+      g += o.G + mul_s64_s64(a0, o.X1) + mul_s64_s64(a1, o.X0);
+      a0 += o.A0;
+      a1 += o.A1;
+    }
+  }
+  __syncthreads();
+  if (seg == 0) red[lane] = active ? g : (u128)0;
+  __syncthreads();
+  for (int off = kLaneThreads / 2; off > 0; off >>= 1) {
+    if (seg == 0 && lane < off) red[lane] += red[lane + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    B.partial[((size_t)T.partial_slot + blockIdx.z) * B.d + row] = red[0];
+}
+
+// Other triangles (more apex children, or bounds beyond the compact
+// sweep): grid (n_tri, d, ceil(w / kLaneThreads)); blocks of two-child
+// tasks that tri_fast_kernel handles return at once.
 __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
     const TriTask *tasks, EstBuffers B) {
   __shared__ u128 red[kLaneThreads];
   // the task is the same for every lane: read it through the constant
   // address space so its fields live in scalar registers
-  typedef const __attribute__((address_space(4))) TriTask ConstTask;
   ConstTask &T = *((ConstTask *)tasks + blockIdx.x);
+  const int path = tri_path(T, B);
+  if (path == kTriFast) return;  // uniform: tri_fast_kernel's block
+  const bool narrow = path == kTriNarrow;
   const int row = blockIdx.y;
   const int J = blockIdx.z * kLaneThreads + threadIdx.x;
   const bool active = J < B.w;
@@ -464,97 +630,9 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
     cval[e] = msg_of(B, T.cut_cmsg[e], row)[Jc];
   }
 
-  // Narrow arithmetic when it is exact: every message value of child c is
-  // bounded by B_c = prod of n_sel over c's subtree (the L1 norm of a
-  // sketch row is at most n_sel), each A_c by (w + 1) B_c, and the apex's
-  // counters by n_sel(apex).  When all of these stay below 2^62, messages
-  // and A are int64 and only the running sum G needs 128 bits.  The compact
-  // two-child sweep also needs every table's n_sel below 2^30 (counters,
-  // keys and thresholds then fit 32 bits).
-  bool narrow = true, small = true;
-  {
-    const u128 lim = (u128)1 << 62;
-    const int64_t nr = B.n_sel[T.root_table];
-    const uint64_t nroot = nr < 0 ? 0 : (uint64_t)nr;
-    small = nroot < (1ull << 30);
-    for (int c = 0; c < m; ++c) {
-      u128 bc = 1;
-      for (uint64_t s = T.child_tables[c]; s; s &= s - 1) {
-        const int64_t ns = B.n_sel[__builtin_ctzll(s)];
-        const uint64_t f = ns < 0 ? 0 : (uint64_t)ns;
-        small = small && f < (1ull << 30);
-        bc = sat_mul63(bc, f);
-      }
-      if (bc * (u128)(B.w + 1) >= lim || bc * (u128)nroot >= lim) narrow = false;
-    }
-  }
-
   u128 G = 0;
   constexpr int kUnroll = 4;
-  if (narrow && small && m == 2) {
-    typedef const __attribute__((address_space(4))) TriElemN ConstElemN;
-    ConstElemN *el = (ConstElemN *)(B.prepn + slot_row * (size_t)B.Lprep);
-    // child slot -> its side state; key < kf  <=>  kappa below the cut
-    // element's (ties in |v| go to the lower edge id)
-    int64_t C0, C1, A0 = 0, A1 = 0;
-    uint32_t kf0, kf1;
-    {
-      uint32_t kf[2];
-#pragma unroll
-      for (int e = 0; e < 2; ++e)
-        kf[e] = (uint32_t)qabs[e] + (T.cut_peid[e] < T.cut_eid ? 1u : 0u);
-      const int e0 = cu == 0 ? 0 : 1;  // cut endpoint in child slot 0
-      kf0 = kf[e0];
-      kf1 = kf[1 - e0];
-      C0 = (int64_t)(uint64_t)cval[e0];
-      C1 = (int64_t)(uint64_t)cval[1 - e0];
-    }
-    constexpr int kGroup = 8;
-    int pos = T.L - 1;
-    while (pos >= z) {
-      const uint32_t c = el[pos].kc >> 31;  // the run's child (uniform)
-      const int lo = max(el[pos].run_lo, z);
-      const uint32_t kf = c ? kf1 : kf0;
-      FastRun r;
-      r.mb = r.xb = 0;
-      r.vb = r.nb = 0;
-      r.vrun = r.nrun = 0;
-      for (; pos - (kGroup - 1) >= lo; pos -= kGroup) {
-        int32_t v[kGroup];
-        uint32_t kc[kGroup];
-        int64_t mu[kGroup], vm[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-          ConstElemN &e = el[pos - u];
-          v[u] = e.v;
-          kc[u] = e.kc;
-          mu[u] = e.mu;
-          vm[u] = e.vm;
-        }
-        // issue the whole group's scalar loads before the first use
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-          __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) fast_elem(r, kf, v[u], kc[u], mu[u], vm[u]);
-      }
-      for (; pos >= lo; --pos) {
-        ConstElemN &e = el[pos];
-        fast_elem(r, kf, e.v, e.kc, e.mu, e.vm);
-      }
-      // close the run: its terms times the other child's running sum
-      const int64_t cc = c ? C1 : C0;
-      const int64_t x = r.xb + cc * (int64_t)(r.vrun - r.vb);
-      const int64_t arun = r.mb + cc * (int64_t)(r.nrun - r.nb);
-      if (c) {
-        G += mul_s64_s64(x, A0);
-        A1 += arun;
-      } else {
-        G += mul_s64_s64(x, A1);
-        A0 += arun;
-      }
-    }
-  } else if (narrow) {
+  if (narrow) {
     typedef const __attribute__((address_space(4))) TriElem ConstElem;
     ConstElem *el = (ConstElem *)(B.prep + slot_row * (size_t)B.Lprep);
     uint64_t kf[2];
@@ -758,6 +836,11 @@ hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
 
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
                            const EstBuffers &B, hipStream_t st) {
+  // each (task, row, z) block does its work in exactly one of the two
+  hipLaunchKernelGGL(tri_fast_kernel, dim3(n, B.d, zblocks),
+                     dim3(kLaneThreads * kFastSegs), 0, st, tasks, B);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(tri_lane_kernel, dim3(n, B.d, zblocks),
                      dim3(kLaneThreads), 0, st, tasks, B);
   return hipGetLastError();
