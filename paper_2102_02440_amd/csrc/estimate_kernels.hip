@@ -493,7 +493,9 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   if (tri_path(T, B) != kTriFast) return;  // uniform: tri_lane_kernel's block
   const int row = blockIdx.y;
   const int lane = threadIdx.x % kLaneThreads;
-  const int seg = threadIdx.x / kLaneThreads;
+  // whole waves share a segment: make that visible to the compiler, so the
+  // sweep's positions and element loads stay scalar
+  const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / kLaneThreads);
   const int J = blockIdx.z * kLaneThreads + lane;
   const bool active = J < B.w;
   const int Jc = active ? J : 0;
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   ConstElemN *el = (ConstElemN *)(B.prepn + slot_row * (size_t)B.Lprep);
   int64_t A0 = 0, A1 = 0, X0 = 0, X1 = 0;
   u128 G = 0;
-  constexpr int kGroup = 4;
+  constexpr int kGroup = 8;
   int pos = top;
   while (pos >= bottom) {
     const uint32_t c = el[pos].kc >> 31;  // the run's child (uniform)
