@@ -89,6 +89,15 @@ __device__ __forceinline__ uint32_t bucket_of(uint64_t g, const BucketMod &m) {
   return (uint32_t)r;
 }
 
+// Canonical residues are only needed through their low bits: for
+// f = fold61(r) (< 2^61 + 8), the residue is f - p = f - 2^61 + 1 when
+// f >= p, else f; 2^61 is a multiple of 2 and of any power-of-two w, so its
+// low bits are those of f + (f >= p).
+__device__ __forceinline__ uint32_t low_of_residue(uint64_t r) {
+  const uint64_t f = fold61(r);
+  return (uint32_t)f + (f >= kP61 ? 1u : 0u);
+}
+
 // sign (+1/-1) and bucket of one field element under one row's seeds.
 template <bool X32>
 __device__ __forceinline__ void hash_xi_h(uint64_t x, const RowSeeds &s,
@@ -107,12 +116,9 @@ __device__ __forceinline__ void hash_xi_h(uint64_t x, const RowSeeds &s,
     v = madd61_x61(v, x, s.a0);
     g = madd61_x61(s.b1, x, s.b0);
   }
-  v = canon61(v);
-  g = canon61(g);
-  sign = 1 - 2 * (int32_t)(v & 1);
-  bucket = bucket_of(g, m);
+  sign = 1 - 2 * (int32_t)(low_of_residue(v) & 1u);
+  bucket = m.pow2 ? (low_of_residue(g) & m.mask) : bucket_of(canon61(g), m);
 }
-
 // ---------------------------------------------------------------------
 // 128-bit two's complement (wrapping) helpers
 // ---------------------------------------------------------------------

@@ -218,16 +218,33 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
       const RowSeeds sd = job.seeds(sl);
       const BucketMod bm = job.bm();
       int32_t *c = cnt + (size_t)(sl - sb) * w;
+      // one uniform branch when no key of the wave needs the 61-bit path
+      // (every non-negative int32 key)
+      bool wide_key = false;
 #pragma unroll
-      for (int k = 0; k < kRowsPerThread; ++k) {
-        if (!valid[k]) continue;
-        int32_t sign;
-        uint32_t b;
-        if ((x[k] >> 32) == 0)
+      for (int k = 0; k < kRowsPerThread; ++k)
+        wide_key = wide_key || (valid[k] && (x[k] >> 32) != 0);
+      if (!__any(wide_key)) {
+#pragma unroll
+        for (int k = 0; k < kRowsPerThread; ++k) {
+          if (!valid[k]) continue;
+          int32_t sign;
+          uint32_t b;
           hash_xi_h<true>(x[k], sd, bm, sign, b);
-        else
-          hash_xi_h<false>(x[k], sd, bm, sign, b);
-        atomicAdd(&c[b], sign);
+          atomicAdd(&c[b], sign);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < kRowsPerThread; ++k) {
+          if (!valid[k]) continue;
+          int32_t sign;
+          uint32_t b;
+          if ((x[k] >> 32) == 0)
+            hash_xi_h<true>(x[k], sd, bm, sign, b);
+          else
+            hash_xi_h<false>(x[k], sd, bm, sign, b);
+          atomicAdd(&c[b], sign);
+        }
       }
     }
     __syncthreads();  // queue and s_qn are reused by the next tile
