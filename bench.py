@@ -327,7 +327,9 @@ def run_large(args):
                                   "int64" % n, "selected_rows": sel,
                       "parallelism": "single-gpu"},
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                        "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                        "traffic": measured_traffic("wide_compact_traffic_large.md",
+                                                    SCAN_SOURCES),
                         "kernel": "wide_compact", "alg_bytes_per_step": alg,
                         "kernel_ms_per_step": k_s * 1e3,
                         "launches_per_step": kn / args.steps,
