@@ -123,7 +123,10 @@ compass_status compass_sketch_build(int64_t n_rows,
  * is "first" in the merge tie rule of Section 5.2.
  * sketch[2e+0] = counters of table edge_u[e] on edge e, sketch[2e+1] = of
  * table edge_v[e]; both built with the same seeds.  n_selected[t] = exact
- * selected cardinality of table t (device). */
+ * selected cardinality of table t (device).  It must also bound the sum of
+ * absolute values of every row of t's sketches (always true of sketches
+ * built from those selected rows): the estimate picks 64-bit arithmetic
+ * where these bounds prove it exact, and 128-bit arithmetic otherwise. */
 typedef struct {
     int32_t n_tables;            /* 1..64 */
     int32_t n_edges;             /* 0..64 */
