@@ -353,8 +353,10 @@ extern "C" compass_status compass_sketch_build(
     const int64_t cap = std::min<int64_t>(
         n_rows, std::max<int64_t>((int64_t)1 << 25,
                                   ((int64_t)1 << 32) / (8 * n_sketches)));
-    const int ranges = (int)(((size_t)w * 4 + kLdsBudget - 1) / kLdsBudget);
-    int chunks = std::max(1, (int)((4ll * ds->n_cu + S * ranges - 1) / (S * ranges)));
+    // phase B: bucket ranges of at most 65536 (16-bit pairs in 128 KiB of
+    // LDS); chunks so that about two whole waves of one-per-CU workgroups run
+    const int ranges = (w + 65535) / 65536;
+    const int chunks = std::max(1, (int)(2ll * ds->n_cu / (S * ranges)));
     const size_t b_surv = (size_t)n_sketches * cap * 8;
     const size_t b_slab = ((size_t)chunks * S * w * 4 + 255) & ~(size_t)255;
     void *scr;

@@ -161,42 +161,76 @@ __global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
 }
 
 // Wide sketches, phase B: block (slice, bucket range, chunk) hashes its
-// chunk of the compacted survivors of the slice's sketch and keeps the
-// buckets of its range in LDS, then writes them to its slab row.  Every
-// range block recomputes the hashes (the price of a range that fits LDS).
+// chunk of the compacted survivors of the slice's sketch into LDS counters
+// for a range of up to 65536 buckets, two 16-bit counters per 32-bit word
+// (bucket j of the range adds +-1 to the low half or +-65536 to the word,
+// i.e. +-1 to the high half: the word holds lo + 65536 hi mod 2^32, which
+// gives back lo and hi exactly while both stay within [-32767, 32767]).  The
+// survivors are taken 32767 at a time, so no half can leave that range;
+// after each piece every lane moves its 2 x kWidePairsPerLane counters into
+// int32 registers and clears them.  One hash per update even at w = 65536.
+constexpr int kWidePiece = 32767;
+constexpr int kWidePairsPerLane = 32;   // 32768 words / 1024 lanes
+constexpr int kWideRange = 2 * kWidePairsPerLane * kBuildThreads;  // 65536
+
 __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
     const uint64_t *__restrict__ surv, int64_t cap,
     const unsigned long long *__restrict__ count,
     const RowSeeds *__restrict__ seeds, BucketMod bm, int32_t d,
     int32_t n_slices, int32_t ranges, int32_t chunks,
     int32_t *__restrict__ slab) {
-  extern __shared__ int32_t cnt[];
+  extern __shared__ uint32_t pairs[];
   const int sl = blockIdx.x % n_slices;
   const int r = (blockIdx.x / n_slices) % ranges;
   const int k = blockIdx.x / (n_slices * ranges);
   const int w = (int)bm.w;
-  const int wr = (w + ranges - 1) / ranges;
+  const int wr = (w + ranges - 1) / ranges;  // <= kWideRange
   const int lo = r * wr, hi = min(w, lo + wr);
-  for (int j = threadIdx.x; j < hi - lo; j += kBuildThreads) cnt[j] = 0;
-  __syncthreads();
+  const int nwords = (hi - lo + 1) / 2;
+  for (int j = threadIdx.x; j < nwords; j += kBuildThreads) pairs[j] = 0;
+  int32_t acc[2 * kWidePairsPerLane];
+#pragma unroll
+  for (int i = 0; i < 2 * kWidePairsPerLane; ++i) acc[i] = 0;
   const int64_t n = (int64_t)*count;
   const int64_t a = n * k / chunks, b = n * (k + 1) / chunks;
   const int s = sl / d;
   const RowSeeds sd = seeds[sl];
   const uint64_t *x = surv + (int64_t)s * cap;
-  for (int64_t i = a + threadIdx.x; i < b; i += kBuildThreads) {
-    const uint64_t xi = x[i];
-    int32_t sign;
-    uint32_t bk;
-    if ((xi >> 32) == 0)
-      hash_xi_h<true>(xi, sd, bm, sign, bk);
-    else
-      hash_xi_h<false>(xi, sd, bm, sign, bk);
-    if ((int)bk >= lo && (int)bk < hi) atomicAdd(&cnt[bk - lo], sign);
+  for (int64_t p0 = a; p0 < b; p0 += kWidePiece) {
+    const int64_t p1 = min(b, p0 + kWidePiece);
+    __syncthreads();  // cleared words
+    for (int64_t i = p0 + threadIdx.x; i < p1; i += kBuildThreads) {
+      const uint64_t xi = x[i];
+      int32_t sign;
+      uint32_t bk;
+      if ((xi >> 32) == 0)
+        hash_xi_h<true>(xi, sd, bm, sign, bk);
+      else
+        hash_xi_h<false>(xi, sd, bm, sign, bk);
+      const int jj = (int)bk - lo;
+      if (jj >= 0 && (int)bk < hi)
+        atomicAdd(&pairs[jj >> 1], (jj & 1) ? (uint32_t)sign << 16 : (uint32_t)sign);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kWidePairsPerLane; ++i) {
+      const int wi = threadIdx.x + i * kBuildThreads;
+      if (wi < nwords) {
+        const uint32_t word = pairs[wi];
+        const int32_t l16 = (int32_t)(int16_t)(word & 0xFFFFu);
+        acc[2 * i] += l16;
+        acc[2 * i + 1] += (int32_t)(word - (uint32_t)l16) >> 16;
+        pairs[wi] = 0;
+      }
+    }
   }
-  __syncthreads();
   int32_t *dst = slab + ((int64_t)k * n_slices + sl) * w + lo;
-  for (int j = threadIdx.x; j < hi - lo; j += kBuildThreads) dst[j] = cnt[j];
+#pragma unroll
+  for (int i = 0; i < kWidePairsPerLane; ++i) {
+    const int wi = threadIdx.x + i * kBuildThreads;
+    if (2 * wi < hi - lo) dst[2 * wi] = acc[2 * i];
+    if (2 * wi + 1 < hi - lo) dst[2 * wi + 1] = acc[2 * i + 1];
+  }
 }
 
 hipError_t launch_wide_compact(const BuildParams &P, uint64_t *surv,
@@ -215,7 +249,7 @@ hipError_t launch_wide_hash(const uint64_t *surv, int64_t cap,
                             int ranges, int chunks, int32_t *slab,
                             hipStream_t st) {
   const int w = (int)bm.w;
-  const size_t lds = (size_t)((w + ranges - 1) / ranges) * 4;
+  const size_t lds = (size_t)(((w + ranges - 1) / ranges + 1) / 2) * 4;
   hipLaunchKernelGGL(wide_hash_kernel, dim3(n_slices * ranges * chunks),
                      dim3(kBuildThreads), lds, st, surv, cap,
                      reinterpret_cast<const unsigned long long *>(count),
