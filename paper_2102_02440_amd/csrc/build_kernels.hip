@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
         queue[qtot + r] = bias + r;
       qtot += nt;
     } else {
-      qtot = compact_tile<DirectJob, kBuildRowsPerThread>(
+      qtot = compact_tile<DirectJob>(
           job, base, nt, P.n_preds, queue, &s_qn, qtot, bias);
     }
     const bool last = base + stride >= row_end;
@@ -249,7 +249,9 @@ hipError_t launch_wide_hash(const uint64_t *surv, int64_t cap,
                             int ranges, int chunks, int32_t *slab,
                             hipStream_t st) {
   const int w = (int)bm.w;
-  const size_t lds = (size_t)(((w + ranges - 1) / ranges + 1) / 2) * 4;
+  const int wr = (w + ranges - 1) / ranges;
+  if (wr > kWideRange) return hipErrorInvalidValue;  // 16-bit pairs, 128 KiB
+  const size_t lds = (size_t)((wr + 1) / 2) * 4;
   hipLaunchKernelGGL(wide_hash_kernel, dim3(n_slices * ranges * chunks),
                      dim3(kBuildThreads), lds, st, surv, cap,
                      reinterpret_cast<const unsigned long long *>(count),
