@@ -350,9 +350,11 @@ extern "C" compass_status compass_sketch_build(
     // reduction adds the partials into the counters (zeroed above unless
     // accumulating).
     // (survivor buffer at most 4 GiB: 8 bytes per sketch per row)
+    // (batches start on tile boundaries, so 16-byte column loads align)
     const int64_t cap = std::min<int64_t>(
         n_rows, std::max<int64_t>((int64_t)1 << 25,
-                                  ((int64_t)1 << 32) / (8 * n_sketches)));
+                                  ((int64_t)1 << 32) / (8 * n_sketches)) /
+                    kBuildTile * kBuildTile);
     // phase B: bucket ranges of at most 65536 (16-bit pairs in 128 KiB of
     // LDS); chunks so that about two whole waves of one-per-CU workgroups run
     const int ranges = (w + 65535) / 65536;
