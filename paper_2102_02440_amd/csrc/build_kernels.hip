@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
         queue[qtot + r] = bias + r;
       qtot += nt;
     } else {
-      qtot = compact_tile<DirectJob>(
+      qtot = compact_tile<DirectJob, kBuildRowsPerThread>(
           job, base, nt, P.n_preds, queue, &s_qn, qtot, bias);
     }
     const bool last = base + stride >= row_end;

@@ -69,72 +69,49 @@ __device__ __forceinline__ void load_fields(const KeyDev &kd, int64_t base,
   }
 }
 
-// The 32-bit words of rows base + 4 * threadIdx.x + k (k < 4) of a
-// predicate column: one 16-byte load when all four rows lie in the tile and
-// the address is 16-byte aligned, else one load per row in the tile.
-__device__ __forceinline__ void load_pred4(const PredDev &p, int64_t base,
-                                           int nt, uint32_t (&v)[4]) {
-  const uint32_t *col = reinterpret_cast<const uint32_t *>(p.col) + base;
-  const int r0 = 4 * threadIdx.x;
-  if (r0 + 3 < nt && ((reinterpret_cast<uintptr_t>(col) & 15) == 0)) {
-    const uint4 q = *reinterpret_cast<const uint4 *>(col + r0);
-    v[0] = q.x;
-    v[1] = q.y;
-    v[2] = q.z;
-    v[3] = q.w;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = r0 + k < nt ? col[r0 + k] : 0u;
-  }
-}
-
 // Compacts the qualifying rows of tile [base, base + nt) into `queue`
 // (entries start .. start + count - 1, each the row offset plus `bias`;
 // unordered: the sums do not depend on order) and returns start + their
-// number.  Each lane evaluates four consecutive rows (16-byte column
-// loads); the first four predicate columns are loaded together before any
-// is evaluated, later ones one ahead of their evaluation.  With no
+// number.  Each predicate column is loaded for all of the thread's rows,
+// and before it is evaluated the next one is loaded too, so loads overlap
+// instead of waiting on the previous predicate's outcome.  With no
 // predicates every row qualifies; the queue is then not used and nt is
 // returned.  Every thread of the block must call it.
-template <class J>
+template <class J, int kRowsPerThread>
 __device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
                             int32_t *queue, int32_t *s_qn, int start = 0,
                             int bias = 0) {
-  static_assert(kBuildRowsPerThread == 4, "four rows per lane");
   if (n_preds == 0) return nt;
   if (threadIdx.x == 0) *s_qn = start;
-  const int r0 = 4 * threadIdx.x;
-  bool pass[4];
+  // predicate q + 1 is loaded before predicate q is evaluated
+  uint32_t cur[kRowsPerThread], nxt[kRowsPerThread];
+  bool pass[kRowsPerThread];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) pass[k] = r0 + k < nt;
-  uint32_t v[4][4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (q < n_preds) load_pred4(job.pred(q), base, nt, v[q]);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (q < n_preds) {
-      const PredDev &p = job.pred(q);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) pass[k] = pass[k] && eval_pred_raw(p, v[q][k]);
-    }
+  for (int k = 0; k < kRowsPerThread; ++k) {
+    const int r = threadIdx.x + k * kBuildThreads;
+    pass[k] = r < nt;
+    cur[k] = pass[k] ? load_pred_raw(job.pred(0), base + r) : 0u;
   }
-  if (n_preds > 4) {
-    uint32_t cur[4], nxt[4];
-    load_pred4(job.pred(4), base, nt, cur);
-    for (int q = 4; q < n_preds; ++q) {
-      if (q + 1 < n_preds) load_pred4(job.pred(q + 1), base, nt, nxt);
-      const PredDev &p = job.pred(q);
+  for (int q = 0; q < n_preds; ++q) {
+    if (q + 1 < n_preds) {
+      const PredDev &pn = job.pred(q + 1);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        pass[k] = pass[k] && eval_pred_raw(p, cur[k]);
-        cur[k] = nxt[k];
+      for (int k = 0; k < kRowsPerThread; ++k) {
+        const int r = threadIdx.x + k * kBuildThreads;
+        nxt[k] = r < nt ? load_pred_raw(pn, base + r) : 0u;
       }
+    }
+    const PredDev &p = job.pred(q);
+#pragma unroll
+    for (int k = 0; k < kRowsPerThread; ++k) {
+      pass[k] = pass[k] && eval_pred_raw(p, cur[k]);
+      cur[k] = nxt[k];
     }
   }
   __syncthreads();  // s_qn initialised
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kRowsPerThread; ++k) {
+    const int r = threadIdx.x + k * kBuildThreads;
     const uint64_t ballot = __ballot(pass[k]);
     const int lane = __lane_id();
     const uint32_t before = __builtin_amdgcn_mbcnt_hi(
@@ -144,7 +121,7 @@ __device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
     int off = 0;
     if (lane == 0 && total) off = atomicAdd(s_qn, total);
     off = __shfl(off, 0);
-    if (pass[k]) queue[off + before] = r0 + k + bias;
+    if (pass[k]) queue[off + before] = r + bias;
   }
   __syncthreads();
   return *s_qn;
@@ -180,7 +157,7 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
   bool have_pre = false;
   for (int64_t base = row0; base < row1; base += kTile) {
     const int nt = (int)min((int64_t)kTile, row1 - base);
-    const int qn = compact_tile<J>(job, base, nt, n_preds,
+    const int qn = compact_tile<J, kRowsPerThread>(job, base, nt, n_preds,
                                                    queue, s_qn);
     sel += (uint64_t)qn;
 
