@@ -199,17 +199,40 @@ __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
   for (int64_t p0 = a; p0 < b; p0 += kWidePiece) {
     const int64_t p1 = min(b, p0 + kWidePiece);
     __syncthreads();  // cleared words
-    for (int64_t i = p0 + threadIdx.x; i < p1; i += kBuildThreads) {
-      const uint64_t xi = x[i];
-      int32_t sign;
-      uint32_t bk;
-      if ((xi >> 32) == 0)
-        hash_xi_h<true>(xi, sd, bm, sign, bk);
-      else
-        hash_xi_h<false>(xi, sd, bm, sign, bk);
-      const int jj = (int)bk - lo;
-      if (jj >= 0 && (int)bk < hi)
-        atomicAdd(&pairs[jj >> 1], (jj & 1) ? (uint32_t)sign << 16 : (uint32_t)sign);
+    // four survivors per lane at a time: their hash chains interleave
+    for (int64_t i0 = p0 + threadIdx.x; i0 < p1; i0 += 4 * kBuildThreads) {
+      uint64_t xs[4];
+      bool ok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * kBuildThreads;
+        ok[u] = i < p1;
+        xs[u] = ok[u] ? x[i] : 0;
+      }
+      bool wide_key = false;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wide_key = wide_key || (xs[u] >> 32) != 0;
+      int32_t sign[4];
+      uint32_t bk[4];
+      if (!__any(wide_key)) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if ((xs[u] >> 32) == 0)
+            hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
+          else
+            hash_xi_h<false>(xs[u], sd, bm, sign[u], bk[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jj = (int)bk[u] - lo;
+        if (ok[u] && jj >= 0 && (int)bk[u] < hi)
+          atomicAdd(&pairs[jj >> 1],
+                    (jj & 1) ? (uint32_t)sign[u] << 16 : (uint32_t)sign[u]);
+      }
     }
     __syncthreads();
 #pragma unroll

@@ -225,14 +225,15 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
       for (int k = 0; k < kRowsPerThread; ++k)
         wide_key = wide_key || (valid[k] && (x[k] >> 32) != 0);
       if (!__any(wide_key)) {
+        // branch-free hashes (the four chains interleave), then the adds
+        int32_t sign[kRowsPerThread];
+        uint32_t b[kRowsPerThread];
 #pragma unroll
-        for (int k = 0; k < kRowsPerThread; ++k) {
-          if (!valid[k]) continue;
-          int32_t sign;
-          uint32_t b;
-          hash_xi_h<true>(x[k], sd, bm, sign, b);
-          atomicAdd(&c[b], sign);
-        }
+        for (int k = 0; k < kRowsPerThread; ++k)
+          hash_xi_h<true>(x[k], sd, bm, sign[k], b[k]);
+#pragma unroll
+        for (int k = 0; k < kRowsPerThread; ++k)
+          if (valid[k]) atomicAdd(&c[b[k]], sign[k]);
       } else {
 #pragma unroll
         for (int k = 0; k < kRowsPerThread; ++k) {
