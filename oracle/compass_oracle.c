@@ -517,6 +517,70 @@ int oracle_estimate(int32_t n_tables, int32_t n_edges, const int32_t *eu,
     return bad;
 }
 
+/* ------------------------------------------------------------------ */
+/* Sketch partitioning (Section 5.1).  For a table taking part in two   */
+/* joins, the counters of one sketch row are arranged as a w1 x w2      */
+/* matrix: a tuple with join keys (a, b) adds xi1(a) * xi2(b) to the    */
+/* entry [h1(a)][h2(b)], where (h1, xi1) are the row's functions of the */
+/* first join (the same seeds as the neighbour's one-dimensional sketch */
+/* on that join) and (h2, xi2) those of the second.                     */
+/* counters: d x w1 x w2 int64, row-major, ADDED to.                    */
+/* ------------------------------------------------------------------ */
+void oracle_sketch2d(const int64_t *keys1, const int64_t *keys2, int64_t n,
+                     const uint64_t *seeds1, const uint64_t *seeds2,
+                     int32_t d, int64_t w1, int64_t w2, int64_t *counters)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        for (int32_t i = 0; i < d; ++i) {
+            int64_t b1, b2;
+            int32_t s1, s2;
+            oracle_hash(seeds1 + 6 * i, keys1[r], w1, &b1, &s1);
+            oracle_hash(seeds2 + 6 * i, keys2[r], w2, &b2, &s2);
+            counters[((int64_t)i * w1 + b1) * w2 + b2] += (int64_t)(s1 * s2);
+        }
+    }
+}
+
+/* The three-table chain estimate of Section 5.1: for row i, the sum over
+ * all entries (j1, j2) of A[j1] * P[j1][j2] * B[j2] (the matrix scaled by
+ * the first sketch along its rows and by the second along its columns,
+ * then summed), exact in 128-bit two's complement; the estimate is the
+ * median over rows.  The flag certifies the row values when
+ * n_A * n_P * n_B < 2^127: every |A[j1]| <= n_A, every |B[j2]| <= n_B and
+ * the |P| entries sum to at most n_P.
+ *   A: d x w1, P: d x w1 x w2, B: d x w2 (int64); n_sel3 = {n_A, n_P, n_B}
+ *   out_rows: d x 2 uint64 (lo, hi) */
+void oracle_chain3(const int64_t *A, const int64_t *P, const int64_t *B,
+                   int32_t d, int64_t w1, int64_t w2, const int64_t *n_sel3,
+                   uint64_t *out_rows, double *out_est, int32_t *out_flag)
+{
+    u128 *rows = (u128 *)malloc(sizeof(u128) * (size_t)d);
+    for (int32_t i = 0; i < d; ++i) {
+        u128 x = 0;
+        for (int64_t j1 = 0; j1 < w1; ++j1) {
+            for (int64_t j2 = 0; j2 < w2; ++j2) {
+                i128 t = (i128)A[(int64_t)i * w1 + j1] *
+                         (i128)P[((int64_t)i * w1 + j1) * w2 + j2];
+                x += (u128)t * (u128)(i128)B[(int64_t)i * w2 + j2];
+            }
+        }
+        rows[i] = x;
+        out_rows[2 * i + 0] = (uint64_t)x;
+        out_rows[2 * i + 1] = (uint64_t)(x >> 64);
+    }
+    *out_est = median_of(rows, d);
+    const u128 LIM = (u128)1 << 127;
+    u128 b = 1;
+    int ok = 1;
+    for (int k = 0; k < 3 && ok; ++k) {
+        u128 f = (u128)(n_sel3[k] < 0 ? 0 : n_sel3[k]);
+        if (f == 0) { b = 0; break; }
+        if (b > LIM / f) ok = 0; else b *= f;
+    }
+    *out_flag = (ok && b < LIM) ? ORACLE_FLAG_EXACT : 0;
+    free(rows);
+}
+
 /* Exact conversion of one 128-bit value to double (round to nearest
  * even), exported so tests can pin the median conversion. */
 double oracle_i128_to_double(uint64_t lo, uint64_t hi)

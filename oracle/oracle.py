@@ -77,6 +77,14 @@ def _load():
             ctypes.c_int64, ctypes.POINTER(i64p), i64p, u64p, ctypes.c_int32,
             ctypes.c_int32, u64p, ctypes.POINTER(ctypes.c_double), i32p]
         lib.oracle_estimate.restype = ctypes.c_int32
+        lib.oracle_sketch2d.argtypes = [i64p, i64p, ctypes.c_int64, u64p, u64p,
+                                        ctypes.c_int32, ctypes.c_int64,
+                                        ctypes.c_int64, i64p]
+        lib.oracle_sketch2d.restype = None
+        lib.oracle_chain3.argtypes = [i64p, i64p, i64p, ctypes.c_int32,
+                                      ctypes.c_int64, ctypes.c_int64, i64p, u64p,
+                                      ctypes.POINTER(ctypes.c_double), i32p]
+        lib.oracle_chain3.restype = None
         lib.oracle_i128_to_double.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.oracle_i128_to_double.restype = ctypes.c_double
         _lib = lib
@@ -149,6 +157,44 @@ def sketch(keys: np.ndarray, seeds: np.ndarray, d: int, w: int) -> np.ndarray:
                       _ptr(s, ctypes.c_uint64), int(d), int(w),
                       _ptr(out, ctypes.c_int64))
     return out
+
+
+def sketch2d(keys1, keys2, seeds1, seeds2, d: int, w1: int, w2: int) -> np.ndarray:
+    """Partitioned sketch (Section 5.1) of the (already filtered) key pairs:
+    d x w1 x w2 int64 counters."""
+    lib = _load()
+    k1 = np.ascontiguousarray(np.asarray(keys1).astype(np.int64))
+    k2 = np.ascontiguousarray(np.asarray(keys2).astype(np.int64))
+    assert k1.size == k2.size
+    s1 = np.ascontiguousarray(np.asarray(seeds1, dtype=np.uint64).reshape(d, 6))
+    s2 = np.ascontiguousarray(np.asarray(seeds2, dtype=np.uint64).reshape(d, 6))
+    out = np.zeros((d, w1, w2), dtype=np.int64)
+    lib.oracle_sketch2d(_ptr(k1, ctypes.c_int64), _ptr(k2, ctypes.c_int64),
+                        int(k1.size), _ptr(s1, ctypes.c_uint64),
+                        _ptr(s2, ctypes.c_uint64), int(d), int(w1), int(w2),
+                        _ptr(out, ctypes.c_int64))
+    return out
+
+
+def chain3(A, P, B, n_sel3):
+    """Three-table chain estimate of Section 5.1 from the sketches A (d x w1),
+    P (d x w1 x w2) and B (d x w2): (row values as python ints, median,
+    exactness flag)."""
+    lib = _load()
+    P = np.ascontiguousarray(np.asarray(P, dtype=np.int64))
+    d, w1, w2 = P.shape
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.int64).reshape(d, w1))
+    B = np.ascontiguousarray(np.asarray(B, dtype=np.int64).reshape(d, w2))
+    ns = np.ascontiguousarray(np.asarray(n_sel3, dtype=np.int64).reshape(3))
+    rows = np.zeros((d, 2), dtype=np.uint64)
+    est = ctypes.c_double()
+    flag = ctypes.c_int32()
+    lib.oracle_chain3(_ptr(A, ctypes.c_int64), _ptr(P, ctypes.c_int64),
+                      _ptr(B, ctypes.c_int64), int(d), int(w1), int(w2),
+                      _ptr(ns, ctypes.c_int64), _ptr(rows, ctypes.c_uint64),
+                      ctypes.byref(est), ctypes.byref(flag))
+    vals = [i128_to_int(rows[i, 0], rows[i, 1]) for i in range(d)]
+    return vals, est.value, flag.value
 
 
 def build_table_sketches(table, edge_cols, seeds_per_edge, d, w):
