@@ -180,6 +180,64 @@ compass_status compass_estimate(const compass_join_graph *g,
                                 int32_t *flags, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Sketch partitioning (Section 5.1): for a table that takes part in two
+ * joins, the counters of each sketch row form a w1 x w2 matrix; the
+ * estimate of the three-table chain through it combines the matrix with
+ * the neighbours' one-dimensional sketches of the two joins.
+ * --------------------------------------------------------------------- */
+
+/* compass_sketch_build_2d -- one scan of the middle table: for every row
+ * that satisfies the conjunction of `preds`, with join keys a (first) and
+ * b (second), and for every sketch row i, adds xi1_i(a) * xi2_i(b) to
+ * entry [h1_i(a)][h2_i(b)] of row i's matrix, where (h1_i, xi1_i) are the
+ * functions of `first->seeds` row i and (h2_i, xi2_i) those of
+ * `second->seeds` row i (the seeds of the two joins, shared with the
+ * neighbours' sketches).  Adds the number of qualifying rows to
+ * *n_selected.
+ *   first, second  key column, key dtype and seeds (host, d x 6) of the two
+ *                  joins; their `counters` fields are ignored
+ *   d              1 .. 24
+ *   w1, w2         1 .. 2^20 each, w1 * w2 <= 2^28
+ *   counters       device, d x w1 x w2 row-major, int32 or int64
+ *   other arguments as for compass_sketch_build.
+ * The matrices exceed LDS at useful sizes, so each update is one
+ * device-scope integer atomic (exact and order-independent). */
+compass_status compass_sketch_build_2d(int64_t n_rows,
+                                       const void *const *pred_cols,
+                                       int32_t n_pred_cols,
+                                       const compass_pred *preds,
+                                       int32_t n_preds,
+                                       const compass_sketch_spec *first,
+                                       const compass_sketch_spec *second,
+                                       int32_t d, int32_t w1, int32_t w2,
+                                       int32_t counter_bits, int32_t accumulate,
+                                       void *counters, int64_t *n_selected,
+                                       hipStream_t stream);
+
+/* compass_estimate_chain3 -- the chain A join P join B (P joins A on its
+ * first key and B on its second): for each sketch row i,
+ *   X_i = sum over j1 < w1, j2 < w2 of A[i][j1] * P[i][j1][j2] * B[i][j2]
+ * exact in 128-bit two's complement; est = median over rows (even d: mean
+ * of the two middle values), round-to-nearest-even; flags =
+ * COMPASS_FLAG_EXACT when n_A * n_P * n_B < 2^127 (|X_i| is below that
+ * product).
+ *   a  device, d x w1 (the first neighbour's sketch on the first join)
+ *   p  device, d x w1 x w2 (compass_sketch_build_2d)
+ *   b  device, d x w2 (the second neighbour's sketch on the second join)
+ *   counter_bits  32 or 64, the same for all three
+ *   d 1 .. 32; w1 1 .. 2^20; w2 1 .. 16384; w1 * w2 <= 2^28
+ *   n_a, n_p, n_b device int64 selected rows of the three tables (each must
+ *                 also bound its sketch rows' sums of absolute values)
+ *   row_est  device, d values (may be NULL); est, flags device, 1 each */
+compass_status compass_estimate_chain3(const void *a, const void *p,
+                                       const void *b, int32_t counter_bits,
+                                       int32_t d, int32_t w1, int32_t w2,
+                                       const int64_t *n_a, const int64_t *n_p,
+                                       const int64_t *n_b, compass_i128 *row_est,
+                                       double *est, int32_t *flags,
+                                       hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batched build: the sketch builds of many tables (for instance every table
  * of hundreds of queries) as ONE persistent launch captured in a HIP graph.
  * Each job is exactly one compass_sketch_build call (same fields, same

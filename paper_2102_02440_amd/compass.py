@@ -94,6 +94,16 @@ def lib():
                                            ctypes.POINTER(ctypes.c_int64),
                                            ctypes.POINTER(ctypes.c_double)]
         L.compass_profile_take.restype = ctypes.c_int32
+        L.compass_sketch_build_2d.argtypes = [
+            ctypes.c_int64, ctypes.POINTER(vp), ctypes.c_int32,
+            ctypes.POINTER(Pred), ctypes.c_int32, ctypes.POINTER(SketchSpec),
+            ctypes.POINTER(SketchSpec), ctypes.c_int32, ctypes.c_int32,
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+        L.compass_sketch_build_2d.restype = ctypes.c_int32
+        L.compass_estimate_chain3.argtypes = [
+            vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+            ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+        L.compass_estimate_chain3.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -154,6 +164,24 @@ def sketch_build(n_rows: int, pred_cols, preds, keys, seeds, counters,
     keys/seeds/counters: one entry per sketch (device key tensor, (d, 6)
     uint64 numpy seeds, device (d, w) counter tensor).
     """
+    cols, ncol, parr, np_ = _marshal_preds(pred_cols, preds)
+    ns = len(keys)
+    sarr = (SketchSpec * ns)()
+    keep = []
+    for i in range(ns):
+        sd = np.ascontiguousarray(np.asarray(seeds[i], dtype=np.uint64).reshape(-1))
+        keep.append(sd)
+        sarr[i].key_col = keys[i].data_ptr()
+        sarr[i].key_dtype = _dtype_code(keys[i])
+        sarr[i].seeds = sd.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        sarr[i].counters = counters[i].data_ptr()
+    _check(lib().compass_sketch_build(
+        int(n_rows), cols, ncol, parr, np_, sarr, ns, int(d), int(w),
+        int(counter_bits), 1 if accumulate else 0,
+        ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))
+
+
+def _marshal_preds(pred_cols, preds):
     ncol = len(pred_cols)
     cols = (ctypes.c_void_p * max(1, ncol))(*[c.data_ptr() for c in pred_cols])
     np_ = len(preds)
@@ -173,20 +201,51 @@ def sketch_build(n_rows: int, pred_cols, preds, keys, seeds, counters,
         bm = p.get("bitmap")
         q.bitmap = bm.data_ptr() if bm is not None else None
         q.domain = int(p.get("domain", 0))
-    ns = len(keys)
-    sarr = (SketchSpec * ns)()
+    return cols, ncol, parr, np_
+
+
+def sketch_build_2d(n_rows: int, pred_cols, preds, key1, seeds1, key2, seeds2,
+                    counters, n_selected: torch.Tensor, d: int, w1: int, w2: int,
+                    counter_bits: int = 32, accumulate: bool = False,
+                    stream=None):
+    """Partitioned sketch of one table over two join keys (device
+    (d, w1, w2) counters); see compass_sketch_build_2d."""
+    cols, ncol, parr, np_ = _marshal_preds(pred_cols, preds)
+    specs = []
     keep = []
-    for i in range(ns):
-        sd = np.ascontiguousarray(np.asarray(seeds[i], dtype=np.uint64).reshape(-1))
-        keep.append(sd)
-        sarr[i].key_col = keys[i].data_ptr()
-        sarr[i].key_dtype = _dtype_code(keys[i])
-        sarr[i].seeds = sd.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
-        sarr[i].counters = counters[i].data_ptr()
-    _check(lib().compass_sketch_build(
-        int(n_rows), cols, ncol, parr, np_, sarr, ns, int(d), int(w),
-        int(counter_bits), 1 if accumulate else 0,
+    for k, sd in ((key1, seeds1), (key2, seeds2)):
+        a = np.ascontiguousarray(np.asarray(sd, dtype=np.uint64).reshape(-1))
+        keep.append(a)
+        sp = SketchSpec()
+        sp.key_col = k.data_ptr()
+        sp.key_dtype = _dtype_code(k)
+        sp.seeds = a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        sp.counters = None
+        specs.append(sp)
+    _check(lib().compass_sketch_build_2d(
+        int(n_rows), cols, ncol, parr, np_, ctypes.byref(specs[0]),
+        ctypes.byref(specs[1]), int(d), int(w1), int(w2), int(counter_bits),
+        1 if accumulate else 0, ctypes.c_void_p(counters.data_ptr()),
         ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))
+
+
+def estimate_chain3(a, p, b, n_a, n_p, n_b, counter_bits: int = 32,
+                    stream=None):
+    """Three-table chain estimate from sketches a (d, w1), p (d, w1, w2)
+    and b (d, w2); n_* are device int64 scalars.  Returns device tensors
+    (row_est (d, 2) int64 = lo, hi; est (1,) float64; flags (1,) int32)."""
+    d, w1, w2 = p.shape
+    dev = p.device
+    row_est = torch.empty((d, 2), dtype=torch.int64, device=dev)
+    est = torch.empty(1, dtype=torch.float64, device=dev)
+    flags = torch.empty(1, dtype=torch.int32, device=dev)
+    vp = ctypes.c_void_p
+    _check(lib().compass_estimate_chain3(
+        vp(a.data_ptr()), vp(p.data_ptr()), vp(b.data_ptr()),
+        int(counter_bits), int(d), int(w1), int(w2), vp(n_a.data_ptr()),
+        vp(n_p.data_ptr()), vp(n_b.data_ptr()), vp(row_est.data_ptr()),
+        vp(est.data_ptr()), vp(flags.data_ptr()), _stream(stream)))
+    return row_est, est, flags
 
 
 # --------------------------------------------------------------------------

@@ -20,6 +20,7 @@
 #include "compass.h"
 #include "estimate_buffers.hpp"
 #include "estimate_params.hpp"
+#include "partition_params.hpp"
 
 namespace compass {
 // kernels (build_kernels.hip, estimate_kernels.hip)
@@ -48,6 +49,9 @@ hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
 hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
                          uint64_t *row_est, double *est, int32_t *flags,
                          int32_t n_tables, hipStream_t st);
+hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st);
+hipError_t launch_chain3(const ChainArgs &a, uint64_t *row_est, double *est,
+                         int32_t *flags, hipStream_t st);
 }  // namespace compass
 
 using namespace compass;
@@ -231,6 +235,38 @@ static BucketMod make_bucket_mod(uint32_t w) {
 
 static int dtype_size(int dt) { return dt == COMPASS_I64 ? 8 : 4; }
 
+// Validates the predicates of one scan and copies them into the kernel
+// parameters.
+static compass_status fill_preds(BuildParams &base, int64_t n_rows,
+                                 const void *const *pred_cols,
+                                 int32_t n_pred_cols, const compass_pred *preds,
+                                 int32_t n_preds) {
+  for (int i = 0; i < n_preds; ++i) {
+    const compass_pred &p = preds[i];
+    if (p.col < 0 || p.col >= n_pred_cols ||
+        (n_rows > 0 && !pred_cols[p.col]))
+      return fail(COMPASS_E_ARG, "predicate %d: bad column index %d", i,
+                  p.col);
+    if (p.kind < COMPASS_PRED_POINT || p.kind > COMPASS_PRED_SUBSET)
+      return fail(COMPASS_E_ARG, "predicate %d: bad kind %d", i, p.kind);
+    if (p.dtype != COMPASS_I32 && p.dtype != COMPASS_F32)
+      return fail(COMPASS_E_ARG, "predicate %d: dtype must be I32 or F32", i);
+    if (p.kind == COMPASS_PRED_SUBSET &&
+        (p.dtype != COMPASS_I32 || !p.bitmap || p.domain < 0))
+      return fail(COMPASS_E_ARG, "predicate %d: subset needs I32 codes, a "
+                  "bitmap and a domain >= 0", i);
+    PredDev &q = base.preds[i];
+    q.col = pred_cols ? pred_cols[p.col] : nullptr;
+    q.bitmap = p.bitmap;
+    q.domain = p.domain;
+    q.kind = p.kind;
+    q.dtype = p.dtype;
+    memcpy(&q.lo, &p.lo, 4);
+    memcpy(&q.hi, &p.hi, 4);
+  }
+  return COMPASS_OK;
+}
+
 extern "C" compass_status compass_sketch_build(
     int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
     const compass_pred *preds, int32_t n_preds,
@@ -267,29 +303,8 @@ extern "C" compass_status compass_sketch_build(
   base.counter_bits = counter_bits;
   base.n_selected = n_selected;
   base.bm = make_bucket_mod((uint32_t)w);
-  for (int i = 0; i < n_preds; ++i) {
-    const compass_pred &p = preds[i];
-    if (p.col < 0 || p.col >= n_pred_cols ||
-        (n_rows > 0 && !pred_cols[p.col]))
-      return fail(COMPASS_E_ARG, "predicate %d: bad column index %d", i,
-                  p.col);
-    if (p.kind < COMPASS_PRED_POINT || p.kind > COMPASS_PRED_SUBSET)
-      return fail(COMPASS_E_ARG, "predicate %d: bad kind %d", i, p.kind);
-    if (p.dtype != COMPASS_I32 && p.dtype != COMPASS_F32)
-      return fail(COMPASS_E_ARG, "predicate %d: dtype must be I32 or F32", i);
-    if (p.kind == COMPASS_PRED_SUBSET &&
-        (p.dtype != COMPASS_I32 || !p.bitmap || p.domain < 0))
-      return fail(COMPASS_E_ARG, "predicate %d: subset needs I32 codes, a "
-                  "bitmap and a domain >= 0", i);
-    PredDev &q = base.preds[i];
-    q.col = pred_cols ? pred_cols[p.col] : nullptr;
-    q.bitmap = p.bitmap;
-    q.domain = p.domain;
-    q.kind = p.kind;
-    q.dtype = p.dtype;
-    memcpy(&q.lo, &p.lo, 4);
-    memcpy(&q.hi, &p.hi, 4);
-  }
+  compass_status st0 = fill_preds(base, n_rows, pred_cols, n_pred_cols, preds, n_preds);
+  if (st0 != COMPASS_OK) return st0;
   for (int s = 0; s < n_sketches; ++s) {
     const compass_sketch_spec &k = sketches[s];
     if (!k.seeds || !k.counters || (n_rows > 0 && !k.key_col))
@@ -954,6 +969,125 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
                          reinterpret_cast<uint64_t *>(row_est), est, flags,
                          g->n_tables, stream));
   }
+  return COMPASS_OK;
+}
+
+// ---------------------------------------------------------------------
+// sketch partitioning (Section 5.1)
+// ---------------------------------------------------------------------
+extern "C" compass_status compass_sketch_build_2d(
+    int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
+    const compass_pred *preds, int32_t n_preds,
+    const compass_sketch_spec *first, const compass_sketch_spec *second,
+    int32_t d, int32_t w1, int32_t w2, int32_t counter_bits,
+    int32_t accumulate, void *counters, int64_t *n_selected,
+    hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  if (n_rows < 0 || n_rows >= (1ll << 47))
+    return fail(COMPASS_E_RANGE, "n_rows %lld outside [0, 2^47)",
+                (long long)n_rows);
+  if (d < 1 || d > kMaxLaunchSlices / 2)
+    return fail(COMPASS_E_ARG, "d=%d outside [1, %d]", d, kMaxLaunchSlices / 2);
+  if (w1 < 1 || w2 < 1 || w1 > (1 << 20) || w2 > (1 << 20) ||
+      (int64_t)w1 * w2 > ((int64_t)1 << 28))
+    return fail(COMPASS_E_ARG, "w1=%d, w2=%d: each in [1, 2^20], product "
+                "at most 2^28", w1, w2);
+  if (counter_bits != 32 && counter_bits != 64)
+    return fail(COMPASS_E_ARG, "counter_bits must be 32 or 64");
+  if (counter_bits == 32 && n_rows > 0x7FFFFFFFll)
+    return fail(COMPASS_E_RANGE, "int32 counters need n_rows < 2^31");
+  if (n_preds < 0 || n_preds > kMaxPreds)
+    return fail(COMPASS_E_ARG, "n_preds=%d outside [0, %d]", n_preds,
+                kMaxPreds);
+  if (!first || !second || !counters || !n_selected || (n_preds > 0 && !preds))
+    return fail(COMPASS_E_ARG, "null pointer argument");
+  if (n_preds > 0 && n_rows > 0 && !pred_cols)
+    return fail(COMPASS_E_ARG, "null predicate column array");
+  BuildParams P;
+  memset(&P, 0, sizeof(P));
+  P.n_rows = n_rows;
+  P.n_preds = n_preds;
+  P.counter_bits = counter_bits;
+  P.n_selected = n_selected;
+  P.count_selected = 1;
+  P.d = d;
+  P.bm1 = make_bucket_mod((uint32_t)w1);
+  P.bm = make_bucket_mod((uint32_t)w2);
+  compass_status st = fill_preds(P, n_rows, pred_cols, n_pred_cols, preds, n_preds);
+  if (st != COMPASS_OK) return st;
+  const compass_sketch_spec *spec[2] = {first, second};
+  for (int s = 0; s < 2; ++s) {
+    const compass_sketch_spec &k = *spec[s];
+    if (!k.seeds || (n_rows > 0 && !k.key_col))
+      return fail(COMPASS_E_ARG, "key %d: null pointer", s);
+    if (k.key_dtype != COMPASS_I32 && k.key_dtype != COMPASS_I64)
+      return fail(COMPASS_E_ARG, "key %d: dtype must be I32 or I64", s);
+    for (int i = 0; i < 6 * d; ++i)
+      if (k.seeds[i] >= kP61)
+        return fail(COMPASS_E_ARG, "key %d: seed %d is not below 2^61-1", s, i);
+    P.keys[s].col = k.key_col;
+    P.keys[s].dtype = k.key_dtype;
+    for (int i = 0; i < d; ++i) {
+      const uint64_t *q = k.seeds + 6 * i;
+      P.seeds[s * d + i] = RowSeeds{q[0], q[1], q[2], q[3], q[4], q[5]};
+    }
+  }
+  P.counters[0] = counters;
+  DeviceState *ds;
+  st = device_state(&ds);
+  if (st != COMPASS_OK) return st;
+  if (!accumulate) {
+    ProfScope ps("fill_zero", stream);
+    HIP_OK(launch_fill_zero(counters,
+                            (int64_t)d * w1 * w2 * (counter_bits / 8), stream));
+    HIP_OK(launch_fill_zero(n_selected, 8, stream));
+  }
+  if (n_rows == 0) return COMPASS_OK;
+  const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
+  ProfScope ps("scan2d", stream);
+  HIP_OK(launch_scan2d(P, (int)std::min<int64_t>(tiles, 4ll * ds->n_cu), stream));
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_estimate_chain3(
+    const void *a, const void *p, const void *b, int32_t counter_bits,
+    int32_t d, int32_t w1, int32_t w2, const int64_t *n_a, const int64_t *n_p,
+    const int64_t *n_b, compass_i128 *row_est, double *est, int32_t *flags,
+    hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  if (!a || !p || !b || !n_a || !n_p || !n_b || !est || !flags)
+    return fail(COMPASS_E_ARG, "null pointer argument");
+  if (d < 1 || d > 32) return fail(COMPASS_E_ARG, "d=%d outside [1, 32]", d);
+  if (w1 < 1 || w2 < 1 || w1 > (1 << 20) || w2 > 16384 ||
+      (int64_t)w1 * w2 > ((int64_t)1 << 28))
+    return fail(COMPASS_E_ARG, "w1=%d in [1, 2^20], w2=%d in [1, 16384], "
+                "product at most 2^28", w1, w2);
+  if (counter_bits != 32 && counter_bits != 64)
+    return fail(COMPASS_E_ARG, "counter_bits must be 32 or 64");
+  DeviceState *ds;
+  compass_status st = device_state(&ds);
+  if (st != COMPASS_OK) return st;
+  const int nblk = (w1 + kChainRows - 1) / kChainRows;
+  void *scr;
+  st = ensure_scratch(ds, (size_t)d * nblk * 16, &scr);
+  if (st != COMPASS_OK) return st;
+  ChainArgs c;
+  c.A = a;
+  c.P = p;
+  c.B = b;
+  c.n_a = n_a;
+  c.n_p = n_p;
+  c.n_b = n_b;
+  c.partial = reinterpret_cast<u128 *>(scr);
+  c.counter_bits = counter_bits;
+  c.d = d;
+  c.w1 = w1;
+  c.w2 = w2;
+  ProfScope ps("chain3", stream);
+  HIP_OK(launch_chain3(c, reinterpret_cast<uint64_t *>(row_est), est, flags,
+                       stream));
   return COMPASS_OK;
 }
 

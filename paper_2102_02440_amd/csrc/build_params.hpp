@@ -52,6 +52,7 @@ struct BuildParams {
   int32_t d;
   int32_t n_slices_total;  // n_sketches * d of the call (slab row count)
   BucketMod bm;
+  BucketMod bm1;        // first dimension of a partitioned sketch (w1)
   PredDev preds[kMaxPreds];
   KeyDev keys[kMaxSketches];
   void *counters[kMaxSketches];

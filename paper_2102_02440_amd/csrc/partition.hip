@@ -1,0 +1,225 @@
+// partition.hip -- sketch partitioning (Section 5.1): the two-dimensional
+// sketch of a table that takes part in two joins, and the three-table chain
+// estimate that combines it with the neighbours' one-dimensional sketches.
+//
+//  scan2d_kernel   fused selection scan (the same compaction as the
+//                  one-dimensional build); per qualifying row and sketch
+//                  row i, both keys are hashed with row i's functions of
+//                  their join and xi1 * xi2 is added to entry
+//                  [h1][h2] of row i's w1 x w2 matrix.  The matrices are far
+//                  larger than LDS (8192 x 8192 per row for the 6a shape),
+//                  so the add is one device-scope integer atomic; integer
+//                  addition makes the result exact and order-independent.
+//  chain3_kernel   X_i = sum over (j1, j2) of A[j1] P[j1][j2] B[j2]: block
+//                  (i, slab of j1 rows) streams its rows of P once with
+//                  coalesced loads, B's row staged in LDS; each lane sums
+//                  P * B over its columns (int64 when n_P n_B < 2^62, else
+//                  128-bit) and adds A[j1] times that sum to a 128-bit total.
+//  chain3_finish   row totals, median, round-to-nearest-even, certificate.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "build_params.hpp"
+#include "device_math.hpp"
+#include "scan_common.hpp"
+#include "partition_params.hpp"
+
+namespace compass {
+
+struct Job2d {
+  const BuildParams &P;
+  __device__ int n_preds() const { return P.n_preds; }
+  __device__ const PredDev &pred(int q) const { return P.preds[q]; }
+};
+
+template <typename C>
+__device__ __forceinline__ void add_counter(C *p, int32_t v);
+template <>
+__device__ __forceinline__ void add_counter<int32_t>(int32_t *p, int32_t v) {
+  atomicAdd(p, v);
+}
+template <>
+__device__ __forceinline__ void add_counter<int64_t>(int64_t *p, int32_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long *>(p),
+            (unsigned long long)(int64_t)v);
+}
+
+template <typename C>
+__global__ __launch_bounds__(kBuildThreads) void scan2d_kernel(
+    const BuildParams P) {
+  __shared__ int32_t queue[kBuildTile];
+  __shared__ int32_t s_qn;
+  const Job2d job{P};
+  const int d = P.d;
+  const int64_t w1 = P.bm1.w, w2 = P.bm.w;
+  C *cnt = reinterpret_cast<C *>(P.counters[0]);
+  uint64_t sel = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBuildTile; base < P.n_rows;
+       base += (int64_t)gridDim.x * kBuildTile) {
+    const int nt = (int)min((int64_t)kBuildTile, P.n_rows - base);
+    const int qn = compact_tile<Job2d, kBuildRowsPerThread>(
+        job, base, nt, P.n_preds, queue, &s_qn);
+    sel += (uint64_t)qn;
+    int ridx[kBuildRowsPerThread];
+    bool valid[kBuildRowsPerThread];
+#pragma unroll
+    for (int k = 0; k < kBuildRowsPerThread; ++k) {
+      const int q = threadIdx.x + k * kBuildThreads;
+      valid[k] = q < qn;
+      ridx[k] = valid[k] ? (P.n_preds ? queue[q] : q) : 0;
+    }
+    uint64_t x1[kBuildRowsPerThread], x2[kBuildRowsPerThread];
+    load_fields<kBuildRowsPerThread>(P.keys[0], base, ridx, x1);
+    load_fields<kBuildRowsPerThread>(P.keys[1], base, ridx, x2);
+    for (int i = 0; i < d; ++i) {
+      const RowSeeds s1 = P.seeds[i], s2 = P.seeds[d + i];
+#pragma unroll
+      for (int k = 0; k < kBuildRowsPerThread; ++k) {
+        if (!valid[k]) continue;
+        int32_t g1, g2;
+        uint32_t b1, b2;
+        if ((x1[k] >> 32) == 0)
+          hash_xi_h<true>(x1[k], s1, P.bm1, g1, b1);
+        else
+          hash_xi_h<false>(x1[k], s1, P.bm1, g1, b1);
+        if ((x2[k] >> 32) == 0)
+          hash_xi_h<true>(x2[k], s2, P.bm, g2, b2);
+        else
+          hash_xi_h<false>(x2[k], s2, P.bm, g2, b2);
+        add_counter<C>(cnt + ((int64_t)i * w1 + b1) * w2 + b2, g1 * g2);
+      }
+    }
+    __syncthreads();  // queue and s_qn are reused by the next tile
+  }
+  if (P.count_selected && threadIdx.x == 0 && sel)
+    atomicAdd(reinterpret_cast<unsigned long long *>(P.n_selected),
+              (unsigned long long)sel);
+}
+
+hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st) {
+  if (P.counter_bits == 32)
+    hipLaunchKernelGGL(scan2d_kernel<int32_t>, dim3(n_blocks),
+                       dim3(kBuildThreads), 0, st, P);
+  else
+    hipLaunchKernelGGL(scan2d_kernel<int64_t>, dim3(n_blocks),
+                       dim3(kBuildThreads), 0, st, P);
+  return hipGetLastError();
+}
+
+constexpr int kChainThreads = 256;
+constexpr int kChainMaxW2 = 16384;    // B's row staged in LDS as int64
+
+template <typename C>
+__device__ __forceinline__ int64_t ld(const void *p, int64_t i) {
+  return (int64_t)reinterpret_cast<const C *>(p)[i];
+}
+
+template <typename C>
+__global__ __launch_bounds__(kChainThreads) void chain3_kernel(ChainArgs a) {
+  __shared__ int64_t bs[kChainMaxW2];
+  __shared__ u128 red[kChainThreads];
+  const int i = blockIdx.x;
+  const int w1 = a.w1, w2 = a.w2;
+  for (int j = threadIdx.x; j < w2; j += kChainThreads)
+    bs[j] = ld<C>(a.B, (int64_t)i * w2 + j);
+  // 64-bit inner sums are exact when n_P * n_B < 2^62: every partial sum
+  // of |P| |B| over one row of P is at most n_P max|B| <= n_P n_B
+  const uint64_t np = *a.n_p < 0 ? 0 : (uint64_t)*a.n_p;
+  const uint64_t nb = *a.n_b < 0 ? 0 : (uint64_t)*a.n_b;
+  const bool narrow = (u128)np * nb < ((u128)1 << 62);
+  __syncthreads();
+  u128 G = 0;
+  const int j1a = blockIdx.y * kChainRows, j1b = min(w1, j1a + kChainRows);
+  for (int j1 = j1a; j1 < j1b; ++j1) {
+    const int64_t row = ((int64_t)i * w1 + j1) * w2;
+    const int64_t aj = ld<C>(a.A, (int64_t)i * w1 + j1);
+    if (narrow) {
+      int64_t t = 0;
+      for (int j2 = threadIdx.x; j2 < w2; j2 += kChainThreads)
+        t += ld<C>(a.P, row + j2) * bs[j2];
+      G += mul_s64_s64(aj, t);
+    } else {
+      u128 t = 0;
+      for (int j2 = threadIdx.x; j2 < w2; j2 += kChainThreads)
+        t += mul_s64_s64(ld<C>(a.P, row + j2), bs[j2]);
+      G += mul_u128_s64(t, aj);
+    }
+  }
+  red[threadIdx.x] = G;
+  __syncthreads();
+  for (int off = kChainThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[(size_t)i * gridDim.y + blockIdx.y] = red[0];
+}
+
+__device__ __forceinline__ bool i128_less(u128 x, u128 y) {
+  return (__int128)x < (__int128)y;
+}
+
+__global__ void chain3_finish_kernel(ChainArgs a, int32_t nblk,
+                                     uint64_t *row_est, double *est,
+                                     int32_t *flags) {
+  __shared__ u128 xs[64];
+  const int d = a.d;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) {
+    u128 x = 0;
+    for (int k = 0; k < nblk; ++k) x += a.partial[(size_t)i * nblk + k];
+    xs[i] = x;
+    if (row_est) {
+      row_est[2 * i] = (uint64_t)x;
+      row_est[2 * i + 1] = (uint64_t)(x >> 64);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int p = 1; p < d; ++p) {  // insertion sort of d <= 32 values
+    const u128 v = xs[p];
+    int q = p - 1;
+    while (q >= 0 && i128_less(v, xs[q])) {
+      xs[q + 1] = xs[q];
+      --q;
+    }
+    xs[q + 1] = v;
+  }
+  double m;
+  if (d & 1) {
+    m = i128_to_double(xs[d / 2]);
+  } else {
+    m = i128_to_double(xs[d / 2 - 1] + xs[d / 2]) * 0.5;
+  }
+  *est = m;
+  // |X_i| <= n_A * n_P * n_B: certified below 2^127
+  const u128 lim = (u128)1 << 127;
+  u128 b = 1;
+  bool ok = true;
+  const int64_t ns[3] = {*a.n_a, *a.n_p, *a.n_b};
+  for (int k = 0; k < 3 && ok; ++k) {
+    const u128 f = (u128)(ns[k] < 0 ? 0 : ns[k]);
+    if (f == 0) {
+      b = 0;
+      break;
+    }
+    if (b > lim / f) ok = false; else b *= f;
+  }
+  *flags = ok && b < lim ? 1 : 0;
+}
+
+hipError_t launch_chain3(const ChainArgs &a, uint64_t *row_est, double *est,
+                         int32_t *flags, hipStream_t st) {
+  const int nblk = (a.w1 + kChainRows - 1) / kChainRows;
+  if (a.counter_bits == 32)
+    hipLaunchKernelGGL(chain3_kernel<int32_t>, dim3(a.d, nblk),
+                       dim3(kChainThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL(chain3_kernel<int64_t>, dim3(a.d, nblk),
+                       dim3(kChainThreads), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(chain3_finish_kernel, dim3(1), dim3(64), 0, st, a, nblk,
+                     row_est, est, flags);
+  return hipGetLastError();
+}
+
+}  // namespace compass

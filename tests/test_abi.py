@@ -80,3 +80,41 @@ def test_estimate_rejects_disconnected(C):
         ctypes.POINTER(ctypes.c_uint64)), 1, None, ctypes.c_void_p(8),
         ctypes.c_void_p(8), ctypes.c_void_p(0))
     assert r == 3
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(d=0), 1), (dict(d=25), 1), (dict(w1=0), 1), (dict(w2=0), 1),
+    (dict(w1=1 << 15, w2=1 << 14), 1), (dict(counter_bits=8), 1),
+    (dict(n_rows=-1), 2), (dict(n_rows=2**31), 2), (dict(bad_seed=True), 1),
+    (dict(null_counters=True), 1),
+])
+def test_build_2d_validation(C, kw, status):
+    L = C.lib()
+    d = kw.get("d", 3)
+    seeds = np.zeros((max(d, 1), 6), np.uint64)
+    if kw.get("bad_seed"):
+        seeds[-1, 5] = (1 << 61) + 7
+    s1, k1 = _spec(C, d, seeds)
+    s2, k2 = _spec(C, d, np.zeros((max(d, 1), 6), np.uint64))
+    r = L.compass_sketch_build_2d(
+        kw.get("n_rows", 10), None, 0, None, 0, s1, s2, d, kw.get("w1", 64),
+        kw.get("w2", 32), kw.get("counter_bits", 32), 0,
+        ctypes.c_void_p(0 if kw.get("null_counters") else 48),
+        ctypes.c_void_p(64), ctypes.c_void_p(0))
+    assert r == status
+    assert L.compass_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(d=0), 1), (dict(d=33), 1), (dict(w2=16385), 1), (dict(w1=0), 1),
+    (dict(counter_bits=16), 1), (dict(null_a=True), 1),
+])
+def test_chain3_validation(C, kw, status):
+    L = C.lib()
+    v = ctypes.c_void_p
+    r = L.compass_estimate_chain3(
+        v(0 if kw.get("null_a") else 16), v(32), v(48), kw.get("counter_bits", 32),
+        kw.get("d", 3), kw.get("w1", 64), kw.get("w2", 64), v(8), v(8), v(8),
+        None, v(8), v(8), v(0))
+    assert r == status
+    assert L.compass_last_error().decode() != ""

@@ -1,0 +1,159 @@
+"""Parity of the partitioned-sketch path (Section 5.1) with the oracle:
+two-dimensional sketch counters bit for bit, chain estimates (128-bit rows,
+median, flag) exactly."""
+import numpy as np
+import pytest
+
+from paper_2102_02440_amd import workloads as W
+
+gpu = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _tables(rng, n_a, n_p, n_b, dom1, dom2, key_dtype=np.int32):
+    ka = rng.integers(0, dom1, n_a).astype(key_dtype)
+    kb = rng.integers(0, dom2, n_b).astype(key_dtype)
+    kp1 = rng.integers(0, dom1, n_p).astype(key_dtype)
+    kp2 = rng.integers(0, dom2, n_p).astype(key_dtype)
+    attr = rng.integers(0, 1000, n_p).astype(np.int32)
+    return ka, kb, kp1, kp2, attr
+
+
+def _run(oracle, ka, kb, kp1, kp2, attr, d, w1, w2, bits, preds, name):
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    _say(name, "n_p", kp1.size, "d", d, "w1", w1, "w2", w2, "bits", bits)
+    rng = np.random.default_rng(kp1.size + w1 * 7 + w2)
+    s1, s2 = W.draw_seeds(rng, 2, d)
+    dev = "cuda"
+    ct = torch.int32 if bits == 32 else torch.int64
+    A = torch.zeros((d, w1), dtype=ct, device=dev)
+    B = torch.zeros((d, w2), dtype=ct, device=dev)
+    P = torch.zeros((d, w1, w2), dtype=ct, device=dev)
+    na = torch.zeros(1, dtype=torch.int64, device=dev)
+    nb = torch.zeros(1, dtype=torch.int64, device=dev)
+    npp = torch.zeros(1, dtype=torch.int64, device=dev)
+    ta, tb = torch.from_numpy(ka).to(dev), torch.from_numpy(kb).to(dev)
+    tp1, tp2 = torch.from_numpy(kp1).to(dev), torch.from_numpy(kp2).to(dev)
+    tattr = torch.from_numpy(attr).to(dev)
+    C.sketch_build(ka.size, [], [], [ta], [s1], [A], na, d, w1, counter_bits=bits)
+    C.sketch_build(kb.size, [], [], [tb], [s2], [B], nb, d, w2, counter_bits=bits)
+    C.sketch_build_2d(kp1.size, [tattr], preds, tp1, s1, tp2, s2, P, npp, d, w1,
+                      w2, counter_bits=bits)
+    row_est, est, flags = C.estimate_chain3(A, P, B, na, npp, nb, counter_bits=bits)
+    torch.cuda.synchronize()
+    mask = np.ones(kp1.size, bool)
+    for p in preds:
+        if p["kind"] == "range":
+            mask &= (attr >= p["lo"]) & (attr <= p["hi"])
+        elif p["kind"] == "point":
+            mask &= attr == p["lo"]
+    assert npp.item() == int(mask.sum())
+    Po = oracle.sketch2d(kp1[mask], kp2[mask], s1, s2, d, w1, w2)
+    assert np.array_equal(P.cpu().numpy().astype(np.int64), Po)
+    Ao = oracle.sketch(ka, s1, d, w1)
+    Bo = oracle.sketch(kb, s2, d, w2)
+    vals, est_o, flag_o = oracle.chain3(Ao, Po, Bo, [ka.size, int(mask.sum()), kb.size])
+    vals_g = C.row_values(row_est.reshape(1, d, 2))[0]
+    assert vals_g == [v & ((1 << 128) - 1) for v in vals]
+    assert est.item() == est_o
+    assert flags.item() == flag_o
+
+
+@gpu
+@pytest.mark.parametrize("bits", [32, 64])
+def test_chain3_small(oracle, bits):
+    rng = np.random.default_rng(3)
+    t = _tables(rng, 3000, 20000, 2500, 500, 300)
+    _run(oracle, *t, 5, 64, 32, bits, [{"col": 0, "kind": "range", "lo": 100, "hi": 700}],
+         "chain3 small")
+
+
+@gpu
+def test_chain3_odd_widths_int64_keys(oracle):
+    """Non-power-of-two widths, int64 keys (negative and above 2^32), a point
+    predicate, ragged row count."""
+    rng = np.random.default_rng(4)
+    ka, kb, kp1, kp2, attr = _tables(rng, 2000, 4096 * 3 + 77, 1500, 400, 200,
+                                     key_dtype=np.int64)
+    big = np.int64(1) << 40
+    kp1 = np.where(kp1 % 3 == 0, kp1 * 977 - big, kp1)
+    ka = np.where(ka % 3 == 0, ka * 977 - big, ka)
+    attr = (attr % 4).astype(np.int32)
+    _run(oracle, ka, kb, kp1, kp2, attr, 3, 100, 37, 64,
+         [{"col": 0, "kind": "point", "lo": 2}], "chain3 odd widths")
+
+
+@gpu
+def test_chain3_empty_selection(oracle):
+    rng = np.random.default_rng(5)
+    t = _tables(rng, 100, 500, 100, 50, 50)
+    _run(oracle, *t, 3, 16, 16, 32, [{"col": 0, "kind": "range", "lo": 2000, "hi": 3000}],
+         "chain3 empty selection")
+
+
+@gpu
+def test_chain3_6a_shape_full_width(oracle):
+    """The 6a-shaped chain k - mk - t at its full size and width
+    (mk 4.5M rows, w1 = w2 = 8192, d = 7): GPU rows 0 and 6 of the
+    partitioned sketch against the oracle's sketch of those rows (seeds of
+    one row, d = 1), and their chain row values."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    q = W.job6a(seed=W.DEFAULT_SEED, scale=1.0)
+    k, mk, t = q.tables[0], q.tables[1], q.tables[2]
+    d, w = q.d, q.w
+    s_e0, s_e1 = q.seeds[0], q.seeds[1]
+    _say("6a chain full width", mk.n_rows, d, w)
+    dev = "cuda"
+    A = torch.zeros((d, w), dtype=torch.int32, device=dev)
+    B = torch.zeros((d, w), dtype=torch.int32, device=dev)
+    P = torch.zeros((d, w, w), dtype=torch.int32, device=dev)
+    na, npp, nb = (torch.zeros(1, dtype=torch.int64, device=dev) for _ in range(3))
+
+    def dcols(tb):
+        return {c: torch.from_numpy(v).to(dev) for c, v in tb.cols.items()}
+
+    def dpreds(tb, cols):
+        names = list(cols)
+        out = []
+        for p in tb.preds:
+            e = {"col": names.index(p.col), "kind": p.kind, "lo": p.lo, "hi": p.hi}
+            if p.kind == "subset":
+                e["bitmap"] = torch.from_numpy(p.bitmap.view(np.int64)).to(dev)
+                e["domain"] = p.domain
+            out.append(e)
+        return out
+
+    kc, tc, mc = dcols(k), dcols(t), dcols(mk)
+    C.sketch_build(k.n_rows, list(kc.values()), dpreds(k, kc), [kc["id"]], [s_e0],
+                   [A], na, d, w)
+    C.sketch_build(t.n_rows, list(tc.values()), dpreds(t, tc), [tc["id"]], [s_e1],
+                   [B], nb, d, w)
+    C.sketch_build_2d(mk.n_rows, list(mc.values()), dpreds(mk, mc), mc["keyword"],
+                      s_e0, mc["movie"], s_e1, P, npp, d, w, w)
+    row_est, est, flags = C.estimate_chain3(A, P, B, na, npp, nb)
+    torch.cuda.synchronize()
+    vals_g = C.row_values(row_est.reshape(1, d, 2))[0]
+    mk_mask = oracle.eval_predicates(mk.cols, mk.preds)
+    k_keys = k.cols["id"][oracle.eval_predicates(k.cols, k.preds)]
+    t_keys = t.cols["id"][oracle.eval_predicates(t.cols, t.preds)]
+    assert npp.item() == int(mk_mask.sum())
+    for i in (0, d - 1):
+        Po = oracle.sketch2d(mk.cols["keyword"][mk_mask], mk.cols["movie"][mk_mask],
+                             s_e0[i:i + 1], s_e1[i:i + 1], 1, w, w)
+        assert np.array_equal(P[i].cpu().numpy().astype(np.int64), Po[0]), i
+        Ao = oracle.sketch(k_keys, s_e0[i:i + 1], 1, w)
+        Bo = oracle.sketch(t_keys, s_e1[i:i + 1], 1, w)
+        v, _, _ = oracle.chain3(Ao, Po, Bo, [k_keys.size, int(mk_mask.sum()), t_keys.size])
+        assert vals_g[i] == v[0] & ((1 << 128) - 1), i
