@@ -12,9 +12,10 @@
 //                  addition makes the result exact and order-independent.
 //  chain3_kernel   X_i = sum over (j1, j2) of A[j1] P[j1][j2] B[j2]: block
 //                  (i, slab of j1 rows) streams its rows of P once with
-//                  coalesced loads, B's row staged in LDS; each lane sums
-//                  P * B over its columns (int64 when n_P n_B < 2^62, else
-//                  128-bit) and adds A[j1] times that sum to a 128-bit total.
+//                  coalesced loads; each lane holds its columns of B in
+//                  registers, sums P * B over them (int64 when n_P n_B <
+//                  2^62, else 128-bit) and adds A[j1] times that sum to a
+//                  128-bit total.
 //  chain3_finish   row totals, median, round-to-nearest-even, certificate.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -106,42 +107,53 @@ hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st) {
   return hipGetLastError();
 }
 
-constexpr int kChainThreads = 256;
-constexpr int kChainMaxW2 = 16384;    // B's row staged in LDS as int64
+constexpr int kChainThreads = 512;
+constexpr int kChainMaxW2 = 16384;
+constexpr int kChainPerLane = kChainMaxW2 / kChainThreads;  // B values per lane
 
 template <typename C>
 __device__ __forceinline__ int64_t ld(const void *p, int64_t i) {
   return (int64_t)reinterpret_cast<const C *>(p)[i];
 }
 
+// Block (i, slab of kChainRows rows of P): lane l owns columns
+// l, l + 512, ... of B (in registers, loaded once) and of every P row.
 template <typename C>
 __global__ __launch_bounds__(kChainThreads) void chain3_kernel(ChainArgs a) {
-  __shared__ int64_t bs[kChainMaxW2];
   __shared__ u128 red[kChainThreads];
   const int i = blockIdx.x;
   const int w1 = a.w1, w2 = a.w2;
-  for (int j = threadIdx.x; j < w2; j += kChainThreads)
-    bs[j] = ld<C>(a.B, (int64_t)i * w2 + j);
+  C bv[kChainPerLane];
+#pragma unroll
+  for (int k = 0; k < kChainPerLane; ++k) {
+    const int j = threadIdx.x + k * kChainThreads;
+    bv[k] = j < w2 ? reinterpret_cast<const C *>(a.B)[(int64_t)i * w2 + j] : (C)0;
+  }
   // 64-bit inner sums are exact when n_P * n_B < 2^62: every partial sum
   // of |P| |B| over one row of P is at most n_P max|B| <= n_P n_B
   const uint64_t np = *a.n_p < 0 ? 0 : (uint64_t)*a.n_p;
   const uint64_t nb = *a.n_b < 0 ? 0 : (uint64_t)*a.n_b;
   const bool narrow = (u128)np * nb < ((u128)1 << 62);
-  __syncthreads();
   u128 G = 0;
   const int j1a = blockIdx.y * kChainRows, j1b = min(w1, j1a + kChainRows);
   for (int j1 = j1a; j1 < j1b; ++j1) {
-    const int64_t row = ((int64_t)i * w1 + j1) * w2;
+    const C *prow = reinterpret_cast<const C *>(a.P) + ((int64_t)i * w1 + j1) * w2;
     const int64_t aj = ld<C>(a.A, (int64_t)i * w1 + j1);
     if (narrow) {
       int64_t t = 0;
-      for (int j2 = threadIdx.x; j2 < w2; j2 += kChainThreads)
-        t += ld<C>(a.P, row + j2) * bs[j2];
+#pragma unroll 8
+      for (int k = 0; k < kChainPerLane; ++k) {
+        const int j = threadIdx.x + k * kChainThreads;
+        if (j < w2) t += (int64_t)prow[j] * (int64_t)bv[k];
+      }
       G += mul_s64_s64(aj, t);
     } else {
       u128 t = 0;
-      for (int j2 = threadIdx.x; j2 < w2; j2 += kChainThreads)
-        t += mul_s64_s64(ld<C>(a.P, row + j2), bs[j2]);
+#pragma unroll 4
+      for (int k = 0; k < kChainPerLane; ++k) {
+        const int j = threadIdx.x + k * kChainThreads;
+        if (j < w2) t += mul_s64_s64((int64_t)prow[j], (int64_t)bv[k]);
+      }
       G += mul_u128_s64(t, aj);
     }
   }

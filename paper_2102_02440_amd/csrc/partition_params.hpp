@@ -6,7 +6,7 @@
 
 namespace compass {
 
-constexpr int kChainRows = 16;  // rows of the two-dimensional sketch per block
+constexpr int kChainRows = 32;  // rows of the two-dimensional sketch per block
 
 struct ChainArgs {
   const void *A, *P, *B;        // d x w1, d x w1 x w2, d x w2 counters
