@@ -581,6 +581,81 @@ void oracle_chain3(const int64_t *A, const int64_t *P, const int64_t *B,
     free(rows);
 }
 
+/* ------------------------------------------------------------------ */
+/* AGMS sketches (Section 4.1), the baseline Fast-AGMS improves on.     */
+/* A table's sketch for one query is r x b independent basic sketches, */
+/* each a single counter: the sum over the table's qualifying tuples   */
+/* of the product, over the joins the table takes part in, of that     */
+/* join's +-1 variable of the tuple's key (one independent family per  */
+/* join and basic sketch; the composed sketch of Section 4.1.2).       */
+/* keys: n_joins arrays of n keys; seeds: n_joins x K x 6 (only a0..a3  */
+/* are used), K = r * b; counters: K int64, ADDED to.                   */
+/* ------------------------------------------------------------------ */
+void oracle_agms_sketch(const int64_t *const *keys, int64_t n,
+                        const uint64_t *seeds, int32_t n_joins, int32_t K,
+                        int64_t *counters)
+{
+    for (int64_t t = 0; t < n; ++t) {
+        for (int32_t c = 0; c < K; ++c) {
+            int32_t prod = 1;
+            for (int32_t e = 0; e < n_joins; ++e) {
+                int64_t bucket;
+                int32_t sign;
+                oracle_hash(seeds + ((int64_t)e * K + c) * 6, keys[e][t], 1,
+                            &bucket, &sign);
+                prod *= sign;
+            }
+            counters[c] += prod;
+        }
+    }
+}
+
+/* AGMS estimate of the query whose tables' sketches are given: basic
+ * estimate (i, j) = product of the tables' counters (i, j); the b basic
+ * estimates of row i are averaged and the median is taken over the r
+ * averages (Section 4.1.1).  Row sums are exact in 128 bits; an average is
+ * the round-to-nearest-even double of the sum divided by b in IEEE
+ * arithmetic; even r takes the mean of the two middle averages.
+ * sk: n_tables pointers to K = r * b int64 counters (row-major r x b).
+ * out_rows: r x 2 uint64 (lo, hi of the row sums); flag EXACT when the
+ * product of the tables' selected counts is below 2^127. */
+void oracle_agms_estimate(const int64_t *const *sk, int32_t n_tables,
+                          int32_t r, int32_t b, const int64_t *n_sel,
+                          uint64_t *out_rows, double *out_est,
+                          int32_t *out_flag)
+{
+    double *avg = (double *)malloc(sizeof(double) * (size_t)r);
+    for (int32_t i = 0; i < r; ++i) {
+        u128 sum = 0;
+        for (int32_t j = 0; j < b; ++j) {
+            u128 x = 1;
+            for (int32_t t = 0; t < n_tables; ++t)
+                x *= (u128)(i128)sk[t][(int64_t)i * b + j];
+            sum += x;
+        }
+        out_rows[2 * i + 0] = (uint64_t)sum;
+        out_rows[2 * i + 1] = (uint64_t)(sum >> 64);
+        avg[i] = (double)(i128)sum / (double)b;
+    }
+    for (int32_t i = 1; i < r; ++i) {  /* insertion sort */
+        double v = avg[i];
+        int32_t k = i - 1;
+        while (k >= 0 && avg[k] > v) { avg[k + 1] = avg[k]; --k; }
+        avg[k + 1] = v;
+    }
+    *out_est = (r & 1) ? avg[r / 2] : (avg[r / 2 - 1] + avg[r / 2]) * 0.5;
+    const u128 LIM = (u128)1 << 127;
+    u128 p = 1;
+    int ok = 1;
+    for (int32_t t = 0; t < n_tables && ok; ++t) {
+        u128 f = (u128)(n_sel[t] < 0 ? 0 : n_sel[t]);
+        if (f == 0) { p = 0; break; }
+        if (p > LIM / f) ok = 0; else p *= f;
+    }
+    *out_flag = (ok && p < LIM) ? ORACLE_FLAG_EXACT : 0;
+    free(avg);
+}
+
 /* Exact conversion of one 128-bit value to double (round to nearest
  * even), exported so tests can pin the median conversion. */
 double oracle_i128_to_double(uint64_t lo, uint64_t hi)

@@ -85,6 +85,15 @@ def _load():
                                       ctypes.c_int64, ctypes.c_int64, i64p, u64p,
                                       ctypes.POINTER(ctypes.c_double), i32p]
         lib.oracle_chain3.restype = None
+        lib.oracle_agms_sketch.argtypes = [ctypes.POINTER(i64p), ctypes.c_int64,
+                                           u64p, ctypes.c_int32, ctypes.c_int32,
+                                           i64p]
+        lib.oracle_agms_sketch.restype = None
+        lib.oracle_agms_estimate.argtypes = [ctypes.POINTER(i64p), ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32, i64p,
+                                             u64p, ctypes.POINTER(ctypes.c_double),
+                                             i32p]
+        lib.oracle_agms_estimate.restype = None
         lib.oracle_i128_to_double.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.oracle_i128_to_double.restype = ctypes.c_double
         _lib = lib
@@ -195,6 +204,41 @@ def chain3(A, P, B, n_sel3):
                       ctypes.byref(est), ctypes.byref(flag))
     vals = [i128_to_int(rows[i, 0], rows[i, 1]) for i in range(d)]
     return vals, est.value, flag.value
+
+
+def agms_sketch(keys_per_join, seeds_per_join, r: int, b: int) -> np.ndarray:
+    """AGMS sketch (Section 4.1) of one table's (already filtered) tuples:
+    ``keys_per_join`` one key array per join of the table, ``seeds_per_join``
+    one (r * b, 6) seed array per join; returns r x b int64 counters."""
+    lib = _load()
+    K = r * b
+    ks = [np.ascontiguousarray(np.asarray(k).astype(np.int64)) for k in keys_per_join]
+    n = ks[0].size
+    assert all(k.size == n for k in ks)
+    arr = (ctypes.POINTER(ctypes.c_int64) * len(ks))(*[_ptr(k, ctypes.c_int64) for k in ks])
+    sd = np.ascontiguousarray(np.stack([np.asarray(s, dtype=np.uint64).reshape(K, 6)
+                                        for s in seeds_per_join]))
+    out = np.zeros(K, dtype=np.int64)
+    lib.oracle_agms_sketch(arr, int(n), _ptr(sd, ctypes.c_uint64), len(ks), K,
+                           _ptr(out, ctypes.c_int64))
+    return out.reshape(r, b)
+
+
+def agms_estimate(sketches, n_sel):
+    """AGMS estimate from the tables' (r, b) sketches: (row sums as python
+    ints, estimate, exactness flag)."""
+    lib = _load()
+    sks = [np.ascontiguousarray(np.asarray(s, dtype=np.int64)) for s in sketches]
+    r, b = sks[0].shape
+    arr = (ctypes.POINTER(ctypes.c_int64) * len(sks))(*[_ptr(s, ctypes.c_int64) for s in sks])
+    ns = np.ascontiguousarray(np.asarray(n_sel, dtype=np.int64))
+    rows = np.zeros((r, 2), dtype=np.uint64)
+    est = ctypes.c_double()
+    flag = ctypes.c_int32()
+    lib.oracle_agms_estimate(arr, len(sks), int(r), int(b), _ptr(ns, ctypes.c_int64),
+                             _ptr(rows, ctypes.c_uint64), ctypes.byref(est),
+                             ctypes.byref(flag))
+    return [i128_to_int(rows[i, 0], rows[i, 1]) for i in range(r)], est.value, flag.value
 
 
 def build_table_sketches(table, edge_cols, seeds_per_edge, d, w):
