@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=3_000_000,
                     help="cast_info rows in the oracle's timed sample")
     ap.add_argument("--workload", default="job6a",
-                    choices=["job6a", "batch", "learned", "large", "partition"],
+                    choices=["job6a", "batch", "learned", "large", "partition", "agms"],
                     help="job6a: the headline step (default); batch: 512 "
                          "queries in one graph-captured persistent launch vs "
                          "one launch per sketch; learned: train + evaluate "
@@ -158,6 +158,8 @@ def main():
         return run_large(args)
     if args.workload == "partition":
         return run_partition(args)
+    if args.workload == "agms":
+        return run_agms(args)
     return run_job6a(args)
 
 
@@ -457,6 +459,113 @@ def run_partition(args):
            "estimate": {"partitioned": e_part, "merged": e_merge, "true": true,
                         "qerror_partitioned": qe(e_part), "qerror_merged": qe(e_merge),
                         "exact_flag": int(flags.item())}}
+    print(json.dumps(out), flush=True)
+
+
+def run_agms(args):
+    """The AGMS baseline (Section 4.1) on the 6a-shaped query: r x b = 7 x 16
+    basic sketches per table, each composed over all of the table's joins;
+    one step = the five table scans; compared with the Fast-AGMS build of
+    the same tables (one launch per table, d = 7, w = 8192) and, for the
+    whole five-table query, with the merged Fast-AGMS estimate and the exact
+    size."""
+    import numpy as np
+    import torch
+    from paper_2102_02440_amd import compass as C
+    from paper_2102_02440_amd import workloads as W
+    seed = W.DEFAULT_SEED if args.seed is None else args.seed
+    q = W.job6a(seed=seed)
+    r, b = 7, 16
+    K = r * b
+    seeds = W.draw_seeds(np.random.default_rng(seed + 1), len(q.edges), K)
+    dev = "cuda"
+    tabs = []
+    for t, tb in enumerate(q.tables):
+        cols = {c: torch.from_numpy(v).to(dev) for c, v in tb.cols.items()}
+        names = list(cols)
+        pr = []
+        for p in tb.preds:
+            e = {"col": names.index(p.col), "kind": p.kind, "lo": p.lo, "hi": p.hi}
+            if p.kind == "subset":
+                e["bitmap"] = torch.from_numpy(
+                    np.asarray(p.bitmap, dtype=np.uint64).view(np.int64)).to(dev)
+                e["domain"] = p.domain
+            pr.append(e)
+        inc = q.incident(t)
+        tabs.append((tb, list(cols.values()), pr, [cols[c] for (_, _, c) in inc],
+                     [seeds[e] for (e, _, _) in inc],
+                     torch.zeros((r, b), dtype=torch.int64, device=dev),
+                     torch.zeros(1, dtype=torch.int64, device=dev)))
+
+    def step():
+        for (tb, cl, pr, keys, sd, cnt, ns) in tabs:
+            C.agms_build(tb.n_rows, cl, pr, keys, sd, cnt, ns, r, b)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    C.profile_enable(True)
+    a = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / args.steps
+    C.profile_enable(False)
+    kn, kms = C.profile_take("agms_build")
+    C.profile_take("fill_zero")
+    rows_g, est, flag = C.agms_estimate([x[5] for x in tabs], [x[6] for x in tabs])
+    torch.cuda.synchronize()
+    # Fast-AGMS on the same tables: build time and the merged estimate
+    dq = C.DeviceQuery(q, device=dev)
+    for _ in range(2):
+        dq.build()
+    torch.cuda.synchronize()
+    a2 = time.perf_counter()
+    for _ in range(args.steps):
+        dq.build()
+    torch.cuda.synchronize()
+    fast_ms = (time.perf_counter() - a2) / args.steps * 1e3
+    _, est_f, _ = dq.estimate([31])
+    torch.cuda.synchronize()
+    true = None
+    tp_ = os.path.join(ROOT, "tests", "golden", "job6a_truth.json")
+    if os.path.exists(tp_):
+        tr = json.load(open(tp_))
+        if tr.get("seed") == seed and 31 in tr["masks"]:
+            true = float(tr["true"][tr["masks"].index(31)])
+
+    def qe(e):
+        if true is None:
+            return None
+        a_, b_ = max(e, 1.0), max(true, 1.0)
+        return max(a_ / b_, b_ / a_)
+
+    n_sel = [int(x[6].item()) for x in tabs]
+    joins = [len(q.incident(t)) for t in range(len(q.tables))]
+    # per (selected row, basic sketch): per join one sign = 3 Horner steps
+    # of 6 operations + 3 for the residue's low bit + 1 multiply into the
+    # product; then 1 add
+    ops = sum(n * K * (22 * j + 1) for n, j in zip(n_sel, joins))
+    k_s = kms / args.steps / 1e3
+    tops = ops / k_s / 1e12
+    rows = sum(tb.n_rows for tb in q.tables)
+    e_a, e_f = float(est.item()), float(est_f[0].item())
+    out = {"metric": "filtered rows sketched/s (% HBM roofline); subplan estimates/s at q-error",
+           "value": rows / dt, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": "AGMS baseline on the 6a-shaped query: 5 tables "
+                                  "(47.1M rows), r x b = 7 x 16 composed sketches",
+                      "selected_rows": n_sel, "parallelism": "single-gpu"},
+           "roofline": {"bound": "alu", "achieved": tops, "peak": ALU_PEAK_TOPS,
+                        "unit": "TOP/s", "frac": tops / ALU_PEAK_TOPS, "traffic": None,
+                        "kernel": "agms_build", "launches_per_step": kn / args.steps,
+                        "kernel_ms_per_step": k_s * 1e3},
+           "fast_agms_build_ms": fast_ms,
+           "agms_over_fast_agms_build_time": dt * 1e3 / fast_ms,
+           "estimate": {"agms": e_a, "fast_agms_merged": e_f, "true": true,
+                        "qerror_agms": qe(e_a), "qerror_fast_agms_merged": qe(e_f),
+                        "exact_flag": int(flag.item())}}
     print(json.dumps(out), flush=True)
 
 

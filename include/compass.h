@@ -238,6 +238,46 @@ compass_status compass_estimate_chain3(const void *a, const void *p,
                                        hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * AGMS baseline (Section 4.1): r x b independent basic sketches per table,
+ * each one counter; composed over every join the table takes part in.
+ * --------------------------------------------------------------------- */
+
+/* compass_agms_build -- one scan of one table for one query: for every row
+ * that satisfies the conjunction of `preds`, basic sketch c = i * b + j
+ * adds the product over the table's joins e of xi^e_c(key_e), where xi^e_c
+ * is the +-1 variable of `joins[e].seeds` row c (a0..a3 of the degree-3
+ * polynomial above; b0, b1 are not used).  Every basic sketch sees every
+ * row: K = r * b sign evaluations per join per row.
+ *   joins     host array of n_joins (1 .. 4) specs: key column, key dtype,
+ *             seeds (host, r*b x 6); `counters` ignored.  Tables joined by
+ *             a join must use that join's seeds.
+ *   r, b      1 <= r <= 64, r * b <= 1024
+ *   counters  device, r x b int64; overwritten (accumulate 0) or added to
+ *   n_selected device int64, as for compass_sketch_build */
+compass_status compass_agms_build(int64_t n_rows, const void *const *pred_cols,
+                                  int32_t n_pred_cols, const compass_pred *preds,
+                                  int32_t n_preds,
+                                  const compass_sketch_spec *joins,
+                                  int32_t n_joins, int32_t r, int32_t b,
+                                  int32_t accumulate, int64_t *counters,
+                                  int64_t *n_selected, hipStream_t stream);
+
+/* compass_agms_estimate -- the query's estimate from its tables' AGMS
+ * sketches: basic estimate (i, j) = product over the tables of counter
+ * (i, j); row i's average = (exact 128-bit sum over j) / b, converted to
+ * double with round-to-nearest-even then divided in IEEE arithmetic; est =
+ * median of the r averages (even r: mean of the two middle ones); flag =
+ * COMPASS_FLAG_EXACT when the product of the tables' selected counts is
+ * below 2^127.
+ *   sketches, n_selected  host arrays of n_tables (1 .. 16) device pointers
+ *   row_sums  device, r values (may be NULL); est, flag device, 1 each */
+compass_status compass_agms_estimate(const int64_t *const *sketches,
+                                     const int64_t *const *n_selected,
+                                     int32_t n_tables, int32_t r, int32_t b,
+                                     compass_i128 *row_sums, double *est,
+                                     int32_t *flag, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batched build: the sketch builds of many tables (for instance every table
  * of hundreds of queries) as ONE persistent launch captured in a HIP graph.
  * Each job is exactly one compass_sketch_build call (same fields, same

@@ -595,8 +595,13 @@ void oracle_agms_sketch(const int64_t *const *keys, int64_t n,
                         const uint64_t *seeds, int32_t n_joins, int32_t K,
                         int64_t *counters)
 {
-    for (int64_t t = 0; t < n; ++t) {
-        for (int32_t c = 0; c < K; ++c) {
+    /* basic sketches are independent: threads split the counters, or
+     * the rows when there are few counters */
+#pragma omp parallel for schedule(dynamic, 1) if (K >= 8)
+    for (int32_t c = 0; c < K; ++c) {
+        int64_t sum = 0;
+#pragma omp parallel for reduction(+ : sum) if (K < 8)
+        for (int64_t t = 0; t < n; ++t) {
             int32_t prod = 1;
             for (int32_t e = 0; e < n_joins; ++e) {
                 int64_t bucket;
@@ -605,8 +610,9 @@ void oracle_agms_sketch(const int64_t *const *keys, int64_t n,
                             &bucket, &sign);
                 prod *= sign;
             }
-            counters[c] += prod;
+            sum += prod;
         }
+        counters[c] += sum;
     }
 }
 

@@ -104,6 +104,15 @@ def lib():
             vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
             ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
         L.compass_estimate_chain3.restype = ctypes.c_int32
+        L.compass_agms_build.argtypes = [
+            ctypes.c_int64, ctypes.POINTER(vp), ctypes.c_int32,
+            ctypes.POINTER(Pred), ctypes.c_int32, ctypes.POINTER(SketchSpec),
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+        L.compass_agms_build.restype = ctypes.c_int32
+        L.compass_agms_estimate.argtypes = [
+            ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32,
+            ctypes.c_int32, vp, vp, vp, vp]
+        L.compass_agms_estimate.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -227,6 +236,46 @@ def sketch_build_2d(n_rows: int, pred_cols, preds, key1, seeds1, key2, seeds2,
         ctypes.byref(specs[1]), int(d), int(w1), int(w2), int(counter_bits),
         1 if accumulate else 0, ctypes.c_void_p(counters.data_ptr()),
         ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))
+
+
+def agms_build(n_rows: int, pred_cols, preds, keys, seeds, counters,
+               n_selected: torch.Tensor, r: int, b: int, accumulate: bool = False,
+               stream=None):
+    """AGMS sketch (Section 4.1) of one table: keys/seeds one entry per join
+    (device key tensor, (r*b, 6) uint64 seeds); counters device (r, b) int64."""
+    cols, ncol, parr, np_ = _marshal_preds(pred_cols, preds)
+    nj = len(keys)
+    sarr = (SketchSpec * nj)()
+    keep = []
+    for e in range(nj):
+        a = np.ascontiguousarray(np.asarray(seeds[e], dtype=np.uint64).reshape(-1))
+        keep.append(a)
+        sarr[e].key_col = keys[e].data_ptr()
+        sarr[e].key_dtype = _dtype_code(keys[e])
+        sarr[e].seeds = a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        sarr[e].counters = None
+    _check(lib().compass_agms_build(
+        int(n_rows), cols, ncol, parr, np_, sarr, nj, int(r), int(b),
+        1 if accumulate else 0, ctypes.c_void_p(counters.data_ptr()),
+        ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))
+
+
+def agms_estimate(sketches, n_selected, stream=None):
+    """AGMS estimate from the tables' (r, b) int64 sketches and their device
+    selected counts; returns device (row_sums (r, 2) int64, est (1,), flag (1,))."""
+    r, b = sketches[0].shape
+    nt = len(sketches)
+    dev = sketches[0].device
+    sk = (ctypes.c_void_p * nt)(*[x.data_ptr() for x in sketches])
+    ns = (ctypes.c_void_p * nt)(*[x.data_ptr() for x in n_selected])
+    rows = torch.empty((r, 2), dtype=torch.int64, device=dev)
+    est = torch.empty(1, dtype=torch.float64, device=dev)
+    flag = torch.empty(1, dtype=torch.int32, device=dev)
+    vp = ctypes.c_void_p
+    _check(lib().compass_agms_estimate(sk, ns, nt, int(r), int(b), vp(rows.data_ptr()),
+                                       vp(est.data_ptr()), vp(flag.data_ptr()),
+                                       _stream(stream)))
+    return rows, est, flag
 
 
 def estimate_chain3(a, p, b, n_a, n_p, n_b, counter_bits: int = 32,

@@ -21,6 +21,7 @@
 #include "estimate_buffers.hpp"
 #include "estimate_params.hpp"
 #include "partition_params.hpp"
+#include "agms_params.hpp"
 
 namespace compass {
 // kernels (build_kernels.hip, estimate_kernels.hip)
@@ -52,6 +53,9 @@ hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
 hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st);
 hipError_t launch_chain3(const ChainArgs &a, uint64_t *row_est, double *est,
                          int32_t *flags, hipStream_t st);
+hipError_t launch_agms_build(const AgmsParams &P, int n_blocks, hipStream_t st);
+hipError_t launch_agms_estimate(const AgmsEstArgs &a, uint64_t *row_sums,
+                                double *est, int32_t *flag, hipStream_t st);
 }  // namespace compass
 
 using namespace compass;
@@ -1088,6 +1092,124 @@ extern "C" compass_status compass_estimate_chain3(
   ProfScope ps("chain3", stream);
   HIP_OK(launch_chain3(c, reinterpret_cast<uint64_t *>(row_est), est, flags,
                        stream));
+  return COMPASS_OK;
+}
+
+// ---------------------------------------------------------------------
+// AGMS baseline (Section 4.1)
+// ---------------------------------------------------------------------
+extern "C" compass_status compass_agms_build(
+    int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
+    const compass_pred *preds, int32_t n_preds,
+    const compass_sketch_spec *joins, int32_t n_joins, int32_t r, int32_t b,
+    int32_t accumulate, int64_t *counters, int64_t *n_selected,
+    hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  if (n_rows < 0 || n_rows >= (1ll << 47))
+    return fail(COMPASS_E_RANGE, "n_rows %lld outside [0, 2^47)",
+                (long long)n_rows);
+  if (n_joins < 1 || n_joins > kAgmsMaxJoins)
+    return fail(COMPASS_E_ARG, "n_joins=%d outside [1, %d]", n_joins,
+                kAgmsMaxJoins);
+  if (r < 1 || r > 64 || b < 1 || r * b > kAgmsMaxCounters)
+    return fail(COMPASS_E_ARG, "r=%d in [1, 64], b=%d, r*b at most %d", r, b,
+                kAgmsMaxCounters);
+  if (n_preds < 0 || n_preds > kMaxPreds)
+    return fail(COMPASS_E_ARG, "n_preds=%d outside [0, %d]", n_preds,
+                kMaxPreds);
+  if (!joins || !counters || !n_selected || (n_preds > 0 && !preds))
+    return fail(COMPASS_E_ARG, "null pointer argument");
+  if (n_preds > 0 && n_rows > 0 && !pred_cols)
+    return fail(COMPASS_E_ARG, "null predicate column array");
+  BuildParams bp;
+  memset(&bp, 0, sizeof(bp));
+  compass_status st = fill_preds(bp, n_rows, pred_cols, n_pred_cols, preds, n_preds);
+  if (st != COMPASS_OK) return st;
+  const int K = r * b;
+  AgmsParams P;
+  memset(&P, 0, sizeof(P));
+  P.n_rows = n_rows;
+  P.n_preds = n_preds;
+  P.n_joins = n_joins;
+  P.K = K;
+  P.count_selected = 1;
+  P.n_selected = n_selected;
+  P.counters = counters;
+  memcpy(P.preds, bp.preds, sizeof(P.preds));
+  std::vector<RowSeeds> sd((size_t)n_joins * K);
+  for (int e = 0; e < n_joins; ++e) {
+    const compass_sketch_spec &k = joins[e];
+    if (!k.seeds || (n_rows > 0 && !k.key_col))
+      return fail(COMPASS_E_ARG, "join %d: null pointer", e);
+    if (k.key_dtype != COMPASS_I32 && k.key_dtype != COMPASS_I64)
+      return fail(COMPASS_E_ARG, "join %d: key dtype must be I32 or I64", e);
+    for (int c = 0; c < K; ++c) {
+      const uint64_t *q = k.seeds + 6 * (size_t)c;
+      for (int z = 0; z < 4; ++z)
+        if (q[z] >= kP61)
+          return fail(COMPASS_E_ARG, "join %d: seed of basic sketch %d is not "
+                      "below 2^61-1", e, c);
+      sd[(size_t)e * K + c] = RowSeeds{q[0], q[1], q[2], q[3], 0, 0};
+    }
+    P.keys[e].col = k.key_col;
+    P.keys[e].dtype = k.key_dtype;
+  }
+  DeviceState *ds;
+  st = device_state(&ds);
+  if (st != COMPASS_OK) return st;
+  void *scr;
+  const size_t bytes = sizeof(RowSeeds) * sd.size();
+  st = ensure_scratch(ds, bytes, &scr);
+  if (st != COMPASS_OK) return st;
+  st = upload(ds, scr, sd.data(), bytes, stream);
+  if (st != COMPASS_OK) return st;
+  P.seeds = reinterpret_cast<const RowSeeds *>(scr);
+  if (!accumulate) {
+    ProfScope ps("fill_zero", stream);
+    HIP_OK(launch_fill_zero(counters, (int64_t)K * 8, stream));
+    HIP_OK(launch_fill_zero(n_selected, 8, stream));
+  }
+  if (n_rows == 0) return COMPASS_OK;
+  const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
+  const int64_t blocks = std::min<int64_t>(tiles, 4ll * ds->n_cu);
+  P.rows_per_chunk = (tiles + blocks - 1) / blocks * kBuildTile;
+  const int64_t chunks = (n_rows + P.rows_per_chunk - 1) / P.rows_per_chunk;
+  ProfScope ps("agms_build", stream);
+  HIP_OK(launch_agms_build(P, (int)chunks, stream));
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_agms_estimate(
+    const int64_t *const *sketches, const int64_t *const *n_selected,
+    int32_t n_tables, int32_t r, int32_t b, compass_i128 *row_sums,
+    double *est, int32_t *flag, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  if (n_tables < 1 || n_tables > 16)
+    return fail(COMPASS_E_ARG, "n_tables=%d outside [1, 16]", n_tables);
+  if (r < 1 || r > 64 || b < 1 || r * b > kAgmsMaxCounters)
+    return fail(COMPASS_E_ARG, "r=%d in [1, 64], b=%d, r*b at most %d", r, b,
+                kAgmsMaxCounters);
+  if (!sketches || !n_selected || !est || !flag)
+    return fail(COMPASS_E_ARG, "null pointer argument");
+  AgmsEstArgs a;
+  memset(&a, 0, sizeof(a));
+  for (int t = 0; t < n_tables; ++t) {
+    if (!sketches[t] || !n_selected[t])
+      return fail(COMPASS_E_ARG, "table %d: null pointer", t);
+    a.sk[t] = sketches[t];
+    a.n_sel[t] = n_selected[t];
+  }
+  a.n_tables = n_tables;
+  a.r = r;
+  a.b = b;
+  DeviceState *ds;
+  compass_status st = device_state(&ds);
+  if (st != COMPASS_OK) return st;
+  ProfScope ps("agms_estimate", stream);
+  HIP_OK(launch_agms_estimate(a, reinterpret_cast<uint64_t *>(row_sums), est,
+                              flag, stream));
   return COMPASS_OK;
 }
 

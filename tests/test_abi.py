@@ -118,3 +118,42 @@ def test_chain3_validation(C, kw, status):
         None, v(8), v(8), v(0))
     assert r == status
     assert L.compass_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(r=0), 1), (dict(r=65), 1), (dict(b=0), 1), (dict(r=32, b=33), 1),
+    (dict(n_joins=0), 1), (dict(n_joins=5), 1), (dict(n_rows=-1), 2),
+    (dict(bad_seed=True), 1), (dict(null_counters=True), 1),
+])
+def test_agms_build_validation(C, kw, status):
+    L = C.lib()
+    r, b = kw.get("r", 3), kw.get("b", 4)
+    nj = kw.get("n_joins", 2)
+    seeds = np.zeros((max(r * b, 1), 6), np.uint64)
+    if kw.get("bad_seed"):
+        seeds[-1, 1] = (1 << 61) - 1
+    specs = (C.SketchSpec * max(nj, 1))()
+    arr = np.ascontiguousarray(seeds.reshape(-1))
+    for e in range(max(nj, 1)):
+        specs[e].key_col = 16
+        specs[e].key_dtype = C.I32
+        specs[e].seeds = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    rc = L.compass_agms_build(kw.get("n_rows", 10), None, 0, None, 0, specs, nj, r, b, 0,
+                              ctypes.c_void_p(0 if kw.get("null_counters") else 48),
+                              ctypes.c_void_p(64), ctypes.c_void_p(0))
+    assert rc == status
+    assert L.compass_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_tables=0), 1), (dict(n_tables=17), 1), (dict(r=0), 1), (dict(b=2000), 1),
+])
+def test_agms_estimate_validation(C, kw, status):
+    L = C.lib()
+    nt = kw.get("n_tables", 2)
+    sk = (ctypes.c_void_p * 17)(*([16] * 17))
+    ns = (ctypes.c_void_p * 17)(*([32] * 17))
+    rc = L.compass_agms_estimate(sk, ns, nt, kw.get("r", 3), kw.get("b", 4), None,
+                                 ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(0))
+    assert rc == status
+    assert L.compass_last_error().decode() != ""
