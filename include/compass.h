@@ -117,6 +117,26 @@ compass_status compass_sketch_build(int64_t n_rows,
                                     int32_t counter_bits, int32_t accumulate,
                                     int64_t *n_selected, hipStream_t stream);
 
+/* compass_sketch_build_select -- compass_sketch_build that also
+ * materialises the selection output (Section 3, "Partitioned query
+ * execution": the selection output is kept when it is small): the indices
+ * of the qualifying rows, plus row_base, are written to rows_out[k] for the
+ * k-th qualifying row seen (in no particular order) while k < rows_cap, and
+ * *rows_count counts every qualifying row (zeroed first unless
+ * accumulate).  The output is complete, without duplicates, iff the final
+ * *rows_count <= rows_cap; beyond that the caller drops it (the sketches
+ * and *n_selected are unaffected).
+ *   rows_out    device int64, rows_cap entries (may be NULL if rows_cap = 0)
+ *   rows_count  device int64
+ *   row_base    0 <= row_base < 2^47 (e.g. the first row of this partition) */
+compass_status compass_sketch_build_select(
+    int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
+    const compass_pred *preds, int32_t n_preds,
+    const compass_sketch_spec *sketches, int32_t n_sketches, int32_t d,
+    int32_t w, int32_t counter_bits, int32_t accumulate, int64_t *n_selected,
+    int64_t *rows_out, int64_t rows_cap, int64_t *rows_count, int64_t row_base,
+    hipStream_t stream);
+
 /* A query join graph with its attribute sketches (Section 3, "Plan
  * enumeration": estimates take only the two-way sketches as input).
  * Edge e joins tables edge_u[e] and edge_v[e]; its id is e, and a lower id

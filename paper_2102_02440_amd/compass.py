@@ -104,6 +104,12 @@ def lib():
             vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
             ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
         L.compass_estimate_chain3.restype = ctypes.c_int32
+        L.compass_sketch_build_select.argtypes = [
+            ctypes.c_int64, ctypes.POINTER(vp), ctypes.c_int32,
+            ctypes.POINTER(Pred), ctypes.c_int32, ctypes.POINTER(SketchSpec),
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+            ctypes.c_int32, vp, vp, ctypes.c_int64, vp, ctypes.c_int64, vp]
+        L.compass_sketch_build_select.restype = ctypes.c_int32
         L.compass_agms_build.argtypes = [
             ctypes.c_int64, ctypes.POINTER(vp), ctypes.c_int32,
             ctypes.POINTER(Pred), ctypes.c_int32, ctypes.POINTER(SketchSpec),
@@ -188,6 +194,34 @@ def sketch_build(n_rows: int, pred_cols, preds, keys, seeds, counters,
         int(n_rows), cols, ncol, parr, np_, sarr, ns, int(d), int(w),
         int(counter_bits), 1 if accumulate else 0,
         ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))
+
+
+def sketch_build_select(n_rows: int, pred_cols, preds, keys, seeds, counters,
+                        n_selected: torch.Tensor, d: int, w: int, rows_out,
+                        rows_count: torch.Tensor, row_base: int = 0,
+                        counter_bits: int = 32, accumulate: bool = False,
+                        stream=None):
+    """sketch_build that also writes the qualifying row indices (plus
+    row_base) to rows_out (device int64, its length is the capacity) and
+    counts them in rows_count (device int64)."""
+    cols, ncol, parr, np_ = _marshal_preds(pred_cols, preds)
+    ns = len(keys)
+    sarr = (SketchSpec * ns)()
+    keep = []
+    for i in range(ns):
+        sd = np.ascontiguousarray(np.asarray(seeds[i], dtype=np.uint64).reshape(-1))
+        keep.append(sd)
+        sarr[i].key_col = keys[i].data_ptr()
+        sarr[i].key_dtype = _dtype_code(keys[i])
+        sarr[i].seeds = sd.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        sarr[i].counters = counters[i].data_ptr()
+    cap = rows_out.numel() if rows_out is not None else 0
+    _check(lib().compass_sketch_build_select(
+        int(n_rows), cols, ncol, parr, np_, sarr, ns, int(d), int(w),
+        int(counter_bits), 1 if accumulate else 0,
+        ctypes.c_void_p(n_selected.data_ptr()),
+        ctypes.c_void_p(rows_out.data_ptr() if cap else 0), int(cap),
+        ctypes.c_void_p(rows_count.data_ptr()), int(row_base), _stream(stream)))
 
 
 def _marshal_preds(pred_cols, preds):

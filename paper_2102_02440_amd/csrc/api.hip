@@ -271,14 +271,12 @@ static compass_status fill_preds(BuildParams &base, int64_t n_rows,
   return COMPASS_OK;
 }
 
-extern "C" compass_status compass_sketch_build(
+static compass_status sketch_build_impl(
     int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
     const compass_pred *preds, int32_t n_preds,
     const compass_sketch_spec *sketches, int32_t n_sketches, int32_t d,
     int32_t w, int32_t counter_bits, int32_t accumulate, int64_t *n_selected,
-    hipStream_t stream) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  g_err.clear();
+    const RowSink &sink, hipStream_t stream) {
   if (n_rows < 0 || n_rows >= (1ll << 47))
     return fail(COMPASS_E_RANGE, "n_rows %lld outside [0, 2^47)",
                 (long long)n_rows);
@@ -307,6 +305,7 @@ extern "C" compass_status compass_sketch_build(
   base.counter_bits = counter_bits;
   base.n_selected = n_selected;
   base.bm = make_bucket_mod((uint32_t)w);
+  base.sink = sink;
   compass_status st0 = fill_preds(base, n_rows, pred_cols, n_pred_cols, preds, n_preds);
   if (st0 != COMPASS_OK) return st0;
   for (int s = 0; s < n_sketches; ++s) {
@@ -339,6 +338,7 @@ extern "C" compass_status compass_sketch_build(
         HIP_OK(launch_fill_zero(sketches[s].counters,
                                 (int64_t)d * w * (counter_bits / 8), stream));
     HIP_OK(launch_fill_zero(n_selected, 8, stream));
+    if (sink.out) HIP_OK(launch_fill_zero(sink.count, 8, stream));
   }
   if (n_rows == 0) return COMPASS_OK;
 
@@ -510,6 +510,48 @@ extern "C" compass_status compass_sketch_build(
                               counter_bits, accumulate, stream));
   }
   return COMPASS_OK;
+}
+
+extern "C" compass_status compass_sketch_build(
+    int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
+    const compass_pred *preds, int32_t n_preds,
+    const compass_sketch_spec *sketches, int32_t n_sketches, int32_t d,
+    int32_t w, int32_t counter_bits, int32_t accumulate, int64_t *n_selected,
+    hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  return sketch_build_impl(n_rows, pred_cols, n_pred_cols, preds, n_preds,
+                           sketches, n_sketches, d, w, counter_bits, accumulate,
+                           n_selected, RowSink{}, stream);
+}
+
+extern "C" compass_status compass_sketch_build_select(
+    int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
+    const compass_pred *preds, int32_t n_preds,
+    const compass_sketch_spec *sketches, int32_t n_sketches, int32_t d,
+    int32_t w, int32_t counter_bits, int32_t accumulate, int64_t *n_selected,
+    int64_t *rows_out, int64_t rows_cap, int64_t *rows_count, int64_t row_base,
+    hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  if (!rows_count || (rows_cap > 0 && !rows_out) || rows_cap < 0)
+    return fail(COMPASS_E_ARG, "selection output: null pointer or negative "
+                "capacity");
+  if (row_base < 0 || row_base >= (1ll << 47))
+    return fail(COMPASS_E_RANGE, "row_base outside [0, 2^47)");
+  RowSink sink;
+  sink.out = rows_cap > 0 ? rows_out : nullptr;
+  sink.cap = rows_cap;
+  sink.count = reinterpret_cast<unsigned long long *>(rows_count);
+  sink.row_base = row_base;
+  if (!sink.out) {
+    // nothing can be written, but the count is still kept
+    sink.out = reinterpret_cast<int64_t *>(rows_count);
+    sink.cap = 0;
+  }
+  return sketch_build_impl(n_rows, pred_cols, n_pred_cols, preds, n_preds,
+                           sketches, n_sketches, d, w, counter_bits, accumulate,
+                           n_selected, sink, stream);
 }
 
 // ---------------------------------------------------------------------

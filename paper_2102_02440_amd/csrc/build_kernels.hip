@@ -70,7 +70,10 @@ __global__ __launch_bounds__(kBuildThreads) void scan_sketch_kernel(
   __syncthreads();
   const int64_t row0 = chunk * P.rows_per_chunk;
   const int64_t row1 = min(row0 + P.rows_per_chunk, P.n_rows);
-  const uint64_t sel = scan_rows(job, row0, row1, sb, se, cnt, queue, &s_qn);
+  RowSink sink = P.sink;
+  if (gi != 0) sink.out = nullptr;  // one slice group writes the rows
+  const uint64_t sel =
+      scan_rows(job, row0, row1, sb, se, cnt, queue, &s_qn, sink);
   // partial counters of this chunk -> its slab rows (plain coalesced
   // stores; the reduction kernel sums the chunks in a fixed order)
   const size_t S = (size_t)P.n_slices_total;
@@ -149,6 +152,16 @@ __global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
             if (q < qtot) dst[q] = v[u];
           }
         }
+      }
+      if (P.sink.out) {  // selection output
+        __syncthreads();  // every lane has read s_off
+        if (threadIdx.x == 0)
+          s_off = atomicAdd(P.sink.count, (unsigned long long)qtot);
+        __syncthreads();
+        const int64_t roff = (int64_t)s_off;
+        for (int q = threadIdx.x; q < qtot; q += kBuildThreads)
+          if (roff + q < P.sink.cap)
+            P.sink.out[roff + q] = P.sink.row_base + row_begin + queue[q];
       }
       sel += (uint64_t)qtot;
       qtot = 0;

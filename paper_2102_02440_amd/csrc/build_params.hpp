@@ -32,6 +32,15 @@ struct PredDev {
   Scalar32 lo, hi;
 };
 
+// Optional materialisation of the selection output (the qualifying row
+// indices) next to the sketches: rows go to out[count ...] while below cap.
+struct RowSink {
+  int64_t *out;                  // nullptr: not materialised
+  int64_t cap;
+  unsigned long long *count;     // device: rows seen so far (all calls)
+  int64_t row_base;              // added to every row index
+};
+
 struct KeyDev {
   const void *col;
   int32_t dtype;
@@ -60,6 +69,7 @@ struct BuildParams {
                         // slice_base + l = sketch * d + row
   int32_t group_begin[kMaxLaunchGroups + 1];  // 32-bit: scalar loads
   RowSeeds seeds[kMaxLaunchSlices];
+  RowSink sink;         // written by the workgroups of slice group 0 only
 };
 
 static_assert(sizeof(BuildParams) <= 4096, "kernel arguments must stay small");

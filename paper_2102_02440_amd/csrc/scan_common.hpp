@@ -134,7 +134,8 @@ __device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
 template <class J>
 __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
                               int sb, int se, int32_t *cnt, int32_t *queue,
-                              int32_t *s_qn) {
+                              int32_t *s_qn, RowSink sink = RowSink{}) {
+  __shared__ unsigned long long s_roff;
   constexpr int kRowsPerThread = kBuildRowsPerThread;
   constexpr int kTile = kBuildTile;
   // the slice range is the same in every lane: say so, so that the slice
@@ -160,6 +161,15 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
     const int qn = compact_tile<J, kRowsPerThread>(job, base, nt, n_preds,
                                                    queue, s_qn);
     sel += (uint64_t)qn;
+    if (sink.out) {  // selection output: one reservation per tile
+      if (threadIdx.x == 0)
+        s_roff = qn ? atomicAdd(sink.count, (unsigned long long)qn) : 0ull;
+      __syncthreads();
+      const int64_t off = (int64_t)s_roff;
+      for (int q = threadIdx.x; q < qn; q += kBuildThreads)
+        if (off + q < sink.cap)
+          sink.out[off + q] = sink.row_base + base + (dense ? q : queue[q]);
+    }
 
     // survivors handled by this thread: entries threadIdx.x + k * threads
     int ridx[kRowsPerThread];

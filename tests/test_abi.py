@@ -157,3 +157,20 @@ def test_agms_estimate_validation(C, kw, status):
                                  ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.c_void_p(0))
     assert rc == status
     assert L.compass_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(cap=-1), 1), (dict(null_count=True), 1), (dict(null_out=True), 1),
+    (dict(row_base=-5), 2), (dict(d=0), 1),
+])
+def test_build_select_validation(C, kw, status):
+    L = C.lib()
+    d = kw.get("d", 3)
+    s, keep = _spec(C, d, np.zeros((max(d, 1), 6), np.uint64))
+    rc = L.compass_sketch_build_select(
+        10, None, 0, None, 0, s, 1, d, 64, 32, 0, ctypes.c_void_p(64),
+        ctypes.c_void_p(0 if kw.get("null_out") else 128), kw.get("cap", 100),
+        ctypes.c_void_p(0 if kw.get("null_count") else 256), kw.get("row_base", 0),
+        ctypes.c_void_p(0))
+    assert rc == status
+    assert L.compass_last_error().decode() != ""
