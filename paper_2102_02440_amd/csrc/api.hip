@@ -45,6 +45,8 @@ hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
                             const EstBuffers &B, hipStream_t st);
 hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
                        int stage_bytes, hipStream_t st);
+hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
+                            hipStream_t st);
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
                            const EstBuffers &B, hipStream_t st);
 hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
@@ -609,13 +611,13 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
   }
   // BFS spanning tree from the lowest table, edges in id order
   std::map<int, int> node_of;
-  std::vector<PlanNode> nodes;
-  nodes.push_back(PlanNode());
-  nodes[0].table = tabs[0];
+  std::vector<PlanNode> base;
+  base.push_back(PlanNode());
+  base[0].table = tabs[0];
   node_of[tabs[0]] = 0;
-  std::vector<char> is_tree(g->n_edges, 0);
-  for (size_t head = 0; head < nodes.size(); ++head) {
-    const int t = nodes[head].table;
+  std::vector<char> base_tree(g->n_edges, 0);
+  for (size_t head = 0; head < base.size(); ++head) {
+    const int t = base[head].table;
     for (int e : edges) {
       int other;
       if (g->edge_u[e] == t)
@@ -627,220 +629,257 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
       if (node_of.count(other)) continue;
       PlanNode nd;
       nd.table = other;
-      node_of[other] = (int)nodes.size();
-      is_tree[e] = 1;
-      nodes.push_back(nd);
+      node_of[other] = (int)base.size();
+      base_tree[e] = 1;
+      base.push_back(nd);
     }
   }
-  if (nodes.size() != tabs.size())
+  if (base.size() != tabs.size())
     return fail(COMPASS_E_GRAPH, "sub-plan %d (mask 0x%llx) is not connected",
                 spi, (unsigned long long)mask);
   std::vector<int> cuts;
   for (int e : edges)
-    if (!is_tree[e]) cuts.push_back(e);
+    if (!base_tree[e]) cuts.push_back(e);
 
-  // undirected tree adjacency
-  const int nn = (int)nodes.size();
-  std::vector<std::vector<std::pair<int, int>>> adj(nn);
-  for (int e : edges) {
-    if (!is_tree[e]) continue;
-    const int a = node_of[g->edge_u[e]], b = node_of[g->edge_v[e]];
-    adj[a].push_back({b, e});
-    adj[b].push_back({a, e});
-  }
-  int root = 0;
-  int cut_u = -1, cut_v = -1, cut_e = -1;
-  bool supported = true;
-  if (cuts.size() > 1) supported = false;
-  if (cuts.size() == 1) {
-    cut_e = cuts[0];
-    cut_u = node_of[g->edge_u[cut_e]];
-    cut_v = node_of[g->edge_v[cut_e]];
-    // apex: a common tree neighbour of both endpoints (a triangle)
-    int apex = -1;
-    bool direct = false;
-    for (auto &pa : adj[cut_u]) {
-      if (pa.first == cut_v) direct = true;
-      for (auto &pb : adj[cut_v])
-        if (pa.first == pb.first) apex = pa.first;
+  const int nn = (int)base.size();
+  auto build_adj = [&](const std::vector<char> &tree) {
+    std::vector<std::vector<std::pair<int, int>>> adj(nn);
+    for (int e : edges) {
+      if (!tree[e]) continue;
+      const int a = node_of[g->edge_u[e]], b = node_of[g->edge_v[e]];
+      adj[a].push_back({b, e});
+      adj[b].push_back({a, e});
     }
-    if (direct || apex < 0) {
-      supported = false;
-    } else {
-      // Any triangle edge may be the cut one (the estimate is the same
-      // number); cut the edge opposite the vertex of fewest sub-plan edges,
-      // so that the apex sweep has as few children as possible (two, when
-      // no other edge meets that vertex).
-      auto degree = [&](int node) {
-        int k = 0;
-        for (int e : edges)
-          k += g->edge_u[e] == nodes[node].table || g->edge_v[e] == nodes[node].table;
-        return k;
-      };
-      auto tree_edge = [&](int a, int b) {
-        for (auto &p : adj[a])
-          if (p.first == b) return p.second;
-        return -1;
-      };
-      int best = apex;
-      if (degree(cut_u) < degree(best)) best = cut_u;
-      if (degree(cut_v) < degree(best)) best = cut_v;
-      if (best != apex) {
-        const int other = best == cut_u ? cut_v : cut_u;
-        const int new_cut = tree_edge(apex, other);
-        is_tree[cut_e] = 1;
-        is_tree[new_cut] = 0;
-        for (auto &v : adj) v.clear();
-        for (int e : edges) {
-          if (!is_tree[e]) continue;
-          const int a = node_of[g->edge_u[e]], b = node_of[g->edge_v[e]];
-          adj[a].push_back({b, e});
-          adj[b].push_back({a, e});
-        }
-        cut_e = new_cut;
-        cut_u = node_of[g->edge_u[new_cut]];
-        cut_v = node_of[g->edge_v[new_cut]];
-      }
-      root = best;
-    }
-  }
-  if (!supported) {
+    return adj;
+  };
+  const auto base_adj = build_adj(base_tree);
+
+  // Roots to plan.  A tree is rooted at its lowest table.  A triangle may
+  // cut any of its three edges (the estimate is the same number); the
+  // apex (the vertex opposite the cut) should have as few children as
+  // possible, so every triangle vertex of fewest sub-plan edges is a
+  // candidate.  All candidates are planned; on the device the one whose
+  // table has the fewest selected rows runs and the others' blocks return
+  // at once (fewer rows give smaller counters with fewer distinct
+  // magnitudes, hence fewer and longer same-child runs in the sweep).
+  std::vector<int> cand;
+  int apex = -1, cut0 = -1;
+  if (cuts.size() > 1) {
     sp.type = kSpUnsupported;
     pl.sps.push_back(sp);
     return COMPASS_OK;
   }
-  // orient the tree at `root`
-  std::vector<int> order;
-  std::vector<char> seen(nn, 0);
-  order.push_back(root);
-  seen[root] = 1;
-  for (size_t h = 0; h < order.size(); ++h) {
-    const int a = order[h];
-    std::vector<std::pair<int, int>> nb = adj[a];
-    std::sort(nb.begin(), nb.end(),
-              [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
-                return x.second < y.second;
-              });
-    for (auto &p : nb) {
-      if (seen[p.first]) continue;
-      seen[p.first] = 1;
-      nodes[p.first].parent = a;
-      nodes[p.first].parent_edge = p.second;
-      nodes[a].children.push_back(p.first);
-      nodes[a].child_edges.push_back(p.second);
-      order.push_back(p.first);
+  if (cuts.size() == 1) {
+    cut0 = cuts[0];
+    const int cu = node_of[g->edge_u[cut0]], cv = node_of[g->edge_v[cut0]];
+    // apex: a common tree neighbour of both endpoints (a triangle)
+    bool direct = false;
+    for (auto &pa : base_adj[cu]) {
+      if (pa.first == cv) direct = true;
+      for (auto &pb : base_adj[cv])
+        if (pa.first == pb.first) apex = pa.first;
     }
-  }
-  if (cut_e >= 0) {
-    nodes[cut_u].cut_edge = cut_e;
-    nodes[cut_v].cut_edge = cut_e;
-  }
-  for (int k = nn - 1; k >= 0; --k) {
-    PlanNode &nd = nodes[order[k]];
-    for (int c : nd.children)
-      nd.height = std::max(nd.height, nodes[c].height + 1);
-    if ((int)nd.children.size() > kMaxChild) {
+    if (direct || apex < 0) {
       sp.type = kSpUnsupported;
       pl.sps.push_back(sp);
       return COMPASS_OK;
     }
+    auto degree = [&](int node) {
+      int k = 0;
+      for (int e : edges)
+        k += g->edge_u[e] == base[node].table || g->edge_v[e] == base[node].table;
+      return k;
+    };
+    const int dmin = std::min(degree(apex), std::min(degree(cu), degree(cv)));
+    for (int x : {apex, cu, cv})
+      if (degree(x) == dmin) cand.push_back(x);
+    std::sort(cand.begin(), cand.end(), [&](int x, int y) {
+      return base[x].table < base[y].table;
+    });
+  } else {
+    cand.push_back(0);
   }
-  // tasks: every non-root node emits a message slot; cut endpoints also a
-  // cut-constant slot
-  std::vector<int> msg_slot(nn, -1), cmsg_slot(nn, -1);
-  for (int a = 0; a < nn; ++a) {
-    if (a != root) msg_slot[a] = pl.n_msg_slots++;
-    if (nodes[a].cut_edge >= 0) cmsg_slot[a] = pl.n_msg_slots++;
+
+  // orient every candidate; drop those with a node beyond kMaxChild children
+  struct Oriented {
+    std::vector<PlanNode> nodes;
+    std::vector<int> order;
+    int root, cut_e, cut_u, cut_v;
+  };
+  std::vector<Oriented> ors;
+  for (int root : cand) {
+    Oriented o;
+    o.nodes = base;
+    o.root = root;
+    o.cut_e = cut0;
+    std::vector<char> tree = base_tree;
+    if (cut0 >= 0 && root != apex) {
+      // cut the triangle edge opposite `root` instead
+      const int cu = node_of[g->edge_u[cut0]], cv = node_of[g->edge_v[cut0]];
+      const int other = root == cu ? cv : cu;
+      int new_cut = -1;
+      for (auto &p : base_adj[apex])
+        if (p.first == other) new_cut = p.second;
+      tree[cut0] = 1;
+      tree[new_cut] = 0;
+      o.cut_e = new_cut;
+    }
+    const auto adj = build_adj(tree);
+    o.cut_u = o.cut_v = -1;
+    if (o.cut_e >= 0) {
+      o.cut_u = node_of[g->edge_u[o.cut_e]];
+      o.cut_v = node_of[g->edge_v[o.cut_e]];
+    }
+    std::vector<char> seen(nn, 0);
+    o.order.push_back(root);
+    seen[root] = 1;
+    for (size_t h = 0; h < o.order.size(); ++h) {
+      const int a = o.order[h];
+      std::vector<std::pair<int, int>> nb = adj[a];
+      std::sort(nb.begin(), nb.end(),
+                [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+                  return x.second < y.second;
+                });
+      for (auto &p : nb) {
+        if (seen[p.first]) continue;
+        seen[p.first] = 1;
+        o.nodes[p.first].parent = a;
+        o.nodes[p.first].parent_edge = p.second;
+        o.nodes[a].children.push_back(p.first);
+        o.nodes[a].child_edges.push_back(p.second);
+        o.order.push_back(p.first);
+      }
+    }
+    if (o.cut_e >= 0) {
+      o.nodes[o.cut_u].cut_edge = o.cut_e;
+      o.nodes[o.cut_v].cut_edge = o.cut_e;
+    }
+    bool fits = true;
+    for (int k = nn - 1; k >= 0; --k) {
+      PlanNode &nd = o.nodes[o.order[k]];
+      for (int c : nd.children)
+        nd.height = std::max(nd.height, o.nodes[c].height + 1);
+      if ((int)nd.children.size() > kMaxChild) fits = false;
+    }
+    if (fits) ors.push_back(std::move(o));
   }
-  for (int k = nn - 1; k >= 0; --k) {
-    const int a = order[k];
-    PlanNode &nd = nodes[a];
-    NodeTask T;
-    memset(&T, 0, sizeof(T));
-    T.m = (int)nd.children.size();
-    T.parent_side = -1;
-    T.cut_side = -1;
-    T.msg_slot = msg_slot[a];
-    T.cmsg_slot = cmsg_slot[a];
-    for (int c = 0; c < T.m; ++c) {
-      const int e = nd.child_edges[c];
-      T.child_side[c] = pl.side_of(nd.table, e);
-      T.child_eid[c] = e;
-      T.child_msg[c] = msg_slot[nd.children[c]];
-      T.child_cut[c] = -1;
-      pl.side_used[T.child_side[c]] = 1;
+  if (ors.empty()) {
+    sp.type = kSpUnsupported;
+    pl.sps.push_back(sp);
+    return COMPASS_OK;
+  }
+  TaskGuard gd;
+  memset(&gd, 0, sizeof(gd));
+  gd.n = (int)ors.size();
+  for (size_t k = 0; k < ors.size(); ++k) gd.tab[k] = base[ors[k].root].table;
+
+  for (size_t ko = 0; ko < ors.size(); ++ko) {
+    Oriented &o = ors[ko];
+    std::vector<PlanNode> &nodes = o.nodes;
+    const int root = o.root, cut_e = o.cut_e, cut_u = o.cut_u, cut_v = o.cut_v;
+    gd.self = (int)ko;
+    // tasks: every non-root node emits a message slot; cut endpoints also a
+    // cut-constant slot
+    std::vector<int> msg_slot(nn, -1), cmsg_slot(nn, -1);
+    for (int a = 0; a < nn; ++a) {
+      if (a != root) msg_slot[a] = pl.n_msg_slots++;
+      if (nodes[a].cut_edge >= 0) cmsg_slot[a] = pl.n_msg_slots++;
     }
-    int nl = T.m;
-    if (a != root) {
-      T.parent_side = pl.side_of(nd.table, nd.parent_edge);
-      T.parent_eid = nd.parent_edge;
-      pl.side_used[T.parent_side] = 1;
-      ++nl;
-    }
-    if (nd.cut_edge >= 0) {
-      T.cut_side = pl.side_of(nd.table, nd.cut_edge);
-      T.cut_eid = nd.cut_edge;
-      pl.side_used[T.cut_side] = 1;
-      ++nl;
-    }
-    if (a != root) {
-      T.mode = kModeMessage;
-    } else if (cut_e < 0) {
-      T.mode = kModeTreeRoot;
-      T.out_slot = pl.n_x_slots++;
-      sp.type = kSpTree;
-      sp.x_slot = T.out_slot;
-    } else {
-      T.mode = kModeTriRootPrep;
-      T.out_slot = pl.n_prep_slots++;
+    for (int k = nn - 1; k >= 0; --k) {
+      const int a = o.order[k];
+      PlanNode &nd = nodes[a];
+      NodeTask T;
+      memset(&T, 0, sizeof(T));
+      T.guard = gd;
+      T.m = (int)nd.children.size();
+      T.parent_side = -1;
+      T.cut_side = -1;
+      T.msg_slot = msg_slot[a];
+      T.cmsg_slot = cmsg_slot[a];
       for (int c = 0; c < T.m; ++c) {
-        const int ch = nd.children[c];
-        if (ch == cut_u) T.child_cut[c] = 0;
-        if (ch == cut_v) T.child_cut[c] = 1;
+        const int e = nd.child_edges[c];
+        T.child_side[c] = pl.side_of(nd.table, e);
+        T.child_eid[c] = e;
+        T.child_msg[c] = msg_slot[nd.children[c]];
+        T.child_cut[c] = -1;
+        pl.side_used[T.child_side[c]] = 1;
       }
-      pl.Lprep = std::max(pl.Lprep, T.m * pl.w);
-      TriTask tr;
-      memset(&tr, 0, sizeof(tr));
-      tr.prep_slot = T.out_slot;
-      tr.L = T.m * pl.w;
-      tr.m = T.m;
-      tr.cut_eid = cut_e;
-      tr.cut_side[0] = pl.side_of(nodes[cut_u].table, cut_e);
-      tr.cut_side[1] = pl.side_of(nodes[cut_v].table, cut_e);
-      tr.cut_cmsg[0] = cmsg_slot[cut_u];
-      tr.cut_cmsg[1] = cmsg_slot[cut_v];
-      for (int c = 0; c < T.m; ++c) {
-        if (nd.children[c] == cut_u) {
-          tr.cut_child[0] = c;
-          tr.cut_peid[0] = nd.child_edges[c];
-        }
-        if (nd.children[c] == cut_v) {
-          tr.cut_child[1] = c;
-          tr.cut_peid[1] = nd.child_edges[c];
-        }
-        // tables of the child's subtree (bounds for narrow arithmetic)
-        uint64_t sub = 0;
-        std::vector<int> stack{nd.children[c]};
-        while (!stack.empty()) {
-          const int x = stack.back();
-          stack.pop_back();
-          sub |= 1ull << nodes[x].table;
-          for (int y : nodes[x].children) stack.push_back(y);
-        }
-        tr.child_tables[c] = sub;
+      int nl = T.m;
+      if (a != root) {
+        T.parent_side = pl.side_of(nd.table, nd.parent_edge);
+        T.parent_eid = nd.parent_edge;
+        pl.side_used[T.parent_side] = 1;
+        ++nl;
       }
-      tr.root_table = nd.table;
-      const int zb = (pl.w + kLaneThreads - 1) / kLaneThreads;
-      tr.partial_slot = pl.n_partial_slots;
-      pl.n_partial_slots += zb;
-      sp.type = kSpTriangle;
-      sp.x_slot = tr.partial_slot;
-      sp.n_partials = zb;
-      pl.tris.push_back(tr);
+      if (nd.cut_edge >= 0) {
+        T.cut_side = pl.side_of(nd.table, nd.cut_edge);
+        T.cut_eid = nd.cut_edge;
+        pl.side_used[T.cut_side] = 1;
+        ++nl;
+      }
+      if (a != root) {
+        T.mode = kModeMessage;
+      } else if (cut_e < 0) {
+        T.mode = kModeTreeRoot;
+        T.out_slot = pl.n_x_slots++;
+        sp.type = kSpTree;
+        sp.x_slot = T.out_slot;
+      } else {
+        T.mode = kModeTriRootPrep;
+        T.out_slot = pl.n_prep_slots++;
+        for (int c = 0; c < T.m; ++c) {
+          const int ch = nd.children[c];
+          if (ch == cut_u) T.child_cut[c] = 0;
+          if (ch == cut_v) T.child_cut[c] = 1;
+        }
+        pl.Lprep = std::max(pl.Lprep, T.m * pl.w);
+        TriTask tr;
+        memset(&tr, 0, sizeof(tr));
+        tr.guard = gd;
+        tr.prep_slot = T.out_slot;
+        tr.L = T.m * pl.w;
+        tr.m = T.m;
+        tr.cut_eid = cut_e;
+        tr.cut_side[0] = pl.side_of(nodes[cut_u].table, cut_e);
+        tr.cut_side[1] = pl.side_of(nodes[cut_v].table, cut_e);
+        tr.cut_cmsg[0] = cmsg_slot[cut_u];
+        tr.cut_cmsg[1] = cmsg_slot[cut_v];
+        for (int c = 0; c < T.m; ++c) {
+          if (nd.children[c] == cut_u) {
+            tr.cut_child[0] = c;
+            tr.cut_peid[0] = nd.child_edges[c];
+          }
+          if (nd.children[c] == cut_v) {
+            tr.cut_child[1] = c;
+            tr.cut_peid[1] = nd.child_edges[c];
+          }
+          // tables of the child's subtree (bounds for narrow arithmetic)
+          uint64_t sub = 0;
+          std::vector<int> stack{nd.children[c]};
+          while (!stack.empty()) {
+            const int x = stack.back();
+            stack.pop_back();
+            sub |= 1ull << nodes[x].table;
+            for (int y : nodes[x].children) stack.push_back(y);
+          }
+          tr.child_tables[c] = sub;
+        }
+        tr.root_table = nd.table;
+        const int zb = (pl.w + kLaneThreads - 1) / kLaneThreads;
+        // every candidate writes the same partial sums (only one runs)
+        if (ko == 0) {
+          sp.type = kSpTriangle;
+          sp.x_slot = pl.n_partial_slots;
+          sp.n_partials = zb;
+          pl.n_partial_slots += zb;
+        }
+        tr.partial_slot = sp.x_slot;
+        pl.tris.push_back(tr);
+      }
+      if (T.m > 0) pl.Lmax = std::max(pl.Lmax, nl * pl.w);
+      pl.tasks.push_back(T);
+      pl.task_level.push_back(nd.height);
     }
-    if (T.m > 0) pl.Lmax = std::max(pl.Lmax, nl * pl.w);
-    pl.tasks.push_back(T);
-    pl.task_level.push_back(nd.height);
   }
   pl.sps.push_back(sp);
   return COMPASS_OK;
@@ -943,6 +982,9 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_prep = carve(sizeof(TriElem) * np * d * lp);
   const size_t o_prepn = carve(sizeof(TriElemN) * np * d * lp);
   const size_t o_prepz = carve(sizeof(int32_t) * np * d);
+  const size_t o_tkey = carve(sizeof(uint32_t) * np * d * lp);
+  const size_t o_tpre = carve(sizeof(TriPre) * np * d * (lp + 1));
+  const size_t o_tord = carve(sizeof(int32_t) * np * d);
   const size_t o_part = carve(16ull * std::max(1, pl.n_partial_slots) * d);
   void *scratch;
   st = ensure_scratch(ds, off, &scratch);
@@ -973,6 +1015,9 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.prep = reinterpret_cast<TriElem *>(base + o_prep);
   B.prepn = reinterpret_cast<TriElemN *>(base + o_prepn);
   B.prep_z = reinterpret_cast<int32_t *>(base + o_prepz);
+  B.tkey = reinterpret_cast<uint32_t *>(base + o_tkey);
+  B.tpre = reinterpret_cast<TriPre *>(base + o_tpre);
+  B.tord = reinterpret_cast<int32_t *>(base + o_tord);
   B.partial = reinterpret_cast<u128 *>(base + o_part);
   B.counter_bits = g->counter_bits;
   B.d = d;
@@ -1001,6 +1046,11 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
     ProfScope ps("node", stream);
     HIP_OK(launch_node(dtasks + level_off[lv], (int)levels[lv].size(), B,
                        stage, stream));
+  }
+  if (!pl.tris.empty()) {
+    ProfScope ps("tri_order", stream);
+    HIP_OK(launch_tri_order(reinterpret_cast<const TriTask *>(base + o_tris),
+                            (int)pl.tris.size(), B, stream));
   }
   if (!pl.tris.empty()) {
     ProfScope ps("tri_lane", stream);

@@ -76,6 +76,27 @@ __device__ __forceinline__ int lower_bound_u64(const uint64_t *a, int n,
   return lo;
 }
 
+// Whether this rooting of a sub-plan is the one that runs: among the
+// planned candidates, the one whose table has the fewest selected rows
+// (ties: the earlier candidate).
+__device__ __forceinline__ bool guard_on(int n, int self, int t0, int t1,
+                                         int t2, const int64_t *n_sel) {
+  if (n <= 1) return true;
+  const int tab[3] = {t0, t1, t2};
+  int best = 0;
+  int64_t nb = n_sel[t0];
+  for (int k = 1; k < n; ++k) {
+    const int64_t v = n_sel[tab[k]];
+    if (v < nb) {
+      nb = v;
+      best = k;
+    }
+  }
+  return best == self;
+}
+#define COMPASS_GUARD_ON(G, NSEL) \
+  guard_on((G).n, (G).self, (G).tab[0], (G).tab[1], (G).tab[2], (NSEL))
+
 // |v| saturated below 2^47 (every sketch built from < 2^47 rows satisfies
 // this; saturation only keeps sort keys well-formed for foreign input)
 __device__ __forceinline__ uint64_t abs_u64(int64_t v) {
@@ -168,6 +189,7 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
   __shared__ u128 sh[kNodeThreads];
   const NodeTask *Tg = tasks + blockIdx.x;
   const NodeTask T = *Tg;
+  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // uniform
   const int row = blockIdx.y;
   const int w = B.w;
   const int m = T.m;
@@ -263,7 +285,7 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
         n.mu = (int64_t)(uint64_t)e.mu;
         n.vm = (int64_t)((uint64_t)e.v * (uint64_t)e.mu);
         n.run_lo = 0;  // set below
-        n.pad = 0;
+        n.run_hi = 0;  // set by tri_order_kernel
         outn[pos] = n;
       }
       // the list is ascending in |v|: its zero counters form a prefix, and
@@ -442,6 +464,7 @@ __device__ __forceinline__ void fast_elem(FastRun &r, uint32_t kf, int32_t v,
 
 typedef const __attribute__((address_space(4))) TriTask ConstTask;
 typedef const __attribute__((address_space(4))) TriElemN ConstElemN;
+typedef const __attribute__((address_space(4))) TriPre ConstPre;
 
 enum { kTriFast = 0, kTriNarrow = 1, kTriWide = 2 };
 
@@ -473,23 +496,170 @@ __device__ int tri_path(ConstTask &T, const EstBuffers &B) {
   return small && T.m == 2 ? kTriFast : kTriNarrow;
 }
 
+// ---------------------------------------------------------------------
+// run ordering of two-child apexes: grid (n_tri, d), kOrderThreads lanes
+// ---------------------------------------------------------------------
+// Within one same-child run the sweep needs, for the lane's threshold kf,
+// the sums over the run's elements whose child key is below kf.  Order
+// every run (cut at the zero prefix) by ascending key, keeping the runs
+// where they are, and take exclusive prefix sums over the reordered list:
+// then the elements below kf of a run piece [lo, hi] are the positions
+// [lo, p) with p found by binary search, and their sums are differences of
+// prefix sums.  A run's elements may be reordered freely: within a run the
+// other child's running sum is fixed, so only the run's totals matter.
+// Keys sort as (run start - z) << 45 | key << 14 | position - z, which
+// needs L - z <= kOrderCap; longer lists keep the element-wise sweep.
+__global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
+    const TriTask *tasks, EstBuffers B) {
+  extern __shared__ uint64_t okey[];  // kOrderCap keys
+  const TriTask &T = tasks[blockIdx.x];
+  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
+  if (tri_path(*(ConstTask *)&T, B) != kTriFast) return;
+  const int row = blockIdx.y;
+  const size_t slot_row = (size_t)T.prep_slot * B.d + row;
+  const int z = B.prep_z[slot_row];
+  const int L = T.L;
+  const int n = L - z;
+  if (n > kOrderCap) {
+    if (threadIdx.x == 0) B.tord[slot_row] = 0;
+    return;
+  }
+  TriElemN *el = B.prepn + slot_row * (size_t)B.Lprep;
+  int n2 = 1;
+  while (n2 < n) n2 <<= 1;
+  for (int q = threadIdx.x; q < n2; q += kOrderThreads) {
+    uint64_t k = ~0ull;
+    if (q < n) {
+      const TriElemN &e = el[z + q];
+      const uint64_t rl = (uint64_t)(max(e.run_lo, z) - z);
+      k = (rl << 45) | ((uint64_t)(e.kc & 0x7FFFFFFFu) << 14) | (uint64_t)q;
+    }
+    okey[q] = k;
+  }
+  __syncthreads();
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < (n2 >> 1); t += kOrderThreads) {
+        const int i = 2 * t - (t & (j - 1));
+        const int ixj = i + j;
+        const uint64_t a = okey[i], b = okey[ixj];
+        if ((a > b) == ((i & k) == 0)) {
+          okey[i] = b;
+          okey[ixj] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // the run ends, the ordered keys, and each thread's consecutive chunk of
+  // prefix sums
+  uint32_t *tk = B.tkey + slot_row * (size_t)B.Lprep;
+  TriPre *E = B.tpre + slot_row * (size_t)(B.Lprep + 1);
+  const int per = (n + kOrderThreads - 1) / kOrderThreads;
+  const int q0 = min(n, (int)threadIdx.x * per);
+  const int q1 = min(n, q0 + per);
+  int64_t sm = 0, sx = 0;
+  uint32_t sv = 0;
+  for (int q = q0; q < q1; ++q) {
+    const uint64_t k = okey[q];
+    const uint64_t rf = k >> 45;
+    // last sorted index of this run: first key of a later run, minus one
+    int lo = q + 1, hi = n;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((okey[mid] >> 45) <= rf) lo = mid + 1; else hi = mid;
+    }
+    const TriElemN &src = el[z + (int)(k & 0x3FFF)];
+    tk[z + q] = (uint32_t)((k >> 14) & 0x7FFFFFFFull);
+    sm = (int64_t)((uint64_t)sm + (uint64_t)src.mu);
+    sx = (int64_t)((uint64_t)sx + (uint64_t)src.vm);
+    sv += (uint32_t)src.v;
+    // run_hi lives in a field nothing else in this kernel reads
+    el[z + q].run_hi = z + lo - 1;
+  }
+  __shared__ int64_t scm[kOrderThreads], scx[kOrderThreads];
+  __shared__ uint32_t scv[kOrderThreads];
+  scm[threadIdx.x] = sm;
+  scx[threadIdx.x] = sx;
+  scv[threadIdx.x] = sv;
+  __syncthreads();
+  for (int off = 1; off < kOrderThreads; off <<= 1) {
+    int64_t am = 0, ax = 0;
+    uint32_t av = 0;
+    if ((int)threadIdx.x >= off) {
+      am = scm[threadIdx.x - off];
+      ax = scx[threadIdx.x - off];
+      av = scv[threadIdx.x - off];
+    }
+    __syncthreads();
+    scm[threadIdx.x] = (int64_t)((uint64_t)scm[threadIdx.x] + (uint64_t)am);
+    scx[threadIdx.x] = (int64_t)((uint64_t)scx[threadIdx.x] + (uint64_t)ax);
+    scv[threadIdx.x] += av;
+    __syncthreads();
+  }
+  // exclusive start of my chunk, then the chunk's running sums
+  uint64_t em = (uint64_t)scm[threadIdx.x] - (uint64_t)sm;
+  uint64_t ex = (uint64_t)scx[threadIdx.x] - (uint64_t)sx;
+  uint32_t ev = scv[threadIdx.x] - sv;
+  for (int q = q0; q < q1; ++q) {
+    TriPre o;
+    o.m = (int64_t)em;
+    o.x = (int64_t)ex;
+    o.v = (int32_t)ev;
+    o.pad = 0;
+    E[z + q] = o;
+    const TriElemN &src = el[z + (int)(okey[q] & 0x3FFF)];
+    em += (uint64_t)src.mu;
+    ex += (uint64_t)src.vm;
+    ev += (uint32_t)src.v;
+  }
+  if (threadIdx.x == kOrderThreads - 1) {
+    TriPre o;
+    o.m = scm[threadIdx.x];
+    o.x = scx[threadIdx.x];
+    o.v = (int32_t)scv[threadIdx.x];
+    o.pad = 0;
+    E[L] = o;
+    B.tord[slot_row] = 1;
+  }
+}
+
 // Two-child apexes: grid (n_tri, d, ceil(w / kLaneThreads)), kFastSegs
 // segments of the sweep per block (segment s = threads s * kLaneThreads ..).
 // Cutting the descending sweep into segments is exact: a segment's runs see
 // the other child's running sum of the earlier segments plus their own, so
 //   G = sum_s [ G_s + A0(before s) * X1_s + A1(before s) * X0_s ]
 // with X_c the segment's sum of the run terms of child c (v * mu summed).
+// A run piece is summed element by element, or, when the run is long and
+// tri_order_kernel has ordered the list, by one binary search over the
+// run-ordered keys (staged in LDS) and two prefix-sum reads.
 constexpr int kFastSegs = 4;
+constexpr int kSearchMin = 8;  // shortest run summed by search
 
 struct SegOut {
   u128 G;
   int64_t A0, A1, X0, X1;
 };
+static_assert(sizeof(SegOut) * kFastSegs * kLaneThreads <= kFastStageBytes,
+              "segment results reuse the key stage");
+
+// first index in [0, n) whose key is >= kf, n >= 1 (uniform trip count)
+__device__ __forceinline__ int lds_lower_bound(const uint32_t *k, int n,
+                                               uint32_t kf) {
+  int base = 0;
+  while (n > 1) {
+    const int half = n >> 1;
+    base = k[base + half] < kf ? base + half : base;
+    n -= half;
+  }
+  return base + (k[base] < kf ? 1 : 0);
+}
 
 __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     const TriTask *tasks, EstBuffers B) {
-  __shared__ SegOut so[kFastSegs][kLaneThreads];
+  extern __shared__ __align__(16) uint32_t skey[];  // run-ordered keys of [z, L)
   ConstTask &T = *((ConstTask *)tasks + blockIdx.x);
+  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // another rooting runs
   if (tri_path(T, B) != kTriFast) return;  // uniform: tri_lane_kernel's block
   const int row = blockIdx.y;
   const int lane = threadIdx.x % kLaneThreads;
@@ -504,6 +674,14 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   const int len = T.L - z;
   const int top = T.L - 1 - (int)((int64_t)len * seg / kFastSegs);
   const int bottom = T.L - (int)((int64_t)len * (seg + 1) / kFastSegs);
+  const bool ordered = B.tord[slot_row] != 0;  // then len <= kOrderCap
+  const uint32_t *tk = B.tkey + slot_row * (size_t)B.Lprep;
+  const TriPre *E = B.tpre + slot_row * (size_t)(B.Lprep + 1);
+  if (ordered) {
+    for (int q = threadIdx.x; q < len; q += kLaneThreads * kFastSegs)
+      skey[q] = tk[z + q];
+    __syncthreads();
+  }
 
   // child slot 0 / 1 state; key < kf  <=>  kappa below the cut element's
   // (ties in |v| go to the lower edge id)
@@ -531,34 +709,54 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   int pos = top;
   while (pos >= bottom) {
     const uint32_t c = el[pos].kc >> 31;  // the run's child (uniform)
-    const int lo = max(el[pos].run_lo, bottom);
+    const int run_lo = el[pos].run_lo;
+    const int lo = max(run_lo, bottom);
     const uint32_t kf = c ? kf1 : kf0;
     FastRun r;
-    r.mb = r.xb = 0;
-    r.vb = r.nb = 0;
-    r.vrun = r.nrun = 0;
-    for (; pos - (kGroup - 1) >= lo; pos -= kGroup) {
-      int32_t v[kGroup];
-      uint32_t kc[kGroup];
-      int64_t mu[kGroup], vm[kGroup];
+    if (ordered && el[pos].run_hi - max(run_lo, z) + 1 >= kSearchMin) {
+      // piece [lo, pos] of a run-ordered run: its elements below kf are
+      // the positions [lo, p)
+      const int p = lo + lds_lower_bound(skey + (lo - z), pos - lo + 1, kf);
+      ConstPre &e0 = ((ConstPre *)E)[lo];
+      const int64_t m0 = e0.m, x0 = e0.x;
+      const int32_t v0 = e0.v;
+      const int32_t v1 = ((ConstPre *)E)[pos + 1].v;
+      const TriPre ep = E[p];
+      r.mb = (int64_t)((uint64_t)ep.m - (uint64_t)m0);
+      r.xb = (int64_t)((uint64_t)ep.x - (uint64_t)x0);
+      r.vb = (int32_t)((uint32_t)ep.v - (uint32_t)v0);
+      r.nb = p - lo;
+      r.vrun = (int32_t)((uint32_t)v1 - (uint32_t)v0);
+      r.nrun = pos - lo + 1;
+      pos = lo - 1;
+    } else {
+      r.mb = r.xb = 0;
+      r.vb = r.nb = 0;
+      r.vrun = r.nrun = 0;
+      for (; pos - (kGroup - 1) >= lo; pos -= kGroup) {
+        int32_t v[kGroup];
+        uint32_t kc[kGroup];
+        int64_t mu[kGroup], vm[kGroup];
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u) {
-        ConstElemN &e = el[pos - u];
-        v[u] = e.v;
-        kc[u] = e.kc;
-        mu[u] = e.mu;
-        vm[u] = e.vm;
+        for (int u = 0; u < kGroup; ++u) {
+          ConstElemN &e = el[pos - u];
+          v[u] = e.v;
+          kc[u] = e.kc;
+          mu[u] = e.mu;
+          vm[u] = e.vm;
+        }
+        // issue the whole group's scalar loads before the first use
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+          __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u)
+          fast_elem(r, kf, v[u], kc[u], mu[u], vm[u]);
       }
-      // issue the whole group's scalar loads before the first use
-#pragma unroll
-      for (int u = 0; u < kGroup; ++u)
-        __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
-#pragma unroll
-      for (int u = 0; u < kGroup; ++u) fast_elem(r, kf, v[u], kc[u], mu[u], vm[u]);
-    }
-    for (; pos >= lo; --pos) {
-      ConstElemN &e = el[pos];
-      fast_elem(r, kf, e.v, e.kc, e.mu, e.vm);
+      for (; pos >= lo; --pos) {
+        ConstElemN &e = el[pos];
+        fast_elem(r, kf, e.v, e.kc, e.mu, e.vm);
+      }
     }
     // close the run: its terms times the other child's running sum
     const int64_t cc = c ? C1 : C0;
@@ -574,6 +772,8 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
       X0 += x;
     }
   }
+  __syncthreads();  // the key stage becomes the segment results
+  SegOut (*so)[kLaneThreads] = reinterpret_cast<SegOut (*)[kLaneThreads]>(skey);
   SegOut &mine = so[seg][lane];
   mine.G = G;
   mine.A0 = A0;
@@ -612,6 +812,7 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
   // the task is the same for every lane: read it through the constant
   // address space so its fields live in scalar registers
   ConstTask &T = *((ConstTask *)tasks + blockIdx.x);
+  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // another rooting runs
   const int path = tri_path(T, B);
   if (path == kTriFast) return;  // uniform: tri_fast_kernel's block
   const bool narrow = path == kTriNarrow;
@@ -836,11 +1037,19 @@ hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
   return hipGetLastError();
 }
 
+hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(tri_order_kernel, dim3(n, B.d), dim3(kOrderThreads),
+                     (size_t)kOrderCap * sizeof(uint64_t), st, tasks, B);
+  return hipGetLastError();
+}
+
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
                            const EstBuffers &B, hipStream_t st) {
   // each (task, row, z) block does its work in exactly one of the two
   hipLaunchKernelGGL(tri_fast_kernel, dim3(n, B.d, zblocks),
-                     dim3(kLaneThreads * kFastSegs), 0, st, tasks, B);
+                     dim3(kLaneThreads * kFastSegs), (size_t)kFastStageBytes,
+                     st, tasks, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(tri_lane_kernel, dim3(n, B.d, zblocks),

@@ -10,8 +10,22 @@ constexpr int kSortThreads = 1024;
 constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
 constexpr int kNodeStageBytes = 96 * 1024;  // node merge: staged magnitudes
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderCap = 16384;  // longest two-child apex list run-ordered
+constexpr int kFastStageBytes = kOrderCap * 4;  // its keys, staged in LDS
 
 enum { kModeMessage = 0, kModeTreeRoot = 1, kModeTriRootPrep = 2 };
+
+// Several rootings of one sub-plan may be planned (the apex candidates of
+// a triangle); each task carries the candidates' tables, and only the
+// rooting whose table has the fewest selected rows (ties: the earlier
+// candidate) does work.  n <= 1: always runs.
+struct TaskGuard {
+  int32_t n;
+  int32_t self;
+  int32_t tab[3];
+  int32_t pad;
+};
 enum { kSpSingle = 0, kSpTree = 1, kSpTriangle = 2, kSpUnsupported = 3 };
 
 // One node of one sub-plan's rooted spanning tree (blockIdx.y = sketch row).
@@ -20,6 +34,7 @@ enum { kSpSingle = 0, kSpTree = 1, kSpTriangle = 2, kSpUnsupported = 3 };
 // then the cut-edge bucket list (query points of the cut constants) if
 // cut_side >= 0.
 struct NodeTask {
+  TaskGuard guard;
   int32_t mode;
   int32_t m;
   int32_t parent_side, parent_eid;
@@ -39,6 +54,7 @@ struct NodeTask {
 // cut-edge bucket J; the two cut endpoints' messages switch to their cut
 // constant when their parent-edge element ranks above the cut element.
 struct TriTask {
+  TaskGuard guard;
   int32_t prep_slot;        // root merged-list arrays
   int32_t L;                // root merged-list length
   int32_t m;                // root children

@@ -279,6 +279,37 @@ def test_triangle_sweep_paths(oracle, extra_child, inflate):
 
 
 @gpu
+@pytest.mark.parametrize("shape", ["long_runs", "zipf_apex", "above_order_cap"])
+def test_triangle_run_order(oracle, shape):
+    """Two-child triangle apexes whose merged list is ordered run by run and
+    summed by binary search (runs of 8 or more elements), next to short
+    runs summed element by element, and a list longer than the ordering
+    holds (w = 16384: element-wise only)."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng({"long_runs": 5, "zipf_apex": 6,
+                                 "above_order_cap": 7}[shape])
+    w, d = {"long_runs": (4096, 2), "zipf_apex": (2048, 3),
+            "above_order_cap": (16384, 1)}[shape]
+    n = {"long_runs": [20000, 200000, 100000], "zipf_apex": [300000, 50000, 80000],
+         "above_order_cap": [40000, 30000, 20000]}[shape]
+    tables = []
+    for t in range(3):
+        if shape == "zipf_apex" and t == 0:
+            k0 = (rng.zipf(1.3, n[t]) % 5000).astype(np.int32)
+            k1 = (rng.zipf(1.1, n[t]) % 5000).astype(np.int32)
+        else:
+            k0 = rng.integers(0, 50000, n[t]).astype(np.int32)
+            k1 = rng.integers(0, 50000, n[t]).astype(np.int32)
+        tables.append(W.Table("t%d" % t, {"k0": k0, "k1": k1}, []))
+    edges = [W.Edge(0, "k0", 1, "k0"), W.Edge(0, "k1", 2, "k0"),
+             W.Edge(1, "k1", 2, "k1")]
+    q = W.Query(tables, edges, d, w, W.draw_seeds(rng, 3, d), 32)
+    masks = [0b111, 0b011, 0b110]
+    check_query(oracle, q, masks=masks, name="triangle run order " + shape)
+
+
+@gpu
 def test_job6a_full_size(oracle):
     """Full-size 6a-shaped workload (ci 36M, mk 4.5M, t 2.5M, n 4.2M, k 134k;
     d=7, w=8192) in the launch configuration the benchmark times.
