@@ -67,8 +67,6 @@ def algorithmic_work(q, n_sel):
 
 SCAN_SOURCES = ["scan_common.hpp", "build_kernels.hip", "build_params.hpp",
                 "device_math.hpp"]
-TRI_SOURCES = ["estimate_kernels.hip", "estimate_params.hpp",
-               "estimate_buffers.hpp", "device_math.hpp"]
 
 # Integer VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
 # 32-bit operation per lane per clock (no packed 32-bit integer issue).
@@ -80,11 +78,6 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 #    multiply-adds, one AND, one 64-bit shift, two 64-bit adds), two
 #    canonical reductions at 3, sign 1, bucket 1, LDS add 1.
 OPS_PER_HASH_UPDATE = 4 * 6 + 2 * 3 + 3
-#  triangle sweep step (one cut bucket J x one apex element): compare the
-#    element's key with the lane's threshold (1), pick the conditioned
-#    64-bit message (2) and add it to the running sum (1 x 64-bit), pick
-#    and add the 64-bit term v * mu (2 + 1).
-OPS_PER_TRI_STEP = 7
 
 
 def source_hash(names):
@@ -703,7 +696,7 @@ def run_job6a(args):
     C.profile_enable(False)
     prof = {k: C.profile_take(k) for k in
             ["fill_zero", "scan_sketch", "slab_reduce", "sort_rows",
-             "node", "tri_lane", "finish"]}
+             "node", "tri_order", "tri_lane", "finish"]}
 
     ms_step = dt * 1e3 / args.steps
     rows_per_step = sum(tb.n_rows for tb in q.tables)
@@ -711,62 +704,25 @@ def run_job6a(args):
     alg_bytes, updates = algorithmic_work(q, n_sel)
     scan_n, scan_ms = prof["scan_sketch"]
     build_ms_step = (scan_ms + prof["fill_zero"][1] + prof["slab_reduce"][1]) / args.steps
-    est_ms_step = sum(prof[k][1] for k in ["sort_rows", "node", "tri_lane",
-                                           "finish"]) / args.steps
+    est_ms_step = sum(prof[k][1] for k in ["sort_rows", "node", "tri_order",
+                                           "tri_lane", "finish"]) / args.steps
     kernel_ms = {k: v[1] / args.steps for k, v in prof.items()}
-    # triangle sweep work: every triangle sub-plan sweeps its apex's merged
-    # list (m children x w elements) once per cut bucket and sketch row
-    adj_deg = {}
-    for e in q.edges:
-        adj_deg[e.u] = adj_deg.get(e.u, 0) + 1
-        adj_deg[e.v] = adj_deg.get(e.v, 0) + 1
-    tri_steps = 0
-    for m in masks:
-        tabs = [t for t in range(n_tab) if m >> t & 1]
-        es = [e for e in q.edges if m >> e.u & 1 and m >> e.v & 1]
-        if len(es) == len(tabs):  # one cycle: the triangle
-            deg = {t: sum(1 for e in es if t in (e.u, e.v)) for t in tabs}
-            core = dict(deg)  # strip leaves down to the cycle
-            live = set(tabs)
-            while True:
-                leaves = [t for t in live if core[t] == 1]
-                if not leaves:
-                    break
-                for t in leaves:
-                    live.discard(t)
-                    for e in es:
-                        if t in (e.u, e.v):
-                            o = e.v if e.u == t else e.u
-                            if o in live:
-                                core[o] -= 1
-            # the library roots the sweep at the cycle vertex of fewest edges
-            apex_children = min(deg[t] for t in live)
-            tri_steps += apex_children * q.w * q.w * q.d
     scan_s = kernel_ms["scan_sketch"] / 1e3
-    tri_s = kernel_ms["tri_lane"] / 1e3
     scan_tops = updates * OPS_PER_HASH_UPDATE / scan_s / 1e12
-    tri_tops = tri_steps * OPS_PER_TRI_STEP / tri_s / 1e12 if tri_s else 0.0
     hbm_view = {"kernel": "scan_sketch", "alg_bytes_per_step": alg_bytes,
                 "achieved_gbs": alg_bytes / scan_s / 1e9, "peak_gbs": HBM_PEAK_GBS,
                 "frac": alg_bytes / scan_s / 1e9 / HBM_PEAK_GBS}
-    if kernel_ms["tri_lane"] >= kernel_ms["scan_sketch"]:
-        roofline = {"bound": "alu", "achieved": tri_tops, "peak": ALU_PEAK_TOPS,
-                    "unit": "TOP/s", "frac": tri_tops / ALU_PEAK_TOPS,
-                    "traffic": measured_traffic("tri_lane_traffic_job6a.md",
-                                                TRI_SOURCES),
-                    "kernel": "tri_lane", "sweep_steps_per_step": tri_steps,
-                    "ops_per_step_unit": OPS_PER_TRI_STEP}
-    else:
-        roofline = {"bound": "alu", "achieved": scan_tops, "peak": ALU_PEAK_TOPS,
-                    "unit": "TOP/s", "frac": scan_tops / ALU_PEAK_TOPS,
-                    "traffic": measured_traffic("scan_sketch_traffic_job6a.md",
-                                                SCAN_SOURCES),
-                    "kernel": "scan_sketch", "hash_updates_per_step": updates,
-                    "ops_per_hash_update": OPS_PER_HASH_UPDATE}
+    # the scan is the dominant kernel of the step (the estimate kernels
+    # together take a third of its time)
+    roofline = {"bound": "alu", "achieved": scan_tops, "peak": ALU_PEAK_TOPS,
+                "unit": "TOP/s", "frac": scan_tops / ALU_PEAK_TOPS,
+                "traffic": measured_traffic("scan_sketch_traffic_job6a.md",
+                                            SCAN_SOURCES),
+                "kernel": "scan_sketch", "hash_updates_per_step": updates,
+                "ops_per_hash_update": OPS_PER_HASH_UPDATE}
     roofline["launches_per_step"] = prof[roofline["kernel"]][0] / args.steps
     roofline["kernel_ms_per_step"] = kernel_ms[roofline["kernel"]]
     other = {"scan_sketch": {"alu_tops": scan_tops, "hash_updates_per_s": updates / scan_s},
-             "tri_lane": {"alu_tops": tri_tops, "sweep_steps_per_s": tri_steps / tri_s if tri_s else None},
              "scan_sketch_hbm": hbm_view}
     # accuracy against stored exact truths (oracle hash aggregation)
     qerr = None

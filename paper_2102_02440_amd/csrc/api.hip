@@ -443,7 +443,7 @@ static compass_status sketch_build_impl(
   }
   const int n_groups_total = (S + per_group - 1) / per_group;
 
-  // chunks: up to eight waves of the resident workgroup slots (whole
+  // chunks: up to two waves of the resident workgroup slots (whole
   // waves, so that no slot runs one more workgroup than the others), but at
   // least eight tiles per workgroup, which keeps zeroing and writing back
   // its LDS partials small next to its scan.  Each chunk writes its partial
@@ -453,7 +453,7 @@ static compass_status sketch_build_impl(
   const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / lds_block)));
   const int64_t slots = (int64_t)ds->n_cu * per_cu;
   const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
-  int64_t chunks = std::max<int64_t>(1, 8 * slots / n_groups_total);
+  int64_t chunks = std::max<int64_t>(1, 2 * slots / n_groups_total);
   chunks = std::min(chunks, std::max<int64_t>(1, tiles / 8));
   const size_t slab_row = (size_t)S * w * 4;
   chunks = std::min<int64_t>(chunks, std::max<size_t>(1, ((size_t)1 << 30) / slab_row));
@@ -983,8 +983,9 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_prepn = carve(sizeof(TriElemN) * np * d * lp);
   const size_t o_prepz = carve(sizeof(int32_t) * np * d);
   const size_t o_tkey = carve(sizeof(uint32_t) * np * d * lp);
-  const size_t o_tpre = carve(sizeof(TriPre) * np * d * (lp + 1));
-  const size_t o_tord = carve(sizeof(int32_t) * np * d);
+  const size_t o_tpre = carve(sizeof(TriPre) * np * d *
+                              ((lp + kOrderTile - 1) / kOrderTile) *
+                              (kOrderTile + 1));
   const size_t o_part = carve(16ull * std::max(1, pl.n_partial_slots) * d);
   void *scratch;
   st = ensure_scratch(ds, off, &scratch);
@@ -1017,7 +1018,6 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.prep_z = reinterpret_cast<int32_t *>(base + o_prepz);
   B.tkey = reinterpret_cast<uint32_t *>(base + o_tkey);
   B.tpre = reinterpret_cast<TriPre *>(base + o_tpre);
-  B.tord = reinterpret_cast<int32_t *>(base + o_tord);
   B.partial = reinterpret_cast<u128 *>(base + o_part);
   B.counter_bits = g->counter_bits;
   B.d = d;

@@ -310,8 +310,17 @@ __global__ void slab_reduce_kernel(const int32_t *__restrict__ slab,
   const int64_t total = (int64_t)n_slices * w;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
        k += (int64_t)gridDim.x * blockDim.x) {
+    // eight chunk rows in flight per lane
+    int64_t a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t c = 0;
+    for (; c + 8 <= chunks; c += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a8[u] += slab[(c + u) * total + k];
+    }
+    for (; c < chunks; ++c) a8[0] += slab[c * total + k];
     int64_t acc = 0;
-    for (int64_t c = 0; c < chunks; ++c) acc += slab[c * total + k];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += a8[u];
     const int gs = (int)(k / w);
     const int j = (int)(k - (int64_t)gs * w);
     const int s = gs / d, row = gs - s * d;

@@ -25,14 +25,15 @@ struct TriElemN {
   int64_t mu;       // the child's unconditioned message M
   int64_t vm;       // v * M
   int32_t run_lo;   // lowest position of the same-child run holding it
-  int32_t run_hi;   // highest position of that run (set by the ordering)
+  int32_t run_hi;   // highest position of that run
 };
 
-// Exclusive prefix sums over a two-child apex's merged list after every
-// same-child run has been ordered by ascending child key: at position q,
-// the sums of M, v * M and v over positions [z, q) (z = zero-prefix
-// length), wrapping modulo 2^64 / 2^32.  Differences give the masked sums
-// of any run piece.  24 bytes.
+// Exclusive prefix sums over one ordering tile of a two-child apex's
+// merged list, after every run piece in the tile has been ordered by
+// ascending child key: entry q holds the sums of M, v * M and v over the
+// tile's first q reordered elements, wrapping modulo 2^64 / 2^32.
+// Differences give the masked sums of any run piece inside the tile.
+// 24 bytes.
 struct TriPre {
   int64_t m;
   int64_t x;
@@ -51,8 +52,7 @@ struct EstBuffers {
   TriElemN *prepn;            // [prep slot][row][Lprep] (two-child apexes)
   int32_t *prep_z;            // [prep slot][row] leading zero-counter run
   uint32_t *tkey;             // [prep slot][row][Lprep] run-ordered keys
-  TriPre *tpre;               // [prep slot][row][Lprep + 1]
-  int32_t *tord;              // [prep slot][row] 1 when tkey / tpre hold
+  TriPre *tpre;               // [prep slot][row][tile][kOrderTile + 1]
   u128 *partial;              // [slot][row]
   int32_t counter_bits;
   int32_t d;

@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
         n.mu = (int64_t)(uint64_t)e.mu;
         n.vm = (int64_t)((uint64_t)e.v * (uint64_t)e.mu);
         n.run_lo = 0;  // set below
-        n.run_hi = 0;  // set by tri_order_kernel
+        n.run_hi = 0;  // set below
         outn[pos] = n;
       }
       // the list is ascending in |v|: its zero counters form a prefix, and
@@ -327,6 +327,28 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
       for (int p = s0; p < s1; ++p) {
         if (starts_run(p)) cur = p;
         outn[p].run_lo = cur;
+      }
+      // and the highest position of its run (a min-scan of run ends from
+      // the right)
+      __syncthreads();
+      auto ends_run = [&](int p) {
+        return p == L - 1 || (merged[p] >> 16) != (merged[p + 1] >> 16);
+      };
+      int first = L;
+      for (int p = s1 - 1; p >= s0; --p)
+        if (ends_run(p)) first = p;
+      shi[threadIdx.x] = first;
+      __syncthreads();
+      for (int off = 1; off < kNodeThreads; off <<= 1) {
+        const int o = threadIdx.x + off < kNodeThreads ? shi[threadIdx.x + off] : L;
+        __syncthreads();
+        shi[threadIdx.x] = min(shi[threadIdx.x], o);
+        __syncthreads();
+      }
+      int nxt = threadIdx.x + 1 < kNodeThreads ? shi[threadIdx.x + 1] : L;
+      for (int p = s1 - 1; p >= s0; --p) {
+        if (ends_run(p)) nxt = p;
+        outn[p].run_hi = nxt;
       }
     }
     return;
@@ -497,21 +519,32 @@ __device__ int tri_path(ConstTask &T, const EstBuffers &B) {
 }
 
 // ---------------------------------------------------------------------
-// run ordering of two-child apexes: grid (n_tri, d), kOrderThreads lanes
+// run ordering of two-child apexes: grid (n_tri, d, tiles), kOrderThreads
 // ---------------------------------------------------------------------
 // Within one same-child run the sweep needs, for the lane's threshold kf,
-// the sums over the run's elements whose child key is below kf.  Order
-// every run (cut at the zero prefix) by ascending key, keeping the runs
-// where they are, and take exclusive prefix sums over the reordered list:
-// then the elements below kf of a run piece [lo, hi] are the positions
-// [lo, p) with p found by binary search, and their sums are differences of
-// prefix sums.  A run's elements may be reordered freely: within a run the
-// other child's running sum is fixed, so only the run's totals matter.
-// Keys sort as (run start - z) << 45 | key << 14 | position - z, which
-// needs L - z <= kOrderCap; longer lists keep the element-wise sweep.
+// the sums over the run's elements whose child key is below kf.  Every
+// tile of kOrderTile positions of [z, L) (z = zero-prefix length) orders
+// each run piece it holds by ascending key, keeping the pieces where they
+// are, and takes tile-local exclusive prefix sums over the reordered
+// elements: the elements below kf of a run piece inside one tile are then
+// the positions [lo, p), with p found by binary search, and their sums are
+// differences of prefix sums.  A run's elements may be reordered freely:
+// within a run the other child's running sum is fixed, so only the run's
+// totals matter.  Keys sort as
+//   (piece start - tile start) << 42 | key << 11 | position - tile start.
+// Lists with L - z > kOrderCap keep the element-wise sweep (its keys would
+// not fit the sweep's LDS stage).
+__device__ __forceinline__ size_t tpre_index(const EstBuffers &B,
+                                             size_t slot_row, int tile, int q) {
+  const int tiles = (B.Lprep + kOrderTile - 1) / kOrderTile;
+  return (slot_row * tiles + tile) * (size_t)(kOrderTile + 1) + q;
+}
+
 __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
     const TriTask *tasks, EstBuffers B) {
-  extern __shared__ uint64_t okey[];  // kOrderCap keys
+  __shared__ uint64_t okey[kOrderTile];
+  __shared__ int64_t scm[kOrderThreads], scx[kOrderThreads];
+  __shared__ uint32_t scv[kOrderThreads];
   const TriTask &T = tasks[blockIdx.x];
   if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
   if (tri_path(*(ConstTask *)&T, B) != kTriFast) return;
@@ -519,20 +552,20 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
   const int z = B.prep_z[slot_row];
   const int L = T.L;
-  const int n = L - z;
-  if (n > kOrderCap) {
-    if (threadIdx.x == 0) B.tord[slot_row] = 0;
-    return;
-  }
-  TriElemN *el = B.prepn + slot_row * (size_t)B.Lprep;
+  if (L - z > kOrderCap) return;
+  const int tile = blockIdx.z;
+  const int t0 = z + tile * kOrderTile;
+  if (t0 >= L) return;
+  const int nt = min(kOrderTile, L - t0);
+  const TriElemN *el = B.prepn + slot_row * (size_t)B.Lprep;
   int n2 = 1;
-  while (n2 < n) n2 <<= 1;
+  while (n2 < nt) n2 <<= 1;
   for (int q = threadIdx.x; q < n2; q += kOrderThreads) {
     uint64_t k = ~0ull;
-    if (q < n) {
-      const TriElemN &e = el[z + q];
-      const uint64_t rl = (uint64_t)(max(e.run_lo, z) - z);
-      k = (rl << 45) | ((uint64_t)(e.kc & 0x7FFFFFFFu) << 14) | (uint64_t)q;
+    if (q < nt) {
+      const TriElemN &e = el[t0 + q];
+      const uint64_t rl = (uint64_t)(max(e.run_lo, t0) - t0);
+      k = (rl << 42) | ((uint64_t)(e.kc & 0x7FFFFFFFu) << 11) | (uint64_t)q;
     }
     okey[q] = k;
   }
@@ -551,36 +584,38 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
       __syncthreads();
     }
   }
-  // the run ends, the ordered keys, and each thread's consecutive chunk of
-  // prefix sums
+  // each thread: a consecutive chunk of at most kOrderPer sorted slots;
+  // all of its element loads are issued before the sums
+  constexpr int kOrderPer = kOrderTile / kOrderThreads;
   uint32_t *tk = B.tkey + slot_row * (size_t)B.Lprep;
-  TriPre *E = B.tpre + slot_row * (size_t)(B.Lprep + 1);
-  const int per = (n + kOrderThreads - 1) / kOrderThreads;
-  const int q0 = min(n, (int)threadIdx.x * per);
-  const int q1 = min(n, q0 + per);
-  int64_t sm = 0, sx = 0;
-  uint32_t sv = 0;
-  for (int q = q0; q < q1; ++q) {
-    const uint64_t k = okey[q];
-    const uint64_t rf = k >> 45;
-    // last sorted index of this run: first key of a later run, minus one
-    int lo = q + 1, hi = n;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if ((okey[mid] >> 45) <= rf) lo = mid + 1; else hi = mid;
+  const int q0 = min(nt, (int)threadIdx.x * kOrderPer);
+  const int q1 = min(nt, q0 + kOrderPer);
+  int64_t mu[kOrderPer], vm[kOrderPer];
+  int32_t vv[kOrderPer];
+#pragma unroll
+  for (int u = 0; u < kOrderPer; ++u) {
+    mu[u] = vm[u] = 0;
+    vv[u] = 0;
+    const int q = q0 + u;
+    if (q < q1) {
+      const uint64_t k = okey[q];
+      const TriElemN &src = el[t0 + (int)(k & 0x7FF)];
+      mu[u] = src.mu;
+      vm[u] = src.vm;
+      vv[u] = src.v;
+      tk[t0 + q] = (uint32_t)((k >> 11) & 0x7FFFFFFFull);
     }
-    const TriElemN &src = el[z + (int)(k & 0x3FFF)];
-    tk[z + q] = (uint32_t)((k >> 14) & 0x7FFFFFFFull);
-    sm = (int64_t)((uint64_t)sm + (uint64_t)src.mu);
-    sx = (int64_t)((uint64_t)sx + (uint64_t)src.vm);
-    sv += (uint32_t)src.v;
-    // run_hi lives in a field nothing else in this kernel reads
-    el[z + q].run_hi = z + lo - 1;
   }
-  __shared__ int64_t scm[kOrderThreads], scx[kOrderThreads];
-  __shared__ uint32_t scv[kOrderThreads];
-  scm[threadIdx.x] = sm;
-  scx[threadIdx.x] = sx;
+  uint64_t sm = 0, sx = 0;
+  uint32_t sv = 0;
+#pragma unroll
+  for (int u = 0; u < kOrderPer; ++u) {
+    sm += (uint64_t)mu[u];
+    sx += (uint64_t)vm[u];
+    sv += (uint32_t)vv[u];
+  }
+  scm[threadIdx.x] = (int64_t)sm;
+  scx[threadIdx.x] = (int64_t)sx;
   scv[threadIdx.x] = sv;
   __syncthreads();
   for (int off = 1; off < kOrderThreads; off <<= 1) {
@@ -597,21 +632,25 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
     scv[threadIdx.x] += av;
     __syncthreads();
   }
-  // exclusive start of my chunk, then the chunk's running sums
-  uint64_t em = (uint64_t)scm[threadIdx.x] - (uint64_t)sm;
-  uint64_t ex = (uint64_t)scx[threadIdx.x] - (uint64_t)sx;
+  // exclusive start of my chunk, then its running sums (wrapping)
+  uint64_t em = (uint64_t)scm[threadIdx.x] - sm;
+  uint64_t ex = (uint64_t)scx[threadIdx.x] - sx;
   uint32_t ev = scv[threadIdx.x] - sv;
-  for (int q = q0; q < q1; ++q) {
-    TriPre o;
-    o.m = (int64_t)em;
-    o.x = (int64_t)ex;
-    o.v = (int32_t)ev;
-    o.pad = 0;
-    E[z + q] = o;
-    const TriElemN &src = el[z + (int)(okey[q] & 0x3FFF)];
-    em += (uint64_t)src.mu;
-    ex += (uint64_t)src.vm;
-    ev += (uint32_t)src.v;
+  TriPre *E = B.tpre + tpre_index(B, slot_row, tile, 0);
+#pragma unroll
+  for (int u = 0; u < kOrderPer; ++u) {
+    const int q = q0 + u;
+    if (q < q1) {
+      TriPre o;
+      o.m = (int64_t)em;
+      o.x = (int64_t)ex;
+      o.v = (int32_t)ev;
+      o.pad = 0;
+      E[q] = o;
+    }
+    em += (uint64_t)mu[u];
+    ex += (uint64_t)vm[u];
+    ev += (uint32_t)vv[u];
   }
   if (threadIdx.x == kOrderThreads - 1) {
     TriPre o;
@@ -619,8 +658,7 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
     o.x = scx[threadIdx.x];
     o.v = (int32_t)scv[threadIdx.x];
     o.pad = 0;
-    E[L] = o;
-    B.tord[slot_row] = 1;
+    E[nt] = o;
   }
 }
 
@@ -674,9 +712,8 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   const int len = T.L - z;
   const int top = T.L - 1 - (int)((int64_t)len * seg / kFastSegs);
   const int bottom = T.L - (int)((int64_t)len * (seg + 1) / kFastSegs);
-  const bool ordered = B.tord[slot_row] != 0;  // then len <= kOrderCap
+  const bool ordered = len <= kOrderCap;  // tri_order_kernel ran
   const uint32_t *tk = B.tkey + slot_row * (size_t)B.Lprep;
-  const TriPre *E = B.tpre + slot_row * (size_t)(B.Lprep + 1);
   if (ordered) {
     for (int q = threadIdx.x; q < len; q += kLaneThreads * kFastSegs)
       skey[q] = tk[z + q];
@@ -714,21 +751,25 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     const uint32_t kf = c ? kf1 : kf0;
     FastRun r;
     if (ordered && el[pos].run_hi - max(run_lo, z) + 1 >= kSearchMin) {
-      // piece [lo, pos] of a run-ordered run: its elements below kf are
-      // the positions [lo, p)
-      const int p = lo + lds_lower_bound(skey + (lo - z), pos - lo + 1, kf);
-      ConstPre &e0 = ((ConstPre *)E)[lo];
+      // piece [lo, pos] of a long run, cut at its ordering tile's start:
+      // its elements below kf are the positions [lo, p)
+      const int tile = (pos - z) / kOrderTile;
+      const int ts = z + tile * kOrderTile;
+      const int lo2 = max(lo, ts);
+      const int p = lo2 + lds_lower_bound(skey + (lo2 - z), pos - lo2 + 1, kf);
+      const size_t eb = tpre_index(B, slot_row, tile, 0) - (size_t)ts;
+      ConstPre &e0 = ((ConstPre *)B.tpre)[eb + lo2];
       const int64_t m0 = e0.m, x0 = e0.x;
       const int32_t v0 = e0.v;
-      const int32_t v1 = ((ConstPre *)E)[pos + 1].v;
-      const TriPre ep = E[p];
+      const int32_t v1 = ((ConstPre *)B.tpre)[eb + pos + 1].v;
+      const TriPre ep = B.tpre[eb + p];
       r.mb = (int64_t)((uint64_t)ep.m - (uint64_t)m0);
       r.xb = (int64_t)((uint64_t)ep.x - (uint64_t)x0);
       r.vb = (int32_t)((uint32_t)ep.v - (uint32_t)v0);
-      r.nb = p - lo;
+      r.nb = p - lo2;
       r.vrun = (int32_t)((uint32_t)v1 - (uint32_t)v0);
-      r.nrun = pos - lo + 1;
-      pos = lo - 1;
+      r.nrun = pos - lo2 + 1;
+      pos = lo2 - 1;
     } else {
       r.mb = r.xb = 0;
       r.vb = r.nb = 0;
@@ -965,8 +1006,18 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
     } else if (S.type == kSpTree) {
       x = B.xout[(size_t)S.x_slot * d + i];
     } else if (S.type == kSpTriangle) {
-      for (int z = 0; z < S.n_partials; ++z)
-        x += B.partial[((size_t)S.x_slot + z) * d + i];
+      // eight loads in flight (the partials sit in different lines)
+      u128 acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int z = 0;
+      for (; z + 8 <= S.n_partials; z += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          acc[u] += B.partial[((size_t)S.x_slot + z + u) * d + i];
+      }
+      for (; z < S.n_partials; ++z)
+        acc[0] += B.partial[((size_t)S.x_slot + z) * d + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x += acc[u];
     }
     xs[i] = x;
     if (row_est) {
@@ -1009,11 +1060,16 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
       zero = true;
       break;
     }
-    if (b > lim / f) ok = false; else b *= f;
+    // b * f > 2^127 stops the product (no 128-bit division)
+    u128 prod;
+    if (__builtin_mul_overflow(b, f, &prod) || prod > lim) ok = false;
+    else b = prod;
   }
   if (!zero)
     for (int k = 0; k < S.n_edges - S.n_tables && ok; ++k) {
-      if (b > lim / (u128)B.w) ok = false; else b *= (u128)B.w;
+      u128 prod;
+      if (__builtin_mul_overflow(b, (u128)B.w, &prod) || prod > lim) ok = false;
+      else b = prod;
     }
   flags[blockIdx.x] = (zero || (ok && b < lim)) ? 1 : 0;
 }
@@ -1039,8 +1095,9 @@ hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
 
 hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
                             hipStream_t st) {
-  hipLaunchKernelGGL(tri_order_kernel, dim3(n, B.d), dim3(kOrderThreads),
-                     (size_t)kOrderCap * sizeof(uint64_t), st, tasks, B);
+  const int tiles = (std::min(B.Lprep, kOrderCap) + kOrderTile - 1) / kOrderTile;
+  hipLaunchKernelGGL(tri_order_kernel, dim3(n, B.d, tiles), dim3(kOrderThreads),
+                     0, st, tasks, B);
   return hipGetLastError();
 }
 

@@ -10,7 +10,8 @@ constexpr int kSortThreads = 1024;
 constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
 constexpr int kNodeStageBytes = 96 * 1024;  // node merge: staged magnitudes
-constexpr int kOrderThreads = 1024;
+constexpr int kOrderThreads = 256;
+constexpr int kOrderTile = 2048;  // positions ordered by one workgroup
 constexpr int kOrderCap = 16384;  // longest two-child apex list run-ordered
 constexpr int kFastStageBytes = kOrderCap * 4;  // its keys, staged in LDS
 
