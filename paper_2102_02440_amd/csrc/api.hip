@@ -951,16 +951,24 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   std::vector<std::vector<NodeTask>> levels(max_level + 1);
   for (size_t k = 0; k < pl.tasks.size(); ++k)
     levels[pl.task_level[k]].push_back(pl.tasks[k]);
+  // a level is launched in groups of node tasks whose merge scratch
+  // (merged list + records per sketch row) stays within kNodeScratchBytes;
+  // groups run one after another on the stream and reuse the slots
+  const int d = g->d, w = g->w;
+  const size_t per_task =
+      (size_t)d * std::max(1, pl.Lmax) * (sizeof(uint32_t) + sizeof(NodeRec));
+  const size_t group_tasks =
+      std::max<size_t>(1, kNodeScratchBytes / per_task);
   size_t max_level_tasks = 0;
   std::vector<NodeTask> flat;
   std::vector<size_t> level_off;
   for (auto &lv : levels) {
-    for (size_t k = 0; k < lv.size(); ++k) lv[k].scratch_slot = (int)k;
+    for (size_t k = 0; k < lv.size(); ++k)
+      lv[k].scratch_slot = (int)(k % group_tasks);
     level_off.push_back(flat.size());
     flat.insert(flat.end(), lv.begin(), lv.end());
-    max_level_tasks = std::max(max_level_tasks, lv.size());
+    max_level_tasks = std::max(max_level_tasks, std::min(lv.size(), group_tasks));
   }
-  const int d = g->d, w = g->w;
   // scratch layout
   size_t off = 0;
   auto carve = [&](size_t bytes) {
@@ -976,6 +984,8 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_sorted = carve(sizeof(uint64_t) * 2 * g->n_edges * d * (size_t)w);
   const size_t o_msg = carve(16ull * pl.n_msg_slots * d * (size_t)w);
   const size_t o_merged = carve(4ull * max_level_tasks * d * (size_t)std::max(1, pl.Lmax));
+  const size_t o_nrec = carve(sizeof(NodeRec) * max_level_tasks * d *
+                              (size_t)std::max(1, pl.Lmax));
   const size_t o_xout = carve(16ull * std::max(1, pl.n_x_slots) * d);
   const size_t np = std::max(1, pl.n_prep_slots);
   const size_t lp = std::max(1, pl.Lprep);
@@ -1012,6 +1022,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.sorted = reinterpret_cast<const uint64_t *>(base + o_sorted);
   B.msg = reinterpret_cast<u128 *>(base + o_msg);
   B.merged = reinterpret_cast<uint32_t *>(base + o_merged);
+  B.nrec = reinterpret_cast<NodeRec *>(base + o_nrec);
   B.xout = reinterpret_cast<u128 *>(base + o_xout);
   B.prep = reinterpret_cast<TriElem *>(base + o_prep);
   B.prepn = reinterpret_cast<TriElemN *>(base + o_prepn);
@@ -1044,8 +1055,10 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
       }
     }
     ProfScope ps("node", stream);
-    HIP_OK(launch_node(dtasks + level_off[lv], (int)levels[lv].size(), B,
-                       stage, stream));
+    for (size_t g0 = 0; g0 < levels[lv].size(); g0 += group_tasks)
+      HIP_OK(launch_node(dtasks + level_off[lv] + g0,
+                         (int)std::min(group_tasks, levels[lv].size() - g0), B,
+                         stage, stream));
   }
   if (!pl.tris.empty()) {
     ProfScope ps("tri_order", stream);

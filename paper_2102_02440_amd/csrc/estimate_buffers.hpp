@@ -41,12 +41,22 @@ struct TriPre {
   int32_t pad;
 };
 
+// One element of a node's merged list, gathered once by the merge so that
+// the node's sweeps read consecutive records (32 bytes).
+struct NodeRec {
+  u128 mu;        // the child's message at the bucket (child lists only)
+  int64_t v;      // the node's counter at the bucket
+  uint32_t aj;    // list << 16 | bucket
+  uint32_t pad;
+};
+
 struct EstBuffers {
   const void *const *sides;   // [2 * n_edges] counter arrays (d x w)
   const int64_t *n_sel;       // [n_tables]
   const uint64_t *sorted;     // [side][row][w] keys (|v| << 16 | j)
   u128 *msg;                  // [slot][row][w]
   uint32_t *merged;           // [scratch slot][row][Lmax]
+  NodeRec *nrec;              // [scratch slot][row][Lmax]
   u128 *xout;                 // [slot][row]
   TriElem *prep;              // [prep slot][row][Lprep]
   TriElemN *prepn;            // [prep slot][row][Lprep] (two-child apexes)

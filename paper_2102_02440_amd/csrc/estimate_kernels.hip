@@ -184,6 +184,112 @@ __device__ __forceinline__ ListRef list_of(const NodeTask *T, int a) {
   return r;
 }
 
+// product of the A of every child but `a` (a >= M: of every child)
+template <int M>
+__device__ __forceinline__ u128 times_others(u128 t, const u128 *A, int a) {
+  if (M == 1) return a >= M ? mul_u128(t, A[0]) : t;
+  if (M == 2 && a < M) return mul_u128(t, a ? A[0] : A[1]);
+#pragma unroll
+  for (int c = 0; c < M; ++c)
+    if (c != a) t = mul_u128(t, A[c]);
+  return t;
+}
+
+// The three sweeps of a node with M children over its merged records, each
+// thread taking a contiguous segment: the segment totals of every child's
+// messages (suffix-scanned into A at the segment start), the running term
+// sum G (prefix-scanned), and the emitted message and cut constants.
+template <int M>
+__device__ void node_sweeps(const NodeTask &T, const NodeRec *rec, int L,
+                            int row, const EstBuffers &B, u128 *sh) {
+  // records loaded together (fewer with more children: registers)
+  constexpr int kSweepU = M <= 2 ? 4 : (M == 3 ? 2 : 1);
+  const int has_parent = T.parent_side >= 0;
+  const int seg = (L + kNodeThreads - 1) / kNodeThreads;
+  const int s0 = min(L, (int)threadIdx.x * seg);
+  const int s1 = min(L, s0 + seg);
+
+  u128 tot[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) tot[c] = 0;
+  for (int p0 = s0; p0 < s1; p0 += kSweepU) {
+    NodeRec rr[kSweepU];
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u)
+      if (p0 + u < s1) rr[u] = rec[p0 + u];
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      if (p0 + u >= s1) break;
+      const int a = (int)(rr[u].aj >> 16);
+#pragma unroll
+      for (int c = 0; c < M; ++c)
+        if (c == a) tot[c] += rr[u].mu;
+    }
+  }
+  u128 A0[M];  // A at the start of my segment (inclusive)
+#pragma unroll
+  for (int c = 0; c < M; ++c) A0[c] = block_scan_incl(tot[c], sh, true);
+
+  u128 A[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) A[c] = A0[c];
+  u128 gl = 0;
+  for (int p0 = s0; p0 < s1; p0 += kSweepU) {
+    NodeRec rr[kSweepU];
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u)
+      if (p0 + u < s1) rr[u] = rec[p0 + u];
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      if (p0 + u >= s1) break;
+      const NodeRec &r = rr[u];
+      const int a = (int)(r.aj >> 16);
+      if (a >= M) continue;
+      gl += times_others<M>(mul_s64_u128(r.v, r.mu), A, a);
+#pragma unroll
+      for (int c = 0; c < M; ++c)
+        if (c == a) A[c] -= r.mu;
+    }
+  }
+  const u128 gincl = block_scan_incl(gl, sh, false);
+
+  if (T.mode == kModeTreeRoot) {
+    if (threadIdx.x == kNodeThreads - 1)
+      B.xout[(size_t)T.out_slot * B.d + row] = gincl;
+    return;
+  }
+
+  // emit the message (parent list) and cut constants (cut list)
+  u128 G = gincl - gl;
+#pragma unroll
+  for (int c = 0; c < M; ++c) A[c] = A0[c];
+  u128 *Mo = has_parent ? msg_of(B, T.msg_slot, row) : nullptr;
+  u128 *Co = T.cut_side >= 0 ? msg_of(B, T.cmsg_slot, row) : nullptr;
+  for (int p0 = s0; p0 < s1; p0 += kSweepU) {
+    NodeRec rr[kSweepU];
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u)
+      if (p0 + u < s1) rr[u] = rec[p0 + u];
+#pragma unroll
+    for (int u = 0; u < kSweepU; ++u) {
+      if (p0 + u >= s1) break;
+      const NodeRec &r = rr[u];
+      const int a = (int)(r.aj >> 16);
+      const int j = (int)(r.aj & 0xFFFF);
+      if (a < M) {
+        G += times_others<M>(mul_s64_u128(r.v, r.mu), A, a);
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+          if (c == a) A[c] -= r.mu;
+      } else {
+        const u128 p = times_others<M>(s64_to_u128(r.v), A, a);
+        const bool is_parent = has_parent && a == M;
+        (is_parent ? Mo : Co)[j] = p + G;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kNodeThreads) void node_kernel(
     const NodeTask *tasks, EstBuffers B, int32_t stage_bytes) {
   __shared__ u128 sh[kNodeThreads];
@@ -211,47 +317,111 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
   const int L = nl * w;
   uint32_t *merged =
       B.merged + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
+  NodeRec *rec = B.nrec + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
 
   // 1. k-way merge by rank: position = own index + elements of smaller
   //    kappa in every other list (ties in |v| go to the lower edge id).
   //    With int32 counters every |v| < 2^32: the lists' sorted magnitudes
   //    are staged in LDS as 32-bit values and the rank searches run there.
   extern __shared__ uint32_t mags[];  // nl * w when staged
+  __shared__ int32_t s_side[kMaxChild + 2], s_eid[kMaxChild + 2],
+      s_msg[kMaxChild + 2];
+  if ((int)threadIdx.x < nl) {
+    const ListRef lr = list_of(Tg, threadIdx.x);
+    s_side[threadIdx.x] = lr.side;
+    s_eid[threadIdx.x] = lr.eid;
+    s_msg[threadIdx.x] = (int)threadIdx.x < m ? Tg->child_msg[threadIdx.x] : -1;
+  }
+  __syncthreads();
   const bool staged = B.counter_bits == 32 &&
                       (size_t)nl * w * 4 <= (size_t)stage_bytes;
   if (staged) {
     for (int e = threadIdx.x; e < L; e += kNodeThreads) {
       const int a = e / w;
       const int k = e - a * w;
-      mags[e] = (uint32_t)(sorted_of(B, list_of(Tg, a).side, row)[k] >> 16);
+      mags[e] = (uint32_t)(sorted_of(B, s_side[a], row)[k] >> 16);
     }
     __syncthreads();
-  }
-  for (int e = threadIdx.x; e < L; e += kNodeThreads) {
-    const int a = e / w;
-    const int k = e - a * w;
-    const ListRef la = list_of(Tg, a);
-    const uint64_t key = sorted_of(B, la.side, row)[k];
-    const uint64_t absv = key >> 16;
-    const uint32_t j = (uint32_t)(key & 0xFFFF);
-    int pos = k;
-    for (int b = 0; b < nl; ++b) {
-      if (b == a) continue;
-      const ListRef lb = list_of(Tg, b);
-      const uint64_t t = absv + (lb.eid < la.eid ? 1 : 0);  // count |v_b| < t
-      if (staged) {
-        const uint32_t *m = mags + (size_t)b * w;
-        int lo = 0, hi = w;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if ((uint64_t)m[mid] < t) lo = mid + 1; else hi = mid;
+    // kMergeU elements per lane at a time: their rank searches run in
+    // lockstep (uniform trip count), so the LDS probes overlap
+    constexpr int kMergeU = 4;
+    for (int e0 = threadIdx.x; e0 < L; e0 += kNodeThreads * kMergeU) {
+      int a[kMergeU], pos[kMergeU];
+      uint32_t j[kMergeU];
+      uint64_t absv[kMergeU];
+      bool ok[kMergeU];
+#pragma unroll
+      for (int u = 0; u < kMergeU; ++u) {
+        const int e = e0 + u * kNodeThreads;
+        ok[u] = e < L;
+        const int ee = ok[u] ? e : 0;
+        a[u] = ee / w;
+        const int k = ee - a[u] * w;
+        const uint64_t key = sorted_of(B, s_side[a[u]], row)[k];
+        absv[u] = key >> 16;
+        j[u] = (uint32_t)(key & 0xFFFF);
+        pos[u] = k;
+      }
+      for (int b = 0; b < nl; ++b) {
+        const uint32_t *mb = mags + (size_t)b * w;
+        const int eb = s_eid[b];
+        uint64_t t[kMergeU];
+        int base[kMergeU];
+#pragma unroll
+        for (int u = 0; u < kMergeU; ++u) {
+          t[u] = absv[u] + (eb < s_eid[a[u]] ? 1 : 0);  // count |v_b| < t
+          base[u] = 0;
         }
-        pos += lo;
-      } else {
-        pos += lower_bound_u64(sorted_of(B, lb.side, row), w, t << 16);
+        int n = w;
+        while (n > 1) {
+          const int half = n >> 1;
+#pragma unroll
+          for (int u = 0; u < kMergeU; ++u)
+            base[u] = (uint64_t)mb[base[u] + half] < t[u] ? base[u] + half : base[u];
+          n -= half;
+        }
+#pragma unroll
+        for (int u = 0; u < kMergeU; ++u) {
+          const int r = base[u] + ((uint64_t)mb[base[u]] < t[u] ? 1 : 0);
+          if (b != a[u]) pos[u] += r;
+        }
+      }
+      NodeRec r[kMergeU];
+#pragma unroll
+      for (int u = 0; u < kMergeU; ++u) {
+        r[u].v = counter_at(B, s_side[a[u]], row, (int)j[u]);
+        r[u].mu = a[u] < m ? msg_of(B, s_msg[a[u]], row)[j[u]] : (u128)0;
+        r[u].aj = ((uint32_t)a[u] << 16) | j[u];
+        r[u].pad = 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kMergeU; ++u) {
+        if (!ok[u]) continue;
+        merged[pos[u]] = r[u].aj;
+        rec[pos[u]] = r[u];
       }
     }
-    merged[pos] = ((uint32_t)a << 16) | j;
+  } else {
+    for (int e = threadIdx.x; e < L; e += kNodeThreads) {
+      const int a = e / w;
+      const int k = e - a * w;
+      const uint64_t key = sorted_of(B, s_side[a], row)[k];
+      const uint64_t absv = key >> 16;
+      const uint32_t j = (uint32_t)(key & 0xFFFF);
+      int pos = k;
+      for (int b = 0; b < nl; ++b) {
+        if (b == a) continue;
+        const uint64_t t = absv + (s_eid[b] < s_eid[a] ? 1 : 0);  // count |v_b| < t
+        pos += lower_bound_u64(sorted_of(B, s_side[b], row), w, t << 16);
+      }
+      NodeRec r;
+      r.v = counter_at(B, s_side[a], row, (int)j);
+      r.mu = a < m ? msg_of(B, s_msg[a], row)[j] : (u128)0;
+      r.aj = ((uint32_t)a << 16) | j;
+      r.pad = 0;
+      merged[pos] = r.aj;
+      rec[pos] = r;
+    }
   }
   __syncthreads();
 
@@ -260,12 +430,12 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
     TriElem *out = B.prep + slot_row * (size_t)B.Lprep;
     TriElemN *outn = B.prepn + slot_row * (size_t)B.Lprep;
     for (int pos = threadIdx.x; pos < L; pos += kNodeThreads) {
-      const uint32_t mt = merged[pos];
-      const int a = (int)(mt >> 16);
-      const int j = (int)(mt & 0xFFFF);
+      const NodeRec nr = rec[pos];
+      const int a = (int)(nr.aj >> 16);
+      const int j = (int)(nr.aj & 0xFFFF);
       TriElem e;
-      e.v = counter_at(B, Tg->child_side[a], row, j);
-      e.mu = msg_of(B, Tg->child_msg[a], row)[j];
+      e.v = nr.v;
+      e.mu = nr.mu;
       e.key = 0;
       uint64_t own = 0;
       if (Tg->child_cut[a] >= 0) {
@@ -354,85 +524,13 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
     return;
   }
 
-  // 2. my segment of the merged list
-  const int seg = (L + kNodeThreads - 1) / kNodeThreads;
-  const int s0 = min(L, (int)threadIdx.x * seg);
-  const int s1 = min(L, s0 + seg);
-
-  u128 tot[kMaxChild];
-#pragma unroll
-  for (int c = 0; c < kMaxChild; ++c) tot[c] = 0;
-  for (int pos = s0; pos < s1; ++pos) {
-    const uint32_t mt = merged[pos];
-    const int a = (int)(mt >> 16);
-    if (a >= m) continue;
-    const u128 mu = msg_of(B, Tg->child_msg[a], row)[mt & 0xFFFF];
-#pragma unroll
-    for (int c = 0; c < kMaxChild; ++c)
-      if (c == a) tot[c] += mu;
-  }
-  u128 A0[kMaxChild];  // A at the start of my segment (inclusive)
-#pragma unroll
-  for (int c = 0; c < kMaxChild; ++c) {
-    A0[c] = 0;
-    if (c < m) A0[c] = block_scan_incl(tot[c], sh, true);
-  }
-
-  // 3. term sums of my segment
-  u128 A[kMaxChild];
-#pragma unroll
-  for (int c = 0; c < kMaxChild; ++c) A[c] = A0[c];
-  u128 gl = 0;
-  for (int pos = s0; pos < s1; ++pos) {
-    const uint32_t mt = merged[pos];
-    const int a = (int)(mt >> 16);
-    if (a >= m) continue;
-    const int j = (int)(mt & 0xFFFF);
-    const u128 mu = msg_of(B, Tg->child_msg[a], row)[j];
-    u128 term = mul_s64_u128(counter_at(B, Tg->child_side[a], row, j), mu);
-#pragma unroll
-    for (int c = 0; c < kMaxChild; ++c) {
-      if (c < m && c != a) term = mul_u128(term, A[c]);
-      if (c == a) A[c] -= mu;
-    }
-    gl += term;
-  }
-  const u128 gincl = block_scan_incl(gl, sh, false);
-
-  if (T.mode == kModeTreeRoot) {
-    if (threadIdx.x == kNodeThreads - 1)
-      B.xout[(size_t)T.out_slot * B.d + row] = gincl;
-    return;
-  }
-
-  // 4. emit the message (parent list) and cut constants (cut list)
-  u128 G = gincl - gl;
-#pragma unroll
-  for (int c = 0; c < kMaxChild; ++c) A[c] = A0[c];
-  u128 *M = has_parent ? msg_of(B, T.msg_slot, row) : nullptr;
-  u128 *C = has_cut ? msg_of(B, T.cmsg_slot, row) : nullptr;
-  for (int pos = s0; pos < s1; ++pos) {
-    const uint32_t mt = merged[pos];
-    const int a = (int)(mt >> 16);
-    const int j = (int)(mt & 0xFFFF);
-    if (a < m) {
-      const u128 mu = msg_of(B, Tg->child_msg[a], row)[j];
-      u128 term = mul_s64_u128(counter_at(B, Tg->child_side[a], row, j), mu);
-#pragma unroll
-      for (int c = 0; c < kMaxChild; ++c) {
-        if (c < m && c != a) term = mul_u128(term, A[c]);
-        if (c == a) A[c] -= mu;
-      }
-      G += term;
-    } else {
-      const ListRef la = list_of(Tg, a);
-      u128 p = s64_to_u128(counter_at(B, la.side, row, j));
-#pragma unroll
-      for (int c = 0; c < kMaxChild; ++c)
-        if (c < m) p = mul_u128(p, A[c]);
-      const bool is_parent = has_parent && a == m;
-      (is_parent ? M : C)[j] = p + G;
-    }
+  switch (m) {
+    case 1: node_sweeps<1>(T, rec, L, row, B, sh); break;
+    case 2: node_sweeps<2>(T, rec, L, row, B, sh); break;
+    case 3: node_sweeps<3>(T, rec, L, row, B, sh); break;
+    case 4: node_sweeps<4>(T, rec, L, row, B, sh); break;
+    case 5: node_sweeps<5>(T, rec, L, row, B, sh); break;
+    default: node_sweeps<kMaxChild>(T, rec, L, row, B, sh); break;
   }
 }
 

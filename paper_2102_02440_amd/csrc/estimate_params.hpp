@@ -1,5 +1,6 @@
 // estimate_params.hpp -- device-side plan of a compass_estimate call.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace compass {
@@ -10,6 +11,7 @@ constexpr int kSortThreads = 1024;
 constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
 constexpr int kNodeStageBytes = 96 * 1024;  // node merge: staged magnitudes
+constexpr size_t kNodeScratchBytes = (size_t)1 << 30;  // per level launch
 constexpr int kOrderThreads = 256;
 constexpr int kOrderTile = 2048;  // positions ordered by one workgroup
 constexpr int kOrderCap = 16384;  // longest two-child apex list run-ordered
