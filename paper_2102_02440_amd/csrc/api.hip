@@ -45,6 +45,10 @@ hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
                             const EstBuffers &B, hipStream_t st);
 hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
                        int stage_bytes, hipStream_t st);
+hipError_t launch_node1(const NodeTask *tasks, int n, const EstBuffers &B,
+                        hipStream_t st);
+hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
+                            const EstBuffers &B, hipStream_t st);
 hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
                             hipStream_t st);
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
@@ -986,6 +990,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_merged = carve(4ull * max_level_tasks * d * (size_t)std::max(1, pl.Lmax));
   const size_t o_nrec = carve(sizeof(NodeRec) * max_level_tasks * d *
                               (size_t)std::max(1, pl.Lmax));
+  const size_t o_n1tot = carve(16ull * 2 * kN1MaxChunks * max_level_tasks * d);
   const size_t o_xout = carve(16ull * std::max(1, pl.n_x_slots) * d);
   const size_t np = std::max(1, pl.n_prep_slots);
   const size_t lp = std::max(1, pl.Lprep);
@@ -1023,6 +1028,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.msg = reinterpret_cast<u128 *>(base + o_msg);
   B.merged = reinterpret_cast<uint32_t *>(base + o_merged);
   B.nrec = reinterpret_cast<NodeRec *>(base + o_nrec);
+  B.n1tot = reinterpret_cast<u128 *>(base + o_n1tot);
   B.xout = reinterpret_cast<u128 *>(base + o_xout);
   B.prep = reinterpret_cast<TriElem *>(base + o_prep);
   B.prepn = reinterpret_cast<TriElemN *>(base + o_prepn);
@@ -1055,10 +1061,20 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
       }
     }
     ProfScope ps("node", stream);
-    for (size_t g0 = 0; g0 < levels[lv].size(); g0 += group_tasks)
-      HIP_OK(launch_node(dtasks + level_off[lv] + g0,
-                         (int)std::min(group_tasks, levels[lv].size() - g0), B,
-                         stage, stream));
+    for (size_t g0 = 0; g0 < levels[lv].size(); g0 += group_tasks) {
+      const size_t ng = std::min(group_tasks, levels[lv].size() - g0);
+      bool any_multi = false, any_one = false;
+      int apex_L = 0;
+      for (size_t k = g0; k < g0 + ng; ++k) {
+        const NodeTask &t = levels[lv][k];
+        if (t.m == 1) any_one = true; else any_multi = true;
+        if (t.mode == kModeTriRootPrep) apex_L = std::max(apex_L, t.m * w);
+      }
+      const NodeTask *dt = dtasks + level_off[lv] + g0;
+      if (any_multi) HIP_OK(launch_node(dt, (int)ng, B, stage, stream));
+      if (any_one) HIP_OK(launch_node1(dt, (int)ng, B, stream));
+      if (apex_L > 0) HIP_OK(launch_apex_prep(dt, (int)ng, apex_L, B, stream));
+    }
   }
   if (!pl.tris.empty()) {
     ProfScope ps("tri_order", stream);

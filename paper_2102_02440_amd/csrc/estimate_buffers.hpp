@@ -57,6 +57,7 @@ struct EstBuffers {
   u128 *msg;                  // [slot][row][w]
   uint32_t *merged;           // [scratch slot][row][Lmax]
   NodeRec *nrec;              // [scratch slot][row][Lmax]
+  u128 *n1tot;                // [scratch slot][row][2 * kN1MaxChunks]
   u128 *xout;                 // [slot][row]
   TriElem *prep;              // [prep slot][row][Lprep]
   TriElemN *prepn;            // [prep slot][row][Lprep] (two-child apexes)

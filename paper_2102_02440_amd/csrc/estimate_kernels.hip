@@ -303,6 +303,7 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
   const int has_cut = T.cut_side >= 0;
   const int nl = m + has_parent + has_cut;
 
+  if (m == 1) return;  // node1_prefix_kernel / node1_emit_kernel
   if (m == 0) {  // leaf: messages are the raw counters
     if (T.mode != kModeMessage) return;
     u128 *M = has_parent ? msg_of(B, T.msg_slot, row) : nullptr;
@@ -425,112 +426,331 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
   }
   __syncthreads();
 
-  if (T.mode == kModeTriRootPrep) {
-    const size_t slot_row = (size_t)T.out_slot * B.d + row;
-    TriElem *out = B.prep + slot_row * (size_t)B.Lprep;
-    TriElemN *outn = B.prepn + slot_row * (size_t)B.Lprep;
-    for (int pos = threadIdx.x; pos < L; pos += kNodeThreads) {
-      const NodeRec nr = rec[pos];
-      const int a = (int)(nr.aj >> 16);
-      const int j = (int)(nr.aj & 0xFFFF);
-      TriElem e;
-      e.v = nr.v;
-      e.mu = nr.mu;
-      e.key = 0;
-      uint64_t own = 0;
-      if (Tg->child_cut[a] >= 0) {
-        // kappa of the child's own bucket on the edge to the apex
-        const int other = Tg->child_side[a] ^ 1;
-        own = abs_u64(counter_at(B, other, row, j));
-        e.key = (own << 7) | (uint64_t)Tg->child_eid[a];
-      }
-      e.child = (uint32_t)a;
-      e.pad[0] = e.pad[1] = e.pad[2] = 0;
-      out[pos] = e;
-      if (m == 2) {
-        // truncating copy; the sweep reads it only when the bounds hold
-        TriElemN n;
-        n.v = (int32_t)e.v;
-        n.kc = ((uint32_t)a << 31) | (uint32_t)(own & 0x7FFFFFFFull);
-        n.mu = (int64_t)(uint64_t)e.mu;
-        n.vm = (int64_t)((uint64_t)e.v * (uint64_t)e.mu);
-        n.run_lo = 0;  // set below
-        n.run_hi = 0;  // set below
-        outn[pos] = n;
-      }
-      // the list is ascending in |v|: its zero counters form a prefix, and
-      // they add nothing to the sweep (it ends there)
-      if (e.v != 0) {
-        bool first = pos == 0;
-        if (!first) {
-          const uint32_t pt = merged[pos - 1];
-          first = counter_at(B, Tg->child_side[pt >> 16], row, pt & 0xFFFF) == 0;
-        }
-        if (first) B.prep_z[slot_row] = pos;
-      } else if (pos == L - 1) {
-        B.prep_z[slot_row] = L;
-      }
-    }
-    if (m == 2) {
-      // runs of equal child: each element gets the lowest position of its
-      // run (a max-scan of run starts over contiguous thread segments)
-      __syncthreads();
-      int *shi = reinterpret_cast<int *>(sh);
-      const int seg = (L + kNodeThreads - 1) / kNodeThreads;
-      const int s0 = min(L, (int)threadIdx.x * seg);
-      const int s1 = min(L, s0 + seg);
-      auto starts_run = [&](int p) {
-        return p == 0 || (merged[p] >> 16) != (merged[p - 1] >> 16);
-      };
-      int last = -1;
-      for (int p = s0; p < s1; ++p)
-        if (starts_run(p)) last = p;
-      shi[threadIdx.x] = last;
-      __syncthreads();
-      for (int off = 1; off < kNodeThreads; off <<= 1) {
-        const int o = threadIdx.x >= off ? shi[threadIdx.x - off] : -1;
-        __syncthreads();
-        shi[threadIdx.x] = max(shi[threadIdx.x], o);
-        __syncthreads();
-      }
-      int cur = threadIdx.x > 0 ? shi[threadIdx.x - 1] : -1;
-      for (int p = s0; p < s1; ++p) {
-        if (starts_run(p)) cur = p;
-        outn[p].run_lo = cur;
-      }
-      // and the highest position of its run (a min-scan of run ends from
-      // the right)
-      __syncthreads();
-      auto ends_run = [&](int p) {
-        return p == L - 1 || (merged[p] >> 16) != (merged[p + 1] >> 16);
-      };
-      int first = L;
-      for (int p = s1 - 1; p >= s0; --p)
-        if (ends_run(p)) first = p;
-      shi[threadIdx.x] = first;
-      __syncthreads();
-      for (int off = 1; off < kNodeThreads; off <<= 1) {
-        const int o = threadIdx.x + off < kNodeThreads ? shi[threadIdx.x + off] : L;
-        __syncthreads();
-        shi[threadIdx.x] = min(shi[threadIdx.x], o);
-        __syncthreads();
-      }
-      int nxt = threadIdx.x + 1 < kNodeThreads ? shi[threadIdx.x + 1] : L;
-      for (int p = s1 - 1; p >= s0; --p) {
-        if (ends_run(p)) nxt = p;
-        outn[p].run_hi = nxt;
-      }
-    }
-    return;
-  }
+  if (T.mode == kModeTriRootPrep) return;  // apex_prep_kernel
 
   switch (m) {
-    case 1: node_sweeps<1>(T, rec, L, row, B, sh); break;
     case 2: node_sweeps<2>(T, rec, L, row, B, sh); break;
     case 3: node_sweeps<3>(T, rec, L, row, B, sh); break;
     case 4: node_sweeps<4>(T, rec, L, row, B, sh); break;
     case 5: node_sweeps<5>(T, rec, L, row, B, sh); break;
     default: node_sweeps<kMaxChild>(T, rec, L, row, B, sh); break;
+  }
+}
+
+// ---------------------------------------------------------------------
+// nodes with one child: grid (tasks, d, chunks), kN1Threads lanes
+// ---------------------------------------------------------------------
+// With a single child c the message of the node for a query element q
+// (a bucket of the parent list or of the cut list) is
+//   M(q) = s_q * A(kappa_q) + G(kappa_q),
+// A = sum of the child's messages over child elements of larger kappa,
+// G = sum of v * mu over child elements of smaller kappa.  The child's
+// elements are already sorted by |v| (sort_rows_kernel), and kappa_z <
+// kappa_q exactly when |v_z| < |s_q| + [eid_c < eid_q]: so with prefix sums
+// of mu and v * mu in that order, M(q) is one binary search and one read.
+// node1_prefix_kernel: chunk-local exclusive prefix sums (and chunk
+// totals); node1_emit_kernel: the messages (or, at a tree root, X).
+__device__ __forceinline__ u128 *n1_prefix(const EstBuffers &B, int slot,
+                                           int row) {
+  return reinterpret_cast<u128 *>(B.nrec +
+                                  ((size_t)slot * B.d + row) * (size_t)B.Lmax);
+}
+__device__ __forceinline__ u128 *n1_total(const EstBuffers &B, int slot,
+                                          int row) {
+  return B.n1tot + ((size_t)slot * B.d + row) * (2 * kN1MaxChunks);
+}
+
+__global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
+    const NodeTask *tasks, EstBuffers B) {
+  __shared__ u128 sh_m[kN1Threads], sh_x[kN1Threads];
+  const NodeTask &T = tasks[blockIdx.x];
+  if (T.m != 1 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
+  const int row = blockIdx.y;
+  const int w = B.w;
+  const int c0 = blockIdx.z * kN1Chunk;
+  if (c0 >= w) return;
+  const int cside = T.child_side[0];
+  const int cmsg = T.child_msg[0];
+  const uint64_t *srt = sorted_of(B, cside, row);
+  const u128 *mu_in = msg_of(B, cmsg, row);
+  u128 pm[kN1Per], px[kN1Per];
+  const int k0 = c0 + threadIdx.x * kN1Per;
+#pragma unroll
+  for (int u = 0; u < kN1Per; ++u) {
+    pm[u] = px[u] = 0;
+    const int k = k0 + u;
+    if (k < w) {
+      const int j = (int)(srt[k] & 0xFFFF);
+      const u128 mu = mu_in[j];
+      pm[u] = mu;
+      px[u] = mul_s64_u128(counter_at(B, cside, row, j), mu);
+    }
+  }
+  u128 tm = 0, tx = 0;
+#pragma unroll
+  for (int u = 0; u < kN1Per; ++u) {
+    tm += pm[u];
+    tx += px[u];
+  }
+  // inclusive block scans of the thread sums
+  sh_m[threadIdx.x] = tm;
+  sh_x[threadIdx.x] = tx;
+  __syncthreads();
+  for (int off = 1; off < kN1Threads; off <<= 1) {
+    u128 am = 0, ax = 0;
+    if ((int)threadIdx.x >= off) {
+      am = sh_m[threadIdx.x - off];
+      ax = sh_x[threadIdx.x - off];
+    }
+    __syncthreads();
+    sh_m[threadIdx.x] += am;
+    sh_x[threadIdx.x] += ax;
+    __syncthreads();
+  }
+  u128 em = sh_m[threadIdx.x] - tm, ex = sh_x[threadIdx.x] - tx;
+  u128 *P = n1_prefix(B, T.scratch_slot, row);
+#pragma unroll
+  for (int u = 0; u < kN1Per; ++u) {
+    const int k = k0 + u;
+    if (k < w) {
+      P[2 * (size_t)k] = em;
+      P[2 * (size_t)k + 1] = ex;
+    }
+    em += pm[u];
+    ex += px[u];
+  }
+  if (threadIdx.x == kN1Threads - 1) {
+    u128 *tot = n1_total(B, T.scratch_slot, row);
+    tot[2 * blockIdx.z] = sh_m[threadIdx.x];
+    tot[2 * blockIdx.z + 1] = sh_x[threadIdx.x];
+  }
+}
+
+__global__ __launch_bounds__(kN1Threads) void node1_emit_kernel(
+    const NodeTask *tasks, EstBuffers B) {
+  extern __shared__ uint32_t smag[];  // the child's sorted |v| (int32 counters)
+  __shared__ u128 soff[2 * kN1MaxChunks + 2];
+  const NodeTask &T = tasks[blockIdx.x];
+  if (T.m != 1 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
+  const int row = blockIdx.y;
+  const int w = B.w;
+  const int has_parent = T.parent_side >= 0;
+  const int nq = has_parent + (T.cut_side >= 0);
+  const int nch = (w + kN1Chunk - 1) / kN1Chunk;
+  const u128 *tot = n1_total(B, T.scratch_slot, row);
+  if (nq == 0) {  // tree root: X = G(+inf)
+    if (blockIdx.z == 0 && threadIdx.x == 0) {
+      u128 x = 0;
+      for (int c = 0; c < nch; ++c) x += tot[2 * c + 1];
+      B.xout[(size_t)T.out_slot * B.d + row] = x;
+    }
+    return;
+  }
+  const int e0 = blockIdx.z * kN1Chunk;
+  if (e0 >= nq * w) return;
+  const int cside = T.child_side[0];
+  const uint64_t *srt = sorted_of(B, cside, row);
+  const bool staged = B.counter_bits == 32;
+  if (staged)
+    for (int k = threadIdx.x; k < w; k += kN1Threads)
+      smag[k] = (uint32_t)(srt[k] >> 16);
+  if (threadIdx.x == 0) {
+    u128 am = 0, ax = 0;
+    for (int c = 0; c < nch; ++c) {
+      soff[2 * c] = am;
+      soff[2 * c + 1] = ax;
+      am += tot[2 * c];
+      ax += tot[2 * c + 1];
+    }
+    soff[2 * nch] = am;  // totals: the prefix at r = w
+    soff[2 * nch + 1] = ax;
+  }
+  __syncthreads();
+  const u128 *P = n1_prefix(B, T.scratch_slot, row);
+  const u128 tot_m = soff[2 * nch];
+  int r[kN1Per], qi[kN1Per], qa[kN1Per];
+  int64_t sv[kN1Per];
+  uint64_t t[kN1Per];
+  bool ok[kN1Per];
+#pragma unroll
+  for (int u = 0; u < kN1Per; ++u) {
+    const int e = e0 + threadIdx.x + u * kN1Threads;
+    ok[u] = e < nq * w;
+    const int ee = ok[u] ? e : 0;
+    qa[u] = ee / w;
+    qi[u] = ee - qa[u] * w;
+    const bool par = has_parent && qa[u] == 0;
+    const int qside = par ? T.parent_side : T.cut_side;
+    const int qeid = par ? T.parent_eid : T.cut_eid;
+    sv[u] = counter_at(B, qside, row, qi[u]);
+    t[u] = abs_u64(sv[u]) + (T.child_eid[0] < qeid ? 1 : 0);
+  }
+  if (staged) {
+    int base[kN1Per];
+#pragma unroll
+    for (int u = 0; u < kN1Per; ++u) base[u] = 0;
+    int n = w;
+    while (n > 1) {
+      const int half = n >> 1;
+#pragma unroll
+      for (int u = 0; u < kN1Per; ++u)
+        base[u] = (uint64_t)smag[base[u] + half] < t[u] ? base[u] + half : base[u];
+      n -= half;
+    }
+#pragma unroll
+    for (int u = 0; u < kN1Per; ++u)
+      r[u] = base[u] + ((uint64_t)smag[base[u]] < t[u] ? 1 : 0);
+  } else {
+#pragma unroll
+    for (int u = 0; u < kN1Per; ++u) r[u] = lower_bound_u64(srt, w, t[u] << 16);
+  }
+#pragma unroll
+  for (int u = 0; u < kN1Per; ++u) {
+    if (!ok[u]) continue;
+    u128 pm, px;
+    if (r[u] == w) {
+      pm = tot_m;
+      px = soff[2 * nch + 1];
+    } else {
+      const int c = r[u] / kN1Chunk;
+      pm = soff[2 * c] + P[2 * (size_t)r[u]];
+      px = soff[2 * c + 1] + P[2 * (size_t)r[u] + 1];
+    }
+    const bool par = has_parent && qa[u] == 0;
+    u128 *out = msg_of(B, par ? T.msg_slot : T.cmsg_slot, row);
+    out[qi[u]] = mul_s64_u128(sv[u], tot_m - pm) + px;
+  }
+}
+
+// ---------------------------------------------------------------------
+// triangle apex preparation: grid (tasks, d, chunks of kPrepChunk)
+// ---------------------------------------------------------------------
+// From the apex's merged records: the element list the sweeps read (its
+// child, counter, message, and the kappa of the child's own bucket), the
+// length of the zero-counter prefix and, for two-child apexes, each
+// element's same-child run [run_lo, run_hi].
+__device__ __forceinline__ int rec_child(const NodeRec *rec, int p) {
+  return (int)(rec[p].aj >> 16);
+}
+
+__global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
+    const NodeTask *tasks, EstBuffers B) {
+  __shared__ int s_lo[kPrepThreads], s_hi[kPrepThreads];
+  __shared__ int s_prev, s_next;
+  const NodeTask &T = tasks[blockIdx.x];
+  if (T.mode != kModeTriRootPrep || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
+  const int row = blockIdx.y;
+  const int m = T.m;
+  const int L = m * B.w;  // an apex has no parent or cut list
+  const int p0 = blockIdx.z * kPrepChunk;
+  if (p0 >= L) return;
+  const int p1 = min(L, p0 + kPrepChunk);
+  const NodeRec *rec =
+      B.nrec + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
+  const size_t slot_row = (size_t)T.out_slot * B.d + row;
+  TriElem *out = B.prep + slot_row * (size_t)B.Lprep;
+  TriElemN *outn = B.prepn + slot_row * (size_t)B.Lprep;
+  const int q0 = p0 + threadIdx.x * kPrepPer;  // my positions [q0, q0 + kPrepPer)
+  int last_start = -1, first_end = L;
+#pragma unroll
+  for (int u = 0; u < kPrepPer; ++u) {
+    const int pos = q0 + u;
+    if (pos >= p1) break;
+    const NodeRec nr = rec[pos];
+    const int a = (int)(nr.aj >> 16);
+    const int j = (int)(nr.aj & 0xFFFF);
+    TriElem e;
+    e.v = nr.v;
+    e.mu = nr.mu;
+    e.key = 0;
+    uint64_t own = 0;
+    if (T.child_cut[a] >= 0) {
+      // kappa of the child's own bucket on the edge to the apex
+      own = abs_u64(counter_at(B, T.child_side[a] ^ 1, row, j));
+      e.key = (own << 7) | (uint64_t)T.child_eid[a];
+    }
+    e.child = (uint32_t)a;
+    e.pad[0] = e.pad[1] = e.pad[2] = 0;
+    out[pos] = e;
+    if (m == 2) {
+      // truncating copy; the sweep reads it only when the bounds hold
+      TriElemN n;
+      n.v = (int32_t)e.v;
+      n.kc = ((uint32_t)a << 31) | (uint32_t)(own & 0x7FFFFFFFull);
+      n.mu = (int64_t)(uint64_t)e.mu;
+      n.vm = (int64_t)((uint64_t)e.v * (uint64_t)e.mu);
+      n.run_lo = 0;  // set below
+      n.run_hi = 0;
+      outn[pos] = n;
+      if (pos == 0 || rec_child(rec, pos - 1) != a) last_start = pos;
+      if (first_end == L && (pos == L - 1 || rec_child(rec, pos + 1) != a))
+        first_end = pos;
+    }
+    // the list is ascending in |v|: its zero counters form a prefix, and
+    // they add nothing to the sweep (it ends there)
+    if (e.v != 0) {
+      if (pos == 0 || rec[pos - 1].v == 0) B.prep_z[slot_row] = pos;
+    } else if (pos == L - 1) {
+      B.prep_z[slot_row] = L;
+    }
+  }
+  if (m != 2) return;  // uniform
+  // run starts: inclusive max-scan over my thread's positions; the run
+  // holding the chunk's first position may start in an earlier chunk
+  s_lo[threadIdx.x] = last_start;
+  s_hi[threadIdx.x] = first_end;
+  if (threadIdx.x == 0) {
+    s_prev = -1;
+    s_next = L;
+  }
+  __syncthreads();
+  for (int off = 1; off < kPrepThreads; off <<= 1) {
+    const int a = (int)threadIdx.x >= off ? s_lo[threadIdx.x - off] : -1;
+    const int b = (int)threadIdx.x + off < kPrepThreads ? s_hi[threadIdx.x + off] : L;
+    __syncthreads();
+    s_lo[threadIdx.x] = max(s_lo[threadIdx.x], a);
+    s_hi[threadIdx.x] = min(s_hi[threadIdx.x], b);
+    __syncthreads();
+  }
+  // the last run start before p0 and the first run end at or after p1
+  // (searched kPrepThreads positions at a time; both loops are uniform)
+  for (int base = p0 - 1; base >= 0; base -= kPrepThreads) {
+    const int q = base - (int)threadIdx.x;
+    if (q >= 0 && (q == 0 || rec_child(rec, q - 1) != rec_child(rec, q)))
+      atomicMax(&s_prev, q);
+    __syncthreads();
+    const bool found = s_prev >= 0;
+    __syncthreads();
+    if (found) break;
+  }
+  for (int base = p1; base < L; base += kPrepThreads) {
+    const int q = base + (int)threadIdx.x;
+    if (q < L && (q == L - 1 || rec_child(rec, q + 1) != rec_child(rec, q)))
+      atomicMin(&s_next, q);
+    __syncthreads();
+    const bool found = s_next < L;
+    __syncthreads();
+    if (found) break;
+  }
+  int cur = threadIdx.x > 0 ? s_lo[threadIdx.x - 1] : -1;
+  if (cur < 0) cur = s_prev;
+  int nxt = threadIdx.x + 1 < kPrepThreads ? s_hi[threadIdx.x + 1] : L;
+  if (nxt == L) nxt = s_next;
+  int lo_of[kPrepPer];
+#pragma unroll
+  for (int u = 0; u < kPrepPer; ++u) {
+    const int pos = q0 + u;
+    if (pos < p1 && (pos == 0 || rec_child(rec, pos - 1) != rec_child(rec, pos)))
+      cur = pos;
+    lo_of[u] = cur;
+  }
+#pragma unroll
+  for (int u = kPrepPer - 1; u >= 0; --u) {
+    const int pos = q0 + u;
+    if (pos >= p1) continue;
+    if (pos == L - 1 || rec_child(rec, pos + 1) != rec_child(rec, pos)) nxt = pos;
+    outn[pos].run_lo = lo_of[u];
+    outn[pos].run_hi = nxt;
   }
 }
 
@@ -1188,6 +1408,26 @@ hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
                        int stage_bytes, hipStream_t st) {
   hipLaunchKernelGGL(node_kernel, dim3(n, B.d), dim3(kNodeThreads),
                      (size_t)stage_bytes, st, tasks, B, stage_bytes);
+  return hipGetLastError();
+}
+
+hipError_t launch_node1(const NodeTask *tasks, int n, const EstBuffers &B,
+                        hipStream_t st) {
+  const int nch = (B.w + kN1Chunk - 1) / kN1Chunk;
+  hipLaunchKernelGGL(node1_prefix_kernel, dim3(n, B.d, nch), dim3(kN1Threads),
+                     0, st, tasks, B);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(node1_emit_kernel, dim3(n, B.d, 2 * nch), dim3(kN1Threads),
+                     B.counter_bits == 32 ? (size_t)B.w * 4 : 0, st, tasks, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
+                            const EstBuffers &B, hipStream_t st) {
+  hipLaunchKernelGGL(apex_prep_kernel,
+                     dim3(n, B.d, (Lmax_apex + kPrepChunk - 1) / kPrepChunk),
+                     dim3(kPrepThreads), 0, st, tasks, B);
   return hipGetLastError();
 }
 

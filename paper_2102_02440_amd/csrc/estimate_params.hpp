@@ -12,6 +12,13 @@ constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
 constexpr int kNodeStageBytes = 96 * 1024;  // node merge: staged magnitudes
 constexpr size_t kNodeScratchBytes = (size_t)1 << 30;  // per level launch
+constexpr int kN1Threads = 256;   // one-child nodes
+constexpr int kN1Per = 4;
+constexpr int kN1Chunk = kN1Threads * kN1Per;
+constexpr int kN1MaxChunks = (kMaxEstimateW + kN1Chunk - 1) / kN1Chunk;
+constexpr int kPrepThreads = 256;  // apex preparation
+constexpr int kPrepPer = 4;
+constexpr int kPrepChunk = kPrepThreads * kPrepPer;
 constexpr int kOrderThreads = 256;
 constexpr int kOrderTile = 2048;  // positions ordered by one workgroup
 constexpr int kOrderCap = 16384;  // longest two-child apex list run-ordered
