@@ -1001,6 +1001,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_tpre = carve(sizeof(TriPre) * np * d *
                               ((lp + kOrderTile - 1) / kOrderTile) *
                               (kOrderTile + 1));
+  const size_t o_tseg = carve(sizeof(int32_t) * np * d * (kFastSegs + 1));
   const size_t o_part = carve(16ull * std::max(1, pl.n_partial_slots) * d);
   void *scratch;
   st = ensure_scratch(ds, off, &scratch);
@@ -1035,6 +1036,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.prep_z = reinterpret_cast<int32_t *>(base + o_prepz);
   B.tkey = reinterpret_cast<uint32_t *>(base + o_tkey);
   B.tpre = reinterpret_cast<TriPre *>(base + o_tpre);
+  B.tseg = reinterpret_cast<int32_t *>(base + o_tseg);
   B.partial = reinterpret_cast<u128 *>(base + o_part);
   B.counter_bits = g->counter_bits;
   B.d = d;

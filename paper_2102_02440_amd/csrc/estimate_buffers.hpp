@@ -64,6 +64,7 @@ struct EstBuffers {
   int32_t *prep_z;            // [prep slot][row] leading zero-counter run
   uint32_t *tkey;             // [prep slot][row][Lprep] run-ordered keys
   TriPre *tpre;               // [prep slot][row][tile][kOrderTile + 1]
+  int32_t *tseg;              // [prep slot][row][kFastSegs + 1] sweep bounds
   u128 *partial;              // [slot][row]
   int32_t counter_bits;
   int32_t d;

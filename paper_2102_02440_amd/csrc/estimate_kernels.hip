@@ -980,8 +980,66 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
   }
 }
 
+// Segment bounds of the two-child sweep: the runs of [z, L) (a run
+// straddling z counts from z) split into kFastSegs groups of equal run
+// count, cut at run starts, so that the four sweep segments of a bucket
+// do equal numbers of run pieces.  bounds[k] = first position of group k
+// in ascending position order, bounds[kFastSegs] = L.
+__global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
+    const TriTask *tasks, EstBuffers B) {
+  __shared__ int s_cnt[kSegThreads];
+  const TriTask &T = tasks[blockIdx.x];
+  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
+  if (tri_path(*(ConstTask *)&T, B) != kTriFast) return;
+  const int row = blockIdx.y;
+  const size_t slot_row = (size_t)T.prep_slot * B.d + row;
+  const int z = B.prep_z[slot_row];
+  const int L = T.L;
+  if (L - z > kOrderCap) {  // unordered lists: equal position ranges
+    if (threadIdx.x <= kFastSegs)
+      B.tseg[slot_row * (kFastSegs + 1) + threadIdx.x] =
+          z + (int)((int64_t)(L - z) * threadIdx.x / kFastSegs);
+    return;
+  }
+  const TriElemN *el = B.prepn + slot_row * (size_t)B.Lprep;
+  int32_t *bounds = B.tseg + slot_row * (kFastSegs + 1);
+  // n <= kOrderCap positions: kSegPer consecutive ones per lane, loaded
+  // together
+  const int q0 = z + (int)threadIdx.x * kSegPer;
+  uint32_t starts = 0;  // bit u: position q0 + u starts a run
+#pragma unroll
+  for (int u = 0; u < kSegPer; ++u) {
+    const int p = q0 + u;
+    if (p < L && (p == z || el[p].run_lo == p)) starts |= 1u << u;
+  }
+  const int c = __popc(starts);
+  s_cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < kSegThreads; off <<= 1) {
+    const int a = (int)threadIdx.x >= off ? s_cnt[threadIdx.x - off] : 0;
+    __syncthreads();
+    s_cnt[threadIdx.x] += a;
+    __syncthreads();
+  }
+  const int R = s_cnt[kSegThreads - 1];
+  int g = s_cnt[threadIdx.x] - c;  // index of my first run start
+  if (threadIdx.x == 0) {
+    bounds[0] = z;
+    bounds[kFastSegs] = L;
+    for (int k = 1; k < kFastSegs; ++k)
+      if ((int)(((int64_t)R * k) / kFastSegs) >= R) bounds[k] = L;
+  }
+  for (; starts; starts &= starts - 1) {
+    const int p = q0 + __builtin_ctz(starts);
+    for (int k = 1; k < kFastSegs; ++k)
+      if ((int)(((int64_t)R * k) / kFastSegs) == g) bounds[k] = p;
+    ++g;
+  }
+}
+
 // Two-child apexes: grid (n_tri, d, ceil(w / kLaneThreads)), kFastSegs
-// segments of the sweep per block (segment s = threads s * kLaneThreads ..).
+// segments of the sweep per block (segment s = threads s * kLaneThreads ..,
+// bounds from tri_seg_kernel).
 // Cutting the descending sweep into segments is exact: a segment's runs see
 // the other child's running sum of the earlier segments plus their own, so
 //   G = sum_s [ G_s + A0(before s) * X1_s + A1(before s) * X0_s ]
@@ -989,7 +1047,6 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
 // A run piece is summed element by element, or, when the run is long and
 // tri_order_kernel has ordered the list, by one binary search over the
 // run-ordered keys (staged in LDS) and two prefix-sum reads.
-constexpr int kFastSegs = 4;
 constexpr int kSearchMin = 8;  // shortest run summed by search
 
 struct SegOut {
@@ -1028,8 +1085,11 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
   const int z = B.prep_z[slot_row];  // the sweep ends at the zero prefix
   const int len = T.L - z;
-  const int top = T.L - 1 - (int)((int64_t)len * seg / kFastSegs);
-  const int bottom = T.L - (int)((int64_t)len * (seg + 1) / kFastSegs);
+  // segment seg sweeps run group kFastSegs - 1 - seg (groups ascend in
+  // position, the sweep descends)
+  const int32_t *sb = B.tseg + slot_row * (kFastSegs + 1);
+  const int top = __builtin_amdgcn_readfirstlane(sb[kFastSegs - seg]) - 1;
+  const int bottom = __builtin_amdgcn_readfirstlane(sb[kFastSegs - 1 - seg]);
   const bool ordered = len <= kOrderCap;  // tri_order_kernel ran
   const uint32_t *tk = B.tkey + slot_row * (size_t)B.Lprep;
   if (ordered) {
@@ -1436,6 +1496,10 @@ hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
   const int tiles = (std::min(B.Lprep, kOrderCap) + kOrderTile - 1) / kOrderTile;
   hipLaunchKernelGGL(tri_order_kernel, dim3(n, B.d, tiles), dim3(kOrderThreads),
                      0, st, tasks, B);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(tri_seg_kernel, dim3(n, B.d), dim3(kSegThreads), 0, st,
+                     tasks, B);
   return hipGetLastError();
 }
 

@@ -20,9 +20,13 @@ constexpr int kPrepThreads = 256;  // apex preparation
 constexpr int kPrepPer = 4;
 constexpr int kPrepChunk = kPrepThreads * kPrepPer;
 constexpr int kOrderThreads = 256;
+constexpr int kSegThreads = 1024;
+constexpr int kSegPer = 16;
+constexpr int kFastSegs = 4;  // sweep segments per cut bucket
 constexpr int kOrderTile = 2048;  // positions ordered by one workgroup
 constexpr int kOrderCap = 16384;  // longest two-child apex list run-ordered
 constexpr int kFastStageBytes = kOrderCap * 4;  // its keys, staged in LDS
+static_assert(kSegThreads * kSegPer >= kOrderCap, "one pass over the list");
 
 enum { kModeMessage = 0, kModeTreeRoot = 1, kModeTriRootPrep = 2 };
 
