@@ -986,6 +986,9 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_tris = carve(sizeof(TriTask) * std::max<size_t>(1, pl.tris.size()));
   const size_t o_sps = carve(sizeof(SubplanTask) * pl.sps.size());
   const size_t o_sorted = carve(sizeof(uint64_t) * 2 * g->n_edges * d * (size_t)w);
+  int w2 = 1;
+  while (w2 < w) w2 <<= 1;
+  const size_t o_stmp = carve(sizeof(uint64_t) * 2 * g->n_edges * d * (size_t)w2);
   const size_t o_msg = carve(16ull * pl.n_msg_slots * d * (size_t)w);
   const size_t o_merged = carve(4ull * max_level_tasks * d * (size_t)std::max(1, pl.Lmax));
   const size_t o_nrec = carve(sizeof(NodeRec) * max_level_tasks * d *
@@ -1026,6 +1029,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.sides = reinterpret_cast<const void *const *>(base + o_sides);
   B.n_sel = g->n_selected;
   B.sorted = reinterpret_cast<const uint64_t *>(base + o_sorted);
+  B.sort_tmp = reinterpret_cast<uint64_t *>(base + o_stmp);
   B.msg = reinterpret_cast<u128 *>(base + o_msg);
   B.merged = reinterpret_cast<uint32_t *>(base + o_merged);
   B.nrec = reinterpret_cast<NodeRec *>(base + o_nrec);

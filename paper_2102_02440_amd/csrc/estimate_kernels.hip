@@ -19,8 +19,9 @@
 // incident bucket lists merged by kappa and two scans over the merged list.
 //
 // Kernels:
-//  sort_rows_kernel    one workgroup per (sketch, row): bitonic sort of the
-//                      w buckets by (|v|, j) in LDS (64-bit keys).
+//  sort_chunk_kernel / sort_merge_kernel
+//                      the w buckets of each (sketch, row) sorted by
+//                      (|v|, j): chunks sorted in LDS, merged by rank.
 //  node_kernel         one workgroup per (tree node, row): k-way merge of
 //                      the node's sorted lists by rank (binary search), then
 //                      block-wide scans of 128-bit A and G, emitting the
@@ -105,38 +106,91 @@ __device__ __forceinline__ uint64_t abs_u64(int64_t v) {
 }
 
 // ---------------------------------------------------------------------
-// sort: grid (n_jobs, d); job_side[blockIdx.x] = sketch side to sort
+// sort of each (sketch side, row) by (|v|, j): grid (n_jobs, d, chunks);
+// job_side[blockIdx.x] = sketch side
 // ---------------------------------------------------------------------
-__global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
+// sort_chunk_kernel: every kSortChunk keys (|v| << 16 | j) sorted in LDS
+// (bitonic; w is padded to a power of two with all-ones keys);
+// sort_merge_kernel: the final position of a key is its index in its
+// chunk plus the number of smaller keys in every other chunk (keys are
+// distinct: j differs), found by binary search over the LDS-staged chunks.
+__global__ __launch_bounds__(kSortThreads) void sort_chunk_kernel(
     const int32_t *job_side, EstBuffers B, int w2) {
-  extern __shared__ uint64_t skeys[];
+  __shared__ uint64_t sk[kSortChunk];
   const int side = job_side[blockIdx.x];
   const int row = blockIdx.y;
   const int w = B.w;
-  for (int j = threadIdx.x; j < w2; j += kSortThreads) {
+  const int c0 = blockIdx.z * kSortChunk;
+  const int n = min(kSortChunk, w2);  // chunk length (w2 < kSortChunk: one)
+  for (int t = threadIdx.x; t < n; t += kSortThreads) {
+    const int j = c0 + t;
     uint64_t k = ~0ull;
     if (j < w) k = (abs_u64(counter_at(B, side, row, j)) << 16) | (uint64_t)j;
-    skeys[j] = k;
+    sk[t] = k;
   }
   __syncthreads();
-  for (int k = 2; k <= w2; k <<= 1) {
+  for (int k = 2; k <= n; k <<= 1) {
     for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int i = threadIdx.x; i < w2; i += kSortThreads) {
-        const int ixj = i ^ jj;
-        if (ixj > i) {
-          const uint64_t a = skeys[i], b = skeys[ixj];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            skeys[i] = b;
-            skeys[ixj] = a;
-          }
+      for (int t = threadIdx.x; t < (n >> 1); t += kSortThreads) {
+        const int i = 2 * t - (t & (jj - 1));
+        const int ixj = i + jj;
+        const uint64_t a = sk[i], b = sk[ixj];
+        if ((a > b) == ((i & k) == 0)) {
+          sk[i] = b;
+          sk[ixj] = a;
         }
       }
       __syncthreads();
     }
   }
+  uint64_t *tmp = B.sort_tmp + ((size_t)side * B.d + row) * (size_t)w2;
+  for (int t = threadIdx.x; t < n; t += kSortThreads) tmp[c0 + t] = sk[t];
+}
+
+__global__ __launch_bounds__(kSortThreads) void sort_merge_kernel(
+    const int32_t *job_side, EstBuffers B, int w2) {
+  extern __shared__ uint64_t ak[];  // all w2 chunk-sorted keys of the row
+  const int side = job_side[blockIdx.x];
+  const int row = blockIdx.y;
+  const int w = B.w;
+  const int n = min(kSortChunk, w2);
+  const int nch = w2 / n;
+  const uint64_t *tmp = B.sort_tmp + ((size_t)side * B.d + row) * (size_t)w2;
+  for (int t = threadIdx.x; t < w2; t += kSortThreads) ak[t] = tmp[t];
+  __syncthreads();
   uint64_t *out = const_cast<uint64_t *>(sorted_of(B, side, row));
-  for (int j = threadIdx.x; j < w; j += kSortThreads) out[j] = skeys[j];
+  const int mine = blockIdx.z;
+  constexpr int U = kSortChunk / kSortThreads;
+  uint64_t key[U];
+  int pos[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int t = threadIdx.x + u * kSortThreads;
+    key[u] = t < n ? ak[mine * n + t] : ~0ull;
+    pos[u] = t;
+  }
+  for (int c = 0; c < nch; ++c) {
+    if (c == mine) continue;  // uniform
+    const uint64_t *ck = ak + (size_t)c * n;
+    int base[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) base[u] = 0;
+    int m = n;
+    while (m > 1) {
+      const int half = m >> 1;
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        base[u] = ck[base[u] + half] < key[u] ? base[u] + half : base[u];
+      m -= half;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) pos[u] += base[u] + (ck[base[u]] < key[u] ? 1 : 0);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int t = threadIdx.x + u * kSortThreads;
+    if (t < n && pos[u] < w) out[pos[u]] = key[u];
+  }
 }
 
 // ---------------------------------------------------------------------
@@ -1459,8 +1513,14 @@ hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
                             const EstBuffers &B, hipStream_t st) {
   int w2 = 1;
   while (w2 < B.w) w2 <<= 1;
-  hipLaunchKernelGGL(sort_rows_kernel, dim3(n_jobs, B.d), dim3(kSortThreads),
-                     (size_t)w2 * sizeof(uint64_t), st, job_side, B, w2);
+  const int nch = std::max(1, w2 / kSortChunk);
+  hipLaunchKernelGGL(sort_chunk_kernel, dim3(n_jobs, B.d, nch),
+                     dim3(kSortThreads), 0, st, job_side, B, w2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sort_merge_kernel, dim3(n_jobs, B.d, nch),
+                     dim3(kSortThreads), (size_t)w2 * sizeof(uint64_t), st,
+                     job_side, B, w2);
   return hipGetLastError();
 }
 

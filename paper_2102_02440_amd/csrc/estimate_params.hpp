@@ -7,7 +7,8 @@ namespace compass {
 
 constexpr int kMaxChild = 6;
 constexpr int kNodeThreads = 1024;
-constexpr int kSortThreads = 1024;
+constexpr int kSortThreads = 256;
+constexpr int kSortChunk = 1024;  // keys sorted by one workgroup
 constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
 constexpr int kNodeStageBytes = 96 * 1024;  // node merge: staged magnitudes
