@@ -40,6 +40,7 @@ hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
                               int n_slices, int d, int w,
                               void *const *counters, int n_sketches,
                               int counter_bits, int accumulate,
+                              const unsigned long long *survivors,
                               hipStream_t st);
 hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
                             const EstBuffers &B, hipStream_t st);
@@ -334,12 +335,18 @@ static compass_status sketch_build_impl(
   compass_status st = device_state(&ds);
   if (st != COMPASS_OK) return st;
 
+  // Two phases (compaction of the survivors' keys, then hashing them) for
+  // rows too wide for LDS-private partials, and for every table with
+  // predicates: the predicates are then evaluated once (not once per slice
+  // group), and the hashing reads only survivors, many workgroups at a
+  // time.  Tables without predicates take the fused scan.
   const bool wide = (size_t)w * 4 > kLdsBudget;
+  const bool two_phase = wide || n_preds > 0;
   if (!accumulate) {
     ProfScope ps("fill_zero", stream);
-    // the LDS path's reduction overwrites the counters itself, except
+    // the fused scan's reduction overwrites the counters itself, except
     // for an empty table, which launches nothing else
-    if (wide || n_rows == 0)
+    if (two_phase || n_rows == 0)
       for (int s = 0; s < n_sketches; ++s)
         HIP_OK(launch_fill_zero(sketches[s].counters,
                                 (int64_t)d * w * (counter_bits / 8), stream));
@@ -348,8 +355,7 @@ static compass_status sketch_build_impl(
   }
   if (n_rows == 0) return COMPASS_OK;
 
-  if (wide) {
-    // rows too wide for LDS-private partials: direct global atomics
+  if (two_phase) {
     const int S = n_sketches * d;
     std::vector<RowSeeds> sd(S);
     for (int s = 0; s < n_sketches; ++s)
@@ -420,7 +426,9 @@ static compass_status sketch_build_impl(
       {
         ProfScope ps("slab_reduce", stream);
         HIP_OK(launch_slab_reduce(wslab, chunks, S, d, w, cp.data(), n_sketches,
-                                  counter_bits, 1, stream));
+                                  counter_bits, 1,
+                                  reinterpret_cast<const unsigned long long *>(count),
+                                  stream));
       }
     }
     return COMPASS_OK;
@@ -513,7 +521,7 @@ static compass_status sketch_build_impl(
     for (int s = 0; s < n_sketches; ++s) cp[s] = sketches[s].counters;
     ProfScope ps("slab_reduce", stream);
     HIP_OK(launch_slab_reduce(base.slab, chunks, S, d, w, cp.data(), n_sketches,
-                              counter_bits, accumulate, stream));
+                              counter_bits, accumulate, nullptr, stream));
   }
   return COMPASS_OK;
 }

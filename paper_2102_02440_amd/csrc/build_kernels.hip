@@ -184,7 +184,16 @@ __global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
 // int32 registers and clears them.  One hash per update even at w = 65536.
 constexpr int kWidePiece = 32767;
 constexpr int kWidePairsPerLane = 32;   // 32768 words / 1024 lanes
+constexpr int64_t kWideMinChunk = 16384;  // survivors per hashing chunk
 constexpr int kWideRange = 2 * kWidePairsPerLane * kBuildThreads;  // 65536
+
+// Chunks of the survivors that carry work: at least kWideMinChunk
+// survivors each (a chunk's fixed cost is clearing, folding and writing w
+// counters), at most `chunks`.  The slab reduction reads the same number.
+__device__ __forceinline__ int64_t active_chunks(int64_t n, int64_t chunks) {
+  const int64_t need = (n + kWideMinChunk - 1) / kWideMinChunk;
+  return need < 1 ? 1 : (need < chunks ? need : chunks);
+}
 
 __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
     const uint64_t *__restrict__ surv, int64_t cap,
@@ -196,6 +205,9 @@ __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
   const int sl = blockIdx.x % n_slices;
   const int r = (blockIdx.x / n_slices) % ranges;
   const int k = blockIdx.x / (n_slices * ranges);
+  const int64_t n = (int64_t)*count;
+  const int64_t act = active_chunks(n, chunks);
+  if (k >= act) return;  // uniform: no survivors for this chunk
   const int w = (int)bm.w;
   const int wr = (w + ranges - 1) / ranges;  // <= kWideRange
   const int lo = r * wr, hi = min(w, lo + wr);
@@ -204,8 +216,7 @@ __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
   int32_t acc[2 * kWidePairsPerLane];
 #pragma unroll
   for (int i = 0; i < 2 * kWidePairsPerLane; ++i) acc[i] = 0;
-  const int64_t n = (int64_t)*count;
-  const int64_t a = n * k / chunks, b = n * (k + 1) / chunks;
+  const int64_t a = n * k / act, b = n * (k + 1) / act;
   const int s = sl / d;
   const RowSeeds sd = seeds[sl];
   const uint64_t *x = surv + (int64_t)s * cap;
@@ -306,7 +317,10 @@ struct CounterList {
 __global__ void slab_reduce_kernel(const int32_t *__restrict__ slab,
                                    int64_t chunks, int32_t n_slices, int32_t d,
                                    int32_t w, CounterList cl,
-                                   int32_t counter_bits, int32_t accumulate) {
+                                   int32_t counter_bits, int32_t accumulate,
+                                   const unsigned long long *survivors) {
+  // two-phase builds: only the chunks wide_hash_kernel filled
+  if (survivors) chunks = active_chunks((int64_t)*survivors, chunks);
   const int64_t total = (int64_t)n_slices * w;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
        k += (int64_t)gridDim.x * blockDim.x) {
@@ -339,6 +353,7 @@ hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
                               int n_slices, int d, int w,
                               void *const *counters, int n_sketches,
                               int counter_bits, int accumulate,
+                              const unsigned long long *survivors,
                               hipStream_t st) {
   CounterList cl;
   for (int s = 0; s < kMaxSketches; ++s)
@@ -348,7 +363,7 @@ hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(slab_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      st, slab, chunks, n_slices, d, w, cl, counter_bits,
-                     accumulate);
+                     accumulate, survivors);
   return hipGetLastError();
 }
 
