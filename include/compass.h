@@ -420,7 +420,8 @@ compass_status compass_enumerate(int32_t n_tables, int32_t n_edges,
  * of HIP events on the launch stream around each kernel launch it makes.
  * compass_profile_take(name) waits for the recorded events of kernel `name`
  * ("scan_sketch", "slab_reduce", "wide_compact", "wide_hash", "fill_zero",
- * "sort_rows", "node", "tri_lane", "finish"),
+ * "sort_rows", "node", "tri_order", "tri_lane", "finish", "scan2d",
+ * "chain3", "agms_build", "agms_estimate"),
  * returns their count and summed elapsed milliseconds, and forgets them. */
 compass_status compass_profile_enable(int32_t on);
 compass_status compass_profile_take(const char *name, int64_t *count,

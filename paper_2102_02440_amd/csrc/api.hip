@@ -437,8 +437,14 @@ static compass_status sketch_build_impl(
   // slice groups: consecutive (sketch, row) slices whose int32 partials fit
   // the LDS budget; among the group sizes that fit, prefer one that splits
   // the slices into equal groups (every workgroup then does equal work)
+  // (the fused scan builds tables without predicates: no row queue; the
+  // queue of one kScanTile is kept for a caller of the fused path with
+  // predicates, inside the CU's 160 KiB with a margin for static LDS)
+  const size_t queue_bytes = n_preds > 0 ? (size_t)kScanTile * 4 : 0;
+  const size_t partial_budget =
+      std::min<size_t>(kLdsBudget, 160 * 1024 - 1024 - queue_bytes);
   const int S = n_sketches * d;
-  const int per_max = (int)std::min<size_t>(kLdsBudget / ((size_t)w * 4),
+  const int per_max = (int)std::min<size_t>(partial_budget / ((size_t)w * 4),
                                             (size_t)kMaxLaunchSlices);
   int per_group = std::min(per_max, S);
   {
@@ -461,17 +467,17 @@ static compass_status sketch_build_impl(
   // its LDS partials small next to its scan.  Each chunk writes its partial
   // counters to a slab (summed by one reduction kernel), which is cheap next
   // to the scan: bound the slab to 1 GiB.
-  const size_t lds_block = (size_t)per_group * w * 4 + (size_t)kBuildTile * 4;
-  const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / lds_block)));
+  const size_t lds_block = (size_t)per_group * w * 4 + queue_bytes;
+  const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / (lds_block + 1024))));
   const int64_t slots = (int64_t)ds->n_cu * per_cu;
-  const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
+  const int64_t tiles = (n_rows + kScanTile - 1) / kScanTile;
   int64_t chunks = std::max<int64_t>(1, 2 * slots / n_groups_total);
   chunks = std::min(chunks, std::max<int64_t>(1, tiles / 8));
   const size_t slab_row = (size_t)S * w * 4;
   chunks = std::min<int64_t>(chunks, std::max<size_t>(1, ((size_t)1 << 30) / slab_row));
   int64_t rows_per_chunk = (n_rows + chunks - 1) / chunks;
   rows_per_chunk =
-      (rows_per_chunk + kBuildTile - 1) / kBuildTile * kBuildTile;
+      (rows_per_chunk + kScanTile - 1) / kScanTile * kScanTile;
   chunks = (n_rows + rows_per_chunk - 1) / rows_per_chunk;
   base.rows_per_chunk = rows_per_chunk;
   void *slab;
@@ -509,7 +515,7 @@ static compass_status sketch_build_impl(
     int max_group = 0;
     for (int g = 0; g < ng; ++g)
       max_group = std::max(max_group, P.group_begin[g + 1] - P.group_begin[g]);
-    const size_t lds = (size_t)max_group * w * 4 + (size_t)kBuildTile * 4;
+    const size_t lds = (size_t)max_group * w * 4 + queue_bytes;
     const int64_t blocks = chunks * ng;
     if (blocks > 0x7FFFFFFF)
       return fail(COMPASS_E_RANGE, "too many workgroups");

@@ -64,7 +64,8 @@ __global__ __launch_bounds__(kBuildThreads) void scan_sketch_kernel(
   const int ns = se - sb;
   const int w = (int)P.bm.w;
   int32_t *cnt = lds;                       // ns * w partial counters
-  int32_t *queue = lds + (size_t)ns * w;    // kBuildTile row offsets
+  int32_t *queue = lds + (size_t)ns * w;    // kScanTile row offsets (with
+                                            // predicates only)
 
   for (int i = threadIdx.x; i < ns * w; i += kBuildThreads) cnt[i] = 0;
   __syncthreads();
@@ -73,7 +74,8 @@ __global__ __launch_bounds__(kBuildThreads) void scan_sketch_kernel(
   RowSink sink = P.sink;
   if (gi != 0) sink.out = nullptr;  // one slice group writes the rows
   const uint64_t sel =
-      scan_rows(job, row0, row1, sb, se, cnt, queue, &s_qn, sink);
+      scan_rows<ParamJob, kScanRowsPerThread>(job, row0, row1, sb, se, cnt,
+                                              queue, &s_qn, sink);
   // partial counters of this chunk -> its slab rows (plain coalesced
   // stores; the reduction kernel sums the chunks in a fixed order)
   const size_t S = (size_t)P.n_slices_total;

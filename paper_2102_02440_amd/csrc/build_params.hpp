@@ -9,6 +9,10 @@ namespace compass {
 constexpr int kBuildThreads = 1024;
 constexpr int kBuildRowsPerThread = 4;
 constexpr int kBuildTile = kBuildThreads * kBuildRowsPerThread;
+// the one-table fused scan (tables without predicates) takes longer tiles:
+// twice the independent hash chains per lane
+constexpr int kScanRowsPerThread = 8;
+constexpr int kScanTile = kBuildThreads * kScanRowsPerThread;
 constexpr int kMaxPreds = 8;
 constexpr int kMaxSketches = 16;
 constexpr int kMaxLaunchSlices = 48;   // slices whose seeds ride in kernargs

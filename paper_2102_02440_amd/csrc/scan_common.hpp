@@ -128,16 +128,17 @@ __device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
 }
 
 // Scans rows [row0, row1) of job J into the LDS partial counters `cnt` of
-// slices [sb, se) (slice sl at cnt + (sl - sb) * w).  Returns, in thread 0,
-// the number of qualifying rows.  `queue` holds kBuildTile row offsets;
-// `s_qn` is a shared counter.  Every thread of the block must call it.
-template <class J>
+// slices [sb, se) (slice sl at cnt + (sl - sb) * w), in tiles of
+// kBuildThreads * kRowsPerThread rows.  Returns, in thread 0, the number of
+// qualifying rows.  `queue` holds a tile's row offsets (unused, and may be
+// null, when the job has no predicates); `s_qn` is a shared counter.  Every
+// thread of the block must call it.
+template <class J, int kRowsPerThread = kBuildRowsPerThread>
 __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
                               int sb, int se, int32_t *cnt, int32_t *queue,
                               int32_t *s_qn, RowSink sink = RowSink{}) {
   __shared__ unsigned long long s_roff;
-  constexpr int kRowsPerThread = kBuildRowsPerThread;
-  constexpr int kTile = kBuildTile;
+  constexpr int kTile = kBuildThreads * kRowsPerThread;
   // the slice range is the same in every lane: say so, so that the slice
   // tables and seeds are read with scalar loads and the per-slice branches
   // stay uniform
