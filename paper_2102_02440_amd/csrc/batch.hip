@@ -147,6 +147,204 @@ __global__ __launch_bounds__(kBuildThreads) void batch_scan_kernel(
   }
 }
 
+// ---------------------------------------------------------------------
+// jobs with predicates: two phases over segments (a row range of one job
+// whose survivors' key field elements fit its own region of the plan's
+// survivor arena; segments of one round share the arena, rounds run one
+// after another)
+// ---------------------------------------------------------------------
+struct BatchSeg {
+  int64_t row0, row1;
+  uint64_t *surv;              // [n_sketch][row1 - row0] field elements
+  unsigned long long *count;   // survivors written so far
+  int32_t job;
+  int32_t chunks;              // hashing chunks at most (all rows surviving)
+};
+
+struct CompactItem {
+  int64_t row0, row1;          // table rows, inside the segment
+  int32_t seg;
+  int32_t pad;
+};
+
+struct HashItem {
+  int32_t seg;
+  int32_t slice;
+  int32_t chunk;
+  int32_t pad;
+};
+
+typedef const __attribute__((address_space(4))) BatchSeg KSeg;
+typedef const __attribute__((address_space(4))) CompactItem KCItem;
+typedef const __attribute__((address_space(4))) HashItem KHItem;
+
+constexpr int kBatchQueue = 16384;       // survivors buffered in LDS
+constexpr int64_t kBatchChunk = 1 << 20;  // survivors per hashing chunk
+constexpr int kBatchPiece = 32767;        // survivors per 16-bit fold
+constexpr int kBatchPairsPerLane = 16;    // 32768 buckets / 2 / 1024 lanes
+
+// Phase A: one workgroup per compact item compacts its tiles (predicates
+// evaluated once per row) into an LDS queue of survivor offsets and, when
+// the queue is nearly full or the item ends, reserves space in the
+// segment's region with one atomic and gathers the key field element of
+// every (sketch, survivor) pair.
+__global__ __launch_bounds__(kBuildThreads) void batch_compact_kernel(
+    const BatchJob *jobs, const BatchSeg *segs, const CompactItem *items) {
+  __shared__ int32_t queue[kBatchQueue];
+  __shared__ int32_t s_qn;
+  __shared__ unsigned long long s_off;
+  KCItem &it = ((KCItem *)items)[blockIdx.x];
+  const int64_t r0 = it.row0, r1 = it.row1;
+  KSeg &sg = ((KSeg *)segs)[it.seg];
+  const GlobalJob job{(KJob *)jobs + sg.job, nullptr};
+  const int64_t seg_rows = sg.row1 - sg.row0;
+  const int n_preds = job.n_preds();
+  const int n_sketch = job.J->n_sketch;
+  uint64_t sel = 0;
+  int qtot = 0;  // block-uniform
+  for (int64_t base = r0; base < r1; base += kBuildTile) {
+    const int nt = (int)min((int64_t)kBuildTile, r1 - base);
+    qtot = compact_tile<GlobalJob, kBuildRowsPerThread>(
+        job, base, nt, n_preds, queue, &s_qn, qtot, (int)(base - r0));
+    const bool last = base + kBuildTile >= r1;
+    if (qtot > kBatchQueue - kBuildTile || (last && qtot > 0)) {
+      __syncthreads();  // queue complete
+      if (threadIdx.x == 0) s_off = atomicAdd(sg.count, (unsigned long long)qtot);
+      __syncthreads();
+      const int64_t off = (int64_t)s_off;
+      for (int s = 0; s < n_sketch; ++s) {
+        const KeyDev kd = job.key(s);
+        uint64_t *dst = sg.surv + (int64_t)s * seg_rows + off;
+        for (int q0 = threadIdx.x; q0 < qtot; q0 += 4 * kBuildThreads) {
+          uint64_t v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * kBuildThreads;
+            v[u] = q < qtot ? load_field(kd, r0 + queue[q]) : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u * kBuildThreads;
+            if (q < qtot) dst[q] = v[u];
+          }
+        }
+      }
+      sel += (uint64_t)qtot;
+      qtot = 0;
+    }
+    __syncthreads();  // queue, s_qn and s_off are reused
+  }
+  if (threadIdx.x == 0 && sel)
+    atomicAdd(reinterpret_cast<unsigned long long *>(job.n_selected()),
+              (unsigned long long)sel);
+}
+
+// chunks of a segment's survivors that carry work: at least kBatchChunk
+// survivors each, at most the planned number
+__device__ __forceinline__ int64_t batch_active_chunks(int64_t n,
+                                                       int64_t chunks) {
+  const int64_t need = (n + kBatchChunk - 1) / kBatchChunk;
+  return need < 1 ? 1 : (need < chunks ? need : chunks);
+}
+
+// Phase B: one workgroup per (segment, slice, chunk) hashes its chunk of the
+// segment's survivors for one sketch row into two 16-bit counters per LDS
+// word (+-1 to the low half, +-65536 to the word for the high half; exact
+// while both halves stay within [-32767, 32767], so survivors are taken
+// kBatchPiece at a time and folded into int32 registers), then adds its
+// non-zero counters to the job's counters (zeroed by the plan's first node).
+__global__ __launch_bounds__(kBuildThreads) void batch_hash_kernel(
+    const BatchJob *jobs, const BatchSeg *segs, const HashItem *items,
+    const RowSeeds *seeds) {
+  extern __shared__ uint32_t pairs[];
+  KHItem &it = ((KHItem *)items)[blockIdx.x];
+  KSeg &sg = ((KSeg *)segs)[it.seg];
+  const int64_t n = (int64_t)*sg.count;
+  const int64_t act = batch_active_chunks(n, sg.chunks);
+  if (it.chunk >= act) return;  // uniform: no survivors for this chunk
+  const GlobalJob job{(KJob *)jobs + sg.job, (KSeeds *)seeds};
+  const BucketMod bm = job.bm();
+  const int w = (int)bm.w;  // <= 2 * kBatchPairsPerLane * kBuildThreads
+  const int nwords = (w + 1) / 2;
+  const int sl = it.slice;
+  const int s = job.slice_sketch(sl), row = job.slice_row(sl);
+  const RowSeeds sd = job.seeds(sl);
+  const int64_t seg_rows = sg.row1 - sg.row0;
+  const uint64_t *x = sg.surv + (int64_t)s * seg_rows;
+  const int64_t a = n * it.chunk / act, b = n * (it.chunk + 1) / act;
+  for (int j = threadIdx.x; j < nwords; j += kBuildThreads) pairs[j] = 0;
+  int32_t acc[2 * kBatchPairsPerLane];
+#pragma unroll
+  for (int i = 0; i < 2 * kBatchPairsPerLane; ++i) acc[i] = 0;
+  for (int64_t p0 = a; p0 < b; p0 += kBatchPiece) {
+    const int64_t p1 = min(b, p0 + (int64_t)kBatchPiece);
+    __syncthreads();  // cleared words
+    for (int64_t i0 = p0 + threadIdx.x; i0 < p1; i0 += 4 * kBuildThreads) {
+      uint64_t xs[4];
+      bool ok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t i = i0 + u * kBuildThreads;
+        ok[u] = i < p1;
+        xs[u] = ok[u] ? x[i] : 0;
+      }
+      bool wide_key = false;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wide_key = wide_key || (xs[u] >> 32) != 0;
+      int32_t sign[4];
+      uint32_t bk[4];
+      if (!__any(wide_key)) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if ((xs[u] >> 32) == 0)
+            hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
+          else
+            hash_xi_h<false>(xs[u], sd, bm, sign[u], bk[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (ok[u])
+          atomicAdd(&pairs[bk[u] >> 1],
+                    (bk[u] & 1) ? (uint32_t)sign[u] << 16 : (uint32_t)sign[u]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kBatchPairsPerLane; ++i) {
+      const int wi = threadIdx.x + i * kBuildThreads;
+      if (wi < nwords) {
+        const uint32_t word = pairs[wi];
+        const int32_t l16 = (int32_t)(int16_t)(word & 0xFFFFu);
+        acc[2 * i] += l16;
+        acc[2 * i + 1] += (int32_t)(word - (uint32_t)l16) >> 16;
+        pairs[wi] = 0;
+      }
+    }
+  }
+  // integer atomics: order-independent, hence exact
+  const size_t rbase = (size_t)row * w;
+#pragma unroll
+  for (int i = 0; i < kBatchPairsPerLane; ++i) {
+    const int wi = threadIdx.x + i * kBuildThreads;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = 2 * wi + h;
+      const int32_t v = acc[2 * i + h];
+      if (j < w && v != 0) {
+        if (job.counter_bits() == 32)
+          atomicAdd(reinterpret_cast<int32_t *>(job.counters(s)) + rbase + j, v);
+        else
+          atomicAdd(reinterpret_cast<unsigned long long *>(job.counters(s)) +
+                        rbase + j,
+                    (unsigned long long)(int64_t)v);
+      }
+    }
+  }
+}
+
 __global__ void zero_regions_kernel(const ZeroRegion *r, int32_t n) {
   for (int k = blockIdx.y; k < n; k += gridDim.y) {
     uint32_t *p = reinterpret_cast<uint32_t *>(r[k].p);
@@ -205,7 +403,86 @@ struct compass_batch_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int n_cu = 0;
+  // jobs with predicates: segments, rounds and the items of both phases
+  struct Round {
+    size_t c0, c1, h0, h1;
+  };
+  std::vector<BatchSeg> segs;        // surv = arena offset until uploaded
+  std::vector<size_t> seg_arena_off;
+  std::vector<CompactItem> citems;
+  std::vector<HashItem> hitems;
+  std::vector<Round> rounds;
+  size_t arena_bytes = 0;
+  char *arena = nullptr;
+  size_t hash_lds = 0;
+  BatchSeg *d_segs = nullptr;
+  CompactItem *d_citems = nullptr;
+  HashItem *d_hitems = nullptr;
+  unsigned long long *d_counts = nullptr;
 };
+
+// Jobs with predicates take two phases (compaction of the survivors' key
+// field elements, then hashing them per sketch row by many workgroups), so
+// their predicates are evaluated once instead of once per slice group.
+// Their rows are cut into segments whose worst-case survivor regions (every
+// row surviving) fit the arena; segments are packed into rounds that share
+// the arena and run one after another.
+static void plan_two_phase(compass_batch_plan_s &pl) {
+  constexpr size_t kArenaMax = (size_t)8 << 30;
+  constexpr int64_t kCompactRows = 64 * kBuildTile;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  pl.segs.clear();
+  pl.seg_arena_off.clear();
+  pl.citems.clear();
+  pl.hitems.clear();
+  pl.rounds.clear();
+  pl.arena_bytes = 0;
+  pl.hash_lds = 0;
+  size_t used = 0;
+  compass_batch_plan_s::Round cur{0, 0, 0, 0};
+  for (size_t j = 0; j < pl.jobs.size(); ++j) {
+    const BatchJob &J = pl.jobs[j];
+    const int64_t n = pl.job_rows[j];
+    if (J.n_preds == 0 || n == 0) continue;
+    pl.hash_lds = std::max(pl.hash_lds, (size_t)((pl.job_w[j] + 1) / 2) * 4);
+    const int64_t max_rows = std::max<int64_t>(
+        kBuildTile, (int64_t)(kArenaMax / (8 * (size_t)J.n_sketch)) /
+                        kBuildTile * kBuildTile);
+    for (int64_t r0 = 0; r0 < n; r0 += max_rows) {
+      const int64_t r1 = std::min(n, r0 + max_rows);
+      const size_t bytes = al((size_t)(r1 - r0) * J.n_sketch * 8);
+      if (used > 0 && used + bytes > kArenaMax) {  // close the round
+        cur.c1 = pl.citems.size();
+        cur.h1 = pl.hitems.size();
+        pl.rounds.push_back(cur);
+        cur = {pl.citems.size(), 0, pl.hitems.size(), 0};
+        used = 0;
+      }
+      BatchSeg sg;
+      memset(&sg, 0, sizeof sg);
+      sg.row0 = r0;
+      sg.row1 = r1;
+      sg.job = (int32_t)j;
+      sg.chunks = (int32_t)((r1 - r0 + kBatchChunk - 1) / kBatchChunk);
+      const int32_t si = (int32_t)pl.segs.size();
+      pl.segs.push_back(sg);
+      pl.seg_arena_off.push_back(used);
+      used += bytes;
+      pl.arena_bytes = std::max(pl.arena_bytes, used);
+      for (int64_t a = r0; a < r1; a += kCompactRows)
+        pl.citems.push_back(CompactItem{a, std::min(r1, a + kCompactRows), si, 0});
+      const int S = pl.job_slices[j];
+      for (int sl = 0; sl < S; ++sl)
+        for (int k = 0; k < sg.chunks; ++k)
+          pl.hitems.push_back(HashItem{si, sl, k, 0});
+    }
+  }
+  if (!pl.segs.empty()) {
+    cur.c1 = pl.citems.size();
+    cur.h1 = pl.hitems.size();
+    pl.rounds.push_back(cur);
+  }
+}
 
 static BucketMod bmod(uint32_t w) {
   BucketMod m;
@@ -227,8 +504,10 @@ static size_t make_items(const compass_batch_plan_s &pl, const compass_tune &t,
     const int S = pl.job_slices[j];
     const int w = pl.job_w[j];
     if (n == 0 || S == 0) continue;
+    if (pl.jobs[j].n_preds > 0) continue;  // two-phase (plan_two_phase)
     const int per_max = std::max(1, std::min<int>(
-        (int)(t.lds_budget / ((size_t)w * 4)), kMaxLaunchSlices));
+        (int)(std::min<size_t>(t.lds_budget, kLdsBudget) / ((size_t)w * 4)),
+        kMaxLaunchSlices));
     const int ng = (S + per_max - 1) / per_max;
     int64_t rpi = std::max<int64_t>(kBuildTile, t.rows_per_item);
     rpi = (rpi + kBuildTile - 1) / kBuildTile * kBuildTile;
@@ -248,18 +527,17 @@ static size_t make_items(const compass_batch_plan_s &pl, const compass_tune &t,
       }
     }
   }
-  // largest first (rows x slices; dense jobs weigh their full hashing)
+  // largest first (rows x slices)
   std::stable_sort(items.begin(), items.end(),
                    [&](const BatchItem &a, const BatchItem &b) {
                      const double ca = (double)(a.row1 - a.row0) *
-                                       (1 + (a.slice_end - a.slice_begin) *
-                                                (pl.jobs[a.job].n_preds ? 0.1 : 1.0));
+                                       (1 + (a.slice_end - a.slice_begin));
                      const double cb = (double)(b.row1 - b.row0) *
-                                       (1 + (b.slice_end - b.slice_begin) *
-                                                (pl.jobs[b.job].n_preds ? 0.1 : 1.0));
+                                       (1 + (b.slice_end - b.slice_begin));
                      return ca > cb;
                    });
-  return lds_max + (size_t)kBuildTile * 4;
+  // jobs without predicates only: the row queue is never used
+  return lds_max;
 }
 
 static compass_status upload_plan(compass_batch_plan_s &pl,
@@ -268,9 +546,14 @@ static compass_status upload_plan(compass_batch_plan_s &pl,
   const size_t b_jobs = al(sizeof(BatchJob) * pl.jobs.size());
   const size_t b_items = al(sizeof(BatchItem) * std::max<size_t>(1, items.size()));
   const size_t b_seeds = al(sizeof(RowSeeds) * std::max<size_t>(1, pl.seeds.size()));
-  const size_t b_zero = al(sizeof(ZeroRegion) * (pl.zeros.size() + 1));
+  const size_t b_zero = al(sizeof(ZeroRegion) * (pl.zeros.size() + 2));
   const size_t b_queue = 256;
-  const size_t total = b_jobs + b_items + b_seeds + b_zero + b_queue;
+  const size_t b_segs = al(sizeof(BatchSeg) * std::max<size_t>(1, pl.segs.size()));
+  const size_t b_cit = al(sizeof(CompactItem) * std::max<size_t>(1, pl.citems.size()));
+  const size_t b_hit = al(sizeof(HashItem) * std::max<size_t>(1, pl.hitems.size()));
+  const size_t b_cnt = al(8 * std::max<size_t>(1, pl.segs.size()));
+  const size_t total = b_jobs + b_items + b_seeds + b_zero + b_queue + b_segs +
+                       b_cit + b_hit + b_cnt;
   if (total > pl.dbytes) {
     if (pl.dmem) BHIP(hipFree(pl.dmem));
     pl.dmem = nullptr;
@@ -282,9 +565,30 @@ static compass_status upload_plan(compass_batch_plan_s &pl,
   pl.d_items = reinterpret_cast<BatchItem *>(pl.dmem + off); off += b_items;
   pl.d_seeds = reinterpret_cast<RowSeeds *>(pl.dmem + off); off += b_seeds;
   pl.d_zeros = reinterpret_cast<ZeroRegion *>(pl.dmem + off); off += b_zero;
-  pl.d_queue = reinterpret_cast<int32_t *>(pl.dmem + off);
+  pl.d_queue = reinterpret_cast<int32_t *>(pl.dmem + off); off += b_queue;
+  pl.d_segs = reinterpret_cast<BatchSeg *>(pl.dmem + off); off += b_segs;
+  pl.d_citems = reinterpret_cast<CompactItem *>(pl.dmem + off); off += b_cit;
+  pl.d_hitems = reinterpret_cast<HashItem *>(pl.dmem + off); off += b_hit;
+  pl.d_counts = reinterpret_cast<unsigned long long *>(pl.dmem + off);
+  if (pl.arena_bytes > 0 && !pl.arena) BHIP(hipMalloc(&pl.arena, pl.arena_bytes));
+  std::vector<BatchSeg> sg = pl.segs;
+  for (size_t k = 0; k < sg.size(); ++k) {
+    sg[k].surv = reinterpret_cast<uint64_t *>(pl.arena + pl.seg_arena_off[k]);
+    sg[k].count = pl.d_counts + k;
+  }
+  if (!sg.empty())
+    BHIP(hipMemcpy(pl.d_segs, sg.data(), sizeof(BatchSeg) * sg.size(),
+                   hipMemcpyHostToDevice));
+  if (!pl.citems.empty())
+    BHIP(hipMemcpy(pl.d_citems, pl.citems.data(),
+                   sizeof(CompactItem) * pl.citems.size(), hipMemcpyHostToDevice));
+  if (!pl.hitems.empty())
+    BHIP(hipMemcpy(pl.d_hitems, pl.hitems.data(),
+                   sizeof(HashItem) * pl.hitems.size(), hipMemcpyHostToDevice));
   std::vector<ZeroRegion> z = pl.zeros;
   z.push_back(ZeroRegion{pl.d_queue, 1});
+  if (!pl.segs.empty())
+    z.push_back(ZeroRegion{pl.d_counts, 2 * (int64_t)pl.segs.size()});
   BHIP(hipMemcpy(pl.d_jobs, pl.jobs.data(), sizeof(BatchJob) * pl.jobs.size(),
                  hipMemcpyHostToDevice));
   if (!items.empty())
@@ -300,13 +604,23 @@ static compass_status upload_plan(compass_batch_plan_s &pl,
 }
 
 static void enqueue(const compass_batch_plan_s &pl, hipStream_t st) {
-  const int nz = (int)pl.zeros.size() + 1;
+  const int nz = (int)pl.zeros.size() + 1 + (pl.segs.empty() ? 0 : 1);
   hipLaunchKernelGGL(zero_regions_kernel, dim3(16, std::min(nz, 65535)),
                      dim3(256), 0, st, pl.d_zeros, nz);
   if (pl.n_items > 0)
     hipLaunchKernelGGL(batch_scan_kernel, dim3(pl.grid), dim3(kBuildThreads),
                        pl.lds, st, pl.d_jobs, pl.d_items, pl.n_items,
                        pl.d_queue, pl.d_seeds);
+  for (const auto &r : pl.rounds) {
+    if (r.c1 > r.c0)
+      hipLaunchKernelGGL(batch_compact_kernel, dim3((unsigned)(r.c1 - r.c0)),
+                         dim3(kBuildThreads), 0, st, pl.d_jobs, pl.d_segs,
+                         pl.d_citems + r.c0);
+    if (r.h1 > r.h0)
+      hipLaunchKernelGGL(batch_hash_kernel, dim3((unsigned)(r.h1 - r.h0)),
+                         dim3(kBuildThreads), pl.hash_lds, st, pl.d_jobs,
+                         pl.d_segs, pl.d_hitems + r.h0, pl.d_seeds);
+  }
 }
 
 static std::string cache_path() {
@@ -435,6 +749,7 @@ extern "C" compass_status compass_batch_plan_create(
   pl->counter_bits = counter_bits;
   auto cleanup = [&](compass_status s) {
     if (pl->dmem) (void)hipFree(pl->dmem);
+    if (pl->arena) (void)hipFree(pl->arena);
     delete pl;
     return s;
   };
@@ -523,6 +838,7 @@ extern "C" compass_status compass_batch_plan_create(
     *out = pl;
     return COMPASS_OK;
   }
+  plan_two_phase(*pl);
   compass_tune t{};
   if (tune) t = *tune;
   const std::string key = shape_key(*pl, prop.gcnArchName);
@@ -587,6 +903,7 @@ extern "C" compass_status compass_batch_plan_destroy(compass_batch_plan pl) {
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   if (pl->dmem) (void)hipFree(pl->dmem);
+  if (pl->arena) (void)hipFree(pl->arena);
   delete pl;
   return COMPASS_OK;
 }
