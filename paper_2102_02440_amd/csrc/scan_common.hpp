@@ -236,15 +236,22 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
       for (int k = 0; k < kRowsPerThread; ++k)
         wide_key = wide_key || (valid[k] && (x[k] >> 32) != 0);
       if (!__any(wide_key)) {
-        // branch-free hashes (the four chains interleave), then the adds
+        // branch-free hashes (the lane's chains interleave), then the adds;
+        // a lane without a row adds 0, so no hash sits under a branch
         int32_t sign[kRowsPerThread];
         uint32_t b[kRowsPerThread];
+        if (bm.pow2) {
+#pragma unroll
+          for (int k = 0; k < kRowsPerThread; ++k)
+            hash_xi_h_pow2<true>(x[k], sd, bm.mask, sign[k], b[k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < kRowsPerThread; ++k)
+            hash_xi_h<true>(x[k], sd, bm, sign[k], b[k]);
+        }
 #pragma unroll
         for (int k = 0; k < kRowsPerThread; ++k)
-          hash_xi_h<true>(x[k], sd, bm, sign[k], b[k]);
-#pragma unroll
-        for (int k = 0; k < kRowsPerThread; ++k)
-          if (valid[k]) atomicAdd(&c[b[k]], sign[k]);
+          atomicAdd(&c[b[k]], valid[k] ? sign[k] : 0);
       } else {
 #pragma unroll
         for (int k = 0; k < kRowsPerThread; ++k) {
