@@ -38,22 +38,44 @@ __device__ __forceinline__ uint64_t canon61(uint64_t r) {
 //   acc * x = t1 * 2^32 + lo32(t0)
 //   t1 * 2^32 = (t1 >> 29) * 2^61 + (t1 mod 2^29) * 2^32,  2^61 == 1 (mod p)
 // so acc * x + c == (t1 mod 2^29) * 2^32 + lo32(t0) + (t1 >> 29) + c, a sum
-// below 2^61 + 2^35 + 2^61.  Two v_mad_u64_u32 (the second takes hi32(t0)
-// as its addend), one AND, one 64-bit shift and two 64-bit adds.
-__device__ __forceinline__ uint64_t madd61_x32(uint64_t acc, uint32_t x,
-                                               uint64_t c) {
+// below 2^61 + 2^35 + 2^61.
+__device__ __forceinline__ uint64_t madd61_x32_any(uint64_t acc, uint32_t x,
+                                                   uint64_t c) {
   const uint64_t t0 = (uint64_t)(uint32_t)acc * x;
   const uint64_t t1 = (uint64_t)(uint32_t)(acc >> 32) * x + (t0 >> 32);
   const uint64_t low = ((t1 & 0x1FFFFFFFull) << 32) | (uint32_t)t0;
   return low + (t1 >> 29) + c;
 }
 
+// The Horner step of the hashes: acc < 2^62, x < 2^32, c < 2^61; returns a
+// value below 2^61 + 2^34 (< 2^62, so steps chain) congruent to
+// acc * x + c (mod p).  With l = lo32(acc), h = hi32(acc):
+//   u = l * x + lo32(c)                      (< 2^64)
+//   v = h * x + hi32(c) + hi32(u)            (< 2^63)
+//   acc * x + c = v * 2^32 + lo32(u)
+//   v * 2^32 == (v >> 29) + (v mod 2^29) * 2^32  (mod p)
+// The two products take c's halves as their addends (scalar pairs), the
+// low word of the result is lo32(u) and its high word (v mod 2^29), so the
+// step is two v_mad_u64_u32, one 32-bit add with carry, one AND, one 64-bit
+// shift and one 64-bit add.
+__device__ __forceinline__ uint64_t madd61_x32(uint64_t acc, uint32_t x,
+                                               uint64_t c) {
+  const uint64_t u = (uint64_t)(uint32_t)acc * x + (uint32_t)c;
+  const uint64_t v =
+      (uint64_t)(uint32_t)(acc >> 32) * x + (c >> 32) + (u >> 32);
+  uint64_t r0 = ((uint64_t)((uint32_t)v & 0x1FFFFFFFu) << 32) | (uint32_t)u;
+  // a register pair as it stands (the AND writes its high word): keeps the
+  // compiler from re-associating it into two 64-bit adds of zero-padded pairs
+  __asm__("" : "+v"(r0));
+  return r0 + (v >> 29);
+}
+
 // acc < 2^63, x < 2^61, c < 2^61: value < 2^63 congruent to acc * x + c.
 //   acc * x = acc * lo32(x) + (acc * hi32(x)) * 2^32
 __device__ __forceinline__ uint64_t madd61_x61(uint64_t acc, uint64_t x,
                                                uint64_t c) {
-  const uint64_t r1 = madd61_x32(acc, (uint32_t)x, c);
-  const uint64_t t = madd61_x32(acc, (uint32_t)(x >> 32), 0);
+  const uint64_t r1 = madd61_x32_any(acc, (uint32_t)x, c);
+  const uint64_t t = madd61_x32_any(acc, (uint32_t)(x >> 32), 0);
   // t * 2^32 == (t >> 29) + (t mod 2^29) * 2^32  (mod p)
   return fold61(r1) + (t >> 29) + ((t & 0x1FFFFFFFull) << 32);
 }
