@@ -142,6 +142,30 @@ __device__ __forceinline__ void hash_xi_h(uint64_t x, const RowSeeds &s,
   bucket = m.pow2 ? (low_of_residue(g) & m.mask) : bucket_of(canon61(g), m);
 }
 
+// Sign and power-of-two bucket of R keys (each below 2^32) under one row's
+// seeds, step by step across the keys so that the R independent Horner
+// chains interleave.
+template <int R>
+__device__ __forceinline__ void hash_many_pow2(const uint64_t (&x)[R],
+                                               const RowSeeds &s, uint32_t mask,
+                                               int32_t (&sign)[R],
+                                               uint32_t (&bucket)[R]) {
+  uint64_t v[R], g[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = madd61_x32(s.a3, (uint32_t)x[k], s.a2);
+#pragma unroll
+  for (int k = 0; k < R; ++k) g[k] = madd61_x32(s.b1, (uint32_t)x[k], s.b0);
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = madd61_x32(v[k], (uint32_t)x[k], s.a1);
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = madd61_x32(v[k], (uint32_t)x[k], s.a0);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    sign[k] = 1 - 2 * (int32_t)(low_of_residue(v[k]) & 1u);
+    bucket[k] = low_of_residue(g[k]) & mask;
+  }
+}
+
 // The same for a power-of-two w known at the call site: straight-line code,
 // so that several keys' chains interleave.
 template <bool X32>

@@ -241,9 +241,7 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
         int32_t sign[kRowsPerThread];
         uint32_t b[kRowsPerThread];
         if (bm.pow2) {
-#pragma unroll
-          for (int k = 0; k < kRowsPerThread; ++k)
-            hash_xi_h_pow2<true>(x[k], sd, bm.mask, sign[k], b[k]);
+          hash_many_pow2<kRowsPerThread>(x, sd, bm.mask, sign, b);
         } else {
 #pragma unroll
           for (int k = 0; k < kRowsPerThread; ++k)
