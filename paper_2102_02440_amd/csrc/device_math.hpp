@@ -161,7 +161,11 @@ __device__ __forceinline__ void hash_many_pow2(const uint64_t (&x)[R],
   for (int k = 0; k < R; ++k) v[k] = madd61_x32(v[k], (uint32_t)x[k], s.a0);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    sign[k] = 1 - 2 * (int32_t)(low_of_residue(v[k]) & 1u);
+    // +1 or -1 from the parity: bit 0 sign-extended (0 or -1), doubled, | 1
+    // (opaque in between, so that it stays two instructions)
+    int32_t par = __builtin_amdgcn_sbfe((int32_t)low_of_residue(v[k]), 0, 1);
+    __asm__("" : "+v"(par));
+    sign[k] = (int32_t)((uint32_t)par << 1) | 1;
     bucket[k] = low_of_residue(g[k]) & mask;
   }
 }

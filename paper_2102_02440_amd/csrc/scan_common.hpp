@@ -183,6 +183,8 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
     }
     uint64_t x[kRowsPerThread];
     int cur_sketch = -1;
+    int x_wide = -1;  // wave-uniform: -1 = not yet decided for these keys
+    const bool full_tile = qn == kTile;  // every lane has all its rows
     if (dense) {
       if (!have_pre) load_fields<kRowsPerThread>(kd_first, base, ridx, x);
       if (have_pre) {
@@ -225,17 +227,21 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
         // rows of invalid entries are row `base` (in the table); their
         // values are never used
         load_fields<kRowsPerThread>(job.key(s), base, ridx, x);
+        x_wide = -1;
       }
       const RowSeeds sd = job.seeds(sl);
       const BucketMod bm = job.bm();
       int32_t *c = cnt + (size_t)(sl - sb) * w;
       // one uniform branch when no key of the wave needs the 61-bit path
-      // (every non-negative int32 key)
-      bool wide_key = false;
+      // (every non-negative int32 key); decided once per key load
+      if (x_wide < 0) {
+        bool wide_key = false;
 #pragma unroll
-      for (int k = 0; k < kRowsPerThread; ++k)
-        wide_key = wide_key || (valid[k] && (x[k] >> 32) != 0);
-      if (!__any(wide_key)) {
+        for (int k = 0; k < kRowsPerThread; ++k)
+          wide_key = wide_key || (valid[k] && (x[k] >> 32) != 0);
+        x_wide = __any(wide_key) ? 1 : 0;
+      }
+      if (!x_wide) {
         // branch-free hashes (the lane's chains interleave), then the adds;
         // a lane without a row adds 0, so no hash sits under a branch
         int32_t sign[kRowsPerThread];
@@ -247,9 +253,14 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
           for (int k = 0; k < kRowsPerThread; ++k)
             hash_xi_h<true>(x[k], sd, bm, sign[k], b[k]);
         }
+        if (full_tile) {
 #pragma unroll
-        for (int k = 0; k < kRowsPerThread; ++k)
-          atomicAdd(&c[b[k]], valid[k] ? sign[k] : 0);
+          for (int k = 0; k < kRowsPerThread; ++k) atomicAdd(&c[b[k]], sign[k]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < kRowsPerThread; ++k)
+            atomicAdd(&c[b[k]], valid[k] ? sign[k] : 0);
+        }
       } else {
 #pragma unroll
         for (int k = 0; k < kRowsPerThread; ++k) {
