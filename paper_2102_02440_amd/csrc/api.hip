@@ -44,8 +44,11 @@ hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
                               hipStream_t st);
 hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
                             const EstBuffers &B, hipStream_t st);
+hipError_t launch_node_merge(const NodeTask *tasks, int n, int max_L,
+                             const EstBuffers &B, int stage_bytes,
+                             hipStream_t st);
 hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
-                       int stage_bytes, hipStream_t st);
+                       hipStream_t st);
 hipError_t launch_node1(const NodeTask *tasks, int n, const EstBuffers &B,
                         hipStream_t st);
 hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
@@ -1074,7 +1077,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
     int stage = 0;
     if (g->counter_bits == 32) {
       for (const NodeTask &t : levels[lv]) {
-        if (t.m == 0) continue;
+        if (t.m < 2) continue;  // only multi-child nodes are merged
         const int nl = t.m + (t.parent_side >= 0) + (t.cut_side >= 0);
         const int need = nl * w * 4;
         if (need <= kNodeStageBytes) stage = std::max(stage, need);
@@ -1083,15 +1086,22 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
     ProfScope ps("node", stream);
     for (size_t g0 = 0; g0 < levels[lv].size(); g0 += group_tasks) {
       const size_t ng = std::min(group_tasks, levels[lv].size() - g0);
-      bool any_multi = false, any_one = false;
-      int apex_L = 0;
+      bool any_one = false, any_node = false;
+      int apex_L = 0, merge_L = 0;
       for (size_t k = g0; k < g0 + ng; ++k) {
         const NodeTask &t = levels[lv][k];
-        if (t.m == 1) any_one = true; else any_multi = true;
+        const int nl = t.m + (t.parent_side >= 0) + (t.cut_side >= 0);
+        if (t.m == 1) any_one = true;
+        if (t.m >= 2) merge_L = std::max(merge_L, nl * w);
+        if ((t.m == 0 && t.mode == kModeMessage) ||
+            (t.m >= 2 && t.mode != kModeTriRootPrep))
+          any_node = true;
         if (t.mode == kModeTriRootPrep) apex_L = std::max(apex_L, t.m * w);
       }
       const NodeTask *dt = dtasks + level_off[lv] + g0;
-      if (any_multi) HIP_OK(launch_node(dt, (int)ng, B, stage, stream));
+      if (merge_L > 0)
+        HIP_OK(launch_node_merge(dt, (int)ng, merge_L, B, stage, stream));
+      if (any_node) HIP_OK(launch_node(dt, (int)ng, B, stream));
       if (any_one) HIP_OK(launch_node1(dt, (int)ng, B, stream));
       if (apex_L > 0) HIP_OK(launch_apex_prep(dt, (int)ng, apex_L, B, stream));
     }

@@ -22,10 +22,12 @@
 //  sort_chunk_kernel / sort_merge_kernel
 //                      the w buckets of each (sketch, row) sorted by
 //                      (|v|, j): chunks sorted in LDS, merged by rank.
-//  node_kernel         one workgroup per (tree node, row): k-way merge of
-//                      the node's sorted lists by rank (binary search), then
-//                      block-wide scans of 128-bit A and G, emitting the
-//                      node's message (or the root's X).
+//  node_merge_kernel   k-way merge of a node's sorted lists by rank (binary
+//                      search), many workgroups per (tree node, row);
+//  node_kernel         one workgroup per (tree node, row): block-wide scans
+//                      of 128-bit A and G over the merged records, emitting
+//                      the node's message (or the root's X);
+//  node1_*             nodes with one child (prefix sums + binary search);
 //  tri_lane_kernel     triangles: one lane per bucket J of the cut edge.
 //                      Fixing J turns each cut endpoint's message into
 //                      "M(j) if its parent-edge element ranks below the
@@ -238,6 +240,136 @@ __device__ __forceinline__ ListRef list_of(const NodeTask *T, int a) {
   return r;
 }
 
+// ---------------------------------------------------------------------
+// merge of a node's lists (nodes with two or more children): grid
+// (tasks, d, chunks of kMergeChunk elements), kMergeThreads lanes
+// ---------------------------------------------------------------------
+// k-way merge by rank: the position of an element is its index in its own
+// list plus the number of elements of smaller kappa in every other list
+// (ties in |v| go to the lower edge id), so every element is placed on its
+// own and a node's merge spreads over many workgroups.  With int32
+// counters every |v| < 2^32: the lists' sorted magnitudes are staged in LDS
+// as 32-bit values and the rank searches run there.  Each element's record
+// (list, bucket, counter, child message) is gathered here once.
+__global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
+    const NodeTask *tasks, EstBuffers B, int32_t stage_bytes) {
+  const NodeTask *Tg = tasks + blockIdx.x;
+  const NodeTask T = *Tg;
+  if (T.m < 2 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // uniform
+  const int row = blockIdx.y;
+  const int w = B.w;
+  const int m = T.m;
+  const int nl = m + (T.parent_side >= 0) + (T.cut_side >= 0);
+  const int L = nl * w;
+  const int e_lo = blockIdx.z * kMergeChunk;
+  if (e_lo >= L) return;
+  const int e_hi = min(L, e_lo + kMergeChunk);
+  uint32_t *merged =
+      B.merged + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
+  NodeRec *rec = B.nrec + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
+  extern __shared__ uint32_t mags[];  // nl * w when staged
+  __shared__ int32_t s_side[kMaxChild + 2], s_eid[kMaxChild + 2],
+      s_msg[kMaxChild + 2];
+  if ((int)threadIdx.x < nl) {
+    const ListRef lr = list_of(Tg, threadIdx.x);
+    s_side[threadIdx.x] = lr.side;
+    s_eid[threadIdx.x] = lr.eid;
+    s_msg[threadIdx.x] = (int)threadIdx.x < m ? Tg->child_msg[threadIdx.x] : -1;
+  }
+  __syncthreads();
+  const bool staged = B.counter_bits == 32 &&
+                      (size_t)nl * w * 4 <= (size_t)stage_bytes;
+  if (staged) {
+    for (int e = threadIdx.x; e < L; e += kMergeThreads) {
+      const int a = e / w;
+      const int k = e - a * w;
+      mags[e] = (uint32_t)(sorted_of(B, s_side[a], row)[k] >> 16);
+    }
+    __syncthreads();
+    // kMergeU elements per lane at a time: their rank searches run in
+    // lockstep (uniform trip count), so the LDS probes overlap
+    constexpr int kMergeU = kMergeChunk / kMergeThreads;
+    {
+      const int e0 = e_lo + (int)threadIdx.x;
+      int a[kMergeU], pos[kMergeU];
+      uint32_t j[kMergeU];
+      uint64_t absv[kMergeU];
+      bool ok[kMergeU];
+#pragma unroll
+      for (int u = 0; u < kMergeU; ++u) {
+        const int e = e0 + u * kMergeThreads;
+        ok[u] = e < e_hi;
+        const int ee = ok[u] ? e : e_lo;
+        a[u] = ee / w;
+        const int k = ee - a[u] * w;
+        const uint64_t key = sorted_of(B, s_side[a[u]], row)[k];
+        absv[u] = key >> 16;
+        j[u] = (uint32_t)(key & 0xFFFF);
+        pos[u] = k;
+      }
+      for (int b = 0; b < nl; ++b) {
+        const uint32_t *mb = mags + (size_t)b * w;
+        const int eb = s_eid[b];
+        uint64_t t[kMergeU];
+        int base[kMergeU];
+#pragma unroll
+        for (int u = 0; u < kMergeU; ++u) {
+          t[u] = absv[u] + (eb < s_eid[a[u]] ? 1 : 0);  // count |v_b| < t
+          base[u] = 0;
+        }
+        int n = w;
+        while (n > 1) {
+          const int half = n >> 1;
+#pragma unroll
+          for (int u = 0; u < kMergeU; ++u)
+            base[u] = (uint64_t)mb[base[u] + half] < t[u] ? base[u] + half : base[u];
+          n -= half;
+        }
+#pragma unroll
+        for (int u = 0; u < kMergeU; ++u) {
+          const int r = base[u] + ((uint64_t)mb[base[u]] < t[u] ? 1 : 0);
+          if (b != a[u]) pos[u] += r;
+        }
+      }
+      NodeRec r[kMergeU];
+#pragma unroll
+      for (int u = 0; u < kMergeU; ++u) {
+        r[u].v = counter_at(B, s_side[a[u]], row, (int)j[u]);
+        r[u].mu = a[u] < m ? msg_of(B, s_msg[a[u]], row)[j[u]] : (u128)0;
+        r[u].aj = ((uint32_t)a[u] << 16) | j[u];
+        r[u].pad = 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kMergeU; ++u) {
+        if (!ok[u]) continue;
+        merged[pos[u]] = r[u].aj;
+        rec[pos[u]] = r[u];
+      }
+    }
+  } else {
+    for (int e = e_lo + (int)threadIdx.x; e < e_hi; e += kMergeThreads) {
+      const int a = e / w;
+      const int k = e - a * w;
+      const uint64_t key = sorted_of(B, s_side[a], row)[k];
+      const uint64_t absv = key >> 16;
+      const uint32_t j = (uint32_t)(key & 0xFFFF);
+      int pos = k;
+      for (int b = 0; b < nl; ++b) {
+        if (b == a) continue;
+        const uint64_t t = absv + (s_eid[b] < s_eid[a] ? 1 : 0);  // count |v_b| < t
+        pos += lower_bound_u64(sorted_of(B, s_side[b], row), w, t << 16);
+      }
+      NodeRec r;
+      r.v = counter_at(B, s_side[a], row, (int)j);
+      r.mu = a < m ? msg_of(B, s_msg[a], row)[j] : (u128)0;
+      r.aj = ((uint32_t)a << 16) | j;
+      r.pad = 0;
+      merged[pos] = r.aj;
+      rec[pos] = r;
+    }
+  }
+}
+
 // product of the A of every child but `a` (a >= M: of every child)
 template <int M>
 __device__ __forceinline__ u128 times_others(u128 t, const u128 *A, int a) {
@@ -345,7 +477,7 @@ __device__ void node_sweeps(const NodeTask &T, const NodeRec *rec, int L,
 }
 
 __global__ __launch_bounds__(kNodeThreads) void node_kernel(
-    const NodeTask *tasks, EstBuffers B, int32_t stage_bytes) {
+    const NodeTask *tasks, EstBuffers B) {
   __shared__ u128 sh[kNodeThreads];
   const NodeTask *Tg = tasks + blockIdx.x;
   const NodeTask T = *Tg;
@@ -370,116 +502,8 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
   }
 
   const int L = nl * w;
-  uint32_t *merged =
-      B.merged + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
   NodeRec *rec = B.nrec + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
-
-  // 1. k-way merge by rank: position = own index + elements of smaller
-  //    kappa in every other list (ties in |v| go to the lower edge id).
-  //    With int32 counters every |v| < 2^32: the lists' sorted magnitudes
-  //    are staged in LDS as 32-bit values and the rank searches run there.
-  extern __shared__ uint32_t mags[];  // nl * w when staged
-  __shared__ int32_t s_side[kMaxChild + 2], s_eid[kMaxChild + 2],
-      s_msg[kMaxChild + 2];
-  if ((int)threadIdx.x < nl) {
-    const ListRef lr = list_of(Tg, threadIdx.x);
-    s_side[threadIdx.x] = lr.side;
-    s_eid[threadIdx.x] = lr.eid;
-    s_msg[threadIdx.x] = (int)threadIdx.x < m ? Tg->child_msg[threadIdx.x] : -1;
-  }
-  __syncthreads();
-  const bool staged = B.counter_bits == 32 &&
-                      (size_t)nl * w * 4 <= (size_t)stage_bytes;
-  if (staged) {
-    for (int e = threadIdx.x; e < L; e += kNodeThreads) {
-      const int a = e / w;
-      const int k = e - a * w;
-      mags[e] = (uint32_t)(sorted_of(B, s_side[a], row)[k] >> 16);
-    }
-    __syncthreads();
-    // kMergeU elements per lane at a time: their rank searches run in
-    // lockstep (uniform trip count), so the LDS probes overlap
-    constexpr int kMergeU = 4;
-    for (int e0 = threadIdx.x; e0 < L; e0 += kNodeThreads * kMergeU) {
-      int a[kMergeU], pos[kMergeU];
-      uint32_t j[kMergeU];
-      uint64_t absv[kMergeU];
-      bool ok[kMergeU];
-#pragma unroll
-      for (int u = 0; u < kMergeU; ++u) {
-        const int e = e0 + u * kNodeThreads;
-        ok[u] = e < L;
-        const int ee = ok[u] ? e : 0;
-        a[u] = ee / w;
-        const int k = ee - a[u] * w;
-        const uint64_t key = sorted_of(B, s_side[a[u]], row)[k];
-        absv[u] = key >> 16;
-        j[u] = (uint32_t)(key & 0xFFFF);
-        pos[u] = k;
-      }
-      for (int b = 0; b < nl; ++b) {
-        const uint32_t *mb = mags + (size_t)b * w;
-        const int eb = s_eid[b];
-        uint64_t t[kMergeU];
-        int base[kMergeU];
-#pragma unroll
-        for (int u = 0; u < kMergeU; ++u) {
-          t[u] = absv[u] + (eb < s_eid[a[u]] ? 1 : 0);  // count |v_b| < t
-          base[u] = 0;
-        }
-        int n = w;
-        while (n > 1) {
-          const int half = n >> 1;
-#pragma unroll
-          for (int u = 0; u < kMergeU; ++u)
-            base[u] = (uint64_t)mb[base[u] + half] < t[u] ? base[u] + half : base[u];
-          n -= half;
-        }
-#pragma unroll
-        for (int u = 0; u < kMergeU; ++u) {
-          const int r = base[u] + ((uint64_t)mb[base[u]] < t[u] ? 1 : 0);
-          if (b != a[u]) pos[u] += r;
-        }
-      }
-      NodeRec r[kMergeU];
-#pragma unroll
-      for (int u = 0; u < kMergeU; ++u) {
-        r[u].v = counter_at(B, s_side[a[u]], row, (int)j[u]);
-        r[u].mu = a[u] < m ? msg_of(B, s_msg[a[u]], row)[j[u]] : (u128)0;
-        r[u].aj = ((uint32_t)a[u] << 16) | j[u];
-        r[u].pad = 0;
-      }
-#pragma unroll
-      for (int u = 0; u < kMergeU; ++u) {
-        if (!ok[u]) continue;
-        merged[pos[u]] = r[u].aj;
-        rec[pos[u]] = r[u];
-      }
-    }
-  } else {
-    for (int e = threadIdx.x; e < L; e += kNodeThreads) {
-      const int a = e / w;
-      const int k = e - a * w;
-      const uint64_t key = sorted_of(B, s_side[a], row)[k];
-      const uint64_t absv = key >> 16;
-      const uint32_t j = (uint32_t)(key & 0xFFFF);
-      int pos = k;
-      for (int b = 0; b < nl; ++b) {
-        if (b == a) continue;
-        const uint64_t t = absv + (s_eid[b] < s_eid[a] ? 1 : 0);  // count |v_b| < t
-        pos += lower_bound_u64(sorted_of(B, s_side[b], row), w, t << 16);
-      }
-      NodeRec r;
-      r.v = counter_at(B, s_side[a], row, (int)j);
-      r.mu = a < m ? msg_of(B, s_msg[a], row)[j] : (u128)0;
-      r.aj = ((uint32_t)a << 16) | j;
-      r.pad = 0;
-      merged[pos] = r.aj;
-      rec[pos] = r;
-    }
-  }
-  __syncthreads();
-
+  // the merged records come from node_merge_kernel
   if (T.mode == kModeTriRootPrep) return;  // apex_prep_kernel
 
   switch (m) {
@@ -1524,10 +1548,20 @@ hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
   return hipGetLastError();
 }
 
+hipError_t launch_node_merge(const NodeTask *tasks, int n, int max_L,
+                             const EstBuffers &B, int stage_bytes,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(node_merge_kernel,
+                     dim3(n, B.d, (max_L + kMergeChunk - 1) / kMergeChunk),
+                     dim3(kMergeThreads), (size_t)stage_bytes, st, tasks, B,
+                     stage_bytes);
+  return hipGetLastError();
+}
+
 hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
-                       int stage_bytes, hipStream_t st) {
-  hipLaunchKernelGGL(node_kernel, dim3(n, B.d), dim3(kNodeThreads),
-                     (size_t)stage_bytes, st, tasks, B, stage_bytes);
+                       hipStream_t st) {
+  hipLaunchKernelGGL(node_kernel, dim3(n, B.d), dim3(kNodeThreads), 0, st,
+                     tasks, B);
   return hipGetLastError();
 }
 
