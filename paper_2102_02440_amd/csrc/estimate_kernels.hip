@@ -707,8 +707,8 @@ __global__ __launch_bounds__(kN1Threads) void node1_emit_kernel(
 // child, counter, message, and the kappa of the child's own bucket), the
 // length of the zero-counter prefix and, for two-child apexes, each
 // element's same-child run [run_lo, run_hi].
-__device__ __forceinline__ int rec_child(const NodeRec *rec, int p) {
-  return (int)(rec[p].aj >> 16);
+__device__ __forceinline__ int rec_child(const uint32_t *merged, int p) {
+  return (int)(merged[p] >> 16);
 }
 
 __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
@@ -725,6 +725,8 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
   const int p1 = min(L, p0 + kPrepChunk);
   const NodeRec *rec =
       B.nrec + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
+  const uint32_t *mg =
+      B.merged + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
   const size_t slot_row = (size_t)T.out_slot * B.d + row;
   TriElem *out = B.prep + slot_row * (size_t)B.Lprep;
   TriElemN *outn = B.prepn + slot_row * (size_t)B.Lprep;
@@ -760,8 +762,8 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
       n.run_lo = 0;  // set below
       n.run_hi = 0;
       outn[pos] = n;
-      if (pos == 0 || rec_child(rec, pos - 1) != a) last_start = pos;
-      if (first_end == L && (pos == L - 1 || rec_child(rec, pos + 1) != a))
+      if (pos == 0 || rec_child(mg, pos - 1) != a) last_start = pos;
+      if (first_end == L && (pos == L - 1 || rec_child(mg, pos + 1) != a))
         first_end = pos;
     }
     // the list is ascending in |v|: its zero counters form a prefix, and
@@ -794,7 +796,7 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
   // (searched kPrepThreads positions at a time; both loops are uniform)
   for (int base = p0 - 1; base >= 0; base -= kPrepThreads) {
     const int q = base - (int)threadIdx.x;
-    if (q >= 0 && (q == 0 || rec_child(rec, q - 1) != rec_child(rec, q)))
+    if (q >= 0 && (q == 0 || rec_child(mg, q - 1) != rec_child(mg, q)))
       atomicMax(&s_prev, q);
     __syncthreads();
     const bool found = s_prev >= 0;
@@ -803,7 +805,7 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
   }
   for (int base = p1; base < L; base += kPrepThreads) {
     const int q = base + (int)threadIdx.x;
-    if (q < L && (q == L - 1 || rec_child(rec, q + 1) != rec_child(rec, q)))
+    if (q < L && (q == L - 1 || rec_child(mg, q + 1) != rec_child(mg, q)))
       atomicMin(&s_next, q);
     __syncthreads();
     const bool found = s_next < L;
@@ -818,7 +820,7 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
 #pragma unroll
   for (int u = 0; u < kPrepPer; ++u) {
     const int pos = q0 + u;
-    if (pos < p1 && (pos == 0 || rec_child(rec, pos - 1) != rec_child(rec, pos)))
+    if (pos < p1 && (pos == 0 || rec_child(mg, pos - 1) != rec_child(mg, pos)))
       cur = pos;
     lo_of[u] = cur;
   }
@@ -826,7 +828,7 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
   for (int u = kPrepPer - 1; u >= 0; --u) {
     const int pos = q0 + u;
     if (pos >= p1) continue;
-    if (pos == L - 1 || rec_child(rec, pos + 1) != rec_child(rec, pos)) nxt = pos;
+    if (pos == L - 1 || rec_child(mg, pos + 1) != rec_child(mg, pos)) nxt = pos;
     outn[pos].run_lo = lo_of[u];
     outn[pos].run_hi = nxt;
   }
