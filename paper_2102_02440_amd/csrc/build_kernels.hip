@@ -108,6 +108,11 @@ struct DirectJob {
 // gathers the keys of every (sketch, survivor) pair, four loads in flight
 // per thread.
 constexpr int kWideQueue = 16384;
+// longer tiles than the fused scan's default: more predicate loads in
+// flight per tile for this streaming pass
+constexpr int kWideRows = 8;
+constexpr int kWideTile = kBuildThreads * kWideRows;
+static_assert(kWideQueue >= 2 * kWideTile, "a tile fits after a partial queue");
 
 __global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
     const BuildParams P, uint64_t *__restrict__ surv, int64_t cap,
@@ -119,21 +124,21 @@ __global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
   const DirectJob job{P};
   uint64_t sel = 0;
   int qtot = 0;  // block-uniform
-  const int64_t stride = (int64_t)gridDim.x * kBuildTile;
-  for (int64_t base = row_begin + (int64_t)blockIdx.x * kBuildTile;
+  const int64_t stride = (int64_t)gridDim.x * kWideTile;
+  for (int64_t base = row_begin + (int64_t)blockIdx.x * kWideTile;
        base < row_end; base += stride) {
-    const int nt = (int)min((int64_t)kBuildTile, row_end - base);
+    const int nt = (int)min((int64_t)kWideTile, row_end - base);
     const int bias = (int)(base - row_begin);
     if (P.n_preds == 0) {
       for (int r = threadIdx.x; r < nt; r += kBuildThreads)
         queue[qtot + r] = bias + r;
       qtot += nt;
     } else {
-      qtot = compact_tile<DirectJob, kBuildRowsPerThread>(
+      qtot = compact_tile<DirectJob, kWideRows>(
           job, base, nt, P.n_preds, queue, &s_qn, qtot, bias);
     }
     const bool last = base + stride >= row_end;
-    if (qtot > kWideQueue - kBuildTile || (last && qtot > 0)) {
+    if (qtot > kWideQueue - kWideTile || (last && qtot > 0)) {
       __syncthreads();  // queue complete
       if (threadIdx.x == 0) s_off = atomicAdd(count, (unsigned long long)qtot);
       __syncthreads();
