@@ -428,7 +428,13 @@ struct compass_batch_plan_s {
 // row surviving) fit the arena; segments are packed into rounds that share
 // the arena and run one after another.
 static void plan_two_phase(compass_batch_plan_s &pl) {
-  constexpr size_t kArenaMax = (size_t)8 << 30;
+  // arena bytes: 8 GiB, or COMPASS_BATCH_ARENA_BYTES (at least one tile of
+  // every job's keys; smaller arenas give more rounds and segments)
+  size_t kArenaMax = (size_t)8 << 30;
+  if (const char *e = getenv("COMPASS_BATCH_ARENA_BYTES")) {
+    const long long v = atoll(e);
+    if (v > 0) kArenaMax = (size_t)v;
+  }
   constexpr int64_t kCompactRows = 64 * kBuildTile;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   pl.segs.clear();

@@ -62,6 +62,36 @@ def test_batch_equals_per_table(oracle, tune, tmp_path, monkeypatch):
 
 
 @gpu
+def test_batch_two_phase_rounds(oracle, tmp_path, monkeypatch):
+    """Jobs with predicates cut into many segments and rounds (a 1 MiB
+    survivor arena instead of 8 GiB): still bit-exact against one build
+    call per table, on repeated graph replays."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    monkeypatch.setenv("COMPASS_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    monkeypatch.setenv("COMPASS_BATCH_ARENA_BYTES", str(1 << 20))
+    pool = W.schema_pool(seed=5, n_tables=10, scale=0.004)
+    qs = W.query_batch(pool, seed=6, n_queries=16, w_choices=(512, 1000, 2048))
+    print("[case] batch rounds jobs", sum(len(q.tables) for q in qs), flush=True)
+    db = C.DeviceBatch(pool, qs)
+    db.build_per_table()
+    torch.cuda.synchronize()
+    ref_sides, ref_n = snapshot(db)
+    for sides in db.sides:
+        for s in sides:
+            s.fill_(-7)
+    plan = db.plan(tune=(65536, 65536, 1))
+    for rep in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        for qi in range(len(qs)):
+            assert torch.equal(db.n_selected[qi], ref_n[qi]), (rep, qi)
+            for a, b in zip(db.sides[qi], ref_sides[qi]):
+                assert torch.equal(a, b), (rep, qi)
+    plan.close()
+
+
+@gpu
 def test_batch_estimates_match_oracle(oracle):
     """Estimates over batch-built sketches (trees and triangles) vs oracle."""
     torch = _torch()
