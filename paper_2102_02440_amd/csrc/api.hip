@@ -26,6 +26,7 @@
 namespace compass {
 // kernels (build_kernels.hip, estimate_kernels.hip)
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t st);
+hipError_t launch_fill_zero_list(const ZeroSpans &z, hipStream_t st);
 hipError_t launch_scan_sketch(const BuildParams &P, int n_blocks,
                               size_t lds_bytes, hipStream_t st);
 hipError_t launch_wide_compact(const BuildParams &P, uint64_t *surv,
@@ -345,18 +346,27 @@ static compass_status sketch_build_impl(
   // time.  Tables without predicates take the fused scan.
   const bool wide = (size_t)w * 4 > kLdsBudget;
   const bool two_phase = wide || n_preds > 0;
+  // what an overwriting call clears first, in one launch: the selected
+  // count and the selection output's count, and the counters unless the
+  // fused scan's reduction overwrites them (the two-phase build adds into
+  // them; an empty table launches nothing else).  The two-phase build adds
+  // its first survivor count to the same launch.
+  ZeroSpans zs;
+  memset(&zs, 0, sizeof zs);
   if (!accumulate) {
-    ProfScope ps("fill_zero", stream);
-    // the fused scan's reduction overwrites the counters itself, except
-    // for an empty table, which launches nothing else
     if (two_phase || n_rows == 0)
       for (int s = 0; s < n_sketches; ++s)
-        HIP_OK(launch_fill_zero(sketches[s].counters,
-                                (int64_t)d * w * (counter_bits / 8), stream));
-    HIP_OK(launch_fill_zero(n_selected, 8, stream));
-    if (sink.out) HIP_OK(launch_fill_zero(sink.count, 8, stream));
+        zs.add(sketches[s].counters, (int64_t)d * w * (counter_bits / 8));
+    zs.add(n_selected, 8);
+    if (sink.out) zs.add(sink.count, 8);
   }
-  if (n_rows == 0) return COMPASS_OK;
+  if (n_rows == 0 || !two_phase) {
+    if (zs.n > 0) {
+      ProfScope ps("fill_zero", stream);
+      HIP_OK(launch_fill_zero_list(zs, stream));
+    }
+    if (n_rows == 0) return COMPASS_OK;
+  }
 
   if (two_phase) {
     const int S = n_sketches * d;
@@ -414,7 +424,12 @@ static compass_status sketch_build_impl(
     for (int64_t r0 = 0; r0 < n_rows; r0 += cap) {
       const int64_t r1 = std::min(n_rows, r0 + cap);
       const int64_t tiles = (r1 - r0 + kBuildTile - 1) / kBuildTile;
-      HIP_OK(launch_fill_zero(count, 8, stream));
+      {
+        ProfScope ps("fill_zero", stream);
+        if (r0 > 0) zs.n = 0;  // the call's regions were cleared with batch 0
+        zs.add(count, 8);
+        HIP_OK(launch_fill_zero_list(zs, stream));
+      }
       {
         ProfScope ps("wide_compact", stream);
         HIP_OK(launch_wide_compact(P, surv, cap, count, r0, r1,

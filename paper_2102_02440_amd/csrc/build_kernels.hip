@@ -382,6 +382,27 @@ __global__ void fill_zero_kernel(uint32_t *p, int64_t n_words) {
     p[i] = 0;
 }
 
+// several regions zeroed by one launch (grid.y walks the regions)
+__global__ void fill_zero_list_kernel(ZeroSpans z) {
+  for (int k = blockIdx.y; k < z.n; k += gridDim.y) {
+    uint32_t *p = reinterpret_cast<uint32_t *>(z.p[k]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+         i < z.words[k]; i += (int64_t)gridDim.x * blockDim.x)
+      p[i] = 0;
+  }
+}
+
+hipError_t launch_fill_zero_list(const ZeroSpans &z, hipStream_t st) {
+  if (z.n <= 0) return hipSuccess;
+  int64_t most = 1;
+  for (int k = 0; k < z.n; ++k) most = std::max(most, z.words[k]);
+  int64_t blocks = (most + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_zero_list_kernel, dim3((unsigned)blocks, (unsigned)z.n),
+                     dim3(256), 0, st, z);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t st) {
   const int64_t words = bytes / 4;
   if (words <= 0) return hipSuccess;

@@ -53,6 +53,20 @@ struct KeyDev {
 
 // One launch covers n_groups slice groups; group g owns launch-local
 // slices [group_begin[g], group_begin[g+1]).
+// regions zeroed by one launch (word counts: 4-byte words)
+constexpr int kMaxZeroSpans = kMaxSketches + 3;
+struct ZeroSpans {
+  void *p[kMaxZeroSpans];
+  int64_t words[kMaxZeroSpans];
+  int32_t n;
+  int32_t pad;
+  void add(void *q, int64_t bytes) {
+    p[n] = q;
+    words[n] = bytes / 4;
+    ++n;
+  }
+};
+
 struct BuildParams {
   int64_t n_rows;
   int64_t rows_per_chunk;
