@@ -535,8 +535,9 @@ static compass_status sketch_build_impl(
       max_group = std::max(max_group, P.group_begin[g + 1] - P.group_begin[g]);
     const size_t lds = (size_t)max_group * w * 4 + queue_bytes;
     const int64_t blocks = chunks * ng;
-    if (blocks > 0x7FFFFFFF)
+    if (blocks > 0x7FFFFFF0)
       return fail(COMPASS_E_RANGE, "too many workgroups");
+    P.n_blocks = (int32_t)blocks;
     ProfScope ps("scan_sketch", stream);
     HIP_OK(launch_scan_sketch(P, (int)blocks, lds, stream));
   }

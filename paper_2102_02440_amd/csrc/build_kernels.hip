@@ -57,8 +57,15 @@ __global__ __launch_bounds__(kBuildThreads) void scan_sketch_kernel(
 
   const ParamJob job{P};
   const int ngroups = P.n_groups;
-  const int gi = blockIdx.x % ngroups;
-  const int64_t chunk = blockIdx.x / ngroups;
+  // Workgroups are dealt to the XCDs round-robin (workgroup b to XCD
+  // b mod kXcds).  Number the (chunk, group) pairs XCD by XCD, so that the
+  // groups of one chunk run on the same XCD, one after another, and read
+  // the chunk's key columns through that XCD's L2.
+  const int per_xcd = (int)gridDim.x / kXcds;
+  const int64_t lin = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  if (lin >= (int64_t)P.n_blocks) return;  // padding of the last XCD's share
+  const int gi = (int)(lin % ngroups);
+  const int64_t chunk = lin / ngroups;
   const int sb = P.group_begin[gi];
   const int se = P.group_begin[gi + 1];
   const int ns = se - sb;
@@ -415,8 +422,10 @@ hipError_t launch_fill_zero(void *p, int64_t bytes, hipStream_t st) {
 
 hipError_t launch_scan_sketch(const BuildParams &P, int n_blocks,
                               size_t lds_bytes, hipStream_t st) {
+  // P.n_blocks pairs, padded to whole rounds of the XCDs
+  const int grid = (n_blocks + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(scan_sketch_kernel,
-                     dim3((unsigned)n_blocks), dim3(kBuildThreads), lds_bytes,
+                     dim3((unsigned)grid), dim3(kBuildThreads), lds_bytes,
                      st, P);
   return hipGetLastError();
 }

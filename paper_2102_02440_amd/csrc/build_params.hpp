@@ -7,6 +7,7 @@
 namespace compass {
 
 constexpr int kBuildThreads = 1024;
+constexpr int kXcds = 8;  // MI355X: accelerator complex dies, one L2 each
 constexpr int kBuildRowsPerThread = 4;
 constexpr int kBuildTile = kBuildThreads * kBuildRowsPerThread;
 // the one-table fused scan (tables without predicates) takes longer tiles:
@@ -78,6 +79,8 @@ struct BuildParams {
   int32_t *slab;        // [chunk][sketch * d + row][w] partial counters
   int32_t d;
   int32_t n_slices_total;  // n_sketches * d of the call (slab row count)
+  int32_t n_blocks;     // (chunk, slice group) pairs of a fused-scan launch
+  int32_t pad_nb;
   BucketMod bm;
   BucketMod bm1;        // first dimension of a partitioned sketch (w1)
   PredDev preds[kMaxPreds];
