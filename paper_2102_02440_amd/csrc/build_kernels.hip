@@ -200,6 +200,7 @@ constexpr int kWidePiece = 32767;
 constexpr int kWidePairsPerLane = 32;   // 32768 words / 1024 lanes
 constexpr int64_t kWideMinChunk = 16384;  // survivors per hashing chunk
 constexpr int kWideRange = 2 * kWidePairsPerLane * kBuildThreads;  // 65536
+constexpr int kWideKeys = 4;  // survivors per lane in flight (fast path)
 
 // Chunks of the survivors that carry work: at least kWideMinChunk
 // survivors each (a chunk's fixed cost is clearing, folding and writing w
@@ -216,12 +217,21 @@ __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
     int32_t n_slices, int32_t ranges, int32_t chunks,
     int32_t *__restrict__ slab) {
   extern __shared__ uint32_t pairs[];
-  const int sl = blockIdx.x % n_slices;
-  const int r = (blockIdx.x / n_slices) % ranges;
-  const int k = blockIdx.x / (n_slices * ranges);
   const int64_t n = (int64_t)*count;
   const int64_t act = active_chunks(n, chunks);
-  if (k >= act) return;  // uniform: no survivors for this chunk
+  // The act * n_slices * ranges items that carry work are numbered with
+  // the slice fastest and split into kXcds contiguous runs, one per XCD
+  // (workgroup b runs on XCD b mod kXcds): the d slices of one sketch read
+  // the same survivors through one L2, and the XCDs share the work evenly
+  // whatever the number of active chunks.
+  const int64_t items = act * n_slices * ranges;
+  const int xcd = (int)(blockIdx.x % kXcds);
+  const int64_t t0 = items * xcd / kXcds, t1 = items * (xcd + 1) / kXcds;
+  const int64_t t = t0 + blockIdx.x / kXcds;
+  if (t >= t1) return;  // uniform: beyond this XCD's share
+  const int sl = (int)(t % n_slices);
+  const int r = (int)((t / n_slices) % ranges);
+  const int k = (int)(t / ((int64_t)n_slices * ranges));
   const int w = (int)bm.w;
   const int wr = (w + ranges - 1) / ranges;  // <= kWideRange
   const int lo = r * wr, hi = min(w, lo + wr);
@@ -234,42 +244,85 @@ __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
   const int s = sl / d;
   const RowSeeds sd = seeds[sl];
   const uint64_t *x = surv + (int64_t)s * cap;
+  const bool fast = bm.pow2 && ranges == 1;  // uniform
   for (int64_t p0 = a; p0 < b; p0 += kWidePiece) {
     const int64_t p1 = min(b, p0 + kWidePiece);
     __syncthreads();  // cleared words
-    // four survivors per lane at a time: their hash chains interleave
-    for (int64_t i0 = p0 + threadIdx.x; i0 < p1; i0 += 4 * kBuildThreads) {
-      uint64_t xs[4];
-      bool ok[4];
+    if (fast) {
+      // kWideKeys survivors per lane at a time, their hash chains interleaved;
+      // a lane past the end adds 0
+      for (int64_t i0 = p0 + threadIdx.x; i0 < p1;
+           i0 += kWideKeys * kBuildThreads) {
+        uint64_t xs[kWideKeys];
+        bool ok[kWideKeys];
+        bool wide_key = false;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t i = i0 + u * kBuildThreads;
-        ok[u] = i < p1;
-        xs[u] = ok[u] ? x[i] : 0;
-      }
-      bool wide_key = false;
+        for (int u = 0; u < kWideKeys; ++u) {
+          const int64_t i = i0 + u * kBuildThreads;
+          ok[u] = i < p1;
+          xs[u] = ok[u] ? x[i] : 0;
+        }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) wide_key = wide_key || (xs[u] >> 32) != 0;
-      int32_t sign[4];
-      uint32_t bk[4];
-      if (!__any(wide_key)) {
+        for (int u = 0; u < kWideKeys; ++u)
+          wide_key = wide_key || (xs[u] >> 32) != 0;
+        if (!__any(wide_key)) {
+          int32_t sign[kWideKeys];
+          uint32_t bk[kWideKeys];
+          hash_many_pow2<kWideKeys>(xs, sd, bm.mask, sign, bk);
+          // one range holds every bucket: the half is bit 0 of the bucket
 #pragma unroll
-        for (int u = 0; u < 4; ++u) hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
-      } else {
+          for (int u = 0; u < kWideKeys; ++u)
+            atomicAdd(&pairs[bk[u] >> 1],
+                      ok[u] ? (uint32_t)sign[u] << ((bk[u] & 1u) << 4) : 0u);
+        } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if ((xs[u] >> 32) == 0)
-            hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
-          else
-            hash_xi_h<false>(xs[u], sd, bm, sign[u], bk[u]);
+          for (int u = 0; u < kWideKeys; ++u) {
+            if (!ok[u]) continue;
+            int32_t sign;
+            uint32_t bk;
+            if ((xs[u] >> 32) == 0)
+              hash_xi_h<true>(xs[u], sd, bm, sign, bk);
+            else
+              hash_xi_h<false>(xs[u], sd, bm, sign, bk);
+            atomicAdd(&pairs[bk >> 1], (uint32_t)sign << ((bk & 1u) << 4));
+          }
         }
       }
+    } else {
+      // four survivors per lane at a time: their hash chains interleave
+      for (int64_t i0 = p0 + threadIdx.x; i0 < p1; i0 += 4 * kBuildThreads) {
+        uint64_t xs[4];
+        bool ok[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int jj = (int)bk[u] - lo;
-        if (ok[u] && jj >= 0 && (int)bk[u] < hi)
-          atomicAdd(&pairs[jj >> 1],
-                    (jj & 1) ? (uint32_t)sign[u] << 16 : (uint32_t)sign[u]);
+        for (int u = 0; u < 4; ++u) {
+          const int64_t i = i0 + u * kBuildThreads;
+          ok[u] = i < p1;
+          xs[u] = ok[u] ? x[i] : 0;
+        }
+        bool wide_key = false;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) wide_key = wide_key || (xs[u] >> 32) != 0;
+        int32_t sign[4];
+        uint32_t bk[4];
+        if (!__any(wide_key)) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if ((xs[u] >> 32) == 0)
+              hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
+            else
+              hash_xi_h<false>(xs[u], sd, bm, sign[u], bk[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jj = (int)bk[u] - lo;
+          if (ok[u] && jj >= 0 && (int)bk[u] < hi)
+            atomicAdd(&pairs[jj >> 1],
+                      (jj & 1) ? (uint32_t)sign[u] << 16 : (uint32_t)sign[u]);
+        }
       }
     }
     __syncthreads();
@@ -313,7 +366,10 @@ hipError_t launch_wide_hash(const uint64_t *surv, int64_t cap,
   const int wr = (w + ranges - 1) / ranges;
   if (wr > kWideRange) return hipErrorInvalidValue;  // 16-bit pairs, 128 KiB
   const size_t lds = (size_t)((wr + 1) / 2) * 4;
-  hipLaunchKernelGGL(wide_hash_kernel, dim3(n_slices * ranges * chunks),
+  // every XCD's share of the items fits its kXcds-th of the grid
+  const int items = n_slices * ranges * chunks;
+  const int grid = (items + kXcds - 1) / kXcds * kXcds;
+  hipLaunchKernelGGL(wide_hash_kernel, dim3(grid),
                      dim3(kBuildThreads), lds, st, surv, cap,
                      reinterpret_cast<const unsigned long long *>(count),
                      reinterpret_cast<const RowSeeds *>(seeds), bm, d,
