@@ -121,7 +121,7 @@ constexpr int kWideRows = 8;
 constexpr int kWideTile = kBuildThreads * kWideRows;
 static_assert(kWideQueue >= 2 * kWideTile, "a tile fits after a partial queue");
 
-__global__ __launch_bounds__(kBuildThreads) void wide_compact_kernel(
+__global__ __launch_bounds__(kBuildThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void wide_compact_kernel(
     const BuildParams P, uint64_t *__restrict__ surv, int64_t cap,
     unsigned long long *__restrict__ count, int64_t row_begin,
     int64_t row_end) {

@@ -166,6 +166,79 @@ __global__ __launch_bounds__(kChainThreads) void chain3_kernel(ChainArgs a) {
   if (threadIdx.x == 0) a.partial[(size_t)i * gridDim.y + blockIdx.y] = red[0];
 }
 
+// int32 counters with w2 a multiple of 4 (16-byte aligned rows): the same
+// sums with 16-byte loads.  Lane l owns the column quads l, l + 512, ...,
+// Q of them (Q * 2048 >= w2), of B and of every P row; a row's loads are
+// all issued before its products (branch-free: a lane past the row's end
+// reloads the row's last quad and uses zeros).
+template <int Q>
+__global__ __launch_bounds__(kChainThreads) void chain3_vec_kernel(ChainArgs a) {
+  __shared__ u128 red[kChainThreads];
+  const int i = blockIdx.x;
+  const int w1 = a.w1, nq = a.w2 / 4;  // quads per row
+  const int4 *brow = reinterpret_cast<const int4 *>(a.B) + (int64_t)i * nq;
+  int4 bv[Q];
+#pragma unroll
+  for (int m = 0; m < Q; ++m) {
+    const int v = threadIdx.x + m * kChainThreads;
+    const int4 t = brow[min(v, nq - 1)];
+    bv[m] = v < nq ? t : make_int4(0, 0, 0, 0);
+  }
+  const uint64_t np = *a.n_p < 0 ? 0 : (uint64_t)*a.n_p;
+  const uint64_t nb = *a.n_b < 0 ? 0 : (uint64_t)*a.n_b;
+  const bool narrow = (u128)np * nb < ((u128)1 << 62);
+  const int j1a = blockIdx.y * kChainRows, j1b = min(w1, j1a + kChainRows);
+  const int4 *P4 = reinterpret_cast<const int4 *>(a.P) + (int64_t)i * w1 * nq;
+  const int32_t *Ai = reinterpret_cast<const int32_t *>(a.A) + (int64_t)i * w1;
+  u128 G = 0;
+  for (int j1 = j1a; j1 < j1b; ++j1) {
+    const int4 *prow = P4 + (int64_t)j1 * nq;
+    const int64_t aj = Ai[j1];
+    int4 cur[Q];
+#pragma unroll
+    for (int m = 0; m < Q; ++m)
+      cur[m] = prow[min((int)threadIdx.x + m * kChainThreads, nq - 1)];
+    // opaque, after every load is issued: B and the row stay in 32-bit
+    // registers (no 64-bit copies, for B none hoisted out of the loop);
+    // the multiply-adds widen them
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      __asm__("" : "+v"(bv[m].x), "+v"(bv[m].y), "+v"(bv[m].z), "+v"(bv[m].w));
+      __asm__("" : "+v"(cur[m].x), "+v"(cur[m].y), "+v"(cur[m].z), "+v"(cur[m].w));
+    }
+    // (B is zero past the row's end, so the reloaded quads add nothing)
+    if (narrow) {
+      int64_t t = 0;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) {
+        t += (int64_t)cur[m].x * bv[m].x;
+        t += (int64_t)cur[m].y * bv[m].y;
+        t += (int64_t)cur[m].z * bv[m].z;
+        t += (int64_t)cur[m].w * bv[m].w;
+      }
+      G += mul_s64_s64(aj, t);
+    } else {
+      // (an int32 x int32 product is exact in int64)
+      u128 t = 0;
+#pragma unroll
+      for (int m = 0; m < Q; ++m) {
+        t += s64_to_u128((int64_t)cur[m].x * bv[m].x);
+        t += s64_to_u128((int64_t)cur[m].y * bv[m].y);
+        t += s64_to_u128((int64_t)cur[m].z * bv[m].z);
+        t += s64_to_u128((int64_t)cur[m].w * bv[m].w);
+      }
+      G += mul_u128_s64(t, aj);
+    }
+  }
+  red[threadIdx.x] = G;
+  __syncthreads();
+  for (int off = kChainThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[(size_t)i * gridDim.y + blockIdx.y] = red[0];
+}
+
 __device__ __forceinline__ bool i128_less(u128 x, u128 y) {
   return (__int128)x < (__int128)y;
 }
@@ -221,7 +294,23 @@ __global__ void chain3_finish_kernel(ChainArgs a, int32_t nblk,
 hipError_t launch_chain3(const ChainArgs &a, uint64_t *row_est, double *est,
                          int32_t *flags, hipStream_t st) {
   const int nblk = (a.w1 + kChainRows - 1) / kChainRows;
-  if (a.counter_bits == 32)
+  const bool aligned =
+      ((reinterpret_cast<uintptr_t>(a.P) | reinterpret_cast<uintptr_t>(a.B)) & 15) == 0;
+  const int quads = (a.w2 / 4 + kChainThreads - 1) / kChainThreads;  // <= 8
+  if (a.counter_bits == 32 && a.w2 % 4 == 0 && aligned) {
+    if (quads <= 1)
+      hipLaunchKernelGGL(chain3_vec_kernel<1>, dim3(a.d, nblk),
+                         dim3(kChainThreads), 0, st, a);
+    else if (quads <= 2)
+      hipLaunchKernelGGL(chain3_vec_kernel<2>, dim3(a.d, nblk),
+                         dim3(kChainThreads), 0, st, a);
+    else if (quads <= 4)
+      hipLaunchKernelGGL(chain3_vec_kernel<4>, dim3(a.d, nblk),
+                         dim3(kChainThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL(chain3_vec_kernel<8>, dim3(a.d, nblk),
+                         dim3(kChainThreads), 0, st, a);
+  } else if (a.counter_bits == 32)
     hipLaunchKernelGGL(chain3_kernel<int32_t>, dim3(a.d, nblk),
                        dim3(kChainThreads), 0, st, a);
   else

@@ -29,7 +29,8 @@ def _tables(rng, n_a, n_p, n_b, dom1, dom2, key_dtype=np.int32):
     return ka, kb, kp1, kp2, attr
 
 
-def _run(oracle, ka, kb, kp1, kp2, attr, d, w1, w2, bits, preds, name):
+def _run(oracle, ka, kb, kp1, kp2, attr, d, w1, w2, bits, preds, name,
+         nb_override=None):
     torch = _torch()
     from paper_2102_02440_amd import compass as C
     _say(name, "n_p", kp1.size, "d", d, "w1", w1, "w2", w2, "bits", bits)
@@ -50,6 +51,10 @@ def _run(oracle, ka, kb, kp1, kp2, attr, d, w1, w2, bits, preds, name):
     C.sketch_build(kb.size, [], [], [tb], [s2], [B], nb, d, w2, counter_bits=bits)
     C.sketch_build_2d(kp1.size, [tattr], preds, tp1, s1, tp2, s2, P, npp, d, w1,
                       w2, counter_bits=bits)
+    n_b = kb.size
+    if nb_override is not None:  # a larger selected count: wider inner sums
+        n_b = nb_override
+        nb.fill_(n_b)
     row_est, est, flags = C.estimate_chain3(A, P, B, na, npp, nb, counter_bits=bits)
     torch.cuda.synchronize()
     mask = np.ones(kp1.size, bool)
@@ -63,7 +68,7 @@ def _run(oracle, ka, kb, kp1, kp2, attr, d, w1, w2, bits, preds, name):
     assert np.array_equal(P.cpu().numpy().astype(np.int64), Po)
     Ao = oracle.sketch(ka, s1, d, w1)
     Bo = oracle.sketch(kb, s2, d, w2)
-    vals, est_o, flag_o = oracle.chain3(Ao, Po, Bo, [ka.size, int(mask.sum()), kb.size])
+    vals, est_o, flag_o = oracle.chain3(Ao, Po, Bo, [ka.size, int(mask.sum()), n_b])
     vals_g = C.row_values(row_est.reshape(1, d, 2))[0]
     assert vals_g == [v & ((1 << 128) - 1) for v in vals]
     assert est.item() == est_o
@@ -92,6 +97,25 @@ def test_chain3_odd_widths_int64_keys(oracle):
     attr = (attr % 4).astype(np.int32)
     _run(oracle, ka, kb, kp1, kp2, attr, 3, 100, 37, 64,
          [{"col": 0, "kind": "point", "lo": 2}], "chain3 odd widths")
+
+
+@gpu
+@pytest.mark.parametrize("w1,w2,nb_override", [
+    (64, 30, None),          # w2 not a multiple of 4: one column per load
+    (9, 12, None),           # one quad per lane, most lanes past the end
+    (40, 4100, None),        # ragged: lanes past the row's end in the last quad
+    (33, 16384, None),       # widest rows: eight quads per lane
+    (40, 4096, 1 << 62),     # 128-bit inner sums (selected counts too large)
+    (64, 30, 1 << 62),
+])
+def test_chain3_row_layouts(oracle, w1, w2, nb_override):
+    """int32 chain estimates across the row layouts of the estimate kernel
+    (16-byte loads of 1, 2, 4 or 8 quads per lane; column-wise loads when
+    w2 is not a multiple of 4) and both inner-sum widths."""
+    rng = np.random.default_rng(w1 * 31 + w2)
+    t = _tables(rng, 1500, 6000, 1200, 300, 700)
+    _run(oracle, *t, 3, w1, w2, 32, [{"col": 0, "kind": "range", "lo": 0, "hi": 899}],
+         "chain3 layout", nb_override=nb_override)
 
 
 @gpu
