@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=3_000_000,
+    ap.add_argument("--cpu-sample-rows", type=int, default=24_000_000,
                     help="cast_info rows in the oracle's timed sample")
     ap.add_argument("--workload", default="job6a",
                     choices=["job6a", "batch", "learned", "large", "partition", "agms",
@@ -200,6 +200,16 @@ def run_batch(args):
         return (time.perf_counter() - a) / k
 
     t_batch = timed(plan.launch, args.steps)
+    # work of one launch (the plan clears the counters and selected counts)
+    updates, alg_bytes = 0, 0
+    for j in db.jobs:
+        ns = int(j["n_selected"].item())
+        nk = len(j["keys"])
+        updates += ns * nk * j["d"]
+        alg_bytes += sum(c.element_size() for c in j["pred_cols"]) * j["n_rows"]
+        alg_bytes += sum(k.element_size() for k in set(j["keys"])) * ns
+        alg_bytes += nk * j["d"] * j["w"] * (32 // 8)
+    tops = updates * OPS_PER_HASH_UPDATE / t_batch / 1e12
     snap = [[x.clone() for x in sides] for sides in db.sides]
     t_plain = timed(db.build_per_sketch, max(1, args.steps // 2))
     same = all(torch.equal(a, b) for sa, sb in zip(snap, db.sides) for a, b in zip(sa, sb))
@@ -218,7 +228,18 @@ def run_batch(args):
            "plain_one_launch_per_sketch_ms": t_plain * 1e3,
            "one_launch_per_table_ms": t_table * 1e3,
            "speedup_vs_plain": t_plain / t_batch,
-           "bit_exact_vs_plain": bool(same), "plan": info}
+           "bit_exact_vs_plain": bool(same), "plan": info,
+           # the whole plan is one graph launch (batch_scan, batch_compact,
+           # batch_hash, slab reduction): its hash updates over the launch's
+           # host-clock time, bound by integer ALU like the fused scan
+           "roofline": {"bound": "alu", "achieved": tops, "peak": ALU_PEAK_TOPS,
+                        "unit": "TOP/s", "frac": tops / ALU_PEAK_TOPS, "traffic": None,
+                        "kernel": "batch plan (one graph launch)",
+                        "hash_updates_per_step": updates,
+                        "ops_per_hash_update": OPS_PER_HASH_UPDATE,
+                        "hbm_view": {"alg_bytes_per_step": alg_bytes,
+                                     "achieved_gbs": alg_bytes / t_batch / 1e9,
+                                     "frac": alg_bytes / t_batch / 1e9 / HBM_PEAK_GBS}}}
     print(json.dumps(out), flush=True)
 
 
