@@ -179,6 +179,10 @@ typedef const __attribute__((address_space(4))) CompactItem KCItem;
 typedef const __attribute__((address_space(4))) HashItem KHItem;
 
 constexpr int kBatchQueue = 16384;       // survivors buffered in LDS
+// compaction tiles of eight rows per lane: more predicate loads in flight
+constexpr int kBatchRows = 8;
+constexpr int kBatchTile = kBuildThreads * kBatchRows;
+static_assert(kBatchQueue >= 2 * kBatchTile, "a tile fits after a partial queue");
 constexpr int64_t kBatchChunk = 1 << 20;  // survivors per hashing chunk
 constexpr int kBatchPiece = 32767;        // survivors per 16-bit fold
 constexpr int kBatchPairsPerLane = 16;    // 32768 buckets / 2 / 1024 lanes
@@ -202,12 +206,12 @@ __global__ __launch_bounds__(kBuildThreads) void batch_compact_kernel(
   const int n_sketch = job.J->n_sketch;
   uint64_t sel = 0;
   int qtot = 0;  // block-uniform
-  for (int64_t base = r0; base < r1; base += kBuildTile) {
-    const int nt = (int)min((int64_t)kBuildTile, r1 - base);
-    qtot = compact_tile<GlobalJob, kBuildRowsPerThread>(
+  for (int64_t base = r0; base < r1; base += kBatchTile) {
+    const int nt = (int)min((int64_t)kBatchTile, r1 - base);
+    qtot = compact_tile<GlobalJob, kBatchRows>(
         job, base, nt, n_preds, queue, &s_qn, qtot, (int)(base - r0));
-    const bool last = base + kBuildTile >= r1;
-    if (qtot > kBatchQueue - kBuildTile || (last && qtot > 0)) {
+    const bool last = base + kBatchTile >= r1;
+    if (qtot > kBatchQueue - kBatchTile || (last && qtot > 0)) {
       __syncthreads();  // queue complete
       if (threadIdx.x == 0) s_off = atomicAdd(sg.count, (unsigned long long)qtot);
       __syncthreads();
@@ -293,6 +297,15 @@ __global__ __launch_bounds__(kBuildThreads) void batch_hash_kernel(
       for (int u = 0; u < 4; ++u) wide_key = wide_key || (xs[u] >> 32) != 0;
       int32_t sign[4];
       uint32_t bk[4];
+      if (!__any(wide_key) && bm.pow2) {
+        // interleaved chains; a lane past the end adds 0
+        hash_many_pow2<4>(xs, sd, bm.mask, sign, bk);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          atomicAdd(&pairs[bk[u] >> 1],
+                    ok[u] ? (uint32_t)sign[u] << ((bk[u] & 1u) << 4) : 0u);
+        continue;
+      }
       if (!__any(wide_key)) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
