@@ -206,10 +206,22 @@ __global__ __launch_bounds__(kBuildThreads) void batch_compact_kernel(
   const int n_sketch = job.J->n_sketch;
   uint64_t sel = 0;
   int qtot = 0;  // block-uniform
+  // the first predicate of the next tile is loaded while this one is
+  // compacted (jobs here have at least one predicate)
+  uint32_t pre[kBatchRows];
+  load_first_pred<GlobalJob, kBatchRows>(
+      job, r0, (int)min((int64_t)kBatchTile, r1 - r0), pre);
   for (int64_t base = r0; base < r1; base += kBatchTile) {
     const int nt = (int)min((int64_t)kBatchTile, r1 - base);
-    qtot = compact_tile<GlobalJob, kBatchRows>(
-        job, base, nt, n_preds, queue, &s_qn, qtot, (int)(base - r0));
+    uint32_t cur[kBatchRows];
+#pragma unroll
+    for (int k = 0; k < kBatchRows; ++k) cur[k] = pre[k];
+    const int64_t nb = base + kBatchTile;
+    if (nb < r1)
+      load_first_pred<GlobalJob, kBatchRows>(
+          job, nb, (int)min((int64_t)kBatchTile, r1 - nb), pre);
+    qtot = compact_tile_loaded<GlobalJob, kBatchRows>(
+        job, base, nt, n_preds, queue, &s_qn, qtot, (int)(base - r0), cur);
     const bool last = base + kBatchTile >= r1;
     if (qtot > kBatchQueue - kBatchTile || (last && qtot > 0)) {
       __syncthreads();  // queue complete

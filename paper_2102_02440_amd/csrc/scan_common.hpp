@@ -69,29 +69,34 @@ __device__ __forceinline__ void load_fields(const KeyDev &kd, int64_t base,
   }
 }
 
-// Compacts the qualifying rows of tile [base, base + nt) into `queue`
-// (entries start .. start + count - 1, each the row offset plus `bias`;
-// unordered: the sums do not depend on order) and returns start + their
-// number.  Each predicate column is loaded for all of the thread's rows,
-// and before it is evaluated the next one is loaded too, so loads overlap
-// instead of waiting on the previous predicate's outcome.  With no
-// predicates every row qualifies; the queue is then not used and nt is
-// returned.  Every thread of the block must call it.
+// First predicate's raw column values of the tile's rows (0 past nt): a
+// caller can issue these loads for the next tile before it compacts the
+// current one.
 template <class J, int kRowsPerThread>
-__device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
-                            int32_t *queue, int32_t *s_qn, int start = 0,
-                            int bias = 0) {
-  if (n_preds == 0) return nt;
-  if (threadIdx.x == 0) *s_qn = start;
-  // predicate q + 1 is loaded before predicate q is evaluated
-  uint32_t cur[kRowsPerThread], nxt[kRowsPerThread];
-  bool pass[kRowsPerThread];
+__device__ __forceinline__ void load_first_pred(const J &job, int64_t base,
+                                                int nt,
+                                                uint32_t (&cur)[kRowsPerThread]) {
 #pragma unroll
   for (int k = 0; k < kRowsPerThread; ++k) {
     const int r = threadIdx.x + k * kBuildThreads;
-    pass[k] = r < nt;
-    cur[k] = pass[k] ? load_pred_raw(job.pred(0), base + r) : 0u;
+    cur[k] = r < nt ? load_pred_raw(job.pred(0), base + r) : 0u;
   }
+}
+
+// compact_tile with the first predicate's values already loaded (by
+// load_first_pred for the same tile); n_preds >= 1.
+template <class J, int kRowsPerThread>
+__device__ int compact_tile_loaded(const J &job, int64_t base, int nt,
+                                   int n_preds, int32_t *queue, int32_t *s_qn,
+                                   int start, int bias,
+                                   uint32_t (&cur)[kRowsPerThread]) {
+  if (threadIdx.x == 0) *s_qn = start;
+  // predicate q + 1 is loaded before predicate q is evaluated
+  uint32_t nxt[kRowsPerThread];
+  bool pass[kRowsPerThread];
+#pragma unroll
+  for (int k = 0; k < kRowsPerThread; ++k)
+    pass[k] = (int)threadIdx.x + k * kBuildThreads < nt;
   for (int q = 0; q < n_preds; ++q) {
     if (q + 1 < n_preds) {
       const PredDev &pn = job.pred(q + 1);
@@ -125,6 +130,25 @@ __device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
   }
   __syncthreads();
   return *s_qn;
+}
+
+// Compacts the qualifying rows of tile [base, base + nt) into `queue`
+// (entries start .. start + count - 1, each the row offset plus `bias`;
+// unordered: the sums do not depend on order) and returns start + their
+// number.  Each predicate column is loaded for all of the thread's rows,
+// and before it is evaluated the next one is loaded too, so loads overlap
+// instead of waiting on the previous predicate's outcome.  With no
+// predicates every row qualifies; the queue is then not used and nt is
+// returned.  Every thread of the block must call it.
+template <class J, int kRowsPerThread>
+__device__ int compact_tile(const J &job, int64_t base, int nt, int n_preds,
+                            int32_t *queue, int32_t *s_qn, int start = 0,
+                            int bias = 0) {
+  if (n_preds == 0) return nt;
+  uint32_t cur[kRowsPerThread];
+  load_first_pred<J, kRowsPerThread>(job, base, nt, cur);
+  return compact_tile_loaded<J, kRowsPerThread>(job, base, nt, n_preds, queue,
+                                                s_qn, start, bias, cur);
 }
 
 // Scans rows [row0, row1) of job J into the LDS partial counters `cnt` of
