@@ -220,8 +220,12 @@ compass_status compass_estimate(const compass_join_graph *g,
  *   w1, w2         1 .. 2^20 each, w1 * w2 <= 2^28
  *   counters       device, d x w1 x w2 row-major, int32 or int64
  *   other arguments as for compass_sketch_build.
- * The matrices exceed LDS at useful sizes, so each update is one
- * device-scope integer atomic (exact and order-independent). */
+ * The matrices exceed LDS at useful sizes: the updates are written as
+ * records, counting-sorted by tile (2^r rows of one sketch row's matrix,
+ * at most 32768 counters) and summed per tile in LDS, each tile written
+ * once (rows of at most 1 GiB of records per pass).  Widths without such a
+ * tiling (w2 > 32768, or more than 32768 tiles) take one device-scope
+ * integer atomic per update.  Both are exact and order-independent. */
 compass_status compass_sketch_build_2d(int64_t n_rows,
                                        const void *const *pred_cols,
                                        int32_t n_pred_cols,

@@ -62,6 +62,8 @@ hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
                          uint64_t *row_est, double *est, int32_t *flags,
                          int32_t n_tables, hipStream_t st);
 hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st);
+hipError_t launch_scan2d_binned(const BuildParams &P, const Bin2dArgs &a,
+                                int accumulate, hipStream_t st);
 hipError_t launch_chain3(const ChainArgs &a, uint64_t *row_est, double *est,
                          int32_t *flags, hipStream_t st);
 hipError_t launch_agms_build(const AgmsParams &P, int n_blocks, hipStream_t st);
@@ -1146,6 +1148,89 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
 // ---------------------------------------------------------------------
 // sketch partitioning (Section 5.1)
 // ---------------------------------------------------------------------
+// Tiles of the binned two-dimensional build: R = 2^r rows of one sketch
+// row's matrix, R * w2 int32 counters.  R grows to fill a 64 KiB tile (no
+// further than w1 needs), then, while there are more than kBinMaxBins tiles,
+// up to kBinTileWords counters.  -1: no tiling fits (the atomic scan is
+// used).
+static int bin2d_shift(int d, int w1, int w2) {
+  if (w2 > kBinTileWords) return -1;
+  int rs = 0;
+  while (((int64_t)w2 << (rs + 1)) <= kBinTileWords / 2 && (1 << rs) < w1) ++rs;
+  auto bins = [&](int r) { return (int64_t)d * ((w1 + (1 << r) - 1) >> r); };
+  while (bins(rs) > kBinMaxBins && ((int64_t)w2 << (rs + 1)) <= kBinTileWords)
+    ++rs;
+  if (bins(rs) > kBinMaxBins) return -1;
+  return rs;
+}
+
+// The binned build in batches of rows whose records (4 bytes per selected
+// row and sketch row) fit the record budget (1 GiB, or
+// COMPASS_2D_RECORD_BYTES); every batch after the first adds to the
+// counters.
+static compass_status sketch_build_2d_binned(const BuildParams &P,
+                                             DeviceState *ds, int64_t n_rows,
+                                             int d, int w1, int w2, int r_shift,
+                                             int accumulate, hipStream_t stream) {
+  int64_t budget = (int64_t)1 << 30;
+  if (const char *e = getenv("COMPASS_2D_RECORD_BYTES")) {
+    const long long v = atoll(e);
+    if (v > 0) budget = v;
+  }
+  const int64_t batch = std::max<int64_t>(
+      kBuildTile, budget / (4 * (int64_t)d) / kBuildTile * kBuildTile);
+  Bin2dArgs a;
+  memset(&a, 0, sizeof(a));
+  a.d = d;
+  a.w1 = w1;
+  a.w2 = w2;
+  a.r_shift = r_shift;
+  a.nbr = (w1 + (1 << r_shift) - 1) >> r_shift;
+  a.n_bins = d * a.nbr;
+  // blocks of the scan: two per CU when their LDS (histogram + row queue)
+  // allows it
+  const size_t scan_lds = (size_t)((a.n_bins + 3) & ~3) * 4 + (size_t)kBuildTile * 4;
+  const int64_t per_cu = scan_lds <= 80 * 1024 ? 2 : 1;
+  const int64_t rows_max = std::min<int64_t>(n_rows, batch);
+  const int64_t tiles_max = (rows_max + kBuildTile - 1) / kBuildTile;
+  const int64_t blocks_max = std::min<int64_t>(tiles_max, per_cu * ds->n_cu);
+  const int64_t rpb_max = (tiles_max + blocks_max - 1) / blocks_max * kBuildTile;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_rec = al((size_t)blocks_max * rpb_max * d * 4);
+  const size_t b_cnt = al((size_t)blocks_max * 4);
+  const size_t b_hist = al((size_t)blocks_max * a.n_bins * 4);
+  const size_t b_tot = al((size_t)a.n_bins * 4);
+  const size_t b_start = al((size_t)(a.n_bins + 1) * 4);
+  const size_t b_sorted = al((size_t)rows_max * d * 2);
+  void *scr;
+  compass_status st = ensure_scratch(
+      ds, b_rec + b_cnt + b_hist + b_tot + b_start + b_sorted, &scr);
+  if (st != COMPASS_OK) return st;
+  char *c = reinterpret_cast<char *>(scr);
+  a.rec = reinterpret_cast<uint32_t *>(c); c += b_rec;
+  a.rec_count = reinterpret_cast<int32_t *>(c); c += b_cnt;
+  a.hist = reinterpret_cast<int32_t *>(c); c += b_hist;
+  a.bin_total = reinterpret_cast<int32_t *>(c); c += b_tot;
+  a.bin_start = reinterpret_cast<int32_t *>(c); c += b_start;
+  a.sorted = reinterpret_cast<uint16_t *>(c);
+  if (!accumulate) {
+    ProfScope ps("fill_zero", stream);
+    HIP_OK(launch_fill_zero(P.n_selected, 8, stream));
+  }
+  for (int64_t b0 = 0; b0 < n_rows; b0 += batch) {
+    const int64_t b1 = std::min(n_rows, b0 + batch);
+    const int64_t tiles = (b1 - b0 + kBuildTile - 1) / kBuildTile;
+    const int64_t blocks = std::min<int64_t>(tiles, per_cu * ds->n_cu);
+    a.rows_per_block = (tiles + blocks - 1) / blocks * kBuildTile;
+    a.n_blocks = (int32_t)((b1 - b0 + a.rows_per_block - 1) / a.rows_per_block);
+    a.row0 = b0;
+    a.row1 = b1;
+    ProfScope ps("scan2d", stream);
+    HIP_OK(launch_scan2d_binned(P, a, (accumulate || b0 > 0) ? 1 : 0, stream));
+  }
+  return COMPASS_OK;
+}
+
 extern "C" compass_status compass_sketch_build_2d(
     int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
     const compass_pred *preds, int32_t n_preds,
@@ -1208,6 +1293,10 @@ extern "C" compass_status compass_sketch_build_2d(
   DeviceState *ds;
   st = device_state(&ds);
   if (st != COMPASS_OK) return st;
+  const int r_shift = bin2d_shift(d, w1, w2);
+  if (r_shift >= 0 && n_rows > 0)
+    return sketch_build_2d_binned(P, ds, n_rows, d, w1, w2, r_shift,
+                                  accumulate, stream);
   if (!accumulate) {
     ProfScope ps("fill_zero", stream);
     HIP_OK(launch_fill_zero(counters,

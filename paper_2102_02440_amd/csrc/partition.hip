@@ -2,14 +2,16 @@
 // sketch of a table that takes part in two joins, and the three-table chain
 // estimate that combines it with the neighbours' one-dimensional sketches.
 //
-//  scan2d_kernel   fused selection scan (the same compaction as the
+//  scan2d_*        fused selection scan (the same compaction as the
 //                  one-dimensional build); per qualifying row and sketch
 //                  row i, both keys are hashed with row i's functions of
 //                  their join and xi1 * xi2 is added to entry
 //                  [h1][h2] of row i's w1 x w2 matrix.  The matrices are far
-//                  larger than LDS (8192 x 8192 per row for the 6a shape),
-//                  so the add is one device-scope integer atomic; integer
-//                  addition makes the result exact and order-independent.
+//                  larger than LDS (8192 x 8192 per row for the 6a shape):
+//                  the binned build below sorts the updates by LDS-sized
+//                  tile; scan2d_kernel (one device-scope integer atomic per
+//                  update) serves the widths no tiling fits.  Integer
+//                  addition makes either exact and order-independent.
 //  chain3_kernel   X_i = sum over (j1, j2) of A[j1] P[j1][j2] B[j2]: block
 //                  (i, slab of j1 rows) streams its rows of P once with
 //                  coalesced loads; each lane holds its columns of B in
@@ -104,6 +106,271 @@ hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st) {
   else
     hipLaunchKernelGGL(scan2d_kernel<int64_t>, dim3(n_blocks),
                        dim3(kBuildThreads), 0, st, P);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Binned two-dimensional build.  The matrices are far larger than LDS, but
+// a tile of R = 2^r_shift consecutive j1 rows of one sketch row's matrix
+// (R * w2 int32 counters) is not.  Each update becomes a 32-bit record
+//     tile << 16 | (offset in the tile) << 1 | [xi1 * xi2 = -1]
+// (tiles < 2^15, offsets < 2^15); the records are counting-sorted by tile
+// and one workgroup per tile adds its records in LDS and writes the tile
+// once, so there is no zero fill and no device-scope atomic per update.
+//   scan2d_bin_kernel      the fused predicate scan of a block's rows:
+//                          records into the block's region, per-tile counts
+//                          in an LDS histogram, written out per block
+//   bin2d_offsets_kernel   per tile: exclusive sums over the blocks
+//   bin2d_scan_kernel      exclusive sums over the tiles (tile starts)
+//   bin2d_scatter_kernel   each block's records to their tile's range (the
+//                          order inside a tile is free: integer sums)
+//   bin2d_tile_kernel      per tile: LDS sums, one coalesced write
+// ---------------------------------------------------------------------
+__global__ __launch_bounds__(kBuildThreads) void scan2d_bin_kernel(
+    const BuildParams P, const Bin2dArgs a) {
+  extern __shared__ int32_t lds2[];
+  int32_t *hist = lds2;                       // a.n_bins counts
+  int32_t *queue = lds2 + ((a.n_bins + 3) & ~3);  // kBuildTile row offsets
+  __shared__ int32_t s_qn;
+  const Job2d job{P};
+  const int d = a.d;
+  const int w2 = a.w2;
+  const uint32_t rmask = (1u << a.r_shift) - 1;
+  const bool pow2 = P.bm1.pow2 && P.bm.pow2;
+  for (int j = threadIdx.x; j < a.n_bins; j += kBuildThreads) hist[j] = 0;
+  __syncthreads();
+  const int b = blockIdx.x;
+  const int64_t r0 = a.row0 + (int64_t)b * a.rows_per_block;
+  const int64_t r1 = min(a.row1, r0 + a.rows_per_block);
+  uint32_t *out = a.rec + (int64_t)b * a.rows_per_block * d;
+  int64_t nrec = 0;  // block-uniform
+  uint64_t sel = 0;
+  for (int64_t base = r0; base < r1; base += kBuildTile) {
+    const int nt = (int)min((int64_t)kBuildTile, r1 - base);
+    const int qn = compact_tile<Job2d, kBuildRowsPerThread>(
+        job, base, nt, P.n_preds, queue, &s_qn);
+    sel += (uint64_t)qn;
+    int ridx[kBuildRowsPerThread];
+    bool valid[kBuildRowsPerThread];
+#pragma unroll
+    for (int k = 0; k < kBuildRowsPerThread; ++k) {
+      const int q = threadIdx.x + k * kBuildThreads;
+      valid[k] = q < qn;
+      ridx[k] = valid[k] ? (P.n_preds ? queue[q] : q) : 0;
+    }
+    uint64_t x1[kBuildRowsPerThread], x2[kBuildRowsPerThread];
+    load_fields<kBuildRowsPerThread>(P.keys[0], base, ridx, x1);
+    load_fields<kBuildRowsPerThread>(P.keys[1], base, ridx, x2);
+    bool wide_key = false;
+#pragma unroll
+    for (int k = 0; k < kBuildRowsPerThread; ++k)
+      wide_key = wide_key || ((x1[k] | x2[k]) >> 32) != 0;
+    // power-of-two widths and 32-bit keys in the whole wave: the keys'
+    // hash chains interleave (lanes without a row hash 0 and skip)
+    const bool fast = pow2 && !__any(wide_key);
+    for (int i = 0; i < d; ++i) {
+      const RowSeeds s1 = P.seeds[i], s2 = P.seeds[d + i];
+      uint32_t *dst = out + nrec + (int64_t)i * qn;
+      int32_t g1[kBuildRowsPerThread], g2[kBuildRowsPerThread];
+      uint32_t b1[kBuildRowsPerThread], b2[kBuildRowsPerThread];
+      if (fast) {
+        hash_many_pow2<kBuildRowsPerThread>(x1, s1, P.bm1.mask, g1, b1);
+        hash_many_pow2<kBuildRowsPerThread>(x2, s2, P.bm.mask, g2, b2);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kBuildRowsPerThread; ++k) {
+          if ((x1[k] >> 32) == 0)
+            hash_xi_h<true>(x1[k], s1, P.bm1, g1[k], b1[k]);
+          else
+            hash_xi_h<false>(x1[k], s1, P.bm1, g1[k], b1[k]);
+          if ((x2[k] >> 32) == 0)
+            hash_xi_h<true>(x2[k], s2, P.bm, g2[k], b2[k]);
+          else
+            hash_xi_h<false>(x2[k], s2, P.bm, g2[k], b2[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kBuildRowsPerThread; ++k) {
+        if (!valid[k]) continue;
+        const uint32_t tile = (uint32_t)(i * a.nbr) + (b1[k] >> a.r_shift);
+        const uint32_t off = (b1[k] & rmask) * (uint32_t)w2 + b2[k];
+        dst[threadIdx.x + k * kBuildThreads] =
+            tile << 16 | off << 1 | (uint32_t)(g1[k] != g2[k]);
+        atomicAdd(&hist[tile], 1);
+      }
+    }
+    nrec += (int64_t)d * qn;
+    __syncthreads();  // queue and s_qn are reused by the next tile
+  }
+  int32_t *h = a.hist + (int64_t)b * a.n_bins;
+  for (int j = threadIdx.x; j < a.n_bins; j += kBuildThreads) h[j] = hist[j];
+  if (threadIdx.x == 0) {
+    a.rec_count[b] = (int32_t)nrec;
+    if (P.count_selected && sel)
+      atomicAdd(reinterpret_cast<unsigned long long *>(P.n_selected),
+                (unsigned long long)sel);
+  }
+}
+
+// one lane per tile: the counts of the blocks become their offsets inside
+// the tile's range, the total is the tile's size
+__global__ void bin2d_offsets_kernel(const Bin2dArgs a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n_bins) return;
+  // sixteen blocks' counts loaded before any offset is written
+  constexpr int kU = 16;
+  int32_t run = 0;
+  for (int b0 = 0; b0 < a.n_blocks; b0 += kU) {
+    int32_t c[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      c[u] = b0 + u < a.n_blocks ? a.hist[(int64_t)(b0 + u) * a.n_bins + j] : 0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (b0 + u < a.n_blocks) a.hist[(int64_t)(b0 + u) * a.n_bins + j] = run;
+      run += c[u];
+    }
+  }
+  a.bin_total[j] = run;
+}
+
+// one workgroup of kBinScanThreads lanes: bin_start = exclusive sums of
+// bin_total, bin_start[n_bins] = the total (< 2^31: one batch's records)
+constexpr int kBinScanThreads = 1024;
+static_assert(kBinMaxBins % kBinScanThreads == 0, "whole tiles per lane");
+__global__ __launch_bounds__(kBinScanThreads) void bin2d_scan_kernel(
+    const Bin2dArgs a) {
+  __shared__ int32_t part[kBinScanThreads];
+  constexpr int kPer = kBinMaxBins / kBinScanThreads;  // tiles per lane at most
+  const int n = a.n_bins;
+  const int per = (n + kBinScanThreads - 1) / kBinScanThreads;
+  const int j0 = threadIdx.x * per, j1 = min(n, j0 + per);
+  int32_t t[kPer];  // all of the lane's loads in flight together
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) t[u] = j0 + u < j1 ? a.bin_total[j0 + u] : 0;
+  int32_t s = 0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) s += t[u];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  // inclusive scan of the lane sums (Hillis-Steele)
+  for (int o = 1; o < kBinScanThreads; o <<= 1) {
+    const int32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int32_t run = part[threadIdx.x] - s;  // exclusive
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    if (j0 + u < j1) a.bin_start[j0 + u] = run;
+    run += t[u];
+  }
+  if (threadIdx.x == kBinScanThreads - 1) a.bin_start[n] = part[threadIdx.x];
+}
+
+// block b moves its records to their tiles' ranges (16-bit records: the
+// tile is known from the range)
+__global__ __launch_bounds__(kBuildThreads) void bin2d_scatter_kernel(
+    const Bin2dArgs a) {
+  extern __shared__ int32_t lds2[];
+  int32_t *pos = lds2;  // a.n_bins next free positions
+  const int b = blockIdx.x;
+  const int32_t *h = a.hist + (int64_t)b * a.n_bins;
+  for (int j = threadIdx.x; j < a.n_bins; j += kBuildThreads)
+    pos[j] = a.bin_start[j] + h[j];
+  __syncthreads();
+  const uint32_t *src = a.rec + (int64_t)b * a.rows_per_block * a.d;
+  const int n = a.rec_count[b];
+  for (int e0 = threadIdx.x; e0 < n; e0 += 4 * kBuildThreads) {
+    uint32_t r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * kBuildThreads;
+      r[u] = e < n ? src[e] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (e0 + u * kBuildThreads >= n) break;
+      const int p = atomicAdd(&pos[r[u] >> 16], 1);
+      a.sorted[p] = (uint16_t)(r[u] & 0xFFFFu);
+    }
+  }
+}
+
+// one workgroup per tile: LDS sums of the tile's records, then the tile's
+// rows (contiguous in the d x w1 x w2 layout) written or added once
+template <typename C>
+__global__ __launch_bounds__(kBuildThreads) void bin2d_tile_kernel(
+    const Bin2dArgs a, C *counters, int32_t accumulate) {
+  extern __shared__ int32_t lds2[];
+  int32_t *tile = lds2;
+  const int t = blockIdx.x;
+  const int i = t / a.nbr;
+  const int j1a = (t % a.nbr) << a.r_shift;
+  const int rows = min(1 << a.r_shift, a.w1 - j1a);
+  const int words = rows * a.w2;
+  // (w2 a multiple of 4: every tile starts on a 16-byte boundary)
+  const bool quads = (a.w2 & 3) == 0;
+  if (quads) {
+    for (int j = threadIdx.x; j < words / 4; j += kBuildThreads)
+      reinterpret_cast<int4 *>(tile)[j] = make_int4(0, 0, 0, 0);
+  } else {
+    for (int j = threadIdx.x; j < words; j += kBuildThreads) tile[j] = 0;
+  }
+  __syncthreads();
+  const int e1 = a.bin_start[t + 1];
+  for (int e0 = a.bin_start[t] + threadIdx.x; e0 < e1; e0 += 4 * kBuildThreads) {
+    uint32_t r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * kBuildThreads;
+      r[u] = e < e1 ? a.sorted[e] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + u * kBuildThreads < e1)
+        atomicAdd(&tile[r[u] >> 1], (r[u] & 1u) ? -1 : 1);
+  }
+  __syncthreads();
+  C *dst = counters + ((int64_t)i * a.w1 + j1a) * a.w2;
+  const bool aligned = (reinterpret_cast<uintptr_t>(counters) & 15) == 0;
+  if (sizeof(C) == 4 && quads && aligned && !accumulate) {
+    for (int j = threadIdx.x; j < words / 4; j += kBuildThreads)
+      reinterpret_cast<int4 *>(dst)[j] = reinterpret_cast<const int4 *>(tile)[j];
+  } else if (accumulate) {
+    for (int j = threadIdx.x; j < words; j += kBuildThreads)
+      dst[j] += (C)tile[j];
+  } else {
+    for (int j = threadIdx.x; j < words; j += kBuildThreads)
+      dst[j] = (C)tile[j];
+  }
+}
+
+hipError_t launch_scan2d_binned(const BuildParams &P, const Bin2dArgs &a,
+                                int accumulate, hipStream_t st) {
+  const size_t hist_lds = (size_t)((a.n_bins + 3) & ~3) * 4;
+  hipLaunchKernelGGL(scan2d_bin_kernel, dim3(a.n_blocks), dim3(kBuildThreads),
+                     hist_lds + (size_t)kBuildTile * 4, st, P, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bin2d_offsets_kernel, dim3((a.n_bins + 255) / 256),
+                     dim3(256), 0, st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(bin2d_scan_kernel, dim3(1), dim3(kBinScanThreads), 0, st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(bin2d_scatter_kernel, dim3(a.n_blocks), dim3(kBuildThreads),
+                     hist_lds, st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const size_t tile_lds = (size_t)(a.w2 << a.r_shift) * 4;
+  if (P.counter_bits == 32)
+    hipLaunchKernelGGL(bin2d_tile_kernel<int32_t>, dim3(a.n_bins),
+                       dim3(kBuildThreads), tile_lds, st, a,
+                       reinterpret_cast<int32_t *>(P.counters[0]), accumulate);
+  else
+    hipLaunchKernelGGL(bin2d_tile_kernel<int64_t>, dim3(a.n_bins),
+                       dim3(kBuildThreads), tile_lds, st, a,
+                       reinterpret_cast<int64_t *>(P.counters[0]), accumulate);
   return hipGetLastError();
 }
 
@@ -243,21 +510,34 @@ __device__ __forceinline__ bool i128_less(u128 x, u128 y) {
   return (__int128)x < (__int128)y;
 }
 
-__global__ void chain3_finish_kernel(ChainArgs a, int32_t nblk,
-                                     uint64_t *row_est, double *est,
-                                     int32_t *flags) {
+constexpr int kFinishThreads = 256;
+__global__ __launch_bounds__(kFinishThreads) void chain3_finish_kernel(
+    ChainArgs a, int32_t nblk, uint64_t *row_est, double *est,
+    int32_t *flags) {
   __shared__ u128 xs[64];
+  __shared__ u128 red[kFinishThreads];
   const int d = a.d;
-  for (int i = threadIdx.x; i < d; i += blockDim.x) {
+  // row sums of the block partials: all lanes per row, then a tree in LDS
+  for (int i = 0; i < d; ++i) {
     u128 x = 0;
-    for (int k = 0; k < nblk; ++k) x += a.partial[(size_t)i * nblk + k];
-    xs[i] = x;
-    if (row_est) {
-      row_est[2 * i] = (uint64_t)x;
-      row_est[2 * i + 1] = (uint64_t)(x >> 64);
+    for (int k = threadIdx.x; k < nblk; k += kFinishThreads)
+      x += a.partial[(size_t)i * nblk + k];
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = kFinishThreads / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
     }
+    if (threadIdx.x == 0) {
+      x = red[0];
+      xs[i] = x;
+      if (row_est) {
+        row_est[2 * i] = (uint64_t)x;
+        row_est[2 * i + 1] = (uint64_t)(x >> 64);
+      }
+    }
+    __syncthreads();  // red is reused by the next row
   }
-  __syncthreads();
   if (threadIdx.x != 0) return;
   for (int p = 1; p < d; ++p) {  // insertion sort of d <= 32 values
     const u128 v = xs[p];
@@ -286,7 +566,9 @@ __global__ void chain3_finish_kernel(ChainArgs a, int32_t nblk,
       b = 0;
       break;
     }
-    if (b > lim / f) ok = false; else b *= f;
+    u128 prod;  // b * f > 2^127 stops the product (no 128-bit division)
+    if (__builtin_mul_overflow(b, f, &prod) || prod > lim) ok = false;
+    else b = prod;
   }
   *flags = ok && b < lim ? 1 : 0;
 }
@@ -318,8 +600,8 @@ hipError_t launch_chain3(const ChainArgs &a, uint64_t *row_est, double *est,
                        dim3(kChainThreads), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(chain3_finish_kernel, dim3(1), dim3(64), 0, st, a, nblk,
-                     row_est, est, flags);
+  hipLaunchKernelGGL(chain3_finish_kernel, dim3(1), dim3(kFinishThreads), 0, st,
+                     a, nblk, row_est, est, flags);
   return hipGetLastError();
 }
 

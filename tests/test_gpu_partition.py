@@ -30,7 +30,7 @@ def _tables(rng, n_a, n_p, n_b, dom1, dom2, key_dtype=np.int32):
 
 
 def _run(oracle, ka, kb, kp1, kp2, attr, d, w1, w2, bits, preds, name,
-         nb_override=None):
+         nb_override=None, np_override=None):
     torch = _torch()
     from paper_2102_02440_amd import compass as C
     _say(name, "n_p", kp1.size, "d", d, "w1", w1, "w2", w2, "bits", bits)
@@ -55,6 +55,12 @@ def _run(oracle, ka, kb, kp1, kp2, attr, d, w1, w2, bits, preds, name,
     if nb_override is not None:  # a larger selected count: wider inner sums
         n_b = nb_override
         nb.fill_(n_b)
+    torch.cuda.synchronize()
+    n_p_built = int(npp.item())
+    n_p = n_p_built
+    if np_override is not None:  # with nb_override: beyond the certificate
+        n_p = np_override
+        npp.fill_(n_p)
     row_est, est, flags = C.estimate_chain3(A, P, B, na, npp, nb, counter_bits=bits)
     torch.cuda.synchronize()
     mask = np.ones(kp1.size, bool)
@@ -63,12 +69,12 @@ def _run(oracle, ka, kb, kp1, kp2, attr, d, w1, w2, bits, preds, name,
             mask &= (attr >= p["lo"]) & (attr <= p["hi"])
         elif p["kind"] == "point":
             mask &= attr == p["lo"]
-    assert npp.item() == int(mask.sum())
+    assert n_p_built == int(mask.sum())
     Po = oracle.sketch2d(kp1[mask], kp2[mask], s1, s2, d, w1, w2)
     assert np.array_equal(P.cpu().numpy().astype(np.int64), Po)
     Ao = oracle.sketch(ka, s1, d, w1)
     Bo = oracle.sketch(kb, s2, d, w2)
-    vals, est_o, flag_o = oracle.chain3(Ao, Po, Bo, [ka.size, int(mask.sum()), n_b])
+    vals, est_o, flag_o = oracle.chain3(Ao, Po, Bo, [ka.size, n_p, n_b])
     vals_g = C.row_values(row_est.reshape(1, d, 2))[0]
     assert vals_g == [v & ((1 << 128) - 1) for v in vals]
     assert est.item() == est_o
@@ -107,6 +113,7 @@ def test_chain3_odd_widths_int64_keys(oracle):
     (33, 16384, None),       # widest rows: eight quads per lane
     (40, 4096, 1 << 62),     # 128-bit inner sums (selected counts too large)
     (64, 30, 1 << 62),
+    (40, 4096, -1),          # selected counts beyond the certificate: flag 0
 ])
 def test_chain3_row_layouts(oracle, w1, w2, nb_override):
     """int32 chain estimates across the row layouts of the estimate kernel
@@ -114,8 +121,57 @@ def test_chain3_row_layouts(oracle, w1, w2, nb_override):
     w2 is not a multiple of 4) and both inner-sum widths."""
     rng = np.random.default_rng(w1 * 31 + w2)
     t = _tables(rng, 1500, 6000, 1200, 300, 700)
+    np_override = None
+    if nb_override == -1:
+        nb_override = np_override = 1 << 62
     _run(oracle, *t, 3, w1, w2, 32, [{"col": 0, "kind": "range", "lo": 0, "hi": 899}],
-         "chain3 layout", nb_override=nb_override)
+         "chain3 layout", nb_override=nb_override, np_override=np_override)
+
+
+@gpu
+@pytest.mark.parametrize("bits", [32, 64])
+def test_sketch2d_batches_accumulate_and_atomic_path(oracle, bits):
+    """The binned two-dimensional build in several row batches (a small
+    record budget), accumulating over two calls, against the oracle; and a
+    width beyond one LDS tile (w2 = 40000), which takes the scan with one
+    device-scope atomic per update."""
+    import os
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(11 + bits)
+    n = 50_000
+    kp1 = rng.integers(0, 3000, n).astype(np.int32)
+    kp2 = rng.integers(0, 5000, n).astype(np.int32)
+    attr = rng.integers(0, 1000, n).astype(np.int32)
+    d = 3
+    s1, s2 = W.draw_seeds(rng, 2, d)
+    ct = torch.int32 if bits == 32 else torch.int64
+    t1, t2, ta = (torch.from_numpy(v).cuda() for v in (kp1, kp2, attr))
+    pr = [{"col": 0, "kind": "range", "lo": 0, "hi": 599}]
+    mask = attr <= 599
+    for w1, w2, budget in [(200, 96, 4096 * 3 * 4 * 3 + 8), (4, 40000, None)]:
+        _say("sketch2d batches", w1, w2, budget, bits)
+        old = os.environ.get("COMPASS_2D_RECORD_BYTES")
+        if budget is not None:
+            os.environ["COMPASS_2D_RECORD_BYTES"] = str(budget)
+        try:
+            P = torch.full((d, w1, w2), 7, dtype=ct, device="cuda")
+            nsel = torch.zeros(1, dtype=torch.int64, device="cuda")
+            half = 23_457
+            C.sketch_build_2d(half, [ta[:half]], pr, t1[:half], s1, t2[:half], s2,
+                              P, nsel, d, w1, w2, counter_bits=bits)
+            C.sketch_build_2d(n - half, [ta[half:]], pr, t1[half:], s1, t2[half:], s2,
+                              P, nsel, d, w1, w2, counter_bits=bits, accumulate=True)
+            torch.cuda.synchronize()
+        finally:
+            if budget is not None:
+                if old is None:
+                    del os.environ["COMPASS_2D_RECORD_BYTES"]
+                else:
+                    os.environ["COMPASS_2D_RECORD_BYTES"] = old
+        assert nsel.item() == int(mask.sum())
+        Po = oracle.sketch2d(kp1[mask], kp2[mask], s1, s2, d, w1, w2)
+        assert np.array_equal(P.cpu().numpy().astype(np.int64), Po)
 
 
 @gpu
