@@ -381,6 +381,17 @@ compass_status compass_mlp_train_step(compass_mlp m, const float *x,
                                       const float *base, const float *target,
                                       int32_t n, float lr, float *loss,
                                       hipStream_t stream);
+/* An epoch of Adam steps without a host round trip per step: step k
+ * trains on samples idx[k * batch .. (k + 1) * batch) (device int32 row
+ * indices into x, base and target, e.g. a permutation) and writes its
+ * batch's mean squared error before the update to losses[k] (device,
+ * n_batches floats).  The same arithmetic as n_batches calls of
+ * compass_mlp_train_step on the gathered rows.  lr > 0. */
+compass_status compass_mlp_train_epoch(compass_mlp m, const float *x,
+                                       const float *base, const float *target,
+                                       const int32_t *idx, int32_t n_batches,
+                                       int32_t batch, float lr, float *losses,
+                                       hipStream_t stream);
 /* Copies to host (synchronous): what = 0 parameters, 1 last gradients,
  * 2 Adam first moments, 3 Adam second moments. */
 compass_status compass_mlp_read(compass_mlp m, int32_t what, float *host_out);

@@ -662,6 +662,9 @@ def _bind_mlp(L):
     L.compass_mlp_train_step.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float,
                                          vp, vp]
     L.compass_mlp_train_step.restype = ctypes.c_int32
+    L.compass_mlp_train_epoch.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_float, vp, vp]
+    L.compass_mlp_train_epoch.restype = ctypes.c_int32
     L.compass_mlp_read.argtypes = [vp, ctypes.c_int32, fp]
     L.compass_mlp_read.restype = ctypes.c_int32
     L.compass_mlp_write.argtypes = [vp, fp, fp, fp, ctypes.c_int64]
@@ -714,6 +717,18 @@ class MLP:
                                             float(lr), self._loss.data_ptr(),
                                             _stream(stream)))
         return self._loss
+
+    def train_epoch(self, x, base, target, idx, batch, lr, stream=None):
+        """Adam steps on the batches idx[k * batch:(k + 1) * batch] (device
+        int32 row indices); returns the device tensor of the batches' MSEs."""
+        assert idx.dtype == torch.int32 and idx.is_contiguous()
+        nb = idx.numel() // batch
+        losses = torch.empty(max(1, nb), dtype=torch.float32, device=x.device)
+        _check(lib().compass_mlp_train_epoch(self.h, x.data_ptr(), base.data_ptr(),
+                                             target.data_ptr(), idx.data_ptr(), nb,
+                                             int(batch), float(lr), losses.data_ptr(),
+                                             _stream(stream)))
+        return losses[:nb]
 
     def read(self, what=0):
         out = np.empty(self.n_params, dtype=np.float32)

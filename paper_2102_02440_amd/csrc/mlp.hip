@@ -58,12 +58,13 @@ __device__ __forceinline__ float round_bf16(float f) {
 
 // Forward pass of up to kMlpTile samples.  act: [layer][sample][kMlpMaxDim]
 // rounded layer inputs, pre: [layer][sample][kMlpMaxDim] pre-activations
-// (both only when `save`).
+// (both only when `save`).  Sample s reads row idx[s] of x and base (row s
+// when idx is null).
 __global__ __launch_bounds__(kMlpThreads) void mlp_fwd_kernel(
     MlpShape S, const uint16_t *__restrict__ wb, const float *__restrict__ p,
-    const float *__restrict__ x, const float *__restrict__ base, int32_t n,
-    float *__restrict__ y, float *__restrict__ act, float *__restrict__ pre,
-    int32_t save) {
+    const float *__restrict__ x, const float *__restrict__ base,
+    const int32_t *__restrict__ idx, int32_t n, float *__restrict__ y,
+    float *__restrict__ act, float *__restrict__ pre, int32_t save) {
   __shared__ float a[kMlpTile][kMlpMaxDim + 1];
   __shared__ float z[kMlpTile][kMlpMaxDim + 1];
   __shared__ float W[kMlpMaxDim][kMlpMaxDim + 1];
@@ -72,7 +73,12 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_fwd_kernel(
   const int n_in = S.dim[0];
   for (int k = threadIdx.x; k < kMlpTile * n_in; k += kMlpThreads) {
     const int s = k / n_in, i = k % n_in;
-    a[s][i] = (s0 + s < n) ? round_bf16(x[(size_t)(s0 + s) * n_in + i]) : 0.f;
+    if (s0 + s < n) {
+      const size_t r = idx ? (size_t)idx[s0 + s] : (size_t)(s0 + s);
+      a[s][i] = round_bf16(x[r * n_in + i]);
+    } else {
+      a[s][i] = 0.f;
+    }
   }
   for (int l = 0; l < S.n_layers; ++l) {
     const int di = S.dim[l], dout = S.dim[l + 1];
@@ -104,14 +110,16 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_fwd_kernel(
     __syncthreads();
   }
   for (int s = threadIdx.x; s < kMlpTile; s += kMlpThreads)
-    if (s0 + s < n) y[s0 + s] = base[s0 + s] + z[s][0];
+    if (s0 + s < n) y[s0 + s] = base[idx ? idx[s0 + s] : s0 + s] + z[s][0];
 }
 
 // Backward pass: dL/dy = 2 (y - t) / n; partial gradients of this
 // workgroup's samples go to slab[blockIdx.x][param]; loss partial too.
+// Sample s's target is t[idx[s]] (t[s] when idx is null).
 __global__ __launch_bounds__(kMlpThreads) void mlp_bwd_kernel(
     MlpShape S, const uint16_t *__restrict__ wb, const float *__restrict__ y,
-    const float *__restrict__ t, int32_t n, const float *__restrict__ act,
+    const float *__restrict__ t, const int32_t *__restrict__ idx, int32_t n,
+    const float *__restrict__ act,
     const float *__restrict__ pre, float *__restrict__ slab,
     float *__restrict__ loss_part) {
   __shared__ float dz[kMlpTile][kMlpMaxDim + 1];
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_bwd_kernel(
   for (int s = threadIdx.x; s < kMlpTile; s += kMlpThreads) {
     float g = 0.f;
     if (s0 + s < n) {
-      const float r = y[s0 + s] - t[s0 + s];
+      const float r = y[s0 + s] - t[idx ? idx[s0 + s] : s0 + s];
       g = 2.f * r / (float)n;
       lsum += r * r;
     }
@@ -362,19 +370,18 @@ extern "C" compass_status compass_mlp_forward(compass_mlp M, const float *x,
     return mfail(COMPASS_E_ARG, "bad argument");
   if (n == 0) return COMPASS_OK;
   hipLaunchKernelGGL(mlp_fwd_kernel, dim3((n + kMlpTile - 1) / kMlpTile),
-                     dim3(kMlpThreads), 0, st, M->S, M->wb, M->p, x, base, n, y,
-                     nullptr, nullptr, 0);
+                     dim3(kMlpThreads), 0, st, M->S, M->wb, M->p, x, base,
+                     (const int32_t *)nullptr, n, y, nullptr, nullptr, 0);
   MHIP(hipGetLastError());
   return COMPASS_OK;
 }
 
-extern "C" compass_status compass_mlp_train_step(compass_mlp M, const float *x,
-                                                 const float *base,
-                                                 const float *target, int32_t n,
-                                                 float lr, float *loss,
-                                                 hipStream_t st) {
-  if (!M || !x || !base || !target || n < 1)
-    return mfail(COMPASS_E_ARG, "bad argument");
+// One Adam step on samples idx[0..n) of (x, base, target) (rows 0..n when
+// idx is null); grows the activation buffers when n exceeds them.
+static compass_status train_batch(compass_mlp M, const float *x,
+                                  const float *base, const float *target,
+                                  const int32_t *idx, int32_t n, float lr,
+                                  float *loss, hipStream_t st) {
   const int blocks = (n + kMlpTile - 1) / kMlpTile;
   if (n > M->cap) {
     (void)hipDeviceSynchronize();
@@ -393,9 +400,9 @@ extern "C" compass_status compass_mlp_train_step(compass_mlp M, const float *x,
     M->cap = n;
   }
   hipLaunchKernelGGL(mlp_fwd_kernel, dim3(blocks), dim3(kMlpThreads), 0, st,
-                     M->S, M->wb, M->p, x, base, n, M->y, M->act, M->pre, 1);
+                     M->S, M->wb, M->p, x, base, idx, n, M->y, M->act, M->pre, 1);
   hipLaunchKernelGGL(mlp_bwd_kernel, dim3(blocks), dim3(kMlpThreads), 0, st,
-                     M->S, M->wb, M->y, target, n, M->act, M->pre, M->slab,
+                     M->S, M->wb, M->y, target, idx, n, M->act, M->pre, M->slab,
                      M->loss_part);
   const int np = M->S.n_params;
   hipLaunchKernelGGL(mlp_reduce_kernel, dim3((np + 255) / 256), dim3(256), 0, st,
@@ -410,6 +417,32 @@ extern "C" compass_status compass_mlp_train_step(compass_mlp M, const float *x,
                        M->p, M->m, M->v, M->wb, M->g, np, lr, b1, b2, 1e-8f, c1,
                        c2);
   MHIP(hipGetLastError());
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_mlp_train_step(compass_mlp M, const float *x,
+                                                 const float *base,
+                                                 const float *target, int32_t n,
+                                                 float lr, float *loss,
+                                                 hipStream_t st) {
+  if (!M || !x || !base || !target || n < 1)
+    return mfail(COMPASS_E_ARG, "bad argument");
+  return train_batch(M, x, base, target, nullptr, n, lr, loss, st);
+}
+
+extern "C" compass_status compass_mlp_train_epoch(
+    compass_mlp M, const float *x, const float *base, const float *target,
+    const int32_t *idx, int32_t n_batches, int32_t batch, float lr,
+    float *losses, hipStream_t st) {
+  if (!M || !x || !base || !target || !idx || !losses || n_batches < 0 ||
+      batch < 1 || lr <= 0.f)
+    return mfail(COMPASS_E_ARG, "bad argument");
+  for (int32_t k = 0; k < n_batches; ++k) {
+    const compass_status s = train_batch(M, x, base, target,
+                                         idx + (int64_t)k * batch, batch, lr,
+                                         losses + k, st);
+    if (s != COMPASS_OK) return s;
+  }
   return COMPASS_OK;
 }
 

@@ -78,16 +78,11 @@ def train(x, base, target, init, epochs=30, batch=512, lr=1e-3, seed=0,
     g.manual_seed(seed)
     hist = []
     for ep in range(epochs):
-        perm = torch.randperm(n, device=x.device, generator=g)
-        tot = torch.zeros((), dtype=torch.float64, device=x.device)
-        steps = 0
-        for s in range(0, n - batch + 1, batch):
-            idx = perm[s:s + batch]
-            loss = mlp.train_step(x[idx].contiguous(), base[idx].contiguous(),
-                                  target[idx].contiguous(), lr)
-            tot += loss[0].double()
-            steps += 1
-        hist.append(float(tot.item()) / max(1, steps))
+        # one library call per epoch: the batches gather their rows through
+        # the permutation inside the kernels
+        perm = torch.randperm(n, device=x.device, generator=g).to(torch.int32)
+        losses = mlp.train_epoch(x, base, target, perm, batch, lr)
+        hist.append(float(losses.double().mean().item()) if losses.numel() else 0.0)
         if log:
             log("[learned] epoch %d mse %.4f" % (ep, hist[-1]))
     return mlp, hist

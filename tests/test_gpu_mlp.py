@@ -105,3 +105,35 @@ def test_training_fits_a_correction():
     final = m._loss.item()
     print("[case] training loss", first, "->", final, flush=True)
     assert final < 0.2 * first
+
+
+@gpu
+def test_train_epoch_matches_steps(oracle):
+    """One epoch through compass_mlp_train_epoch (rows gathered through a
+    permutation inside the kernels) equals the same batches trained one
+    compass_mlp_train_step at a time on gathered copies: parameters, Adam
+    state and per-batch losses bit for bit; a ragged tail is left out."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(5)
+    n, batch = 2000, 300
+    x, base, t = _data(rng, n)
+    p0 = oracle.mlp_init(3).astype(np.float32)
+    xd, bd, td = (torch.from_numpy(a).cuda() for a in (x, base, t))
+    perm = torch.from_numpy(rng.permutation(n).astype(np.int32)).cuda()
+    print("[case] mlp epoch", n, batch, flush=True)
+    m1 = C.MLP(p0)
+    losses = m1.train_epoch(xd, bd, td, perm, batch, 1e-3)
+    m2 = C.MLP(p0)
+    ref = []
+    for k in range(n // batch):
+        idx = perm[k * batch:(k + 1) * batch].long()
+        ref.append(m2.train_step(xd[idx].contiguous(), bd[idx].contiguous(),
+                                 td[idx].contiguous(), 1e-3).item())
+    torch.cuda.synchronize()
+    assert losses.numel() == n // batch
+    assert np.array_equal(losses.cpu().numpy(), np.asarray(ref, dtype=np.float32))
+    for what in (0, 2, 3):
+        assert np.array_equal(m1.read(what), m2.read(what)), what
+    m1.close()
+    m2.close()
