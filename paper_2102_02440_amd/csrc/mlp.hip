@@ -9,11 +9,12 @@
 //
 // Kernels (tiny dense layers: H <= 64, so plain FP32 FMA over LDS tiles; a
 // matrix-core tile would sit idle at these shapes):
-//   mlp_fwd_kernel     32 samples per workgroup; layer weights staged in LDS;
+//   mlp_fwd_kernel     8 samples per workgroup (64 workgroups per 512-sample
+//                      batch); layer weights staged in LDS;
 //                      saves rounded inputs and pre-activations for training
 //   mlp_bwd_kernel     per-workgroup partial gradients (deterministic slab)
-//   mlp_reduce_kernel  sums the slab in a fixed order
-//   mlp_adam_kernel    Adam on fp32 masters, refreshes the bfloat16 copy
+//   mlp_reduce_adam_kernel  sums the slab in a fixed order, then Adam on
+//                      the fp32 masters and the bfloat16 copy
 //   mlp_features_kernel  sub-plan features from the 128-bit row estimates
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -30,7 +31,7 @@ namespace compass {
 
 constexpr int kMlpMaxDim = 64;
 constexpr int kMlpMaxLayers = 8;
-constexpr int kMlpTile = 32;       // samples per workgroup
+constexpr int kMlpTile = 8;        // samples per workgroup
 constexpr int kMlpThreads = 256;
 
 struct MlpShape {
@@ -187,33 +188,38 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_bwd_kernel(
   }
 }
 
-__global__ void mlp_reduce_kernel(const float *__restrict__ slab, int32_t parts,
-                                  int32_t n_params, float *__restrict__ g,
-                                  const float *__restrict__ loss_part,
-                                  float *__restrict__ loss, float inv_n) {
+// Gradient = sum of the workgroups' partials (in workgroup order, eight
+// partials' loads in flight per lane), then, when `adam`, the Adam update
+// of the same parameter (fp32 master, moments, bfloat16 copy).  Lane 0 of
+// workgroup 0 also sums the loss partials.
+__global__ void mlp_reduce_adam_kernel(
+    const float *__restrict__ slab, int32_t parts, int32_t n_params,
+    float *__restrict__ g, const float *__restrict__ loss_part,
+    float *__restrict__ loss, float inv_n, int32_t adam, float *__restrict__ p,
+    float *__restrict__ m, float *__restrict__ v, uint16_t *__restrict__ wb,
+    float lr, float b1, float b2, float eps, float c1, float c2) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n_params) {
-    float acc = 0.f;
-    for (int b = 0; b < parts; ++b) acc += slab[(size_t)b * n_params + k];
-    g[k] = acc;
-  }
   if (k == 0 && loss) {
     float acc = 0.f;
     for (int b = 0; b < parts; ++b) acc += loss_part[b];
     *loss = acc * inv_n;  // mean squared error
   }
-}
-
-__global__ void mlp_adam_kernel(float *__restrict__ p, float *__restrict__ m,
-                                float *__restrict__ v, uint16_t *__restrict__ wb,
-                                const float *__restrict__ g, int32_t n_params,
-                                float lr, float b1, float b2, float eps,
-                                float c1, float c2) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_params) return;
-  const float gk = g[k];
-  const float mk = b1 * m[k] + (1.f - b1) * gk;
-  const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+  constexpr int kU = 8;
+  float acc = 0.f;
+  for (int b0 = 0; b0 < parts; b0 += kU) {
+    float t[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      t[u] = b0 + u < parts ? slab[(size_t)(b0 + u) * n_params + k] : 0.f;
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (b0 + u < parts) acc += t[u];
+  }
+  g[k] = acc;
+  if (!adam) return;
+  const float mk = b1 * m[k] + (1.f - b1) * acc;
+  const float vk = b2 * v[k] + (1.f - b2) * acc * acc;
   m[k] = mk;
   v[k] = vk;
   const float pk = p[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
@@ -405,17 +411,14 @@ static compass_status train_batch(compass_mlp M, const float *x,
                      M->S, M->wb, M->y, target, idx, n, M->act, M->pre, M->slab,
                      M->loss_part);
   const int np = M->S.n_params;
-  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((np + 255) / 256), dim3(256), 0, st,
-                     M->slab, blocks, np, M->g, M->loss_part, loss,
-                     1.f / (float)n);
   if (lr > 0.f) M->step += 1;  // a gradient-only call is not an Adam step
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - powf(b1, (float)M->step);
   const float c2 = 1.f - powf(b2, (float)M->step);
-  if (lr > 0.f)
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3((np + 255) / 256), dim3(256), 0, st,
-                       M->p, M->m, M->v, M->wb, M->g, np, lr, b1, b2, 1e-8f, c1,
-                       c2);
+  hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((np + 255) / 256), dim3(256),
+                     0, st, M->slab, blocks, np, M->g, M->loss_part, loss,
+                     1.f / (float)n, lr > 0.f ? 1 : 0, M->p, M->m, M->v, M->wb,
+                     lr, b1, b2, 1e-8f, c1, c2);
   MHIP(hipGetLastError());
   return COMPASS_OK;
 }
