@@ -11,25 +11,75 @@
 
 namespace compass {
 
-// predicate columns are int32 or float32: their 32-bit patterns
-__device__ __forceinline__ uint32_t load_pred_raw(const PredDev &p,
-                                                  int64_t row) {
-  return reinterpret_cast<const uint32_t *>(p.col)[row];
+// predicate columns are int32 or float32: their 32-bit patterns.  Rows of
+// a tile are read through the tile's first row (a wave-uniform pointer)
+// and a 32-bit lane offset, so the loads take the scalar-base form and no
+// 64-bit address per row stays live.
+__device__ __forceinline__ const uint32_t *pred_tile(const PredDev &p,
+                                                    int64_t base) {
+  return reinterpret_cast<const uint32_t *>(p.col) + base;
 }
 
-__device__ __forceinline__ bool eval_pred_raw(const PredDev &p, uint32_t raw) {
+// pass[k] &= (row k satisfies p) for the R rows of a lane.  The
+// predicate's kind and type are the same for every row, so they are
+// dispatched once; each row is then a few compares with no branch (a
+// subset reads its bitmap word at a clamped index, then masks).
+template <int R>
+__device__ __forceinline__ void and_pred(const PredDev &p,
+                                         const uint32_t (&raw)[R],
+                                         bool (&pass)[R]) {
+  const int32_t kind = p.kind;
   if (p.dtype == kDtF32) {
-    const float v = __uint_as_float(raw);
-    if (p.kind == kPredPoint) return v == p.lo.f;
-    return (v >= p.lo.f) & (v <= p.hi.f);
+    const float lo = p.lo.f, hi = p.hi.f;
+    if (kind == kPredPoint) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) pass[k] = pass[k] & (__uint_as_float(raw[k]) == lo);
+    } else {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const float v = __uint_as_float(raw[k]);
+        pass[k] = pass[k] & (v >= lo) & (v <= hi);
+      }
+    }
+    return;
   }
-  const int32_t v = (int32_t)raw;
-  if (p.kind == kPredPoint) return v == p.lo.i;
-  if (p.kind == kPredRange) return (v >= p.lo.i) & (v <= p.hi.i);
-  // subset: dictionary code must lie in [0, domain) and have its bit set
-  if (v < 0 || (int64_t)v >= p.domain) return false;
-  const uint64_t word = p.bitmap[v >> 6];
-  return (word >> (v & 63)) & 1ull;
+  const int32_t lo = p.lo.i, hi = p.hi.i;
+  if (kind == kPredPoint) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) pass[k] = pass[k] & ((int32_t)raw[k] == lo);
+  } else if (kind == kPredRange) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int32_t v = (int32_t)raw[k];
+      pass[k] = pass[k] & (v >= lo) & (v <= hi);
+    }
+  } else if (p.domain <= 0) {  // subset of an empty domain
+#pragma unroll
+    for (int k = 0; k < R; ++k) pass[k] = false;
+  } else {
+    // dictionary code in [0, domain) with its bit set; the bitmap is read
+    // as 32-bit words (bit c of the 64-bit words is bit c & 31 of 32-bit
+    // word c >> 5), and out-of-domain codes read word 0, then are masked
+    // (four rows at a time, so that few words are live at once)
+    const int64_t dom = p.domain;
+    const uint32_t *bm32 = reinterpret_cast<const uint32_t *>(p.bitmap);
+#pragma unroll
+    for (int h = 0; h < R; h += 4) {
+      uint32_t word[4];
+      bool in[4];
+#pragma unroll
+      for (int u = 0; u < 4 && h + u < R; ++u) {
+        const int32_t v = (int32_t)raw[h + u];
+        in[u] = (v >= 0) & ((int64_t)v < dom);
+        word[u] = bm32[in[u] ? (v >> 5) : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < 4 && h + u < R; ++u)
+        pass[h + u] = pass[h + u] & in[u] &
+                      (((word[u] >> (raw[h + u] & 31u)) & 1u) != 0);
+      __asm__ volatile("" ::: "memory");  // the next four loads stay below
+    }
+  }
 }
 
 __device__ __forceinline__ uint64_t field_of_raw(int64_t v) {
@@ -76,10 +126,13 @@ template <class J, int kRowsPerThread>
 __device__ __forceinline__ void load_first_pred(const J &job, int64_t base,
                                                 int nt,
                                                 uint32_t (&cur)[kRowsPerThread]) {
+  const uint32_t *t = pred_tile(job.pred(0), base);
+  uint32_t lane = threadIdx.x;
+  __asm__("" : "+v"(lane));  // per call: no per-row addresses kept live
 #pragma unroll
   for (int k = 0; k < kRowsPerThread; ++k) {
-    const int r = threadIdx.x + k * kBuildThreads;
-    cur[k] = r < nt ? load_pred_raw(job.pred(0), base + r) : 0u;
+    const uint32_t r = lane + k * kBuildThreads;
+    cur[k] = (int)r < nt ? t[r] : 0u;
   }
 }
 
@@ -99,19 +152,18 @@ __device__ int compact_tile_loaded(const J &job, int64_t base, int nt,
     pass[k] = (int)threadIdx.x + k * kBuildThreads < nt;
   for (int q = 0; q < n_preds; ++q) {
     if (q + 1 < n_preds) {
-      const PredDev &pn = job.pred(q + 1);
+      const uint32_t *t = pred_tile(job.pred(q + 1), base);
+      uint32_t lane = threadIdx.x;
+      __asm__("" : "+v"(lane));
 #pragma unroll
       for (int k = 0; k < kRowsPerThread; ++k) {
-        const int r = threadIdx.x + k * kBuildThreads;
-        nxt[k] = r < nt ? load_pred_raw(pn, base + r) : 0u;
+        const uint32_t r = lane + k * kBuildThreads;
+        nxt[k] = (int)r < nt ? t[r] : 0u;
       }
     }
-    const PredDev &p = job.pred(q);
+    and_pred<kRowsPerThread>(job.pred(q), cur, pass);
 #pragma unroll
-    for (int k = 0; k < kRowsPerThread; ++k) {
-      pass[k] = pass[k] && eval_pred_raw(p, cur[k]);
-      cur[k] = nxt[k];
-    }
+    for (int k = 0; k < kRowsPerThread; ++k) cur[k] = nxt[k];
   }
   __syncthreads();  // s_qn initialised
 #pragma unroll
