@@ -481,3 +481,63 @@ def test_large_scan_full_size(oracle):
         assert np.array_equal(part[k].cpu().numpy(), o)
     del cols, keys, pc
     torch.cuda.empty_cache()
+
+
+@gpu
+def test_predicate_semantics(oracle):
+    """Every predicate kind and column type at its edges against the oracle's
+    reading: inclusive int32 ranges with negative values, float32 point
+    (-0 equals +0) and ranges (NaN and infinities), subsets with codes below
+    0, at and beyond the domain, an empty domain; and a conjunction of
+    three.  Selected count and sketch rows must match exactly."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(404)
+    n = 40_000 + 123
+    a = rng.integers(-50, 200, n).astype(np.int32)
+    f = rng.normal(size=n).astype(np.float32)
+    special = np.array([np.nan, np.inf, -np.inf, 0.0, -0.0, 1.0, -1.0], np.float32)
+    pick = rng.random(n) < 0.2
+    f[pick] = special[rng.integers(0, special.size, int(pick.sum()))]
+    c = rng.integers(-5, 1100, n).astype(np.int32)
+    bits = rng.random(1024) < 0.3
+    bitmap = np.zeros(16, np.uint64)
+    for j in range(1000):
+        if bits[j]:
+            bitmap[j >> 6] |= np.uint64(1) << np.uint64(j & 63)
+    keys = W.fk_column(rng, n, 30_000, 1.0, rng.permutation(30_000)).astype(np.int32)
+    d, w = 5, 2048
+    seeds = W.draw_seeds(rng, 1, d)[0]
+    cols = {"a": a, "f": f, "c": c}
+    names = list(cols)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in cols.items()}
+    bm_dev = torch.from_numpy(bitmap.view(np.int64)).cuda()
+    kt = torch.from_numpy(keys).cuda()
+    cases = [
+        [W.Predicate("a", "point", 7)],
+        [W.Predicate("a", "range", -10, 10)],
+        [W.Predicate("f", "point", 0.0)],
+        [W.Predicate("f", "range", -1.0, 1.0)],
+        [W.Predicate("f", "range", -np.inf, 0.5)],
+        [W.Predicate("c", "subset", bitmap=bitmap, domain=1000)],
+        [W.Predicate("c", "subset", bitmap=bitmap, domain=0)],
+        [W.Predicate("a", "range", 0, 150), W.Predicate("f", "range", -2.0, 2.0),
+         W.Predicate("c", "subset", bitmap=bitmap, domain=1000)],
+    ]
+    for preds in cases:
+        _say("predicates", [(p.col, p.kind, p.lo, p.hi, p.domain) for p in preds])
+        pd = []
+        for p in preds:
+            e = {"col": names.index(p.col), "kind": p.kind, "lo": p.lo, "hi": p.hi}
+            if p.kind == "subset":
+                e["bitmap"] = bm_dev
+                e["domain"] = p.domain
+            pd.append(e)
+        cnt = torch.full((d, w), 9, dtype=torch.int32, device="cuda")
+        nsel = torch.zeros(1, dtype=torch.int64, device="cuda")
+        C.sketch_build(n, [dev[k] for k in names], pd, [kt], [seeds], [cnt], nsel, d, w)
+        torch.cuda.synchronize()
+        mask = oracle.eval_predicates(cols, preds)
+        assert nsel.item() == int(mask.sum())
+        assert np.array_equal(cnt.cpu().numpy().astype(np.int64),
+                              oracle.sketch(keys[mask], seeds, d, w))
