@@ -370,6 +370,76 @@ __global__ __launch_bounds__(kBuildThreads) void batch_hash_kernel(
   }
 }
 
+// Phase B for rows of at most kBatchNarrowW buckets: one int32 LDS counter
+// per bucket (a chunk holds at most kBatchChunk survivors, far inside int32),
+// so there is no piece folding and no register copy of the counters, and
+// two workgroups fit a CU.  Same items and result as batch_hash_kernel.
+constexpr int kBatchNarrowW = 16384;  // 64 KiB of int32 counters
+__global__ __launch_bounds__(kBuildThreads) void batch_hash32_kernel(
+    const BatchJob *jobs, const BatchSeg *segs, const HashItem *items,
+    const RowSeeds *seeds) {
+  extern __shared__ int32_t cnt32[];
+  KHItem &it = ((KHItem *)items)[blockIdx.x];
+  KSeg &sg = ((KSeg *)segs)[it.seg];
+  const int64_t n = (int64_t)*sg.count;
+  const int64_t act = batch_active_chunks(n, sg.chunks);
+  if (it.chunk >= act) return;  // uniform: no survivors for this chunk
+  const GlobalJob job{(KJob *)jobs + sg.job, (KSeeds *)seeds};
+  const BucketMod bm = job.bm();
+  const int w = (int)bm.w;  // <= kBatchNarrowW
+  const int sl = it.slice;
+  const int s = job.slice_sketch(sl), row = job.slice_row(sl);
+  const RowSeeds sd = job.seeds(sl);
+  const int64_t seg_rows = sg.row1 - sg.row0;
+  const uint64_t *x = sg.surv + (int64_t)s * seg_rows;
+  const int64_t a = n * it.chunk / act, b = n * (it.chunk + 1) / act;
+  for (int j = threadIdx.x; j < w; j += kBuildThreads) cnt32[j] = 0;
+  __syncthreads();
+  for (int64_t i0 = a + threadIdx.x; i0 < b; i0 += 4 * kBuildThreads) {
+    uint64_t xs[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0 + u * kBuildThreads;
+      ok[u] = i < b;
+      xs[u] = ok[u] ? x[i] : 0;
+    }
+    bool wide_key = false;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) wide_key = wide_key || (xs[u] >> 32) != 0;
+    int32_t sign[4];
+    uint32_t bk[4];
+    if (!__any(wide_key) && bm.pow2) {
+      // interleaved chains; a lane past the end adds 0
+      hash_many_pow2<4>(xs, sd, bm.mask, sign, bk);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) atomicAdd(&cnt32[bk[u]], ok[u] ? sign[u] : 0);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!ok[u]) continue;
+        if ((xs[u] >> 32) == 0)
+          hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
+        else
+          hash_xi_h<false>(xs[u], sd, bm, sign[u], bk[u]);
+        atomicAdd(&cnt32[bk[u]], sign[u]);
+      }
+    }
+  }
+  __syncthreads();
+  // integer atomics: order-independent, hence exact
+  const size_t rbase = (size_t)row * w;
+  for (int j = threadIdx.x; j < w; j += kBuildThreads) {
+    const int32_t v = cnt32[j];
+    if (v == 0) continue;
+    if (job.counter_bits() == 32)
+      atomicAdd(reinterpret_cast<int32_t *>(job.counters(s)) + rbase + j, v);
+    else
+      atomicAdd(reinterpret_cast<unsigned long long *>(job.counters(s)) + rbase + j,
+                (unsigned long long)(int64_t)v);
+  }
+}
+
 __global__ void zero_regions_kernel(const ZeroRegion *r, int32_t n) {
   for (int k = blockIdx.y; k < n; k += gridDim.y) {
     uint32_t *p = reinterpret_cast<uint32_t *>(r[k].p);
@@ -430,19 +500,22 @@ struct compass_batch_plan_s {
   int n_cu = 0;
   // jobs with predicates: segments, rounds and the items of both phases
   struct Round {
-    size_t c0, c1, h0, h1;
+    size_t c0, c1, h0, h1, g0, g1;  // g: hash items of narrow rows
   };
   std::vector<BatchSeg> segs;        // surv = arena offset until uploaded
   std::vector<size_t> seg_arena_off;
   std::vector<CompactItem> citems;
   std::vector<HashItem> hitems;
+  std::vector<HashItem> gitems;      // rows of at most kBatchNarrowW buckets
   std::vector<Round> rounds;
   size_t arena_bytes = 0;
   char *arena = nullptr;
   size_t hash_lds = 0;
+  size_t hash32_lds = 0;
   BatchSeg *d_segs = nullptr;
   CompactItem *d_citems = nullptr;
   HashItem *d_hitems = nullptr;
+  HashItem *d_gitems = nullptr;
   unsigned long long *d_counts = nullptr;
 };
 
@@ -466,16 +539,22 @@ static void plan_two_phase(compass_batch_plan_s &pl) {
   pl.seg_arena_off.clear();
   pl.citems.clear();
   pl.hitems.clear();
+  pl.gitems.clear();
   pl.rounds.clear();
   pl.arena_bytes = 0;
   pl.hash_lds = 0;
+  pl.hash32_lds = 0;
   size_t used = 0;
-  compass_batch_plan_s::Round cur{0, 0, 0, 0};
+  compass_batch_plan_s::Round cur{0, 0, 0, 0, 0, 0};
   for (size_t j = 0; j < pl.jobs.size(); ++j) {
     const BatchJob &J = pl.jobs[j];
     const int64_t n = pl.job_rows[j];
     if (J.n_preds == 0 || n == 0) continue;
-    pl.hash_lds = std::max(pl.hash_lds, (size_t)((pl.job_w[j] + 1) / 2) * 4);
+    const bool narrow = pl.job_w[j] <= kBatchNarrowW;
+    if (narrow)
+      pl.hash32_lds = std::max(pl.hash32_lds, (size_t)pl.job_w[j] * 4);
+    else
+      pl.hash_lds = std::max(pl.hash_lds, (size_t)((pl.job_w[j] + 1) / 2) * 4);
     const int64_t max_rows = std::max<int64_t>(
         kBuildTile, (int64_t)(kArenaMax / (8 * (size_t)J.n_sketch)) /
                         kBuildTile * kBuildTile);
@@ -485,8 +564,9 @@ static void plan_two_phase(compass_batch_plan_s &pl) {
       if (used > 0 && used + bytes > kArenaMax) {  // close the round
         cur.c1 = pl.citems.size();
         cur.h1 = pl.hitems.size();
+        cur.g1 = pl.gitems.size();
         pl.rounds.push_back(cur);
-        cur = {pl.citems.size(), 0, pl.hitems.size(), 0};
+        cur = {pl.citems.size(), 0, pl.hitems.size(), 0, pl.gitems.size(), 0};
         used = 0;
       }
       BatchSeg sg;
@@ -505,12 +585,13 @@ static void plan_two_phase(compass_batch_plan_s &pl) {
       const int S = pl.job_slices[j];
       for (int sl = 0; sl < S; ++sl)
         for (int k = 0; k < sg.chunks; ++k)
-          pl.hitems.push_back(HashItem{si, sl, k, 0});
+          (narrow ? pl.gitems : pl.hitems).push_back(HashItem{si, sl, k, 0});
     }
   }
   if (!pl.segs.empty()) {
     cur.c1 = pl.citems.size();
     cur.h1 = pl.hitems.size();
+    cur.g1 = pl.gitems.size();
     pl.rounds.push_back(cur);
   }
 }
@@ -582,9 +663,10 @@ static compass_status upload_plan(compass_batch_plan_s &pl,
   const size_t b_segs = al(sizeof(BatchSeg) * std::max<size_t>(1, pl.segs.size()));
   const size_t b_cit = al(sizeof(CompactItem) * std::max<size_t>(1, pl.citems.size()));
   const size_t b_hit = al(sizeof(HashItem) * std::max<size_t>(1, pl.hitems.size()));
+  const size_t b_git = al(sizeof(HashItem) * std::max<size_t>(1, pl.gitems.size()));
   const size_t b_cnt = al(8 * std::max<size_t>(1, pl.segs.size()));
   const size_t total = b_jobs + b_items + b_seeds + b_zero + b_queue + b_segs +
-                       b_cit + b_hit + b_cnt;
+                       b_cit + b_hit + b_git + b_cnt;
   if (total > pl.dbytes) {
     if (pl.dmem) BHIP(hipFree(pl.dmem));
     pl.dmem = nullptr;
@@ -600,6 +682,7 @@ static compass_status upload_plan(compass_batch_plan_s &pl,
   pl.d_segs = reinterpret_cast<BatchSeg *>(pl.dmem + off); off += b_segs;
   pl.d_citems = reinterpret_cast<CompactItem *>(pl.dmem + off); off += b_cit;
   pl.d_hitems = reinterpret_cast<HashItem *>(pl.dmem + off); off += b_hit;
+  pl.d_gitems = reinterpret_cast<HashItem *>(pl.dmem + off); off += b_git;
   pl.d_counts = reinterpret_cast<unsigned long long *>(pl.dmem + off);
   if (pl.arena_bytes > 0 && !pl.arena) BHIP(hipMalloc(&pl.arena, pl.arena_bytes));
   std::vector<BatchSeg> sg = pl.segs;
@@ -616,6 +699,9 @@ static compass_status upload_plan(compass_batch_plan_s &pl,
   if (!pl.hitems.empty())
     BHIP(hipMemcpy(pl.d_hitems, pl.hitems.data(),
                    sizeof(HashItem) * pl.hitems.size(), hipMemcpyHostToDevice));
+  if (!pl.gitems.empty())
+    BHIP(hipMemcpy(pl.d_gitems, pl.gitems.data(),
+                   sizeof(HashItem) * pl.gitems.size(), hipMemcpyHostToDevice));
   std::vector<ZeroRegion> z = pl.zeros;
   z.push_back(ZeroRegion{pl.d_queue, 1});
   if (!pl.segs.empty())
@@ -647,6 +733,10 @@ static void enqueue(const compass_batch_plan_s &pl, hipStream_t st) {
       hipLaunchKernelGGL(batch_compact_kernel, dim3((unsigned)(r.c1 - r.c0)),
                          dim3(kBuildThreads), 0, st, pl.d_jobs, pl.d_segs,
                          pl.d_citems + r.c0);
+    if (r.g1 > r.g0)
+      hipLaunchKernelGGL(batch_hash32_kernel, dim3((unsigned)(r.g1 - r.g0)),
+                         dim3(kBuildThreads), pl.hash32_lds, st, pl.d_jobs,
+                         pl.d_segs, pl.d_gitems + r.g0, pl.d_seeds);
     if (r.h1 > r.h0)
       hipLaunchKernelGGL(batch_hash_kernel, dim3((unsigned)(r.h1 - r.h0)),
                          dim3(kBuildThreads), pl.hash_lds, st, pl.d_jobs,

@@ -62,17 +62,21 @@ def test_batch_equals_per_table(oracle, tune, tmp_path, monkeypatch):
 
 
 @gpu
-def test_batch_two_phase_rounds(oracle, tmp_path, monkeypatch):
+@pytest.mark.parametrize("w_choices", [(512, 1000, 2048), (1024, 20000, 32768)])
+def test_batch_two_phase_rounds(oracle, tmp_path, monkeypatch, w_choices):
     """Jobs with predicates cut into many segments and rounds (a 1 MiB
     survivor arena instead of 8 GiB): still bit-exact against one build
-    call per table, on repeated graph replays."""
+    call per table, on repeated graph replays.  Rows of at most 16384
+    buckets hash into int32 LDS counters, wider ones into 16-bit pairs; the
+    second case mixes both in the same rounds."""
     torch = _torch()
     from paper_2102_02440_amd import compass as C
     monkeypatch.setenv("COMPASS_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
     monkeypatch.setenv("COMPASS_BATCH_ARENA_BYTES", str(1 << 20))
     pool = W.schema_pool(seed=5, n_tables=10, scale=0.004)
-    qs = W.query_batch(pool, seed=6, n_queries=16, w_choices=(512, 1000, 2048))
-    print("[case] batch rounds jobs", sum(len(q.tables) for q in qs), flush=True)
+    qs = W.query_batch(pool, seed=6, n_queries=16, w_choices=w_choices)
+    print("[case] batch rounds jobs", sum(len(q.tables) for q in qs), w_choices,
+          flush=True)
     db = C.DeviceBatch(pool, qs)
     db.build_per_table()
     torch.cuda.synchronize()
