@@ -386,7 +386,8 @@ compass_status compass_mlp_train_step(compass_mlp m, const float *x,
  * indices into x, base and target, e.g. a permutation) and writes its
  * batch's mean squared error before the update to losses[k] (device,
  * n_batches floats).  The same arithmetic as n_batches calls of
- * compass_mlp_train_step on the gathered rows.  lr > 0. */
+ * compass_mlp_train_step on the gathered rows.  lr > 0.  The indices are
+ * not checked: each must be a row of x, base and target. */
 compass_status compass_mlp_train_epoch(compass_mlp m, const float *x,
                                        const float *base, const float *target,
                                        const int32_t *idx, int32_t n_batches,
