@@ -162,8 +162,12 @@ __device__ __forceinline__ void hash_many_pow2(const uint64_t (&x)[R],
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     // +1 or -1 from the parity: bit 0 sign-extended (0 or -1), doubled, | 1
-    // (opaque in between, so that it stays two instructions)
-    int32_t par = __builtin_amdgcn_sbfe((int32_t)low_of_residue(v[k]), 0, 1);
+    // (opaque before and after the extract: the low bits stay one add with
+    // carry, and the sign two instructions, instead of a compare of bit 0,
+    // a mask xor and a select)
+    uint32_t lr = low_of_residue(v[k]);
+    __asm__("" : "+v"(lr));
+    int32_t par = __builtin_amdgcn_sbfe((int32_t)lr, 0, 1);
     __asm__("" : "+v"(par));
     sign[k] = (int32_t)((uint32_t)par << 1) | 1;
     bucket[k] = low_of_residue(g[k]) & mask;
