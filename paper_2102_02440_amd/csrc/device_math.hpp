@@ -70,6 +70,24 @@ __device__ __forceinline__ uint64_t madd61_x32(uint64_t acc, uint32_t x,
   return r0 + (v >> 29);
 }
 
+// The same step for x < 2^31 (every non-negative int32 key): then
+// l * x + c < 2^63 + 2^61 cannot wrap, so c enters whole as the first
+// product's addend, and hi32(u) is the second one's:
+//   u = l * x + c                            (< 2^64)
+//   v = h * x + hi32(u)                      (< 2^61 + 2^32)
+//   acc * x + c = v * 2^32 + lo32(u)
+// Two v_mad_u64_u32 (and the move of hi32(u) into an addend pair), one AND,
+// one 64-bit shift and one 64-bit add: one 64-bit add less than
+// madd61_x32.  Result below 2^61 + 2^33.
+__device__ __forceinline__ uint64_t madd61_x31(uint64_t acc, uint32_t x,
+                                               uint64_t c) {
+  const uint64_t u = (uint64_t)(uint32_t)acc * x + c;
+  const uint64_t v = (uint64_t)(uint32_t)(acc >> 32) * x + (u >> 32);
+  uint64_t r0 = ((uint64_t)((uint32_t)v & 0x1FFFFFFFu) << 32) | (uint32_t)u;
+  __asm__("" : "+v"(r0));
+  return r0 + (v >> 29);
+}
+
 // acc < 2^63, x < 2^61, c < 2^61: value < 2^63 congruent to acc * x + c.
 //   acc * x = acc * lo32(x) + (acc * hi32(x)) * 2^32
 __device__ __forceinline__ uint64_t madd61_x61(uint64_t acc, uint64_t x,
@@ -142,23 +160,26 @@ __device__ __forceinline__ void hash_xi_h(uint64_t x, const RowSeeds &s,
   bucket = m.pow2 ? (low_of_residue(g) & m.mask) : bucket_of(canon61(g), m);
 }
 
-// Sign and power-of-two bucket of R keys (each below 2^32) under one row's
-// seeds, step by step across the keys so that the R independent Horner
-// chains interleave.
-template <int R>
+// Sign and power-of-two bucket of R keys (each below 2^32, or below 2^31
+// with X31) under one row's seeds, step by step across the keys so that the
+// R independent Horner chains interleave.
+template <int R, bool X31 = false>
 __device__ __forceinline__ void hash_many_pow2(const uint64_t (&x)[R],
                                                const RowSeeds &s, uint32_t mask,
                                                int32_t (&sign)[R],
                                                uint32_t (&bucket)[R]) {
+  auto step = [](uint64_t acc, uint32_t xx, uint64_t c) {
+    return X31 ? madd61_x31(acc, xx, c) : madd61_x32(acc, xx, c);
+  };
   uint64_t v[R], g[R];
 #pragma unroll
-  for (int k = 0; k < R; ++k) v[k] = madd61_x32(s.a3, (uint32_t)x[k], s.a2);
+  for (int k = 0; k < R; ++k) v[k] = step(s.a3, (uint32_t)x[k], s.a2);
 #pragma unroll
-  for (int k = 0; k < R; ++k) g[k] = madd61_x32(s.b1, (uint32_t)x[k], s.b0);
+  for (int k = 0; k < R; ++k) g[k] = step(s.b1, (uint32_t)x[k], s.b0);
 #pragma unroll
-  for (int k = 0; k < R; ++k) v[k] = madd61_x32(v[k], (uint32_t)x[k], s.a1);
+  for (int k = 0; k < R; ++k) v[k] = step(v[k], (uint32_t)x[k], s.a1);
 #pragma unroll
-  for (int k = 0; k < R; ++k) v[k] = madd61_x32(v[k], (uint32_t)x[k], s.a0);
+  for (int k = 0; k < R; ++k) v[k] = step(v[k], (uint32_t)x[k], s.a0);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     // +1 or -1 from the parity: bit 0 sign-extended (0 or -1), doubled, | 1

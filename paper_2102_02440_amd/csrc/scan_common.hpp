@@ -309,20 +309,25 @@ __device__ uint64_t scan_rows(const J &job, int64_t row0, int64_t row1,
       const BucketMod bm = job.bm();
       int32_t *c = cnt + (size_t)(sl - sb) * w;
       // one uniform branch when no key of the wave needs the 61-bit path
-      // (every non-negative int32 key); decided once per key load
+      // (every non-negative int32 key); decided once per key load:
+      // x_wide 0 = every key below 2^31, 2 = below 2^32, 1 = wider
       if (x_wide < 0) {
-        bool wide_key = false;
+        bool wide_key = false, big_key = false;
 #pragma unroll
-        for (int k = 0; k < kRowsPerThread; ++k)
+        for (int k = 0; k < kRowsPerThread; ++k) {
           wide_key = wide_key || (valid[k] && (x[k] >> 32) != 0);
-        x_wide = __any(wide_key) ? 1 : 0;
+          big_key = big_key || (valid[k] && (x[k] >> 31) != 0);
+        }
+        x_wide = __any(wide_key) ? 1 : (__any(big_key) ? 2 : 0);
       }
-      if (!x_wide) {
+      if (x_wide != 1) {
         // branch-free hashes (the lane's chains interleave), then the adds;
         // a lane without a row adds 0, so no hash sits under a branch
         int32_t sign[kRowsPerThread];
         uint32_t b[kRowsPerThread];
-        if (bm.pow2) {
+        if (bm.pow2 && x_wide == 0) {
+          hash_many_pow2<kRowsPerThread, true>(x, sd, bm.mask, sign, b);
+        } else if (bm.pow2) {
           hash_many_pow2<kRowsPerThread>(x, sd, bm.mask, sign, b);
         } else {
 #pragma unroll
