@@ -541,3 +541,33 @@ def test_predicate_semantics(oracle):
         assert nsel.item() == int(mask.sum())
         assert np.array_equal(cnt.cpu().numpy().astype(np.int64),
                               oracle.sketch(keys[mask], seeds, d, w))
+
+
+@gpu
+def test_key_width_classes(oracle):
+    """The fused scan picks the Horner step per wave from its keys' widths:
+    all below 2^31, all below 2^32, or wider (61-bit).  int64 keys at the
+    class edges (2^31 - 1, 2^31, 2^32 - 1, 2^32, p - 1, negative), in runs
+    that give every wave one class and in a mixed run, against the oracle."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(31)
+    n_run = 8192 * 3
+    small = rng.integers(0, 2**31, n_run)
+    mid = rng.integers(2**31, 2**32, n_run)
+    wide = rng.integers(2**32, 2**61 - 1, n_run)
+    edges = np.array([2**31 - 1, 2**31, 2**32 - 1, 2**32, 2**61 - 2, -1, 0, 1],
+                     np.int64)
+    mixed = np.concatenate([edges, rng.choice(np.concatenate([small, mid, wide]), 20_000)])
+    keys = np.concatenate([small, mid, wide, mixed, edges]).astype(np.int64)
+    d, w = 7, 4096
+    seeds = W.draw_seeds(rng, 1, d)[0]
+    kt = torch.from_numpy(keys).cuda()
+    cnt = torch.zeros((d, w), dtype=torch.int32, device="cuda")
+    nsel = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _say("key width classes", keys.size)
+    C.sketch_build(keys.size, [], [], [kt], [seeds], [cnt], nsel, d, w)
+    torch.cuda.synchronize()
+    assert nsel.item() == keys.size
+    assert np.array_equal(cnt.cpu().numpy().astype(np.int64),
+                          oracle.sketch(keys, seeds, d, w))
