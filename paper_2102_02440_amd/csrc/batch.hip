@@ -311,7 +311,7 @@ __global__ __launch_bounds__(kBuildThreads) void batch_hash_kernel(
       uint32_t bk[4];
       if (!__any(wide_key) && bm.pow2) {
         // interleaved chains; a lane past the end adds 0
-        hash_many_pow2<4>(xs, sd, bm.mask, sign, bk);
+        hash_many_pow2_auto<4>(xs, sd, bm.mask, sign, bk);
 #pragma unroll
         for (int u = 0; u < 4; ++u)
           atomicAdd(&pairs[bk[u] >> 1],
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kBuildThreads) void batch_hash32_kernel(
     uint32_t bk[4];
     if (!__any(wide_key) && bm.pow2) {
       // interleaved chains; a lane past the end adds 0
-      hash_many_pow2<4>(xs, sd, bm.mask, sign, bk);
+      hash_many_pow2_auto<4>(xs, sd, bm.mask, sign, bk);
 #pragma unroll
       for (int u = 0; u < 4; ++u) atomicAdd(&cnt32[bk[u]], ok[u] ? sign[u] : 0);
     } else {

@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
         if (!__any(wide_key)) {
           int32_t sign[kWideKeys];
           uint32_t bk[kWideKeys];
-          hash_many_pow2<kWideKeys>(xs, sd, bm.mask, sign, bk);
+          hash_many_pow2_auto<kWideKeys>(xs, sd, bm.mask, sign, bk);
           // one range holds every bucket: the half is bit 0 of the bucket
 #pragma unroll
           for (int u = 0; u < kWideKeys; ++u)

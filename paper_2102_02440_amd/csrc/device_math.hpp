@@ -195,6 +195,23 @@ __device__ __forceinline__ void hash_many_pow2(const uint64_t (&x)[R],
   }
 }
 
+// hash_many_pow2 of keys below 2^32 with the Horner step picked per wave:
+// the shorter step when no key of the wave reaches 2^31.
+template <int R>
+__device__ __forceinline__ void hash_many_pow2_auto(const uint64_t (&x)[R],
+                                                    const RowSeeds &s,
+                                                    uint32_t mask,
+                                                    int32_t (&sign)[R],
+                                                    uint32_t (&bucket)[R]) {
+  bool big = false;
+#pragma unroll
+  for (int k = 0; k < R; ++k) big = big || (x[k] >> 31) != 0;
+  if (__any(big))
+    hash_many_pow2<R, false>(x, s, mask, sign, bucket);
+  else
+    hash_many_pow2<R, true>(x, s, mask, sign, bucket);
+}
+
 // The same for a power-of-two w known at the call site: straight-line code,
 // so that several keys' chains interleave.
 template <bool X32>

@@ -174,8 +174,8 @@ __global__ __launch_bounds__(kBuildThreads) void scan2d_bin_kernel(
       int32_t g1[kBuildRowsPerThread], g2[kBuildRowsPerThread];
       uint32_t b1[kBuildRowsPerThread], b2[kBuildRowsPerThread];
       if (fast) {
-        hash_many_pow2<kBuildRowsPerThread>(x1, s1, P.bm1.mask, g1, b1);
-        hash_many_pow2<kBuildRowsPerThread>(x2, s2, P.bm.mask, g2, b2);
+        hash_many_pow2_auto<kBuildRowsPerThread>(x1, s1, P.bm1.mask, g1, b1);
+        hash_many_pow2_auto<kBuildRowsPerThread>(x2, s2, P.bm.mask, g2, b2);
       } else {
 #pragma unroll
         for (int k = 0; k < kBuildRowsPerThread; ++k) {
