@@ -212,28 +212,6 @@ __device__ __forceinline__ void hash_many_pow2_auto(const uint64_t (&x)[R],
     hash_many_pow2<R, true>(x, s, mask, sign, bucket);
 }
 
-// The same for a power-of-two w known at the call site: straight-line code,
-// so that several keys' chains interleave.
-template <bool X32>
-__device__ __forceinline__ void hash_xi_h_pow2(uint64_t x, const RowSeeds &s,
-                                               uint32_t mask, int32_t &sign,
-                                               uint32_t &bucket) {
-  uint64_t v, g;
-  if (X32) {
-    const uint32_t x32 = (uint32_t)x;
-    v = madd61_x32(s.a3, x32, s.a2);
-    v = madd61_x32(v, x32, s.a1);
-    v = madd61_x32(v, x32, s.a0);
-    g = madd61_x32(s.b1, x32, s.b0);
-  } else {
-    v = madd61_x61(s.a3, x, s.a2);
-    v = madd61_x61(v, x, s.a1);
-    v = madd61_x61(v, x, s.a0);
-    g = madd61_x61(s.b1, x, s.b0);
-  }
-  sign = 1 - 2 * (int32_t)(low_of_residue(v) & 1u);
-  bucket = low_of_residue(g) & mask;
-}
 // ---------------------------------------------------------------------
 // 128-bit two's complement (wrapping) helpers
 // ---------------------------------------------------------------------
