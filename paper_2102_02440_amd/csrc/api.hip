@@ -481,18 +481,25 @@ static compass_status sketch_build_impl(
   }
   const int n_groups_total = (S + per_group - 1) / per_group;
 
-  // chunks: up to two waves of the resident workgroup slots (whole
-  // waves, so that no slot runs one more workgroup than the others), but at
-  // least eight tiles per workgroup, which keeps zeroing and writing back
-  // its LDS partials small next to its scan.  Each chunk writes its partial
-  // counters to a slab (summed by one reduction kernel), which is cheap next
-  // to the scan: bound the slab to 1 GiB.
+  // chunks: two whole waves of the resident workgroup slots, else one
+  // (whole waves, so that no slot runs one more workgroup than the others),
+  // with at least eight tiles per workgroup, which keeps zeroing and
+  // writing back its LDS partials small next to its scan; a table too small
+  // for one full wave at eight tiles gets fewer chunks.  Each chunk writes
+  // its partial counters to a slab (summed by one reduction kernel), which
+  // is cheap next to the scan: bound the slab to 1 GiB.
   const size_t lds_block = (size_t)per_group * w * 4 + queue_bytes;
   const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / (lds_block + 1024))));
   const int64_t slots = (int64_t)ds->n_cu * per_cu;
   const int64_t tiles = (n_rows + kScanTile - 1) / kScanTile;
-  int64_t chunks = std::max<int64_t>(1, 2 * slots / n_groups_total);
-  chunks = std::min(chunks, std::max<int64_t>(1, tiles / 8));
+  int64_t chunks = 1;
+  for (int waves = 2; waves >= 1; --waves) {
+    const int64_t c = std::max<int64_t>(1, waves * slots / n_groups_total);
+    if (tiles / c >= 8 || waves == 1) {
+      chunks = std::min(c, std::max<int64_t>(1, tiles / 8));
+      break;
+    }
+  }
   const size_t slab_row = (size_t)S * w * 4;
   chunks = std::min<int64_t>(chunks, std::max<size_t>(1, ((size_t)1 << 30) / slab_row));
   int64_t rows_per_chunk = (n_rows + chunks - 1) / chunks;
