@@ -75,8 +75,7 @@ SCAN_SOURCES = ["scan_common.hpp", "build_kernels.hip", "build_params.hpp",
 # Integer VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
 # 32-bit operation per lane per clock (no packed 32-bit integer issue).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic 32-bit integer operations per unit of work (derivation in the
-# design notes):
+# Algorithmic 32-bit integer operations per unit of work:
 #  hash update (key below 2^32): four Horner steps of a 61 x 32-bit
 #    multiply-add mod 2^61-1 at 6 operations (two 32 x 32 -> 64
 #    multiply-adds, one AND, one 64-bit shift, two 64-bit adds), two
@@ -143,9 +142,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(sketches would shard by rows with one integer all-reduce; see "
-              "the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (sketches "
+              "would shard by rows, then one integer sum all-reduce of the "
+              "counters). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":

@@ -26,8 +26,8 @@ Query Optimization", arXiv 2102.02440):
 * ``mlp_*``            -- learned correction network (not in the paper),
   forward/backward in float64 NumPy on bfloat16-rounded parameters.
 
-Readings of silent or ambiguous passages are listed in the design notes of
-the repository; each is restated next to the code that applies it.
+Each reading of a silent or ambiguous passage is stated next to the code
+that applies it.
 """
 from __future__ import annotations
 
