@@ -54,7 +54,7 @@ typedef enum {
     COMPASS_E_RANGE = 2,        /* a size exceeds what the exact arithmetic allows */
     COMPASS_E_GRAPH = 3,        /* sub-plan empty / not connected / bad edge */
     COMPASS_E_HIP = 4,          /* HIP runtime failure */
-    COMPASS_E_UNSUPPORTED = 5   /* valid request outside what this build runs */
+    COMPASS_E_UNSUPPORTED = 5   /* valid request outside what this library runs */
 } compass_status;
 
 enum { COMPASS_I32 = 0, COMPASS_F32 = 1, COMPASS_I64 = 2 };
@@ -170,7 +170,7 @@ enum {
      * prod over the sub-plan's tables of n_selected, times w^(#edges -
      * #tables) when positive, is below 2^127 */
     COMPASS_FLAG_EXACT = 1,
-    /* the sub-plan's shape is outside what this build evaluates (more than
+    /* the sub-plan's shape is outside what this library evaluates (more than
      * one independent cycle, or a cycle longer than a triangle, or two
      * edges between the same two tables); its outputs are zero / NaN */
     COMPASS_FLAG_UNSUPPORTED = 2
