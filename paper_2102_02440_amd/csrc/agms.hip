@@ -29,9 +29,16 @@ struct AgmsJob {
 };
 
 // +-1 variable of one field element under one basic sketch's seeds
+// (the lanes of a wave mostly share the key: the width test is nearly
+// always uniform)
 __device__ __forceinline__ int32_t agms_xi(uint64_t x, const RowSeeds &s) {
   uint64_t v;
-  if ((x >> 32) == 0) {
+  if ((x >> 31) == 0) {
+    const uint32_t x32 = (uint32_t)x;
+    v = madd61_x31(s.a3, x32, s.a2);
+    v = madd61_x31(v, x32, s.a1);
+    v = madd61_x31(v, x32, s.a0);
+  } else if ((x >> 32) == 0) {
     const uint32_t x32 = (uint32_t)x;
     v = madd61_x32(s.a3, x32, s.a2);
     v = madd61_x32(v, x32, s.a1);
@@ -41,7 +48,12 @@ __device__ __forceinline__ int32_t agms_xi(uint64_t x, const RowSeeds &s) {
     v = madd61_x61(v, x, s.a1);
     v = madd61_x61(v, x, s.a0);
   }
-  return 1 - 2 * (int32_t)(low_of_residue(v) & 1u);
+  // parity as add-with-carry plus bit extract, then doubled | 1
+  uint32_t lr = low_of_residue(v);
+  __asm__("" : "+v"(lr));
+  int32_t par = __builtin_amdgcn_sbfe((int32_t)lr, 0, 1);
+  __asm__("" : "+v"(par));
+  return (int32_t)((uint32_t)par << 1) | 1;
 }
 
 __global__ __launch_bounds__(kBuildThreads) void agms_build_kernel(
