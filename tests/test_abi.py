@@ -174,3 +174,24 @@ def test_build_select_validation(C, kw, status):
         ctypes.c_void_p(0))
     assert rc == status
     assert L.compass_last_error().decode() != ""
+
+
+def test_mlp_entry_points_reject_bad_arguments(C):
+    """Null handles and pointers, empty batches and a non-positive rate are
+    rejected before any GPU work."""
+    L = C.lib()
+    C._bind_mlp(L)
+    vp = ctypes.c_void_p
+    one = vp(16)
+    assert L.compass_mlp_train_step(None, one, one, one, 4, ctypes.c_float(1e-3),
+                                    one, None) == 1
+    assert L.compass_mlp_train_epoch(None, one, one, one, one, 1, 4,
+                                     ctypes.c_float(1e-3), one, None) == 1
+    assert L.compass_mlp_forward(None, one, one, 4, one, None) == 1
+    h = vp(16)  # a non-null handle is still not dereferenced when an argument is bad
+    assert L.compass_mlp_train_epoch(h, None, one, one, one, 1, 4,
+                                     ctypes.c_float(1e-3), one, None) == 1
+    assert L.compass_mlp_train_epoch(h, one, one, one, one, 1, 0,
+                                     ctypes.c_float(1e-3), one, None) == 1
+    assert L.compass_mlp_train_epoch(h, one, one, one, one, 1, 4,
+                                     ctypes.c_float(0.0), one, None) == 1
