@@ -75,6 +75,8 @@ SCAN_SOURCES = ["scan_common.hpp", "build_kernels.hip", "build_params.hpp",
 # Integer VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one
 # 32-bit operation per lane per clock (no packed 32-bit integer issue).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# fp32 vector peak of MI355X (FMA = 2 flops)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 # Algorithmic 32-bit integer operations per unit of work:
 #  hash update (key below 2^32): four Horner steps of a 61 x 32-bit
 #    multiply-add mod 2^61-1 at 6 operations (two 32 x 32 -> 64
@@ -282,6 +284,10 @@ def run_learned(args):
     torch.cuda.synchronize()
     t_inf = (time.perf_counter() - a) / 10
     n = x.shape[0]
+    dims = [20, 64, 64, 64, 1]
+    macs = sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+    flops_per_sample = 2 * (3 * macs - dims[0] * dims[1])
+    train_tflops = flops_per_sample * n * args.epochs / t_train / 1e12
     out = {"metric": "subplan estimates/s at q-error (learned correction)",
            "value": xt.shape[0] / t_inf, "unit": "corrected estimates/s",
            "n_gpus": 1, "steps": args.epochs, "warmup": 0,
@@ -293,7 +299,18 @@ def run_learned(args):
                                   % (n, xt.shape[0]), "parallelism": "single-gpu"},
            "train_samples_per_s": n * args.epochs / t_train,
            "feature_build_s": t_feat, "mse_first_last": [hist[0], hist[-1]],
-           "qerror_heldout": res}
+           "qerror_heldout": res,
+           # training kernels (forward, backward, gradient sum + Adam): fp32
+           # FMA on the vector units; 2 flops per multiply-add of the three
+           # products of each layer (forward, input gradient, weight
+           # gradient; the first layer has no input gradient)
+           "roofline": {"bound": "alu", "achieved": train_tflops,
+                        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": train_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                        "traffic": None, "kernel": "mlp training step (fwd, bwd, reduce+Adam)",
+                        "flops_per_sample": flops_per_sample,
+                        "note": "512-sample batches of a 20-64-64-64-1 network: "
+                                "latency-bound, far from any roof"}}
     print(json.dumps(out), flush=True)
 
 
