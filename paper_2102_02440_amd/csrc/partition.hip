@@ -336,8 +336,15 @@ __global__ __launch_bounds__(kBuildThreads) void bin2d_tile_kernel(
   C *dst = counters + ((int64_t)i * a.w1 + j1a) * a.w2;
   const bool aligned = (reinterpret_cast<uintptr_t>(counters) & 15) == 0;
   if (sizeof(C) == 4 && quads && aligned && !accumulate) {
-    for (int j = threadIdx.x; j < words / 4; j += kBuildThreads)
-      reinterpret_cast<int4 *>(dst)[j] = reinterpret_cast<const int4 *>(tile)[j];
+    // written once and not read by this kernel: streaming stores
+    for (int j = threadIdx.x; j < words / 4; j += kBuildThreads) {
+      const int4 q = reinterpret_cast<const int4 *>(tile)[j];
+      int *o = reinterpret_cast<int *>(dst) + 4 * j;
+      __builtin_nontemporal_store(q.x, o);
+      __builtin_nontemporal_store(q.y, o + 1);
+      __builtin_nontemporal_store(q.z, o + 2);
+      __builtin_nontemporal_store(q.w, o + 3);
+    }
   } else if (accumulate) {
     for (int j = threadIdx.x; j < words; j += kBuildThreads)
       dst[j] += (C)tile[j];
