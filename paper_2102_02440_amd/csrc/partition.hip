@@ -469,9 +469,14 @@ __global__ __launch_bounds__(kChainThreads) void chain3_vec_kernel(ChainArgs a) 
     const int4 *prow = P4 + (int64_t)j1 * nq;
     const int64_t aj = Ai[j1];
     int4 cur[Q];
+    // the matrix is read once: streaming loads
 #pragma unroll
-    for (int m = 0; m < Q; ++m)
-      cur[m] = prow[min((int)threadIdx.x + m * kChainThreads, nq - 1)];
+    for (int m = 0; m < Q; ++m) {
+      typedef int v4i __attribute__((ext_vector_type(4)));
+      const v4i q = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(
+          prow + min((int)threadIdx.x + m * kChainThreads, nq - 1)));
+      cur[m] = make_int4(q.x, q.y, q.z, q.w);
+    }
     // opaque, after every load is issued: B and the row stay in 32-bit
     // registers (no 64-bit copies, for B none hoisted out of the loop);
     // the multiply-adds widen them
