@@ -13,8 +13,8 @@ namespace compass {
 
 // predicate columns are int32 or float32: their 32-bit patterns.  Rows of
 // a tile are read through the tile's first row (a wave-uniform pointer)
-// and a 32-bit lane offset, so the loads take the scalar-base form and no
-// 64-bit address per row stays live.
+// and a 32-bit lane offset, so no 64-bit address per row stays live; the
+// loads are streaming (nontemporal): each column word is read once.
 __device__ __forceinline__ const uint32_t *pred_tile(const PredDev &p,
                                                     int64_t base) {
   return reinterpret_cast<const uint32_t *>(p.col) + base;
@@ -132,7 +132,7 @@ __device__ __forceinline__ void load_first_pred(const J &job, int64_t base,
 #pragma unroll
   for (int k = 0; k < kRowsPerThread; ++k) {
     const uint32_t r = lane + k * kBuildThreads;
-    cur[k] = (int)r < nt ? t[r] : 0u;
+    cur[k] = (int)r < nt ? __builtin_nontemporal_load(t + r) : 0u;
   }
 }
 
@@ -158,7 +158,7 @@ __device__ int compact_tile_loaded(const J &job, int64_t base, int nt,
 #pragma unroll
       for (int k = 0; k < kRowsPerThread; ++k) {
         const uint32_t r = lane + k * kBuildThreads;
-        nxt[k] = (int)r < nt ? t[r] : 0u;
+        nxt[k] = (int)r < nt ? __builtin_nontemporal_load(t + r) : 0u;
       }
     }
     and_pred<kRowsPerThread>(job.pred(q), cur, pass);
