@@ -24,10 +24,11 @@
  *     never frees caller memory.
  *   - All GPU work is enqueued on `stream` (0 = the null stream) and is
  *     asynchronous: outputs are valid once the stream has synchronised.
- *   - Scratch memory is cached per device by the library and released by
- *     compass_release().  Calls that share the library's scratch on one
- *     device are serialised on their streams by the caller: two calls in
- *     flight at once on different streams of the same device race on it.
+ *   - Scratch memory is cached by the library per (device, stream) and
+ *     released by compass_release().  Calls on different streams never
+ *     share scratch, so they may be in flight at the same time (reentrant
+ *     across streams); calls on one stream run in stream order.  Host entry
+ *     is serialised by one library-wide lock.
  *
  * Hash families (the paper requires a 4-wise independent +-1 family xi and
  * one bucket hash h per sketch row, Sections 4.1 and 4.2, and names no
@@ -107,7 +108,16 @@ typedef struct {
  *   counter_bits  32 or 64 (int32 counters need n_rows < 2^31)
  *   accumulate    0: counters and *n_selected are overwritten; 1: added to
  *                 (sketches are mergeable by addition, Section 2)
- *   n_selected    device int64 */
+ *   n_selected    device int64
+ * Tables with predicates, and rows wider than 32768 buckets, are built in
+ * two phases: batches of rows have their qualifying rows' key field
+ * elements compacted into a survivor buffer (8 bytes per sketch per row),
+ * which is hashed into the counters only when the next batch might not fit
+ * it and after the last batch (so a selective scan hashes once).  The
+ * buffer takes at most 8.5 GiB of scratch (environment: COMPASS_TWO_PHASE_
+ * BYTES sets that budget, COMPASS_SURVIVOR_CAP_ROWS caps the buffer's rows;
+ * both exist to force many batches in tests).  E_RANGE if one batch of
+ * 4096 rows cannot fit the budget. */
 compass_status compass_sketch_build(int64_t n_rows,
                                     const void *const *pred_cols,
                                     int32_t n_pred_cols,
@@ -336,7 +346,12 @@ typedef struct compass_batch_plan_s *compass_batch_plan;
 
 /* Validates the jobs (as compass_sketch_build), builds the work-item list,
  * tunes, and captures "zero outputs + persistent kernel" into a graph.
- * Synchronous; runs on `stream` when autotuning. */
+ * Synchronous; runs on `stream` when autotuning.  Every kernel's LDS
+ * (static + dynamic) is checked against what one workgroup may allocate on
+ * the device (or a smaller COMPASS_LDS_LIMIT_BYTES) before anything runs:
+ * E_UNSUPPORTED if one does not fit.  When the autotune winner cannot be
+ * written to the cache file the call still succeeds and
+ * compass_last_error() says why. */
 compass_status compass_batch_plan_create(const compass_build_job *jobs,
                                          int32_t n_jobs, int32_t counter_bits,
                                          const compass_tune *tune,

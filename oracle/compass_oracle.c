@@ -16,6 +16,7 @@
  *
  * Build: gcc -O2 -fPIC -shared -fopenmp -o liboracle.so compass_oracle.c
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -87,6 +88,43 @@ void oracle_sketch(const int64_t *keys, int64_t n, const uint64_t *seeds,
             counters[(int64_t)i * w + b] += s;
         }
     }
+}
+
+/* The same counters computed by n_threads OpenMP threads: thread k sums
+ * the tuples of its contiguous share of the keys into counters of its own
+ * (the literal loop above, on a part of the input), and the parts' counters
+ * are then added.  Integer addition is exact and order-free, so the result
+ * equals the single-threaded one (Section 2: the sketch of a union is the
+ * sum of the parts' sketches).  counters: d x w int64, ADDED to. */
+void oracle_sketch_mt(const int64_t *keys, int64_t n, const uint64_t *seeds,
+                      int32_t d, int64_t w, int64_t *counters,
+                      int32_t n_threads)
+{
+    if (n_threads < 1) n_threads = 1;
+    if ((int64_t)n_threads > n / 4096 + 1) n_threads = (int32_t)(n / 4096 + 1);
+    const int64_t cells = (int64_t)d * w;
+    if (n_threads == 1) {
+        oracle_sketch(keys, n, seeds, d, w, counters);
+        return;
+    }
+    int64_t *part = (int64_t *)calloc((size_t)n_threads * (size_t)cells,
+                                      sizeof(int64_t));
+    if (!part) {  /* not enough memory for private counters: one thread */
+        oracle_sketch(keys, n, seeds, d, w, counters);
+        return;
+    }
+#pragma omp parallel for num_threads(n_threads) schedule(static, 1)
+    for (int32_t k = 0; k < n_threads; ++k) {
+        const int64_t r0 = n * k / n_threads, r1 = n * (k + 1) / n_threads;
+        oracle_sketch(keys + r0, r1 - r0, seeds, d, w, part + (int64_t)k * cells);
+    }
+#pragma omp parallel for num_threads(n_threads) schedule(static)
+    for (int64_t c = 0; c < cells; ++c) {
+        int64_t s = 0;
+        for (int32_t k = 0; k < n_threads; ++k) s += part[(int64_t)k * cells + c];
+        counters[c] += s;
+    }
+    free(part);
 }
 
 /* ------------------------------------------------------------------ */
@@ -668,4 +706,11 @@ double oracle_i128_to_double(uint64_t lo, uint64_t hi)
 {
     u128 u = (u128)lo | ((u128)hi << 64);
     return (double)(i128)u;
+}
+
+/* Number of threads the OpenMP loops of the estimate use from now on
+ * (the CPU baseline times the oracle with one thread and with all). */
+void oracle_set_threads(int32_t n)
+{
+    omp_set_num_threads(n < 1 ? 1 : n);
 }

@@ -71,6 +71,9 @@ def _load():
         lib.oracle_hash.restype = None
         lib.oracle_sketch.argtypes = [i64p, ctypes.c_int64, u64p,
                                       ctypes.c_int32, ctypes.c_int64, i64p]
+        lib.oracle_sketch_mt.argtypes = [i64p, ctypes.c_int64, u64p,
+                                         ctypes.c_int32, ctypes.c_int64, i64p,
+                                         ctypes.c_int32]
         lib.oracle_sketch.restype = None
         lib.oracle_estimate.argtypes = [
             ctypes.c_int32, ctypes.c_int32, i32p, i32p, ctypes.c_int32,
@@ -94,6 +97,7 @@ def _load():
                                              u64p, ctypes.POINTER(ctypes.c_double),
                                              i32p]
         lib.oracle_agms_estimate.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int32]
         lib.oracle_i128_to_double.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.oracle_i128_to_double.restype = ctypes.c_double
         _lib = lib
@@ -156,15 +160,33 @@ def eval_predicates(columns: dict, preds) -> np.ndarray:
 # --------------------------------------------------------------------------
 # Sketch build
 # --------------------------------------------------------------------------
-def sketch(keys: np.ndarray, seeds: np.ndarray, d: int, w: int) -> np.ndarray:
-    """Fast-AGMS counters (d x w, int64) of the given (already filtered) keys."""
+def default_threads() -> int:
+    """Threads the oracle's parallel loops use: OMP_NUM_THREADS when set,
+    else the CPUs this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.strip().isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def sketch(keys: np.ndarray, seeds: np.ndarray, d: int, w: int,
+           threads: int | None = None) -> np.ndarray:
+    """Fast-AGMS counters (d x w, int64) of the given (already filtered) keys.
+
+    ``threads``: 1 runs the literal loop; more split the keys into
+    contiguous parts with private counters that are summed at the end
+    (default: ``default_threads()``)."""
     lib = _load()
     k = np.ascontiguousarray(np.asarray(keys).astype(np.int64))
     s = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(d, 6))
     out = np.zeros((d, w), dtype=np.int64)
-    lib.oracle_sketch(_ptr(k, ctypes.c_int64), int(k.size),
-                      _ptr(s, ctypes.c_uint64), int(d), int(w),
-                      _ptr(out, ctypes.c_int64))
+    nt = default_threads() if threads is None else int(threads)
+    lib.oracle_sketch_mt(_ptr(k, ctypes.c_int64), int(k.size),
+                         _ptr(s, ctypes.c_uint64), int(d), int(w),
+                         _ptr(out, ctypes.c_int64), nt)
     return out
 
 
@@ -260,6 +282,11 @@ def build_table_sketches(table, edge_cols, seeds_per_edge, d, w):
 def i128_to_int(lo: int, hi: int) -> int:
     v = (int(hi) << 64) | int(lo)
     return v - (1 << 128) if v >> 127 else v
+
+
+def set_threads(n: int | None = None) -> None:
+    """Threads of the oracle's OpenMP loops (None: ``default_threads()``)."""
+    _load().oracle_set_threads(default_threads() if n is None else int(n))
 
 
 def estimate(n_tables, edge_u, edge_v, d, w, sketches, n_sel, masks,

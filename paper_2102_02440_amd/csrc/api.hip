@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "build_params.hpp"
+#include "build_plan.hpp"
 #include "compass.h"
 #include "estimate_buffers.hpp"
 #include "estimate_params.hpp"
@@ -32,16 +33,16 @@ hipError_t launch_scan_sketch(const BuildParams &P, int n_blocks,
 hipError_t launch_wide_compact(const BuildParams &P, uint64_t *surv,
                                int64_t cap, void *count, int64_t row_begin,
                                int64_t row_end, int n_blocks, hipStream_t st);
-hipError_t launch_wide_hash(const uint64_t *surv, int64_t cap,
-                            const void *count, const void *seeds,
-                            const BucketMod &bm, int d, int n_slices,
-                            int ranges, int chunks, int32_t *slab,
-                            hipStream_t st);
+hipError_t launch_wide_hash(const uint64_t *surv, const FlushCtl &fc,
+                            const void *seeds, const BucketMod &bm, int d,
+                            int n_slices, int ranges, int chunks,
+                            int32_t *slab, hipStream_t st);
 hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
                               int n_slices, int d, int w,
                               void *const *counters, int n_sketches,
                               int counter_bits, int accumulate,
-                              const unsigned long long *survivors,
+                              const FlushCtl &fc, hipStream_t st);
+hipError_t launch_store_seeds(const RowSeeds *src, int n, RowSeeds *dst,
                               hipStream_t st);
 hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
                             const EstBuffers &B, hipStream_t st);
@@ -103,8 +104,13 @@ void set_last_error(const std::string &s) { g_err = s; }
 // per-device state: scratch memory, pinned staging ring, kernel attrs
 // ---------------------------------------------------------------------
 struct DeviceState {
-  void *scratch = nullptr;
-  size_t scratch_bytes = 0;
+  // scratch memory per stream: calls on different streams of one device
+  // never share it, so they may be in flight at the same time
+  struct Scratch {
+    void *p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<hipStream_t, Scratch> scratch;
   static constexpr int kRing = 4;
   void *pinned[kRing] = {};
   size_t pinned_bytes[kRing] = {};
@@ -113,8 +119,6 @@ struct DeviceState {
   int ring_next = 0;
   bool attrs_set = false;
   int n_cu = 256;
-  void *dseeds = nullptr;      // seeds of wide sketches (direct kernel)
-  size_t dseeds_bytes = 0;
 };
 
 static std::mutex g_mu;
@@ -137,20 +141,24 @@ static compass_status device_state(DeviceState **out) {
   return COMPASS_OK;
 }
 
-static compass_status ensure_scratch(DeviceState *ds, size_t bytes,
-                                     void **out) {
-  if (bytes > ds->scratch_bytes) {
-    if (ds->scratch) {
+// Scratch of at least `bytes` for work on `stream` (grown, never shrunk,
+// until compass_release).  Growing waits for the device first: the old
+// buffer may still be in use by work already enqueued.
+static compass_status ensure_scratch(DeviceState *ds, hipStream_t stream,
+                                     size_t bytes, void **out) {
+  DeviceState::Scratch &sc = ds->scratch[stream];
+  if (bytes > sc.bytes) {
+    if (sc.p) {
       HIP_OK(hipDeviceSynchronize());
-      HIP_OK(hipFree(ds->scratch));
-      ds->scratch = nullptr;
-      ds->scratch_bytes = 0;
+      HIP_OK(hipFree(sc.p));
+      sc.p = nullptr;
     }
-    size_t want = std::max(bytes, ds->scratch_bytes * 2);
-    HIP_OK(hipMalloc(&ds->scratch, want));
-    ds->scratch_bytes = want;
+    const size_t want = std::max(bytes, sc.bytes * 2);
+    sc.bytes = 0;
+    HIP_OK(hipMalloc(&sc.p, want));
+    sc.bytes = want;
   }
-  *out = ds->scratch;
+  *out = sc.p;
   return COMPASS_OK;
 }
 
@@ -284,12 +292,134 @@ static compass_status fill_preds(BuildParams &base, int64_t n_rows,
   return COMPASS_OK;
 }
 
+// Where a build's scratch comes from: the pool of the calling stream, or a
+// fixed device region (the entry point that allocates nothing).
+struct Arena {
+  DeviceState *ds = nullptr;   // pooled
+  hipStream_t stream = 0;
+  char *fixed = nullptr;       // fixed region, fixed_bytes long
+  size_t fixed_bytes = 0;
+  compass_status get(size_t bytes, void **out) const {
+    if (fixed) {
+      if (bytes > fixed_bytes)
+        return fail(COMPASS_E_RANGE, "build needs %zu bytes of scratch, the "
+                    "fixed region holds %zu", bytes, fixed_bytes);
+      *out = fixed;
+      return COMPASS_OK;
+    }
+    return ensure_scratch(ds, stream, bytes, out);
+  }
+};
+
+// Scratch the pooled two-phase build may take: survivor buffer (8 bytes
+// per sketch per buffered survivor) + slab + seeds.
+static size_t pooled_two_phase_budget() {
+  size_t b = ((size_t)17) << 29;  // 8.5 GiB
+  if (const char *e = getenv("COMPASS_TWO_PHASE_BYTES")) {
+    const long long v = atoll(e);
+    if (v > 0) b = (size_t)v;
+  }
+  return b;
+}
+
+// Two-phase build (tables with predicates, and rows too wide for LDS
+// partials): batches of rows are compacted into the survivor buffer
+// (their keys' field elements, per sketch); the buffer is hashed into LDS
+// counters over bucket ranges and reduced into the counters only when the
+// next batch might not fit it, and after the last batch.  `zs` holds the
+// regions the call clears first; the buffer's count and ticket join them.
+static compass_status build_two_phase(const BuildParams &base,
+                                      const compass_sketch_spec *sketches,
+                                      int n_sketches, int d, int w,
+                                      int counter_bits, int64_t n_rows,
+                                      ZeroSpans zs, int n_cu, const Arena &ar,
+                                      hipStream_t stream) {
+  const int S = n_sketches * d;
+  int64_t cap_env = 0;
+  if (const char *e = getenv("COMPASS_SURVIVOR_CAP_ROWS")) cap_env = atoll(e);
+  const size_t budget = ar.fixed ? ar.fixed_bytes : pooled_two_phase_budget();
+  const TwoPhasePlan pl = plan_two_phase(n_rows, n_sketches, d, w, n_cu, budget,
+                                         cap_env, kBuildTile, sizeof(RowSeeds));
+  if (!pl.ok)
+    return fail(COMPASS_E_RANGE, "two-phase build of %d sketches x d=%d x "
+                "w=%d does not fit %zu bytes of scratch", n_sketches, d, w,
+                budget);
+  void *scr;
+  compass_status st = ar.get(pl.total_bytes, &scr);
+  if (st != COMPASS_OK) return st;
+  char *c = reinterpret_cast<char *>(scr);
+  RowSeeds *dseeds = reinterpret_cast<RowSeeds *>(c);
+  unsigned long long *count =
+      reinterpret_cast<unsigned long long *>(c + pl.seeds_bytes);
+  unsigned int *ticket = reinterpret_cast<unsigned int *>(c + pl.seeds_bytes + 8);
+  uint64_t *surv = reinterpret_cast<uint64_t *>(c + pl.seeds_bytes + pl.ctl_bytes);
+  int32_t *wslab = reinterpret_cast<int32_t *>(c + pl.seeds_bytes + pl.ctl_bytes +
+                                               pl.surv_bytes);
+  std::vector<RowSeeds> sd(S);
+  for (int s = 0; s < n_sketches; ++s)
+    for (int i = 0; i < d; ++i) {
+      const uint64_t *p = sketches[s].seeds + 6 * i;
+      sd[s * d + i] = RowSeeds{p[0], p[1], p[2], p[3], p[4], p[5]};
+    }
+  HIP_OK(launch_store_seeds(sd.data(), S, dseeds, stream));
+  {
+    ProfScope ps("fill_zero", stream);
+    zs.add(count, 16);  // count and ticket
+    HIP_OK(launch_fill_zero_list(zs, stream));
+  }
+  BuildParams P = base;
+  P.count_selected = 1;
+  P.n_groups = n_sketches;
+  std::vector<void *> cp(n_sketches);
+  for (int s = 0; s < n_sketches; ++s) cp[s] = sketches[s].counters;
+  for (int64_t r0 = 0; r0 < n_rows; r0 += pl.batch) {
+    const int64_t r1 = std::min(n_rows, r0 + pl.batch);
+    const int64_t tiles = (r1 - r0 + kBuildTile - 1) / kBuildTile;
+    {
+      ProfScope ps("wide_compact", stream);
+      HIP_OK(launch_wide_compact(P, surv, pl.cap, count, r0, r1,
+                                 (int)std::min<int64_t>(tiles, 2ll * n_cu),
+                                 stream));
+    }
+    FlushCtl fc;
+    memset(&fc, 0, sizeof fc);
+    fc.count = count;
+    fc.ticket = ticket;
+    fc.cap = pl.cap;
+    fc.need = r1 < n_rows ? std::min(pl.batch, n_rows - r1) : 0;
+    fc.force = r1 >= n_rows;
+    {
+      ProfScope ps("wide_hash", stream);
+      HIP_OK(launch_wide_hash(surv, fc, dseeds, base.bm, d, S, pl.ranges,
+                              pl.chunks, wslab, stream));
+    }
+    {
+      ProfScope ps("slab_reduce", stream);
+      HIP_OK(launch_slab_reduce(wslab, pl.chunks, S, d, w, cp.data(), n_sketches,
+                                counter_bits, 1, fc, stream));
+    }
+  }
+  return COMPASS_OK;
+}
+
+// The pooled arena of the current device and `stream`, and its CU count.
+static compass_status pooled_arena(hipStream_t stream, Arena *ar, int *n_cu) {
+  DeviceState *ds;
+  compass_status st = device_state(&ds);
+  if (st != COMPASS_OK) return st;
+  ar->ds = ds;
+  ar->stream = stream;
+  *n_cu = ds->n_cu;
+  return COMPASS_OK;
+}
+
 static compass_status sketch_build_impl(
     int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
     const compass_pred *preds, int32_t n_preds,
     const compass_sketch_spec *sketches, int32_t n_sketches, int32_t d,
     int32_t w, int32_t counter_bits, int32_t accumulate, int64_t *n_selected,
-    const RowSink &sink, hipStream_t stream) {
+    const RowSink &sink, const Arena *fixed, int fixed_n_cu,
+    hipStream_t stream) {
   if (n_rows < 0 || n_rows >= (1ll << 47))
     return fail(COMPASS_E_RANGE, "n_rows %lld outside [0, 2^47)",
                 (long long)n_rows);
@@ -336,10 +466,16 @@ static compass_status sketch_build_impl(
     base.counters[s] = k.counters;
   }
   (void)dtype_size;
-
-  DeviceState *ds;
-  compass_status st = device_state(&ds);
-  if (st != COMPASS_OK) return st;
+  compass_status st;
+  // scratch: the calling stream's pool, or the caller's fixed region
+  Arena ar;
+  int n_cu = fixed_n_cu;
+  if (fixed) {
+    ar = *fixed;
+  } else {
+    st = pooled_arena(stream, &ar, &n_cu);
+    if (st != COMPASS_OK) return st;
+  }
 
   // Two phases (compaction of the survivors' keys, then hashing them) for
   // rows too wide for LDS-private partials, and for every table with
@@ -352,7 +488,7 @@ static compass_status sketch_build_impl(
   // count and the selection output's count, and the counters unless the
   // fused scan's reduction overwrites them (the two-phase build adds into
   // them; an empty table launches nothing else).  The two-phase build adds
-  // its first survivor count to the same launch.
+  // its survivor buffer's count to the same launch.
   ZeroSpans zs;
   memset(&zs, 0, sizeof zs);
   if (!accumulate) {
@@ -362,96 +498,19 @@ static compass_status sketch_build_impl(
     zs.add(n_selected, 8);
     if (sink.out) zs.add(sink.count, 8);
   }
-  if (n_rows == 0 || !two_phase) {
+  if (n_rows == 0) {
     if (zs.n > 0) {
       ProfScope ps("fill_zero", stream);
       HIP_OK(launch_fill_zero_list(zs, stream));
     }
-    if (n_rows == 0) return COMPASS_OK;
-  }
-
-  if (two_phase) {
-    const int S = n_sketches * d;
-    std::vector<RowSeeds> sd(S);
-    for (int s = 0; s < n_sketches; ++s)
-      for (int i = 0; i < d; ++i) {
-        const uint64_t *p = sketches[s].seeds + 6 * i;
-        sd[s * d + i] = RowSeeds{p[0], p[1], p[2], p[3], p[4], p[5]};
-      }
-    const size_t bytes = sizeof(RowSeeds) * S;
-    if (ds->dseeds_bytes < bytes) {
-      if (ds->dseeds) {
-        HIP_OK(hipDeviceSynchronize());
-        HIP_OK(hipFree(ds->dseeds));
-      }
-      ds->dseeds = nullptr;
-      HIP_OK(hipMalloc(&ds->dseeds, std::max(bytes, (size_t)65536)));
-      ds->dseeds_bytes = std::max(bytes, (size_t)65536);
-    }
-    st = upload(ds, ds->dseeds, sd.data(), bytes, stream);
-    if (st != COMPASS_OK) return st;
-    // batches of at most `cap` rows: phase A compacts the survivors' key
-    // field elements (so the buffer can never overflow), phase B hashes
-    // them into LDS counters over a bucket range per block, and the slab
-    // reduction adds the partials into the counters (zeroed above unless
-    // accumulating).
-    // (survivor buffer at most 4 GiB: 8 bytes per sketch per row)
-    // (batches start on tile boundaries, so 16-byte column loads align)
-    const int64_t cap = std::min<int64_t>(
-        n_rows, std::max<int64_t>((int64_t)1 << 25,
-                                  ((int64_t)1 << 32) / (8 * n_sketches)) /
-                    kBuildTile * kBuildTile);
-    // phase B: bucket ranges of at most 65536 (16-bit pairs in 128 KiB of
-    // LDS); chunks so that about two whole waves of one-per-CU workgroups run
-    const int ranges = (w + 65535) / 65536;
-    const int chunks = std::max(1, (int)(2ll * ds->n_cu / (S * ranges)));
-    const size_t b_surv = (size_t)n_sketches * cap * 8;
-    const size_t b_slab = ((size_t)chunks * S * w * 4 + 255) & ~(size_t)255;
-    void *scr;
-    st = ensure_scratch(ds, b_surv + b_slab + 256, &scr);
-    if (st != COMPASS_OK) return st;
-    uint64_t *surv = reinterpret_cast<uint64_t *>(scr);
-    int32_t *wslab = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(scr) + b_surv);
-    void *count = reinterpret_cast<char *>(scr) + b_surv + b_slab;
-    BuildParams P = base;
-    P.count_selected = 1;
-    P.n_groups = n_sketches;
-    for (int s = 0; s < n_sketches; ++s) {
-      P.keys[s].col = sketches[s].key_col;
-      P.keys[s].dtype = sketches[s].key_dtype;
-      P.counters[s] = sketches[s].counters;
-    }
-    std::vector<void *> cp(n_sketches);
-    for (int s = 0; s < n_sketches; ++s) cp[s] = sketches[s].counters;
-    for (int64_t r0 = 0; r0 < n_rows; r0 += cap) {
-      const int64_t r1 = std::min(n_rows, r0 + cap);
-      const int64_t tiles = (r1 - r0 + kBuildTile - 1) / kBuildTile;
-      {
-        ProfScope ps("fill_zero", stream);
-        if (r0 > 0) zs.n = 0;  // the call's regions were cleared with batch 0
-        zs.add(count, 8);
-        HIP_OK(launch_fill_zero_list(zs, stream));
-      }
-      {
-        ProfScope ps("wide_compact", stream);
-        HIP_OK(launch_wide_compact(P, surv, cap, count, r0, r1,
-                                   (int)std::min<int64_t>(tiles, 2ll * ds->n_cu),
-                                   stream));
-      }
-      {
-        ProfScope ps("wide_hash", stream);
-        HIP_OK(launch_wide_hash(surv, cap, count, ds->dseeds, base.bm, d, S,
-                                ranges, chunks, wslab, stream));
-      }
-      {
-        ProfScope ps("slab_reduce", stream);
-        HIP_OK(launch_slab_reduce(wslab, chunks, S, d, w, cp.data(), n_sketches,
-                                  counter_bits, 1,
-                                  reinterpret_cast<const unsigned long long *>(count),
-                                  stream));
-      }
-    }
     return COMPASS_OK;
+  }
+  if (two_phase)
+    return build_two_phase(base, sketches, n_sketches, d, w, counter_bits,
+                           n_rows, zs, n_cu, ar, stream);
+  if (zs.n > 0) {
+    ProfScope ps("fill_zero", stream);
+    HIP_OK(launch_fill_zero_list(zs, stream));
   }
 
   // slice groups: consecutive (sketch, row) slices whose int32 partials fit
@@ -487,10 +546,12 @@ static compass_status sketch_build_impl(
   // writing back its LDS partials small next to its scan; a table too small
   // for one full wave at eight tiles gets fewer chunks.  Each chunk writes
   // its partial counters to a slab (summed by one reduction kernel), which
-  // is cheap next to the scan: bound the slab to 1 GiB.
+  // is cheap next to the scan: bound the slab to 1 GiB (or to the fixed
+  // scratch region).  A chunk never exceeds INT32_MAX rows (its partials
+  // are int32), so very long tables get more chunks than that bound.
   const size_t lds_block = (size_t)per_group * w * 4 + queue_bytes;
   const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / (lds_block + 1024))));
-  const int64_t slots = (int64_t)ds->n_cu * per_cu;
+  const int64_t slots = (int64_t)n_cu * per_cu;
   const int64_t tiles = (n_rows + kScanTile - 1) / kScanTile;
   int64_t chunks = 1;
   for (int waves = 2; waves >= 1; --waves) {
@@ -501,14 +562,16 @@ static compass_status sketch_build_impl(
     }
   }
   const size_t slab_row = (size_t)S * w * 4;
-  chunks = std::min<int64_t>(chunks, std::max<size_t>(1, ((size_t)1 << 30) / slab_row));
-  int64_t rows_per_chunk = (n_rows + chunks - 1) / chunks;
-  rows_per_chunk =
-      (rows_per_chunk + kScanTile - 1) / kScanTile * kScanTile;
+  const size_t slab_cap = ar.fixed ? ar.fixed_bytes : ((size_t)1 << 30);
+  if (slab_row > slab_cap)
+    return fail(COMPASS_E_RANGE, "one chunk's partial counters (%zu bytes) "
+                "exceed the scratch", slab_row);
+  chunks = std::min<int64_t>(chunks, std::max<size_t>(1, slab_cap / slab_row));
+  const int64_t rows_per_chunk = fused_rows_per_chunk(n_rows, chunks, kScanTile);
   chunks = (n_rows + rows_per_chunk - 1) / rows_per_chunk;
   base.rows_per_chunk = rows_per_chunk;
   void *slab;
-  st = ensure_scratch(ds, (size_t)chunks * slab_row, &slab);
+  st = ar.get((size_t)chunks * slab_row, &slab);
   if (st != COMPASS_OK) return st;
   base.slab = reinterpret_cast<int32_t *>(slab);
   base.d = d;
@@ -553,9 +616,11 @@ static compass_status sketch_build_impl(
   {
     std::vector<void *> cp(n_sketches);
     for (int s = 0; s < n_sketches; ++s) cp[s] = sketches[s].counters;
+    FlushCtl none;
+    memset(&none, 0, sizeof none);
     ProfScope ps("slab_reduce", stream);
     HIP_OK(launch_slab_reduce(base.slab, chunks, S, d, w, cp.data(), n_sketches,
-                              counter_bits, accumulate, nullptr, stream));
+                              counter_bits, accumulate, none, stream));
   }
   return COMPASS_OK;
 }
@@ -570,7 +635,7 @@ extern "C" compass_status compass_sketch_build(
   g_err.clear();
   return sketch_build_impl(n_rows, pred_cols, n_pred_cols, preds, n_preds,
                            sketches, n_sketches, d, w, counter_bits, accumulate,
-                           n_selected, RowSink{}, stream);
+                           n_selected, RowSink{}, nullptr, 0, stream);
 }
 
 extern "C" compass_status compass_sketch_build_select(
@@ -599,7 +664,7 @@ extern "C" compass_status compass_sketch_build_select(
   }
   return sketch_build_impl(n_rows, pred_cols, n_pred_cols, preds, n_preds,
                            sketches, n_sketches, d, w, counter_bits, accumulate,
-                           n_selected, sink, stream);
+                           n_selected, sink, nullptr, 0, stream);
 }
 
 // ---------------------------------------------------------------------
@@ -1049,7 +1114,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_tseg = carve(sizeof(int32_t) * np * d * (kFastSegs + 1));
   const size_t o_part = carve(16ull * std::max(1, pl.n_partial_slots) * d);
   void *scratch;
-  st = ensure_scratch(ds, off, &scratch);
+  st = ensure_scratch(ds, stream, off, &scratch);
   if (st != COMPASS_OK) return st;
   char *base = reinterpret_cast<char *>(scratch);
 
@@ -1211,7 +1276,7 @@ static compass_status sketch_build_2d_binned(const BuildParams &P,
   const size_t b_sorted = al((size_t)rows_max * d * 2);
   void *scr;
   compass_status st = ensure_scratch(
-      ds, b_rec + b_cnt + b_hist + b_tot + b_start + b_sorted, &scr);
+      ds, stream, b_rec + b_cnt + b_hist + b_tot + b_start + b_sorted, &scr);
   if (st != COMPASS_OK) return st;
   char *c = reinterpret_cast<char *>(scr);
   a.rec = reinterpret_cast<uint32_t *>(c); c += b_rec;
@@ -1338,7 +1403,7 @@ extern "C" compass_status compass_estimate_chain3(
   if (st != COMPASS_OK) return st;
   const int nblk = (w1 + kChainRows - 1) / kChainRows;
   void *scr;
-  st = ensure_scratch(ds, (size_t)d * nblk * 16, &scr);
+  st = ensure_scratch(ds, stream, (size_t)d * nblk * 16, &scr);
   if (st != COMPASS_OK) return st;
   ChainArgs c;
   c.A = a;
@@ -1423,7 +1488,7 @@ extern "C" compass_status compass_agms_build(
   if (st != COMPASS_OK) return st;
   void *scr;
   const size_t bytes = sizeof(RowSeeds) * sd.size();
-  st = ensure_scratch(ds, bytes, &scr);
+  st = ensure_scratch(ds, stream, bytes, &scr);
   if (st != COMPASS_OK) return st;
   st = upload(ds, scr, sd.data(), bytes, stream);
   if (st != COMPASS_OK) return st;
@@ -1484,9 +1549,9 @@ extern "C" compass_status compass_release(void) {
   if (it == g_dev.end()) return COMPASS_OK;
   DeviceState &ds = it->second;
   HIP_OK(hipDeviceSynchronize());
-  if (ds.scratch) HIP_OK(hipFree(ds.scratch));
-  ds.scratch = nullptr;
-  ds.scratch_bytes = 0;
+  for (auto &kv : ds.scratch)
+    if (kv.second.p) HIP_OK(hipFree(kv.second.p));
+  ds.scratch.clear();
   for (int k = 0; k < DeviceState::kRing; ++k) {
     if (ds.pinned[k]) HIP_OK(hipHostFree(ds.pinned[k]));
     ds.pinned[k] = nullptr;

@@ -17,6 +17,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <errno.h>
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -28,6 +31,7 @@
 #include <vector>
 
 #include "build_params.hpp"
+#include "build_plan.hpp"
 #include "compass.h"
 #include "device_math.hpp"
 #include "scan_common.hpp"
@@ -498,6 +502,7 @@ struct compass_batch_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int n_cu = 0;
+  size_t lds_limit = 0;   // LDS one workgroup may allocate on the device
   // jobs with predicates: segments, rounds and the items of both phases
   struct Round {
     size_t c0, c1, h0, h1, g0, g1;  // g: hash items of narrow rows
@@ -789,26 +794,75 @@ static bool cache_lookup(const std::string &key, compass_tune *t) {
   return false;
 }
 
-static void cache_store(const std::string &key, const compass_tune &t) {
+// Creates every missing directory of `dir` in this process (mkdir(2) per
+// path component; no child process).  Returns false with errno set.
+static bool make_dirs(const std::string &dir) {
+  for (size_t i = 1; i <= dir.size(); ++i) {
+    if (i < dir.size() && dir[i] != '/') continue;
+    const std::string part = dir.substr(0, i);
+    if (mkdir(part.c_str(), 0755) != 0 && errno != EEXIST) return false;
+  }
+  return true;
+}
+
+// Appends the winner to the cache file.  A cache that cannot be written
+// does not fail plan creation (the plan is complete either way); the
+// reason is left in compass_last_error() and false is returned.
+static bool cache_store(const std::string &key, const compass_tune &t) {
   const std::string p = cache_path();
   const size_t slash = p.rfind('/');
-  if (slash != std::string::npos) {
-    const std::string dir = p.substr(0, slash);
-    std::string cmd = "mkdir -p '" + dir + "'";
-    if (system(cmd.c_str()) != 0) return;
+  if (slash != std::string::npos && slash > 0 && !make_dirs(p.substr(0, slash))) {
+    bfail(COMPASS_OK, "autotune cache not written: cannot create the "
+                      "directory of " + p + ": " + strerror(errno));
+    return false;
   }
   std::ofstream f(p, std::ios::app);
-  f << key << " " << (long long)t.rows_per_item << " " << t.lds_budget << " "
-    << t.blocks_per_cu << "\n";
+  if (f)
+    f << key << " " << (long long)t.rows_per_item << " " << t.lds_budget << " "
+      << t.blocks_per_cu << "\n";
+  if (!f) {
+    bfail(COMPASS_OK, "autotune cache not written: cannot write " + p);
+    return false;
+  }
+  return true;
+}
+
+// Every kernel of the plan fits the LDS one workgroup may allocate:
+// dynamic (from the plan) plus static (from the compiled kernel).  Checked
+// before anything of the plan is launched.
+static compass_status check_lds(const compass_batch_plan_s &pl) {
+  struct K {
+    const void *fn;
+    size_t dyn;
+    const char *name;
+  } ks[] = {
+      {reinterpret_cast<const void *>(batch_scan_kernel), pl.lds, "batch_scan"},
+      {reinterpret_cast<const void *>(batch_compact_kernel), 0, "batch_compact"},
+      {reinterpret_cast<const void *>(batch_hash32_kernel), pl.hash32_lds,
+       "batch_hash32"},
+      {reinterpret_cast<const void *>(batch_hash_kernel), pl.hash_lds, "batch_hash"},
+  };
+  for (const K &k : ks) {
+    hipFuncAttributes at;
+    BHIP(hipFuncGetAttributes(&at, k.fn));
+    if (!lds_fits(k.dyn, at.sharedSizeBytes, pl.lds_limit)) {
+      char msg[256];
+      snprintf(msg, sizeof msg, "%s needs %zu + %zu bytes of LDS, above the "
+               "%zu a workgroup may allocate", k.name, k.dyn,
+               (size_t)at.sharedSizeBytes, pl.lds_limit);
+      return bfail(COMPASS_E_UNSUPPORTED, msg);
+    }
+  }
+  return COMPASS_OK;
 }
 
 static compass_status apply_tune(compass_batch_plan_s &pl,
                                  const compass_tune &t) {
   std::vector<BatchItem> items;
   pl.lds = make_items(pl, t, items);
-  if (pl.lds > 160 * 1024)
-    return bfail(COMPASS_E_UNSUPPORTED, "LDS need exceeds 160 KiB");
-  compass_status s = upload_plan(pl, items);
+  compass_status s = check_lds(pl);
+  if (s != COMPASS_OK) return s;
+  s = upload_plan(pl, items);
   if (s != COMPASS_OK) return s;
   int bpc = std::max(1, t.blocks_per_cu);
   if (pl.lds * bpc > 160 * 1024) bpc = 1;
@@ -827,6 +881,8 @@ static compass_status autotune(compass_batch_plan_s &pl, hipStream_t st,
   BHIP(hipEventCreate(&b));
   float best = 1e30f;
   compass_tune bt{};
+  compass_status last_fail = COMPASS_OK;
+  std::string last_msg;
   for (int64_t rpi : rpis)
     for (int32_t lb : budgets)
       for (int32_t bpc : bpcs) {
@@ -837,7 +893,11 @@ static compass_status autotune(compass_batch_plan_s &pl, hipStream_t st,
           if ((size_t)w * 4 > (size_t)lb) fits = false;
         if (!fits) continue;
         compass_status s = apply_tune(pl, t);
-        if (s != COMPASS_OK) continue;
+        if (s != COMPASS_OK) {
+          last_fail = s;
+          last_msg = compass_last_error();
+          continue;
+        }
         enqueue(pl, st);  // warm
         BHIP(hipEventRecord(a, st));
         enqueue(pl, st);
@@ -852,7 +912,10 @@ static compass_status autotune(compass_batch_plan_s &pl, hipStream_t st,
       }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  if (best >= 1e30f) return bfail(COMPASS_E_UNSUPPORTED, "no tile fits");
+  if (best >= 1e30f)
+    return last_fail != COMPASS_OK ? bfail(last_fail, last_msg)
+                                   : bfail(COMPASS_E_UNSUPPORTED, "no tile fits");
+  compass::set_last_error("");
   *best_out = bt;
   return COMPASS_OK;
 }
@@ -860,6 +923,7 @@ static compass_status autotune(compass_batch_plan_s &pl, hipStream_t st,
 extern "C" compass_status compass_batch_plan_create(
     const compass_build_job *jobs, int32_t n_jobs, int32_t counter_bits,
     const compass_tune *tune, hipStream_t stream, compass_batch_plan *out) {
+  compass::set_last_error("");
   if (!out || (n_jobs > 0 && !jobs))
     return bfail(COMPASS_E_ARG, "null pointer argument");
   *out = nullptr;
@@ -955,6 +1019,13 @@ extern "C" compass_status compass_batch_plan_create(
       hipGetDeviceProperties(&prop, pl->device) != hipSuccess)
     return cleanup(bfail(COMPASS_E_HIP, "device query failed"));
   pl->n_cu = prop.multiProcessorCount;
+  // LDS per workgroup: the device's, or a smaller COMPASS_LDS_LIMIT_BYTES
+  // (lets a test force the guard without launching anything)
+  pl->lds_limit = prop.sharedMemPerBlock;
+  if (const char *e = getenv("COMPASS_LDS_LIMIT_BYTES")) {
+    const long long v = atoll(e);
+    if (v > 0 && (size_t)v < pl->lds_limit) pl->lds_limit = (size_t)v;
+  }
   if (pl->jobs.empty()) {
     *out = pl;
     return COMPASS_OK;
@@ -971,7 +1042,7 @@ extern "C" compass_status compass_batch_plan_create(
       compass_status s = autotune(*pl, stream, &found);
       if (s != COMPASS_OK) return cleanup(s);
       t = found;
-      cache_store(key, t);
+      (void)cache_store(key, t);  // a failure is reported, not fatal
     }
   }
   compass_status s = apply_tune(*pl, t);

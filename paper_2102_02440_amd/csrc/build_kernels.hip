@@ -12,10 +12,11 @@
 //    group of slices whose int32 partial counters fit in LDS (privatised
 //    sketch, as the paper's per-warp replicas, but one per workgroup) and
 //    a contiguous chunk of table rows.
-//  * Rows are read in coalesced 4-byte columns, 4096 rows per tile
-//    (1024 lanes x 4).  Predicates are evaluated per row; survivors are
-//    compacted with a wave ballot + mbcnt prefix into an LDS queue of row
-//    offsets, so hashing runs on dense waves even at 0.1% selectivity.
+//  * Rows are read in coalesced 4-byte columns, 8192 rows per tile
+//    (1024 lanes x 8) in the fused scan.  Where a scan has predicates they
+//    are evaluated per row and survivors are compacted with a wave ballot +
+//    mbcnt prefix into an LDS queue of row offsets, so hashing runs on
+//    dense waves even at 0.1% selectivity.
 //  * Each survivor's key is turned into its field element once per sketch;
 //    the d row hashes then use wave-uniform seeds (scalar registers) and a
 //    fire-and-forget ds_add into LDS.
@@ -24,11 +25,13 @@
 //    addition is order-independent, so the result is bit-exact whatever
 //    the schedule (Section 2: sketches of partitions add up to the sketch
 //    of the whole).
-//  * Block -> (chunk, group) with the group varying fastest, so the groups
-//    that re-read one chunk's columns are dispatched together and share it
-//    through the Infinity Cache.
+//  * Block -> (chunk, group) pairs are numbered XCD by XCD (the hardware
+//    deals workgroup b to XCD b mod 8), so the slice groups that re-read one
+//    chunk's key columns run on one XCD and share them through its L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "build_params.hpp"
 #include "device_math.hpp"
@@ -210,14 +213,24 @@ __device__ __forceinline__ int64_t active_chunks(int64_t n, int64_t chunks) {
   return need < 1 ? 1 : (need < chunks ? need : chunks);
 }
 
+// A flush (hashing of the survivors buffered so far, then the slab
+// reduction) runs when it is forced (last batch of a build) or when the
+// next batch's rows might not fit the buffer: count + need > cap.  Every
+// workgroup of both kernels reads the same count, so the decision is
+// uniform over the launch.
+__device__ __forceinline__ bool flush_due(const FlushCtl &f, int64_t n) {
+  return f.force || n + f.need > f.cap;
+}
+
 __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
-    const uint64_t *__restrict__ surv, int64_t cap,
-    const unsigned long long *__restrict__ count,
+    const uint64_t *__restrict__ surv, FlushCtl fc,
     const RowSeeds *__restrict__ seeds, BucketMod bm, int32_t d,
     int32_t n_slices, int32_t ranges, int32_t chunks,
     int32_t *__restrict__ slab) {
   extern __shared__ uint32_t pairs[];
-  const int64_t n = (int64_t)*count;
+  const int64_t n = (int64_t)*fc.count;
+  if (!flush_due(fc, n)) return;  // the buffer takes the next batch
+  const int64_t cap = fc.cap;
   const int64_t act = active_chunks(n, chunks);
   // The act * n_slices * ranges items that carry work are numbered with
   // the slice fastest and split into kXcds contiguous runs, one per XCD
@@ -357,11 +370,10 @@ hipError_t launch_wide_compact(const BuildParams &P, uint64_t *surv,
   return hipGetLastError();
 }
 
-hipError_t launch_wide_hash(const uint64_t *surv, int64_t cap,
-                            const void *count, const void *seeds,
-                            const BucketMod &bm, int d, int n_slices,
-                            int ranges, int chunks, int32_t *slab,
-                            hipStream_t st) {
+hipError_t launch_wide_hash(const uint64_t *surv, const FlushCtl &fc,
+                            const void *seeds, const BucketMod &bm, int d,
+                            int n_slices, int ranges, int chunks,
+                            int32_t *slab, hipStream_t st) {
   const int w = (int)bm.w;
   const int wr = (w + ranges - 1) / ranges;
   if (wr > kWideRange) return hipErrorInvalidValue;  // 16-bit pairs, 128 KiB
@@ -370,8 +382,7 @@ hipError_t launch_wide_hash(const uint64_t *surv, int64_t cap,
   const int items = n_slices * ranges * chunks;
   const int grid = (items + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(wide_hash_kernel, dim3(grid),
-                     dim3(kBuildThreads), lds, st, surv, cap,
-                     reinterpret_cast<const unsigned long long *>(count),
+                     dim3(kBuildThreads), lds, st, surv, fc,
                      reinterpret_cast<const RowSeeds *>(seeds), bm, d,
                      n_slices, ranges, chunks, slab);
   return hipGetLastError();
@@ -388,9 +399,14 @@ __global__ void slab_reduce_kernel(const int32_t *__restrict__ slab,
                                    int64_t chunks, int32_t n_slices, int32_t d,
                                    int32_t w, CounterList cl,
                                    int32_t counter_bits, int32_t accumulate,
-                                   const unsigned long long *survivors) {
-  // two-phase builds: only the chunks wide_hash_kernel filled
-  if (survivors) chunks = active_chunks((int64_t)*survivors, chunks);
+                                   FlushCtl fc) {
+  // two-phase builds: a flush reduces only the chunks wide_hash_kernel
+  // filled, and its last workgroup empties the survivor buffer
+  if (fc.count) {
+    const int64_t n = (int64_t)*fc.count;
+    if (!flush_due(fc, n)) return;
+    chunks = active_chunks(n, chunks);
+  }
   const int64_t total = (int64_t)n_slices * w;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
        k += (int64_t)gridDim.x * blockDim.x) {
@@ -417,24 +433,58 @@ __global__ void slab_reduce_kernel(const int32_t *__restrict__ slab,
       g[idx] = (accumulate ? g[idx] : 0) + acc;
     }
   }
+  if (fc.count) {
+    // every workgroup has read the count before it takes a ticket; the
+    // last one resets the count (and the ticket) for the next batch
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const unsigned t = atomicAdd(fc.ticket, 1u);
+      if (t == gridDim.x - 1) {
+        atomicExch(fc.count, 0ull);
+        atomicExch(fc.ticket, 0u);
+      }
+    }
+  }
 }
 
 hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
                               int n_slices, int d, int w,
                               void *const *counters, int n_sketches,
                               int counter_bits, int accumulate,
-                              const unsigned long long *survivors,
-                              hipStream_t st) {
+                              const FlushCtl &fc, hipStream_t st) {
   CounterList cl;
   for (int s = 0; s < kMaxSketches; ++s)
     cl.p[s] = s < n_sketches ? counters[s] : nullptr;
   const int64_t total = (int64_t)n_slices * w;
   int64_t blocks = (total + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  if (blocks > 2048) blocks = 2048;
   hipLaunchKernelGGL(slab_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      st, slab, chunks, n_slices, d, w, cl, counter_bits,
-                     accumulate, survivors);
+                     accumulate, fc);
   return hipGetLastError();
+}
+
+// Seeds of the two-phase build's slices to device memory, written by a
+// kernel from its arguments (no host staging buffer).
+__global__ void store_seeds_kernel(SeedBlock b, RowSeeds *__restrict__ dst) {
+  const int i = threadIdx.x;
+  if (i < b.n) dst[b.first + i] = b.s[i];
+}
+
+hipError_t launch_store_seeds(const RowSeeds *src, int n, RowSeeds *dst,
+                              hipStream_t st) {
+  for (int a = 0; a < n; a += kSeedBlock) {
+    SeedBlock b;
+    b.first = a;
+    b.n = std::min(kSeedBlock, n - a);
+    for (int k = 0; k < b.n; ++k) b.s[k] = src[a + k];
+    hipLaunchKernelGGL(store_seeds_kernel, dim3(1), dim3(kSeedBlock), 0, st, b,
+                       dst);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // zero-fill used instead of hipMemsetAsync so that callers may capture the

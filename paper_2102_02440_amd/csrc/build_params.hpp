@@ -95,4 +95,25 @@ struct BuildParams {
 
 static_assert(sizeof(BuildParams) <= 4096, "kernel arguments must stay small");
 
+// Survivor buffer of the two-phase build and when to empty it: the hashing
+// and the slab reduction after a batch run only when `force` is set or
+// count + need > cap (the next batch of `need` rows might not fit); the
+// reduction's last workgroup then sets count (and ticket) back to 0.
+struct FlushCtl {
+  unsigned long long *count;   // survivors in the buffer (device)
+  unsigned int *ticket;        // workgroups of the reduction done (device)
+  int64_t cap;                 // survivors the buffer holds per sketch
+  int64_t need;                // rows of the next batch
+  int32_t force;
+  int32_t pad;
+};
+
+// A run of slice seeds written to device memory by one small launch.
+constexpr int kSeedBlock = 64;
+struct SeedBlock {
+  int32_t first, n;
+  RowSeeds s[kSeedBlock];
+};
+static_assert(sizeof(SeedBlock) <= 4096, "kernel arguments must stay small");
+
 }  // namespace compass

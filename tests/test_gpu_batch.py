@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2102_02440_amd import workloads as W
+from tests.shapes import supported_shape
 
 gpu = pytest.mark.gpu
 
@@ -120,6 +121,9 @@ def test_batch_estimates_match_oracle(oracle):
         got = C.row_values(row_est)
         fl = flags.cpu().numpy()
         for m in range(len(masks)):
+            sup = supported_shape(eu, ev, masks[m])
+            if sup is not None:
+                assert bool(fl[m] & C.FLAG_UNSUPPORTED) == (not sup), hex(masks[m])
             if fl[m] & C.FLAG_UNSUPPORTED:
                 continue
             assert got[m] == [v & ((1 << 128) - 1) for v in vals[m]]

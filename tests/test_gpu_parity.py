@@ -2,10 +2,13 @@
 
 Every case prints its name, seed and shape before touching the GPU.
 """
+import os
+
 import numpy as np
 import pytest
 
 from paper_2102_02440_amd import workloads as W
+from tests.shapes import supported_shape
 
 gpu = pytest.mark.gpu
 
@@ -57,6 +60,9 @@ def check_query(oracle, q, masks=None, name=""):
     vals_g = C.row_values(row_est)
     fl = flags.cpu().numpy()
     for m in range(len(masks)):
+        sup = supported_shape(q.edge_u, q.edge_v, masks[m])
+        if sup is not None:
+            assert bool(fl[m] & C.FLAG_UNSUPPORTED) == (not sup), "mask 0x%x" % masks[m]
         if fl[m] & C.FLAG_UNSUPPORTED:
             continue
         go = [v & ((1 << 128) - 1) for v in vals_o[m]]
@@ -312,13 +318,12 @@ def test_triangle_run_order(oracle, shape):
 @gpu
 def test_job6a_full_size(oracle):
     """Full-size 6a-shaped workload (ci 36M, mk 4.5M, t 2.5M, n 4.2M, k 134k;
-    d=7, w=8192) in the launch configuration the benchmark times.
-    Exact oracle comparison for the sketches of k, mk, t, n and the selected
-    counts; for ci (756M hash updates) exact comparison on a 1M-row slice
-    plus properties that hold at any size: linearity across launches with a
-    different chunking, sum of a row == n_sel (mod 2), L1 of a row <= n_sel.
-    Estimates: every tree sub-plan on all rows; the four triangle sub-plans
-    on sampled rows 0 and 6 (the oracle costs ~w^2 per row there)."""
+    d=7, w=8192) in the launch configuration the benchmark times: every
+    sketch of every table (ci's 756M hash updates included) element by
+    element against the oracle's (multi-threaded, private counters summed),
+    the selected counts, and all 19 sub-plans on all 7 rows (the four with
+    the triangle too), their medians and flags.  Also linearity across
+    launches with a different chunking of ci."""
     torch = _torch()
     from paper_2102_02440_amd import compass as C
     q = W.job6a()
@@ -326,27 +331,15 @@ def test_job6a_full_size(oracle):
     dq = C.DeviceQuery(q)
     dq.build()
     torch.cuda.synchronize()
-    n_sel = []
-    side_sk = [None] * (2 * len(q.edges))
-    for t, tb in enumerate(q.tables):
-        mask = oracle.eval_predicates(tb.cols, tb.preds)
-        n_sel.append(int(mask.sum()))
-        if tb.name == "ci":
-            continue
-        for (e, side, c) in q.incident(t):
-            side_sk[2 * e + side] = oracle.sketch(tb.cols[c][mask], q.seeds[e], q.d, q.w)
-            g = dq.sketch_of_side[2 * e + side].cpu().numpy().astype(np.int64)
-            assert np.array_equal(g, side_sk[2 * e + side]), (tb.name, e)
+    side_sk, n_sel = oracle_query(oracle, q)
     assert dq.n_selected.cpu().tolist() == n_sel
+    for k, (g, o) in enumerate(zip(dq.sketch_of_side, side_sk)):
+        assert np.array_equal(g.cpu().numpy().astype(np.int64), o), "side %d" % k
+    # linearity across launches: ci in three slices accumulated into new
+    # counters equals the one-call build
     ci = 3
     tb = q.tables[ci]
     inc = q.incident(ci)
-    for (e, side, c) in inc:
-        g = dq.sketch_of_side[2 * e + side].cpu().numpy().astype(np.int64)
-        assert np.all(g.sum(axis=1) % 2 == n_sel[ci] % 2)
-        assert np.all(np.abs(g).sum(axis=1) <= n_sel[ci])
-        side_sk[2 * e + side] = g
-    # linearity across launches: three slices accumulated into new counters
     keys = [dq.tables[ci]["keys"][k] for k in range(len(inc))]
     acc = [torch.zeros_like(dq.tables[ci]["counters"][k]) for k in range(len(inc))]
     nacc = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -358,37 +351,22 @@ def test_job6a_full_size(oracle):
     torch.cuda.synchronize()
     for k in range(len(inc)):
         assert torch.equal(acc[k], dq.tables[ci]["counters"][k])
-    # exact oracle check of the first slice (1M rows), built alone
-    part = [torch.zeros_like(x) for x in acc]
-    C.sketch_build(1_000_000, [], [], [k[:1_000_000] for k in keys],
-                   [q.seeds[e] for (e, _, _) in inc], part, nacc, q.d, q.w)
-    torch.cuda.synchronize()
-    for k, (e, _, c) in enumerate(inc):
-        o = oracle.sketch(tb.cols[c][:1_000_000], q.seeds[e], q.d, q.w)
-        assert np.array_equal(part[k].cpu().numpy().astype(np.int64), o)
-    # estimates
+    assert nacc.item() == tb.n_rows
+    # estimates: all sub-plans, all rows
     masks = oracle.connected_subplans(5, q.edge_u, q.edge_v)
+    assert len(masks) == 19
     row_est, est, flags = dq.estimate(masks)
     torch.cuda.synchronize()
     got = C.row_values(row_est)
     fl = flags.cpu().numpy()
     assert not np.any(fl & C.FLAG_UNSUPPORTED)
-    tri = [m for m in masks if (m & 0b1110) == 0b1110]
-    trees = [m for m in masks if m not in tri]
     vals, e_o, f_o = oracle.estimate(5, q.edge_u, q.edge_v, q.d, q.w, side_sk,
-                                     n_sel, trees)
-    for m, v in zip(trees, vals):
-        assert got[masks.index(m)] == [x & ((1 << 128) - 1) for x in v], hex(m)
-    for m, e in zip(trees, e_o):
-        assert est.cpu().numpy()[masks.index(m)] == e
-    for row in (0, q.d - 1):
-        sk1 = [s[row:row + 1] for s in side_sk]
-        v1, _, _ = oracle.estimate(5, q.edge_u, q.edge_v, 1, q.w, sk1, n_sel, tri)
-        for m, v in zip(tri, v1):
-            assert got[masks.index(m)][row] == v[0] & ((1 << 128) - 1), (hex(m), row)
-    assert np.array_equal(fl, np.asarray(
-        oracle.estimate(5, q.edge_u, q.edge_v, 1, 1,
-                        [np.zeros((1, 1), np.int64)] * 10, n_sel, masks)[2]))
+                                     n_sel, masks)
+    e_g = est.cpu().numpy()
+    for m in range(len(masks)):
+        assert got[m] == [x & ((1 << 128) - 1) for x in vals[m]], hex(masks[m])
+        assert e_g[m] == e_o[m], hex(masks[m])
+        assert fl[m] == f_o[m], hex(masks[m])
 
 
 @gpu
@@ -429,10 +407,12 @@ def test_wide_sketches_direct_path(oracle, w, bits):
 def test_large_scan_full_size(oracle):
     """1B-row fact table (6 int64 Zipf(1.1) keys over 50M, 4 range
     predicates, 1% combined; d=11, w=65536, int64 counters) in the launch
-    configuration the benchmark times.  Exact oracle comparison on a 2M-row
-    slice built alone; on the whole table: the selected count against a
-    torch mask count, linearity across three launches with accumulate,
-    sum of a row == n_sel (mod 2), L1 of a row <= n_sel."""
+    configuration the benchmark times (batches of rows compacted into the
+    survivor buffer, one hashing pass).  The oracle evaluates the predicates
+    on the host over the whole table (columns copied back in chunks), the
+    qualifying rows' keys are copied back by index, and all six sketches
+    are compared element by element with the oracle's; plus linearity
+    across three launches with accumulate."""
     torch = _torch()
     from paper_2102_02440_amd import compass as C
     n = 1_000_000_000
@@ -448,15 +428,23 @@ def test_large_scan_full_size(oracle):
     pc = [cols[c] for c in names]
     C.sketch_build(n, pc, pd, keys, list(seeds), cnt, nsel, d, w, counter_bits=64)
     torch.cuda.synchronize()
-    m = ((cols["i0"] <= 316_227) & (cols["i1"] <= 316_227) &
-         (cols["f0"] >= 0.0) & (cols["f0"] <= 0.316227) &
-         (cols["f1"] >= 0.0) & (cols["f1"] <= 0.316227))
-    ns = int(m.sum().item())
-    del m
-    assert nsel.item() == ns
-    for c in cnt:
-        assert torch.all(c.sum(dim=1) % 2 == ns % 2)
-        assert torch.all(c.abs().sum(dim=1) <= ns)
+    # the oracle's selection over the whole table, chunk by chunk
+    idx = []
+    step = 1 << 26
+    for a in range(0, n, step):
+        b = min(n, a + step)
+        host = {c: cols[c][a:b].cpu().numpy() for c in names}
+        idx.append(np.flatnonzero(oracle.eval_predicates(host, preds)) + a)
+    idx = np.concatenate(idx)
+    _say("large scan: oracle selected", idx.size)
+    assert nsel.item() == idx.size
+    it = torch.from_numpy(idx).cuda()
+    for k in range(6):
+        kh = keys[k].index_select(0, it).cpu().numpy()
+        o = oracle.sketch(kh, seeds[k], d, w)
+        assert np.array_equal(cnt[k].cpu().numpy(), o), k
+    del it
+    # linearity across launches
     acc = [torch.zeros_like(c) for c in cnt]
     n2 = torch.zeros(1, dtype=torch.int64, device="cuda")
     cuts = [0, 333_333_331, 700_000_000, n]
@@ -464,23 +452,70 @@ def test_large_scan_full_size(oracle):
         C.sketch_build(b - a, [x[a:b] for x in pc], pd, [k[a:b] for k in keys],
                        list(seeds), acc, n2, d, w, counter_bits=64, accumulate=True)
     torch.cuda.synchronize()
-    assert n2.item() == ns
+    assert n2.item() == idx.size
     for a_, c in zip(acc, cnt):
         assert torch.equal(a_, c)
-    # exact oracle check of a 2M-row slice
-    a0, b0 = 123_456_789, 125_456_789
-    part = [torch.zeros_like(c) for c in cnt]
-    C.sketch_build(b0 - a0, [x[a0:b0] for x in pc], pd, [k[a0:b0] for k in keys],
-                   list(seeds), part, n2, d, w, counter_bits=64)
-    torch.cuda.synchronize()
-    host = {c: cols[c][a0:b0].cpu().numpy() for c in names}
-    mask = oracle.eval_predicates(host, preds)
-    assert n2.item() == int(mask.sum())
-    for k in range(6):
-        o = oracle.sketch(keys[k][a0:b0].cpu().numpy()[mask], seeds[k], d, w)
-        assert np.array_equal(part[k].cpu().numpy(), o)
     del cols, keys, pc
     torch.cuda.empty_cache()
+
+
+def _with_env(name, value, fn):
+    old = os.environ.get(name)
+    os.environ[name] = str(value)
+    try:
+        return fn()
+    finally:
+        if old is None:
+            del os.environ[name]
+        else:
+            os.environ[name] = old
+
+
+@gpu
+@pytest.mark.parametrize("w,bits,pattern", [
+    (65536, 64, "uniform"), (65536, 32, "bursts"), (1024, 32, "bursts"),
+    (40000, 64, "uniform"), (8192, 32, "all_then_none")])
+def test_two_phase_many_batches(oracle, w, bits, pattern):
+    """The two-phase build with its survivor buffer capped at 98,304 rows
+    (batches of 49,152 rows): many compaction batches, and flushes
+    (hashing + reduction) whenever the next batch might not fit, at points
+    that depend on how many rows qualified so far: uniform 40%
+    selectivity, bursts (whole batches qualifying, then almost none), and
+    every row qualifying in the first half, none in the second.  Counters
+    and selected count element by element against the oracle."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(w + bits + len(pattern))
+    n = 1_500_007
+    d = 5
+    keys = [W.fk_column(rng, n, 200_000, 1.1, rng.permutation(200_000)).astype(np.int64),
+            rng.integers(-2**40, 2**40, n).astype(np.int64)]
+    if pattern == "uniform":
+        a = rng.integers(0, 100, n).astype(np.int32)
+    elif pattern == "bursts":
+        a = np.where((np.arange(n) // 150_000) % 2 == 0,
+                     rng.integers(0, 40, n), rng.integers(39, 100, n)).astype(np.int32)
+    else:
+        a = np.where(np.arange(n) < n // 2, 0, 99).astype(np.int32)
+    preds = [{"col": 0, "kind": "range", "lo": 0, "hi": 39}]
+    seeds = [W.draw_seeds(rng, 1, d)[0] for _ in keys]
+    cdt = torch.int64 if bits == 64 else torch.int32
+    cnt = [torch.full((d, w), 3, dtype=cdt, device="cuda") for _ in keys]
+    nsel = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _say("two-phase batches", w, bits, pattern)
+
+    def run():
+        C.sketch_build(n, [torch.from_numpy(a).cuda()], preds,
+                       [torch.from_numpy(k).cuda() for k in keys], seeds, cnt, nsel,
+                       d, w, counter_bits=bits)
+        torch.cuda.synchronize()
+
+    _with_env("COMPASS_SURVIVOR_CAP_ROWS", 100_000, run)
+    mask = (a >= 0) & (a <= 39)
+    assert nsel.item() == int(mask.sum())
+    for i, (k, c) in enumerate(zip(keys, cnt)):
+        o = oracle.sketch(k[mask], seeds[i], d, w)
+        assert np.array_equal(c.cpu().numpy().astype(np.int64), o), i
 
 
 @gpu

@@ -185,9 +185,9 @@ def test_chain3_empty_selection(oracle):
 @gpu
 def test_chain3_6a_shape_full_width(oracle):
     """The 6a-shaped chain k - mk - t at its full size and width
-    (mk 4.5M rows, w1 = w2 = 8192, d = 7): GPU rows 0 and 6 of the
-    partitioned sketch against the oracle's sketch of those rows (seeds of
-    one row, d = 1), and their chain row values."""
+    (mk 4.5M rows, w1 = w2 = 8192, d = 7): every row of the partitioned
+    sketch against the oracle's sketch of that row (seeds of one row,
+    d = 1), every chain row value, and the median and flag."""
     torch = _torch()
     from paper_2102_02440_amd import compass as C
     q = W.job6a(seed=W.DEFAULT_SEED, scale=1.0)
@@ -229,7 +229,8 @@ def test_chain3_6a_shape_full_width(oracle):
     k_keys = k.cols["id"][oracle.eval_predicates(k.cols, k.preds)]
     t_keys = t.cols["id"][oracle.eval_predicates(t.cols, t.preds)]
     assert npp.item() == int(mk_mask.sum())
-    for i in (0, d - 1):
+    vals_o = []
+    for i in range(d):
         Po = oracle.sketch2d(mk.cols["keyword"][mk_mask], mk.cols["movie"][mk_mask],
                              s_e0[i:i + 1], s_e1[i:i + 1], 1, w, w)
         assert np.array_equal(P[i].cpu().numpy().astype(np.int64), Po[0]), i
@@ -237,3 +238,10 @@ def test_chain3_6a_shape_full_width(oracle):
         Bo = oracle.sketch(t_keys, s_e1[i:i + 1], 1, w)
         v, _, _ = oracle.chain3(Ao, Po, Bo, [k_keys.size, int(mk_mask.sum()), t_keys.size])
         assert vals_g[i] == v[0] & ((1 << 128) - 1), i
+        vals_o.append(v[0])
+        del Po
+    # median (odd d: the middle row value) and certificate
+    mid = sorted(vals_o)[d // 2]
+    assert est.item() == oracle.i128_to_double(mid)
+    ns = [k_keys.size, int(mk_mask.sum()), t_keys.size]
+    assert flags.item() == (1 if ns[0] * ns[1] * ns[2] < 2**127 else 0)

@@ -110,8 +110,9 @@ def test_sketch_linearity(oracle):
     whole = oracle.sketch(np.concatenate([a, b]), seeds, 5, 37)
     assert np.array_equal(whole, oracle.sketch(a, seeds, 5, 37) +
                           oracle.sketch(b, seeds, 5, 37))
-    assert whole.sum(axis=1).tolist() != [0] * 5 or True
-    # every row has the same total count in absolute terms bound
+    # a row's counters sum to the number of keys mod 2 (each key adds +-1)
+    assert np.all(whole.sum(axis=1) % 2 == 5000 % 2)
+    # and their absolute values sum to at most the number of keys
     assert np.all(np.abs(whole).sum(axis=1) <= 5000)
 
 
@@ -389,3 +390,25 @@ def test_i128_rows_feature_reference(oracle):
     assert x[0] == -np.log1p(2.0**65) and x[6] == np.log1p(2.0**70)
     assert x[7] == np.log2(1001.0) and x[9] == np.log2(4.0) and x[10] == 0.0
     assert base == np.log1p(99.5)
+
+
+def test_feature_positions_odd_d(oracle):
+    """The 7 order statistics of the learned model's features sit at
+    positions round(k (d - 1) / 6), k = 0..6, of the sorted row values.
+    Written out by hand: d = 5 -> rows 0, 1, 1, 2, 3, 3, 4 (k = 1: 0.67 -> 1,
+    k = 2: 1.33 -> 1, k = 4: 2.67 -> 3, k = 5: 3.33 -> 3); d = 11 -> rows 0, 2,
+    3, 5, 7, 8, 10 (1.67 -> 2, 3.33 -> 3, 6.67 -> 7, 8.33 -> 8).  Rows are
+    given unsorted; the values are chosen so each position is identified."""
+    rows5 = [40, -7, 300, 2, 5000]            # sorted: -7, 2, 40, 300, 5000
+    x, _ = oracle.mlp_features(rows5, 1.0, [1], [0, 0, 0, 0, 0])
+    want = [-7, 2, 2, 40, 300, 300, 5000]
+    for k, v in enumerate(want):
+        ref = -np.log1p(-v) if v < 0 else np.log1p(v)
+        assert x[k] == ref, (k, x[k], v)
+    rows11 = [9, 1, -4, 100, 3, 0, 27, 81, -30, 243, 729]
+    # sorted: -30, -4, 0, 1, 3, 9, 27, 81, 100, 243, 729
+    x, _ = oracle.mlp_features(rows11, 1.0, [1], [0, 0, 0, 0, 0])
+    want = [-30, 0, 1, 9, 81, 100, 729]
+    for k, v in enumerate(want):
+        ref = -np.log1p(-v) if v < 0 else np.log1p(v)
+        assert x[k] == ref, (k, x[k], v)
