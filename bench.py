@@ -888,6 +888,38 @@ def run_select(args):
     print(json.dumps(out), flush=True)
 
 
+def plan_quality(q, masks, est, n_sel, true):
+    """Algorithm 1 on the step's GPU estimates in the four search spaces of
+    Section 7.2.8; each chosen left-deep plan scored by its true cost (sum
+    of the exact sizes of its prefixes) against the optimum of exhaustive
+    search over the exact sizes."""
+    from paper_2102_02440_amd import compass as C
+    true_of = dict(zip(masks, true))
+    card = [float(x) for x in n_sel]
+    eu, ev = q.edge_u, q.edge_v
+    n = len(q.tables)
+
+    def true_cost(order):
+        m, c = 0, 0.0
+        for v in order:
+            m |= 1 << v
+            c += true_of[m]
+        return c
+
+    opt_order, opt_cost, _ = C.enumerate_plan(n, eu, ev, masks, true, card, max_plans=0)
+    out = {"optimal": {"order": [q.tables[v].name for v in opt_order],
+                       "true_cost": opt_cost}}
+    for name, _ in C.ENUM_VARIANTS:
+        a = time.perf_counter()
+        order, cost = C.enumerate_variant(name, n, eu, ev, masks, list(est), card)
+        us = (time.perf_counter() - a) * 1e6
+        tc = true_cost(order)
+        out[name] = {"order": [q.tables[v].name for v in order], "est_cost": cost,
+                     "true_cost": tc, "true_cost_over_optimal": tc / opt_cost,
+                     "host_us": us}
+    return out
+
+
 def run_job6a(args):
     import numpy as np
     import torch
@@ -980,6 +1012,7 @@ def run_job6a(args):
                            "achieved_gbs": sel_bytes / two_s / 1e9 if two_s else None}}
     # accuracy against stored exact truths (oracle hash aggregation)
     qerr = None
+    plans = None
     tp = os.path.join(ROOT, "tests", "golden", "job6a_truth.json")
     if os.path.exists(tp):
         tr = json.load(open(tp))
@@ -989,6 +1022,8 @@ def run_job6a(args):
             qe = np.maximum(e / t, t / e)
             qerr = {"median": float(np.median(qe)), "p90": float(np.percentile(qe, 90)),
                     "max": float(qe.max())}
+            plans = plan_quality(q, masks, est.cpu().numpy().astype(np.float64),
+                                 n_sel, tr["true"])
     out = {
         "metric": METRIC,
         "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
@@ -1005,6 +1040,7 @@ def run_job6a(args):
         "estimate_ms_per_step": est_ms_step,
         "subplan_estimates_per_s": len(masks) / (est_ms_step / 1e3) if est_ms_step else None,
         "qerror": qerr,
+        "plan_enumeration": plans,
         "kernel_ms_per_step": kernel_ms,
         "roofline": roofline,
         "kernel_rooflines": other,

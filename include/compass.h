@@ -447,6 +447,22 @@ compass_status compass_enumerate(int32_t n_tables, int32_t n_edges,
                                  int32_t *order_out, double *cost_out,
                                  int64_t *n_plans_out);
 
+/* compass_enumerate_greedy -- the greedy variant, the paper's default
+ * (Section 7.1, defined in Section 7.2.8): one source only, the smaller
+ * table (by card; ties to the lower id) of the two-table sub-plan with the
+ * smallest estimate (ties to the lower mask), then the left-deep order
+ * grows by the adjacent table whose extended sub-plan has the smallest
+ * estimate (ties to the lower id), without backtracking.  Same inputs and
+ * outputs as compass_enumerate; *cost_out = sum of the estimates of every
+ * prefix.  (full-greedy, limit-10 and exhaustive are compass_enumerate with
+ * max_plans 1, 10 and 0.) */
+compass_status compass_enumerate_greedy(int32_t n_tables, int32_t n_edges,
+                                        const int32_t *edge_u,
+                                        const int32_t *edge_v,
+                                        const uint64_t *masks, const double *est,
+                                        int32_t n_masks, const double *card,
+                                        int32_t *order_out, double *cost_out);
+
 /* Kernel timing for measurement: while enabled, the library records a pair
  * of HIP events on the launch stream around each kernel launch it makes.
  * compass_profile_take(name) waits for the recorded events of kernel `name`

@@ -577,6 +577,47 @@ def mlp_init(seed: int, dims=MLP_DIMS) -> np.ndarray:
     return np.concatenate(flat)
 
 
+def plan_greedy(n_tables, edge_u, edge_v, est_of, card):
+    """The greedy search of Section 7.2.8 (the default of Section 7.1):
+    start from the smaller table (by card; ties to the lower id) of the
+    two-way join with the smallest estimate (ties to the lower mask), then
+    repeatedly append the not-yet-joined table adjacent to the order whose
+    extended sub-plan has the smallest estimate (ties to the lower id).
+    Returns (order, cost) with cost = sum of the estimates of every prefix."""
+    adj = [set() for _ in range(n_tables)]
+    for u, v in zip(edge_u, edge_v):
+        adj[u].add(v)
+        adj[v].add(u)
+    if n_tables == 1:
+        return [0], est_of[1]
+    pairs = sorted({(min(u, v), max(u, v)) for u, v in zip(edge_u, edge_v)})
+    best = min(pairs, key=lambda p: (est_of[(1 << p[0]) | (1 << p[1])],
+                                     (1 << p[0]) | (1 << p[1])))
+    u, v = best
+    order = [v] if card[v] < card[u] else [u]
+    mask = 1 << order[0]
+    cost = est_of[mask]
+    while len(order) < n_tables:
+        cand = sorted({b for a in order for b in adj[a]} - set(order))
+        nxt = min(cand, key=lambda x: (est_of[mask | (1 << x)], x))
+        order.append(nxt)
+        mask |= 1 << nxt
+        cost += est_of[mask]
+    return order, cost
+
+
+def plan_cost(order, value_of):
+    """Cost of a left-deep order under any cardinality map: the sum over
+    its prefixes (one table, two, ..., all) of value_of[prefix mask].  With
+    exact join sizes this is the plan's true cost (the sum of its
+    intermediate result sizes, Section 2)."""
+    m, c = 0, 0.0
+    for v in order:
+        m |= 1 << v
+        c += float(value_of[m])
+    return c
+
+
 def true_cardinality_fk_tree(filtered_cols, edges, mask, domain_of):
     """Exact join size of a tree-shaped sub-plan whose every edge joins a
     foreign-key column to a dense primary key "id" in [0, domain) (the

@@ -190,10 +190,10 @@ def sketch_build(n_rows: int, pred_cols, preds, keys, seeds, counters,
         sarr[i].key_dtype = _dtype_code(keys[i])
         sarr[i].seeds = sd.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
         sarr[i].counters = counters[i].data_ptr()
-    _check(lib().compass_sketch_build(
-        int(n_rows), cols, ncol, parr, np_, sarr, ns, int(d), int(w),
-        int(counter_bits), 1 if accumulate else 0,
-        ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))
+    fn = lib().compass_sketch_build
+    _check(fn(int(n_rows), cols, ncol, parr, np_, sarr, ns, int(d), int(w),
+              int(counter_bits), 1 if accumulate else 0,
+              ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))
 
 
 def sketch_build_select(n_rows: int, pred_cols, preds, keys, seeds, counters,
@@ -828,3 +828,44 @@ def enumerate_plan(n_tables, edge_u, edge_v, masks, est, card, max_plans=10,
                                float(beta), order.ctypes.data, cost.ctypes.data,
                                npl.ctypes.data))
     return order.tolist(), float(cost[0]), int(npl[0])
+
+
+def enumerate_greedy(n_tables, edge_u, edge_v, masks, est, card):
+    """The greedy variant (one source: the smaller table of the two-table
+    sub-plan with the smallest estimate); returns (order, cost)."""
+    L = lib()
+    if not getattr(L, "_greedy_bound", False):
+        vp = ctypes.c_void_p
+        L.compass_enumerate_greedy.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                               vp, vp, ctypes.c_int32, vp, vp, vp]
+        L.compass_enumerate_greedy.restype = ctypes.c_int32
+        L._greedy_bound = True
+    ne = len(edge_u)
+    eu = np.ascontiguousarray(np.asarray(edge_u, dtype=np.int32))
+    ev = np.ascontiguousarray(np.asarray(edge_v, dtype=np.int32))
+    ms = np.ascontiguousarray(np.asarray(masks, dtype=np.uint64))
+    es = np.ascontiguousarray(np.asarray(est, dtype=np.float64))
+    cd = np.ascontiguousarray(np.asarray(card, dtype=np.float64))
+    order = np.zeros(n_tables, dtype=np.int32)
+    cost = np.zeros(1, dtype=np.float64)
+    _check(L.compass_enumerate_greedy(int(n_tables), ne, eu.ctypes.data, ev.ctypes.data,
+                                      ms.ctypes.data, es.ctypes.data, int(ms.size),
+                                      cd.ctypes.data, order.ctypes.data,
+                                      cost.ctypes.data))
+    return order.tolist(), float(cost[0])
+
+
+# The four search spaces of the paper's plan-enumeration experiment
+# (Section 7.2.8): name -> max_plans of Algorithm 1 (greedy: one source).
+ENUM_VARIANTS = (("greedy", None), ("full-greedy", 1), ("limit-10", 10),
+                 ("exhaustive", 0))
+
+
+def enumerate_variant(name, n_tables, edge_u, edge_v, masks, est, card):
+    """(order, estimated cost) of one of ENUM_VARIANTS."""
+    mp = dict(ENUM_VARIANTS)[name]
+    if mp is None:
+        return enumerate_greedy(n_tables, edge_u, edge_v, masks, est, card)
+    order, cost, _ = enumerate_plan(n_tables, edge_u, edge_v, masks, est, card,
+                                    max_plans=mp)
+    return order, cost

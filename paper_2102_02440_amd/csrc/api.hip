@@ -36,7 +36,7 @@ hipError_t launch_wide_compact(const BuildParams &P, uint64_t *surv,
 hipError_t launch_wide_hash(const uint64_t *surv, const FlushCtl &fc,
                             const void *seeds, const BucketMod &bm, int d,
                             int n_slices, int ranges, int chunks,
-                            int32_t *slab, hipStream_t st);
+                            int32_t *slab, int n_cu, hipStream_t st);
 hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
                               int n_slices, int d, int w,
                               void *const *counters, int n_sketches,
@@ -355,13 +355,13 @@ static compass_status build_two_phase(const BuildParams &base,
   uint64_t *surv = reinterpret_cast<uint64_t *>(c + pl.seeds_bytes + pl.ctl_bytes);
   int32_t *wslab = reinterpret_cast<int32_t *>(c + pl.seeds_bytes + pl.ctl_bytes +
                                                pl.surv_bytes);
-  std::vector<RowSeeds> sd(S);
+  RowSeeds sd[kMaxSketches * 32];  // S <= 16 sketches x 32 rows
   for (int s = 0; s < n_sketches; ++s)
     for (int i = 0; i < d; ++i) {
       const uint64_t *p = sketches[s].seeds + 6 * i;
       sd[s * d + i] = RowSeeds{p[0], p[1], p[2], p[3], p[4], p[5]};
     }
-  HIP_OK(launch_store_seeds(sd.data(), S, dseeds, stream));
+  HIP_OK(launch_store_seeds(sd, S, dseeds, stream));
   {
     ProfScope ps("fill_zero", stream);
     zs.add(count, 16);  // count and ticket
@@ -370,7 +370,7 @@ static compass_status build_two_phase(const BuildParams &base,
   BuildParams P = base;
   P.count_selected = 1;
   P.n_groups = n_sketches;
-  std::vector<void *> cp(n_sketches);
+  void *cp[kMaxSketches];
   for (int s = 0; s < n_sketches; ++s) cp[s] = sketches[s].counters;
   for (int64_t r0 = 0; r0 < n_rows; r0 += pl.batch) {
     const int64_t r1 = std::min(n_rows, r0 + pl.batch);
@@ -391,11 +391,11 @@ static compass_status build_two_phase(const BuildParams &base,
     {
       ProfScope ps("wide_hash", stream);
       HIP_OK(launch_wide_hash(surv, fc, dseeds, base.bm, d, S, pl.ranges,
-                              pl.chunks, wslab, stream));
+                              pl.chunks, wslab, n_cu, stream));
     }
     {
       ProfScope ps("slab_reduce", stream);
-      HIP_OK(launch_slab_reduce(wslab, pl.chunks, S, d, w, cp.data(), n_sketches,
+      HIP_OK(launch_slab_reduce(wslab, pl.chunks, S, d, w, cp, n_sketches,
                                 counter_bits, 1, fc, stream));
     }
   }
@@ -508,10 +508,6 @@ static compass_status sketch_build_impl(
   if (two_phase)
     return build_two_phase(base, sketches, n_sketches, d, w, counter_bits,
                            n_rows, zs, n_cu, ar, stream);
-  if (zs.n > 0) {
-    ProfScope ps("fill_zero", stream);
-    HIP_OK(launch_fill_zero_list(zs, stream));
-  }
 
   // slice groups: consecutive (sketch, row) slices whose int32 partials fit
   // the LDS budget; among the group sizes that fit, prefer one that splits
@@ -576,6 +572,10 @@ static compass_status sketch_build_impl(
   base.slab = reinterpret_cast<int32_t *>(slab);
   base.d = d;
   base.n_slices_total = S;
+  if (zs.n > 0) {
+    ProfScope ps("fill_zero", stream);
+    HIP_OK(launch_fill_zero_list(zs, stream));
+  }
 
   // launches: as many whole groups as the kernel-argument seed table holds
   int slice = 0;
@@ -614,12 +614,12 @@ static compass_status sketch_build_impl(
     HIP_OK(launch_scan_sketch(P, (int)blocks, lds, stream));
   }
   {
-    std::vector<void *> cp(n_sketches);
+    void *cp[kMaxSketches];
     for (int s = 0; s < n_sketches; ++s) cp[s] = sketches[s].counters;
     FlushCtl none;
     memset(&none, 0, sizeof none);
     ProfScope ps("slab_reduce", stream);
-    HIP_OK(launch_slab_reduce(base.slab, chunks, S, d, w, cp.data(), n_sketches,
+    HIP_OK(launch_slab_reduce(base.slab, chunks, S, d, w, cp, n_sketches,
                               counter_bits, accumulate, none, stream));
   }
   return COMPASS_OK;

@@ -240,123 +240,127 @@ __global__ __launch_bounds__(kBuildThreads) void wide_hash_kernel(
   const int64_t items = act * n_slices * ranges;
   const int xcd = (int)(blockIdx.x % kXcds);
   const int64_t t0 = items * xcd / kXcds, t1 = items * (xcd + 1) / kXcds;
-  const int64_t t = t0 + blockIdx.x / kXcds;
-  if (t >= t1) return;  // uniform: beyond this XCD's share
-  const int sl = (int)(t % n_slices);
-  const int r = (int)((t / n_slices) % ranges);
-  const int k = (int)(t / ((int64_t)n_slices * ranges));
-  const int w = (int)bm.w;
-  const int wr = (w + ranges - 1) / ranges;  // <= kWideRange
-  const int lo = r * wr, hi = min(w, lo + wr);
-  const int nwords = (hi - lo + 1) / 2;
-  for (int j = threadIdx.x; j < nwords; j += kBuildThreads) pairs[j] = 0;
-  int32_t acc[2 * kWidePairsPerLane];
+  // a grid of about one workgroup per CU walks its XCD's items (a flush
+  // that is not due costs one small launch)
+  const int64_t per_xcd = gridDim.x / kXcds;
+  for (int64_t t = t0 + blockIdx.x / kXcds; t < t1; t += per_xcd) {
+    __syncthreads();  // the previous item's LDS words are read
+    const int sl = (int)(t % n_slices);
+    const int r = (int)((t / n_slices) % ranges);
+    const int k = (int)(t / ((int64_t)n_slices * ranges));
+    const int w = (int)bm.w;
+    const int wr = (w + ranges - 1) / ranges;  // <= kWideRange
+    const int lo = r * wr, hi = min(w, lo + wr);
+    const int nwords = (hi - lo + 1) / 2;
+    for (int j = threadIdx.x; j < nwords; j += kBuildThreads) pairs[j] = 0;
+    int32_t acc[2 * kWidePairsPerLane];
 #pragma unroll
-  for (int i = 0; i < 2 * kWidePairsPerLane; ++i) acc[i] = 0;
-  const int64_t a = n * k / act, b = n * (k + 1) / act;
-  const int s = sl / d;
-  const RowSeeds sd = seeds[sl];
-  const uint64_t *x = surv + (int64_t)s * cap;
-  const bool fast = bm.pow2 && ranges == 1;  // uniform
-  for (int64_t p0 = a; p0 < b; p0 += kWidePiece) {
-    const int64_t p1 = min(b, p0 + kWidePiece);
-    __syncthreads();  // cleared words
-    if (fast) {
-      // kWideKeys survivors per lane at a time, their hash chains interleaved;
-      // a lane past the end adds 0
-      for (int64_t i0 = p0 + threadIdx.x; i0 < p1;
-           i0 += kWideKeys * kBuildThreads) {
-        uint64_t xs[kWideKeys];
-        bool ok[kWideKeys];
-        bool wide_key = false;
-#pragma unroll
-        for (int u = 0; u < kWideKeys; ++u) {
-          const int64_t i = i0 + u * kBuildThreads;
-          ok[u] = i < p1;
-          xs[u] = ok[u] ? x[i] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < kWideKeys; ++u)
-          wide_key = wide_key || (xs[u] >> 32) != 0;
-        if (!__any(wide_key)) {
-          int32_t sign[kWideKeys];
-          uint32_t bk[kWideKeys];
-          hash_many_pow2_auto<kWideKeys>(xs, sd, bm.mask, sign, bk);
-          // one range holds every bucket: the half is bit 0 of the bucket
-#pragma unroll
-          for (int u = 0; u < kWideKeys; ++u)
-            atomicAdd(&pairs[bk[u] >> 1],
-                      ok[u] ? (uint32_t)sign[u] << ((bk[u] & 1u) << 4) : 0u);
-        } else {
+    for (int i = 0; i < 2 * kWidePairsPerLane; ++i) acc[i] = 0;
+    const int64_t a = n * k / act, b = n * (k + 1) / act;
+    const int s = sl / d;
+    const RowSeeds sd = seeds[sl];
+    const uint64_t *x = surv + (int64_t)s * cap;
+    const bool fast = bm.pow2 && ranges == 1;  // uniform
+    for (int64_t p0 = a; p0 < b; p0 += kWidePiece) {
+      const int64_t p1 = min(b, p0 + kWidePiece);
+      __syncthreads();  // cleared words
+      if (fast) {
+        // kWideKeys survivors per lane at a time, their hash chains interleaved;
+        // a lane past the end adds 0
+        for (int64_t i0 = p0 + threadIdx.x; i0 < p1;
+             i0 += kWideKeys * kBuildThreads) {
+          uint64_t xs[kWideKeys];
+          bool ok[kWideKeys];
+          bool wide_key = false;
 #pragma unroll
           for (int u = 0; u < kWideKeys; ++u) {
-            if (!ok[u]) continue;
-            int32_t sign;
-            uint32_t bk;
-            if ((xs[u] >> 32) == 0)
-              hash_xi_h<true>(xs[u], sd, bm, sign, bk);
-            else
-              hash_xi_h<false>(xs[u], sd, bm, sign, bk);
-            atomicAdd(&pairs[bk >> 1], (uint32_t)sign << ((bk & 1u) << 4));
+            const int64_t i = i0 + u * kBuildThreads;
+            ok[u] = i < p1;
+            xs[u] = ok[u] ? x[i] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < kWideKeys; ++u)
+            wide_key = wide_key || (xs[u] >> 32) != 0;
+          if (!__any(wide_key)) {
+            int32_t sign[kWideKeys];
+            uint32_t bk[kWideKeys];
+            hash_many_pow2_auto<kWideKeys>(xs, sd, bm.mask, sign, bk);
+            // one range holds every bucket: the half is bit 0 of the bucket
+#pragma unroll
+            for (int u = 0; u < kWideKeys; ++u)
+              atomicAdd(&pairs[bk[u] >> 1],
+                        ok[u] ? (uint32_t)sign[u] << ((bk[u] & 1u) << 4) : 0u);
+          } else {
+#pragma unroll
+            for (int u = 0; u < kWideKeys; ++u) {
+              if (!ok[u]) continue;
+              int32_t sign;
+              uint32_t bk;
+              if ((xs[u] >> 32) == 0)
+                hash_xi_h<true>(xs[u], sd, bm, sign, bk);
+              else
+                hash_xi_h<false>(xs[u], sd, bm, sign, bk);
+              atomicAdd(&pairs[bk >> 1], (uint32_t)sign << ((bk & 1u) << 4));
+            }
+          }
+        }
+      } else {
+        // four survivors per lane at a time: their hash chains interleave
+        for (int64_t i0 = p0 + threadIdx.x; i0 < p1; i0 += 4 * kBuildThreads) {
+          uint64_t xs[4];
+          bool ok[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * kBuildThreads;
+            ok[u] = i < p1;
+            xs[u] = ok[u] ? x[i] : 0;
+          }
+          bool wide_key = false;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) wide_key = wide_key || (xs[u] >> 32) != 0;
+          int32_t sign[4];
+          uint32_t bk[4];
+          if (!__any(wide_key)) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if ((xs[u] >> 32) == 0)
+                hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
+              else
+                hash_xi_h<false>(xs[u], sd, bm, sign[u], bk[u]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int jj = (int)bk[u] - lo;
+            if (ok[u] && jj >= 0 && (int)bk[u] < hi)
+              atomicAdd(&pairs[jj >> 1],
+                        (jj & 1) ? (uint32_t)sign[u] << 16 : (uint32_t)sign[u]);
           }
         }
       }
-    } else {
-      // four survivors per lane at a time: their hash chains interleave
-      for (int64_t i0 = p0 + threadIdx.x; i0 < p1; i0 += 4 * kBuildThreads) {
-        uint64_t xs[4];
-        bool ok[4];
+      __syncthreads();
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t i = i0 + u * kBuildThreads;
-          ok[u] = i < p1;
-          xs[u] = ok[u] ? x[i] : 0;
-        }
-        bool wide_key = false;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) wide_key = wide_key || (xs[u] >> 32) != 0;
-        int32_t sign[4];
-        uint32_t bk[4];
-        if (!__any(wide_key)) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
-        } else {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            if ((xs[u] >> 32) == 0)
-              hash_xi_h<true>(xs[u], sd, bm, sign[u], bk[u]);
-            else
-              hash_xi_h<false>(xs[u], sd, bm, sign[u], bk[u]);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int jj = (int)bk[u] - lo;
-          if (ok[u] && jj >= 0 && (int)bk[u] < hi)
-            atomicAdd(&pairs[jj >> 1],
-                      (jj & 1) ? (uint32_t)sign[u] << 16 : (uint32_t)sign[u]);
+      for (int i = 0; i < kWidePairsPerLane; ++i) {
+        const int wi = threadIdx.x + i * kBuildThreads;
+        if (wi < nwords) {
+          const uint32_t word = pairs[wi];
+          const int32_t l16 = (int32_t)(int16_t)(word & 0xFFFFu);
+          acc[2 * i] += l16;
+          acc[2 * i + 1] += (int32_t)(word - (uint32_t)l16) >> 16;
+          pairs[wi] = 0;
         }
       }
     }
-    __syncthreads();
+    int32_t *dst = slab + ((int64_t)k * n_slices + sl) * w + lo;
 #pragma unroll
     for (int i = 0; i < kWidePairsPerLane; ++i) {
       const int wi = threadIdx.x + i * kBuildThreads;
-      if (wi < nwords) {
-        const uint32_t word = pairs[wi];
-        const int32_t l16 = (int32_t)(int16_t)(word & 0xFFFFu);
-        acc[2 * i] += l16;
-        acc[2 * i + 1] += (int32_t)(word - (uint32_t)l16) >> 16;
-        pairs[wi] = 0;
-      }
+      if (2 * wi < hi - lo) dst[2 * wi] = acc[2 * i];
+      if (2 * wi + 1 < hi - lo) dst[2 * wi + 1] = acc[2 * i + 1];
     }
-  }
-  int32_t *dst = slab + ((int64_t)k * n_slices + sl) * w + lo;
-#pragma unroll
-  for (int i = 0; i < kWidePairsPerLane; ++i) {
-    const int wi = threadIdx.x + i * kBuildThreads;
-    if (2 * wi < hi - lo) dst[2 * wi] = acc[2 * i];
-    if (2 * wi + 1 < hi - lo) dst[2 * wi + 1] = acc[2 * i + 1];
   }
 }
 
@@ -373,14 +377,14 @@ hipError_t launch_wide_compact(const BuildParams &P, uint64_t *surv,
 hipError_t launch_wide_hash(const uint64_t *surv, const FlushCtl &fc,
                             const void *seeds, const BucketMod &bm, int d,
                             int n_slices, int ranges, int chunks,
-                            int32_t *slab, hipStream_t st) {
+                            int32_t *slab, int n_cu, hipStream_t st) {
   const int w = (int)bm.w;
   const int wr = (w + ranges - 1) / ranges;
   if (wr > kWideRange) return hipErrorInvalidValue;  // 16-bit pairs, 128 KiB
   const size_t lds = (size_t)((wr + 1) / 2) * 4;
-  // every XCD's share of the items fits its kXcds-th of the grid
+  // one workgroup per CU (128 KiB of LDS each), whole XCD shares
   const int items = n_slices * ranges * chunks;
-  const int grid = (items + kXcds - 1) / kXcds * kXcds;
+  const int grid = (std::min(items, std::max(kXcds, n_cu)) + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL(wide_hash_kernel, dim3(grid),
                      dim3(kBuildThreads), lds, st, surv, fc,
                      reinterpret_cast<const RowSeeds *>(seeds), bm, d,
@@ -458,7 +462,7 @@ hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
     cl.p[s] = s < n_sketches ? counters[s] : nullptr;
   const int64_t total = (int64_t)n_slices * w;
   int64_t blocks = (total + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(slab_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      st, slab, chunks, n_slices, d, w, cl, counter_bits,
                      accumulate, fc);

@@ -95,6 +95,69 @@ __global__ void k_copy(const uint4 *__restrict__ in, uint4 *__restrict__ out,
     out[i] = in[i];
 }
 
+// Gather probes: out[i] = in[idx(i)] for about 1% of the positions of an
+// 8 GiB array of 8-byte values, in increasing order (like the survivors of
+// a 1%-selective scan), read three ways: plain loads, nontemporal loads and
+// system-scope relaxed atomic loads.  idx(i) = 100 i + h(i) mod 100 <
+// 100 n_idx <= the array's length (checked on the host).
+__device__ __host__ inline uint64_t gather_idx(uint64_t i) {
+  return 100 * i + ((i * 2654435761ull) >> 7) % 100;
+}
+
+__global__ void k_gather_plain(const uint64_t *__restrict__ in, uint64_t n_idx,
+                               uint64_t *__restrict__ out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_idx;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = in[gather_idx(i)];
+}
+
+__global__ void k_gather_nt(const uint64_t *__restrict__ in, uint64_t n_idx,
+                            uint64_t *__restrict__ out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_idx;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = __builtin_nontemporal_load(in + gather_idx(i));
+}
+
+__global__ void k_gather_sys(const uint64_t *__restrict__ in, uint64_t n_idx,
+                             uint64_t *__restrict__ out) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_idx;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = __hip_atomic_load(in + gather_idx(i), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+static int gather_probe() {
+  const uint64_t n = (uint64_t)1 << 30;  // 8 GiB of uint64
+  const uint64_t n_idx = n / 100;
+  if (gather_idx(n_idx - 1) >= n) {
+    printf("gather index out of range\n");
+    return 1;
+  }
+  uint64_t *in, *out;
+  CK(hipMalloc(&in, n * 8));
+  CK(hipMalloc(&out, n_idx * 8));
+  CK(hipMemset(in, 3, n * 8));
+  CK(hipDeviceSynchronize());
+  hipEvent_t a, b;
+  CK(hipEventCreate(&a));
+  CK(hipEventCreate(&b));
+  const char *names[3] = {"plain", "nontemporal", "system-scope"};
+  for (int rep = 0; rep < 2; ++rep)
+    for (int v = 0; v < 3; ++v) {
+      CK(hipEventRecord(a));
+      if (v == 0) hipLaunchKernelGGL(k_gather_plain, dim3(2048), dim3(256), 0, 0, in, n_idx, out);
+      if (v == 1) hipLaunchKernelGGL(k_gather_nt, dim3(2048), dim3(256), 0, 0, in, n_idx, out);
+      if (v == 2) hipLaunchKernelGGL(k_gather_sys, dim3(2048), dim3(256), 0, 0, in, n_idx, out);
+      CK(hipEventRecord(b));
+      CK(hipEventSynchronize(b));
+      float ms;
+      CK(hipEventElapsedTime(&ms, a, b));
+      printf("gather %s: %llu values of 8 bytes at 1%% density in %.3f ms\n",
+             names[v], (unsigned long long)n_idx, ms);
+    }
+  return 0;
+}
+
 // `micro copy`: one plain copy of exactly 1 GiB (read 1 GiB, write 1 GiB),
 // the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters.
 static int copy_probe() {
@@ -112,6 +175,7 @@ static int copy_probe() {
 
 int main(int argc, char **argv) {
   if (argc > 1 && std::string(argv[1]) == "copy") return copy_probe();
+  if (argc > 1 && std::string(argv[1]) == "gather") return gather_probe();
   hipDeviceProp_t p; CK(hipGetDeviceProperties(&p, 0));
   printf("device %s CUs %d clock %d kHz l2 %d bytes sharedPerBlock %zu maxSharedPerMP %zu\n", p.name, p.multiProcessorCount, p.clockRate, p.l2CacheSize, p.sharedMemPerBlock, p.maxSharedMemoryPerMultiProcessor);
   hipEvent_t a, b; CK(hipEventCreate(&a)); CK(hipEventCreate(&b));
