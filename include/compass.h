@@ -127,6 +127,34 @@ compass_status compass_sketch_build(int64_t n_rows,
                                     int32_t counter_bits, int32_t accumulate,
                                     int64_t *n_selected, hipStream_t stream);
 
+/* compass_sketch_build_noalloc -- compass_sketch_build for callers that
+ * cannot allocate memory during the call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): same arguments,
+ * same kernels, same results, but no hipMalloc, hipFree, host or pinned
+ * allocation and no timing events.  Its scratch (slab of partial
+ * counters, survivor buffer, seeds) is one fixed 256 MiB region of device
+ * memory per GPU, held until the process ends, with the work cut to fit
+ * it (fewer chunks, smaller survivor batches).  E_RANGE, before any GPU
+ * work, when the build cannot fit: one chunk of partial counters
+ * (n_sketches x d x w x 4 bytes) above 256 MiB in the fused scan, or in
+ * the two-phase build a slab of n_sketches x d x w x 4 bytes plus one
+ * survivor batch of 4096 rows x n_sketches x 8 bytes above it.  Every call
+ * on one GPU uses that GPU's region (the previous call's contents are
+ * overwritten; what must start at zero is cleared by the call), so calls
+ * that overlap on one GPU, on any streams, race: the caller serialises
+ * them. */
+compass_status compass_sketch_build_noalloc(int64_t n_rows,
+                                            const void *const *pred_cols,
+                                            int32_t n_pred_cols,
+                                            const compass_pred *preds,
+                                            int32_t n_preds,
+                                            const compass_sketch_spec *sketches,
+                                            int32_t n_sketches, int32_t d,
+                                            int32_t w, int32_t counter_bits,
+                                            int32_t accumulate,
+                                            int64_t *n_selected,
+                                            hipStream_t stream);
+
 /* compass_sketch_build_select -- compass_sketch_build that also
  * materialises the selection output (Section 3, "Partitioned query
  * execution": the selection output is kept when it is small): the indices

@@ -78,6 +78,8 @@ def lib():
             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
             ctypes.c_int32, vp, vp]
         L.compass_sketch_build.restype = ctypes.c_int32
+        L.compass_sketch_build_noalloc.argtypes = L.compass_sketch_build.argtypes
+        L.compass_sketch_build_noalloc.restype = ctypes.c_int32
         L.compass_estimate.argtypes = [
             ctypes.POINTER(JoinGraph), ctypes.POINTER(ctypes.c_uint64),
             ctypes.c_int32, vp, vp, vp, vp]
@@ -171,13 +173,14 @@ def profile_take(name: str):
 def sketch_build(n_rows: int, pred_cols, preds, keys, seeds, counters,
                  n_selected: torch.Tensor, d: int, w: int,
                  counter_bits: int = 32, accumulate: bool = False,
-                 stream=None):
+                 stream=None, noalloc: bool = False):
     """One fused selection scan + sketch build (see include/compass.h).
 
     pred_cols: list of device column tensors; preds: list of dicts
     {col, kind, lo, hi, bitmap (device uint64 tensor), domain};
     keys/seeds/counters: one entry per sketch (device key tensor, (d, 6)
-    uint64 numpy seeds, device (d, w) counter tensor).
+    uint64 numpy seeds, device (d, w) counter tensor).  noalloc: call
+    compass_sketch_build_noalloc (fixed scratch region, allocates nothing).
     """
     cols, ncol, parr, np_ = _marshal_preds(pred_cols, preds)
     ns = len(keys)
@@ -190,7 +193,7 @@ def sketch_build(n_rows: int, pred_cols, preds, keys, seeds, counters,
         sarr[i].key_dtype = _dtype_code(keys[i])
         sarr[i].seeds = sd.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
         sarr[i].counters = counters[i].data_ptr()
-    fn = lib().compass_sketch_build
+    fn = lib().compass_sketch_build_noalloc if noalloc else lib().compass_sketch_build
     _check(fn(int(n_rows), cols, ncol, parr, np_, sarr, ns, int(d), int(w),
               int(counter_bits), 1 if accumulate else 0,
               ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))

@@ -193,12 +193,15 @@ struct ProfRec {
 };
 static bool g_prof_on = false;
 static std::vector<ProfRec> g_prof;
+// set while an entry point that must not allocate runs: no timing events
+static bool g_prof_suppressed = false;
 
 struct ProfScope {
   ProfRec rec;
   bool on;
   hipStream_t st;
-  ProfScope(const char *name, hipStream_t s) : on(g_prof_on), st(s) {
+  ProfScope(const char *name, hipStream_t s)
+      : on(g_prof_on && !g_prof_suppressed), st(s) {
     if (!on) return;
     rec.name = name;
     (void)hipEventCreate(&rec.a);
@@ -299,6 +302,9 @@ struct Arena {
   hipStream_t stream = 0;
   char *fixed = nullptr;       // fixed region, fixed_bytes long
   size_t fixed_bytes = 0;
+  // called once the arguments are valid, before any GPU work: sets up the
+  // fixed region and the CU count
+  compass_status (*prepare)(Arena *, int *n_cu) = nullptr;
   compass_status get(size_t bytes, void **out) const {
     if (fixed) {
       if (bytes > fixed_bytes)
@@ -472,6 +478,10 @@ static compass_status sketch_build_impl(
   int n_cu = fixed_n_cu;
   if (fixed) {
     ar = *fixed;
+    if (ar.prepare) {
+      st = ar.prepare(&ar, &n_cu);
+      if (st != COMPASS_OK) return st;
+    }
   } else {
     st = pooled_arena(stream, &ar, &n_cu);
     if (st != COMPASS_OK) return st;
@@ -665,6 +675,61 @@ extern "C" compass_status compass_sketch_build_select(
   return sketch_build_impl(n_rows, pred_cols, n_pred_cols, preds, n_preds,
                            sketches, n_sketches, d, w, counter_bits, accumulate,
                            n_selected, sink, nullptr, 0, stream);
+}
+
+// ---------------------------------------------------------------------
+// compass_sketch_build_noalloc: the same build with a fixed scratch region
+// ---------------------------------------------------------------------
+// One region per device, held until the process ends.  In host code
+// `scratch` names a host-side stand-in: kernels get the device address
+// taken with hipGetSymbolAddress on the device itself.
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+struct NoAllocDevice {
+  char *ptr = nullptr;  // device address of this device's `scratch`
+  int n_cu = 0;
+};
+static std::map<int, NoAllocDevice> g_noalloc;
+
+// The current device's region: its device address is looked up once per
+// device, on the first call there, with that device current.
+static compass_status noalloc_prepare(Arena *ar, int *n_cu) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  NoAllocDevice &na = g_noalloc[dev];
+  if (!na.ptr) {
+    void *p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(COMPASS_E_HIP, "no device address for the scratch region");
+    int cus = 0;
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    na.ptr = reinterpret_cast<char *>(p);
+    na.n_cu = cus;
+  }
+  ar->fixed = na.ptr;
+  *n_cu = na.n_cu;
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_sketch_build_noalloc(
+    int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
+    const compass_pred *preds, int32_t n_preds,
+    const compass_sketch_spec *sketches, int32_t n_sketches, int32_t d,
+    int32_t w, int32_t counter_bits, int32_t accumulate, int64_t *n_selected,
+    hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  Arena ar;
+  ar.fixed_bytes = kNoAllocScratchBytes;
+  ar.stream = stream;
+  ar.prepare = noalloc_prepare;
+  g_prof_suppressed = true;
+  const compass_status st = sketch_build_impl(
+      n_rows, pred_cols, n_pred_cols, preds, n_preds, sketches, n_sketches, d, w,
+      counter_bits, accumulate, n_selected, RowSink{}, &ar, 0, stream);
+  g_prof_suppressed = false;
+  return st;
 }
 
 // ---------------------------------------------------------------------
