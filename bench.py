@@ -431,6 +431,10 @@ def run_learned(args):
     t_train = time.time() - t0
     res = Lrn.evaluate(mlp, xt, bt, et, tr["test_true"])
     torch.cuda.synchronize()
+    # the spec comparison on the held-out workload: plain path (one
+    # launch per sketch, raw estimates) vs batched + learned
+    e2e = Lrn.compare_paths(pool_te, q_te, s_te, mlp, tr["test_true"],
+                            tune=(262144, 131072, 1), log=log)
     a = time.perf_counter()
     for _ in range(10):
         mlp.forward(xt, bt)
@@ -450,6 +454,7 @@ def run_learned(args):
            "config": {"workload": "learned correction: %d training and %d held-out "
                                   "sub-plans, d=7 w=8192, MLP 20-64-64-64-1"
                                   % (n, xt.shape[0]), "parallelism": "single-gpu"},
+           "end_to_end_heldout": e2e,
            "train_samples_per_s": n * args.epochs / t_train,
            "feature_build_s": t_feat, "mse_first_last": [hist[0], hist[-1]],
            "qerror_heldout": res,

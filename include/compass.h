@@ -444,15 +444,19 @@ compass_status compass_mlp_write(compass_mlp m, const float *params,
                                  const float *adam_m, const float *adam_v,
                                  int64_t step);
 compass_status compass_mlp_destroy(compass_mlp m);
-/* Features of n sub-plans (device in, device out): x = n x 20 floats:
- * 7 order statistics (positions round(k (d-1) / 6), k = 0..6) of
+/* Features of n sub-plans of one query (device in, device out): x = n x 20
+ * floats: 7 order statistics (positions round(k (d-1) / 6), k = 0..6) of
  * sign(X) ln(1 + |X|) over the sorted row estimates; log2(1 + n_sel) of the
- * sub-plan's tables, descending, first 8, zero padded; the 5 caller shape
- * statistics (n x 5 device floats).  base = ln(1 + max(est, 0)). */
+ * sub-plan's tables, descending, first 8, zero padded; 5 shape statistics
+ * of the sub-plan over the query's join graph (edge_u/edge_v: host arrays
+ * of n_edges <= 64 edges): number of tables, number of edges between them,
+ * diameter (in edges), largest degree, independent cycles (edges - tables
+ * + 1).  base = ln(1 + max(est, 0)). */
 compass_status compass_mlp_features(const compass_i128 *row_est, int32_t d,
                                     const double *est, const uint64_t *masks,
                                     const int64_t *n_selected,
-                                    int32_t n_tables, const float *shape,
+                                    int32_t n_tables, int32_t n_edges,
+                                    const int32_t *edge_u, const int32_t *edge_v,
                                     int32_t n, float *x, float *base,
                                     hipStream_t stream);
 

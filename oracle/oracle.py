@@ -661,6 +661,33 @@ def true_cardinality_fk_tree(filtered_cols, edges, mask, domain_of):
     return float(weight[root].sum())
 
 
+def shape_stats(n_tables, edge_u, edge_v, masks):
+    """Shape of each sub-plan over the query's join graph, the learned
+    model's last 5 features: number of tables, number of join edges between
+    them, diameter (largest over table pairs of the fewest edges on a path
+    inside the sub-plan), largest number of edges at one table, and
+    independent cycles (edges - tables + 1 for a connected sub-plan).
+    Returns an n x 5 float64 array."""
+    out = np.zeros((len(masks), 5))
+    for k, m in enumerate(masks):
+        m = int(m)
+        tabs = [t for t in range(n_tables) if m >> t & 1]
+        es = [(u, v) for u, v in zip(edge_u, edge_v) if m >> u & 1 and m >> v & 1]
+        # all-pairs fewest edges (Floyd-Warshall over the sub-plan)
+        inf = float("inf")
+        dist = {(a, b): (0 if a == b else inf) for a in tabs for b in tabs}
+        for u, v in es:
+            dist[(u, v)] = dist[(v, u)] = 1
+        for c in tabs:
+            for a in tabs:
+                for b in tabs:
+                    if dist[(a, c)] + dist[(c, b)] < dist[(a, b)]:
+                        dist[(a, b)] = dist[(a, c)] + dist[(c, b)]
+        deg = [sum((u == t) + (v == t) for u, v in es) for t in tabs]
+        out[k] = (len(tabs), len(es), max(dist.values()), max(deg), len(es) - len(tabs) + 1)
+    return out
+
+
 def mlp_features(rows, est, n_sel_sub, shape):
     """Reference of the learned model's 20 features of one sub-plan (same
     definition as compass_mlp_features): 7 order statistics (positions

@@ -675,7 +675,8 @@ def _bind_mlp(L):
     L.compass_mlp_destroy.argtypes = [vp]
     L.compass_mlp_destroy.restype = ctypes.c_int32
     L.compass_mlp_features.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_int32,
-                                       vp, ctypes.c_int32, vp, vp, vp]
+                                       ctypes.c_int32, vp, vp, ctypes.c_int32, vp, vp,
+                                       vp]
     L.compass_mlp_features.restype = ctypes.c_int32
     L._mlp_bound = True
 
@@ -758,49 +759,23 @@ class MLP:
             pass
 
 
-def shape_stats(n_tables, edge_u, edge_v, masks):
-    """Per sub-plan (host): #tables, #edges, diameter, max degree and number
-    of independent cycles of the induced join graph (float32, n x 5)."""
-    out = np.zeros((len(masks), 5), dtype=np.float32)
-    for k, m in enumerate(masks):
-        m = int(m)
-        tabs = [t for t in range(n_tables) if m >> t & 1]
-        es = [(u, v) for u, v in zip(edge_u, edge_v) if m >> u & 1 and m >> v & 1]
-        adj = {t: [] for t in tabs}
-        for u, v in es:
-            adj[u].append(v)
-            adj[v].append(u)
-        diam = 0
-        for s in tabs:
-            dist = {s: 0}
-            frontier = [s]
-            while frontier:
-                nxt = []
-                for a in frontier:
-                    for b in adj[a]:
-                        if b not in dist:
-                            dist[b] = dist[a] + 1
-                            nxt.append(b)
-                frontier = nxt
-            diam = max(diam, max(dist.values()))
-        out[k] = (len(tabs), len(es), diam,
-                  max((len(v) for v in adj.values()), default=0),
-                  len(es) - len(tabs) + 1)
-    return out
-
-
-def features(row_est, est, masks_dev, n_selected, n_tables, shape_dev, stream=None):
-    """(x n x 20, base n) device float32 features of n sub-plans."""
+def features(row_est, est, masks_dev, n_selected, n_tables, edge_u, edge_v,
+             stream=None):
+    """(x n x 20, base n) device float32 features of n sub-plans of one
+    query (join graph edge_u/edge_v; the kernel computes every feature)."""
     L = lib()
     _bind_mlp(L)
     n, d = row_est.shape[0], row_est.shape[1]
     dev = row_est.device
     x = torch.empty((n, 20), dtype=torch.float32, device=dev)
     base = torch.empty(n, dtype=torch.float32, device=dev)
+    eu = np.ascontiguousarray(np.asarray(edge_u, dtype=np.int32))
+    ev = np.ascontiguousarray(np.asarray(edge_v, dtype=np.int32))
     _check(L.compass_mlp_features(row_est.data_ptr(), d, est.data_ptr(),
                                   masks_dev.data_ptr(), n_selected.data_ptr(),
-                                  int(n_tables), shape_dev.data_ptr(), n,
-                                  x.data_ptr(), base.data_ptr(), _stream(stream)))
+                                  int(n_tables), int(eu.size), eu.ctypes.data,
+                                  ev.ctypes.data, n, x.data_ptr(), base.data_ptr(),
+                                  _stream(stream)))
     return x, base
 
 

@@ -403,7 +403,7 @@ __global__ void slab_reduce_kernel(const int32_t *__restrict__ slab,
                                    int64_t chunks, int32_t n_slices, int32_t d,
                                    int32_t w, CounterList cl,
                                    int32_t counter_bits, int32_t accumulate,
-                                   FlushCtl fc) {
+                                   FlushCtl fc, int32_t vec4) {
   // two-phase builds: a flush reduces only the chunks wide_hash_kernel
   // filled, and its last workgroup empties the survivor buffer
   if (fc.count) {
@@ -412,8 +412,62 @@ __global__ void slab_reduce_kernel(const int32_t *__restrict__ slab,
     chunks = active_chunks(n, chunks);
   }
   const int64_t total = (int64_t)n_slices * w;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total;
-       k += (int64_t)gridDim.x * blockDim.x) {
+  if (vec4) {
+    // four consecutive counters of one sketch row per lane: 16-byte loads
+    // of the slab (eight chunk rows in flight) and of the counters
+    const int64_t total4 = total / 4;
+    const int4 *slab4 = reinterpret_cast<const int4 *>(slab);
+    for (int64_t k4 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+         k4 < total4; k4 += (int64_t)gridDim.x * blockDim.x) {
+      int64_t a[4] = {0, 0, 0, 0};
+      int64_t c = 0;
+      for (; c + 8 <= chunks; c += 8) {
+        int4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = slab4[(c + u) * total4 + k4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[0] += v[u].x;
+          a[1] += v[u].y;
+          a[2] += v[u].z;
+          a[3] += v[u].w;
+        }
+      }
+      for (; c < chunks; ++c) {
+        const int4 v = slab4[c * total4 + k4];
+        a[0] += v.x;
+        a[1] += v.y;
+        a[2] += v.z;
+        a[3] += v.w;
+      }
+      const int64_t k = 4 * k4;
+      const int gs = (int)(k / w);
+      const int j = (int)(k - (int64_t)gs * w);
+      const int s = gs / d, row = gs - s * d;
+      const size_t idx = (size_t)row * w + j;  // a multiple of 4
+      if (counter_bits == 32) {
+        int4 *g = reinterpret_cast<int4 *>(reinterpret_cast<int32_t *>(cl.p[s]) + idx);
+        int4 o = accumulate ? *g : make_int4(0, 0, 0, 0);
+        o.x += (int32_t)a[0];
+        o.y += (int32_t)a[1];
+        o.z += (int32_t)a[2];
+        o.w += (int32_t)a[3];
+        *g = o;
+      } else {
+        longlong2 *g = reinterpret_cast<longlong2 *>(reinterpret_cast<int64_t *>(cl.p[s]) + idx);
+        longlong2 o0 = accumulate ? g[0] : make_longlong2(0, 0);
+        longlong2 o1 = accumulate ? g[1] : make_longlong2(0, 0);
+        o0.x += a[0];
+        o0.y += a[1];
+        o1.x += a[2];
+        o1.y += a[3];
+        g[0] = o0;
+        g[1] = o1;
+      }
+    }
+  }
+  for (int64_t k = vec4 ? total : blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+       k < total; k += (int64_t)gridDim.x * blockDim.x) {
     // eight chunk rows in flight per lane
     int64_t a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t c = 0;
@@ -458,14 +512,20 @@ hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
                               int counter_bits, int accumulate,
                               const FlushCtl &fc, hipStream_t st) {
   CounterList cl;
-  for (int s = 0; s < kMaxSketches; ++s)
+  // 16-byte vector path: rows of a multiple of 4 counters, every counter
+  // array 16-byte aligned (the slab is)
+  int vec4 = (w % 4) == 0;
+  for (int s = 0; s < kMaxSketches; ++s) {
     cl.p[s] = s < n_sketches ? counters[s] : nullptr;
+    if (s < n_sketches && (reinterpret_cast<uintptr_t>(counters[s]) & 15)) vec4 = 0;
+  }
   const int64_t total = (int64_t)n_slices * w;
-  int64_t blocks = (total + 255) / 256;
+  int64_t blocks = (total / (vec4 ? 4 : 1) + 255) / 256;
   if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(slab_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0,
                      st, slab, chunks, n_slices, d, w, cl, counter_bits,
-                     accumulate, fc);
+                     accumulate, fc, vec4);
   return hipGetLastError();
 }
 

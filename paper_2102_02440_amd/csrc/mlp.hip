@@ -233,16 +233,63 @@ __global__ void mlp_to_bf16_kernel(const float *__restrict__ p,
   if (k < n) wb[k] = f_to_bf16(p[k]);
 }
 
+// The query's join graph in kernel arguments (edge endpoints).
+struct FeatGraph {
+  int32_t n_edges;
+  uint8_t u[64], v[64];
+};
+
+// Shape of the sub-plan `m` (its tables and the edges between them):
+// number of tables, number of edges, diameter (longest shortest path, in
+// edges), largest degree, independent cycles (edges - tables + 1).
+__device__ void subplan_shape(const FeatGraph &g, uint64_t m, float out[5]) {
+  int ne = 0;
+  int deg_max = 0;
+  const int nt = __popcll(m);
+  for (int e = 0; e < g.n_edges; ++e)
+    ne += ((m >> g.u[e]) & (m >> g.v[e]) & 1ull) ? 1 : 0;
+  int diam = 0;
+  for (uint64_t rest = m; rest; rest &= rest - 1) {
+    const int t = __ffsll((long long)rest) - 1;
+    int deg = 0;
+    for (int e = 0; e < g.n_edges; ++e)
+      if ((m >> g.u[e]) & (m >> g.v[e]) & 1ull)
+        deg += (g.u[e] == t) + (g.v[e] == t);
+    deg_max = deg > deg_max ? deg : deg_max;
+    // breadth-first levels from t over the sub-plan's edges
+    uint64_t seen = 1ull << t, frontier = seen;
+    int depth = 0;
+    while (true) {
+      uint64_t next = 0;
+      for (int e = 0; e < g.n_edges; ++e) {
+        if (!((m >> g.u[e]) & (m >> g.v[e]) & 1ull)) continue;
+        if ((frontier >> g.u[e]) & 1ull) next |= 1ull << g.v[e];
+        if ((frontier >> g.v[e]) & 1ull) next |= 1ull << g.u[e];
+      }
+      next &= ~seen;
+      if (!next) break;
+      seen |= next;
+      frontier = next;
+      ++depth;
+    }
+    diam = depth > diam ? depth : diam;
+  }
+  out[0] = (float)nt;
+  out[1] = (float)ne;
+  out[2] = (float)diam;
+  out[3] = (float)deg_max;
+  out[4] = (float)(ne - nt + 1);
+}
+
 // Sub-plan features: 7 order statistics (positions round(k (d-1) / 6)) of
 // slog(X_i) = sign * ln(1 + |X_i|) over the sorted row estimates; log2(1 +
-// n_sel) of the sub-plan's tables, descending, first 8, zero padded; the
-// caller's 5 shape statistics.  base = ln(1 + max(est, 0)).
+// n_sel) of the sub-plan's tables, descending, first 8, zero padded; the 5
+// shape statistics of subplan_shape.  base = ln(1 + max(est, 0)).
 __global__ void mlp_features_kernel(const u128 *__restrict__ rows, int32_t d,
                                     const double *__restrict__ est,
                                     const uint64_t *__restrict__ masks,
                                     const int64_t *__restrict__ n_sel,
-                                    int32_t n_tables,
-                                    const float *__restrict__ shape,
+                                    int32_t n_tables, FeatGraph g,
                                     int32_t n, float *__restrict__ x,
                                     float *__restrict__ base) {
   const int sp = blockIdx.x * blockDim.x + threadIdx.x;
@@ -282,7 +329,9 @@ __global__ void mlp_features_kernel(const u128 *__restrict__ rows, int32_t d,
     ls[best] = tmp;
   }
   for (int k = 0; k < 8; ++k) xo[7 + k] = k < cnt ? (float)ls[k] : 0.f;
-  for (int k = 0; k < 5; ++k) xo[15 + k] = shape[(size_t)sp * 5 + k];
+  float sh[5];
+  subplan_shape(g, m, sh);
+  for (int k = 0; k < 5; ++k) xo[15 + k] = sh[k];
   const double e = est[sp];
   base[sp] = (float)log1p(e > 0 ? e : 0.0);
 }
@@ -498,15 +547,29 @@ extern "C" compass_status compass_mlp_destroy(compass_mlp M) {
 extern "C" compass_status compass_mlp_features(
     const compass_i128 *row_est, int32_t d, const double *est,
     const uint64_t *masks, const int64_t *n_selected, int32_t n_tables,
-    const float *shape, int32_t n, float *x, float *base, hipStream_t st) {
-  if (n < 0 || d < 1 || d > 32 || n_tables < 1 || n_tables > 64)
+    int32_t n_edges, const int32_t *edge_u, const int32_t *edge_v, int32_t n,
+    float *x, float *base, hipStream_t st) {
+  if (n < 0 || d < 1 || d > 32 || n_tables < 1 || n_tables > 64 ||
+      n_edges < 0 || n_edges > 64)
     return mfail(COMPASS_E_ARG, "bad feature arguments");
+  if (n_edges > 0 && (!edge_u || !edge_v))
+    return mfail(COMPASS_E_ARG, "null edge array");
+  FeatGraph g;
+  memset(&g, 0, sizeof g);
+  g.n_edges = n_edges;
+  for (int e = 0; e < n_edges; ++e) {
+    if (edge_u[e] < 0 || edge_u[e] >= n_tables || edge_v[e] < 0 ||
+        edge_v[e] >= n_tables || edge_u[e] == edge_v[e])
+      return mfail(COMPASS_E_GRAPH, "edge with bad endpoints");
+    g.u[e] = (uint8_t)edge_u[e];
+    g.v[e] = (uint8_t)edge_v[e];
+  }
   if (n == 0) return COMPASS_OK;
-  if (!row_est || !est || !masks || !n_selected || !shape || !x || !base)
+  if (!row_est || !est || !masks || !n_selected || !x || !base)
     return mfail(COMPASS_E_ARG, "null pointer argument");
   hipLaunchKernelGGL(mlp_features_kernel, dim3((n + 127) / 128), dim3(128), 0, st,
                      reinterpret_cast<const u128 *>(row_est), d, est, masks,
-                     n_selected, n_tables, shape, n, x, base);
+                     n_selected, n_tables, g, n, x, base);
   MHIP(hipGetLastError());
   return COMPASS_OK;
 }

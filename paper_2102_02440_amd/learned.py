@@ -53,9 +53,8 @@ def build_features(pool, queries, subplans, device="cuda", group=1500,
             eu = [e.u for e in pq.edges]
             ev = [e.v for e in pq.edges]
             row_est, est, fl = db.estimate(k, masks)
-            shape = torch.from_numpy(C.shape_stats(len(pq.tables), eu, ev, masks)).to(device)
             md = torch.from_numpy(np.asarray(masks, dtype=np.uint64).view(np.int64)).to(device)
-            x, base = C.features(row_est, est, md, db.n_selected[k], len(pq.tables), shape)
+            x, base = C.features(row_est, est, md, db.n_selected[k], len(pq.tables), eu, ev)
             xs.append(x)
             bases.append(base)
             ests.append(est)
@@ -107,3 +106,67 @@ def evaluate(mlp, x, base, est, true):
     return {"raw": summarize(qerror(raw, true)),
             "learned": summarize(qerror(learned, true)),
             "n": int(len(true))}
+
+
+def compare_paths(pool, queries, subplans, mlp, true, device="cuda", tune=None,
+                  log=None, reps=2):
+    """End to end on one workload, same GPU: the plain path (one
+    compass_sketch_build launch per sketch, then the raw median estimates)
+    against the batched + learned path (one graph launch for every sketch,
+    the same estimates, the feature kernel and the network's forward pass).
+    Returns wall times (host clock, after a warm-up of each path) and the
+    q-error of each path's estimates against `true`."""
+    pool_cols = C.upload_pool(pool, device)
+    db = C.DeviceBatch(pool, queries, device=device, pool_cols=pool_cols)
+    plan = db.plan(tune=tune)
+    todo = [(k, subplans[k]) for k in range(len(queries)) if subplans[k]]
+    masks_dev = {k: torch.from_numpy(np.asarray(m, dtype=np.uint64).view(np.int64)).to(device)
+                 for k, m in todo}
+
+    def estimates():
+        return [(k,) + tuple(db.estimate(k, m)) for k, m in todo]
+
+    def plain():
+        db.build_per_sketch()
+        outs = estimates()
+        return torch.cat([o[2] for o in outs])
+
+    def batched_learned():
+        plan.launch()
+        outs = estimates()
+        xs, bs = [], []
+        for (k, row_est, est, fl) in outs:
+            pq = queries[k]
+            x, b = C.features(row_est, est, masks_dev[k], db.n_selected[k],
+                              len(pq.tables), [e.u for e in pq.edges],
+                              [e.v for e in pq.edges])
+            xs.append(x)
+            bs.append(b)
+        return mlp.forward(torch.cat(xs), torch.cat(bs))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            a = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - a
+            best = dt if best is None else min(best, dt)
+        return best, out
+
+    t_plain, raw = timed(plain)
+    t_bl, y = timed(batched_learned)
+    raw = raw.cpu().numpy()
+    learned = np.expm1(y.double().cpu().numpy())
+    plan.close()
+    n_sk = sum(len(j["keys"]) for j in db.jobs)
+    res = {"queries": len(queries), "sub_plans": int(len(true)), "sketches": n_sk,
+           "plain_s": t_plain, "batched_learned_s": t_bl,
+           "speedup": t_plain / t_bl,
+           "qerror_plain_raw": summarize(qerror(raw, true)),
+           "qerror_batched_learned": summarize(qerror(learned, true))}
+    if log:
+        log("[learned] end to end: plain %.3f s, batched + learned %.3f s" % (t_plain, t_bl))
+    return res

@@ -171,9 +171,9 @@ def test_features_match_reference(oracle, d):
     dq.build()
     masks = oracle.connected_subplans(5, q.edge_u, q.edge_v)
     row_est, est, flags = dq.estimate(masks)
-    shape = C.shape_stats(5, q.edge_u, q.edge_v, masks)
+    shape = oracle.shape_stats(5, q.edge_u, q.edge_v, masks)
     md = torch.tensor(np.asarray(masks, dtype=np.uint64).view(np.int64), device="cuda")
-    x, base = C.features(row_est, est, md, dq.n_selected, 5, torch.from_numpy(shape).cuda())
+    x, base = C.features(row_est, est, md, dq.n_selected, 5, q.edge_u, q.edge_v)
     torch.cuda.synchronize()
     rows = C.row_values(row_est)
     n_sel = dq.n_selected.cpu().tolist()
@@ -244,3 +244,42 @@ def test_train_epoch_matches_steps(oracle):
         assert np.array_equal(m1.read(what), m2.read(what)), what
     m1.close()
     m2.close()
+
+
+@gpu
+def test_feature_shapes_on_large_graphs(oracle):
+    """The kernel's 5 shape features (tables, edges, diameter, largest
+    degree, cycles) against the oracle's all-pairs shortest paths, on
+    random connected sub-plans of a 17-table join graph with extra edges
+    (cycles), and on a 6-cycle with chords."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(17)
+    n = 17
+    eu, ev = [], []
+    for t in range(1, n):
+        eu.append(int(rng.integers(0, t)))
+        ev.append(t)
+    for _ in range(6):
+        a, b = rng.choice(n, size=2, replace=False)
+        eu.append(int(a))
+        ev.append(int(b))
+    masks = W.connected_masks(n, eu, ev, max_tables=9)
+    masks = [masks[i] for i in rng.choice(len(masks), size=min(3000, len(masks)),
+                                          replace=False)]
+    graphs = [(n, eu, ev, masks),
+              (6, [0, 1, 2, 3, 4, 5, 0, 1, 2], [1, 2, 3, 4, 5, 0, 3, 4, 5],
+               W.connected_masks(6, [0, 1, 2, 3, 4, 5, 0, 1, 2],
+                                 [1, 2, 3, 4, 5, 0, 3, 4, 5]))]
+    for (nt, gu, gv, ms) in graphs:
+        print("[case] feature shapes", nt, len(gu), len(ms), flush=True)
+        k = len(ms)
+        d = 3
+        row_est = torch.zeros((k, d, 2), dtype=torch.int64, device="cuda")
+        est = torch.zeros(k, dtype=torch.float64, device="cuda")
+        nsel = torch.ones(nt, dtype=torch.int64, device="cuda")
+        md = torch.tensor(np.asarray(ms, dtype=np.uint64).view(np.int64), device="cuda")
+        x, base = C.features(row_est, est, md, nsel, nt, gu, gv)
+        torch.cuda.synchronize()
+        ref = oracle.shape_stats(nt, gu, gv, ms)
+        assert np.array_equal(x[:, 15:].cpu().numpy().astype(np.float64), ref)

@@ -606,3 +606,33 @@ def test_key_width_classes(oracle):
     assert nsel.item() == keys.size
     assert np.array_equal(cnt.cpu().numpy().astype(np.int64),
                           oracle.sketch(keys, seeds, d, w))
+
+
+@gpu
+@pytest.mark.parametrize("bits", [32, 64])
+def test_counters_not_16_byte_aligned(oracle, bits):
+    """Counter arrays that start 4 or 8 bytes past a 16-byte boundary take
+    the reduction's scalar path; same counters as the oracle, for the fused
+    scan and the two-phase build."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(55 + bits)
+    d, n = 5, 200_003
+    keys = torch.from_numpy(W.fk_column(rng, n, 20_000, 1.0,
+                                        rng.permutation(20_000))).cuda()
+    a = torch.from_numpy(rng.integers(0, 10, n).astype(np.int32)).cuda()
+    seeds = W.draw_seeds(rng, 1, d)[0]
+    cdt = torch.int32 if bits == 32 else torch.int64
+    for w, preds in [(2048, []), (65536, [{"col": 0, "kind": "range", "lo": 0, "hi": 6}])]:
+        _say("unaligned counters", bits, w, len(preds))
+        big = torch.full((d * w + 1,), 7, dtype=cdt, device="cuda")
+        cnt = big[1:].view(d, w)
+        assert cnt.data_ptr() % 16 != 0
+        nsel = torch.zeros(1, dtype=torch.int64, device="cuda")
+        C.sketch_build(n, [a], preds, [keys], [seeds], [cnt], nsel, d, w, bits)
+        torch.cuda.synchronize()
+        mask = np.ones(n, bool) if not preds else (a.cpu().numpy() <= 6)
+        assert nsel.item() == int(mask.sum())
+        assert big[0].item() == 7
+        assert np.array_equal(cnt.cpu().numpy().astype(np.int64),
+                              oracle.sketch(keys.cpu().numpy()[mask], seeds, d, w))

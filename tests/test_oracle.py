@@ -412,3 +412,23 @@ def test_feature_positions_odd_d(oracle):
     for k, v in enumerate(want):
         ref = -np.log1p(-v) if v < 0 else np.log1p(v)
         assert x[k] == ref, (k, x[k], v)
+
+
+def test_shape_stats_by_hand(oracle):
+    """6a join graph: k0-mk1 (e0), t2-mk1 (e1), t2-ci3 (e2), ci3-mk1 (e3),
+    n4-ci3 (e4).  By hand: the whole query has 5 tables, 5 edges, diameter
+    3 (k to n: k-mk-ci-n), largest degree 3 (mk and ci), 1 cycle (the
+    triangle mk-t-ci); {k, mk, ci, n} is a chain of 3 edges (diameter 3,
+    degree 2, no cycle); {mk, t, ci} is the triangle (diameter 1); a single
+    table has diameter 0 and 0 cycles."""
+    eu, ev = [0, 2, 2, 3, 4], [1, 1, 3, 1, 3]
+    s = oracle.shape_stats(5, eu, ev, [0b11111, 0b11011, 0b01110, 0b00100, 0b00011])
+    assert s.tolist() == [[5, 5, 3, 3, 1], [4, 3, 3, 2, 0], [3, 3, 1, 2, 1],
+                          [1, 0, 0, 0, 0], [2, 1, 1, 1, 0]]
+    # a 6-cycle: diameter 3; one chord 0-3 leaves 1 and 4 three edges
+    # apart; the three long chords 0-3, 1-4, 2-5 bring every pair within 2
+    c6u, c6v = [0, 1, 2, 3, 4, 5], [1, 2, 3, 4, 5, 0]
+    assert oracle.shape_stats(6, c6u, c6v, [63]).tolist() == [[6, 6, 3, 2, 1]]
+    assert oracle.shape_stats(6, c6u + [0], c6v + [3], [63]).tolist() == [[6, 7, 3, 3, 2]]
+    assert oracle.shape_stats(6, c6u + [0, 1, 2], c6v + [3, 4, 5],
+                              [63]).tolist() == [[6, 9, 2, 3, 4]]
