@@ -397,11 +397,14 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def run_learned(args):
+def measure_learned(epochs=30):
     """Trains the correction network with the library's kernels on ~213k
-    sub-plans (exact truths stored by tests/golden/make_learned_truth.py)
-    and evaluates it against the raw median estimate on ~21k held-out
-    sub-plans from disjoint seeds."""
+    sub-plans (exact truths stored by tests/golden/make_learned_truth.py),
+    evaluates it against the raw median estimate on ~21k held-out sub-plans
+    from disjoint seeds, and times the held-out workload end to end: the
+    plain path (one build launch per sketch, raw estimates) against the
+    batched + learned path (one graph launch, the same estimates, the
+    network's correction)."""
     import numpy as np
     import torch
     from paper_2102_02440_amd import learned as Lrn
@@ -426,13 +429,11 @@ def run_learned(args):
     init = Lrn.init_params(0)
     torch.cuda.synchronize()
     t0 = time.time()
-    mlp, hist = Lrn.train(x, b, tgt, init, epochs=args.epochs, log=log)
+    mlp, hist = Lrn.train(x, b, tgt, init, epochs=epochs, log=log)
     torch.cuda.synchronize()
     t_train = time.time() - t0
     res = Lrn.evaluate(mlp, xt, bt, et, tr["test_true"])
     torch.cuda.synchronize()
-    # the spec comparison on the held-out workload: plain path (one
-    # launch per sketch, raw estimates) vs batched + learned
     e2e = Lrn.compare_paths(pool_te, q_te, s_te, mlp, tr["test_true"],
                             tune=(262144, 131072, 1), log=log)
     a = time.perf_counter()
@@ -444,31 +445,39 @@ def run_learned(args):
     dims = [20, 64, 64, 64, 1]
     macs = sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
     flops_per_sample = 2 * (3 * macs - dims[0] * dims[1])
-    train_tflops = flops_per_sample * n * args.epochs / t_train / 1e12
+    train_tflops = flops_per_sample * n * epochs / t_train / 1e12
+    return {"workload": "learned correction: %d training and %d held-out sub-plans, "
+                        "d=7 w=8192, MLP 20-64-64-64-1" % (n, xt.shape[0]),
+            "value": xt.shape[0] / t_inf, "unit": "corrected estimates/s",
+            "ms_per_step": t_train * 1e3 / max(1, epochs), "steps": epochs,
+            "dtype": "bf16 weights / fp32 accumulate",
+            "end_to_end_heldout": e2e,
+            "train_samples_per_s": n * epochs / t_train,
+            "feature_build_s": t_feat, "mse_first_last": [hist[0], hist[-1]],
+            "qerror_heldout": res,
+            # training kernels (forward, backward, gradient sum + Adam): fp32
+            # FMA on the vector units; 2 flops per multiply-add of the three
+            # products of each layer (forward, input gradient, weight
+            # gradient; the first layer has no input gradient)
+            "roofline": {"bound": "alu", "achieved": train_tflops,
+                         "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": train_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                         "traffic": None,
+                         "kernel": "mlp training step (fwd, bwd, reduce+Adam)",
+                         "flops_per_sample": flops_per_sample,
+                         "note": "512-sample batches of a 20-64-64-64-1 network: "
+                                 "latency-bound, far from any roof"}}
+
+
+def run_learned(args):
+    m = measure_learned(args.epochs)
     out = {"metric": "subplan estimates/s at q-error (learned correction)",
-           "value": xt.shape[0] / t_inf, "unit": "corrected estimates/s",
-           "n_gpus": 1, "steps": args.epochs, "warmup": 0,
-           "ms_per_step": t_train * 1e3 / max(1, args.epochs),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "bf16 weights / fp32 accumulate", "data": "synthetic",
-           "config": {"workload": "learned correction: %d training and %d held-out "
-                                  "sub-plans, d=7 w=8192, MLP 20-64-64-64-1"
-                                  % (n, xt.shape[0]), "parallelism": "single-gpu"},
-           "end_to_end_heldout": e2e,
-           "train_samples_per_s": n * args.epochs / t_train,
-           "feature_build_s": t_feat, "mse_first_last": [hist[0], hist[-1]],
-           "qerror_heldout": res,
-           # training kernels (forward, backward, gradient sum + Adam): fp32
-           # FMA on the vector units; 2 flops per multiply-add of the three
-           # products of each layer (forward, input gradient, weight
-           # gradient; the first layer has no input gradient)
-           "roofline": {"bound": "alu", "achieved": train_tflops,
-                        "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                        "frac": train_tflops / FP32_VECTOR_PEAK_TFLOPS,
-                        "traffic": None, "kernel": "mlp training step (fwd, bwd, reduce+Adam)",
-                        "flops_per_sample": flops_per_sample,
-                        "note": "512-sample batches of a 20-64-64-64-1 network: "
-                                "latency-bound, far from any roof"}}
+           "value": m["value"], "unit": m["unit"], "n_gpus": 1, "steps": args.epochs,
+           "warmup": 0, "ms_per_step": m["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": m["dtype"],
+           "data": "synthetic",
+           "config": {"workload": m["workload"], "parallelism": "single-gpu"}}
+    out.update({k: v for k, v in m.items() if k not in out and k != "workload"})
     print(json.dumps(out), flush=True)
 
 
@@ -1063,6 +1072,8 @@ def run_job6a(args):
         log("[bench] batched build")
         out["configs"]["batched"] = measure_batch(cs, 1, seed,
                                                   cpu=not args.no_cpu_baseline)
+        log("[bench] learned correction, end to end")
+        out["configs"]["learned"] = measure_learned(args.epochs)
     print(json.dumps(out), flush=True)
 
 

@@ -208,10 +208,16 @@ enum {
      * prod over the sub-plan's tables of n_selected, times w^(#edges -
      * #tables) when positive, is below 2^127 */
     COMPASS_FLAG_EXACT = 1,
-    /* the sub-plan's shape is outside what this library evaluates (more than
-     * one independent cycle, or a cycle longer than a triangle, or two
-     * edges between the same two tables); its outputs are zero / NaN */
-    COMPASS_FLAG_UNSUPPORTED = 2
+    /* the sub-plan's shape is outside what this library evaluates (more
+     * than 6 independent cycles, a table with more than 8 join edges inside
+     * the sub-plan, or more than 2^36 element steps of the conditioned
+     * contraction, w^cycles x list length x d); its outputs are zero / NaN */
+    COMPASS_FLAG_UNSUPPORTED = 2,
+    /* the row values could not be certified (EXACT is clear) and est is the
+     * median of an fp64 evaluation of the same contraction (relative
+     * rounding of about 1e-15 times the same sum over absolute values);
+     * row_est still holds the 128-bit values modulo 2^128 */
+    COMPASS_FLAG_APPROX = 4
 };
 
 /* compass_estimate -- for each sub-plan C (bitmask of tables, connected over
@@ -230,8 +236,17 @@ enum {
  *   row_est    device, n_subplans x d (may be NULL)
  *   est        device, n_subplans doubles
  *   flags      device, n_subplans int32 (COMPASS_FLAG_*)
- * Supported shapes: any tree, and trees plus one edge that closes a
- * triangle.  Others get COMPASS_FLAG_UNSUPPORTED and do not fail the call. */
+ * Shapes: trees and trees plus one triangle take the specialised path
+ * (message passing; the triangle by conditioning on one edge's bucket with
+ * run-ordered sweeps).  Every other connected shape (longer cycles, several
+ * cycles, two edges between one pair of tables, tables with more than 6
+ * children) takes the generic contraction: the edges outside a spanning
+ * tree are conditioned on their buckets (w^k assignments, each contracted
+ * bottom-up), exact in the same 128-bit arithmetic, slower by about w per
+ * conditioned edge.  Shapes beyond its bounds get COMPASS_FLAG_UNSUPPORTED
+ * and do not fail the call.  When a sub-plan's values are not certified,
+ * its estimate comes from an fp64 evaluation (COMPASS_FLAG_APPROX); that
+ * evaluation runs on the device only for those sub-plans. */
 compass_status compass_estimate(const compass_join_graph *g,
                                 const uint64_t *masks, int32_t n_subplans,
                                 compass_i128 *row_est, double *est,
@@ -412,6 +427,10 @@ compass_status compass_mlp_create(int32_t n_in, int32_t hidden,
                                   int32_t n_hidden_layers, const float *init,
                                   compass_mlp *out);
 int64_t compass_mlp_n_params(compass_mlp m);
+/* Adam steps taken so far (the bias-correction count); with
+ * compass_mlp_read (parameters, first and second moments) it is all a
+ * checkpoint needs, and compass_mlp_write restores it. */
+int64_t compass_mlp_adam_steps(compass_mlp m);
 /* y[i] = base[i] + net(x[i]); x: device n x n_in fp32, base/y: device n. */
 compass_status compass_mlp_forward(compass_mlp m, const float *x,
                                    const float *base, int32_t n, float *y,

@@ -32,6 +32,7 @@ that applies it.
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
 import subprocess
 
@@ -322,6 +323,102 @@ def estimate(n_tables, edge_u, edge_v, d, w, sketches, n_sel, masks,
     vals = [[i128_to_int(rows[m, i, 0], rows[m, i, 1]) for i in range(d)]
             for m in range(nm)]
     return vals, est, flags
+
+
+def row_values_exact(n_tables, edge_u, edge_v, d, w, sketches, mask):
+    """The sub-plan's row values X_0..X_{d-1} as unbounded Python integers
+    (no wrap modulo 2^128): the same definition as ``estimate`` (Section 5.1
+    contraction with the Section 5.2 min-abs merge), evaluated by
+    conditioning on the buckets of the edges outside a spanning tree and
+    passing messages up the tree.  For one node, with its elements (parent
+    buckets as queries, child buckets weighted by the children's messages,
+    conditioned buckets weighted 1) ordered by kappa = (|value|, edge id,
+    bucket), the message for a query q is
+        value(q) * prod_groups W_g(above q) + sum over weighted elements z
+        below q of value(z) * weight(z) * prod_{g != group(z)} W_g(above z),
+    W_g(above k) = total weight of group g's elements ordered after k.
+    For sizes where the exact value exceeds 128 bits (uncertified
+    sub-plans).  ``sketches[2e + side]``: (d, w) integer arrays."""
+    tabs = [t for t in range(n_tables) if mask >> t & 1]
+    edges = [e for e in range(len(edge_u))
+             if mask >> edge_u[e] & 1 and mask >> edge_v[e] & 1]
+    if len(tabs) == 1:
+        raise ValueError("single table: the selected count, not a contraction")
+
+    def side(t, e):
+        return 2 * e + (0 if edge_u[e] == t else 1)
+
+    # spanning tree by breadth-first search from the lowest table
+    parent = {tabs[0]: None}
+    order = [tabs[0]]
+    tree = set()
+    for a in order:
+        for e in edges:
+            if a in (edge_u[e], edge_v[e]):
+                b = edge_v[e] if edge_u[e] == a else edge_u[e]
+                if b not in parent:
+                    parent[b] = (a, e)
+                    tree.add(e)
+                    order.append(b)
+    if len(order) != len(tabs):
+        raise ValueError("not connected")
+    cut = [e for e in edges if e not in tree]
+    children = {t: [] for t in tabs}
+    for b in order[1:]:
+        children[parent[b][0]].append((b, parent[b][1]))
+    out = []
+    for i in range(d):
+        sk = [np.asarray(sketches[k])[i].astype(object) if sketches[k] is not None
+              else None for k in range(len(sketches))]
+        total = 0
+        for J in itertools.product(range(w), repeat=len(cut)):
+            fixed = dict(zip(cut, J))
+            msg = {}
+            root_val = 0
+            for t in reversed(order):
+                elems = []   # (kappa, group, weight or None for queries, value, bucket)
+                groups = []
+                for (b, e) in children[t]:
+                    g = len(groups)
+                    groups.append(sum(msg[b]))
+                    for j in range(w):
+                        v = int(sk[side(t, e)][j])
+                        elems.append(((abs(v), e, j), g, msg[b][j], v, j))
+                for e, j in fixed.items():
+                    if t in (edge_u[e], edge_v[e]):
+                        g = len(groups)
+                        groups.append(1)
+                        v = int(sk[side(t, e)][j])
+                        elems.append(((abs(v), e, j), g, 1, v, j))
+                if parent[t] is not None:
+                    pe = parent[t][1]
+                    for j in range(w):
+                        v = int(sk[side(t, pe)][j])
+                        elems.append(((abs(v), pe, j), -1, None, v, j))
+                elems.sort(key=lambda z: z[0])
+                above = list(groups)   # W_g(above the current element)
+                below = 0              # sum over weighted elements passed
+                m = [0] * w
+                for (_, g, wt, v, j) in elems:
+                    if g < 0:
+                        p = v
+                        for x in above:
+                            p *= x
+                        m[j] = p + below
+                    else:
+                        above[g] -= wt
+                        p = v * wt
+                        for k, x in enumerate(above):
+                            if k != g:
+                                p *= x
+                        below += p
+                if parent[t] is None:
+                    root_val = below
+                else:
+                    msg[t] = m
+            total += root_val
+        out.append(total)
+    return out
 
 
 def i128_to_double(v: int) -> float:

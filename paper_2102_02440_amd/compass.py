@@ -14,12 +14,14 @@ import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libcompass.so")
+# COMPASS_LIB selects another build of the same library (a sanitizer build)
+LIB_PATH = os.environ.get("COMPASS_LIB") or os.path.join(_PKG, "libcompass.so")
 
 I32, F32, I64 = 0, 1, 2
 PRED_KIND = {"point": 0, "range": 1, "subset": 2}
 FLAG_EXACT = 1
 FLAG_UNSUPPORTED = 2
+FLAG_APPROX = 4
 
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_RANGE", 3: "E_GRAPH", 4: "E_HIP",
           5: "E_UNSUPPORTED"}
@@ -660,6 +662,8 @@ def _bind_mlp(L):
     L.compass_mlp_create.restype = ctypes.c_int32
     L.compass_mlp_n_params.argtypes = [vp]
     L.compass_mlp_n_params.restype = ctypes.c_int64
+    L.compass_mlp_adam_steps.argtypes = [vp]
+    L.compass_mlp_adam_steps.restype = ctypes.c_int64
     L.compass_mlp_forward.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp]
     L.compass_mlp_forward.restype = ctypes.c_int32
     L.compass_mlp_train_step.argtypes = [vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float,
@@ -701,6 +705,8 @@ class MLP:
                                     ctypes.byref(h)))
         self.h = h
         self.n_in = n_in
+        self.hidden = hidden
+        self.layers = layers
         self.n_params = int(L.compass_mlp_n_params(h))
         self._loss = None
 
@@ -746,6 +752,24 @@ class MLP:
                 for a in (params, m, v)]
         ptrs = [None if a is None else a.ctypes.data_as(fp) for a in arrs]
         _check(lib().compass_mlp_write(self.h, ptrs[0], ptrs[1], ptrs[2], int(step)))
+
+    def adam_steps(self):
+        return int(lib().compass_mlp_adam_steps(self.h))
+
+    def save(self, path):
+        """Checkpoint: parameters, Adam moments and step count (npz)."""
+        np.savez(path, params=self.read(0), adam_m=self.read(2), adam_v=self.read(3),
+                 step=np.int64(self.adam_steps()), n_in=np.int32(self.n_in),
+                 hidden=np.int32(self.hidden), layers=np.int32(self.layers))
+
+    @classmethod
+    def load(cls, path):
+        """A network restored from save(): the same parameters and Adam
+        state, so training continues exactly where it stopped."""
+        z = np.load(path)
+        m = cls(z["params"], int(z["n_in"]), int(z["hidden"]), int(z["layers"]))
+        m.write(z["params"], z["adam_m"], z["adam_v"], int(z["step"]))
+        return m
 
     def close(self):
         if self.h:

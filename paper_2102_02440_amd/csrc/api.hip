@@ -21,6 +21,7 @@
 #include "compass.h"
 #include "estimate_buffers.hpp"
 #include "estimate_params.hpp"
+#include "generic_params.hpp"
 #include "partition_params.hpp"
 #include "agms_params.hpp"
 
@@ -59,9 +60,11 @@ hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
                             hipStream_t st);
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
                            const EstBuffers &B, hipStream_t st);
+hipError_t launch_gen_contract(const GenArgs &A, const EstBuffers &B,
+                               int n_blocks, int fp64, hipStream_t st);
 hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
-                         uint64_t *row_est, double *est, int32_t *flags,
-                         int32_t n_tables, hipStream_t st);
+                         const double *approx, uint64_t *row_est, double *est,
+                         int32_t *flags, int32_t n_tables, hipStream_t st);
 hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st);
 hipError_t launch_scan2d_binned(const BuildParams &P, const Bin2dArgs &a,
                                 int accumulate, hipStream_t st);
@@ -757,6 +760,13 @@ struct Planner {
   int n_msg_slots = 0, n_x_slots = 0, n_prep_slots = 0, n_partial_slots = 0;
   int Lmax = 0, Lprep = 0;
   std::vector<char> side_used;
+  // generic contraction (any shape; fp64 evaluation of uncertified ones)
+  std::vector<GenNode> gnodes;
+  std::vector<GenPlan> gplans;
+  std::vector<GenBlock> gblocks[2];   // [fp64]
+  int64_t glists_len = 0;             // merged list entries, all blocks
+  int64_t gmsg_len = 0;               // values (16 bytes each)
+  int n_approx_slots = 0;
 
   int side_of(int table, int e) const {
     return 2 * e + (g->edge_u[e] == table ? 0 : 1);
@@ -765,12 +775,159 @@ struct Planner {
 
 }  // namespace
 
+// Work bounds of the generic contraction: list elements walked over all
+// assignments and rows, and message scratch of one plan.
+constexpr double kGenWorkCap = 68719476736.0;  // 2^36 element steps
+constexpr size_t kGenMsgCap = (size_t)256 << 20;     // exact plans
+constexpr size_t kGenMsgCapFp64 = (size_t)64 << 20;  // fp64 plans
+
+// Plans the generic contraction of sub-plan `mask` (index spi): a BFS
+// spanning tree from its lowest table (edges in id order), the other edges
+// conditioned.  fp64: the approximate evaluation run when the 128-bit
+// values are not certified.  Returns false when the shape or its work
+// exceeds the bounds (then nothing is added).
+static bool plan_generic(Planner &pl, uint64_t mask, int spi, bool fp64,
+                         int *out_slot, int *n_slots) {
+  const compass_join_graph *g = pl.g;
+  const int w = pl.w, d = pl.d;
+  std::vector<int> tabs, edges;
+  for (int t = 0; t < g->n_tables; ++t)
+    if (mask >> t & 1ull) tabs.push_back(t);
+  for (int e = 0; e < g->n_edges; ++e)
+    if ((mask >> g->edge_u[e] & 1ull) && (mask >> g->edge_v[e] & 1ull))
+      edges.push_back(e);
+  if (tabs.size() < 2) return false;
+  std::vector<int> node_of(g->n_tables, -1), table_of, parent_edge, parent;
+  std::vector<char> tree(g->n_edges, 0);
+  table_of.push_back(tabs[0]);
+  parent_edge.push_back(-1);
+  parent.push_back(-1);
+  node_of[tabs[0]] = 0;
+  for (size_t h = 0; h < table_of.size(); ++h) {
+    const int t = table_of[h];
+    for (int e : edges) {
+      int other;
+      if (g->edge_u[e] == t) other = g->edge_v[e];
+      else if (g->edge_v[e] == t) other = g->edge_u[e];
+      else continue;
+      if (node_of[other] >= 0) continue;
+      node_of[other] = (int)table_of.size();
+      table_of.push_back(other);
+      parent_edge.push_back(e);
+      parent.push_back((int)h);
+      tree[e] = 1;
+    }
+  }
+  const int nn = (int)table_of.size();
+  if (nn != (int)tabs.size() || nn > 64) return false;
+  std::vector<int> cuts;
+  for (int e : edges)
+    if (!tree[e]) cuts.push_back(e);
+  if ((int)cuts.size() > kGenMaxCut) return false;
+  double n_assign = 1;
+  for (size_t k = 0; k < cuts.size(); ++k) n_assign *= w;
+  // nodes in post-order (reverse BFS order: children before parents)
+  std::vector<GenNode> nodes(nn);
+  std::vector<int> msg_of(nn, -1);
+  int n_msgs = 0;
+  for (int a = 1; a < nn; ++a) msg_of[a] = n_msgs++;
+  int64_t list_len = 0;
+  std::vector<int> post;
+  for (int a = nn - 1; a >= 0; --a) post.push_back(a);
+  std::vector<char> dynamic(nn, 0);
+  for (int a : post) {
+    GenNode &N = nodes[a];
+    memset(&N, 0, sizeof N);
+    const int t = table_of[a];
+    N.parent_side = a == 0 ? -1 : pl.side_of(t, parent_edge[a]);
+    N.parent_eid = a == 0 ? -1 : parent_edge[a];
+    N.msg = msg_of[a];
+    for (int c = 1; c < nn; ++c) {
+      if (parent[c] != a) continue;
+      if (N.n_child >= kGenMaxGroups) return false;
+      N.c_side[N.n_child] = pl.side_of(t, parent_edge[c]);
+      N.c_eid[N.n_child] = parent_edge[c];
+      N.c_msg[N.n_child] = msg_of[c];
+      dynamic[a] |= dynamic[c];
+      ++N.n_child;
+    }
+    for (size_t k = 0; k < cuts.size(); ++k) {
+      const int e = cuts[k];
+      if (g->edge_u[e] != t && g->edge_v[e] != t) continue;
+      if (N.n_fixed >= kGenMaxGroups) return false;
+      N.f_side[N.n_fixed] = pl.side_of(t, e);
+      N.f_eid[N.n_fixed] = e;
+      N.f_cut[N.n_fixed] = (int)k;
+      ++N.n_fixed;
+      dynamic[a] = 1;
+    }
+    N.is_static = !dynamic[a];
+    N.list_off = (int)list_len;
+    N.list_len = (N.n_child + (a != 0)) * w;
+    list_len += N.list_len;
+  }
+  if (n_assign * (double)list_len * d > kGenWorkCap) return false;
+  // J blocks: enough workgroups to fill the device, message scratch bounded
+  const size_t per_block = (size_t)std::max(1, n_msgs) * w * 16;
+  int64_t blocks = (int64_t)std::min<double>(n_assign, std::max(1, 2048 / d));
+  const size_t cap = fp64 ? kGenMsgCapFp64 : kGenMsgCap;
+  blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, (int64_t)(cap / (per_block * d))));
+  GenPlan P;
+  memset(&P, 0, sizeof P);
+  P.node0 = (int)pl.gnodes.size();
+  P.n_nodes = nn;
+  P.n_msgs = n_msgs;
+  P.n_cut = (int)cuts.size();
+  P.n_assign = (int64_t)n_assign;
+  P.lists_off = pl.glists_len;
+  P.msg_off = pl.gmsg_len;
+  P.n_blocks = (int)blocks;
+  P.sp = spi;
+  P.fp64 = fp64 ? 1 : 0;
+  if (fp64) {
+    P.out_slot = pl.n_approx_slots;
+    pl.n_approx_slots += (int)blocks;
+  } else {
+    P.out_slot = pl.n_partial_slots;
+    pl.n_partial_slots += (int)blocks;
+  }
+  *out_slot = P.out_slot;
+  *n_slots = (int)blocks;
+  const int plan_idx = (int)pl.gplans.size();
+  P.lists_len = (int)list_len;
+  for (int a : post) {
+    const GenNode &N = nodes[a];
+    for (int c = 0; c < N.n_child; ++c) pl.side_used[N.c_side[c]] = 1;
+    if (N.parent_side >= 0) pl.side_used[N.parent_side] = 1;
+    pl.gnodes.push_back(N);
+  }
+  for (int b = 0; b < blocks; ++b) pl.gblocks[fp64 ? 1 : 0].push_back(GenBlock{plan_idx, b});
+  pl.gplans.push_back(P);
+  pl.glists_len += (int64_t)blocks * d * list_len;
+  pl.gmsg_len += (int64_t)blocks * d * n_msgs * w;
+  return true;
+}
+
+// A sub-plan the triangle-specialised path does not evaluate: the generic
+// contraction if it fits its bounds, else flagged unsupported.
+static void plan_other_shape(Planner &pl, SubplanTask &sp, uint64_t mask, int spi) {
+  int slot = 0, n = 0;
+  if (plan_generic(pl, mask, spi, false, &slot, &n)) {
+    sp.type = kSpGeneric;
+    sp.x_slot = slot;
+    sp.n_partials = n;
+  } else {
+    sp.type = kSpUnsupported;
+  }
+}
+
 // Builds the rooted spanning tree of one sub-plan and its node tasks.
 static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
   const compass_join_graph *g = pl.g;
   SubplanTask sp;
   memset(&sp, 0, sizeof(sp));
   sp.mask = mask;
+  sp.approx_slot = -1;
   std::vector<int> tabs, edges;
   for (int t = 0; t < g->n_tables; ++t)
     if (mask >> t & 1ull) tabs.push_back(t);
@@ -841,7 +998,7 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
   std::vector<int> cand;
   int apex = -1, cut0 = -1;
   if (cuts.size() > 1) {
-    sp.type = kSpUnsupported;
+    plan_other_shape(pl, sp, mask, spi);
     pl.sps.push_back(sp);
     return COMPASS_OK;
   }
@@ -856,7 +1013,7 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
         if (pa.first == pb.first) apex = pa.first;
     }
     if (direct || apex < 0) {
-      sp.type = kSpUnsupported;
+      plan_other_shape(pl, sp, mask, spi);
       pl.sps.push_back(sp);
       return COMPASS_OK;
     }
@@ -940,7 +1097,7 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
     if (fits) ors.push_back(std::move(o));
   }
   if (ors.empty()) {
-    sp.type = kSpUnsupported;
+    plan_other_shape(pl, sp, mask, spi);
     pl.sps.push_back(sp);
     return COMPASS_OK;
   }
@@ -1112,6 +1269,17 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
     compass_status s = plan_subplan(pl, masks[i], i);
     if (s != COMPASS_OK) return s;
   }
+  // an fp64 evaluation of every multi-table sub-plan, run on the device
+  // only when its 128-bit values cannot be certified
+  for (int i = 0; i < n_subplans; ++i) {
+    SubplanTask &sp = pl.sps[i];
+    if (sp.n_tables < 2 || sp.type == kSpUnsupported) continue;
+    int slot = 0, n = 0;
+    if (plan_generic(pl, masks[i], i, true, &slot, &n)) {
+      sp.approx_slot = slot;
+      sp.n_approx = n;
+    }
+  }
 
   DeviceState *ds;
   compass_status st = device_state(&ds);
@@ -1178,6 +1346,13 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
                               (kOrderTile + 1));
   const size_t o_tseg = carve(sizeof(int32_t) * np * d * (kFastSegs + 1));
   const size_t o_part = carve(16ull * std::max(1, pl.n_partial_slots) * d);
+  const size_t o_gnodes = carve(sizeof(GenNode) * std::max<size_t>(1, pl.gnodes.size()));
+  const size_t o_gplans = carve(sizeof(GenPlan) * std::max<size_t>(1, pl.gplans.size()));
+  const size_t o_gblk0 = carve(sizeof(GenBlock) * std::max<size_t>(1, pl.gblocks[0].size()));
+  const size_t o_gblk1 = carve(sizeof(GenBlock) * std::max<size_t>(1, pl.gblocks[1].size()));
+  const size_t o_glists = carve(4ull * std::max<int64_t>(1, pl.glists_len));
+  const size_t o_gmsg = carve(16ull * std::max<int64_t>(1, pl.gmsg_len));
+  const size_t o_approx = carve(8ull * std::max(1, pl.n_approx_slots) * d);
   void *scratch;
   st = ensure_scratch(ds, stream, off, &scratch);
   if (st != COMPASS_OK) return st;
@@ -1195,6 +1370,21 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   memcpy(host.data() + o_sps, pl.sps.data(), sizeof(SubplanTask) * pl.sps.size());
   st = upload(ds, base, host.data(), o_sorted, stream);
   if (st != COMPASS_OK) return st;
+  if (!pl.gplans.empty()) {
+    // the generic plans' tables (between o_gnodes and o_glists)
+    std::vector<char> gh(o_glists - o_gnodes, 0);
+    memcpy(gh.data(), pl.gnodes.data(), sizeof(GenNode) * pl.gnodes.size());
+    memcpy(gh.data() + (o_gplans - o_gnodes), pl.gplans.data(),
+           sizeof(GenPlan) * pl.gplans.size());
+    if (!pl.gblocks[0].empty())
+      memcpy(gh.data() + (o_gblk0 - o_gnodes), pl.gblocks[0].data(),
+             sizeof(GenBlock) * pl.gblocks[0].size());
+    if (!pl.gblocks[1].empty())
+      memcpy(gh.data() + (o_gblk1 - o_gnodes), pl.gblocks[1].data(),
+             sizeof(GenBlock) * pl.gblocks[1].size());
+    st = upload(ds, base + o_gnodes, gh.data(), gh.size(), stream);
+    if (st != COMPASS_OK) return st;
+  }
 
   EstBuffers B;
   memset(&B, 0, sizeof(B));
@@ -1272,10 +1462,28 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
                            (int)pl.tris.size(),
                            (w + kLaneThreads - 1) / kLaneThreads, B, stream));
   }
+  if (!pl.gplans.empty()) {
+    GenArgs A;
+    memset(&A, 0, sizeof A);
+    A.nodes = reinterpret_cast<const GenNode *>(base + o_gnodes);
+    A.plans = reinterpret_cast<const GenPlan *>(base + o_gplans);
+    A.lists = reinterpret_cast<uint32_t *>(base + o_glists);
+    A.msg = base + o_gmsg;
+    A.partial = B.partial;
+    A.approx = reinterpret_cast<double *>(base + o_approx);
+    A.sps = reinterpret_cast<const SubplanTask *>(base + o_sps);
+    A.n_tables = g->n_tables;
+    ProfScope ps("generic", stream);
+    A.blocks = reinterpret_cast<const GenBlock *>(base + o_gblk0);
+    HIP_OK(launch_gen_contract(A, B, (int)pl.gblocks[0].size(), 0, stream));
+    A.blocks = reinterpret_cast<const GenBlock *>(base + o_gblk1);
+    HIP_OK(launch_gen_contract(A, B, (int)pl.gblocks[1].size(), 1, stream));
+  }
   {
     ProfScope ps("finish", stream);
     HIP_OK(launch_finish(reinterpret_cast<const SubplanTask *>(base + o_sps),
                          (int)pl.sps.size(), B,
+                         reinterpret_cast<const double *>(base + o_approx),
                          reinterpret_cast<uint64_t *>(row_est), est, flags,
                          g->n_tables, stream));
   }

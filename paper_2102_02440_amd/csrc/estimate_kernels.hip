@@ -42,6 +42,7 @@
 #include "device_math.hpp"
 #include "estimate_params.hpp"
 #include "estimate_buffers.hpp"
+#include "certificate.hpp"
 
 namespace compass {
 
@@ -1451,9 +1452,10 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
 // per sub-plan: rows, median, double, certificate
 // ---------------------------------------------------------------------
 __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
-                              uint64_t *row_est, double *est, int32_t *flags,
-                              int32_t n_tables) {
+                              const double *approx, uint64_t *row_est,
+                              double *est, int32_t *flags, int32_t n_tables) {
   __shared__ u128 xs[64];
+  __shared__ double xd[64];
   const SubplanTask S = sps[blockIdx.x];
   const int d = B.d;
   const int i = threadIdx.x;
@@ -1463,7 +1465,7 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
       x = s64_to_u128(B.n_sel[S.single_table]);
     } else if (S.type == kSpTree) {
       x = B.xout[(size_t)S.x_slot * d + i];
-    } else if (S.type == kSpTriangle) {
+    } else if (S.type == kSpTriangle || S.type == kSpGeneric) {
       // eight loads in flight (the partials sit in different lines)
       u128 acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       int z = 0;
@@ -1478,6 +1480,12 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
       for (int u = 0; u < 8; ++u) x += acc[u];
     }
     xs[i] = x;
+    if (S.approx_slot >= 0) {
+      double a = 0;
+      for (int z = 0; z < S.n_approx; ++z)
+        a += approx[((size_t)S.approx_slot + z) * d + i];
+      xd[i] = a;
+    }
     if (row_est) {
       row_est[((size_t)blockIdx.x * d + i) * 2 + 0] = (uint64_t)x;
       row_est[((size_t)blockIdx.x * d + i) * 2 + 1] = (uint64_t)(x >> 64);
@@ -1488,6 +1496,24 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
   if (S.type == kSpUnsupported) {
     est[blockIdx.x] = __builtin_nan("");
     flags[blockIdx.x] = 2;
+    return;
+  }
+  const bool cert = S.type == kSpSingle ||
+                    subplan_certified(S, B.n_sel, n_tables, B.w);
+  if (!cert && S.approx_slot >= 0) {
+    // the 128-bit values may have wrapped: the median of the fp64
+    // evaluation, flagged approximate
+    for (int a = 1; a < d; ++a) {
+      const double v = xd[a];
+      int b = a - 1;
+      while (b >= 0 && xd[b] > v) {
+        xd[b + 1] = xd[b];
+        --b;
+      }
+      xd[b + 1] = v;
+    }
+    est[blockIdx.x] = (d & 1) ? xd[d / 2] : (xd[d / 2 - 1] + xd[d / 2]) * 0.5;
+    flags[blockIdx.x] = 4;
     return;
   }
   // insertion sort as signed 128-bit values
@@ -1506,30 +1532,7 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
   else
     e = i128_to_double(xs[d / 2 - 1] + xs[d / 2]) * 0.5;
   est[blockIdx.x] = e;
-  // certificate: prod n_sel * w^(E - V) < 2^127
-  const u128 lim = (u128)1 << 127;
-  u128 b = 1;
-  bool ok = true, zero = false;
-  for (int t = 0; t < n_tables && ok; ++t) {
-    if (!((S.mask >> t) & 1ull)) continue;
-    const int64_t ns = B.n_sel[t];
-    const u128 f = ns < 0 ? 0 : (u128)ns;
-    if (f == 0) {
-      zero = true;
-      break;
-    }
-    // b * f > 2^127 stops the product (no 128-bit division)
-    u128 prod;
-    if (__builtin_mul_overflow(b, f, &prod) || prod > lim) ok = false;
-    else b = prod;
-  }
-  if (!zero)
-    for (int k = 0; k < S.n_edges - S.n_tables && ok; ++k) {
-      u128 prod;
-      if (__builtin_mul_overflow(b, (u128)B.w, &prod) || prod > lim) ok = false;
-      else b = prod;
-    }
-  flags[blockIdx.x] = (zero || (ok && b < lim)) ? 1 : 0;
+  flags[blockIdx.x] = cert ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------
@@ -1613,10 +1616,10 @@ hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
 }
 
 hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
-                         uint64_t *row_est, double *est, int32_t *flags,
-                         int32_t n_tables, hipStream_t st) {
-  hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(64), 0, st, sps, B, row_est,
-                     est, flags, n_tables);
+                         const double *approx, uint64_t *row_est, double *est,
+                         int32_t *flags, int32_t n_tables, hipStream_t st) {
+  hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(64), 0, st, sps, B, approx,
+                     row_est, est, flags, n_tables);
   return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ struct TaskGuard {
   int32_t tab[3];
   int32_t pad;
 };
-enum { kSpSingle = 0, kSpTree = 1, kSpTriangle = 2, kSpUnsupported = 3 };
+enum { kSpSingle = 0, kSpTree = 1, kSpTriangle = 2, kSpUnsupported = 3,
+       kSpGeneric = 4 };
 
 // One node of one sub-plan's rooted spanning tree (blockIdx.y = sketch row).
 // Lists: children 0..m-1 (weighted by their messages), then the parent
@@ -90,9 +91,11 @@ struct SubplanTask {
   int32_t n_tables;
   int32_t n_edges;
   int32_t single_table;
-  int32_t x_slot;           // tree: X slot; triangle: first partial slot
+  int32_t x_slot;           // tree: X slot; triangle, generic: first partial slot
   int32_t n_partials;
   uint64_t mask;
+  int32_t approx_slot;      // first slot of the fp64 evaluation (-1: none)
+  int32_t n_approx;         // its slots (summed per row)
 };
 
 }  // namespace compass

@@ -418,6 +418,10 @@ extern "C" int64_t compass_mlp_n_params(compass_mlp M) {
   return M ? M->S.n_params : 0;
 }
 
+extern "C" int64_t compass_mlp_adam_steps(compass_mlp M) {
+  return M ? (int64_t)M->step : 0;
+}
+
 extern "C" compass_status compass_mlp_forward(compass_mlp M, const float *x,
                                               const float *base, int32_t n,
                                               float *y, hipStream_t st) {

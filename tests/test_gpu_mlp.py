@@ -283,3 +283,34 @@ def test_feature_shapes_on_large_graphs(oracle):
         torch.cuda.synchronize()
         ref = oracle.shape_stats(nt, gu, gv, ms)
         assert np.array_equal(x[:, 15:].cpu().numpy().astype(np.float64), ref)
+
+
+@gpu
+def test_checkpoint_resumes_training_exactly(oracle, tmp_path):
+    """A checkpoint (parameters, Adam moments, step count) written after some
+    steps and loaded into a new network: both continue identically, bit
+    for bit, through further Adam steps."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(8)
+    x, base, t = _data(rng, 1024)
+    xd, bd, td = (torch.from_numpy(a).cuda() for a in (x, base, t))
+    m1 = C.MLP(oracle.mlp_init(2).astype(np.float32))
+    print("[case] mlp checkpoint", flush=True)
+    for k in range(5):
+        m1.train_step(xd[k * 200:(k + 1) * 200].contiguous(),
+                      bd[k * 200:(k + 1) * 200].contiguous(),
+                      td[k * 200:(k + 1) * 200].contiguous(), 1e-3)
+    path = str(tmp_path / "ckpt.npz")
+    m1.save(path)
+    m2 = C.MLP.load(path)
+    assert m2.adam_steps() == m1.adam_steps() == 5
+    for k in range(3):
+        for m in (m1, m2):
+            m.train_step(xd[:300].contiguous(), bd[:300].contiguous(),
+                         td[:300].contiguous(), 1e-3)
+    torch.cuda.synchronize()
+    for what in (0, 2, 3):
+        assert np.array_equal(m1.read(what), m2.read(what)), what
+    m1.close()
+    m2.close()
