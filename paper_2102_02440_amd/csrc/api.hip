@@ -767,6 +767,8 @@ struct Planner {
   int64_t glists_len = 0;             // merged list entries, all blocks
   int64_t gmsg_len = 0;               // values (16 bytes each)
   int n_approx_slots = 0;
+  // message tasks by subtree: shared by every sub-plan that needs them
+  std::map<std::string, int> msg_task;
 
   int side_of(int table, int e) const {
     return 2 * e + (g->edge_u[e] == table ? 0 : 1);
@@ -1112,15 +1114,41 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
     const int root = o.root, cut_e = o.cut_e, cut_u = o.cut_u, cut_v = o.cut_v;
     gd.self = (int)ko;
     // tasks: every non-root node emits a message slot; cut endpoints also a
-    // cut-constant slot
+    // cut-constant slot.  A leaf's message and cut constants are its own
+    // counters (slot -1 - side: read in place, no task).  A message whose
+    // subtree (tables, edges, cut edges) another sub-plan already planned
+    // is the same array: its slots are shared and no task is added.
     std::vector<int> msg_slot(nn, -1), cmsg_slot(nn, -1);
-    for (int a = 0; a < nn; ++a) {
-      if (a != root) msg_slot[a] = pl.n_msg_slots++;
-      if (nodes[a].cut_edge >= 0) cmsg_slot[a] = pl.n_msg_slots++;
-    }
+    std::vector<std::string> key(nn);
     for (int k = nn - 1; k >= 0; --k) {
       const int a = o.order[k];
       PlanNode &nd = nodes[a];
+      if (a != root) {
+        std::vector<std::string> ck;
+        for (size_t c = 0; c < nd.children.size(); ++c) ck.push_back(key[nd.children[c]]);
+        std::sort(ck.begin(), ck.end());
+        key[a] = "(" + std::to_string(nd.table) + "," + std::to_string(nd.parent_edge) +
+                 "," + std::to_string(nd.cut_edge) + ":";
+        for (auto &x : ck) key[a] += x;
+        key[a] += ")";
+        if (nd.children.empty()) {
+          msg_slot[a] = -1 - pl.side_of(nd.table, nd.parent_edge);
+          if (nd.cut_edge >= 0) cmsg_slot[a] = -1 - pl.side_of(nd.table, nd.cut_edge);
+          continue;
+        }
+        auto it = pl.msg_task.find(key[a]);
+        if (it != pl.msg_task.end()) {
+          NodeTask &S = pl.tasks[it->second];
+          msg_slot[a] = S.msg_slot;
+          cmsg_slot[a] = S.cmsg_slot;
+          // shared by rootings of different guards: always computed
+          if (memcmp(&S.guard, &gd, sizeof(gd)) != 0) S.guard.n = 0;
+          continue;
+        }
+        msg_slot[a] = pl.n_msg_slots++;
+        if (nd.cut_edge >= 0) cmsg_slot[a] = pl.n_msg_slots++;
+        pl.msg_task[key[a]] = (int)pl.tasks.size();
+      }
       NodeTask T;
       memset(&T, 0, sizeof(T));
       T.guard = gd;
@@ -1301,12 +1329,21 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const int d = g->d, w = g->w;
   const size_t per_task =
       (size_t)d * std::max(1, pl.Lmax) * (sizeof(uint32_t) + sizeof(NodeRec));
-  const size_t group_tasks =
-      std::max<size_t>(1, kNodeScratchBytes / per_task);
+  const size_t group_tasks = std::min<size_t>(
+      kMaxGridZ, std::max<size_t>(1, kNodeScratchBytes / per_task));
   size_t max_level_tasks = 0;
   std::vector<NodeTask> flat;
   std::vector<size_t> level_off;
+  // within a level: one-child nodes, other nodes, triangle apexes, so that
+  // every kernel of a group is launched over its own tasks only
+  auto kind = [](const NodeTask &t) {
+    return t.mode == kModeTriRootPrep ? 2 : (t.m == 1 ? 0 : 1);
+  };
   for (auto &lv : levels) {
+    std::stable_sort(lv.begin(), lv.end(),
+                     [&](const NodeTask &a, const NodeTask &b) {
+                       return kind(a) < kind(b);
+                     });
     for (size_t k = 0; k < lv.size(); ++k)
       lv[k].scratch_slot = (int)(k % group_tasks);
     level_off.push_back(flat.size());
@@ -1431,24 +1468,24 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
     ProfScope ps("node", stream);
     for (size_t g0 = 0; g0 < levels[lv].size(); g0 += group_tasks) {
       const size_t ng = std::min(group_tasks, levels[lv].size() - g0);
-      bool any_one = false, any_node = false;
+      int n_kind[3] = {0, 0, 0};
       int apex_L = 0, merge_L = 0;
       for (size_t k = g0; k < g0 + ng; ++k) {
         const NodeTask &t = levels[lv][k];
         const int nl = t.m + (t.parent_side >= 0) + (t.cut_side >= 0);
-        if (t.m == 1) any_one = true;
+        ++n_kind[kind(t)];
         if (t.m >= 2) merge_L = std::max(merge_L, nl * w);
-        if ((t.m == 0 && t.mode == kModeMessage) ||
-            (t.m >= 2 && t.mode != kModeTriRootPrep))
-          any_node = true;
         if (t.mode == kModeTriRootPrep) apex_L = std::max(apex_L, t.m * w);
       }
       const NodeTask *dt = dtasks + level_off[lv] + g0;
-      if (merge_L > 0)
-        HIP_OK(launch_node_merge(dt, (int)ng, merge_L, B, stage, stream));
-      if (any_node) HIP_OK(launch_node(dt, (int)ng, B, stream));
-      if (any_one) HIP_OK(launch_node1(dt, (int)ng, B, stream));
-      if (apex_L > 0) HIP_OK(launch_apex_prep(dt, (int)ng, apex_L, B, stream));
+      const NodeTask *d1 = dt + n_kind[0], *d2 = d1 + n_kind[1];
+      if (n_kind[1] + n_kind[2] > 0)
+        HIP_OK(launch_node_merge(d1, n_kind[1] + n_kind[2], merge_L, B, stage,
+                                 stream));
+      if (n_kind[1] > 0) HIP_OK(launch_node(d1, n_kind[1], B, stream));
+      if (n_kind[0] > 0) HIP_OK(launch_node1(dt, n_kind[0], B, stream));
+      if (n_kind[2] > 0)
+        HIP_OK(launch_apex_prep(d2, n_kind[2], apex_L, B, stream));
     }
   }
   if (!pl.tris.empty()) {

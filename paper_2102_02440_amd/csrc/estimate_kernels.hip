@@ -43,6 +43,7 @@
 #include "estimate_params.hpp"
 #include "estimate_buffers.hpp"
 #include "certificate.hpp"
+#include "lds_stage.hpp"
 
 namespace compass {
 
@@ -64,6 +65,15 @@ __device__ __forceinline__ const uint64_t *sorted_of(const EstBuffers &B,
 __device__ __forceinline__ u128 *msg_of(const EstBuffers &B, int slot,
                                         int row) {
   return B.msg + ((size_t)slot * B.d + row) * B.w;
+}
+
+// A child's message (or cut constant) at bucket j: slot >= 0 is a computed
+// message array; a leaf's message is its own counter on that edge, read in
+// place (slot = -1 - side).
+__device__ __forceinline__ u128 child_msg_at(const EstBuffers &B, int slot,
+                                             int row, int j) {
+  if (slot >= 0) return msg_of(B, slot, row)[j];
+  return s64_to_u128(counter_at(B, -1 - slot, row, j));
 }
 
 // number of keys < thr in a sorted array
@@ -120,16 +130,34 @@ __device__ __forceinline__ uint64_t abs_u64(int64_t v) {
 __global__ __launch_bounds__(kSortThreads) void sort_chunk_kernel(
     const int32_t *job_side, EstBuffers B, int w2) {
   __shared__ uint64_t sk[kSortChunk];
-  const int side = job_side[blockIdx.x];
+  const int side = job_side[blockIdx.z];
   const int row = blockIdx.y;
   const int w = B.w;
-  const int c0 = blockIdx.z * kSortChunk;
+  const int c0 = blockIdx.x * kSortChunk;
   const int n = min(kSortChunk, w2);  // chunk length (w2 < kSortChunk: one)
-  for (int t = threadIdx.x; t < n; t += kSortThreads) {
-    const int j = c0 + t;
-    uint64_t k = ~0ull;
-    if (j < w) k = (abs_u64(counter_at(B, side, row, j)) << 16) | (uint64_t)j;
-    sk[t] = k;
+  {
+    // all of a lane's counter loads in flight together (indexes clamped)
+    constexpr int kU = kSortChunk / kSortThreads;
+    int64_t v[kU];
+    const size_t rb = (size_t)row * w;
+    if (B.counter_bits == 32) {
+      const int32_t *src = reinterpret_cast<const int32_t *>(B.sides[side]) + rb;
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        v[u] = src[min(c0 + (int)threadIdx.x + u * kSortThreads, w - 1)];
+    } else {
+      const int64_t *src = reinterpret_cast<const int64_t *>(B.sides[side]) + rb;
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        v[u] = src[min(c0 + (int)threadIdx.x + u * kSortThreads, w - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = (int)threadIdx.x + u * kSortThreads;
+      const int j = c0 + t;
+      if (t < n)
+        sk[t] = j < w ? (abs_u64(v[u]) << 16) | (uint64_t)j : ~0ull;
+    }
   }
   __syncthreads();
   for (int k = 2; k <= n; k <<= 1) {
@@ -153,16 +181,16 @@ __global__ __launch_bounds__(kSortThreads) void sort_chunk_kernel(
 __global__ __launch_bounds__(kSortThreads) void sort_merge_kernel(
     const int32_t *job_side, EstBuffers B, int w2) {
   extern __shared__ uint64_t ak[];  // all w2 chunk-sorted keys of the row
-  const int side = job_side[blockIdx.x];
+  const int side = job_side[blockIdx.z];
   const int row = blockIdx.y;
   const int w = B.w;
   const int n = min(kSortChunk, w2);
   const int nch = w2 / n;
   const uint64_t *tmp = B.sort_tmp + ((size_t)side * B.d + row) * (size_t)w2;
-  for (int t = threadIdx.x; t < w2; t += kSortThreads) ak[t] = tmp[t];
+  stage_lds<kSortThreads, 8>(ak, tmp, w2, StageCopy());
   __syncthreads();
   uint64_t *out = const_cast<uint64_t *>(sorted_of(B, side, row));
-  const int mine = blockIdx.z;
+  const int mine = blockIdx.x;
   constexpr int U = kSortChunk / kSortThreads;
   uint64_t key[U];
   int pos[U];
@@ -254,7 +282,7 @@ __device__ __forceinline__ ListRef list_of(const NodeTask *T, int a) {
 // (list, bucket, counter, child message) is gathered here once.
 __global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
     const NodeTask *tasks, EstBuffers B, int32_t stage_bytes) {
-  const NodeTask *Tg = tasks + blockIdx.x;
+  const NodeTask *Tg = tasks + blockIdx.z;
   const NodeTask T = *Tg;
   if (T.m < 2 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // uniform
   const int row = blockIdx.y;
@@ -262,7 +290,7 @@ __global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
   const int m = T.m;
   const int nl = m + (T.parent_side >= 0) + (T.cut_side >= 0);
   const int L = nl * w;
-  const int e_lo = blockIdx.z * kMergeChunk;
+  const int e_lo = blockIdx.x * kMergeChunk;
   if (e_lo >= L) return;
   const int e_hi = min(L, e_lo + kMergeChunk);
   uint32_t *merged =
@@ -275,17 +303,15 @@ __global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
     const ListRef lr = list_of(Tg, threadIdx.x);
     s_side[threadIdx.x] = lr.side;
     s_eid[threadIdx.x] = lr.eid;
-    s_msg[threadIdx.x] = (int)threadIdx.x < m ? Tg->child_msg[threadIdx.x] : -1;
+    s_msg[threadIdx.x] = (int)threadIdx.x < m ? Tg->child_msg[threadIdx.x] : 0;
   }
   __syncthreads();
   const bool staged = B.counter_bits == 32 &&
                       (size_t)nl * w * 4 <= (size_t)stage_bytes;
   if (staged) {
-    for (int e = threadIdx.x; e < L; e += kMergeThreads) {
-      const int a = e / w;
-      const int k = e - a * w;
-      mags[e] = (uint32_t)(sorted_of(B, s_side[a], row)[k] >> 16);
-    }
+    for (int a = 0; a < nl; ++a)
+      stage_lds<kMergeThreads, 8>(mags + (size_t)a * w,
+                                  sorted_of(B, s_side[a], row), w, StageMag());
     __syncthreads();
     // kMergeU elements per lane at a time: their rank searches run in
     // lockstep (uniform trip count), so the LDS probes overlap
@@ -336,7 +362,7 @@ __global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
 #pragma unroll
       for (int u = 0; u < kMergeU; ++u) {
         r[u].v = counter_at(B, s_side[a[u]], row, (int)j[u]);
-        r[u].mu = a[u] < m ? msg_of(B, s_msg[a[u]], row)[j[u]] : (u128)0;
+        r[u].mu = a[u] < m ? child_msg_at(B, s_msg[a[u]], row, (int)j[u]) : (u128)0;
         r[u].aj = ((uint32_t)a[u] << 16) | j[u];
         r[u].pad = 0;
       }
@@ -362,7 +388,7 @@ __global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
       }
       NodeRec r;
       r.v = counter_at(B, s_side[a], row, (int)j);
-      r.mu = a < m ? msg_of(B, s_msg[a], row)[j] : (u128)0;
+      r.mu = a < m ? child_msg_at(B, s_msg[a], row, (int)j) : (u128)0;
       r.aj = ((uint32_t)a << 16) | j;
       r.pad = 0;
       merged[pos] = r.aj;
@@ -490,17 +516,9 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
   const int has_cut = T.cut_side >= 0;
   const int nl = m + has_parent + has_cut;
 
-  if (m == 1) return;  // node1_prefix_kernel / node1_emit_kernel
-  if (m == 0) {  // leaf: messages are the raw counters
-    if (T.mode != kModeMessage) return;
-    u128 *M = has_parent ? msg_of(B, T.msg_slot, row) : nullptr;
-    u128 *C = has_cut ? msg_of(B, T.cmsg_slot, row) : nullptr;
-    for (int j = threadIdx.x; j < w; j += kNodeThreads) {
-      if (M) M[j] = s64_to_u128(counter_at(B, T.parent_side, row, j));
-      if (C) C[j] = s64_to_u128(counter_at(B, T.cut_side, row, j));
-    }
-    return;
-  }
+  // one child: node1_prefix_kernel / node1_emit_kernel; leaves have no
+  // task (their messages are their counters)
+  if (m < 2) return;
 
   const int L = nl * w;
   NodeRec *rec = B.nrec + ((size_t)T.scratch_slot * B.d + row) * (size_t)B.Lmax;
@@ -542,16 +560,15 @@ __device__ __forceinline__ u128 *n1_total(const EstBuffers &B, int slot,
 __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
     const NodeTask *tasks, EstBuffers B) {
   __shared__ u128 sh_m[kN1Threads], sh_x[kN1Threads];
-  const NodeTask &T = tasks[blockIdx.x];
+  const NodeTask &T = tasks[blockIdx.z];
   if (T.m != 1 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
   const int row = blockIdx.y;
   const int w = B.w;
-  const int c0 = blockIdx.z * kN1Chunk;
+  const int c0 = blockIdx.x * kN1Chunk;
   if (c0 >= w) return;
   const int cside = T.child_side[0];
   const int cmsg = T.child_msg[0];
   const uint64_t *srt = sorted_of(B, cside, row);
-  const u128 *mu_in = msg_of(B, cmsg, row);
   u128 pm[kN1Per], px[kN1Per];
   const int k0 = c0 + threadIdx.x * kN1Per;
 #pragma unroll
@@ -560,7 +577,7 @@ __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
     const int k = k0 + u;
     if (k < w) {
       const int j = (int)(srt[k] & 0xFFFF);
-      const u128 mu = mu_in[j];
+      const u128 mu = child_msg_at(B, cmsg, row, j);
       pm[u] = mu;
       px[u] = mul_s64_u128(counter_at(B, cside, row, j), mu);
     }
@@ -600,8 +617,8 @@ __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
   }
   if (threadIdx.x == kN1Threads - 1) {
     u128 *tot = n1_total(B, T.scratch_slot, row);
-    tot[2 * blockIdx.z] = sh_m[threadIdx.x];
-    tot[2 * blockIdx.z + 1] = sh_x[threadIdx.x];
+    tot[2 * blockIdx.x] = sh_m[threadIdx.x];
+    tot[2 * blockIdx.x + 1] = sh_x[threadIdx.x];
   }
 }
 
@@ -609,7 +626,7 @@ __global__ __launch_bounds__(kN1Threads) void node1_emit_kernel(
     const NodeTask *tasks, EstBuffers B) {
   extern __shared__ uint32_t smag[];  // the child's sorted |v| (int32 counters)
   __shared__ u128 soff[2 * kN1MaxChunks + 2];
-  const NodeTask &T = tasks[blockIdx.x];
+  const NodeTask &T = tasks[blockIdx.z];
   if (T.m != 1 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
   const int row = blockIdx.y;
   const int w = B.w;
@@ -618,21 +635,19 @@ __global__ __launch_bounds__(kN1Threads) void node1_emit_kernel(
   const int nch = (w + kN1Chunk - 1) / kN1Chunk;
   const u128 *tot = n1_total(B, T.scratch_slot, row);
   if (nq == 0) {  // tree root: X = G(+inf)
-    if (blockIdx.z == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       u128 x = 0;
       for (int c = 0; c < nch; ++c) x += tot[2 * c + 1];
       B.xout[(size_t)T.out_slot * B.d + row] = x;
     }
     return;
   }
-  const int e0 = blockIdx.z * kN1Chunk;
+  const int e0 = blockIdx.x * kN1Chunk;
   if (e0 >= nq * w) return;
   const int cside = T.child_side[0];
   const uint64_t *srt = sorted_of(B, cside, row);
   const bool staged = B.counter_bits == 32;
-  if (staged)
-    for (int k = threadIdx.x; k < w; k += kN1Threads)
-      smag[k] = (uint32_t)(srt[k] >> 16);
+  if (staged) stage_lds<kN1Threads, 8>(smag, srt, w, StageMag());
   if (threadIdx.x == 0) {
     u128 am = 0, ax = 0;
     for (int c = 0; c < nch; ++c) {
@@ -716,12 +731,12 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
     const NodeTask *tasks, EstBuffers B) {
   __shared__ int s_lo[kPrepThreads], s_hi[kPrepThreads];
   __shared__ int s_prev, s_next;
-  const NodeTask &T = tasks[blockIdx.x];
+  const NodeTask &T = tasks[blockIdx.z];
   if (T.mode != kModeTriRootPrep || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
   const int row = blockIdx.y;
   const int m = T.m;
   const int L = m * B.w;  // an apex has no parent or cut list
-  const int p0 = blockIdx.z * kPrepChunk;
+  const int p0 = blockIdx.x * kPrepChunk;
   if (p0 >= L) return;
   const int p1 = min(L, p0 + kPrepChunk);
   const NodeRec *rec =
@@ -944,7 +959,7 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
   __shared__ uint64_t okey[kOrderTile];
   __shared__ int64_t scm[kOrderThreads], scx[kOrderThreads];
   __shared__ uint32_t scv[kOrderThreads];
-  const TriTask &T = tasks[blockIdx.x];
+  const TriTask &T = tasks[blockIdx.z];
   if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
   if (tri_path(*(ConstTask *)&T, B) != kTriFast) return;
   const int row = blockIdx.y;
@@ -952,21 +967,35 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
   const int z = B.prep_z[slot_row];
   const int L = T.L;
   if (L - z > kOrderCap) return;
-  const int tile = blockIdx.z;
+  const int tile = blockIdx.x;
   const int t0 = z + tile * kOrderTile;
   if (t0 >= L) return;
   const int nt = min(kOrderTile, L - t0);
   const TriElemN *el = B.prepn + slot_row * (size_t)B.Lprep;
   int n2 = 1;
   while (n2 < nt) n2 <<= 1;
-  for (int q = threadIdx.x; q < n2; q += kOrderThreads) {
-    uint64_t k = ~0ull;
-    if (q < nt) {
-      const TriElemN &e = el[t0 + q];
-      const uint64_t rl = (uint64_t)(max(e.run_lo, t0) - t0);
-      k = (rl << 42) | ((uint64_t)(e.kc & 0x7FFFFFFFu) << 11) | (uint64_t)q;
+  {
+    // every lane's element loads in flight together (indexes clamped)
+    constexpr int kU = kOrderTile / kOrderThreads;
+    int32_t rlo[kU];
+    uint32_t kcs[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const TriElemN &e = el[t0 + min((int)threadIdx.x + u * kOrderThreads, nt - 1)];
+      rlo[u] = e.run_lo;
+      kcs[u] = e.kc;
     }
-    okey[q] = k;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = (int)threadIdx.x + u * kOrderThreads;
+      if (q >= n2) continue;
+      uint64_t k = ~0ull;
+      if (q < nt) {
+        const uint64_t rl = (uint64_t)(max(rlo[u], t0) - t0);
+        k = (rl << 42) | ((uint64_t)(kcs[u] & 0x7FFFFFFFu) << 11) | (uint64_t)q;
+      }
+      okey[q] = k;
+    }
   }
   __syncthreads();
   for (int k = 2; k <= n2; k <<= 1) {
@@ -1152,7 +1181,7 @@ __device__ __forceinline__ int lds_lower_bound(const uint32_t *k, int n,
 __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     const TriTask *tasks, EstBuffers B) {
   extern __shared__ __align__(16) uint32_t skey[];  // run-ordered keys of [z, L)
-  ConstTask &T = *((ConstTask *)tasks + blockIdx.x);
+  ConstTask &T = *((ConstTask *)tasks + blockIdx.z);
   if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // another rooting runs
   if (tri_path(T, B) != kTriFast) return;  // uniform: tri_lane_kernel's block
   const int row = blockIdx.y;
@@ -1160,7 +1189,7 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   // whole waves share a segment: make that visible to the compiler, so the
   // sweep's positions and element loads stay scalar
   const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / kLaneThreads);
-  const int J = blockIdx.z * kLaneThreads + lane;
+  const int J = blockIdx.x * kLaneThreads + lane;
   const bool active = J < B.w;
   const int Jc = active ? J : 0;
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
@@ -1174,8 +1203,7 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   const bool ordered = len <= kOrderCap;  // tri_order_kernel ran
   const uint32_t *tk = B.tkey + slot_row * (size_t)B.Lprep;
   if (ordered) {
-    for (int q = threadIdx.x; q < len; q += kLaneThreads * kFastSegs)
-      skey[q] = tk[z + q];
+    stage_lds<kLaneThreads * kFastSegs, 16>(skey, tk + z, len, StageCopy());
     __syncthreads();
   }
 
@@ -1190,7 +1218,7 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     for (int e = 0; e < 2; ++e) {
       kf[e] = (uint32_t)abs_u64(counter_at(B, T.cut_side[e], row, Jc)) +
               (T.cut_peid[e] < T.cut_eid ? 1u : 0u);
-      cv[e] = (int64_t)(uint64_t)msg_of(B, T.cut_cmsg[e], row)[Jc];
+      cv[e] = (int64_t)(uint64_t)child_msg_at(B, T.cut_cmsg[e], row, Jc);
     }
     const int e0 = T.cut_child[0] == 0 ? 0 : 1;  // cut endpoint in slot 0
     kf0 = kf[e0];
@@ -1300,7 +1328,7 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    B.partial[((size_t)T.partial_slot + blockIdx.z) * B.d + row] = red[0];
+    B.partial[((size_t)T.partial_slot + blockIdx.x) * B.d + row] = red[0];
 }
 
 // Other triangles (more apex children, or bounds beyond the compact
@@ -1311,13 +1339,13 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
   __shared__ u128 red[kLaneThreads];
   // the task is the same for every lane: read it through the constant
   // address space so its fields live in scalar registers
-  ConstTask &T = *((ConstTask *)tasks + blockIdx.x);
+  ConstTask &T = *((ConstTask *)tasks + blockIdx.z);
   if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // another rooting runs
   const int path = tri_path(T, B);
   if (path == kTriFast) return;  // uniform: tri_fast_kernel's block
   const bool narrow = path == kTriNarrow;
   const int row = blockIdx.y;
-  const int J = blockIdx.z * kLaneThreads + threadIdx.x;
+  const int J = blockIdx.x * kLaneThreads + threadIdx.x;
   const bool active = J < B.w;
   const int Jc = active ? J : 0;
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
@@ -1330,7 +1358,7 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     qabs[e] = abs_u64(counter_at(B, T.cut_side[e], row, Jc));
-    cval[e] = msg_of(B, T.cut_cmsg[e], row)[Jc];
+    cval[e] = child_msg_at(B, T.cut_cmsg[e], row, Jc);
   }
 
   u128 G = 0;
@@ -1445,7 +1473,7 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    B.partial[((size_t)T.partial_slot + blockIdx.z) * B.d + row] = red[0];
+    B.partial[((size_t)T.partial_slot + blockIdx.x) * B.d + row] = red[0];
 }
 
 // ---------------------------------------------------------------------
@@ -1543,11 +1571,11 @@ hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
   int w2 = 1;
   while (w2 < B.w) w2 <<= 1;
   const int nch = std::max(1, w2 / kSortChunk);
-  hipLaunchKernelGGL(sort_chunk_kernel, dim3(n_jobs, B.d, nch),
+  hipLaunchKernelGGL(sort_chunk_kernel, dim3(nch, B.d, n_jobs),
                      dim3(kSortThreads), 0, st, job_side, B, w2);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sort_merge_kernel, dim3(n_jobs, B.d, nch),
+  hipLaunchKernelGGL(sort_merge_kernel, dim3(nch, B.d, n_jobs),
                      dim3(kSortThreads), (size_t)w2 * sizeof(uint64_t), st,
                      job_side, B, w2);
   return hipGetLastError();
@@ -1557,7 +1585,7 @@ hipError_t launch_node_merge(const NodeTask *tasks, int n, int max_L,
                              const EstBuffers &B, int stage_bytes,
                              hipStream_t st) {
   hipLaunchKernelGGL(node_merge_kernel,
-                     dim3(n, B.d, (max_L + kMergeChunk - 1) / kMergeChunk),
+                     dim3((max_L + kMergeChunk - 1) / kMergeChunk, B.d, n),
                      dim3(kMergeThreads), (size_t)stage_bytes, st, tasks, B,
                      stage_bytes);
   return hipGetLastError();
@@ -1573,11 +1601,11 @@ hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
 hipError_t launch_node1(const NodeTask *tasks, int n, const EstBuffers &B,
                         hipStream_t st) {
   const int nch = (B.w + kN1Chunk - 1) / kN1Chunk;
-  hipLaunchKernelGGL(node1_prefix_kernel, dim3(n, B.d, nch), dim3(kN1Threads),
+  hipLaunchKernelGGL(node1_prefix_kernel, dim3(nch, B.d, n), dim3(kN1Threads),
                      0, st, tasks, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(node1_emit_kernel, dim3(n, B.d, 2 * nch), dim3(kN1Threads),
+  hipLaunchKernelGGL(node1_emit_kernel, dim3(2 * nch, B.d, n), dim3(kN1Threads),
                      B.counter_bits == 32 ? (size_t)B.w * 4 : 0, st, tasks, B);
   return hipGetLastError();
 }
@@ -1585,18 +1613,24 @@ hipError_t launch_node1(const NodeTask *tasks, int n, const EstBuffers &B,
 hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
                             const EstBuffers &B, hipStream_t st) {
   hipLaunchKernelGGL(apex_prep_kernel,
-                     dim3(n, B.d, (Lmax_apex + kPrepChunk - 1) / kPrepChunk),
+                     dim3((Lmax_apex + kPrepChunk - 1) / kPrepChunk, B.d, n),
                      dim3(kPrepThreads), 0, st, tasks, B);
   return hipGetLastError();
 }
 
+// Grids put the chunks of one (task, row) in x, so that consecutive
+// workgroups (dispatched to the 8 XCDs in turn) spread one task's work over
+// every XCD; tasks go in z, at most kMaxGridZ per launch.
 hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
                             hipStream_t st) {
   const int tiles = (std::min(B.Lprep, kOrderCap) + kOrderTile - 1) / kOrderTile;
-  hipLaunchKernelGGL(tri_order_kernel, dim3(n, B.d, tiles), dim3(kOrderThreads),
-                     0, st, tasks, B);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  for (int t0 = 0; t0 < n; t0 += kMaxGridZ) {
+    const int nt = std::min(kMaxGridZ, n - t0);
+    hipLaunchKernelGGL(tri_order_kernel, dim3(tiles, B.d, nt),
+                       dim3(kOrderThreads), 0, st, tasks + t0, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(tri_seg_kernel, dim3(n, B.d), dim3(kSegThreads), 0, st,
                      tasks, B);
   return hipGetLastError();
@@ -1605,14 +1639,19 @@ hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
                            const EstBuffers &B, hipStream_t st) {
   // each (task, row, z) block does its work in exactly one of the two
-  hipLaunchKernelGGL(tri_fast_kernel, dim3(n, B.d, zblocks),
-                     dim3(kLaneThreads * kFastSegs), (size_t)kFastStageBytes,
-                     st, tasks, B);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(tri_lane_kernel, dim3(n, B.d, zblocks),
-                     dim3(kLaneThreads), 0, st, tasks, B);
-  return hipGetLastError();
+  for (int t0 = 0; t0 < n; t0 += kMaxGridZ) {
+    const int nt = std::min(kMaxGridZ, n - t0);
+    hipLaunchKernelGGL(tri_fast_kernel, dim3(zblocks, B.d, nt),
+                       dim3(kLaneThreads * kFastSegs), (size_t)kFastStageBytes,
+                       st, tasks + t0, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tri_lane_kernel, dim3(zblocks, B.d, nt),
+                       dim3(kLaneThreads), 0, st, tasks + t0, B);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,

@@ -13,6 +13,7 @@ constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
 constexpr int kNodeStageBytes = 96 * 1024;  // node merge: staged magnitudes
 constexpr size_t kNodeScratchBytes = (size_t)1 << 30;  // per level launch
+constexpr int kMaxGridZ = 65535;  // tasks per launch (grid z)
 constexpr int kMergeThreads = 512;  // node list merge
 constexpr int kMergeChunk = 2048;  // merged elements per workgroup
 constexpr int kN1Threads = 256;   // one-child nodes
