@@ -122,6 +122,38 @@ def measured_traffic(profile, names):
         return None
 
 
+def timed_steps(C, torch, step, steps, dominant):
+    """Runs `steps` steps between two device synchronisations; only the
+    dominant kernel's launches carry timing events (the other kernels'
+    events would add their own cost to the timed region).  Returns
+    (seconds per step, (launches, total ms) of the dominant kernel)."""
+    C.profile_take(dominant)
+    C.profile_select([dominant])
+    C.profile_enable(True)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / steps
+    C.profile_enable(False)
+    C.profile_select(None)
+    return dt, C.profile_take(dominant)
+
+
+def profiled_steps(C, torch, step, steps, names):
+    """Per-kernel (launches, total ms) over `steps` further steps with every
+    kernel's events recorded (outside the timed region)."""
+    for n in names:
+        C.profile_take(n)
+    C.profile_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    C.profile_enable(False)
+    return {n: C.profile_take(n) for n in names}
+
+
 def cpu_model():
     """CPU model name of this host (first 'model name' of /proc/cpuinfo)."""
     try:
@@ -508,17 +540,11 @@ def measure_large(steps, warmup, seed, cpu=True, cpu_rows=50_000_000):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    C.profile_enable(True)
-    a = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - a) / steps
-    C.profile_enable(False)
-    kn, kms = C.profile_take("wide_compact")
-    hn, hms = C.profile_take("wide_hash")
-    rn, rms = C.profile_take("slab_reduce")
-    zn, zms = C.profile_take("fill_zero")
+    dt, (kn, kms) = timed_steps(C, torch, step, steps, "wide_compact")
+    other = profiled_steps(C, torch, step, steps, ["wide_hash", "slab_reduce", "fill_zero"])
+    hn, hms = other["wide_hash"]
+    rn, rms = other["slab_reduce"]
+    zn, zms = other["fill_zero"]
     sel = int(nsel.item())
     alg = 16 * n + sel * 6 * 8 + 6 * d * w * 8
     # dominant kernel: the predicate scan + compaction (phase A), which moves
@@ -642,15 +668,16 @@ def run_partition(args):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    C.profile_enable(True)
-    a = time.perf_counter()
-    for _ in range(args.steps):
-        row_est, est, flags = step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - a) / args.steps
-    C.profile_enable(False)
-    prof = {kname: C.profile_take(kname) for kname in
-            ["fill_zero", "scan_sketch", "slab_reduce", "scan2d", "chain3"]}
+    out_last = []
+
+    def step_keep():
+        out_last[:] = [step()]
+
+    dt, scan2d_prof = timed_steps(C, torch, step_keep, args.steps, "scan2d")
+    row_est, est, flags = out_last[0]
+    prof = profiled_steps(C, torch, step, args.steps,
+                          ["fill_zero", "scan_sketch", "slab_reduce", "chain3"])
+    prof["scan2d"] = scan2d_prof
     kms = {kname: v[1] / args.steps for kname, v in prof.items()}
     # merged-sketch estimate of the same sub-plan (edges e0, e1) for contrast
     Amk0 = torch.zeros((d, w), dtype=torch.int32, device=dev)
@@ -758,15 +785,7 @@ def run_agms(args):
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    C.profile_enable(True)
-    a = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - a) / args.steps
-    C.profile_enable(False)
-    kn, kms = C.profile_take("agms_build")
-    C.profile_take("fill_zero")
+    dt, (kn, kms) = timed_steps(C, torch, step, args.steps, "agms_build")
     rows_g, est, flag = C.agms_estimate([x[5] for x in tabs], [x[6] for x in tabs])
     torch.cuda.synchronize()
     # Fast-AGMS on the same tables: build time and the merged estimate
@@ -976,18 +995,20 @@ def run_job6a(args):
     torch.cuda.synchronize()
     n_sel = dq.n_selected.cpu().tolist()
 
-    C.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        row_est, est, flags = step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    C.profile_enable(False)
-    prof = {k: C.profile_take(k) for k in
-            ["fill_zero", "scan_sketch", "slab_reduce", "wide_compact",
-             "wide_hash", "sort_rows", "node", "tri_order", "tri_lane",
-             "finish"]}
+    out_last = []
+
+    def step_keep():
+        out_last[:] = [step()]
+
+    dt1, scan_prof = timed_steps(C, torch, step_keep, args.steps, "scan_sketch")
+    dt = dt1 * args.steps
+    row_est, est, flags = out_last[0]
+    # the other kernels' times: a second pass with every kernel's events
+    prof = profiled_steps(C, torch, step, args.steps,
+                          ["fill_zero", "scan_sketch", "slab_reduce", "wide_compact",
+                           "wide_hash", "sort_rows", "node", "tri_order", "tri_lane",
+                           "generic", "finish"])
+    prof["scan_sketch"] = scan_prof
 
     ms_step = dt * 1e3 / args.steps
     rows_per_step = sum(tb.n_rows for tb in q.tables)
@@ -1000,7 +1021,7 @@ def run_job6a(args):
     build_ms_step = sum(prof[k][1] for k in ["fill_zero", "scan_sketch", "slab_reduce",
                                              "wide_compact", "wide_hash"]) / args.steps
     est_ms_step = sum(prof[k][1] for k in ["sort_rows", "node", "tri_order",
-                                           "tri_lane", "finish"]) / args.steps
+                                           "tri_lane", "generic", "finish"]) / args.steps
     kernel_ms = {k: v[1] / args.steps for k, v in prof.items()}
     scan_s = kernel_ms["scan_sketch"] / 1e3
     scan_tops = updates * OPS_PER_HASH_UPDATE / scan_s / 1e12

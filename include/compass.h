@@ -519,9 +519,13 @@ compass_status compass_enumerate_greedy(int32_t n_tables, int32_t n_edges,
  * compass_profile_take(name) waits for the recorded events of kernel `name`
  * ("scan_sketch", "slab_reduce", "wide_compact", "wide_hash", "fill_zero",
  * "sort_rows", "node", "tri_order", "tri_lane", "finish", "scan2d",
- * "chain3", "agms_build", "agms_estimate"),
- * returns their count and summed elapsed milliseconds, and forgets them. */
+ * "chain3", "agms_build", "agms_estimate", "generic"),
+ * returns their count and summed elapsed milliseconds, and forgets them.
+ * compass_profile_select(names) restricts the recording to the kernels in
+ * the comma-separated list `names` (NULL or "": every kernel), so that a
+ * timed region pays for the events of the kernels it measures only. */
 compass_status compass_profile_enable(int32_t on);
+compass_status compass_profile_select(const char *names);
 compass_status compass_profile_take(const char *name, int64_t *count,
                                     double *total_ms);
 

@@ -86,6 +86,8 @@ def lib():
             ctypes.POINTER(JoinGraph), ctypes.POINTER(ctypes.c_uint64),
             ctypes.c_int32, vp, vp, vp, vp]
         L.compass_estimate.restype = ctypes.c_int32
+        L.compass_profile_select.argtypes = [ctypes.c_char_p]
+        L.compass_profile_select.restype = ctypes.c_int32
         L.compass_release.argtypes = []
         L.compass_release.restype = ctypes.c_int32
         L.compass_last_error.argtypes = []
@@ -158,6 +160,12 @@ def release():
 
 def profile_enable(on: bool = True):
     _check(lib().compass_profile_enable(1 if on else 0))
+
+
+def profile_select(names=None):
+    """Records only the kernels named (a list of names; None: every kernel)."""
+    arg = None if not names else ",".join(names).encode()
+    _check(lib().compass_profile_select(arg))
 
 
 def profile_take(name: str):

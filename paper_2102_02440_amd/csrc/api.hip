@@ -198,6 +198,7 @@ static bool g_prof_on = false;
 static std::vector<ProfRec> g_prof;
 // set while an entry point that must not allocate runs: no timing events
 static bool g_prof_suppressed = false;
+static std::vector<std::string> g_prof_sel;  // empty: every kernel
 
 struct ProfScope {
   ProfRec rec;
@@ -205,6 +206,8 @@ struct ProfScope {
   hipStream_t st;
   ProfScope(const char *name, hipStream_t s)
       : on(g_prof_on && !g_prof_suppressed), st(s) {
+    if (on && !g_prof_sel.empty())
+      on = std::find(g_prof_sel.begin(), g_prof_sel.end(), name) != g_prof_sel.end();
     if (!on) return;
     rec.name = name;
     (void)hipEventCreate(&rec.a);
@@ -227,6 +230,22 @@ extern "C" compass_status compass_profile_enable(int32_t on) {
 // Synchronises the recorded events and returns, for kernel `name`, the
 // number of launches and their total time in milliseconds; then forgets
 // every record of that name.
+extern "C" compass_status compass_profile_select(const char *names) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_prof_sel.clear();
+  if (!names) return COMPASS_OK;
+  std::string cur;
+  for (const char *c = names;; ++c) {
+    if (*c == ',' || *c == 0) {
+      if (!cur.empty()) g_prof_sel.push_back(cur);
+      cur.clear();
+      if (*c == 0) break;
+    } else {
+      cur += *c;
+    }
+  }
+  return COMPASS_OK;
+}
 extern "C" compass_status compass_profile_take(const char *name,
                                                int64_t *count,
                                                double *total_ms) {
@@ -1382,6 +1401,9 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
                               ((lp + kOrderTile - 1) / kOrderTile) *
                               (kOrderTile + 1));
   const size_t o_tseg = carve(sizeof(int32_t) * np * d * (kFastSegs + 1));
+  const int pcap = std::min((int)lp, kOrderCap) + 1;
+  const size_t o_tpiece = carve(sizeof(TriPiece) * np * d * (size_t)pcap);
+  const size_t o_tsegp = carve(sizeof(int32_t) * np * d * (kFastSegs + 1));
   const size_t o_part = carve(16ull * std::max(1, pl.n_partial_slots) * d);
   const size_t o_gnodes = carve(sizeof(GenNode) * std::max<size_t>(1, pl.gnodes.size()));
   const size_t o_gplans = carve(sizeof(GenPlan) * std::max<size_t>(1, pl.gplans.size()));
@@ -1440,6 +1462,9 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.tkey = reinterpret_cast<uint32_t *>(base + o_tkey);
   B.tpre = reinterpret_cast<TriPre *>(base + o_tpre);
   B.tseg = reinterpret_cast<int32_t *>(base + o_tseg);
+  B.tpiece = reinterpret_cast<TriPiece *>(base + o_tpiece);
+  B.tsegp = reinterpret_cast<int32_t *>(base + o_tsegp);
+  B.Pcap = pcap;
   B.partial = reinterpret_cast<u128 *>(base + o_part);
   B.counter_bits = g->counter_bits;
   B.d = d;
@@ -1862,6 +1887,7 @@ extern "C" compass_status compass_release(void) {
   for (auto &kv : ds.scratch)
     if (kv.second.p) HIP_OK(hipFree(kv.second.p));
   ds.scratch.clear();
+
   for (int k = 0; k < DeviceState::kRing; ++k) {
     if (ds.pinned[k]) HIP_OK(hipHostFree(ds.pinned[k]));
     ds.pinned[k] = nullptr;

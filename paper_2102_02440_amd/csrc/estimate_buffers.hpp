@@ -41,6 +41,17 @@ struct TriPre {
   int32_t pad;
 };
 
+// One piece of the two-child sweep: a maximal same-child run of [z, L)
+// cut at the ordering tiles' starts, with the tile-local prefix sums at its
+// ends (long runs only: the sweep sums those by search).  40 bytes.
+struct TriPiece {
+  int64_t m0, x0;   // prefixes of M and v * M at lo
+  int32_t lo, hi;   // positions [lo, hi]
+  int32_t info;     // bit 0: child slot; bit 1: summed by search; bits 2..: tile
+  int32_t v0, v1;   // prefixes of v at lo and at hi + 1
+  int32_t pad;
+};
+
 // One element of a node's merged list, gathered once by the merge so that
 // the node's sweeps read consecutive records (32 bytes).
 struct NodeRec {
@@ -66,13 +77,15 @@ struct EstBuffers {
   uint32_t *tkey;             // [prep slot][row][Lprep] run-ordered keys
   TriPre *tpre;               // [prep slot][row][tile][kOrderTile + 1]
   int32_t *tseg;              // [prep slot][row][kFastSegs + 1] sweep bounds
+  TriPiece *tpiece;           // [prep slot][row][Pcap] run pieces
+  int32_t *tsegp;             // [prep slot][row][kFastSegs + 1] piece bounds
   u128 *partial;              // [slot][row]
   int32_t counter_bits;
   int32_t d;
   int32_t w;
   int32_t Lmax;
   int32_t Lprep;
-  int32_t pad;
+  int32_t Pcap;               // run pieces per (prep slot, row)
 };
 
 }  // namespace compass

@@ -44,6 +44,7 @@
 #include "estimate_buffers.hpp"
 #include "certificate.hpp"
 #include "lds_stage.hpp"
+#include "bitonic.hpp"
 
 namespace compass {
 
@@ -155,25 +156,14 @@ __global__ __launch_bounds__(kSortThreads) void sort_chunk_kernel(
     for (int u = 0; u < kU; ++u) {
       const int t = (int)threadIdx.x + u * kSortThreads;
       const int j = c0 + t;
-      if (t < n)
-        sk[t] = j < w ? (abs_u64(v[u]) << 16) | (uint64_t)j : ~0ull;
+      // keys beyond the row (and the padding up to kSortPad) are all ones
+      if (t < (n < kSortPad ? kSortPad : n))
+        sk[t] = (t < n && j < w) ? (abs_u64(v[u]) << 16) | (uint64_t)j : ~0ull;
     }
   }
   __syncthreads();
-  for (int k = 2; k <= n; k <<= 1) {
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int t = threadIdx.x; t < (n >> 1); t += kSortThreads) {
-        const int i = 2 * t - (t & (jj - 1));
-        const int ixj = i + jj;
-        const uint64_t a = sk[i], b = sk[ixj];
-        if ((a > b) == ((i & k) == 0)) {
-          sk[i] = b;
-          sk[ixj] = a;
-        }
-      }
-      __syncthreads();
-    }
-  }
+  bitonic_sort_lds<kSortThreads, kSortChunk / kSortThreads>(
+      reinterpret_cast<unsigned long long *>(sk), n < kSortPad ? kSortPad : n);
   uint64_t *tmp = B.sort_tmp + ((size_t)side * B.d + row) * (size_t)w2;
   for (int t = threadIdx.x; t < n; t += kSortThreads) tmp[c0 + t] = sk[t];
 }
@@ -957,8 +947,8 @@ __device__ __forceinline__ size_t tpre_index(const EstBuffers &B,
 __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
     const TriTask *tasks, EstBuffers B) {
   __shared__ uint64_t okey[kOrderTile];
-  __shared__ int64_t scm[kOrderThreads], scx[kOrderThreads];
-  __shared__ uint32_t scv[kOrderThreads];
+  __shared__ int64_t scm[kOrderThreads / 64], scx[kOrderThreads / 64];
+  __shared__ uint32_t scv[kOrderThreads / 64];
   const TriTask &T = tasks[blockIdx.z];
   if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
   if (tri_path(*(ConstTask *)&T, B) != kTriFast) return;
@@ -988,7 +978,7 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int q = (int)threadIdx.x + u * kOrderThreads;
-      if (q >= n2) continue;
+      if (q >= (n2 < 128 ? 128 : n2)) continue;
       uint64_t k = ~0ull;
       if (q < nt) {
         const uint64_t rl = (uint64_t)(max(rlo[u], t0) - t0);
@@ -998,20 +988,9 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
     }
   }
   __syncthreads();
-  for (int k = 2; k <= n2; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < (n2 >> 1); t += kOrderThreads) {
-        const int i = 2 * t - (t & (j - 1));
-        const int ixj = i + j;
-        const uint64_t a = okey[i], b = okey[ixj];
-        if ((a > b) == ((i & k) == 0)) {
-          okey[i] = b;
-          okey[ixj] = a;
-        }
-      }
-      __syncthreads();
-    }
-  }
+  // padding keys (all ones) sort last
+  bitonic_sort_lds<kOrderThreads, 2>(
+      reinterpret_cast<unsigned long long *>(okey), n2 < 128 ? 128 : n2);
   // each thread: a consecutive chunk of at most kOrderPer sorted slots;
   // all of its element loads are issued before the sums
   constexpr int kOrderPer = kOrderTile / kOrderThreads;
@@ -1042,28 +1021,37 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
     sx += (uint64_t)vm[u];
     sv += (uint32_t)vv[u];
   }
-  scm[threadIdx.x] = (int64_t)sm;
-  scx[threadIdx.x] = (int64_t)sx;
-  scv[threadIdx.x] = sv;
-  __syncthreads();
-  for (int off = 1; off < kOrderThreads; off <<= 1) {
-    int64_t am = 0, ax = 0;
-    uint32_t av = 0;
-    if ((int)threadIdx.x >= off) {
-      am = scm[threadIdx.x - off];
-      ax = scx[threadIdx.x - off];
-      av = scv[threadIdx.x - off];
+  // inclusive scans of the three thread sums: within each wave by
+  // shuffles, then over the earlier waves' totals (wrapping)
+  unsigned long long im = sm, ix = sx;
+  uint32_t iv = sv;
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long a = __shfl_up(im, off);
+    const unsigned long long c = __shfl_up(ix, off);
+    const uint32_t e = (uint32_t)__shfl_up((int)iv, off);
+    if (lane >= off) {
+      im += a;
+      ix += c;
+      iv += e;
     }
-    __syncthreads();
-    scm[threadIdx.x] = (int64_t)((uint64_t)scm[threadIdx.x] + (uint64_t)am);
-    scx[threadIdx.x] = (int64_t)((uint64_t)scx[threadIdx.x] + (uint64_t)ax);
-    scv[threadIdx.x] += av;
-    __syncthreads();
+  }
+  if (lane == 63) {
+    scm[wv] = (int64_t)im;
+    scx[wv] = (int64_t)ix;
+    scv[wv] = iv;
+  }
+  __syncthreads();
+  for (int k = 0; k < wv; ++k) {
+    im += (uint64_t)scm[k];
+    ix += (uint64_t)scx[k];
+    iv += scv[k];
   }
   // exclusive start of my chunk, then its running sums (wrapping)
-  uint64_t em = (uint64_t)scm[threadIdx.x] - sm;
-  uint64_t ex = (uint64_t)scx[threadIdx.x] - sx;
-  uint32_t ev = scv[threadIdx.x] - sv;
+  uint64_t em = (uint64_t)im - sm;
+  uint64_t ex = (uint64_t)ix - sx;
+  uint32_t ev = iv - sv;
   TriPre *E = B.tpre + tpre_index(B, slot_row, tile, 0);
 #pragma unroll
   for (int u = 0; u < kOrderPer; ++u) {
@@ -1082,9 +1070,9 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
   }
   if (threadIdx.x == kOrderThreads - 1) {
     TriPre o;
-    o.m = scm[threadIdx.x];
-    o.x = scx[threadIdx.x];
-    o.v = (int32_t)scv[threadIdx.x];
+    o.m = (int64_t)im;
+    o.x = (int64_t)ix;
+    o.v = (int32_t)iv;
     o.pad = 0;
     E[nt] = o;
   }
@@ -1097,7 +1085,8 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
 // in ascending position order, bounds[kFastSegs] = L.
 __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
     const TriTask *tasks, EstBuffers B) {
-  __shared__ int s_cnt[kSegThreads];
+  extern __shared__ int32_t s_ps[];  // piece starts (kOrderCap + 1)
+  __shared__ int s_rc[kSegThreads], s_pc[kSegThreads];
   const TriTask &T = tasks[blockIdx.x];
   if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
   if (tri_path(*(ConstTask *)&T, B) != kTriFast) return;
@@ -1113,37 +1102,93 @@ __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
   }
   const TriElemN *el = B.prepn + slot_row * (size_t)B.Lprep;
   int32_t *bounds = B.tseg + slot_row * (kFastSegs + 1);
+  int32_t *pbounds = B.tsegp + slot_row * (kFastSegs + 1);
   // n <= kOrderCap positions: kSegPer consecutive ones per lane, loaded
-  // together
+  // together.  Run starts: z and every position that begins a same-child
+  // run; piece starts: run starts and ordering tile starts.
   const int q0 = z + (int)threadIdx.x * kSegPer;
-  uint32_t starts = 0;  // bit u: position q0 + u starts a run
+  uint32_t rs = 0, ps = 0;
+  {
+    int32_t rl[kSegPer];  // every load in flight together (clamped)
 #pragma unroll
-  for (int u = 0; u < kSegPer; ++u) {
-    const int p = q0 + u;
-    if (p < L && (p == z || el[p].run_lo == p)) starts |= 1u << u;
+    for (int u = 0; u < kSegPer; ++u) rl[u] = el[min(q0 + u, L - 1)].run_lo;
+#pragma unroll
+    for (int u = 0; u < kSegPer; ++u) {
+      const int p = q0 + u;
+      if (p >= L) continue;
+      const bool r = p == z || rl[u] == p;
+      if (r) rs |= 1u << u;
+      if (r || (p - z) % kOrderTile == 0) ps |= 1u << u;
+    }
   }
-  const int c = __popc(starts);
-  s_cnt[threadIdx.x] = c;
+  const int rc = __popc(rs), pc = __popc(ps);
+  s_rc[threadIdx.x] = rc;
+  s_pc[threadIdx.x] = pc;
   __syncthreads();
   for (int off = 1; off < kSegThreads; off <<= 1) {
-    const int a = (int)threadIdx.x >= off ? s_cnt[threadIdx.x - off] : 0;
+    const int a = (int)threadIdx.x >= off ? s_rc[threadIdx.x - off] : 0;
+    const int b = (int)threadIdx.x >= off ? s_pc[threadIdx.x - off] : 0;
     __syncthreads();
-    s_cnt[threadIdx.x] += a;
+    s_rc[threadIdx.x] += a;
+    s_pc[threadIdx.x] += b;
     __syncthreads();
   }
-  const int R = s_cnt[kSegThreads - 1];
-  int g = s_cnt[threadIdx.x] - c;  // index of my first run start
+  const int R = s_rc[kSegThreads - 1];
+  const int P = s_pc[kSegThreads - 1];
+  int g = s_rc[threadIdx.x] - rc;  // index of my first run start
+  int h = s_pc[threadIdx.x] - pc;  // index of my first piece start
   if (threadIdx.x == 0) {
     bounds[0] = z;
     bounds[kFastSegs] = L;
+    pbounds[0] = 0;
+    pbounds[kFastSegs] = P;
     for (int k = 1; k < kFastSegs; ++k)
-      if ((int)(((int64_t)R * k) / kFastSegs) >= R) bounds[k] = L;
+      if ((int)(((int64_t)R * k) / kFastSegs) >= R) {
+        bounds[k] = L;
+        pbounds[k] = P;
+      }
+    s_ps[P] = L;
   }
-  for (; starts; starts &= starts - 1) {
-    const int p = q0 + __builtin_ctz(starts);
-    for (int k = 1; k < kFastSegs; ++k)
-      if ((int)(((int64_t)R * k) / kFastSegs) == g) bounds[k] = p;
-    ++g;
+  // groups of equal run count, cut at run starts (which are piece starts)
+  for (uint32_t m = ps; m; m &= m - 1) {
+    const int u = __builtin_ctz(m);
+    const int p = q0 + u;
+    s_ps[h] = p;
+    if ((rs >> u) & 1u) {
+      for (int k = 1; k < kFastSegs; ++k)
+        if ((int)(((int64_t)R * k) / kFastSegs) == g) {
+          bounds[k] = p;
+          pbounds[k] = h;
+        }
+      ++g;
+    }
+    ++h;
+  }
+  __syncthreads();
+  // the pieces: child, summed by search (runs of at least kSearchMin
+  // elements in [z, L)), tile, and the tile-local prefixes at both ends
+  TriPiece *out = B.tpiece + slot_row * (size_t)B.Pcap;
+  const TriPre *pre0 = B.tpre + tpre_index(B, slot_row, 0, 0);
+  for (int i = threadIdx.x; i < P; i += kSegThreads) {
+    const int lo = s_ps[i], hi = s_ps[i + 1] - 1;
+    const TriElemN e = el[lo];
+    const bool lng = e.run_hi - max(e.run_lo, z) + 1 >= kSearchMin;
+    const int tile = (lo - z) / kOrderTile;
+    TriPiece o;
+    o.lo = lo;
+    o.hi = hi;
+    o.info = (int32_t)((e.kc >> 31) | (lng ? 2u : 0u) | ((uint32_t)tile << 2));
+    o.m0 = o.x0 = 0;
+    o.v0 = o.v1 = o.pad = 0;
+    if (lng) {
+      const int ts = z + tile * kOrderTile;
+      const TriPre a = pre0[(size_t)tile * (kOrderTile + 1) + (lo - ts)];
+      o.m0 = a.m;
+      o.x0 = a.x;
+      o.v0 = a.v;
+      o.v1 = pre0[(size_t)tile * (kOrderTile + 1) + (hi + 1 - ts)].v;
+    }
+    out[i] = o;
   }
 }
 
@@ -1157,7 +1202,12 @@ __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
 // A run piece is summed element by element, or, when the run is long and
 // tri_order_kernel has ordered the list, by one binary search over the
 // run-ordered keys (staged in LDS) and two prefix-sum reads.
-constexpr int kSearchMin = 8;  // shortest run summed by search
+
+// a run piece as the sweep reads it (wave-uniform)
+struct PieceIn {
+  int lo, hi, info, v0, v1;
+  int64_t m0, x0;
+};
 
 struct SegOut {
   u128 G;
@@ -1229,64 +1279,8 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   ConstElemN *el = (ConstElemN *)(B.prepn + slot_row * (size_t)B.Lprep);
   int64_t A0 = 0, A1 = 0, X0 = 0, X1 = 0;
   u128 G = 0;
-  constexpr int kGroup = 8;
-  int pos = top;
-  while (pos >= bottom) {
-    const uint32_t c = el[pos].kc >> 31;  // the run's child (uniform)
-    const int run_lo = el[pos].run_lo;
-    const int lo = max(run_lo, bottom);
-    const uint32_t kf = c ? kf1 : kf0;
-    FastRun r;
-    if (ordered && el[pos].run_hi - max(run_lo, z) + 1 >= kSearchMin) {
-      // piece [lo, pos] of a long run, cut at its ordering tile's start:
-      // its elements below kf are the positions [lo, p)
-      const int tile = (pos - z) / kOrderTile;
-      const int ts = z + tile * kOrderTile;
-      const int lo2 = max(lo, ts);
-      const int p = lo2 + lds_lower_bound(skey + (lo2 - z), pos - lo2 + 1, kf);
-      const size_t eb = tpre_index(B, slot_row, tile, 0) - (size_t)ts;
-      ConstPre &e0 = ((ConstPre *)B.tpre)[eb + lo2];
-      const int64_t m0 = e0.m, x0 = e0.x;
-      const int32_t v0 = e0.v;
-      const int32_t v1 = ((ConstPre *)B.tpre)[eb + pos + 1].v;
-      const TriPre ep = B.tpre[eb + p];
-      r.mb = (int64_t)((uint64_t)ep.m - (uint64_t)m0);
-      r.xb = (int64_t)((uint64_t)ep.x - (uint64_t)x0);
-      r.vb = (int32_t)((uint32_t)ep.v - (uint32_t)v0);
-      r.nb = p - lo2;
-      r.vrun = (int32_t)((uint32_t)v1 - (uint32_t)v0);
-      r.nrun = pos - lo2 + 1;
-      pos = lo2 - 1;
-    } else {
-      r.mb = r.xb = 0;
-      r.vb = r.nb = 0;
-      r.vrun = r.nrun = 0;
-      for (; pos - (kGroup - 1) >= lo; pos -= kGroup) {
-        int32_t v[kGroup];
-        uint32_t kc[kGroup];
-        int64_t mu[kGroup], vm[kGroup];
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
-          ConstElemN &e = el[pos - u];
-          v[u] = e.v;
-          kc[u] = e.kc;
-          mu[u] = e.mu;
-          vm[u] = e.vm;
-        }
-        // issue the whole group's scalar loads before the first use
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-          __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u)
-          fast_elem(r, kf, v[u], kc[u], mu[u], vm[u]);
-      }
-      for (; pos >= lo; --pos) {
-        ConstElemN &e = el[pos];
-        fast_elem(r, kf, e.v, e.kc, e.mu, e.vm);
-      }
-    }
-    // close the run: its terms times the other child's running sum
+  // close a run piece: its terms times the other child's running sum
+  auto close = [&](uint32_t c, const FastRun &r) {
     const int64_t cc = c ? C1 : C0;
     const int64_t x = r.xb + cc * (int64_t)(r.vrun - r.vb);
     const int64_t arun = r.mb + cc * (int64_t)(r.nrun - r.nb);
@@ -1298,6 +1292,116 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
       G += mul_s64_s64(x, A1);
       A0 += arun;
       X0 += x;
+    }
+  };
+  // element by element over [lo, hi], descending
+  auto elements = [&](int lo, int hi, uint32_t kf, FastRun &r) {
+    constexpr int kGroup = 8;
+    r.mb = r.xb = 0;
+    r.vb = r.nb = 0;
+    r.vrun = r.nrun = 0;
+    int pos = hi;
+    for (; pos - (kGroup - 1) >= lo; pos -= kGroup) {
+      int32_t v[kGroup];
+      uint32_t kc[kGroup];
+      int64_t mu[kGroup], vm[kGroup];
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        ConstElemN &e = el[pos - u];
+        v[u] = e.v;
+        kc[u] = e.kc;
+        mu[u] = e.mu;
+        vm[u] = e.vm;
+      }
+      // issue the whole group's scalar loads before the first use
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u)
+        __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u)
+        fast_elem(r, kf, v[u], kc[u], mu[u], vm[u]);
+    }
+    for (; pos >= lo; --pos) {
+      ConstElemN &e = el[pos];
+      fast_elem(r, kf, e.v, e.kc, e.mu, e.vm);
+    }
+  };
+  if (ordered) {
+    // the pieces of run group kFastSegs - 1 - seg (tri_seg_kernel), 64 at a
+    // time: lane k loads piece b0 + k, the sweep broadcasts it with
+    // readlane; the next long piece's search and prefix load are issued
+    // before the current piece is summed
+    const int32_t *sp = B.tsegp + slot_row * (kFastSegs + 1);
+    const int pb = __builtin_amdgcn_readfirstlane(sp[kFastSegs - 1 - seg]);
+    const int pe = __builtin_amdgcn_readfirstlane(sp[kFastSegs - seg]);
+    const TriPiece *pcs = B.tpiece + slot_row * (size_t)B.Pcap;
+    const TriPre *pre0 = B.tpre + tpre_index(B, slot_row, 0, 0);
+    const int wl = (int)threadIdx.x & 63;
+    for (int hb = pe; hb > pb; hb -= 64) {
+      const int b0 = max(pb, hb - 64);
+      const int nb = hb - b0;
+      const TriPiece dv = pcs[b0 + min(wl, nb - 1)];
+      auto get = [&](int k, PieceIn &o) {
+        o.lo = __builtin_amdgcn_readlane(dv.lo, k);
+        o.hi = __builtin_amdgcn_readlane(dv.hi, k);
+        o.info = __builtin_amdgcn_readlane(dv.info, k);
+        o.v0 = __builtin_amdgcn_readlane(dv.v0, k);
+        o.v1 = __builtin_amdgcn_readlane(dv.v1, k);
+        o.m0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                              (int)((uint64_t)dv.m0 >> 32), k) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int)dv.m0, k));
+        o.x0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                              (int)((uint64_t)dv.x0 >> 32), k) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int)dv.x0, k));
+      };
+      // position of the first key >= kf in a long piece, and its prefix
+      auto search = [&](const PieceIn &o, int &p, TriPre &ep) {
+        const uint32_t kf = (o.info & 1) ? kf1 : kf0;
+        p = o.lo + lds_lower_bound(skey + (o.lo - z), o.hi - o.lo + 1, kf);
+        const int tile = o.info >> 2;
+        ep = pre0[(size_t)tile * (kOrderTile + 1) + (p - z - tile * kOrderTile)];
+      };
+      PieceIn cur, nxt;
+      int pc = 0, pn = 0;
+      TriPre ec, en;
+      ec.m = ec.x = 0;
+      ec.v = ec.pad = 0;
+      en = ec;
+      get(nb - 1, cur);
+      if (cur.info & 2) search(cur, pc, ec);
+      for (int k = nb - 1; k >= 0; --k) {
+        if (k > 0) {
+          get(k - 1, nxt);
+          if (nxt.info & 2) search(nxt, pn, en);
+        }
+        const uint32_t c = cur.info & 1;
+        FastRun r;
+        if (cur.info & 2) {
+          r.mb = (int64_t)((uint64_t)ec.m - (uint64_t)cur.m0);
+          r.xb = (int64_t)((uint64_t)ec.x - (uint64_t)cur.x0);
+          r.vb = (int32_t)((uint32_t)ec.v - (uint32_t)cur.v0);
+          r.nb = pc - cur.lo;
+          r.vrun = (int32_t)((uint32_t)cur.v1 - (uint32_t)cur.v0);
+          r.nrun = cur.hi - cur.lo + 1;
+        } else {
+          elements(cur.lo, cur.hi, c ? kf1 : kf0, r);
+        }
+        close(c, r);
+        cur = nxt;
+        pc = pn;
+        ec = en;
+      }
+    }
+  } else {
+    // unordered list: runs element by element, segments by position
+    int pos = top;
+    while (pos >= bottom) {
+      const uint32_t c = el[pos].kc >> 31;  // the run's child (uniform)
+      const int lo = max(el[pos].run_lo, bottom);
+      FastRun r;
+      elements(lo, pos, c ? kf1 : kf0, r);
+      close(c, r);
+      pos = lo - 1;
     }
   }
   __syncthreads();  // the key stage becomes the segment results
@@ -1487,6 +1591,11 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
   const SubplanTask S = sps[blockIdx.x];
   const int d = B.d;
   const int i = threadIdx.x;
+  // the fp64 rows are read only when the 128-bit ones are not certified
+  const bool cert = S.type == kSpSingle ||
+                    (S.type != kSpUnsupported &&
+                     subplan_certified(S, B.n_sel, n_tables, B.w));
+  const bool use_approx = !cert && S.approx_slot >= 0;
   if (i < d) {
     u128 x = 0;
     if (S.type == kSpSingle) {
@@ -1508,10 +1617,19 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
       for (int u = 0; u < 8; ++u) x += acc[u];
     }
     xs[i] = x;
-    if (S.approx_slot >= 0) {
+    if (use_approx) {
+      double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int z = 0;
+      for (; z + 8 <= S.n_approx; z += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          acc[u] += approx[((size_t)S.approx_slot + z + u) * d + i];
+      }
+      for (; z < S.n_approx; ++z)
+        acc[0] += approx[((size_t)S.approx_slot + z) * d + i];
       double a = 0;
-      for (int z = 0; z < S.n_approx; ++z)
-        a += approx[((size_t)S.approx_slot + z) * d + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a += acc[u];
       xd[i] = a;
     }
     if (row_est) {
@@ -1526,9 +1644,7 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
     flags[blockIdx.x] = 2;
     return;
   }
-  const bool cert = S.type == kSpSingle ||
-                    subplan_certified(S, B.n_sel, n_tables, B.w);
-  if (!cert && S.approx_slot >= 0) {
+  if (use_approx) {
     // the 128-bit values may have wrapped: the median of the fp64
     // evaluation, flagged approximate
     for (int a = 1; a < d; ++a) {
@@ -1631,8 +1747,8 @@ hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(tri_seg_kernel, dim3(n, B.d), dim3(kSegThreads), 0, st,
-                     tasks, B);
+  hipLaunchKernelGGL(tri_seg_kernel, dim3(n, B.d), dim3(kSegThreads),
+                     (size_t)(kOrderCap + 1) * sizeof(int32_t), st, tasks, B);
   return hipGetLastError();
 }
 

@@ -9,6 +9,8 @@ constexpr int kMaxChild = 6;
 constexpr int kNodeThreads = 1024;
 constexpr int kSortThreads = 256;
 constexpr int kSortChunk = 1024;  // keys sorted by one workgroup
+constexpr int kSortPad = 64 * (kSortChunk / kSortThreads);  // shortest sort:
+                                  // the keys one wave holds in registers
 constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
 constexpr int kNodeStageBytes = 96 * 1024;  // node merge: staged magnitudes
@@ -23,10 +25,11 @@ constexpr int kN1MaxChunks = (kMaxEstimateW + kN1Chunk - 1) / kN1Chunk;
 constexpr int kPrepThreads = 256;  // apex preparation
 constexpr int kPrepPer = 4;
 constexpr int kPrepChunk = kPrepThreads * kPrepPer;
-constexpr int kOrderThreads = 256;
+constexpr int kOrderThreads = 1024;
 constexpr int kSegThreads = 1024;
 constexpr int kSegPer = 16;
 constexpr int kFastSegs = 4;  // sweep segments per cut bucket
+constexpr int kSearchMin = 8;  // shortest run the sweep sums by search
 constexpr int kOrderTile = 2048;  // positions ordered by one workgroup
 constexpr int kOrderCap = 16384;  // longest two-child apex list run-ordered
 constexpr int kFastStageBytes = kOrderCap * 4;  // its keys, staged in LDS
