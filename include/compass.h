@@ -117,7 +117,10 @@ typedef struct {
  * buffer takes at most 8.5 GiB of scratch (environment: COMPASS_TWO_PHASE_
  * BYTES sets that budget, COMPASS_SURVIVOR_CAP_ROWS caps the buffer's rows;
  * both exist to force many batches in tests).  E_RANGE if one batch of
- * 4096 rows cannot fit the budget. */
+ * 4096 rows cannot fit the budget.  COMPASS_SERIAL=1 (a debugging mode,
+ * read at each call) builds with one chunk per group of sketch rows and a
+ * single compaction workgroup, so that no two workgroups combine partial
+ * counters: its results equal the default launch's bit for bit. */
 compass_status compass_sketch_build(int64_t n_rows,
                                     const void *const *pred_cols,
                                     int32_t n_pred_cols,
@@ -290,6 +293,65 @@ compass_status compass_sketch_build_2d(int64_t n_rows,
                                        int32_t counter_bits, int32_t accumulate,
                                        void *counters, int64_t *n_selected,
                                        hipStream_t stream);
+
+/* compass_sketch_build_kd -- the partitioned sketch of a table that takes
+ * part in k = 2 .. 4 joins (Section 5.1: a table with k joins has a k-D
+ * tensor as its sketch): for every row that satisfies the conjunction of
+ * `preds`, with join keys a_1 .. a_k, and every sketch row i, adds
+ * prod_m xi_{m,i}(a_m) to entry [h_{1,i}(a_1)] .. [h_{k,i}(a_k)] of row i's
+ * w_1 x .. x w_k tensor (row-major), (h_{m,i}, xi_{m,i}) being row i's
+ * functions of joins[m].seeds.  k = 2 is compass_sketch_build_2d.
+ *   joins     host array of k specs (key column, dtype, seeds d x 6; the
+ *             counters fields are ignored)
+ *   d         1 .. 48 / k
+ *   w         host array of k widths, each 1 .. 2^20, product <= 2^28
+ *   counters  device, d x w_1 x .. x w_k, int32 or int64
+ * Joins 2 .. k form the second dimension of the binned build (their
+ * indices flattened); other arguments, errors and exactness as for
+ * compass_sketch_build_2d. */
+compass_status compass_sketch_build_kd(int64_t n_rows,
+                                       const void *const *pred_cols,
+                                       int32_t n_pred_cols,
+                                       const compass_pred *preds,
+                                       int32_t n_preds,
+                                       const compass_sketch_spec *joins,
+                                       int32_t k, int32_t d, const int32_t *w,
+                                       int32_t counter_bits, int32_t accumulate,
+                                       void *counters, int64_t *n_selected,
+                                       hipStream_t stream);
+
+/* A tree of tables with partitioned sketches (Section 5.1): table t's
+ * sketch has one dimension per incident edge, in increasing edge id, of
+ * that edge's width; a table with one join has a d x w sketch, one with k
+ * joins a d x w_e1 x .. x w_ek tensor (compass_sketch_build_kd, keys in
+ * the same edge order; both sides of an edge share its seeds). */
+typedef struct {
+  int32_t n_tables;        /* 2 .. 64 */
+  int32_t n_edges;         /* n_tables - 1 (a tree) */
+  int32_t d;               /* 1 .. 32 */
+  int32_t counter_bits;    /* 32 or 64, all tables */
+  const int32_t *edge_u;   /* host, n_edges */
+  const int32_t *edge_v;   /* host, n_edges */
+  const int32_t *width;    /* host, n_edges: buckets of each join */
+  const void *const *tensor;  /* host array of n_tables device pointers */
+  const int64_t *n_selected;  /* device, n_tables: selected rows */
+} compass_tensor_graph;
+
+/* compass_estimate_partitioned -- the join size estimate of the whole tree
+ * from partitioned sketches (Section 5.1): for each sketch row i,
+ *   X_i = sum over a bucket j_e of every edge e of
+ *         prod over tables t of T_t[i][j_e for the edges e at t],
+ * exact in 128-bit two's complement (message passing from the leaves to
+ * table 0); est = median over rows (even d: mean of the two middle
+ * values), round-to-nearest-even; flags = COMPASS_FLAG_EXACT when the
+ * product of the tables' selected rows is below 2^127 (it bounds |X_i|).
+ *   row_est  device, d values (may be NULL); est, flags device, 1 each
+ * E_GRAPH if the edges do not form a tree over the tables; E_UNSUPPORTED
+ * for a table with more than 4 joins; E_ARG for a tensor above 2^28
+ * entries per row. */
+compass_status compass_estimate_partitioned(const compass_tensor_graph *g,
+                                            compass_i128 *row_est, double *est,
+                                            int32_t *flags, hipStream_t stream);
 
 /* compass_estimate_chain3 -- the chain A join P join B (P joins A on its
  * first key and B on its second): for each sketch row i,

@@ -579,6 +579,94 @@ void oracle_sketch2d(const int64_t *keys1, const int64_t *keys2, int64_t n,
     }
 }
 
+/* Partitioned sketch of a table with k joins (Section 5.1: the sketch of a
+ * table with k joins is a k-dimensional tensor): for every row r and
+ * sketch row i, adds the product over joins m of xi_{m,i}(keys[m][r]) to
+ * entry [h_{1,i}(keys[0][r])] .. [h_{k,i}(keys[k-1][r])] of row i's tensor
+ * (row-major, widths w[0] .. w[k-1]).  seeds[m] is join m's d x 6 seed
+ * table. */
+void oracle_sketch_kd(const int64_t *const *keys, int32_t k, int64_t n,
+                      const uint64_t *const *seeds, int32_t d, const int64_t *w,
+                      int64_t *counters)
+{
+    int64_t size = 1;
+    for (int32_t m = 0; m < k; ++m) size *= w[m];
+    for (int64_t r = 0; r < n; ++r) {
+        for (int32_t i = 0; i < d; ++i) {
+            int64_t idx = 0;
+            int32_t sign = 1;
+            for (int32_t m = 0; m < k; ++m) {
+                int64_t b;
+                int32_t g;
+                oracle_hash(seeds[m] + 6 * i, keys[m][r], w[m], &b, &g);
+                idx = idx * w[m] + b;
+                sign *= g;
+            }
+            counters[(int64_t)i * size + idx] += (int64_t)sign;
+        }
+    }
+}
+
+/* Estimate of a join graph from partitioned sketches (Section 5.1): table
+ * t's sketch row i is a tensor with one dimension per incident edge (edges
+ * in increasing id, widths w[e]); the row value is the sum over every
+ * assignment of a bucket j_e to each edge e of the product over tables of
+ * their entries at those buckets, exact in 128-bit two's complement, taken
+ * literally: one term per assignment.  The estimate is the median over rows
+ * and the flag certifies the rows when the product of the tables' selected
+ * rows is below 2^127.
+ *   tensors[t]: d x prod of w over t's edges (int64); out_rows: d x 2 */
+void oracle_tensor_join(int32_t n_tables, int32_t n_edges, const int32_t *eu,
+                        const int32_t *ev, int32_t d, const int64_t *w,
+                        const int64_t *const *tensors, const int64_t *n_sel,
+                        uint64_t *out_rows, double *out_est, int32_t *out_flag)
+{
+    int32_t *j = (int32_t *)calloc((size_t)(n_edges > 0 ? n_edges : 1), sizeof(int32_t));
+    int64_t *size = (int64_t *)calloc((size_t)n_tables, sizeof(int64_t));
+    for (int32_t t = 0; t < n_tables; ++t) {
+        size[t] = 1;
+        for (int32_t e = 0; e < n_edges; ++e)
+            if (eu[e] == t || ev[e] == t) size[t] *= w[e];
+    }
+    u128 *rows = (u128 *)malloc(sizeof(u128) * (size_t)d);
+    for (int32_t i = 0; i < d; ++i) {
+        u128 x = 0;
+        for (int32_t e = 0; e < n_edges; ++e) j[e] = 0;
+        for (;;) {
+            u128 term = 1;
+            for (int32_t t = 0; t < n_tables; ++t) {
+                int64_t idx = 0;  /* the table's entry: its edges in id order */
+                for (int32_t e = 0; e < n_edges; ++e)
+                    if (eu[e] == t || ev[e] == t) idx = idx * w[e] + j[e];
+                term *= (u128)(i128)tensors[t][(int64_t)i * size[t] + idx];
+            }
+            x += term;
+            int32_t e = n_edges - 1;  /* next assignment */
+            while (e >= 0 && ++j[e] == w[e]) j[e--] = 0;
+            if (e < 0) break;
+        }
+        rows[i] = x;
+        out_rows[2 * i + 0] = (uint64_t)x;
+        out_rows[2 * i + 1] = (uint64_t)(x >> 64);
+    }
+    *out_est = median_of(rows, d);
+    /* |X_i| <= product of n_sel (the entries of a table's sketch row sum to
+     * at most its selected rows in absolute value) */
+    const u128 lim = (u128)1 << 127;
+    u128 b = 1;
+    int ok = 1;
+    for (int32_t t = 0; t < n_tables && ok; ++t) {
+        const u128 f = (u128)(n_sel[t] < 0 ? 0 : n_sel[t]);
+        if (f == 0) { b = 0; break; }
+        if (b > lim / f) ok = 0;
+        else b *= f;
+    }
+    *out_flag = ok && b < lim ? 1 : 0;
+    free(rows);
+    free(size);
+    free(j);
+}
+
 /* The three-table chain estimate of Section 5.1: for row i, the sum over
  * all entries (j1, j2) of A[j1] * P[j1][j2] * B[j2] (the matrix scaled by
  * the first sketch along its rows and by the second along its columns,

@@ -85,6 +85,14 @@ def _load():
                                         ctypes.c_int32, ctypes.c_int64,
                                         ctypes.c_int64, i64p]
         lib.oracle_sketch2d.restype = None
+        lib.oracle_sketch_kd.argtypes = [ctypes.POINTER(i64p), ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.POINTER(u64p),
+                                         ctypes.c_int32, i64p, i64p]
+        lib.oracle_sketch_kd.restype = None
+        lib.oracle_tensor_join.argtypes = [
+            ctypes.c_int32, ctypes.c_int32, i32p, i32p, ctypes.c_int32, i64p,
+            ctypes.POINTER(i64p), i64p, u64p, ctypes.POINTER(ctypes.c_double), i32p]
+        lib.oracle_tensor_join.restype = None
         lib.oracle_chain3.argtypes = [i64p, i64p, i64p, ctypes.c_int32,
                                       ctypes.c_int64, ctypes.c_int64, i64p, u64p,
                                       ctypes.POINTER(ctypes.c_double), i32p]
@@ -226,6 +234,50 @@ def chain3(A, P, B, n_sel3):
                       _ptr(ns, ctypes.c_int64), _ptr(rows, ctypes.c_uint64),
                       ctypes.byref(est), ctypes.byref(flag))
     vals = [i128_to_int(rows[i, 0], rows[i, 1]) for i in range(d)]
+    return vals, est.value, flag.value
+
+
+def sketch_kd(keys_per_join, seeds_per_join, d: int, widths) -> np.ndarray:
+    """Partitioned sketch (Section 5.1) of a table with k joins: one (already
+    filtered) key array and one (d, 6) seed table per join; returns the
+    d x w_1 x .. x w_k int64 tensor."""
+    lib = _load()
+    k = len(keys_per_join)
+    ks = [np.ascontiguousarray(np.asarray(x).astype(np.int64)) for x in keys_per_join]
+    n = ks[0].size
+    assert all(x.size == n for x in ks) and len(seeds_per_join) == k == len(widths)
+    ss = [np.ascontiguousarray(np.asarray(x, dtype=np.uint64).reshape(d, 6))
+          for x in seeds_per_join]
+    w = np.ascontiguousarray(np.asarray(widths, dtype=np.int64))
+    out = np.zeros((d,) + tuple(int(x) for x in widths), dtype=np.int64)
+    kp = (ctypes.POINTER(ctypes.c_int64) * k)(*[_ptr(x, ctypes.c_int64) for x in ks])
+    sp = (ctypes.POINTER(ctypes.c_uint64) * k)(*[_ptr(x, ctypes.c_uint64) for x in ss])
+    lib.oracle_sketch_kd(kp, k, int(n), sp, int(d), _ptr(w, ctypes.c_int64),
+                         _ptr(out, ctypes.c_int64))
+    return out
+
+
+def tensor_join(n_tables, edge_u, edge_v, d, widths, tensors, n_sel):
+    """Estimate of a join graph from partitioned sketches (Section 5.1):
+    tensors[t] is table t's d x (widths of its edges, in increasing edge
+    id) sketch; the literal sum over every bucket assignment of the edges.
+    Returns (row values as python ints mod 2^128, median, exactness flag)."""
+    lib = _load()
+    ne = len(edge_u)
+    eu = np.ascontiguousarray(np.asarray(edge_u, dtype=np.int32))
+    ev = np.ascontiguousarray(np.asarray(edge_v, dtype=np.int32))
+    w = np.ascontiguousarray(np.asarray(widths, dtype=np.int64))
+    ts = [np.ascontiguousarray(np.asarray(x, dtype=np.int64)) for x in tensors]
+    tp = (ctypes.POINTER(ctypes.c_int64) * n_tables)(*[_ptr(x, ctypes.c_int64) for x in ts])
+    ns = np.ascontiguousarray(np.asarray(n_sel, dtype=np.int64))
+    rows = np.zeros((d, 2), dtype=np.uint64)
+    est = ctypes.c_double()
+    flag = ctypes.c_int32()
+    lib.oracle_tensor_join(int(n_tables), int(ne), _ptr(eu, ctypes.c_int32),
+                           _ptr(ev, ctypes.c_int32), int(d), _ptr(w, ctypes.c_int64),
+                           tp, _ptr(ns, ctypes.c_int64), _ptr(rows, ctypes.c_uint64),
+                           ctypes.byref(est), ctypes.byref(flag))
+    vals = [int(rows[i, 0]) | (int(rows[i, 1]) << 64) for i in range(d)]
     return vals, est.value, flag.value
 
 

@@ -61,6 +61,16 @@ class JoinGraph(ctypes.Structure):
                 ("sketch", ctypes.POINTER(ctypes.c_void_p))]
 
 
+class TensorGraph(ctypes.Structure):
+    _fields_ = [("n_tables", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("counter_bits", ctypes.c_int32),
+                ("edge_u", ctypes.POINTER(ctypes.c_int32)),
+                ("edge_v", ctypes.POINTER(ctypes.c_int32)),
+                ("width", ctypes.POINTER(ctypes.c_int32)),
+                ("tensor", ctypes.POINTER(ctypes.c_void_p)),
+                ("n_selected", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -106,6 +116,15 @@ def lib():
             ctypes.POINTER(SketchSpec), ctypes.c_int32, ctypes.c_int32,
             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
         L.compass_sketch_build_2d.restype = ctypes.c_int32
+        L.compass_sketch_build_kd.argtypes = [
+            ctypes.c_int64, ctypes.POINTER(vp), ctypes.c_int32,
+            ctypes.POINTER(Pred), ctypes.c_int32, ctypes.POINTER(SketchSpec),
+            ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+            ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+        L.compass_sketch_build_kd.restype = ctypes.c_int32
+        L.compass_estimate_partitioned.argtypes = [
+            ctypes.POINTER(TensorGraph), vp, vp, vp, vp]
+        L.compass_estimate_partitioned.restype = ctypes.c_int32
         L.compass_estimate_chain3.argtypes = [
             vp, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
             ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
@@ -283,6 +302,56 @@ def sketch_build_2d(n_rows: int, pred_cols, preds, key1, seeds1, key2, seeds2,
         ctypes.byref(specs[1]), int(d), int(w1), int(w2), int(counter_bits),
         1 if accumulate else 0, ctypes.c_void_p(counters.data_ptr()),
         ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))
+
+
+def sketch_build_kd(n_rows: int, pred_cols, preds, keys, seeds, counters,
+                    n_selected: torch.Tensor, d: int, widths,
+                    counter_bits: int = 32, accumulate: bool = False,
+                    stream=None):
+    """Partitioned sketch of one table over k = 2 .. 4 join keys (device
+    (d, w_1, .., w_k) counters); see compass_sketch_build_kd."""
+    cols, ncol, parr, np_ = _marshal_preds(pred_cols, preds)
+    k = len(keys)
+    specs = (SketchSpec * k)()
+    keep = []
+    for m in range(k):
+        a = np.ascontiguousarray(np.asarray(seeds[m], dtype=np.uint64).reshape(-1))
+        keep.append(a)
+        specs[m].key_col = keys[m].data_ptr()
+        specs[m].key_dtype = _dtype_code(keys[m])
+        specs[m].seeds = a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        specs[m].counters = None
+    w = (ctypes.c_int32 * k)(*[int(x) for x in widths])
+    _check(lib().compass_sketch_build_kd(
+        int(n_rows), cols, ncol, parr, np_, specs, k, int(d), w, int(counter_bits),
+        1 if accumulate else 0, ctypes.c_void_p(counters.data_ptr()),
+        ctypes.c_void_p(n_selected.data_ptr()), _stream(stream)))
+
+
+def estimate_partitioned(edge_u, edge_v, d: int, widths, tensors,
+                         n_selected: torch.Tensor, counter_bits: int = 32,
+                         stream=None):
+    """Join size estimate of a tree of tables from partitioned sketches
+    (tensors[t]: device counters with one dimension per incident edge, in
+    increasing edge id).  Returns (row_est (d, 2) int64, est, flag) device
+    tensors."""
+    nt = len(tensors)
+    ne = len(edge_u)
+    eu = (ctypes.c_int32 * max(1, ne))(*[int(x) for x in edge_u])
+    ev = (ctypes.c_int32 * max(1, ne))(*[int(x) for x in edge_v])
+    wd = (ctypes.c_int32 * max(1, ne))(*[int(x) for x in widths])
+    tp = (ctypes.c_void_p * nt)(*[t.data_ptr() for t in tensors])
+    g = TensorGraph(nt, ne, int(d), int(counter_bits), eu, ev, wd, tp,
+                    n_selected.data_ptr())
+    dev = n_selected.device
+    row_est = torch.empty((d, 2), dtype=torch.int64, device=dev)
+    est = torch.empty(1, dtype=torch.float64, device=dev)
+    flag = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().compass_estimate_partitioned(
+        ctypes.byref(g), ctypes.c_void_p(row_est.data_ptr()),
+        ctypes.c_void_p(est.data_ptr()), ctypes.c_void_p(flag.data_ptr()),
+        _stream(stream)))
+    return row_est, est, flag
 
 
 def agms_build(n_rows: int, pred_cols, preds, keys, seeds, counters,

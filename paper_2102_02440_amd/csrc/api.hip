@@ -55,7 +55,8 @@ hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
 hipError_t launch_node1(const NodeTask *tasks, int n, const EstBuffers &B,
                         hipStream_t st);
 hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
-                            const EstBuffers &B, hipStream_t st);
+                            const TriTask *tris, const EstBuffers &B,
+                            hipStream_t st);
 hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
                             hipStream_t st);
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
@@ -65,8 +66,16 @@ hipError_t launch_gen_contract(const GenArgs &A, const EstBuffers &B,
 hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,
                          const double *approx, uint64_t *row_est, double *est,
                          int32_t *flags, int32_t n_tables, hipStream_t st);
-hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st);
+hipError_t launch_scan2d(const BuildParams &P, const KdDims &kx, int n_blocks,
+                         hipStream_t st);
+hipError_t launch_tensor_level(const TensorArgs &A, int n_tasks, int max_blocks,
+                               hipStream_t st);
+hipError_t launch_tensor_finish(const u128 *partial, int n_chunks, int d,
+                                const int64_t *n_sel, int n_tables,
+                                uint64_t *row_est, double *est, int32_t *flags,
+                                hipStream_t st);
 hipError_t launch_scan2d_binned(const BuildParams &P, const Bin2dArgs &a,
+                                const KdDims &kx,
                                 int accumulate, hipStream_t st);
 hipError_t launch_chain3(const ChainArgs &a, uint64_t *row_est, double *est,
                          int32_t *flags, hipStream_t st);
@@ -360,8 +369,8 @@ static compass_status build_two_phase(const BuildParams &base,
                                       const compass_sketch_spec *sketches,
                                       int n_sketches, int d, int w,
                                       int counter_bits, int64_t n_rows,
-                                      ZeroSpans zs, int n_cu, const Arena &ar,
-                                      hipStream_t stream) {
+                                      ZeroSpans zs, int n_cu, bool serial,
+                                      const Arena &ar, hipStream_t stream) {
   const int S = n_sketches * d;
   int64_t cap_env = 0;
   if (const char *e = getenv("COMPASS_SURVIVOR_CAP_ROWS")) cap_env = atoll(e);
@@ -406,7 +415,7 @@ static compass_status build_two_phase(const BuildParams &base,
     {
       ProfScope ps("wide_compact", stream);
       HIP_OK(launch_wide_compact(P, surv, pl.cap, count, r0, r1,
-                                 (int)std::min<int64_t>(tiles, 2ll * n_cu),
+                                 serial ? 1 : (int)std::min<int64_t>(tiles, 2ll * n_cu),
                                  stream));
     }
     FlushCtl fc;
@@ -508,6 +517,13 @@ static compass_status sketch_build_impl(
     st = pooled_arena(stream, &ar, &n_cu);
     if (st != COMPASS_OK) return st;
   }
+  // serial mode (COMPASS_SERIAL=1, for debugging): one chunk per slice
+  // group and single-workgroup compaction and hashing, so that no two
+  // workgroups combine partial counters; its results must equal the
+  // default launch's bit for bit (integer sums do not depend on order)
+  const char *ser = getenv("COMPASS_SERIAL");
+  const bool serial = ser && atoi(ser) != 0;
+  if (serial) n_cu = 1;
 
   // Two phases (compaction of the survivors' keys, then hashing them) for
   // rows too wide for LDS-private partials, and for every table with
@@ -539,7 +555,7 @@ static compass_status sketch_build_impl(
   }
   if (two_phase)
     return build_two_phase(base, sketches, n_sketches, d, w, counter_bits,
-                           n_rows, zs, n_cu, ar, stream);
+                           n_rows, zs, n_cu, serial, ar, stream);
 
   // slice groups: consecutive (sketch, row) slices whose int32 partials fit
   // the LDS budget; among the group sizes that fit, prefer one that splits
@@ -595,6 +611,7 @@ static compass_status sketch_build_impl(
     return fail(COMPASS_E_RANGE, "one chunk's partial counters (%zu bytes) "
                 "exceed the scratch", slab_row);
   chunks = std::min<int64_t>(chunks, std::max<size_t>(1, slab_cap / slab_row));
+  if (serial) chunks = 1;
   const int64_t rows_per_chunk = fused_rows_per_chunk(n_rows, chunks, kScanTile);
   chunks = (n_rows + rows_per_chunk - 1) / rows_per_chunk;
   base.rows_per_chunk = rows_per_chunk;
@@ -778,7 +795,7 @@ struct Planner {
   std::vector<SubplanTask> sps;
   int n_msg_slots = 0, n_x_slots = 0, n_prep_slots = 0, n_partial_slots = 0;
   int Lmax = 0, Lprep = 0;
-  std::vector<char> side_used;
+  std::vector<char> side_used;   // sides read in sorted order
   // generic contraction (any shape; fp64 evaluation of uncertified ones)
   std::vector<GenNode> gnodes;
   std::vector<GenPlan> gplans;
@@ -918,6 +935,10 @@ static bool plan_generic(Planner &pl, uint64_t mask, int spi, bool fp64,
   P.lists_len = (int)list_len;
   for (int a : post) {
     const GenNode &N = nodes[a];
+    // the merge reads every list of the node in sorted order (the fp64
+    // plans' sides too: sorting them only when some sub-plan is not
+    // certified would need the certificates first, which costs more than
+    // the sorts it saves)
     for (int c = 0; c < N.n_child; ++c) pl.side_used[N.c_side[c]] = 1;
     if (N.parent_side >= 0) pl.side_used[N.parent_side] = 1;
     pl.gnodes.push_back(N);
@@ -1184,17 +1205,19 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
         T.child_cut[c] = -1;
         pl.side_used[T.child_side[c]] = 1;
       }
+      // a one-child node reads its query lists (parent, cut) by bucket; a
+      // merged node reads every list in sorted order
       int nl = T.m;
       if (a != root) {
         T.parent_side = pl.side_of(nd.table, nd.parent_edge);
         T.parent_eid = nd.parent_edge;
-        pl.side_used[T.parent_side] = 1;
+        if (T.m >= 2) pl.side_used[T.parent_side] = 1;
         ++nl;
       }
       if (nd.cut_edge >= 0) {
         T.cut_side = pl.side_of(nd.table, nd.cut_edge);
         T.cut_eid = nd.cut_edge;
-        pl.side_used[T.cut_side] = 1;
+        if (T.m >= 2) pl.side_used[T.cut_side] = 1;
         ++nl;
       }
       if (a != root) {
@@ -1254,6 +1277,7 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
           pl.n_partial_slots += zb;
         }
         tr.partial_slot = sp.x_slot;
+        T.tri = (int)pl.tris.size();
         pl.tris.push_back(tr);
       }
       if (T.m > 0) pl.Lmax = std::max(pl.Lmax, nl * pl.w);
@@ -1510,7 +1534,9 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
       if (n_kind[1] > 0) HIP_OK(launch_node(d1, n_kind[1], B, stream));
       if (n_kind[0] > 0) HIP_OK(launch_node1(dt, n_kind[0], B, stream));
       if (n_kind[2] > 0)
-        HIP_OK(launch_apex_prep(d2, n_kind[2], apex_L, B, stream));
+        HIP_OK(launch_apex_prep(d2, n_kind[2], apex_L,
+                                reinterpret_cast<const TriTask *>(base + o_tris),
+                                B, stream));
     }
   }
   if (!pl.tris.empty()) {
@@ -1576,6 +1602,7 @@ static int bin2d_shift(int d, int w1, int w2) {
 // COMPASS_2D_RECORD_BYTES); every batch after the first adds to the
 // counters.
 static compass_status sketch_build_2d_binned(const BuildParams &P,
+                                             const KdDims &kx,
                                              DeviceState *ds, int64_t n_rows,
                                              int d, int w1, int w2, int r_shift,
                                              int accumulate, hipStream_t stream) {
@@ -1633,8 +1660,104 @@ static compass_status sketch_build_2d_binned(const BuildParams &P,
     a.row0 = b0;
     a.row1 = b1;
     ProfScope ps("scan2d", stream);
-    HIP_OK(launch_scan2d_binned(P, a, (accumulate || b0 > 0) ? 1 : 0, stream));
+    HIP_OK(launch_scan2d_binned(P, a, kx, (accumulate || b0 > 0) ? 1 : 0,
+                                stream));
   }
+  return COMPASS_OK;
+}
+
+// Partitioned sketch of k = 2 .. 4 joins: the second dimension of the
+// binned (or atomic) two-dimensional build is the flattened index of joins
+// 2 .. k.
+static compass_status sketch_build_kd_impl(
+    int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
+    const compass_pred *preds, int32_t n_preds,
+    const compass_sketch_spec *const *spec, int32_t k, int32_t d,
+    const int32_t *w, int32_t counter_bits, int32_t accumulate, void *counters,
+    int64_t *n_selected, hipStream_t stream) {
+  if (n_rows < 0 || n_rows >= (1ll << 47))
+    return fail(COMPASS_E_RANGE, "n_rows %lld outside [0, 2^47)",
+                (long long)n_rows);
+  if (k < 2 || k > 4) return fail(COMPASS_E_ARG, "k=%d outside [2, 4]", k);
+  if (d < 1 || d > kMaxLaunchSlices / k)
+    return fail(COMPASS_E_ARG, "d=%d outside [1, %d] for %d joins", d,
+                kMaxLaunchSlices / k, k);
+  int64_t total = 1;
+  for (int m = 0; m < k; ++m) {
+    if (w[m] < 1 || w[m] > (1 << 20))
+      return fail(COMPASS_E_ARG, "w%d=%d outside [1, 2^20]", m + 1, w[m]);
+    total *= w[m];
+    if (total > ((int64_t)1 << 28))
+      return fail(COMPASS_E_ARG, "the widths' product exceeds 2^28");
+  }
+  if (counter_bits != 32 && counter_bits != 64)
+    return fail(COMPASS_E_ARG, "counter_bits must be 32 or 64");
+  if (counter_bits == 32 && n_rows > 0x7FFFFFFFll)
+    return fail(COMPASS_E_RANGE, "int32 counters need n_rows < 2^31");
+  if (n_preds < 0 || n_preds > kMaxPreds)
+    return fail(COMPASS_E_ARG, "n_preds=%d outside [0, %d]", n_preds,
+                kMaxPreds);
+  if (!counters || !n_selected || (n_preds > 0 && !preds))
+    return fail(COMPASS_E_ARG, "null pointer argument");
+  if (n_preds > 0 && n_rows > 0 && !pred_cols)
+    return fail(COMPASS_E_ARG, "null predicate column array");
+  BuildParams P;
+  memset(&P, 0, sizeof(P));
+  P.n_rows = n_rows;
+  P.n_preds = n_preds;
+  P.counter_bits = counter_bits;
+  P.n_selected = n_selected;
+  P.count_selected = 1;
+  P.d = d;
+  P.bm1 = make_bucket_mod((uint32_t)w[0]);
+  P.bm = make_bucket_mod((uint32_t)w[1]);
+  KdDims kx;
+  memset(&kx, 0, sizeof kx);
+  kx.kd = k;
+  kx.w3 = k > 2 ? w[2] : 1;
+  kx.w4 = k > 3 ? w[3] : 1;
+  kx.bm3 = make_bucket_mod((uint32_t)kx.w3);
+  kx.bm4 = make_bucket_mod((uint32_t)kx.w4);
+  compass_status st = fill_preds(P, n_rows, pred_cols, n_pred_cols, preds, n_preds);
+  if (st != COMPASS_OK) return st;
+  for (int s = 0; s < k; ++s) {
+    if (!spec[s]) return fail(COMPASS_E_ARG, "key %d: null pointer", s);
+    const compass_sketch_spec &ks = *spec[s];
+    if (!ks.seeds || (n_rows > 0 && !ks.key_col))
+      return fail(COMPASS_E_ARG, "key %d: null pointer", s);
+    if (ks.key_dtype != COMPASS_I32 && ks.key_dtype != COMPASS_I64)
+      return fail(COMPASS_E_ARG, "key %d: dtype must be I32 or I64", s);
+    for (int i = 0; i < 6 * d; ++i)
+      if (ks.seeds[i] >= kP61)
+        return fail(COMPASS_E_ARG, "key %d: seed %d is not below 2^61-1", s, i);
+    P.keys[s].col = ks.key_col;
+    P.keys[s].dtype = ks.key_dtype;
+    for (int i = 0; i < d; ++i) {
+      const uint64_t *q = ks.seeds + 6 * i;
+      P.seeds[s * d + i] = RowSeeds{q[0], q[1], q[2], q[3], q[4], q[5]};
+    }
+  }
+  P.counters[0] = counters;
+  DeviceState *ds;
+  st = device_state(&ds);
+  if (st != COMPASS_OK) return st;
+  const int w1 = w[0];
+  const int64_t wrest = total / w1;
+  const int r_shift = wrest <= kBinTileWords ? bin2d_shift(d, w1, (int)wrest) : -1;
+  if (r_shift >= 0 && n_rows > 0)
+    return sketch_build_2d_binned(P, kx, ds, n_rows, d, w1, (int)wrest, r_shift,
+                                  accumulate, stream);
+  if (!accumulate) {
+    ProfScope ps("fill_zero", stream);
+    HIP_OK(launch_fill_zero(counters, (int64_t)d * total * (counter_bits / 8),
+                            stream));
+    HIP_OK(launch_fill_zero(n_selected, 8, stream));
+  }
+  if (n_rows == 0) return COMPASS_OK;
+  const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
+  ProfScope ps("scan2d", stream);
+  HIP_OK(launch_scan2d(P, kx, (int)std::min<int64_t>(tiles, 4ll * ds->n_cu),
+                       stream));
   return COMPASS_OK;
 }
 
@@ -1647,74 +1770,28 @@ extern "C" compass_status compass_sketch_build_2d(
     hipStream_t stream) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_err.clear();
-  if (n_rows < 0 || n_rows >= (1ll << 47))
-    return fail(COMPASS_E_RANGE, "n_rows %lld outside [0, 2^47)",
-                (long long)n_rows);
-  if (d < 1 || d > kMaxLaunchSlices / 2)
-    return fail(COMPASS_E_ARG, "d=%d outside [1, %d]", d, kMaxLaunchSlices / 2);
-  if (w1 < 1 || w2 < 1 || w1 > (1 << 20) || w2 > (1 << 20) ||
-      (int64_t)w1 * w2 > ((int64_t)1 << 28))
-    return fail(COMPASS_E_ARG, "w1=%d, w2=%d: each in [1, 2^20], product "
-                "at most 2^28", w1, w2);
-  if (counter_bits != 32 && counter_bits != 64)
-    return fail(COMPASS_E_ARG, "counter_bits must be 32 or 64");
-  if (counter_bits == 32 && n_rows > 0x7FFFFFFFll)
-    return fail(COMPASS_E_RANGE, "int32 counters need n_rows < 2^31");
-  if (n_preds < 0 || n_preds > kMaxPreds)
-    return fail(COMPASS_E_ARG, "n_preds=%d outside [0, %d]", n_preds,
-                kMaxPreds);
-  if (!first || !second || !counters || !n_selected || (n_preds > 0 && !preds))
-    return fail(COMPASS_E_ARG, "null pointer argument");
-  if (n_preds > 0 && n_rows > 0 && !pred_cols)
-    return fail(COMPASS_E_ARG, "null predicate column array");
-  BuildParams P;
-  memset(&P, 0, sizeof(P));
-  P.n_rows = n_rows;
-  P.n_preds = n_preds;
-  P.counter_bits = counter_bits;
-  P.n_selected = n_selected;
-  P.count_selected = 1;
-  P.d = d;
-  P.bm1 = make_bucket_mod((uint32_t)w1);
-  P.bm = make_bucket_mod((uint32_t)w2);
-  compass_status st = fill_preds(P, n_rows, pred_cols, n_pred_cols, preds, n_preds);
-  if (st != COMPASS_OK) return st;
   const compass_sketch_spec *spec[2] = {first, second};
-  for (int s = 0; s < 2; ++s) {
-    const compass_sketch_spec &k = *spec[s];
-    if (!k.seeds || (n_rows > 0 && !k.key_col))
-      return fail(COMPASS_E_ARG, "key %d: null pointer", s);
-    if (k.key_dtype != COMPASS_I32 && k.key_dtype != COMPASS_I64)
-      return fail(COMPASS_E_ARG, "key %d: dtype must be I32 or I64", s);
-    for (int i = 0; i < 6 * d; ++i)
-      if (k.seeds[i] >= kP61)
-        return fail(COMPASS_E_ARG, "key %d: seed %d is not below 2^61-1", s, i);
-    P.keys[s].col = k.key_col;
-    P.keys[s].dtype = k.key_dtype;
-    for (int i = 0; i < d; ++i) {
-      const uint64_t *q = k.seeds + 6 * i;
-      P.seeds[s * d + i] = RowSeeds{q[0], q[1], q[2], q[3], q[4], q[5]};
-    }
-  }
-  P.counters[0] = counters;
-  DeviceState *ds;
-  st = device_state(&ds);
-  if (st != COMPASS_OK) return st;
-  const int r_shift = bin2d_shift(d, w1, w2);
-  if (r_shift >= 0 && n_rows > 0)
-    return sketch_build_2d_binned(P, ds, n_rows, d, w1, w2, r_shift,
-                                  accumulate, stream);
-  if (!accumulate) {
-    ProfScope ps("fill_zero", stream);
-    HIP_OK(launch_fill_zero(counters,
-                            (int64_t)d * w1 * w2 * (counter_bits / 8), stream));
-    HIP_OK(launch_fill_zero(n_selected, 8, stream));
-  }
-  if (n_rows == 0) return COMPASS_OK;
-  const int64_t tiles = (n_rows + kBuildTile - 1) / kBuildTile;
-  ProfScope ps("scan2d", stream);
-  HIP_OK(launch_scan2d(P, (int)std::min<int64_t>(tiles, 4ll * ds->n_cu), stream));
-  return COMPASS_OK;
+  const int32_t w[2] = {w1, w2};
+  return sketch_build_kd_impl(n_rows, pred_cols, n_pred_cols, preds, n_preds,
+                              spec, 2, d, w, counter_bits, accumulate,
+                              counters, n_selected, stream);
+}
+
+extern "C" compass_status compass_sketch_build_kd(
+    int64_t n_rows, const void *const *pred_cols, int32_t n_pred_cols,
+    const compass_pred *preds, int32_t n_preds,
+    const compass_sketch_spec *joins, int32_t k, int32_t d, const int32_t *w,
+    int32_t counter_bits, int32_t accumulate, void *counters,
+    int64_t *n_selected, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  if (!joins || !w) return fail(COMPASS_E_ARG, "null pointer argument");
+  if (k < 2 || k > 4) return fail(COMPASS_E_ARG, "k=%d outside [2, 4]", k);
+  const compass_sketch_spec *spec[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int m = 0; m < k; ++m) spec[m] = joins + m;
+  return sketch_build_kd_impl(n_rows, pred_cols, n_pred_cols, preds, n_preds,
+                              spec, k, d, w, counter_bits, accumulate,
+                              counters, n_selected, stream);
 }
 
 extern "C" compass_status compass_estimate_chain3(
@@ -1755,6 +1832,155 @@ extern "C" compass_status compass_estimate_chain3(
   ProfScope ps("chain3", stream);
   HIP_OK(launch_chain3(c, reinterpret_cast<uint64_t *>(row_est), est, flags,
                        stream));
+  return COMPASS_OK;
+}
+
+extern "C" compass_status compass_estimate_partitioned(
+    const compass_tensor_graph *g, compass_i128 *row_est, double *est,
+    int32_t *flags, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_err.clear();
+  if (!g || !est || !flags) return fail(COMPASS_E_ARG, "null pointer argument");
+  const int nt = g->n_tables, ne = g->n_edges, d = g->d;
+  if (nt < 2 || nt > 64)
+    return fail(COMPASS_E_RANGE, "n_tables=%d outside [2, 64]", nt);
+  if (ne != nt - 1)
+    return fail(COMPASS_E_GRAPH, "%d edges for %d tables: not a tree", ne, nt);
+  if (d < 1 || d > 32) return fail(COMPASS_E_ARG, "d=%d outside [1, 32]", d);
+  if (g->counter_bits != 32 && g->counter_bits != 64)
+    return fail(COMPASS_E_ARG, "counter_bits must be 32 or 64");
+  if (!g->edge_u || !g->edge_v || !g->width || !g->tensor || !g->n_selected)
+    return fail(COMPASS_E_ARG, "null graph array");
+  std::vector<std::vector<int>> inc(nt);
+  for (int e = 0; e < ne; ++e) {
+    const int u = g->edge_u[e], v = g->edge_v[e];
+    if (u < 0 || u >= nt || v < 0 || v >= nt || u == v)
+      return fail(COMPASS_E_GRAPH, "edge %d has bad endpoints", e);
+    if (g->width[e] < 1 || g->width[e] > (1 << 20))
+      return fail(COMPASS_E_ARG, "edge %d: width %d outside [1, 2^20]", e,
+                  g->width[e]);
+    inc[u].push_back(e);
+    inc[v].push_back(e);
+  }
+  for (int t = 0; t < nt; ++t) {
+    if (!g->tensor[t]) return fail(COMPASS_E_ARG, "table %d: null tensor", t);
+    if ((int)inc[t].size() > kTensorMaxDims)
+      return fail(COMPASS_E_UNSUPPORTED, "table %d has %d joins (at most %d)",
+                  t, (int)inc[t].size(), kTensorMaxDims);
+  }
+  // rooted at table 0: parents, depths (a tree: every table reached once)
+  std::vector<int> parent(nt, -2), pedge(nt, -1), depth(nt, 0), order{0};
+  parent[0] = -1;
+  for (size_t h = 0; h < order.size(); ++h) {
+    const int t = order[h];
+    for (int e : inc[t]) {
+      const int o = g->edge_u[e] == t ? g->edge_v[e] : g->edge_u[e];
+      if (parent[o] != -2) continue;
+      parent[o] = t;
+      pedge[o] = e;
+      depth[o] = depth[t] + 1;
+      order.push_back(o);
+    }
+  }
+  if ((int)order.size() != nt)
+    return fail(COMPASS_E_GRAPH, "the join graph is not connected");
+  // tasks: every table but the leaves (their messages are their counters)
+  std::vector<int> slot(nt, -1);
+  int n_slots = 0, w_max = 1, max_depth = 0;
+  for (int e = 0; e < ne; ++e) w_max = std::max(w_max, (int)g->width[e]);
+  for (int t = 1; t < nt; ++t)
+    if (inc[t].size() > 1) slot[t] = n_slots++;
+  std::vector<std::vector<TensorTask>> levels;
+  for (int t = 0; t < nt; ++t) max_depth = std::max(max_depth, depth[t]);
+  levels.resize(max_depth + 1);
+  int root_chunks = 1;
+  for (int t = 0; t < nt; ++t) {
+    if (t != 0 && inc[t].size() == 1) continue;  // leaf
+    std::vector<int> dims = inc[t];
+    std::sort(dims.begin(), dims.end());
+    TensorTask T;
+    memset(&T, 0, sizeof T);
+    T.tensor = g->tensor[t];
+    T.n_dims = (int)dims.size();
+    T.parent_dim = -1;
+    int64_t size = 1;
+    for (int k = T.n_dims - 1; k >= 0; --k) {
+      T.width[k] = g->width[dims[k]];
+      T.stride[k] = size;
+      size *= T.width[k];
+      if (size > ((int64_t)1 << 28))
+        return fail(COMPASS_E_ARG, "table %d: tensor of more than 2^28 "
+                    "entries per row", t);
+    }
+    T.size = size;
+    for (int k = 0; k < T.n_dims; ++k) {
+      const int e = dims[k];
+      if (e == pedge[t]) {
+        T.parent_dim = k;
+        continue;
+      }
+      const int c = g->edge_u[e] == t ? g->edge_v[e] : g->edge_u[e];
+      if (inc[c].size() == 1) {
+        T.child_msg[k] = -1 - c;
+        T.leaf[k] = g->tensor[c];
+      } else {
+        T.child_msg[k] = slot[c];
+      }
+    }
+    T.out_slot = slot[t];
+    if (t == 0) {
+      T.n_chunks = (int)((size + kTensorChunk - 1) / kTensorChunk);
+      root_chunks = T.n_chunks;
+    }
+    levels[depth[t]].push_back(T);
+  }
+  DeviceState *ds;
+  compass_status st = device_state(&ds);
+  if (st != COMPASS_OK) return st;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t o_tasks = carve(sizeof(TensorTask) * nt);
+  const size_t o_msg = carve(16ull * std::max(1, n_slots) * d * w_max);
+  const size_t o_part = carve(16ull * d * root_chunks);
+  void *scratch;
+  st = ensure_scratch(ds, stream, off, &scratch);
+  if (st != COMPASS_OK) return st;
+  char *base = reinterpret_cast<char *>(scratch);
+  std::vector<TensorTask> flat;
+  std::vector<std::pair<size_t, size_t>> range;  // per level: [first, count)
+  for (int lv = max_depth; lv >= 0; --lv) {
+    range.push_back({flat.size(), levels[lv].size()});
+    flat.insert(flat.end(), levels[lv].begin(), levels[lv].end());
+  }
+  st = upload(ds, base + o_tasks, flat.data(), sizeof(TensorTask) * flat.size(),
+              stream);
+  if (st != COMPASS_OK) return st;
+  TensorArgs A;
+  memset(&A, 0, sizeof A);
+  A.msg = reinterpret_cast<u128 *>(base + o_msg);
+  A.partial = reinterpret_cast<u128 *>(base + o_part);
+  A.counter_bits = g->counter_bits;
+  A.d = d;
+  A.w_max = w_max;
+  ProfScope ps("tensor_tree", stream);
+  for (auto &r : range) {
+    if (r.second == 0) continue;
+    int per_row = 1;
+    for (size_t k = r.first; k < r.first + r.second; ++k) {
+      const TensorTask &T = flat[k];
+      per_row = std::max(per_row, T.parent_dim < 0 ? T.n_chunks
+                                                   : T.width[T.parent_dim]);
+    }
+    A.tasks = reinterpret_cast<const TensorTask *>(base + o_tasks) + r.first;
+    HIP_OK(launch_tensor_level(A, (int)r.second, d * per_row, stream));
+  }
+  HIP_OK(launch_tensor_finish(A.partial, root_chunks, d, g->n_selected, nt,
+                              reinterpret_cast<uint64_t *>(row_est), est, flags,
+                              stream));
   return COMPASS_OK;
 }
 

@@ -112,6 +112,38 @@ __device__ __forceinline__ bool guard_on(int n, int self, int t0, int t1,
 #define COMPASS_GUARD_ON(G, NSEL) \
   guard_on((G).n, (G).self, (G).tab[0], (G).tab[1], (G).tab[2], (NSEL))
 
+// Workgroup placement.  A launch covers Q = tasks x sketch rows (task, row)
+// pairs of X chunks each, on a 1-D grid; workgroups go to the 8 XCDs in
+// turn by linear id and every XCD has its own L2.  xcd = 1 (Q >= 8): the
+// grid has 8 X ceil(Q / 8) workgroups and all chunks of pair q run on XCD
+// q % 8, so that data they share (a staged sorted row, a list the chunks
+// gather from) stays in one L2; xcd = 0: chunk-major (X Q workgroups, a
+// pair's chunks spread over every XCD).
+struct GridMap {
+  int32_t X, Q, d, xcd;
+};
+struct GridPos {
+  int c, row, task;
+  bool ok;
+};
+__device__ __forceinline__ GridPos grid_pos(const GridMap &m) {
+  GridPos g;
+  const int i = blockIdx.x;
+  int q;
+  if (m.xcd) {
+    const int k = i >> 3;
+    q = (i & 7) + 8 * (k / m.X);
+    g.c = k % m.X;
+  } else {
+    q = i / m.X;
+    g.c = i % m.X;
+  }
+  g.ok = q < m.Q;
+  g.row = q % m.d;
+  g.task = q / m.d;
+  return g;
+}
+
 // |v| saturated below 2^47 (every sketch built from < 2^47 rows satisfies
 // this; saturation only keeps sort keys well-formed for foreign input)
 __device__ __forceinline__ uint64_t abs_u64(int64_t v) {
@@ -129,12 +161,14 @@ __device__ __forceinline__ uint64_t abs_u64(int64_t v) {
 // chunk plus the number of smaller keys in every other chunk (keys are
 // distinct: j differs), found by binary search over the LDS-staged chunks.
 __global__ __launch_bounds__(kSortThreads) void sort_chunk_kernel(
-    const int32_t *job_side, EstBuffers B, int w2) {
+    const int32_t *job_side, EstBuffers B, int w2, GridMap gm) {
+  const GridPos gp = grid_pos(gm);
+  if (!gp.ok) return;
   __shared__ uint64_t sk[kSortChunk];
-  const int side = job_side[blockIdx.z];
-  const int row = blockIdx.y;
+  const int side = job_side[gp.task];
+  const int row = gp.row;
   const int w = B.w;
-  const int c0 = blockIdx.x * kSortChunk;
+  const int c0 = gp.c * kSortChunk;
   const int n = min(kSortChunk, w2);  // chunk length (w2 < kSortChunk: one)
   {
     // all of a lane's counter loads in flight together (indexes clamped)
@@ -169,10 +203,12 @@ __global__ __launch_bounds__(kSortThreads) void sort_chunk_kernel(
 }
 
 __global__ __launch_bounds__(kSortThreads) void sort_merge_kernel(
-    const int32_t *job_side, EstBuffers B, int w2) {
+    const int32_t *job_side, EstBuffers B, int w2, GridMap gm) {
+  const GridPos gp = grid_pos(gm);
+  if (!gp.ok) return;
   extern __shared__ uint64_t ak[];  // all w2 chunk-sorted keys of the row
-  const int side = job_side[blockIdx.z];
-  const int row = blockIdx.y;
+  const int side = job_side[gp.task];
+  const int row = gp.row;
   const int w = B.w;
   const int n = min(kSortChunk, w2);
   const int nch = w2 / n;
@@ -180,7 +216,7 @@ __global__ __launch_bounds__(kSortThreads) void sort_merge_kernel(
   stage_lds<kSortThreads, 8>(ak, tmp, w2, StageCopy());
   __syncthreads();
   uint64_t *out = const_cast<uint64_t *>(sorted_of(B, side, row));
-  const int mine = blockIdx.x;
+  const int mine = gp.c;
   constexpr int U = kSortChunk / kSortThreads;
   uint64_t key[U];
   int pos[U];
@@ -271,16 +307,18 @@ __device__ __forceinline__ ListRef list_of(const NodeTask *T, int a) {
 // as 32-bit values and the rank searches run there.  Each element's record
 // (list, bucket, counter, child message) is gathered here once.
 __global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
-    const NodeTask *tasks, EstBuffers B, int32_t stage_bytes) {
-  const NodeTask *Tg = tasks + blockIdx.z;
+    const NodeTask *tasks, EstBuffers B, int32_t stage_bytes, GridMap gm) {
+  const GridPos gp = grid_pos(gm);
+  if (!gp.ok) return;
+  const NodeTask *Tg = tasks + gp.task;
   const NodeTask T = *Tg;
   if (T.m < 2 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // uniform
-  const int row = blockIdx.y;
+  const int row = gp.row;
   const int w = B.w;
   const int m = T.m;
   const int nl = m + (T.parent_side >= 0) + (T.cut_side >= 0);
   const int L = nl * w;
-  const int e_lo = blockIdx.x * kMergeChunk;
+  const int e_lo = gp.c * kMergeChunk;
   if (e_lo >= L) return;
   const int e_hi = min(L, e_lo + kMergeChunk);
   uint32_t *merged =
@@ -548,13 +586,15 @@ __device__ __forceinline__ u128 *n1_total(const EstBuffers &B, int slot,
 }
 
 __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
-    const NodeTask *tasks, EstBuffers B) {
+    const NodeTask *tasks, EstBuffers B, GridMap gm) {
+  const GridPos gp = grid_pos(gm);
+  if (!gp.ok) return;
   __shared__ u128 sh_m[kN1Threads], sh_x[kN1Threads];
-  const NodeTask &T = tasks[blockIdx.z];
+  const NodeTask &T = tasks[gp.task];
   if (T.m != 1 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
-  const int row = blockIdx.y;
+  const int row = gp.row;
   const int w = B.w;
-  const int c0 = blockIdx.x * kN1Chunk;
+  const int c0 = gp.c * kN1Chunk;
   if (c0 >= w) return;
   const int cside = T.child_side[0];
   const int cmsg = T.child_msg[0];
@@ -607,32 +647,34 @@ __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
   }
   if (threadIdx.x == kN1Threads - 1) {
     u128 *tot = n1_total(B, T.scratch_slot, row);
-    tot[2 * blockIdx.x] = sh_m[threadIdx.x];
-    tot[2 * blockIdx.x + 1] = sh_x[threadIdx.x];
+    tot[2 * gp.c] = sh_m[threadIdx.x];
+    tot[2 * gp.c + 1] = sh_x[threadIdx.x];
   }
 }
 
 __global__ __launch_bounds__(kN1Threads) void node1_emit_kernel(
-    const NodeTask *tasks, EstBuffers B) {
+    const NodeTask *tasks, EstBuffers B, GridMap gm) {
+  const GridPos gp = grid_pos(gm);
+  if (!gp.ok) return;
   extern __shared__ uint32_t smag[];  // the child's sorted |v| (int32 counters)
   __shared__ u128 soff[2 * kN1MaxChunks + 2];
-  const NodeTask &T = tasks[blockIdx.z];
+  const NodeTask &T = tasks[gp.task];
   if (T.m != 1 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
-  const int row = blockIdx.y;
+  const int row = gp.row;
   const int w = B.w;
   const int has_parent = T.parent_side >= 0;
   const int nq = has_parent + (T.cut_side >= 0);
   const int nch = (w + kN1Chunk - 1) / kN1Chunk;
   const u128 *tot = n1_total(B, T.scratch_slot, row);
   if (nq == 0) {  // tree root: X = G(+inf)
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (gp.c == 0 && threadIdx.x == 0) {
       u128 x = 0;
       for (int c = 0; c < nch; ++c) x += tot[2 * c + 1];
       B.xout[(size_t)T.out_slot * B.d + row] = x;
     }
     return;
   }
-  const int e0 = blockIdx.x * kN1Chunk;
+  const int e0 = gp.c * kN1Chunk;
   if (e0 >= nq * w) return;
   const int cside = T.child_side[0];
   const uint64_t *srt = sorted_of(B, cside, row);
@@ -706,6 +748,47 @@ __global__ __launch_bounds__(kN1Threads) void node1_emit_kernel(
   }
 }
 
+// min(a * b, 2^63) for a <= 2^63, b < 2^63
+__device__ __forceinline__ u128 sat_mul63(u128 a, uint64_t b) {
+  const u128 r = a * (u128)b;
+  const u128 cap = (u128)1 << 63;
+  return r > cap ? cap : r;
+}
+
+typedef const __attribute__((address_space(4))) TriTask ConstTask;
+typedef const __attribute__((address_space(4))) TriElemN ConstElemN;
+typedef const __attribute__((address_space(4))) TriPre ConstPre;
+
+enum { kTriFast = 0, kTriNarrow = 1, kTriWide = 2 };
+
+// Arithmetic of one triangle task (the same in every lane and block).
+// Narrow arithmetic is exact when: every message value of child c is
+// bounded by B_c = prod of n_sel over c's subtree (the L1 norm of a sketch
+// row is at most n_sel), each A_c by (w + 1) B_c, and the apex's counters by
+// n_sel(apex); when all of these stay below 2^62, messages and A are int64
+// and only the running sum G needs 128 bits.  The compact two-child sweep
+// also needs every table's n_sel below 2^30 (counters, keys and thresholds
+// then fit 32 bits).
+__device__ int tri_path(ConstTask &T, const EstBuffers &B) {
+  bool narrow = true, small = true;
+  const u128 lim = (u128)1 << 62;
+  const int64_t nr = B.n_sel[T.root_table];
+  const uint64_t nroot = nr < 0 ? 0 : (uint64_t)nr;
+  small = nroot < (1ull << 30);
+  for (int c = 0; c < T.m; ++c) {
+    u128 bc = 1;
+    for (uint64_t s = T.child_tables[c]; s; s &= s - 1) {
+      const int64_t ns = B.n_sel[__builtin_ctzll(s)];
+      const uint64_t f = ns < 0 ? 0 : (uint64_t)ns;
+      small = small && f < (1ull << 30);
+      bc = sat_mul63(bc, f);
+    }
+    if (bc * (u128)(B.w + 1) >= lim || bc * (u128)nroot >= lim) narrow = false;
+  }
+  if (!narrow) return kTriWide;
+  return small && T.m == 2 ? kTriFast : kTriNarrow;
+}
+
 // ---------------------------------------------------------------------
 // triangle apex preparation: grid (tasks, d, chunks of kPrepChunk)
 // ---------------------------------------------------------------------
@@ -718,15 +801,17 @@ __device__ __forceinline__ int rec_child(const uint32_t *merged, int p) {
 }
 
 __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
-    const NodeTask *tasks, EstBuffers B) {
+    const NodeTask *tasks, const TriTask *tris, EstBuffers B, GridMap gm) {
+  const GridPos gp = grid_pos(gm);
+  if (!gp.ok) return;
   __shared__ int s_lo[kPrepThreads], s_hi[kPrepThreads];
   __shared__ int s_prev, s_next;
-  const NodeTask &T = tasks[blockIdx.z];
+  const NodeTask &T = tasks[gp.task];
   if (T.mode != kModeTriRootPrep || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
-  const int row = blockIdx.y;
+  const int row = gp.row;
   const int m = T.m;
   const int L = m * B.w;  // an apex has no parent or cut list
-  const int p0 = blockIdx.x * kPrepChunk;
+  const int p0 = gp.c * kPrepChunk;
   if (p0 >= L) return;
   const int p1 = min(L, p0 + kPrepChunk);
   const NodeRec *rec =
@@ -736,6 +821,10 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
   const size_t slot_row = (size_t)T.out_slot * B.d + row;
   TriElem *out = B.prep + slot_row * (size_t)B.Lprep;
   TriElemN *outn = B.prepn + slot_row * (size_t)B.Lprep;
+  // the two-child sweep reads the compact elements only, the general one
+  // the full elements only
+  const bool fast =
+      m == 2 && tri_path(*(ConstTask *)(tris + T.tri), B) == kTriFast;
   const int q0 = p0 + threadIdx.x * kPrepPer;  // my positions [q0, q0 + kPrepPer)
   int last_start = -1, first_end = L;
 #pragma unroll
@@ -757,8 +846,8 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
     }
     e.child = (uint32_t)a;
     e.pad[0] = e.pad[1] = e.pad[2] = 0;
-    out[pos] = e;
-    if (m == 2) {
+    if (!fast) out[pos] = e;
+    if (fast) {
       // truncating copy; the sweep reads it only when the bounds hold
       TriElemN n;
       n.v = (int32_t)e.v;
@@ -780,7 +869,7 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
       B.prep_z[slot_row] = L;
     }
   }
-  if (m != 2) return;  // uniform
+  if (!fast) return;  // uniform
   // run starts: inclusive max-scan over my thread's positions; the run
   // holding the chunk's first position may start in an earlier chunk
   s_lo[threadIdx.x] = last_start;
@@ -844,12 +933,6 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
 // triangle apex sweep: grid (n_tri, d, ceil(w / kLaneThreads))
 // ---------------------------------------------------------------------
 
-// min(a * b, 2^63) for a <= 2^63, b < 2^63
-__device__ __forceinline__ u128 sat_mul63(u128 a, uint64_t b) {
-  const u128 r = a * (u128)b;
-  const u128 cap = (u128)1 << 63;
-  return r > cap ? cap : r;
-}
 
 // Two-child apex, all magnitudes below 2^30, messages in 64 bits.  Sweeping
 // in descending kappa, a maximal run of one child's elements sees the other
@@ -888,39 +971,7 @@ __device__ __forceinline__ void fast_elem(FastRun &r, uint32_t kf, int32_t v,
   r.nrun += 1;
 }
 
-typedef const __attribute__((address_space(4))) TriTask ConstTask;
-typedef const __attribute__((address_space(4))) TriElemN ConstElemN;
-typedef const __attribute__((address_space(4))) TriPre ConstPre;
 
-enum { kTriFast = 0, kTriNarrow = 1, kTriWide = 2 };
-
-// Arithmetic of one triangle task (the same in every lane and block).
-// Narrow arithmetic is exact when: every message value of child c is
-// bounded by B_c = prod of n_sel over c's subtree (the L1 norm of a sketch
-// row is at most n_sel), each A_c by (w + 1) B_c, and the apex's counters by
-// n_sel(apex); when all of these stay below 2^62, messages and A are int64
-// and only the running sum G needs 128 bits.  The compact two-child sweep
-// also needs every table's n_sel below 2^30 (counters, keys and thresholds
-// then fit 32 bits).
-__device__ int tri_path(ConstTask &T, const EstBuffers &B) {
-  bool narrow = true, small = true;
-  const u128 lim = (u128)1 << 62;
-  const int64_t nr = B.n_sel[T.root_table];
-  const uint64_t nroot = nr < 0 ? 0 : (uint64_t)nr;
-  small = nroot < (1ull << 30);
-  for (int c = 0; c < T.m; ++c) {
-    u128 bc = 1;
-    for (uint64_t s = T.child_tables[c]; s; s &= s - 1) {
-      const int64_t ns = B.n_sel[__builtin_ctzll(s)];
-      const uint64_t f = ns < 0 ? 0 : (uint64_t)ns;
-      small = small && f < (1ull << 30);
-      bc = sat_mul63(bc, f);
-    }
-    if (bc * (u128)(B.w + 1) >= lim || bc * (u128)nroot >= lim) narrow = false;
-  }
-  if (!narrow) return kTriWide;
-  return small && T.m == 2 ? kTriFast : kTriNarrow;
-}
 
 // ---------------------------------------------------------------------
 // run ordering of two-child apexes: grid (n_tri, d, tiles), kOrderThreads
@@ -945,19 +996,21 @@ __device__ __forceinline__ size_t tpre_index(const EstBuffers &B,
 }
 
 __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
-    const TriTask *tasks, EstBuffers B) {
+    const TriTask *tasks, EstBuffers B, GridMap gm) {
+  const GridPos gp = grid_pos(gm);
+  if (!gp.ok) return;
   __shared__ uint64_t okey[kOrderTile];
   __shared__ int64_t scm[kOrderThreads / 64], scx[kOrderThreads / 64];
   __shared__ uint32_t scv[kOrderThreads / 64];
-  const TriTask &T = tasks[blockIdx.z];
+  const TriTask &T = tasks[gp.task];
   if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
   if (tri_path(*(ConstTask *)&T, B) != kTriFast) return;
-  const int row = blockIdx.y;
+  const int row = gp.row;
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
   const int z = B.prep_z[slot_row];
   const int L = T.L;
   if (L - z > kOrderCap) return;
-  const int tile = blockIdx.x;
+  const int tile = gp.c;
   const int t0 = z + tile * kOrderTile;
   if (t0 >= L) return;
   const int nt = min(kOrderTile, L - t0);
@@ -1229,19 +1282,27 @@ __device__ __forceinline__ int lds_lower_bound(const uint32_t *k, int n,
 }
 
 __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
-    const TriTask *tasks, EstBuffers B) {
+    const TriTask *tasks, EstBuffers B, GridMap gm) {
+  const GridPos gp = grid_pos(gm);
+  if (!gp.ok) return;
   extern __shared__ __align__(16) uint32_t skey[];  // run-ordered keys of [z, L)
-  ConstTask &T = *((ConstTask *)tasks + blockIdx.z);
+  ConstTask &T = *((ConstTask *)tasks + gp.task);
   if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // another rooting runs
   if (tri_path(T, B) != kTriFast) return;  // uniform: tri_lane_kernel's block
-  const int row = blockIdx.y;
+  const int row = gp.row;
   const int lane = threadIdx.x % kLaneThreads;
   // whole waves share a segment: make that visible to the compiler, so the
   // sweep's positions and element loads stay scalar
   const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / kLaneThreads);
-  const int J = blockIdx.x * kLaneThreads + lane;
-  const bool active = J < B.w;
-  const int Jc = active ? J : 0;
+  // kFastJ buckets J per lane (their searches and loads overlap)
+  int Jc[kFastJ];
+  bool active[kFastJ];
+#pragma unroll
+  for (int u = 0; u < kFastJ; ++u) {
+    const int J = (gp.c * kFastJ + u) * kLaneThreads + lane;
+    active[u] = J < B.w;
+    Jc[u] = active[u] ? J : 0;
+  }
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
   const int z = B.prep_z[slot_row];  // the sweep ends at the zero prefix
   const int len = T.L - z;
@@ -1259,77 +1320,94 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
 
   // child slot 0 / 1 state; key < kf  <=>  kappa below the cut element's
   // (ties in |v| go to the lower edge id)
-  uint32_t kf0, kf1;
-  int64_t C0, C1;
-  {
+  uint32_t kf0[kFastJ], kf1[kFastJ];
+  int64_t C0[kFastJ], C1[kFastJ];
+  const int e0 = T.cut_child[0] == 0 ? 0 : 1;  // cut endpoint in slot 0
+#pragma unroll
+  for (int u = 0; u < kFastJ; ++u) {
     uint32_t kf[2];
     int64_t cv[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      kf[e] = (uint32_t)abs_u64(counter_at(B, T.cut_side[e], row, Jc)) +
+      kf[e] = (uint32_t)abs_u64(counter_at(B, T.cut_side[e], row, Jc[u])) +
               (T.cut_peid[e] < T.cut_eid ? 1u : 0u);
-      cv[e] = (int64_t)(uint64_t)child_msg_at(B, T.cut_cmsg[e], row, Jc);
+      cv[e] = (int64_t)(uint64_t)child_msg_at(B, T.cut_cmsg[e], row, Jc[u]);
     }
-    const int e0 = T.cut_child[0] == 0 ? 0 : 1;  // cut endpoint in slot 0
-    kf0 = kf[e0];
-    kf1 = kf[1 - e0];
-    C0 = cv[e0];
-    C1 = cv[1 - e0];
+    kf0[u] = kf[e0];
+    kf1[u] = kf[1 - e0];
+    C0[u] = cv[e0];
+    C1[u] = cv[1 - e0];
   }
   ConstElemN *el = (ConstElemN *)(B.prepn + slot_row * (size_t)B.Lprep);
-  int64_t A0 = 0, A1 = 0, X0 = 0, X1 = 0;
-  u128 G = 0;
-  // close a run piece: its terms times the other child's running sum
-  auto close = [&](uint32_t c, const FastRun &r) {
-    const int64_t cc = c ? C1 : C0;
+  int64_t A0[kFastJ], A1[kFastJ], X0[kFastJ], X1[kFastJ];
+  u128 G[kFastJ];
+#pragma unroll
+  for (int u = 0; u < kFastJ; ++u) {
+    A0[u] = A1[u] = X0[u] = X1[u] = 0;
+    G[u] = 0;
+  }
+  // close a run piece of bucket u: its terms times the other child's
+  // running sum
+  auto close = [&](int u, uint32_t c, const FastRun &r) {
+    const int64_t cc = c ? C1[u] : C0[u];
     const int64_t x = r.xb + cc * (int64_t)(r.vrun - r.vb);
     const int64_t arun = r.mb + cc * (int64_t)(r.nrun - r.nb);
     if (c) {
-      G += mul_s64_s64(x, A0);
-      A1 += arun;
-      X1 += x;
+      G[u] += mul_s64_s64(x, A0[u]);
+      A1[u] += arun;
+      X1[u] += x;
     } else {
-      G += mul_s64_s64(x, A1);
-      A0 += arun;
-      X0 += x;
+      G[u] += mul_s64_s64(x, A1[u]);
+      A0[u] += arun;
+      X0[u] += x;
     }
   };
-  // element by element over [lo, hi], descending
-  auto elements = [&](int lo, int hi, uint32_t kf, FastRun &r) {
+  // element by element over [lo, hi], descending, for every bucket of the
+  // lane (the element loads are shared)
+  auto elements = [&](int lo, int hi, uint32_t c, FastRun *r) {
     constexpr int kGroup = 8;
-    r.mb = r.xb = 0;
-    r.vb = r.nb = 0;
-    r.vrun = r.nrun = 0;
+    uint32_t kf[kFastJ];
+#pragma unroll
+    for (int u = 0; u < kFastJ; ++u) {
+      kf[u] = c ? kf1[u] : kf0[u];
+      r[u].mb = r[u].xb = 0;
+      r[u].vb = r[u].nb = 0;
+      r[u].vrun = r[u].nrun = 0;
+    }
     int pos = hi;
     for (; pos - (kGroup - 1) >= lo; pos -= kGroup) {
       int32_t v[kGroup];
       uint32_t kc[kGroup];
       int64_t mu[kGroup], vm[kGroup];
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u) {
-        ConstElemN &e = el[pos - u];
-        v[u] = e.v;
-        kc[u] = e.kc;
-        mu[u] = e.mu;
-        vm[u] = e.vm;
+      for (int q = 0; q < kGroup; ++q) {
+        ConstElemN &e = el[pos - q];
+        v[q] = e.v;
+        kc[q] = e.kc;
+        mu[q] = e.mu;
+        vm[q] = e.vm;
       }
       // issue the whole group's scalar loads before the first use
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u)
-        __asm__ volatile("" ::"s"(v[u]), "s"(kc[u]), "s"(mu[u]), "s"(vm[u]));
+      for (int q = 0; q < kGroup; ++q)
+        __asm__ volatile("" ::"s"(v[q]), "s"(kc[q]), "s"(mu[q]), "s"(vm[q]));
 #pragma unroll
-      for (int u = 0; u < kGroup; ++u)
-        fast_elem(r, kf, v[u], kc[u], mu[u], vm[u]);
+      for (int q = 0; q < kGroup; ++q)
+#pragma unroll
+        for (int u = 0; u < kFastJ; ++u)
+          fast_elem(r[u], kf[u], v[q], kc[q], mu[q], vm[q]);
     }
     for (; pos >= lo; --pos) {
       ConstElemN &e = el[pos];
-      fast_elem(r, kf, e.v, e.kc, e.mu, e.vm);
+#pragma unroll
+      for (int u = 0; u < kFastJ; ++u)
+        fast_elem(r[u], kf[u], e.v, e.kc, e.mu, e.vm);
     }
   };
   if (ordered) {
     // the pieces of run group kFastSegs - 1 - seg (tri_seg_kernel), 64 at a
     // time: lane k loads piece b0 + k, the sweep broadcasts it with
-    // readlane; the next long piece's search and prefix load are issued
+    // readlane; the next long piece's searches and prefix loads are issued
     // before the current piece is summed
     const int32_t *sp = B.tsegp + slot_row * (kFastSegs + 1);
     const int pb = __builtin_amdgcn_readfirstlane(sp[kFastSegs - 1 - seg]);
@@ -1354,19 +1432,44 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
                               (int)((uint64_t)dv.x0 >> 32), k) << 32) |
                          (uint32_t)__builtin_amdgcn_readlane((int)dv.x0, k));
       };
-      // position of the first key >= kf in a long piece, and its prefix
-      auto search = [&](const PieceIn &o, int &p, TriPre &ep) {
-        const uint32_t kf = (o.info & 1) ? kf1 : kf0;
-        p = o.lo + lds_lower_bound(skey + (o.lo - z), o.hi - o.lo + 1, kf);
+      // per bucket: position of the first key >= kf in a long piece (the
+      // binary searches of all buckets in lockstep), and its prefix
+      auto search = [&](const PieceIn &o, int *p, TriPre *ep) {
+        const uint32_t *k = skey + (o.lo - z);
+        uint32_t kf[kFastJ];
+        int base[kFastJ];
+#pragma unroll
+        for (int u = 0; u < kFastJ; ++u) {
+          kf[u] = (o.info & 1) ? kf1[u] : kf0[u];
+          base[u] = 0;
+        }
+        int n = o.hi - o.lo + 1;
+        while (n > 1) {
+          const int half = n >> 1;
+#pragma unroll
+          for (int u = 0; u < kFastJ; ++u)
+            base[u] = k[base[u] + half] < kf[u] ? base[u] + half : base[u];
+          n -= half;
+        }
         const int tile = o.info >> 2;
-        ep = pre0[(size_t)tile * (kOrderTile + 1) + (p - z - tile * kOrderTile)];
+        const TriPre *tp = pre0 + (size_t)tile * (kOrderTile + 1) -
+                           (z + tile * kOrderTile);
+#pragma unroll
+        for (int u = 0; u < kFastJ; ++u) {
+          p[u] = o.lo + base[u] + (k[base[u]] < kf[u] ? 1 : 0);
+          ep[u] = tp[p[u]];
+        }
       };
       PieceIn cur, nxt;
-      int pc = 0, pn = 0;
-      TriPre ec, en;
-      ec.m = ec.x = 0;
-      ec.v = ec.pad = 0;
-      en = ec;
+      int pc[kFastJ], pn[kFastJ];
+      TriPre ec[kFastJ], en[kFastJ];
+#pragma unroll
+      for (int u = 0; u < kFastJ; ++u) {
+        pc[u] = pn[u] = 0;
+        ec[u].m = ec[u].x = 0;
+        ec[u].v = ec[u].pad = 0;
+        en[u] = ec[u];
+      }
       get(nb - 1, cur);
       if (cur.info & 2) search(cur, pc, ec);
       for (int k = nb - 1; k >= 0; --k) {
@@ -1375,21 +1478,28 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
           if (nxt.info & 2) search(nxt, pn, en);
         }
         const uint32_t c = cur.info & 1;
-        FastRun r;
+        FastRun r[kFastJ];
         if (cur.info & 2) {
-          r.mb = (int64_t)((uint64_t)ec.m - (uint64_t)cur.m0);
-          r.xb = (int64_t)((uint64_t)ec.x - (uint64_t)cur.x0);
-          r.vb = (int32_t)((uint32_t)ec.v - (uint32_t)cur.v0);
-          r.nb = pc - cur.lo;
-          r.vrun = (int32_t)((uint32_t)cur.v1 - (uint32_t)cur.v0);
-          r.nrun = cur.hi - cur.lo + 1;
+#pragma unroll
+          for (int u = 0; u < kFastJ; ++u) {
+            r[u].mb = (int64_t)((uint64_t)ec[u].m - (uint64_t)cur.m0);
+            r[u].xb = (int64_t)((uint64_t)ec[u].x - (uint64_t)cur.x0);
+            r[u].vb = (int32_t)((uint32_t)ec[u].v - (uint32_t)cur.v0);
+            r[u].nb = pc[u] - cur.lo;
+            r[u].vrun = (int32_t)((uint32_t)cur.v1 - (uint32_t)cur.v0);
+            r[u].nrun = cur.hi - cur.lo + 1;
+          }
         } else {
-          elements(cur.lo, cur.hi, c ? kf1 : kf0, r);
+          elements(cur.lo, cur.hi, c, r);
         }
-        close(c, r);
+#pragma unroll
+        for (int u = 0; u < kFastJ; ++u) close(u, c, r[u]);
         cur = nxt;
-        pc = pn;
-        ec = en;
+#pragma unroll
+        for (int u = 0; u < kFastJ; ++u) {
+          pc[u] = pn[u];
+          ec[u] = en[u];
+        }
       }
     }
   } else {
@@ -1398,58 +1508,68 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     while (pos >= bottom) {
       const uint32_t c = el[pos].kc >> 31;  // the run's child (uniform)
       const int lo = max(el[pos].run_lo, bottom);
-      FastRun r;
-      elements(lo, pos, c ? kf1 : kf0, r);
-      close(c, r);
+      FastRun r[kFastJ];
+      elements(lo, pos, c, r);
+#pragma unroll
+      for (int u = 0; u < kFastJ; ++u) close(u, c, r[u]);
       pos = lo - 1;
     }
   }
-  __syncthreads();  // the key stage becomes the segment results
+  // segments combine exactly (one bucket of the lane at a time: the LDS
+  // stage holds one set of segment results)
   SegOut (*so)[kLaneThreads] = reinterpret_cast<SegOut (*)[kLaneThreads]>(skey);
-  SegOut &mine = so[seg][lane];
-  mine.G = G;
-  mine.A0 = A0;
-  mine.A1 = A1;
-  mine.X0 = X0;
-  mine.X1 = X1;
-  __syncthreads();
   u128 *red = reinterpret_cast<u128 *>(&so[1][0]);  // free once combined
-  u128 g = 0;
-  if (seg == 0) {
-    int64_t a0 = 0, a1 = 0;
-    for (int s2 = 0; s2 < kFastSegs; ++s2) {
-      const SegOut &o = so[s2][lane];
-      g += o.G + mul_s64_s64(a0, o.X1) + mul_s64_s64(a1, o.X0);
-      a0 += o.A0;
-      a1 += o.A1;
-    }
-  }
-  __syncthreads();
-  if (seg == 0) red[lane] = active ? g : (u128)0;
-  __syncthreads();
-  for (int off = kLaneThreads / 2; off > 0; off >>= 1) {
-    if (seg == 0 && lane < off) red[lane] += red[lane + off];
+#pragma unroll
+  for (int u = 0; u < kFastJ; ++u) {
+    __syncthreads();  // the key stage (or the previous round) is done with
+    SegOut &mine = so[seg][lane];
+    mine.G = G[u];
+    mine.A0 = A0[u];
+    mine.A1 = A1[u];
+    mine.X0 = X0[u];
+    mine.X1 = X1[u];
     __syncthreads();
+    u128 g = 0;
+    if (seg == 0) {
+      int64_t a0 = 0, a1 = 0;
+      for (int s2 = 0; s2 < kFastSegs; ++s2) {
+        const SegOut &o = so[s2][lane];
+        g += o.G + mul_s64_s64(a0, o.X1) + mul_s64_s64(a1, o.X0);
+        a0 += o.A0;
+        a1 += o.A1;
+      }
+    }
+    __syncthreads();
+    if (seg == 0) red[lane] = active[u] ? g : (u128)0;
+    __syncthreads();
+    for (int off = kLaneThreads / 2; off > 0; off >>= 1) {
+      if (seg == 0 && lane < off) red[lane] += red[lane + off];
+      __syncthreads();
+    }
+    // one partial slot per kLaneThreads buckets
+    const int slot = gp.c * kFastJ + u;
+    if (threadIdx.x == 0 && slot * kLaneThreads < B.w)
+      B.partial[((size_t)T.partial_slot + slot) * B.d + row] = red[0];
   }
-  if (threadIdx.x == 0)
-    B.partial[((size_t)T.partial_slot + blockIdx.x) * B.d + row] = red[0];
 }
 
 // Other triangles (more apex children, or bounds beyond the compact
 // sweep): grid (n_tri, d, ceil(w / kLaneThreads)); blocks of two-child
 // tasks that tri_fast_kernel handles return at once.
 __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
-    const TriTask *tasks, EstBuffers B) {
+    const TriTask *tasks, EstBuffers B, GridMap gm) {
+  const GridPos gp = grid_pos(gm);
+  if (!gp.ok) return;
   __shared__ u128 red[kLaneThreads];
   // the task is the same for every lane: read it through the constant
   // address space so its fields live in scalar registers
-  ConstTask &T = *((ConstTask *)tasks + blockIdx.z);
+  ConstTask &T = *((ConstTask *)tasks + gp.task);
   if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // another rooting runs
   const int path = tri_path(T, B);
   if (path == kTriFast) return;  // uniform: tri_fast_kernel's block
   const bool narrow = path == kTriNarrow;
-  const int row = blockIdx.y;
-  const int J = blockIdx.x * kLaneThreads + threadIdx.x;
+  const int row = gp.row;
+  const int J = gp.c * kLaneThreads + threadIdx.x;
   const bool active = J < B.w;
   const int Jc = active ? J : 0;
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
@@ -1577,7 +1697,7 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    B.partial[((size_t)T.partial_slot + blockIdx.x) * B.d + row] = red[0];
+    B.partial[((size_t)T.partial_slot + gp.c) * B.d + row] = red[0];
 }
 
 // ---------------------------------------------------------------------
@@ -1682,28 +1802,46 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
 // ---------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------
+// The grid of n tasks x d rows x X chunks (see GridMap); 0 blocks when it
+// would exceed a 1-D grid.
+static GridMap grid_map(int X, int n, int d, int64_t *blocks) {
+  GridMap m;
+  m.X = X;
+  m.Q = n * d;
+  m.d = d;
+  m.xcd = m.Q >= 8 ? 1 : 0;
+  const int64_t b = m.xcd ? 8ll * X * ((m.Q + 7) / 8) : (int64_t)X * m.Q;
+  *blocks = b < 0x7FFFFFFFll ? b : 0;
+  return m;
+}
+#define COMPASS_GRID(X, n)                                \
+  int64_t blocks_;                                        \
+  const GridMap gm_ = grid_map((X), (n), B.d, &blocks_);  \
+  if (blocks_ == 0) return hipErrorInvalidConfiguration;
+
 hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
                             const EstBuffers &B, hipStream_t st) {
   int w2 = 1;
   while (w2 < B.w) w2 <<= 1;
   const int nch = std::max(1, w2 / kSortChunk);
-  hipLaunchKernelGGL(sort_chunk_kernel, dim3(nch, B.d, n_jobs),
-                     dim3(kSortThreads), 0, st, job_side, B, w2);
+  COMPASS_GRID(nch, n_jobs);
+  hipLaunchKernelGGL(sort_chunk_kernel, dim3((uint32_t)blocks_),
+                     dim3(kSortThreads), 0, st, job_side, B, w2, gm_);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sort_merge_kernel, dim3(nch, B.d, n_jobs),
+  hipLaunchKernelGGL(sort_merge_kernel, dim3((uint32_t)blocks_),
                      dim3(kSortThreads), (size_t)w2 * sizeof(uint64_t), st,
-                     job_side, B, w2);
+                     job_side, B, w2, gm_);
   return hipGetLastError();
 }
 
 hipError_t launch_node_merge(const NodeTask *tasks, int n, int max_L,
                              const EstBuffers &B, int stage_bytes,
                              hipStream_t st) {
-  hipLaunchKernelGGL(node_merge_kernel,
-                     dim3((max_L + kMergeChunk - 1) / kMergeChunk, B.d, n),
+  COMPASS_GRID((max_L + kMergeChunk - 1) / kMergeChunk, n);
+  hipLaunchKernelGGL(node_merge_kernel, dim3((uint32_t)blocks_),
                      dim3(kMergeThreads), (size_t)stage_bytes, st, tasks, B,
-                     stage_bytes);
+                     stage_bytes, gm_);
   return hipGetLastError();
 }
 
@@ -1717,33 +1855,36 @@ hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
 hipError_t launch_node1(const NodeTask *tasks, int n, const EstBuffers &B,
                         hipStream_t st) {
   const int nch = (B.w + kN1Chunk - 1) / kN1Chunk;
-  hipLaunchKernelGGL(node1_prefix_kernel, dim3(nch, B.d, n), dim3(kN1Threads),
-                     0, st, tasks, B);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(node1_emit_kernel, dim3(2 * nch, B.d, n), dim3(kN1Threads),
-                     B.counter_bits == 32 ? (size_t)B.w * 4 : 0, st, tasks, B);
+  {
+    COMPASS_GRID(nch, n);
+    hipLaunchKernelGGL(node1_prefix_kernel, dim3((uint32_t)blocks_),
+                       dim3(kN1Threads), 0, st, tasks, B, gm_);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  COMPASS_GRID(2 * nch, n);
+  hipLaunchKernelGGL(node1_emit_kernel, dim3((uint32_t)blocks_), dim3(kN1Threads),
+                     B.counter_bits == 32 ? (size_t)B.w * 4 : 0, st, tasks, B,
+                     gm_);
   return hipGetLastError();
 }
 
 hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
-                            const EstBuffers &B, hipStream_t st) {
-  hipLaunchKernelGGL(apex_prep_kernel,
-                     dim3((Lmax_apex + kPrepChunk - 1) / kPrepChunk, B.d, n),
-                     dim3(kPrepThreads), 0, st, tasks, B);
+                            const TriTask *tris, const EstBuffers &B,
+                            hipStream_t st) {
+  COMPASS_GRID((Lmax_apex + kPrepChunk - 1) / kPrepChunk, n);
+  hipLaunchKernelGGL(apex_prep_kernel, dim3((uint32_t)blocks_),
+                     dim3(kPrepThreads), 0, st, tasks, tris, B, gm_);
   return hipGetLastError();
 }
 
-// Grids put the chunks of one (task, row) in x, so that consecutive
-// workgroups (dispatched to the 8 XCDs in turn) spread one task's work over
-// every XCD; tasks go in z, at most kMaxGridZ per launch.
 hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
                             hipStream_t st) {
   const int tiles = (std::min(B.Lprep, kOrderCap) + kOrderTile - 1) / kOrderTile;
-  for (int t0 = 0; t0 < n; t0 += kMaxGridZ) {
-    const int nt = std::min(kMaxGridZ, n - t0);
-    hipLaunchKernelGGL(tri_order_kernel, dim3(tiles, B.d, nt),
-                       dim3(kOrderThreads), 0, st, tasks + t0, B);
+  {
+    COMPASS_GRID(tiles, n);
+    hipLaunchKernelGGL(tri_order_kernel, dim3((uint32_t)blocks_),
+                       dim3(kOrderThreads), 0, st, tasks, B, gm_);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -1754,20 +1895,19 @@ hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
 
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
                            const EstBuffers &B, hipStream_t st) {
-  // each (task, row, z) block does its work in exactly one of the two
-  for (int t0 = 0; t0 < n; t0 += kMaxGridZ) {
-    const int nt = std::min(kMaxGridZ, n - t0);
-    hipLaunchKernelGGL(tri_fast_kernel, dim3(zblocks, B.d, nt),
+  // each (task, row, chunk) block does its work in exactly one of the two
+  {
+    COMPASS_GRID((zblocks + kFastJ - 1) / kFastJ, n);
+    hipLaunchKernelGGL(tri_fast_kernel, dim3((uint32_t)blocks_),
                        dim3(kLaneThreads * kFastSegs), (size_t)kFastStageBytes,
-                       st, tasks + t0, B);
+                       st, tasks, B, gm_);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(tri_lane_kernel, dim3(zblocks, B.d, nt),
-                       dim3(kLaneThreads), 0, st, tasks + t0, B);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  COMPASS_GRID(zblocks, n);
+  hipLaunchKernelGGL(tri_lane_kernel, dim3((uint32_t)blocks_),
+                     dim3(kLaneThreads), 0, st, tasks, B, gm_);
+  return hipGetLastError();
 }
 
 hipError_t launch_finish(const SubplanTask *sps, int n, const EstBuffers &B,

@@ -30,6 +30,7 @@ constexpr int kSegThreads = 1024;
 constexpr int kSegPer = 16;
 constexpr int kFastSegs = 4;  // sweep segments per cut bucket
 constexpr int kSearchMin = 8;  // shortest run the sweep sums by search
+constexpr int kFastJ = 1;  // cut buckets per lane of the two-child sweep
 constexpr int kOrderTile = 2048;  // positions ordered by one workgroup
 constexpr int kOrderCap = 16384;  // longest two-child apex list run-ordered
 constexpr int kFastStageBytes = kOrderCap * 4;  // its keys, staged in LDS
@@ -70,6 +71,8 @@ struct NodeTask {
   int32_t child_msg[kMaxChild];
   int32_t child_cut[kMaxChild];   // mode 2: index (0/1) of the cut endpoint, or -1
   int32_t child_parent_eid[kMaxChild];  // mode 2: edge id of the child's parent edge
+  int32_t tri;                    // mode 2: its triangle task
+  int32_t pad;
 };
 
 // Triangle sub-plan: the root (apex) sweeps its merged child list once per

@@ -47,14 +47,55 @@ __device__ __forceinline__ void add_counter<int64_t>(int64_t *p, int32_t v) {
             (unsigned long long)(int64_t)v);
 }
 
+// hash of one key with a row's functions (the key's width class decides
+// the Horner step)
+__device__ __forceinline__ void hash_key(uint64_t x, const RowSeeds &s,
+                                         const BucketMod &bm, int32_t &g,
+                                         uint32_t &b) {
+  if ((x >> 32) == 0)
+    hash_xi_h<true>(x, s, bm, g, b);
+  else
+    hash_xi_h<false>(x, s, bm, g, b);
+}
+
+// The third and fourth joins of a row set: their buckets are appended to
+// the flattened second index b2, their signs multiplied into g2.
+template <int R>
+__device__ __forceinline__ void hash_more(const BuildParams &P, const KdDims &kx,
+                                          int i, const uint64_t *x3,
+                                          const uint64_t *x4, int32_t *g2,
+                                          uint32_t *b2) {
+  if (kx.kd < 3) return;
+  const int d = P.d;
+  const RowSeeds s3 = P.seeds[2 * d + i];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    int32_t g;
+    uint32_t b;
+    hash_key(x3[k], s3, kx.bm3, g, b);
+    b2[k] = b2[k] * (uint32_t)kx.w3 + b;
+    g2[k] *= g;
+  }
+  if (kx.kd < 4) return;
+  const RowSeeds s4 = P.seeds[3 * d + i];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    int32_t g;
+    uint32_t b;
+    hash_key(x4[k], s4, kx.bm4, g, b);
+    b2[k] = b2[k] * (uint32_t)kx.w4 + b;
+    g2[k] *= g;
+  }
+}
+
 template <typename C>
 __global__ __launch_bounds__(kBuildThreads) void scan2d_kernel(
-    const BuildParams P) {
+    const BuildParams P, const KdDims kx) {
   __shared__ int32_t queue[kBuildTile];
   __shared__ int32_t s_qn;
   const Job2d job{P};
   const int d = P.d;
-  const int64_t w1 = P.bm1.w, w2 = P.bm.w;
+  const int64_t w1 = P.bm1.w, w2 = (int64_t)P.bm.w * kx.w3 * kx.w4;
   C *cnt = reinterpret_cast<C *>(P.counters[0]);
   uint64_t sel = 0;
   for (int64_t base = (int64_t)blockIdx.x * kBuildTile; base < P.n_rows;
@@ -72,24 +113,26 @@ __global__ __launch_bounds__(kBuildThreads) void scan2d_kernel(
       ridx[k] = valid[k] ? (P.n_preds ? queue[q] : q) : 0;
     }
     uint64_t x1[kBuildRowsPerThread], x2[kBuildRowsPerThread];
+    uint64_t x3[kBuildRowsPerThread], x4[kBuildRowsPerThread];
     load_fields<kBuildRowsPerThread>(P.keys[0], base, ridx, x1);
     load_fields<kBuildRowsPerThread>(P.keys[1], base, ridx, x2);
+    if (kx.kd > 2) load_fields<kBuildRowsPerThread>(P.keys[2], base, ridx, x3);
+    if (kx.kd > 3) load_fields<kBuildRowsPerThread>(P.keys[3], base, ridx, x4);
     for (int i = 0; i < d; ++i) {
       const RowSeeds s1 = P.seeds[i], s2 = P.seeds[d + i];
+      int32_t g1[kBuildRowsPerThread], g2[kBuildRowsPerThread];
+      uint32_t b1[kBuildRowsPerThread], b2[kBuildRowsPerThread];
+#pragma unroll
+      for (int k = 0; k < kBuildRowsPerThread; ++k) {
+        hash_key(x1[k], s1, P.bm1, g1[k], b1[k]);
+        hash_key(x2[k], s2, P.bm, g2[k], b2[k]);
+      }
+      hash_more<kBuildRowsPerThread>(P, kx, i, x3, x4, g2, b2);
 #pragma unroll
       for (int k = 0; k < kBuildRowsPerThread; ++k) {
         if (!valid[k]) continue;
-        int32_t g1, g2;
-        uint32_t b1, b2;
-        if ((x1[k] >> 32) == 0)
-          hash_xi_h<true>(x1[k], s1, P.bm1, g1, b1);
-        else
-          hash_xi_h<false>(x1[k], s1, P.bm1, g1, b1);
-        if ((x2[k] >> 32) == 0)
-          hash_xi_h<true>(x2[k], s2, P.bm, g2, b2);
-        else
-          hash_xi_h<false>(x2[k], s2, P.bm, g2, b2);
-        add_counter<C>(cnt + ((int64_t)i * w1 + b1) * w2 + b2, g1 * g2);
+        add_counter<C>(cnt + ((int64_t)i * w1 + b1[k]) * w2 + b2[k],
+                       g1[k] * g2[k]);
       }
     }
     __syncthreads();  // queue and s_qn are reused by the next tile
@@ -99,13 +142,14 @@ __global__ __launch_bounds__(kBuildThreads) void scan2d_kernel(
               (unsigned long long)sel);
 }
 
-hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st) {
+hipError_t launch_scan2d(const BuildParams &P, const KdDims &kx, int n_blocks,
+                         hipStream_t st) {
   if (P.counter_bits == 32)
     hipLaunchKernelGGL(scan2d_kernel<int32_t>, dim3(n_blocks),
-                       dim3(kBuildThreads), 0, st, P);
+                       dim3(kBuildThreads), 0, st, P, kx);
   else
     hipLaunchKernelGGL(scan2d_kernel<int64_t>, dim3(n_blocks),
-                       dim3(kBuildThreads), 0, st, P);
+                       dim3(kBuildThreads), 0, st, P, kx);
   return hipGetLastError();
 }
 
@@ -127,7 +171,7 @@ hipError_t launch_scan2d(const BuildParams &P, int n_blocks, hipStream_t st) {
 //   bin2d_tile_kernel      per tile: LDS sums, one coalesced write
 // ---------------------------------------------------------------------
 __global__ __launch_bounds__(kBuildThreads) void scan2d_bin_kernel(
-    const BuildParams P, const Bin2dArgs a) {
+    const BuildParams P, const Bin2dArgs a, const KdDims kx) {
   extern __shared__ int32_t lds2[];
   int32_t *hist = lds2;                       // a.n_bins counts
   int32_t *queue = lds2 + ((a.n_bins + 3) & ~3);  // kBuildTile row offsets
@@ -159,8 +203,11 @@ __global__ __launch_bounds__(kBuildThreads) void scan2d_bin_kernel(
       ridx[k] = valid[k] ? (P.n_preds ? queue[q] : q) : 0;
     }
     uint64_t x1[kBuildRowsPerThread], x2[kBuildRowsPerThread];
+    uint64_t x3[kBuildRowsPerThread], x4[kBuildRowsPerThread];
     load_fields<kBuildRowsPerThread>(P.keys[0], base, ridx, x1);
     load_fields<kBuildRowsPerThread>(P.keys[1], base, ridx, x2);
+    if (kx.kd > 2) load_fields<kBuildRowsPerThread>(P.keys[2], base, ridx, x3);
+    if (kx.kd > 3) load_fields<kBuildRowsPerThread>(P.keys[3], base, ridx, x4);
     bool wide_key = false;
 #pragma unroll
     for (int k = 0; k < kBuildRowsPerThread; ++k)
@@ -189,6 +236,7 @@ __global__ __launch_bounds__(kBuildThreads) void scan2d_bin_kernel(
             hash_xi_h<false>(x2[k], s2, P.bm, g2[k], b2[k]);
         }
       }
+      hash_more<kBuildRowsPerThread>(P, kx, i, x3, x4, g2, b2);
 #pragma unroll
       for (int k = 0; k < kBuildRowsPerThread; ++k) {
         if (!valid[k]) continue;
@@ -355,10 +403,11 @@ __global__ __launch_bounds__(kBuildThreads) void bin2d_tile_kernel(
 }
 
 hipError_t launch_scan2d_binned(const BuildParams &P, const Bin2dArgs &a,
-                                int accumulate, hipStream_t st) {
+                                const KdDims &kx, int accumulate,
+                                hipStream_t st) {
   const size_t hist_lds = (size_t)((a.n_bins + 3) & ~3) * 4;
   hipLaunchKernelGGL(scan2d_bin_kernel, dim3(a.n_blocks), dim3(kBuildThreads),
-                     hist_lds + (size_t)kBuildTile * 4, st, P, a);
+                     hist_lds + (size_t)kBuildTile * 4, st, P, a, kx);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(bin2d_offsets_kernel, dim3((a.n_bins + 255) / 256),
@@ -614,6 +663,160 @@ hipError_t launch_chain3(const ChainArgs &a, uint64_t *row_est, double *est,
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(chain3_finish_kernel, dim3(1), dim3(kFinishThreads), 0, st,
                      a, nblk, row_est, est, flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// tree of partitioned sketches: grid (d x (parent width or root chunks),
+// tasks of one tree level), kTensorThreads lanes
+// ---------------------------------------------------------------------
+template <typename C>
+__device__ __forceinline__ u128 tensor_entry(const TensorTask &T, int row,
+                                             int64_t off) {
+  return s64_to_u128(
+      (int64_t)reinterpret_cast<const C *>(T.tensor)[(int64_t)row * T.size + off]);
+}
+
+// the value of dimension k's message at bucket j (a leaf child's counter,
+// or a computed message)
+__device__ __forceinline__ u128 dim_msg(const TensorArgs &A, const TensorTask &T,
+                                        int k, int row, int j) {
+  const int s = T.child_msg[k];
+  if (s >= 0) return A.msg[((size_t)s * A.d + row) * A.w_max + j];
+  const int64_t idx = (int64_t)row * T.width[k] + j;
+  if (A.counter_bits == 32)
+    return s64_to_u128(reinterpret_cast<const int32_t *>(T.leaf[k])[idx]);
+  return s64_to_u128(reinterpret_cast<const int64_t *>(T.leaf[k])[idx]);
+}
+
+__global__ __launch_bounds__(kTensorThreads) void tensor_node_kernel(
+    TensorArgs A) {
+  __shared__ u128 red[kTensorThreads];
+  const TensorTask &T = A.tasks[blockIdx.y];
+  const int root = T.parent_dim < 0;
+  const int per_row = root ? T.n_chunks : T.width[T.parent_dim];
+  const int row = blockIdx.x / per_row;
+  const int jb = blockIdx.x % per_row;  // parent bucket, or root chunk
+  if (row >= A.d) return;
+  // entries of the block: root: a chunk of the flattened tensor; else the
+  // slice at parent bucket jb, enumerated over the other dimensions
+  int64_t n_ent, f0 = 0;
+  if (root) {
+    f0 = (int64_t)jb * kTensorChunk;
+    n_ent = min((int64_t)kTensorChunk, T.size - f0);
+  } else {
+    n_ent = T.size / T.width[T.parent_dim];
+  }
+  u128 acc = 0;
+  for (int64_t e = threadIdx.x; e < n_ent; e += kTensorThreads) {
+    int64_t off;
+    int idx[kTensorMaxDims];
+    if (root) {
+      off = f0 + e;
+      int64_t r = off;
+      for (int k = T.n_dims - 1; k >= 0; --k) {
+        idx[k] = (int)(r % T.width[k]);
+        r /= T.width[k];
+      }
+    } else {
+      int64_t r = e;
+      off = (int64_t)jb * T.stride[T.parent_dim];
+      for (int k = T.n_dims - 1; k >= 0; --k) {
+        if (k == T.parent_dim) {
+          idx[k] = jb;
+          continue;
+        }
+        idx[k] = (int)(r % T.width[k]);
+        r /= T.width[k];
+        off += (int64_t)idx[k] * T.stride[k];
+      }
+    }
+    u128 v = A.counter_bits == 32 ? tensor_entry<int32_t>(T, row, off)
+                                  : tensor_entry<int64_t>(T, row, off);
+    for (int k = 0; k < T.n_dims; ++k)
+      if (k != T.parent_dim) v *= dim_msg(A, T, k, row, idx[k]);
+    acc += v;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kTensorThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  if (root)
+    A.partial[(size_t)row * T.n_chunks + jb] = red[0];
+  else
+    A.msg[((size_t)T.out_slot * A.d + row) * A.w_max + jb] = red[0];
+}
+
+hipError_t launch_tensor_level(const TensorArgs &A, int n_tasks, int max_blocks,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(tensor_node_kernel, dim3(max_blocks, n_tasks),
+                     dim3(kTensorThreads), 0, st, A);
+  return hipGetLastError();
+}
+
+// row sums of the root's chunk partials, median, certificate (|X_i| <= the
+// product of the tables' selected rows)
+__global__ __launch_bounds__(kFinishThreads) void tensor_finish_kernel(
+    const u128 *partial, int32_t n_chunks, int32_t d, const int64_t *n_sel,
+    int32_t n_tables, uint64_t *row_est, double *est, int32_t *flags) {
+  __shared__ u128 xs[64];
+  __shared__ u128 red[kFinishThreads];
+  for (int i = 0; i < d; ++i) {
+    u128 x = 0;
+    for (int k = threadIdx.x; k < n_chunks; k += kFinishThreads)
+      x += partial[(size_t)i * n_chunks + k];
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = kFinishThreads / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      xs[i] = red[0];
+      if (row_est) {
+        row_est[2 * i] = (uint64_t)red[0];
+        row_est[2 * i + 1] = (uint64_t)(red[0] >> 64);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  for (int p = 1; p < d; ++p) {
+    const u128 v = xs[p];
+    int q = p - 1;
+    while (q >= 0 && i128_less(v, xs[q])) {
+      xs[q + 1] = xs[q];
+      --q;
+    }
+    xs[q + 1] = v;
+  }
+  *est = (d & 1) ? i128_to_double(xs[d / 2])
+                 : i128_to_double(xs[d / 2 - 1] + xs[d / 2]) * 0.5;
+  const u128 lim = (u128)1 << 127;
+  u128 b = 1;
+  bool ok = true;
+  for (int t = 0; t < n_tables && ok; ++t) {
+    const u128 f = (u128)(n_sel[t] < 0 ? 0 : n_sel[t]);
+    if (f == 0) {
+      b = 0;
+      break;
+    }
+    u128 prod;
+    if (__builtin_mul_overflow(b, f, &prod) || prod > lim) ok = false;
+    else b = prod;
+  }
+  *flags = ok && b < lim ? 1 : 0;
+}
+
+hipError_t launch_tensor_finish(const u128 *partial, int n_chunks, int d,
+                                const int64_t *n_sel, int n_tables,
+                                uint64_t *row_est, double *est, int32_t *flags,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(tensor_finish_kernel, dim3(1), dim3(kFinishThreads), 0, st,
+                     partial, n_chunks, d, n_sel, n_tables, row_est, est, flags);
   return hipGetLastError();
 }
 

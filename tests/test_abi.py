@@ -195,3 +195,62 @@ def test_mlp_entry_points_reject_bad_arguments(C):
                                      ctypes.c_float(1e-3), one, None) == 1
     assert L.compass_mlp_train_epoch(h, one, one, one, one, 1, 4,
                                      ctypes.c_float(0.0), one, None) == 1
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(k=1), 1), (dict(k=5), 1), (dict(k=4, d=13), 1), (dict(k=3, d=17), 1),
+    (dict(w=[64, 0, 8]), 1), (dict(w=[1 << 10, 1 << 10, 1 << 9]), 1),
+    (dict(counter_bits=8), 1), (dict(n_rows=-1), 2), (dict(bad_seed=True), 1),
+    (dict(null_counters=True), 1),
+])
+def test_build_kd_validation(C, kw, status):
+    """Argument checks of compass_sketch_build_kd (no device work)."""
+    L = C.lib()
+    k = kw.get("k", 3)
+    d = kw.get("d", 3)
+    w = kw.get("w", [16, 8, 4, 2][:max(1, min(k, 4))] + [2] * max(0, k - 4))
+    specs = (C.SketchSpec * max(1, k))()
+    keep = []
+    for m in range(max(1, k)):
+        s = np.zeros((max(d, 1), 6), np.uint64)
+        if kw.get("bad_seed") and m == 1:
+            s[-1, 3] = (1 << 61) + 1
+        keep.append(s)
+        specs[m].key_col = 8
+        specs[m].key_dtype = C.I32
+        specs[m].seeds = s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    wa = (ctypes.c_int32 * max(1, len(w)))(*w)
+    r = L.compass_sketch_build_kd(
+        kw.get("n_rows", 10), None, 0, None, 0, specs, k, d, wa,
+        kw.get("counter_bits", 32), 0,
+        ctypes.c_void_p(0 if kw.get("null_counters") else 48), ctypes.c_void_p(64),
+        ctypes.c_void_p(0))
+    assert r == status
+    assert L.compass_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n_tables=1, eu=[], ev=[]), 2), (dict(eu=[0, 1, 0], ev=[1, 2, 2]), 3),
+    (dict(eu=[0, 0], ev=[1, 1]), 3), (dict(eu=[0, 2], ev=[0, 1]), 3),
+    (dict(d=0), 1), (dict(d=33), 1), (dict(counter_bits=16), 1),
+    (dict(width=[0, 4]), 1), (dict(null_tensor=True), 1),
+    (dict(n_tables=6, eu=[0, 0, 0, 0, 0], ev=[1, 2, 3, 4, 5]), 5),
+])
+def test_estimate_partitioned_validation(C, kw, status):
+    """Argument checks of compass_estimate_partitioned (no device work):
+    not a tree, disconnected, bad sizes, a table with five joins."""
+    L = C.lib()
+    nt = kw.get("n_tables", 3)
+    eu, ev = kw.get("eu", [0, 1]), kw.get("ev", [1, 2])
+    width = kw.get("width", [4] * len(eu))
+    ne = len(eu)
+    ea = (ctypes.c_int32 * max(1, ne))(*eu)
+    eb = (ctypes.c_int32 * max(1, ne))(*ev)
+    wa = (ctypes.c_int32 * max(1, ne))(*width)
+    tp = (ctypes.c_void_p * max(1, nt))(*([0] if kw.get("null_tensor") else [64]) * max(1, nt))
+    g = C.TensorGraph(nt, ne, kw.get("d", 3), kw.get("counter_bits", 32), ea, eb, wa,
+                      tp, 8)
+    r = L.compass_estimate_partitioned(ctypes.byref(g), None, ctypes.c_void_p(8),
+                                       ctypes.c_void_p(8), ctypes.c_void_p(0))
+    assert r == status, L.compass_last_error().decode()
+    assert L.compass_last_error().decode() != ""

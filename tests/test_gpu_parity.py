@@ -479,6 +479,41 @@ def _with_env(name, value, fn):
 
 
 @gpu
+@pytest.mark.parametrize("preds_on,w", [(False, 4096), (True, 65536), (True, 1000)])
+def test_serial_mode_matches_default(preds_on, w):
+    """Serial mode (COMPASS_SERIAL=1: one chunk per slice group, one
+    compaction workgroup, no two workgroups combining partial counters)
+    gives the default launch's counters and selected count bit for bit: a
+    difference would be a lost or doubled update.  Fused scan (no
+    predicates) and two-phase build (with predicates)."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(w + preds_on)
+    n = 2_000_003
+    d = 3
+    keys = [W.fk_column(rng, n, 300_000, 1.1, rng.permutation(300_000)).astype(np.int32)]
+    a = rng.integers(0, 100, n).astype(np.int32)
+    preds = [{"col": 0, "kind": "range", "lo": 10, "hi": 69}] if preds_on else []
+    seeds = [W.draw_seeds(rng, 1, d)[0] for _ in keys]
+    _say("serial mode", preds_on, w)
+
+    def run():
+        cnt = [torch.zeros((d, w), dtype=torch.int32, device="cuda") for _ in keys]
+        nsel = torch.zeros(1, dtype=torch.int64, device="cuda")
+        C.sketch_build(n, [torch.from_numpy(a).cuda()] if preds_on else [], preds,
+                       [torch.from_numpy(k).cuda() for k in keys], seeds, cnt, nsel, d, w)
+        torch.cuda.synchronize()
+        return [c.cpu().numpy() for c in cnt], int(nsel.item())
+
+    par = run()
+    ser = _with_env("COMPASS_SERIAL", 1, run)
+    assert ser[1] == par[1]
+    for x, y in zip(ser[0], par[0]):
+        assert np.array_equal(x, y)
+    assert par[1] == (int(((a >= 10) & (a <= 69)).sum()) if preds_on else n)
+
+
+@gpu
 @pytest.mark.parametrize("w,bits,pattern", [
     (65536, 64, "uniform"), (65536, 32, "bursts"), (1024, 32, "bursts"),
     (40000, 64, "uniform"), (8192, 32, "all_then_none")])
