@@ -124,6 +124,46 @@ def subset_bitmap(codes: np.ndarray, domain: int) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# Star join for partitioned sketches (Section 5.1): a fact table of 36M rows
+# with three foreign keys (Zipf 1.0 over 2.5M movies, 0.8 over 4.2M people,
+# 1.1 over 200k companies) and three dimension tables keyed by id, each with
+# one predicate (year range ~10%, subset ~0.5%, point ~1%).  Edges: fact-t
+# (0), fact-n (1), fact-cn (2); table order [fact, t, n, cn].
+# --------------------------------------------------------------------------
+def star3(seed: int = DEFAULT_SEED, scale: float = 1.0, d: int = 5,
+          w: int = 128) -> Query:
+    rng = rng_of(seed, 30)
+
+    def sz(n):
+        return max(8, int(round(n * scale)))
+
+    n_f, n_t, n_n, n_c = sz(36_000_000), sz(2_500_000), sz(4_200_000), sz(200_000)
+    perm_t = rng.permutation(n_t).astype(np.int64)
+    perm_n = rng.permutation(n_n).astype(np.int64)
+    perm_c = rng.permutation(n_c).astype(np.int64)
+    fact = Table("f", {"movie": fk_column(rng, n_f, n_t, 1.0, perm_t),
+                       "person": fk_column(rng, n_f, n_n, 0.8, perm_n),
+                       "company": fk_column(rng, n_f, n_c, 1.1, perm_c)})
+    t = Table("t", {"id": np.arange(n_t, dtype=np.int32),
+                    "year": rng.integers(1900, 2020, size=n_t,
+                                         dtype=np.int64).astype(np.int32)},
+              [Predicate("year", "range", 2008, 2019)])
+    chosen = rng.choice(n_n, size=max(1, n_n // 200), replace=False)
+    n = Table("n", {"id": np.arange(n_n, dtype=np.int32),
+                    "name_code": np.arange(n_n, dtype=np.int32)},
+              [Predicate("name_code", "subset", bitmap=subset_bitmap(chosen, n_n),
+                         domain=n_n)])
+    cn = Table("cn", {"id": np.arange(n_c, dtype=np.int32),
+                      "country": rng.integers(0, 100, size=n_c,
+                                              dtype=np.int64).astype(np.int32)},
+               [Predicate("country", "point", 3)])
+    edges = [Edge(0, "movie", 1, "id"), Edge(0, "person", 2, "id"),
+             Edge(0, "company", 3, "id")]
+    seeds = draw_seeds(rng_of(seed, 31), len(edges), d)
+    return Query([fact, t, n, cn], edges, d, w, seeds, 32)
+
+
+# --------------------------------------------------------------------------
 # Plain two-table equi-join: R 1M rows (range predicate, 10%), S 100k rows,
 # Zipf(1.0) keys over a 100k domain; d=5, w=1024, int32 counters.
 # --------------------------------------------------------------------------
