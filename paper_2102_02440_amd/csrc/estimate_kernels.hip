@@ -635,10 +635,12 @@ __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
   }
   u128 em = sh_m[threadIdx.x] - tm, ex = sh_x[threadIdx.x] - tx;
   u128 *P = n1_prefix(B, T.scratch_slot, row);
+  // a tree root (no parent or cut list) needs the chunk totals only
+  const bool queries = T.parent_side >= 0 || T.cut_side >= 0;
 #pragma unroll
   for (int u = 0; u < kN1Per; ++u) {
     const int k = k0 + u;
-    if (k < w) {
+    if (queries && k < w) {
       P[2 * (size_t)k] = em;
       P[2 * (size_t)k + 1] = ex;
     }

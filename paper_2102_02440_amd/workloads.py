@@ -127,7 +127,7 @@ def subset_bitmap(codes: np.ndarray, domain: int) -> np.ndarray:
 # Star join for partitioned sketches (Section 5.1): a fact table of 36M rows
 # with three foreign keys (Zipf 1.0 over 2.5M movies, 0.8 over 4.2M people,
 # 1.1 over 200k companies) and three dimension tables keyed by id, each with
-# one predicate (year range ~10%, subset ~0.5%, point ~1%).  Edges: fact-t
+# one predicate (year range ~10%, subset 20%, country range 30%).  Edges: fact-t
 # (0), fact-n (1), fact-cn (2); table order [fact, t, n, cn].
 # --------------------------------------------------------------------------
 def star3(seed: int = DEFAULT_SEED, scale: float = 1.0, d: int = 5,
@@ -148,7 +148,7 @@ def star3(seed: int = DEFAULT_SEED, scale: float = 1.0, d: int = 5,
                     "year": rng.integers(1900, 2020, size=n_t,
                                          dtype=np.int64).astype(np.int32)},
               [Predicate("year", "range", 2008, 2019)])
-    chosen = rng.choice(n_n, size=max(1, n_n // 200), replace=False)
+    chosen = rng.choice(n_n, size=max(1, n_n // 5), replace=False)
     n = Table("n", {"id": np.arange(n_n, dtype=np.int32),
                     "name_code": np.arange(n_n, dtype=np.int32)},
               [Predicate("name_code", "subset", bitmap=subset_bitmap(chosen, n_n),
@@ -156,7 +156,7 @@ def star3(seed: int = DEFAULT_SEED, scale: float = 1.0, d: int = 5,
     cn = Table("cn", {"id": np.arange(n_c, dtype=np.int32),
                       "country": rng.integers(0, 100, size=n_c,
                                               dtype=np.int64).astype(np.int32)},
-               [Predicate("country", "point", 3)])
+               [Predicate("country", "range", 0, 29)])
     edges = [Edge(0, "movie", 1, "id"), Edge(0, "person", 2, "id"),
              Edge(0, "company", 3, "id")]
     seeds = draw_seeds(rng_of(seed, 31), len(edges), d)
