@@ -46,7 +46,8 @@ hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
 hipError_t launch_store_seeds(const RowSeeds *src, int n, RowSeeds *dst,
                               hipStream_t st);
 hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
-                            const EstBuffers &B, hipStream_t st);
+                            ResolveArgs R, const EstBuffers &B,
+                            hipStream_t st);
 hipError_t launch_node_merge(const NodeTask *tasks, int n, int max_L,
                              const EstBuffers &B, int stage_bytes,
                              hipStream_t st);
@@ -55,8 +56,7 @@ hipError_t launch_node(const NodeTask *tasks, int n, const EstBuffers &B,
 hipError_t launch_node1(const NodeTask *tasks, int n, const EstBuffers &B,
                         hipStream_t st);
 hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
-                            const TriTask *tris, const EstBuffers &B,
-                            hipStream_t st);
+                            const EstBuffers &B, hipStream_t st);
 hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
                             hipStream_t st);
 hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
@@ -1496,10 +1496,17 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.Lmax = std::max(1, pl.Lmax);
   B.Lprep = (int)lp;
 
-  if (!sort_jobs.empty()) {
+  {
+    // the row sorts, with every task's guard resolved alongside
+    ResolveArgs R;
+    memset(&R, 0, sizeof R);
+    R.tasks = reinterpret_cast<NodeTask *>(base + o_tasks);
+    R.tris = reinterpret_cast<TriTask *>(base + o_tris);
+    R.n = (int)flat.size();
+    R.n_tri = (int)pl.tris.size();
     ProfScope ps("sort_rows", stream);
     HIP_OK(launch_sort_rows(reinterpret_cast<const int32_t *>(base + o_jobs),
-                            (int)sort_jobs.size(), B, stream));
+                            (int)sort_jobs.size(), R, B, stream));
   }
   const NodeTask *dtasks = reinterpret_cast<const NodeTask *>(base + o_tasks);
   for (size_t lv = 0; lv < levels.size(); ++lv) {
@@ -1534,9 +1541,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
       if (n_kind[1] > 0) HIP_OK(launch_node(d1, n_kind[1], B, stream));
       if (n_kind[0] > 0) HIP_OK(launch_node1(dt, n_kind[0], B, stream));
       if (n_kind[2] > 0)
-        HIP_OK(launch_apex_prep(d2, n_kind[2], apex_L,
-                                reinterpret_cast<const TriTask *>(base + o_tris),
-                                B, stream));
+        HIP_OK(launch_apex_prep(d2, n_kind[2], apex_L, B, stream));
     }
   }
   if (!pl.tris.empty()) {

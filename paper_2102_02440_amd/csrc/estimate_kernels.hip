@@ -160,8 +160,19 @@ __device__ __forceinline__ uint64_t abs_u64(int64_t v) {
 // sort_merge_kernel: the final position of a key is its index in its
 // chunk plus the number of smaller keys in every other chunk (keys are
 // distinct: j differs), found by binary search over the LDS-staged chunks.
+__device__ void resolve_task(const ResolveArgs &R, int i, const EstBuffers &B);
+
+// The guard resolution (resolve_task) rides along as the last R.blocks
+// workgroups of the chunk sort, which needs none of it: its dependent
+// loads then overlap the sort instead of adding a launch.
 __global__ __launch_bounds__(kSortThreads) void sort_chunk_kernel(
-    const int32_t *job_side, EstBuffers B, int w2, GridMap gm) {
+    const int32_t *job_side, EstBuffers B, int w2, GridMap gm,
+    ResolveArgs R) {
+  const int rb = (int)blockIdx.x - (int)(gridDim.x - R.blocks);
+  if (rb >= 0) {
+    resolve_task(R, rb * kSortThreads + (int)threadIdx.x, B);
+    return;
+  }
   const GridPos gp = grid_pos(gm);
   if (!gp.ok) return;
   __shared__ uint64_t sk[kSortChunk];
@@ -312,7 +323,7 @@ __global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
   if (!gp.ok) return;
   const NodeTask *Tg = tasks + gp.task;
   const NodeTask T = *Tg;
-  if (T.m < 2 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // uniform
+  if (T.m < 2 || !T.guard.on) return;  // uniform
   const int row = gp.row;
   const int w = B.w;
   const int m = T.m;
@@ -536,7 +547,7 @@ __global__ __launch_bounds__(kNodeThreads) void node_kernel(
   __shared__ u128 sh[kNodeThreads];
   const NodeTask *Tg = tasks + blockIdx.x;
   const NodeTask T = *Tg;
-  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // uniform
+  if (!T.guard.on) return;  // uniform
   const int row = blockIdx.y;
   const int w = B.w;
   const int m = T.m;
@@ -591,7 +602,7 @@ __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
   if (!gp.ok) return;
   __shared__ u128 sh_m[kN1Threads], sh_x[kN1Threads];
   const NodeTask &T = tasks[gp.task];
-  if (T.m != 1 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
+  if (T.m != 1 || !T.guard.on) return;
   const int row = gp.row;
   const int w = B.w;
   const int c0 = gp.c * kN1Chunk;
@@ -661,7 +672,7 @@ __global__ __launch_bounds__(kN1Threads) void node1_emit_kernel(
   extern __shared__ uint32_t smag[];  // the child's sorted |v| (int32 counters)
   __shared__ u128 soff[2 * kN1MaxChunks + 2];
   const NodeTask &T = tasks[gp.task];
-  if (T.m != 1 || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
+  if (T.m != 1 || !T.guard.on) return;
   const int row = gp.row;
   const int w = B.w;
   const int has_parent = T.parent_side >= 0;
@@ -791,6 +802,31 @@ __device__ int tri_path(ConstTask &T, const EstBuffers &B) {
   return small && T.m == 2 ? kTriFast : kTriNarrow;
 }
 
+// Every task's guard (and a triangle's arithmetic path) resolved once per
+// estimate into guard.on, so that the later launches test one field of the
+// task they load anyway instead of re-reading the selected-row counts.
+// Index i: triangle tasks first, then node tasks.
+__device__ void resolve_task(const ResolveArgs &R, int i, const EstBuffers &B) {
+  if (i < R.n_tri) {
+    TriTask &T = R.tris[i];
+    const bool on = COMPASS_GUARD_ON(T.guard, B.n_sel);
+    T.guard.on = on ? 1 + tri_path(*(ConstTask *)&T, B) : 0;
+  } else if (i < R.n_tri + R.n) {
+    NodeTask &T = R.tasks[i - R.n_tri];
+    int on = COMPASS_GUARD_ON(T.guard, B.n_sel) ? 1 : 0;
+    if (on && T.mode == kModeTriRootPrep && T.m == 2 &&
+        tri_path(*(ConstTask *)(R.tris + T.tri), B) == kTriFast)
+      on |= 2;
+    T.guard.on = on;
+  }
+}
+
+// the guard resolution on its own (an estimate with no row sorts)
+__global__ __launch_bounds__(kSortThreads) void resolve_kernel(ResolveArgs R,
+                                                               EstBuffers B) {
+  resolve_task(R, blockIdx.x * kSortThreads + (int)threadIdx.x, B);
+}
+
 // ---------------------------------------------------------------------
 // triangle apex preparation: grid (tasks, d, chunks of kPrepChunk)
 // ---------------------------------------------------------------------
@@ -803,13 +839,13 @@ __device__ __forceinline__ int rec_child(const uint32_t *merged, int p) {
 }
 
 __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
-    const NodeTask *tasks, const TriTask *tris, EstBuffers B, GridMap gm) {
+    const NodeTask *tasks, EstBuffers B, GridMap gm) {
   const GridPos gp = grid_pos(gm);
   if (!gp.ok) return;
   __shared__ int s_lo[kPrepThreads], s_hi[kPrepThreads];
   __shared__ int s_prev, s_next;
   const NodeTask &T = tasks[gp.task];
-  if (T.mode != kModeTriRootPrep || !COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
+  if (T.mode != kModeTriRootPrep || !T.guard.on) return;
   const int row = gp.row;
   const int m = T.m;
   const int L = m * B.w;  // an apex has no parent or cut list
@@ -825,8 +861,7 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
   TriElemN *outn = B.prepn + slot_row * (size_t)B.Lprep;
   // the two-child sweep reads the compact elements only, the general one
   // the full elements only
-  const bool fast =
-      m == 2 && tri_path(*(ConstTask *)(tris + T.tri), B) == kTriFast;
+  const bool fast = (T.guard.on & 2) != 0;
   const int q0 = p0 + threadIdx.x * kPrepPer;  // my positions [q0, q0 + kPrepPer)
   int last_start = -1, first_end = L;
 #pragma unroll
@@ -1005,8 +1040,7 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
   __shared__ int64_t scm[kOrderThreads / 64], scx[kOrderThreads / 64];
   __shared__ uint32_t scv[kOrderThreads / 64];
   const TriTask &T = tasks[gp.task];
-  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
-  if (tri_path(*(ConstTask *)&T, B) != kTriFast) return;
+  if (T.guard.on != 1 + kTriFast) return;  // another rooting, or path
   const int row = gp.row;
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
   const int z = B.prep_z[slot_row];
@@ -1143,8 +1177,7 @@ __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
   extern __shared__ int32_t s_ps[];  // piece starts (kOrderCap + 1)
   __shared__ int s_rc[kSegThreads], s_pc[kSegThreads];
   const TriTask &T = tasks[blockIdx.x];
-  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;
-  if (tri_path(*(ConstTask *)&T, B) != kTriFast) return;
+  if (T.guard.on != 1 + kTriFast) return;  // another rooting, or path
   const int row = blockIdx.y;
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
   const int z = B.prep_z[slot_row];
@@ -1289,8 +1322,8 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   if (!gp.ok) return;
   extern __shared__ __align__(16) uint32_t skey[];  // run-ordered keys of [z, L)
   ConstTask &T = *((ConstTask *)tasks + gp.task);
-  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // another rooting runs
-  if (tri_path(T, B) != kTriFast) return;  // uniform: tri_lane_kernel's block
+  // another rooting runs, or tri_lane_kernel's block (uniform)
+  if (T.guard.on != 1 + kTriFast) return;
   const int row = gp.row;
   const int lane = threadIdx.x % kLaneThreads;
   // whole waves share a segment: make that visible to the compiler, so the
@@ -1566,8 +1599,8 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
   // the task is the same for every lane: read it through the constant
   // address space so its fields live in scalar registers
   ConstTask &T = *((ConstTask *)tasks + gp.task);
-  if (!COMPASS_GUARD_ON(T.guard, B.n_sel)) return;  // another rooting runs
-  const int path = tri_path(T, B);
+  if (!T.guard.on) return;  // another rooting runs
+  const int path = T.guard.on - 1;
   if (path == kTriFast) return;  // uniform: tri_fast_kernel's block
   const bool narrow = path == kTriNarrow;
   const int row = gp.row;
@@ -1822,13 +1855,21 @@ static GridMap grid_map(int X, int n, int d, int64_t *blocks) {
   if (blocks_ == 0) return hipErrorInvalidConfiguration;
 
 hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
-                            const EstBuffers &B, hipStream_t st) {
+                            ResolveArgs R, const EstBuffers &B,
+                            hipStream_t st) {
+  R.blocks = (R.n + R.n_tri + kSortThreads - 1) / kSortThreads;
+  if (n_jobs == 0) {
+    if (R.blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(resolve_kernel, dim3((uint32_t)R.blocks),
+                       dim3(kSortThreads), 0, st, R, B);
+    return hipGetLastError();
+  }
   int w2 = 1;
   while (w2 < B.w) w2 <<= 1;
   const int nch = std::max(1, w2 / kSortChunk);
   COMPASS_GRID(nch, n_jobs);
-  hipLaunchKernelGGL(sort_chunk_kernel, dim3((uint32_t)blocks_),
-                     dim3(kSortThreads), 0, st, job_side, B, w2, gm_);
+  hipLaunchKernelGGL(sort_chunk_kernel, dim3((uint32_t)(blocks_ + R.blocks)),
+                     dim3(kSortThreads), 0, st, job_side, B, w2, gm_, R);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sort_merge_kernel, dim3((uint32_t)blocks_),
@@ -1872,11 +1913,10 @@ hipError_t launch_node1(const NodeTask *tasks, int n, const EstBuffers &B,
 }
 
 hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
-                            const TriTask *tris, const EstBuffers &B,
-                            hipStream_t st) {
+                            const EstBuffers &B, hipStream_t st) {
   COMPASS_GRID((Lmax_apex + kPrepChunk - 1) / kPrepChunk, n);
   hipLaunchKernelGGL(apex_prep_kernel, dim3((uint32_t)blocks_),
-                     dim3(kPrepThreads), 0, st, tasks, tris, B, gm_);
+                     dim3(kPrepThreads), 0, st, tasks, B, gm_);
   return hipGetLastError();
 }
 

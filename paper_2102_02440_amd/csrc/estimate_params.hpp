@@ -41,12 +41,16 @@ enum { kModeMessage = 0, kModeTreeRoot = 1, kModeTriRootPrep = 2 };
 // Several rootings of one sub-plan may be planned (the apex candidates of
 // a triangle); each task carries the candidates' tables, and only the
 // rooting whose table has the fewest selected rows (ties: the earlier
-// candidate) does work.  n <= 1: always runs.
+// candidate) does work.  n <= 1: always runs.  `on` is resolved on the
+// device once per estimate, before the other launches (resolve_kernel):
+// 0 = the task does nothing; a node task: 1, plus 2 for a two-child apex
+// whose sweep is the compact one; a triangle task: 1 + its arithmetic path
+// (kTriFast, kTriNarrow, kTriWide).
 struct TaskGuard {
   int32_t n;
   int32_t self;
   int32_t tab[3];
-  int32_t pad;
+  int32_t on;
 };
 enum { kSpSingle = 0, kSpTree = 1, kSpTriangle = 2, kSpUnsupported = 3,
        kSpGeneric = 4 };
@@ -91,6 +95,15 @@ struct TriTask {
   int32_t partial_slot;     // first of gridDim.z partial sums
   int32_t root_table;
   uint64_t child_tables[kMaxChild];  // tables of each child's subtree
+};
+
+// The tasks whose guards resolve_task sets (blocks: workgroups of
+// kSortThreads lanes for them, one task a lane).
+struct ResolveArgs {
+  NodeTask *tasks;
+  TriTask *tris;
+  int32_t n, n_tri;
+  int32_t blocks, pad;
 };
 
 struct SubplanTask {
