@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <array>
 #include <map>
 #include <mutex>
 #include <string>
@@ -59,7 +60,8 @@ hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
                             const EstBuffers &B, hipStream_t st);
 hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
                             hipStream_t st);
-hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
+hipError_t launch_tri_lane(const TriTask *tasks, int n, const TriGroup *groups,
+                           int n_groups, int zblocks,
                            const EstBuffers &B, hipStream_t st);
 hipError_t launch_gen_contract(const GenArgs &A, const EstBuffers &B,
                                int n_blocks, int fp64, hipStream_t st);
@@ -792,6 +794,7 @@ struct Planner {
   std::vector<NodeTask> tasks;
   std::vector<int> task_level;
   std::vector<TriTask> tris;
+  std::vector<std::array<int32_t, 9>> tri_key;  // what a sweep group shares
   std::vector<SubplanTask> sps;
   int n_msg_slots = 0, n_x_slots = 0, n_prep_slots = 0, n_partial_slots = 0;
   int Lmax = 0, Lprep = 0;
@@ -1279,6 +1282,10 @@ static compass_status plan_subplan(Planner &pl, uint64_t mask, int spi) {
         tr.partial_slot = sp.x_slot;
         T.tri = (int)pl.tris.size();
         pl.tris.push_back(tr);
+        pl.tri_key.push_back({tr.root_table, T.m, T.child_side[0],
+                              T.m > 1 ? T.child_side[1] : -1, tr.cut_eid,
+                              tr.cut_side[0], tr.cut_side[1], tr.cut_child[0],
+                              tr.cut_child[1]});
       }
       if (T.m > 0) pl.Lmax = std::max(pl.Lmax, nl * pl.w);
       pl.tasks.push_back(T);
@@ -1404,6 +1411,26 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_jobs = carve(sizeof(int32_t) * std::max<size_t>(1, sort_jobs.size()));
   const size_t o_tasks = carve(sizeof(NodeTask) * std::max<size_t>(1, flat.size()));
   const size_t o_tris = carve(sizeof(TriTask) * std::max<size_t>(1, pl.tris.size()));
+  // two-child sweep groups: triangle tasks of the same apex structure, in
+  // order of first appearance, kFastSegs at most per group
+  std::vector<TriGroup> tgroups;
+  {
+    std::map<std::array<int32_t, 9>, int> open;  // key -> group being filled
+    for (size_t t = 0; t < pl.tris.size(); ++t) {
+      if (pl.tris[t].m != 2) continue;
+      auto it = open.find(pl.tri_key[t]);
+      if (it == open.end() || tgroups[it->second].n == kFastSegs) {
+        TriGroup gr;
+        memset(&gr, 0, sizeof gr);
+        tgroups.push_back(gr);
+        open[pl.tri_key[t]] = (int)tgroups.size() - 1;
+        it = open.find(pl.tri_key[t]);
+      }
+      TriGroup &gr = tgroups[it->second];
+      gr.member[gr.n++] = (int)t;
+    }
+  }
+  const size_t o_tgroups = carve(sizeof(TriGroup) * std::max<size_t>(1, tgroups.size()));
   const size_t o_sps = carve(sizeof(SubplanTask) * pl.sps.size());
   const size_t o_sorted = carve(sizeof(uint64_t) * 2 * g->n_edges * d * (size_t)w);
   int w2 = 1;
@@ -1450,6 +1477,8 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
     memcpy(host.data() + o_tasks, flat.data(), sizeof(NodeTask) * flat.size());
   if (!pl.tris.empty())
     memcpy(host.data() + o_tris, pl.tris.data(), sizeof(TriTask) * pl.tris.size());
+  if (!tgroups.empty())
+    memcpy(host.data() + o_tgroups, tgroups.data(), sizeof(TriGroup) * tgroups.size());
   memcpy(host.data() + o_sps, pl.sps.data(), sizeof(SubplanTask) * pl.sps.size());
   st = upload(ds, base, host.data(), o_sorted, stream);
   if (st != COMPASS_OK) return st;
@@ -1553,6 +1582,8 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
     ProfScope ps("tri_lane", stream);
     HIP_OK(launch_tri_lane(reinterpret_cast<const TriTask *>(base + o_tris),
                            (int)pl.tris.size(),
+                           reinterpret_cast<const TriGroup *>(base + o_tgroups),
+                           (int)tgroups.size(),
                            (w + kLaneThreads - 1) / kLaneThreads, B, stream));
   }
   if (!pl.gplans.empty()) {

@@ -1280,22 +1280,29 @@ __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
   }
 }
 
-// Two-child apexes: grid (n_tri, d, ceil(w / kLaneThreads)), kFastSegs
-// segments of the sweep per block (segment s = threads s * kLaneThreads ..,
-// bounds from tri_seg_kernel).
-// Cutting the descending sweep into segments is exact: a segment's runs see
-// the other child's running sum of the earlier segments plus their own, so
-//   G = sum_s [ G_s + A0(before s) * X1_s + A1(before s) * X0_s ]
+// Two-child apexes, by group: grid (groups, d, ceil(w / kLaneThreads)),
+// kFastSegs slots of kLaneThreads lanes per workgroup.  The triangle tasks
+// of a group share the apex's merged list, its runs and run pieces, the
+// cut edge and its sides; they differ in the children's messages only.  A
+// lane's binary search of a run piece (the first key at or above its
+// threshold) is therefore the same for every member: it is done once, by
+// one slot, and handed to the others through LDS.
+//
+// With nm members running, slot s works for member s % nm on segment
+// s / nm of S = kFastSegs / nm (rounded down to 1, 2 or 4) segments of the
+// sweep; segment g covers tri_seg_kernel's run groups
+// [4 - (g + 1) 4 / S, 4 - g 4 / S).  Cutting the descending sweep into
+// segments is exact: a segment's runs see the other child's running sum
+// of the earlier segments plus their own, so
+//   G = sum_g [ G_g + A0(before g) * X1_g + A1(before g) * X0_g ]
 // with X_c the segment's sum of the run terms of child c (v * mu summed).
-// A run piece is summed element by element, or, when the run is long and
-// tri_order_kernel has ordered the list, by one binary search over the
-// run-ordered keys (staged in LDS) and two prefix-sum reads.
-
-// a run piece as the sweep reads it (wave-uniform)
-struct PieceIn {
-  int lo, hi, info, v0, v1;
-  int64_t m0, x0;
-};
+// The slots of one segment go through its pieces in rounds of nm: in round
+// r each searches one piece (writing its lanes' offsets into LDS), and
+// after one barrier each closes all nm pieces for its member (prefix-sum
+// reads of its own member at the searched positions).  The searches of
+// round r + 1 are issued before the closes of round r (two LDS buffers).
+// Short runs are summed element by element, lists too long to order
+// element by element throughout.
 
 struct SegOut {
   u128 G;
@@ -1303,6 +1310,8 @@ struct SegOut {
 };
 static_assert(sizeof(SegOut) * kFastSegs * kLaneThreads <= kFastStageBytes,
               "segment results reuse the key stage");
+constexpr int kFastPbufBytes = 2 * kFastSegs * kLaneThreads * 2;
+constexpr int kFastLds = kFastStageBytes + kFastPbufBytes;
 
 // first index in [0, n) whose key is >= kf, n >= 1 (uniform trip count)
 __device__ __forceinline__ int lds_lower_bound(const uint32_t *k, int n,
@@ -1316,36 +1325,60 @@ __device__ __forceinline__ int lds_lower_bound(const uint32_t *k, int n,
   return base + (k[base] < kf ? 1 : 0);
 }
 
+typedef const __attribute__((address_space(4))) TriPiece ConstPiece;
+
 __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
-    const TriTask *tasks, EstBuffers B, GridMap gm) {
+    const TriTask *tasks, const TriGroup *groups, EstBuffers B, GridMap gm) {
   const GridPos gp = grid_pos(gm);
   if (!gp.ok) return;
   extern __shared__ __align__(16) uint32_t skey[];  // run-ordered keys of [z, L)
-  ConstTask &T = *((ConstTask *)tasks + gp.task);
-  // another rooting runs, or tri_lane_kernel's block (uniform)
-  if (T.guard.on != 1 + kTriFast) return;
+  // search offsets [buffer][slot][lane], addressed from my lane's column
+  uint16_t *pcol = reinterpret_cast<uint16_t *>(
+                       reinterpret_cast<char *>(skey) + kFastStageBytes) +
+                   threadIdx.x % kLaneThreads;
+  auto pbuf_at = [&](int buf, int sl) -> uint16_t & {
+    return pcol[(buf * kFastSegs + sl) * kLaneThreads];
+  };
+  // the members that run (compacted with static indices, so that they stay
+  // in scalar registers); slots past nm repeat the first
+  const TriGroup &Gr = groups[gp.task];
+  int mem[kFastSegs];
+  int nm = 0;
+#pragma unroll
+  for (int q = 0; q < kFastSegs; ++q) {
+    mem[q] = 0;
+    if (q >= Gr.n) continue;
+    const int t = Gr.member[q];
+    if (tasks[t].guard.on != 1 + kTriFast) continue;  // another rooting, or path
+#pragma unroll
+    for (int g = 0; g <= q; ++g)
+      if (g == nm) mem[g] = t;
+    ++nm;
+  }
+  if (nm == 0) return;  // uniform
+  const int S = nm == 1 ? 4 : (nm == 2 ? 2 : 1);  // segments
+  const int gs = kFastSegs / S;                    // run groups per segment
   const int row = gp.row;
   const int lane = threadIdx.x % kLaneThreads;
-  // whole waves share a segment: make that visible to the compiler, so the
+  // whole waves share a slot: make that visible to the compiler, so the
   // sweep's positions and element loads stay scalar
-  const int seg = __builtin_amdgcn_readfirstlane(threadIdx.x / kLaneThreads);
-  // kFastJ buckets J per lane (their searches and loads overlap)
-  int Jc[kFastJ];
-  bool active[kFastJ];
+  const int slot = __builtin_amdgcn_readfirstlane(threadIdx.x / kLaneThreads);
+  const bool working = slot < S * nm;  // nm = 3: one slot only searches
+  const int mi = slot % nm;            // my member
+  const int seg = slot / nm;           // my segment
+  int my = mem[0];
 #pragma unroll
-  for (int u = 0; u < kFastJ; ++u) {
-    const int J = (gp.c * kFastJ + u) * kLaneThreads + lane;
-    active[u] = J < B.w;
-    Jc[u] = active[u] ? J : 0;
-  }
+  for (int g = 1; g < kFastSegs; ++g)
+    if (g == mi) my = mem[g];
+  ConstTask &T = *((ConstTask *)tasks + mem[0]);  // the shared structure
+  ConstTask &M = *((ConstTask *)tasks + my);      // my member
+  const int J = gp.c * kLaneThreads + lane;
+  const bool active = J < B.w;
+  const int Jc = active ? J : 0;
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
+  const size_t my_row = (size_t)M.prep_slot * B.d + row;
   const int z = B.prep_z[slot_row];  // the sweep ends at the zero prefix
   const int len = T.L - z;
-  // segment seg sweeps run group kFastSegs - 1 - seg (groups ascend in
-  // position, the sweep descends)
-  const int32_t *sb = B.tseg + slot_row * (kFastSegs + 1);
-  const int top = __builtin_amdgcn_readfirstlane(sb[kFastSegs - seg]) - 1;
-  const int bottom = __builtin_amdgcn_readfirstlane(sb[kFastSegs - 1 - seg]);
   const bool ordered = len <= kOrderCap;  // tri_order_kernel ran
   const uint32_t *tk = B.tkey + slot_row * (size_t)B.Lprep;
   if (ordered) {
@@ -1353,62 +1386,74 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     __syncthreads();
   }
 
-  // child slot 0 / 1 state; key < kf  <=>  kappa below the cut element's
-  // (ties in |v| go to the lower edge id)
-  uint32_t kf0[kFastJ], kf1[kFastJ];
-  int64_t C0[kFastJ], C1[kFastJ];
+  // key < kf  <=>  kappa below the cut element's (ties in |v| go to the
+  // lower edge id); the cut constants are my member's
   const int e0 = T.cut_child[0] == 0 ? 0 : 1;  // cut endpoint in slot 0
-#pragma unroll
-  for (int u = 0; u < kFastJ; ++u) {
+  uint32_t kf0, kf1;
+  int64_t C0, C1;
+  {
     uint32_t kf[2];
     int64_t cv[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      kf[e] = (uint32_t)abs_u64(counter_at(B, T.cut_side[e], row, Jc[u])) +
+      kf[e] = (uint32_t)abs_u64(counter_at(B, T.cut_side[e], row, Jc)) +
               (T.cut_peid[e] < T.cut_eid ? 1u : 0u);
-      cv[e] = (int64_t)(uint64_t)child_msg_at(B, T.cut_cmsg[e], row, Jc[u]);
+      cv[e] = (int64_t)(uint64_t)child_msg_at(B, M.cut_cmsg[e], row, Jc);
     }
-    kf0[u] = kf[e0];
-    kf1[u] = kf[1 - e0];
-    C0[u] = cv[e0];
-    C1[u] = cv[1 - e0];
+    kf0 = kf[e0];
+    kf1 = kf[1 - e0];
+    C0 = cv[e0];
+    C1 = cv[1 - e0];
   }
-  ConstElemN *el = (ConstElemN *)(B.prepn + slot_row * (size_t)B.Lprep);
-  int64_t A0[kFastJ], A1[kFastJ], X0[kFastJ], X1[kFastJ];
-  u128 G[kFastJ];
-#pragma unroll
-  for (int u = 0; u < kFastJ; ++u) {
-    A0[u] = A1[u] = X0[u] = X1[u] = 0;
-    G[u] = 0;
-  }
-  // close a run piece of bucket u: its terms times the other child's
-  // running sum
-  auto close = [&](int u, uint32_t c, const FastRun &r) {
-    const int64_t cc = c ? C1[u] : C0[u];
+  ConstElemN *el = (ConstElemN *)(B.prepn + my_row * (size_t)B.Lprep);
+  u128 G = 0;
+  // Runs close in alternating children (consecutive pieces of one child
+  // are merged first, below), so the running sums are kept as "child of
+  // the last close" (Ap, Xp) and "the other child" (Aq, Xq): a close
+  // multiplies by Ap, adds its run to Aq and Xq, and the two swap roles.
+  // No per-lane selects between the children's sums.
+  int64_t Ap = 0, Aq = 0, Xp = 0, Xq = 0;
+  uint32_t lastc = 0;  // child of the last close (before the first: any)
+  auto close = [&](uint32_t c, const FastRun &r) {
+    const int64_t cc = c ? C1 : C0;
     const int64_t x = r.xb + cc * (int64_t)(r.vrun - r.vb);
     const int64_t arun = r.mb + cc * (int64_t)(r.nrun - r.nb);
-    if (c) {
-      G[u] += mul_s64_s64(x, A0[u]);
-      A1[u] += arun;
-      X1[u] += x;
+    G += mul_s64_s64(x, Ap);
+    const int64_t an = Aq + arun, xn = Xq + x;
+    Aq = Ap;
+    Xq = Xp;
+    Ap = an;
+    Xp = xn;
+    lastc = c;
+  };
+  // consecutive pieces of one child (a run cut at ordering tiles) close
+  // as one: within a run the other child's running sum does not change,
+  // and a piece's sums add
+  FastRun pend;
+  pend.mb = pend.xb = 0;
+  pend.vb = pend.nb = pend.vrun = pend.nrun = 0;
+  uint32_t pc = 2;  // child of the pending pieces (2: none)
+  auto add_piece = [&](uint32_t c, const FastRun &r) {
+    if (c == pc) {
+      pend.mb += r.mb;
+      pend.xb += r.xb;
+      pend.vb += r.vb;
+      pend.nb += r.nb;
+      pend.vrun += r.vrun;
+      pend.nrun += r.nrun;
     } else {
-      G[u] += mul_s64_s64(x, A1[u]);
-      A0[u] += arun;
-      X0[u] += x;
+      if (pc < 2) close(pc, pend);
+      pend = r;
+      pc = c;
     }
   };
-  // element by element over [lo, hi], descending, for every bucket of the
-  // lane (the element loads are shared)
-  auto elements = [&](int lo, int hi, uint32_t c, FastRun *r) {
-    constexpr int kGroup = 8;
-    uint32_t kf[kFastJ];
-#pragma unroll
-    for (int u = 0; u < kFastJ; ++u) {
-      kf[u] = c ? kf1[u] : kf0[u];
-      r[u].mb = r[u].xb = 0;
-      r[u].vb = r[u].nb = 0;
-      r[u].vrun = r[u].nrun = 0;
-    }
+  // element by element over [lo, hi], descending (my member's elements)
+  auto elements = [&](int lo, int hi, uint32_t c, FastRun &r) {
+    constexpr int kGroup = 4;  // its loads stay in scalar registers
+    const uint32_t kf = c ? kf1 : kf0;
+    r.mb = r.xb = 0;
+    r.vb = r.nb = 0;
+    r.vrun = r.nrun = 0;
     int pos = hi;
     for (; pos - (kGroup - 1) >= lo; pos -= kGroup) {
       int32_t v[kGroup];
@@ -1427,164 +1472,153 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
       for (int q = 0; q < kGroup; ++q)
         __asm__ volatile("" ::"s"(v[q]), "s"(kc[q]), "s"(mu[q]), "s"(vm[q]));
 #pragma unroll
-      for (int q = 0; q < kGroup; ++q)
-#pragma unroll
-        for (int u = 0; u < kFastJ; ++u)
-          fast_elem(r[u], kf[u], v[q], kc[q], mu[q], vm[q]);
+      for (int q = 0; q < kGroup; ++q) fast_elem(r, kf, v[q], kc[q], mu[q], vm[q]);
     }
     for (; pos >= lo; --pos) {
       ConstElemN &e = el[pos];
-#pragma unroll
-      for (int u = 0; u < kFastJ; ++u)
-        fast_elem(r[u], kf[u], e.v, e.kc, e.mu, e.vm);
+      fast_elem(r, kf, e.v, e.kc, e.mu, e.vm);
     }
   };
   if (ordered) {
-    // the pieces of run group kFastSegs - 1 - seg (tri_seg_kernel), 64 at a
-    // time: lane k loads piece b0 + k, the sweep broadcasts it with
-    // readlane; the next long piece's searches and prefix loads are issued
-    // before the current piece is summed
+    // segment bounds in the piece table; rounds of nm pieces
     const int32_t *sp = B.tsegp + slot_row * (kFastSegs + 1);
-    const int pb = __builtin_amdgcn_readfirstlane(sp[kFastSegs - 1 - seg]);
-    const int pe = __builtin_amdgcn_readfirstlane(sp[kFastSegs - seg]);
-    const TriPiece *pcs = B.tpiece + slot_row * (size_t)B.Pcap;
-    const TriPre *pre0 = B.tpre + tpre_index(B, slot_row, 0, 0);
-    const int wl = (int)threadIdx.x & 63;
-    for (int hb = pe; hb > pb; hb -= 64) {
-      const int b0 = max(pb, hb - 64);
-      const int nb = hb - b0;
-      const TriPiece dv = pcs[b0 + min(wl, nb - 1)];
-      auto get = [&](int k, PieceIn &o) {
-        o.lo = __builtin_amdgcn_readlane(dv.lo, k);
-        o.hi = __builtin_amdgcn_readlane(dv.hi, k);
-        o.info = __builtin_amdgcn_readlane(dv.info, k);
-        o.v0 = __builtin_amdgcn_readlane(dv.v0, k);
-        o.v1 = __builtin_amdgcn_readlane(dv.v1, k);
-        o.m0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
-                              (int)((uint64_t)dv.m0 >> 32), k) << 32) |
-                         (uint32_t)__builtin_amdgcn_readlane((int)dv.m0, k));
-        o.x0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
-                              (int)((uint64_t)dv.x0 >> 32), k) << 32) |
-                         (uint32_t)__builtin_amdgcn_readlane((int)dv.x0, k));
+    int rounds = 0;
+    for (int g = 0; g < S; ++g) {  // uniform
+      const int n = sp[kFastSegs - g * gs] - sp[kFastSegs - (g + 1) * gs];
+      rounds = max(rounds, (n + nm - 1) / nm);
+    }
+    const int pb = __builtin_amdgcn_readfirstlane(sp[kFastSegs - (seg + 1) * gs]);
+    const int pe = __builtin_amdgcn_readfirstlane(sp[kFastSegs - seg * gs]);
+    ConstPiece *pcs = (ConstPiece *)B.tpiece + slot_row * (size_t)B.Pcap;
+    ConstPiece *mpcs = (ConstPiece *)B.tpiece + my_row * (size_t)B.Pcap;
+    const TriPre *mpre = B.tpre + tpre_index(B, my_row, 0, 0);
+    // my search of round r: piece pe - 1 - (nm r + mi), its lanes' offsets
+    // into buffer r & 1
+    auto search = [&](int r) {
+      const int i = pe - 1 - (nm * r + mi);
+      if (!working || i < pb) return;  // uniform
+      const int info = pcs[i].info;
+      if (!(info & 2)) return;
+      const int lo = pcs[i].lo, hi = pcs[i].hi;
+      const uint32_t kf = (info & 1) ? kf1 : kf0;
+      const int p = lds_lower_bound(skey + (lo - z), hi - lo + 1, kf);
+      pbuf_at(r & 1, slot) = (uint16_t)p;
+    };
+    search(0);
+    for (int r = 0; r < rounds; ++r) {
+      __syncthreads();  // round r's offsets are written
+      // my member's prefixes at the searched positions of the round: the
+      // first is loaded during the next round's search, each later one
+      // during the close of the piece before it
+      const int i0 = pe - 1 - nm * r;
+      const int nq = working ? min(nm, i0 - pb + 1) : 0;  // my pieces left
+      auto gather = [&](int q, TriPre &e) {
+        e.m = e.x = 0;
+        e.v = e.pad = 0;
+        if (q >= nq) return;
+        const int i = i0 - q;
+        const int info = pcs[i].info;
+        if (!(info & 2)) return;
+        const int tile = info >> 2;
+        const int p = pcs[i].lo + pbuf_at(r & 1, seg * nm + q);
+        e = mpre[(size_t)tile * (kOrderTile + 1) + (p - z - tile * kOrderTile)];
       };
-      // per bucket: position of the first key >= kf in a long piece (the
-      // binary searches of all buckets in lockstep), and its prefix
-      auto search = [&](const PieceIn &o, int *p, TriPre *ep) {
-        const uint32_t *k = skey + (o.lo - z);
-        uint32_t kf[kFastJ];
-        int base[kFastJ];
+      TriPre ep;
+      gather(0, ep);
+      if (r + 1 < rounds) search(r + 1);
 #pragma unroll
-        for (int u = 0; u < kFastJ; ++u) {
-          kf[u] = (o.info & 1) ? kf1[u] : kf0[u];
-          base[u] = 0;
-        }
-        int n = o.hi - o.lo + 1;
-        while (n > 1) {
-          const int half = n >> 1;
-#pragma unroll
-          for (int u = 0; u < kFastJ; ++u)
-            base[u] = k[base[u] + half] < kf[u] ? base[u] + half : base[u];
-          n -= half;
-        }
-        const int tile = o.info >> 2;
-        const TriPre *tp = pre0 + (size_t)tile * (kOrderTile + 1) -
-                           (z + tile * kOrderTile);
-#pragma unroll
-        for (int u = 0; u < kFastJ; ++u) {
-          p[u] = o.lo + base[u] + (k[base[u]] < kf[u] ? 1 : 0);
-          ep[u] = tp[p[u]];
-        }
-      };
-      PieceIn cur, nxt;
-      int pc[kFastJ], pn[kFastJ];
-      TriPre ec[kFastJ], en[kFastJ];
-#pragma unroll
-      for (int u = 0; u < kFastJ; ++u) {
-        pc[u] = pn[u] = 0;
-        ec[u].m = ec[u].x = 0;
-        ec[u].v = ec[u].pad = 0;
-        en[u] = ec[u];
-      }
-      get(nb - 1, cur);
-      if (cur.info & 2) search(cur, pc, ec);
-      for (int k = nb - 1; k >= 0; --k) {
-        if (k > 0) {
-          get(k - 1, nxt);
-          if (nxt.info & 2) search(nxt, pn, en);
-        }
-        const uint32_t c = cur.info & 1;
-        FastRun r[kFastJ];
-        if (cur.info & 2) {
-#pragma unroll
-          for (int u = 0; u < kFastJ; ++u) {
-            r[u].mb = (int64_t)((uint64_t)ec[u].m - (uint64_t)cur.m0);
-            r[u].xb = (int64_t)((uint64_t)ec[u].x - (uint64_t)cur.x0);
-            r[u].vb = (int32_t)((uint32_t)ec[u].v - (uint32_t)cur.v0);
-            r[u].nb = pc[u] - cur.lo;
-            r[u].vrun = (int32_t)((uint32_t)cur.v1 - (uint32_t)cur.v0);
-            r[u].nrun = cur.hi - cur.lo + 1;
-          }
+      for (int q = 0; q < kFastSegs; ++q) {
+        if (q >= nq) break;
+        const int i = i0 - q;
+        const int info = pcs[i].info;
+        const int lo = pcs[i].lo, hi = pcs[i].hi;
+        const uint32_t c = info & 1;
+        FastRun rr;
+        if (info & 2) {
+          const TriPre &e = ep;
+          const int p = lo + pbuf_at(r & 1, seg * nm + q);
+          rr.mb = (int64_t)((uint64_t)e.m - (uint64_t)mpcs[i].m0);
+          rr.xb = (int64_t)((uint64_t)e.x - (uint64_t)mpcs[i].x0);
+          rr.vb = (int32_t)((uint32_t)e.v - (uint32_t)pcs[i].v0);
+          rr.nb = p - lo;
+          rr.vrun = (int32_t)((uint32_t)pcs[i].v1 - (uint32_t)pcs[i].v0);
+          rr.nrun = hi - lo + 1;
         } else {
-          elements(cur.lo, cur.hi, c, r);
+          elements(lo, hi, c, rr);
         }
-#pragma unroll
-        for (int u = 0; u < kFastJ; ++u) close(u, c, r[u]);
-        cur = nxt;
-#pragma unroll
-        for (int u = 0; u < kFastJ; ++u) {
-          pc[u] = pn[u];
-          ec[u] = en[u];
-        }
+        if (q + 1 < kFastSegs) gather(q + 1, ep);
+        add_piece(c, rr);
       }
     }
-  } else {
+  } else if (working) {
     // unordered list: runs element by element, segments by position
+    const int32_t *sb = B.tseg + slot_row * (kFastSegs + 1);
+    const int top = __builtin_amdgcn_readfirstlane(sb[kFastSegs - seg * gs]) - 1;
+    const int bottom =
+        __builtin_amdgcn_readfirstlane(sb[kFastSegs - (seg + 1) * gs]);
     int pos = top;
     while (pos >= bottom) {
       const uint32_t c = el[pos].kc >> 31;  // the run's child (uniform)
       const int lo = max(el[pos].run_lo, bottom);
-      FastRun r[kFastJ];
-      elements(lo, pos, c, r);
-#pragma unroll
-      for (int u = 0; u < kFastJ; ++u) close(u, c, r[u]);
+      FastRun rr;
+      elements(lo, pos, c, rr);
+      add_piece(c, rr);
       pos = lo - 1;
     }
   }
-  // segments combine exactly (one bucket of the lane at a time: the LDS
-  // stage holds one set of segment results)
+  if (pc < 2) close(pc, pend);
+  const int64_t A0 = lastc ? Aq : Ap, A1 = lastc ? Ap : Aq;
+  const int64_t X0 = lastc ? Xq : Xp, X1 = lastc ? Xp : Xq;
+  // segments combine exactly, per member (slot (mi, 0) sums its member's
+  // S segments), then the member's lanes are summed
+  __syncthreads();  // the key stage and the offset buffers are done with
   SegOut (*so)[kLaneThreads] = reinterpret_cast<SegOut (*)[kLaneThreads]>(skey);
-  u128 *red = reinterpret_cast<u128 *>(&so[1][0]);  // free once combined
+  {
+    SegOut &mine = so[slot][lane];
+    mine.G = G;
+    mine.A0 = A0;
+    mine.A1 = A1;
+    mine.X0 = X0;
+    mine.X1 = X1;
+  }
+  __syncthreads();
+  u128 tot = 0;
+  if (working && seg == 0) {
+    int64_t a0 = 0, a1 = 0;
+    for (int g = 0; g < S; ++g) {
+      const SegOut &o = so[g * nm + mi][lane];
+      tot += o.G + mul_s64_s64(a0, o.X1) + mul_s64_s64(a1, o.X0);
+      a0 += o.A0;
+      a1 += o.A1;
+    }
+    if (!active) tot = 0;
+  }
+  // lanes: within each wave by shuffles, then the slot's four waves
+  __syncthreads();  // the segment results are read
+  u128 *red = reinterpret_cast<u128 *>(skey);  // [kFastSegs][4]
+  {
+    uint32_t w4[4] = {(uint32_t)tot, (uint32_t)(tot >> 32),
+                      (uint32_t)(tot >> 64), (uint32_t)(tot >> 96)};
+    // 128-bit sums: add 32-bit limbs with carries, one xor distance at a time
 #pragma unroll
-  for (int u = 0; u < kFastJ; ++u) {
-    __syncthreads();  // the key stage (or the previous round) is done with
-    SegOut &mine = so[seg][lane];
-    mine.G = G[u];
-    mine.A0 = A0[u];
-    mine.A1 = A1[u];
-    mine.X0 = X0[u];
-    mine.X1 = X1[u];
-    __syncthreads();
-    u128 g = 0;
-    if (seg == 0) {
-      int64_t a0 = 0, a1 = 0;
-      for (int s2 = 0; s2 < kFastSegs; ++s2) {
-        const SegOut &o = so[s2][lane];
-        g += o.G + mul_s64_s64(a0, o.X1) + mul_s64_s64(a1, o.X0);
-        a0 += o.A0;
-        a1 += o.A1;
-      }
+    for (int off = 32; off > 0; off >>= 1) {
+      u128 o = 0;
+#pragma unroll
+      for (int k = 3; k >= 0; --k)
+        o = (o << 32) | (uint32_t)__shfl_xor((int)w4[k], off);
+      tot += o;
+      w4[0] = (uint32_t)tot;
+      w4[1] = (uint32_t)(tot >> 32);
+      w4[2] = (uint32_t)(tot >> 64);
+      w4[3] = (uint32_t)(tot >> 96);
     }
-    __syncthreads();
-    if (seg == 0) red[lane] = active[u] ? g : (u128)0;
-    __syncthreads();
-    for (int off = kLaneThreads / 2; off > 0; off >>= 1) {
-      if (seg == 0 && lane < off) red[lane] += red[lane + off];
-      __syncthreads();
-    }
-    // one partial slot per kLaneThreads buckets
-    const int slot = gp.c * kFastJ + u;
-    if (threadIdx.x == 0 && slot * kLaneThreads < B.w)
-      B.partial[((size_t)T.partial_slot + slot) * B.d + row] = red[0];
+    if ((threadIdx.x & 63) == 0) red[slot * 4 + lane / 64] = tot;
+  }
+  __syncthreads();
+  if (working && seg == 0 && lane == 0) {
+    const u128 sum = red[slot * 4] + red[slot * 4 + 1] + red[slot * 4 + 2] +
+                     red[slot * 4 + 3];
+    B.partial[((size_t)M.partial_slot + gp.c) * B.d + row] = sum;
   }
 }
 
@@ -1935,14 +1969,15 @@ hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
   return hipGetLastError();
 }
 
-hipError_t launch_tri_lane(const TriTask *tasks, int n, int zblocks,
-                           const EstBuffers &B, hipStream_t st) {
+hipError_t launch_tri_lane(const TriTask *tasks, int n, const TriGroup *groups,
+                           int n_groups, int zblocks, const EstBuffers &B,
+                           hipStream_t st) {
   // each (task, row, chunk) block does its work in exactly one of the two
-  {
-    COMPASS_GRID((zblocks + kFastJ - 1) / kFastJ, n);
+  if (n_groups > 0) {
+    COMPASS_GRID(zblocks, n_groups);
     hipLaunchKernelGGL(tri_fast_kernel, dim3((uint32_t)blocks_),
-                       dim3(kLaneThreads * kFastSegs), (size_t)kFastStageBytes,
-                       st, tasks, B, gm_);
+                       dim3(kLaneThreads * kFastSegs), (size_t)kFastLds, st,
+                       tasks, groups, B, gm_);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -30,7 +30,6 @@ constexpr int kSegThreads = 1024;
 constexpr int kSegPer = 16;
 constexpr int kFastSegs = 4;  // sweep segments per cut bucket
 constexpr int kSearchMin = 8;  // shortest run the sweep sums by search
-constexpr int kFastJ = 1;  // cut buckets per lane of the two-child sweep
 constexpr int kOrderTile = 2048;  // positions ordered by one workgroup
 constexpr int kOrderCap = 16384;  // longest two-child apex list run-ordered
 constexpr int kFastStageBytes = kOrderCap * 4;  // its keys, staged in LDS
@@ -95,6 +94,15 @@ struct TriTask {
   int32_t partial_slot;     // first of gridDim.z partial sums
   int32_t root_table;
   uint64_t child_tables[kMaxChild];  // tables of each child's subtree
+};
+
+// Triangle tasks whose apex list, runs and cut edge are the same (the same
+// apex table, child sides and cut edge; they differ in the messages of the
+// subtrees below): the two-child sweep searches once for all of them.
+struct TriGroup {
+  int32_t n;
+  int32_t member[kFastSegs];
+  int32_t pad[3];
 };
 
 // The tasks whose guards resolve_task sets (blocks: workgroups of

@@ -322,6 +322,67 @@ def test_triangle_run_order(oracle, shape):
     check_query(oracle, q, masks=masks, name="triangle run order " + shape)
 
 
+def _triangle_group_query(seed, w, d):
+    """Triangle 0-1-2 (table 0 the smallest, so the apex of every rooting
+    that runs) with table 3 hanging off table 1 and table 4 off table 2: the
+    sub-plans {0,1,2}, {0,1,2,3}, {0,1,2,4}, {0,1,2,3,4} share the apex's
+    list, runs and cut edge and differ in the cut endpoints' messages."""
+    rng = np.random.default_rng(seed)
+    n = [1500, 6000, 5000, 4000, 3000]
+    tables = []
+    for t in range(5):
+        cols = {"k0": rng.integers(0, 400, n[t]).astype(np.int32),
+                "k1": rng.integers(0, 400, n[t]).astype(np.int32)}
+        tables.append(W.Table("t%d" % t, cols, []))
+    edges = [W.Edge(0, "k0", 1, "k0"), W.Edge(0, "k1", 2, "k0"),
+             W.Edge(1, "k1", 2, "k1"), W.Edge(1, "k0", 3, "k0"),
+             W.Edge(2, "k1", 4, "k1")]
+    return W.Query(tables, edges, d, w, W.draw_seeds(rng, len(edges), d), 32)
+
+
+_GROUP_CASES = ([(m, 512, 3, x) for m in (1, 2, 3, 4) for x in (False, True)] +
+                [(2, 16384, 1, False), (3, 16384, 1, True)])
+
+
+@gpu
+@pytest.mark.parametrize("members,w,d,mixed", _GROUP_CASES)
+def test_triangle_groups(oracle, members, w, d, mixed):
+    """Triangle sub-plans that share one two-child apex are swept together
+    (the binary searches once for all of them): groups of 1 to 4 running
+    members, ordered lists and lists beyond the ordering (w = 16384), and
+    groups where the sub-plans holding table 3 take the general sweep
+    instead (its selected count raised above 2^30, a valid bound)."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    q = _triangle_group_query(300 + members + w, w, d)
+    _say("triangle groups", "members", members, "w", w, "d", d, "mixed", mixed)
+    dq = C.DeviceQuery(q)
+    dq.build()
+    torch.cuda.synchronize()
+    side_sk, n_sel = oracle_query(oracle, q)
+    assert dq.n_selected.cpu().tolist() == n_sel
+    if mixed:
+        n_sel[3] += 1 << 30
+        dq.n_selected.copy_(torch.tensor(n_sel, dtype=torch.int64))
+    tri = [0b00111, 0b01111, 0b10111, 0b11111][:members]
+    masks = tri + [0b00011, 0b01010, 0b10100]
+    row_est, est, flags = dq.estimate(masks)
+    torch.cuda.synchronize()
+    vals_o, est_o, flags_o = oracle.estimate(len(q.tables), q.edge_u, q.edge_v,
+                                             q.d, q.w, side_sk, n_sel, masks)
+    vals_g = C.row_values(row_est)
+    fl = flags.cpu().numpy()
+    for m in range(len(masks)):
+        assert not fl[m] & C.FLAG_UNSUPPORTED, "mask 0x%x" % masks[m]
+        go = [v & ((1 << 128) - 1) for v in vals_o[m]]
+        assert vals_g[m] == go, "mask 0x%x" % masks[m]
+        f_x, e_x, tol = expected_flag_est(oracle, len(q.tables), q.edge_u, q.edge_v,
+                                          q.d, q.w, side_sk, n_sel, masks[m],
+                                          vals_o[m], flags_o[m], est_o[m])
+        assert fl[m] == f_x, "mask 0x%x" % masks[m]
+        assert abs(est.cpu().numpy()[m] - e_x) <= tol, "mask 0x%x" % masks[m]
+
+
 @gpu
 def test_job6a_full_size(oracle):
     """Full-size 6a-shaped workload (ci 36M, mk 4.5M, t 2.5M, n 4.2M, k 134k;
