@@ -46,7 +46,7 @@ hipError_t launch_slab_reduce(const int32_t *slab, int64_t chunks,
                               const FlushCtl &fc, hipStream_t st);
 hipError_t launch_store_seeds(const RowSeeds *src, int n, RowSeeds *dst,
                               hipStream_t st);
-hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
+hipError_t launch_sort_rows(const SortJob *jobs, int n_jobs,
                             ResolveArgs R, const EstBuffers &B,
                             hipStream_t st);
 hipError_t launch_node_merge(const NodeTask *tasks, int n, int max_L,
@@ -1364,9 +1364,15 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   if (st != COMPASS_OK) return st;
 
   // sort jobs
-  std::vector<int32_t> sort_jobs;
+  std::vector<SortJob> sort_jobs;
   for (int s = 0; s < 2 * g->n_edges; ++s)
-    if (pl.side_used[s]) sort_jobs.push_back(s);
+    if (pl.side_used[s]) {
+      SortJob j;
+      memset(&j, 0, sizeof j);
+      j.counters = g->sketch[s];
+      j.side = s;
+      sort_jobs.push_back(j);
+    }
   // levels
   int max_level = 0;
   for (int lv : pl.task_level) max_level = std::max(max_level, lv);
@@ -1408,7 +1414,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
     return o;
   };
   const size_t o_sides = carve(sizeof(void *) * std::max(1, 2 * g->n_edges));
-  const size_t o_jobs = carve(sizeof(int32_t) * std::max<size_t>(1, sort_jobs.size()));
+  const size_t o_jobs = carve(sizeof(SortJob) * std::max<size_t>(1, sort_jobs.size()));
   const size_t o_tasks = carve(sizeof(NodeTask) * std::max<size_t>(1, flat.size()));
   const size_t o_tris = carve(sizeof(TriTask) * std::max<size_t>(1, pl.tris.size()));
   // two-child sweep groups: triangle tasks of the same apex structure, in
@@ -1433,9 +1439,6 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_tgroups = carve(sizeof(TriGroup) * std::max<size_t>(1, tgroups.size()));
   const size_t o_sps = carve(sizeof(SubplanTask) * pl.sps.size());
   const size_t o_sorted = carve(sizeof(uint64_t) * 2 * g->n_edges * d * (size_t)w);
-  int w2 = 1;
-  while (w2 < w) w2 <<= 1;
-  const size_t o_stmp = carve(sizeof(uint64_t) * 2 * g->n_edges * d * (size_t)w2);
   const size_t o_msg = carve(16ull * pl.n_msg_slots * d * (size_t)w);
   const size_t o_merged = carve(4ull * max_level_tasks * d * (size_t)std::max(1, pl.Lmax));
   const size_t o_nrec = carve(sizeof(NodeRec) * max_level_tasks * d *
@@ -1472,7 +1475,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   std::vector<char> host(o_sorted, 0);
   memcpy(host.data() + o_sides, g->sketch, sizeof(void *) * 2 * g->n_edges);
   if (!sort_jobs.empty())
-    memcpy(host.data() + o_jobs, sort_jobs.data(), 4 * sort_jobs.size());
+    memcpy(host.data() + o_jobs, sort_jobs.data(), sizeof(SortJob) * sort_jobs.size());
   if (!flat.empty())
     memcpy(host.data() + o_tasks, flat.data(), sizeof(NodeTask) * flat.size());
   if (!pl.tris.empty())
@@ -1503,7 +1506,6 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   B.sides = reinterpret_cast<const void *const *>(base + o_sides);
   B.n_sel = g->n_selected;
   B.sorted = reinterpret_cast<const uint64_t *>(base + o_sorted);
-  B.sort_tmp = reinterpret_cast<uint64_t *>(base + o_stmp);
   B.msg = reinterpret_cast<u128 *>(base + o_msg);
   B.merged = reinterpret_cast<uint32_t *>(base + o_merged);
   B.nrec = reinterpret_cast<NodeRec *>(base + o_nrec);
@@ -1534,7 +1536,7 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
     R.n = (int)flat.size();
     R.n_tri = (int)pl.tris.size();
     ProfScope ps("sort_rows", stream);
-    HIP_OK(launch_sort_rows(reinterpret_cast<const int32_t *>(base + o_jobs),
+    HIP_OK(launch_sort_rows(reinterpret_cast<const SortJob *>(base + o_jobs),
                             (int)sort_jobs.size(), R, B, stream));
   }
   const NodeTask *dtasks = reinterpret_cast<const NodeTask *>(base + o_tasks);

@@ -65,7 +65,6 @@ struct EstBuffers {
   const void *const *sides;   // [2 * n_edges] counter arrays (d x w)
   const int64_t *n_sel;       // [n_tables]
   const uint64_t *sorted;     // [side][row][w] keys (|v| << 16 | j)
-  uint64_t *sort_tmp;         // [side][row][w2] chunk-sorted keys
   u128 *msg;                  // [slot][row][w]
   uint32_t *merged;           // [scratch slot][row][Lmax]
   NodeRec *nrec;              // [scratch slot][row][Lmax]

@@ -153,111 +153,183 @@ __device__ __forceinline__ uint64_t abs_u64(int64_t v) {
 
 // ---------------------------------------------------------------------
 // sort of each (sketch side, row) by (|v|, j): grid (n_jobs, d, chunks);
-// job_side[blockIdx.x] = sketch side
+// jobs[blockIdx.x / d] = sketch side, blockIdx.x % d = row
 // ---------------------------------------------------------------------
-// sort_chunk_kernel: every kSortChunk keys (|v| << 16 | j) sorted in LDS
-// (bitonic; w is padded to a power of two with all-ones keys);
-// sort_merge_kernel: the final position of a key is its index in its
-// chunk plus the number of smaller keys in every other chunk (keys are
-// distinct: j differs), found by binary search over the LDS-staged chunks.
+// sort_rows_kernel: one workgroup per (sketch side, row) sorts the row's w
+// keys (|v| << 16 | j) ascending: an LSD radix sort on |v|, four bits a
+// pass, as many passes as the row's largest |v| needs.  The keys start in
+// j order and every pass is stable, so equal |v| stay in j order, which is
+// the order of the full keys.  Thread t holds the consecutive keys
+// [t kpt, (t + 1) kpt) (kpt = ceil(w / kSortThreads)), so thread order is
+// key order.  A pass: each thread counts its keys per digit (4-bit fields
+// of one 64-bit word), the counts are scanned over the workgroup (16-bit
+// fields, two per 32-bit word, wave scans by DPP row shifts and
+// broadcasts, then over the waves), and each key goes to its digit's base
+// plus the count of equal digits before it.
 __device__ void resolve_task(const ResolveArgs &R, int i, const EstBuffers &B);
 
-// The guard resolution (resolve_task) rides along as the last R.blocks
-// workgroups of the chunk sort, which needs none of it: its dependent
-// loads then overlap the sort instead of adding a launch.
-__global__ __launch_bounds__(kSortThreads) void sort_chunk_kernel(
-    const int32_t *job_side, EstBuffers B, int w2, GridMap gm,
-    ResolveArgs R) {
-  const int rb = (int)blockIdx.x - (int)(gridDim.x - R.blocks);
-  if (rb >= 0) {
-    resolve_task(R, rb * kSortThreads + (int)threadIdx.x, B);
-    return;
-  }
-  const GridPos gp = grid_pos(gm);
-  if (!gp.ok) return;
-  __shared__ uint64_t sk[kSortChunk];
-  const int side = job_side[gp.task];
-  const int row = gp.row;
-  const int w = B.w;
-  const int c0 = gp.c * kSortChunk;
-  const int n = min(kSortChunk, w2);  // chunk length (w2 < kSortChunk: one)
-  {
-    // all of a lane's counter loads in flight together (indexes clamped)
-    constexpr int kU = kSortChunk / kSortThreads;
-    int64_t v[kU];
-    const size_t rb = (size_t)row * w;
-    if (B.counter_bits == 32) {
-      const int32_t *src = reinterpret_cast<const int32_t *>(B.sides[side]) + rb;
-#pragma unroll
-      for (int u = 0; u < kU; ++u)
-        v[u] = src[min(c0 + (int)threadIdx.x + u * kSortThreads, w - 1)];
-    } else {
-      const int64_t *src = reinterpret_cast<const int64_t *>(B.sides[side]) + rb;
-#pragma unroll
-      for (int u = 0; u < kU; ++u)
-        v[u] = src[min(c0 + (int)threadIdx.x + u * kSortThreads, w - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int t = (int)threadIdx.x + u * kSortThreads;
-      const int j = c0 + t;
-      // keys beyond the row (and the padding up to kSortPad) are all ones
-      if (t < (n < kSortPad ? kSortPad : n))
-        sk[t] = (t < n && j < w) ? (abs_u64(v[u]) << 16) | (uint64_t)j : ~0ull;
-    }
-  }
-  __syncthreads();
-  bitonic_sort_lds<kSortThreads, kSortChunk / kSortThreads>(
-      reinterpret_cast<unsigned long long *>(sk), n < kSortPad ? kSortPad : n);
-  uint64_t *tmp = B.sort_tmp + ((size_t)side * B.d + row) * (size_t)w2;
-  for (int t = threadIdx.x; t < n; t += kSortThreads) tmp[c0 + t] = sk[t];
+// inclusive scan over the 64 lanes of a wave (32-bit words of two 16-bit
+// fields that never carry into each other)
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr 1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr 2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr 4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr 8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast 15
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast 31
+  return x;
 }
 
-__global__ __launch_bounds__(kSortThreads) void sort_merge_kernel(
-    const int32_t *job_side, EstBuffers B, int w2, GridMap gm) {
-  const GridPos gp = grid_pos(gm);
-  if (!gp.ok) return;
-  extern __shared__ uint64_t ak[];  // all w2 chunk-sorted keys of the row
-  const int side = job_side[gp.task];
-  const int row = gp.row;
-  const int w = B.w;
-  const int n = min(kSortChunk, w2);
-  const int nch = w2 / n;
-  const uint64_t *tmp = B.sort_tmp + ((size_t)side * B.d + row) * (size_t)w2;
-  stage_lds<kSortThreads, 8>(ak, tmp, w2, StageCopy());
-  __syncthreads();
-  uint64_t *out = const_cast<uint64_t *>(sorted_of(B, side, row));
-  const int mine = gp.c;
-  constexpr int U = kSortChunk / kSortThreads;
-  uint64_t key[U];
-  int pos[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int t = threadIdx.x + u * kSortThreads;
-    key[u] = t < n ? ak[mine * n + t] : ~0ull;
-    pos[u] = t;
+// 4-bit digit counts (one nibble per digit) -> word k = count(2k) | count(2k+1) << 16
+__device__ __forceinline__ uint32_t nibbles_to_word(uint64_t c, int k) {
+  const uint32_t b = (uint32_t)(c >> (8 * k)) & 0xFFu;  // digits 2k, 2k + 1
+  return (b & 0xFu) | ((b >> 4) << 16);
+}
+
+// The guard resolution (resolve_task) rides along as the last R.blocks
+// workgroups, which need none of the sort: its dependent loads then
+// overlap the sort instead of adding a launch.
+template <int KPT>  // keys per thread at most (8 or kSortKpt)
+__global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
+    const SortJob *jobs, EstBuffers B, int n_pairs, ResolveArgs R) {
+  if ((int)blockIdx.x >= n_pairs) {
+    resolve_task(R, ((int)blockIdx.x - n_pairs) * kSortThreads + (int)threadIdx.x, B);
+    return;
   }
-  for (int c = 0; c < nch; ++c) {
-    if (c == mine) continue;  // uniform
-    const uint64_t *ck = ak + (size_t)c * n;
-    int base[U];
+  // LDS: the keys by position, one pad entry after every 16 so that the
+  // threads' consecutive runs of keys fall on different banks, then the
+  // digit starts of the pass, [digit][thread] 16-bit (before the first
+  // pass: the wave maxima), then the scan's scratch.  The largest rows
+  // (KPT = 16) fill the LDS with the keys unpadded and the starts; their
+  // scan scratch takes the keys' space before each scatter.
+  extern __shared__ __align__(16) uint64_t sk[];
+  constexpr int kWaves = kSortThreads / 64;
+  const int w = B.w;
+  const int kpt = (w + kSortThreads - 1) / kSortThreads;  // uniform, <= KPT
+  constexpr bool kPad = KPT <= 8;  // also: the scan scratch after the starts
+  const int nsk = kpt * kSortThreads + (kPad ? kpt * kSortThreads / 16 : 0);
+  uint16_t *runtab = reinterpret_cast<uint16_t *>(sk + nsk);
+  auto at = [](int p) { return kPad ? p + (p >> 4) : p; };
+  uint32_t *scr = kPad ? reinterpret_cast<uint32_t *>(runtab + 16 * kSortThreads)
+                       : reinterpret_cast<uint32_t *>(sk);  // [kWaves][8]
+  const SortJob &job = jobs[blockIdx.x / B.d];
+  const int side = job.side;
+  const int row = (int)blockIdx.x % B.d;
+  const int t = (int)threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int p0 = t * kpt;
+  uint64_t key[KPT];
+  uint64_t mx = 0;
+  {
+    // the row's keys, loaded coalesced (all of a lane's loads in flight
+    // together) into LDS, then each thread's consecutive run from there
+    int64_t v[KPT];
+    const size_t rb = (size_t)row * w;
+    if (B.counter_bits == 32) {
+      const int32_t *src = reinterpret_cast<const int32_t *>(job.counters) + rb;
 #pragma unroll
-    for (int u = 0; u < U; ++u) base[u] = 0;
-    int m = n;
-    while (m > 1) {
-      const int half = m >> 1;
+      for (int i = 0; i < KPT; ++i) {
+        const int j = t + i * kSortThreads;
+        v[i] = j < w ? src[j] : 0;
+      }
+    } else {
+      const int64_t *src = reinterpret_cast<const int64_t *>(job.counters) + rb;
 #pragma unroll
-      for (int u = 0; u < U; ++u)
-        base[u] = ck[base[u] + half] < key[u] ? base[u] + half : base[u];
-      m -= half;
+      for (int i = 0; i < KPT; ++i) {
+        const int j = t + i * kSortThreads;
+        v[i] = j < w ? src[j] : 0;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) pos[u] += base[u] + (ck[base[u]] < key[u] ? 1 : 0);
+    for (int i = 0; i < KPT; ++i) {
+      const int j = t + i * kSortThreads;
+      const uint64_t a = abs_u64(v[i]);
+      if (j < w) sk[at(j)] = (a << 16) | (uint64_t)(uint32_t)j;
+      mx = a > mx ? a : mx;
+    }
   }
+  // passes: the bits of the row's largest |v|, four at a time
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int t = threadIdx.x + u * kSortThreads;
-    if (t < n && pos[u] < w) out[pos[u]] = key[u];
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(mx, off);
+    mx = o > mx ? o : mx;
+  }
+  uint64_t *wmax = reinterpret_cast<uint64_t *>(runtab);  // free until a pass
+  if (lane == 0) wmax[wave] = mx;
+  __syncthreads();
+  mx = 0;
+  for (int k = 0; k < kWaves; ++k) mx = wmax[k] > mx ? wmax[k] : mx;
+#pragma unroll
+  for (int i = 0; i < KPT; ++i)
+    if (i < kpt && p0 + i < w) key[i] = sk[at(p0 + i)];
+  const int bits = mx ? 64 - __builtin_clzll(mx) : 0;
+  const int passes = (bits + 3) / 4;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int sh = 16 + 4 * pass;
+    // my keys' digit counts (at most 8 keys a nibble word)
+    uint64_t ca = 0, cb = 0;
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      if (i >= kpt || p0 + i >= w) continue;
+      const uint64_t inc = 1ull << (4 * (int)((key[i] >> sh) & 15));
+      if (i < 8) ca += inc; else cb += inc;
+    }
+    auto count = [&](int k) {  // word k: digits 2k, 2k + 1
+      return nibbles_to_word(ca, k) + (KPT > 8 ? nibbles_to_word(cb, k) : 0u);
+    };
+    // scan of the counts over the workgroup: 8 words of two digits
+    uint32_t incl[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) incl[k] = wave_scan_incl(count(k));
+    if (!kPad) __syncthreads();  // the previous pass's reads of sk are done
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) scr[wave * 8 + k] = incl[k];
+    }
+    __syncthreads();
+    // per word: the earlier waves' counts, the workgroup totals, the digit
+    // bases (exclusive prefix of the totals over the 16 digits), and my
+    // first position per digit
+    // (lane q < kWaves holds wave q's total; one more wave scan)
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t wi = wave_scan_incl(lane < kWaves ? scr[lane * 8 + k] : 0u);
+      const uint32_t a =
+          wave > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)wi, wave - 1) : 0u;
+      const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)wi, kWaves - 1);
+      const uint32_t lo = b & 0xFFFFu, hi = b >> 16;
+      const uint32_t basew = run | ((run + lo) << 16);
+      run += lo + hi;
+      const uint32_t st = basew + a + incl[k] - count(k);
+      runtab[(2 * k) * kSortThreads + t] = (uint16_t)(st & 0xFFFFu);
+      runtab[(2 * k + 1) * kSortThreads + t] = (uint16_t)(st >> 16);
+    }
+    __syncthreads();  // the scan scratch is read; sk takes the scatter
+    // scatter: digit start + equal digits earlier in my keys
+    uint64_t seen = 0;  // running nibble counts (the last increment may carry)
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      if (i >= kpt || p0 + i >= w) continue;
+      const int dg = (int)((key[i] >> sh) & 15);
+      const int pos = (int)runtab[dg * kSortThreads + t] + (int)((seen >> (4 * dg)) & 15);
+      seen += 1ull << (4 * dg);
+      sk[at(pos)] = key[i];
+    }
+    __syncthreads();
+    if (pass + 1 < passes) {
+#pragma unroll
+      for (int i = 0; i < KPT; ++i)
+        if (i < kpt && p0 + i < w) key[i] = sk[at(p0 + i)];
+    }
+  }
+  // the sorted row (in LDS by position: the loads' order when no pass ran),
+  // stored coalesced
+  uint64_t *out = const_cast<uint64_t *>(sorted_of(B, side, row));
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) {
+    const int j = t + i * kSortThreads;
+    if (j < w) out[j] = sk[at(j)];
   }
 }
 
@@ -821,11 +893,6 @@ __device__ void resolve_task(const ResolveArgs &R, int i, const EstBuffers &B) {
   }
 }
 
-// the guard resolution on its own (an estimate with no row sorts)
-__global__ __launch_bounds__(kSortThreads) void resolve_kernel(ResolveArgs R,
-                                                               EstBuffers B) {
-  resolve_task(R, blockIdx.x * kSortThreads + (int)threadIdx.x, B);
-}
 
 // ---------------------------------------------------------------------
 // triangle apex preparation: grid (tasks, d, chunks of kPrepChunk)
@@ -1888,27 +1955,29 @@ static GridMap grid_map(int X, int n, int d, int64_t *blocks) {
   const GridMap gm_ = grid_map((X), (n), B.d, &blocks_);  \
   if (blocks_ == 0) return hipErrorInvalidConfiguration;
 
-hipError_t launch_sort_rows(const int32_t *job_side, int n_jobs,
+hipError_t launch_sort_rows(const SortJob *jobs, int n_jobs,
                             ResolveArgs R, const EstBuffers &B,
                             hipStream_t st) {
   R.blocks = (R.n + R.n_tri + kSortThreads - 1) / kSortThreads;
-  if (n_jobs == 0) {
-    if (R.blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(resolve_kernel, dim3((uint32_t)R.blocks),
-                       dim3(kSortThreads), 0, st, R, B);
-    return hipGetLastError();
-  }
-  int w2 = 1;
-  while (w2 < B.w) w2 <<= 1;
-  const int nch = std::max(1, w2 / kSortChunk);
-  COMPASS_GRID(nch, n_jobs);
-  hipLaunchKernelGGL(sort_chunk_kernel, dim3((uint32_t)(blocks_ + R.blocks)),
-                     dim3(kSortThreads), 0, st, job_side, B, w2, gm_, R);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sort_merge_kernel, dim3((uint32_t)blocks_),
-                     dim3(kSortThreads), (size_t)w2 * sizeof(uint64_t), st,
-                     job_side, B, w2, gm_);
+  const int n_pairs = n_jobs * B.d;
+  if (n_pairs + R.blocks == 0) return hipSuccess;
+  const int kpt = (B.w + kSortThreads - 1) / kSortThreads;
+  // keys (one pad entry per 16), 16 digit starts (16-bit) per thread and
+  // the scan scratch; rows of more than 8 keys a thread: keys unpadded, the
+  // scratch in the keys' space
+  const bool pad = kpt <= 8;
+  const size_t lds =
+      (size_t)(kpt * kSortThreads + (pad ? kpt * kSortThreads / 16 : 0)) *
+          sizeof(uint64_t) +
+      (size_t)kSortThreads * 16 * sizeof(uint16_t) +
+      (pad ? (size_t)(kSortThreads / 64) * 8 * sizeof(uint32_t) : 0);
+  if (kpt <= 8)
+    hipLaunchKernelGGL(sort_rows_kernel<8>, dim3((uint32_t)(n_pairs + R.blocks)),
+                       dim3(kSortThreads), lds, st, jobs, B, n_pairs, R);
+  else
+    hipLaunchKernelGGL(sort_rows_kernel<kSortKpt>,
+                       dim3((uint32_t)(n_pairs + R.blocks)), dim3(kSortThreads),
+                       lds, st, jobs, B, n_pairs, R);
   return hipGetLastError();
 }
 

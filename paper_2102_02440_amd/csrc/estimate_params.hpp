@@ -7,12 +7,10 @@ namespace compass {
 
 constexpr int kMaxChild = 6;
 constexpr int kNodeThreads = 1024;
-constexpr int kSortThreads = 256;
-constexpr int kSortChunk = 1024;  // keys sorted by one workgroup
-constexpr int kSortPad = 64 * (kSortChunk / kSortThreads);  // shortest sort:
-                                  // the keys one wave holds in registers
 constexpr int kLaneThreads = 256;
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
+constexpr int kSortThreads = 1024;    // one workgroup sorts a row's keys
+constexpr int kSortKpt = kMaxEstimateW / kSortThreads;  // keys per thread
 constexpr int kNodeStageBytes = 96 * 1024;  // node merge: staged magnitudes
 constexpr size_t kNodeScratchBytes = (size_t)1 << 30;  // per level launch
 constexpr int kMaxGridZ = 65535;  // tasks per launch (grid z)
@@ -103,6 +101,13 @@ struct TriGroup {
   int32_t n;
   int32_t member[kFastSegs];
   int32_t pad[3];
+};
+
+// One row sort: the sketch side and its counters (the pointer carried
+// here saves the kernel a dependent load of the side table).
+struct SortJob {
+  const void *counters;
+  int32_t side, pad;
 };
 
 // The tasks whose guards resolve_task sets (blocks: workgroups of
