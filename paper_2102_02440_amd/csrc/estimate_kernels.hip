@@ -198,20 +198,22 @@ __global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
   }
   // LDS: the keys by position, one pad entry after every 16 so that the
   // threads' consecutive runs of keys fall on different banks, then the
-  // digit starts of the pass, [digit][thread] 16-bit (before the first
-  // pass: the wave maxima), then the scan's scratch.  The largest rows
-  // (KPT = 16) fill the LDS with the keys unpadded and the starts; their
-  // scan scratch takes the keys' space before each scatter.
+  // digit starts of the pass (16-bit, two digits a word, [word][thread];
+  // before the first pass: the wave maxima), then the scan's scratch and
+  // the waves' digit bases.  The largest rows (KPT = 16) fill the LDS with
+  // the keys unpadded and the starts; their scratch and bases take the
+  // keys' space before each scatter.
   extern __shared__ __align__(16) uint64_t sk[];
   constexpr int kWaves = kSortThreads / 64;
   const int w = B.w;
   const int kpt = (w + kSortThreads - 1) / kSortThreads;  // uniform, <= KPT
   constexpr bool kPad = KPT <= 8;  // also: the scan scratch after the starts
   const int nsk = kpt * kSortThreads + (kPad ? kpt * kSortThreads / 16 : 0);
-  uint16_t *runtab = reinterpret_cast<uint16_t *>(sk + nsk);
+  uint32_t *runtab = reinterpret_cast<uint32_t *>(sk + nsk);  // [8][threads]
   auto at = [](int p) { return kPad ? p + (p >> 4) : p; };
-  uint32_t *scr = kPad ? reinterpret_cast<uint32_t *>(runtab + 16 * kSortThreads)
+  uint32_t *scr = kPad ? runtab + 8 * kSortThreads
                        : reinterpret_cast<uint32_t *>(sk);  // [kWaves][8]
+  uint32_t *wbase = scr + kWaves * 8;                       // [kWaves][8]
   const SortJob &job = jobs[blockIdx.x / B.d];
   const int side = job.side;
   const int row = (int)blockIdx.x % B.d;
@@ -274,45 +276,50 @@ __global__ __launch_bounds__(kSortThreads) void sort_rows_kernel(
       const uint64_t inc = 1ull << (4 * (int)((key[i] >> sh) & 15));
       if (i < 8) ca += inc; else cb += inc;
     }
-    auto count = [&](int k) {  // word k: digits 2k, 2k + 1
-      return nibbles_to_word(ca, k) + (KPT > 8 ? nibbles_to_word(cb, k) : 0u);
-    };
     // scan of the counts over the workgroup: 8 words of two digits
-    uint32_t incl[8];
+    uint32_t cnt[8], incl[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) incl[k] = wave_scan_incl(count(k));
+    for (int k = 0; k < 8; ++k) {
+      cnt[k] = nibbles_to_word(ca, k) + (KPT > 8 ? nibbles_to_word(cb, k) : 0u);
+      incl[k] = wave_scan_incl(cnt[k]);
+    }
     if (!kPad) __syncthreads();  // the previous pass's reads of sk are done
     if (lane == 63) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) scr[wave * 8 + k] = incl[k];
     }
     __syncthreads();
-    // per word: the earlier waves' counts, the workgroup totals, the digit
-    // bases (exclusive prefix of the totals over the 16 digits), and my
-    // first position per digit
-    // (lane q < kWaves holds wave q's total; one more wave scan)
-    uint32_t run = 0;
+    if (wave == 0) {  // uniform
+      // lane q < kWaves: wave q's totals; per word the earlier waves'
+      // counts, the workgroup totals and the digit bases (exclusive prefix
+      // of the totals over the 16 digits), summed into each wave's base
+      uint32_t run = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const uint32_t wi = wave_scan_incl(lane < kWaves ? scr[lane * 8 + k] : 0u);
-      const uint32_t a =
-          wave > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)wi, wave - 1) : 0u;
-      const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)wi, kWaves - 1);
-      const uint32_t lo = b & 0xFFFFu, hi = b >> 16;
-      const uint32_t basew = run | ((run + lo) << 16);
-      run += lo + hi;
-      const uint32_t st = basew + a + incl[k] - count(k);
-      runtab[(2 * k) * kSortThreads + t] = (uint16_t)(st & 0xFFFFu);
-      runtab[(2 * k + 1) * kSortThreads + t] = (uint16_t)(st >> 16);
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t x = lane < kWaves ? scr[lane * 8 + k] : 0u;
+        const uint32_t wi = wave_scan_incl(x);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)wi, kWaves - 1);
+        const uint32_t lo = b & 0xFFFFu, hi = b >> 16;
+        const uint32_t basew = run | ((run + lo) << 16);
+        run += lo + hi;
+        if (lane < kWaves) wbase[lane * 8 + k] = basew + wi - x;
+      }
     }
-    __syncthreads();  // the scan scratch is read; sk takes the scatter
+    __syncthreads();
+    // my first position per digit
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      runtab[k * kSortThreads + t] = wbase[wave * 8 + k] + incl[k] - cnt[k];
+    if (!kPad) __syncthreads();  // the bases (in the keys' space) are read
     // scatter: digit start + equal digits earlier in my keys
+    const uint16_t *start16 = reinterpret_cast<const uint16_t *>(runtab);
     uint64_t seen = 0;  // running nibble counts (the last increment may carry)
 #pragma unroll
     for (int i = 0; i < KPT; ++i) {
       if (i >= kpt || p0 + i >= w) continue;
       const int dg = (int)((key[i] >> sh) & 15);
-      const int pos = (int)runtab[dg * kSortThreads + t] + (int)((seen >> (4 * dg)) & 15);
+      const int pos = (int)start16[((dg >> 1) * kSortThreads + t) * 2 + (dg & 1)] +
+                      (int)((seen >> (4 * dg)) & 15);
       seen += 1ull << (4 * dg);
       sk[at(pos)] = key[i];
     }
@@ -1962,15 +1969,15 @@ hipError_t launch_sort_rows(const SortJob *jobs, int n_jobs,
   const int n_pairs = n_jobs * B.d;
   if (n_pairs + R.blocks == 0) return hipSuccess;
   const int kpt = (B.w + kSortThreads - 1) / kSortThreads;
-  // keys (one pad entry per 16), 16 digit starts (16-bit) per thread and
-  // the scan scratch; rows of more than 8 keys a thread: keys unpadded, the
-  // scratch in the keys' space
+  // keys (one pad entry per 16), 16 digit starts (16-bit) per thread, the
+  // scan scratch and the waves' bases; rows of more than 8 keys a thread:
+  // keys unpadded, the scratch and bases in the keys' space
   const bool pad = kpt <= 8;
   const size_t lds =
       (size_t)(kpt * kSortThreads + (pad ? kpt * kSortThreads / 16 : 0)) *
           sizeof(uint64_t) +
       (size_t)kSortThreads * 16 * sizeof(uint16_t) +
-      (pad ? (size_t)(kSortThreads / 64) * 8 * sizeof(uint32_t) : 0);
+      (pad ? (size_t)2 * (kSortThreads / 64) * 8 * sizeof(uint32_t) : 0);
   if (kpt <= 8)
     hipLaunchKernelGGL(sort_rows_kernel<8>, dim3((uint32_t)(n_pairs + R.blocks)),
                        dim3(kSortThreads), lds, st, jobs, B, n_pairs, R);
