@@ -912,12 +912,49 @@ __device__ __forceinline__ int rec_child(const uint32_t *merged, int p) {
   return (int)(merged[p] >> 16);
 }
 
+// block-wide inclusive max-scan (forward) and min-scan (from the end) of
+// one int per thread, kPrepThreads lanes: shuffles within the waves, then
+// the earlier (later) waves' totals from LDS
+__device__ __forceinline__ void prep_scans(int &mx, int &mn, int *wtot) {
+  constexpr int kW = kPrepThreads / 64;
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int a = __shfl_up(mx, off);
+    const int b = __shfl_down(mn, off);
+    if (lane >= off) mx = max(mx, a);
+    if (lane + off < 64) mn = min(mn, b);
+  }
+  if (lane == 63) wtot[wave] = mx;
+  if (lane == 0) wtot[kW + wave] = mn;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kW; ++k) {
+    if (k < wave) mx = max(mx, wtot[k]);
+    if (k > wave) mn = min(mn, wtot[kW + k]);
+  }
+}
+
+// block max / min of one int per thread (all threads get it); red holds
+// 2 * waves ints and must not be in use by a previous call still read
+__device__ __forceinline__ int block_max(int v, int *red) {
+  constexpr int kW = kPrepThreads / 64;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  if (((int)threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = red[0];
+#pragma unroll
+  for (int k = 1; k < kW; ++k) v = max(v, red[k]);
+  return v;
+}
+
 __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
     const NodeTask *tasks, EstBuffers B, GridMap gm) {
   const GridPos gp = grid_pos(gm);
   if (!gp.ok) return;
-  __shared__ int s_lo[kPrepThreads], s_hi[kPrepThreads];
-  __shared__ int s_prev, s_next;
+  constexpr int kW = kPrepThreads / 64;
+  __shared__ int s_tot[2 * kW], s_red[4][kW];
   const NodeTask &T = tasks[gp.task];
   if (T.mode != kModeTriRootPrep || !T.guard.on) return;
   const int row = gp.row;
@@ -937,106 +974,128 @@ __global__ __launch_bounds__(kPrepThreads) void apex_prep_kernel(
   // the full elements only
   const bool fast = (T.guard.on & 2) != 0;
   const int q0 = p0 + threadIdx.x * kPrepPer;  // my positions [q0, q0 + kPrepPer)
+  // my records, the children around them, then the own-bucket counters
+  NodeRec nr[kPrepPer];
+  int ch[kPrepPer + 2];  // children of q0 - 1 .. q0 + kPrepPer (-1: none)
+#pragma unroll
+  for (int u = 0; u < kPrepPer; ++u) nr[u] = rec[min(q0 + u, p1 - 1)];
+#pragma unroll
+  for (int u = 0; u < kPrepPer + 2; ++u) {
+    const int q = q0 - 1 + u;
+    ch[u] = (q >= 0 && q < L) ? rec_child(mg, q) : -1;
+  }
+  const int64_t vprev = q0 > 0 && q0 - 1 < L ? rec[q0 - 1].v : 0;
+  uint64_t own[kPrepPer];
+#pragma unroll
+  for (int u = 0; u < kPrepPer; ++u) {
+    const int a = (int)(nr[u].aj >> 16);
+    const int j = (int)(nr[u].aj & 0xFFFF);
+    own[u] = 0;
+    // kappa of the child's own bucket on the edge to the apex
+    if (q0 + u < p1 && T.child_cut[a] >= 0)
+      own[u] = abs_u64(counter_at(B, T.child_side[a] ^ 1, row, j));
+  }
   int last_start = -1, first_end = L;
 #pragma unroll
   for (int u = 0; u < kPrepPer; ++u) {
     const int pos = q0 + u;
     if (pos >= p1) break;
-    const NodeRec nr = rec[pos];
-    const int a = (int)(nr.aj >> 16);
-    const int j = (int)(nr.aj & 0xFFFF);
-    TriElem e;
-    e.v = nr.v;
-    e.mu = nr.mu;
-    e.key = 0;
-    uint64_t own = 0;
-    if (T.child_cut[a] >= 0) {
-      // kappa of the child's own bucket on the edge to the apex
-      own = abs_u64(counter_at(B, T.child_side[a] ^ 1, row, j));
-      e.key = (own << 7) | (uint64_t)T.child_eid[a];
-    }
-    e.child = (uint32_t)a;
-    e.pad[0] = e.pad[1] = e.pad[2] = 0;
-    if (!fast) out[pos] = e;
-    if (fast) {
-      // truncating copy; the sweep reads it only when the bounds hold
-      TriElemN n;
-      n.v = (int32_t)e.v;
-      n.kc = ((uint32_t)a << 31) | (uint32_t)(own & 0x7FFFFFFFull);
-      n.mu = (int64_t)(uint64_t)e.mu;
-      n.vm = (int64_t)((uint64_t)e.v * (uint64_t)e.mu);
-      n.run_lo = 0;  // set below
-      n.run_hi = 0;
-      outn[pos] = n;
-      if (pos == 0 || rec_child(mg, pos - 1) != a) last_start = pos;
-      if (first_end == L && (pos == L - 1 || rec_child(mg, pos + 1) != a))
-        first_end = pos;
-    }
+    const int a = (int)(nr[u].aj >> 16);
     // the list is ascending in |v|: its zero counters form a prefix, and
     // they add nothing to the sweep (it ends there)
-    if (e.v != 0) {
-      if (pos == 0 || rec[pos - 1].v == 0) B.prep_z[slot_row] = pos;
+    const int64_t vp = u == 0 ? vprev : nr[u - 1].v;
+    if (nr[u].v != 0) {
+      if (pos == 0 || vp == 0) B.prep_z[slot_row] = pos;
     } else if (pos == L - 1) {
       B.prep_z[slot_row] = L;
     }
+    if (!fast) {
+      TriElem e;
+      e.v = nr[u].v;
+      e.mu = nr[u].mu;
+      e.key = T.child_cut[a] >= 0 ? (own[u] << 7) | (uint64_t)T.child_eid[a] : 0;
+      e.child = (uint32_t)a;
+      e.pad[0] = e.pad[1] = e.pad[2] = 0;
+      out[pos] = e;
+    }
+    if (ch[u] != a) last_start = pos;
+    if (first_end == L && ch[u + 2] != a) first_end = pos;
   }
   if (!fast) return;  // uniform
-  // run starts: inclusive max-scan over my thread's positions; the run
-  // holding the chunk's first position may start in an earlier chunk
-  s_lo[threadIdx.x] = last_start;
-  s_hi[threadIdx.x] = first_end;
-  if (threadIdx.x == 0) {
-    s_prev = -1;
-    s_next = L;
+  // run starts and ends: the latest start at or before each of my
+  // positions, the earliest end at or after; the run holding the chunk's
+  // first (last) position may start (end) in an earlier (later) chunk:
+  // searched kPrepThreads * kPrepPer positions at a time (uniform loops)
+  int cur = last_start, nxt = first_end;
+  prep_scans(cur, nxt, s_tot);
+  int prev = -1, next = L;
+  int it = 0;
+  for (int base = p0 - 1; base >= 0; base -= kPrepThreads * kPrepPer, ++it) {
+    int f = -1;
+#pragma unroll
+    for (int u = 0; u < kPrepPer; ++u) {
+      const int q = base - ((int)threadIdx.x * kPrepPer + u);
+      if (q >= 0 && (q == 0 || rec_child(mg, q - 1) != rec_child(mg, q))) f = max(f, q);
+    }
+    prev = block_max(f, s_red[it & 3]);
+    if (prev >= 0) break;
   }
-  __syncthreads();
-  for (int off = 1; off < kPrepThreads; off <<= 1) {
-    const int a = (int)threadIdx.x >= off ? s_lo[threadIdx.x - off] : -1;
-    const int b = (int)threadIdx.x + off < kPrepThreads ? s_hi[threadIdx.x + off] : L;
-    __syncthreads();
-    s_lo[threadIdx.x] = max(s_lo[threadIdx.x], a);
-    s_hi[threadIdx.x] = min(s_hi[threadIdx.x], b);
-    __syncthreads();
+  for (int base = p1; base < L; base += kPrepThreads * kPrepPer, ++it) {
+    int f = -L;
+#pragma unroll
+    for (int u = 0; u < kPrepPer; ++u) {
+      const int q = base + (int)threadIdx.x * kPrepPer + u;
+      if (q < L && (q == L - 1 || rec_child(mg, q + 1) != rec_child(mg, q))) f = max(f, -q);
+    }
+    next = -block_max(f, s_red[it & 3]);
+    if (next < L) break;
   }
-  // the last run start before p0 and the first run end at or after p1
-  // (searched kPrepThreads positions at a time; both loops are uniform)
-  for (int base = p0 - 1; base >= 0; base -= kPrepThreads) {
-    const int q = base - (int)threadIdx.x;
-    if (q >= 0 && (q == 0 || rec_child(mg, q - 1) != rec_child(mg, q)))
-      atomicMax(&s_prev, q);
-    __syncthreads();
-    const bool found = s_prev >= 0;
-    __syncthreads();
-    if (found) break;
+  // my positions' run bounds (exclusive of my own starts / ends first)
+  int lo = __shfl_up(cur, 1);
+  int hi = __shfl_down(nxt, 1);
+  {
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    if (lane == 0) {
+      lo = -1;
+      for (int k = 0; k < wave; ++k) lo = max(lo, s_tot[k]);
+    }
+    if (lane == 63) {
+      hi = L;
+      for (int k = wave + 1; k < kW; ++k) hi = min(hi, s_tot[kW + k]);
+    }
   }
-  for (int base = p1; base < L; base += kPrepThreads) {
-    const int q = base + (int)threadIdx.x;
-    if (q < L && (q == L - 1 || rec_child(mg, q + 1) != rec_child(mg, q)))
-      atomicMin(&s_next, q);
-    __syncthreads();
-    const bool found = s_next < L;
-    __syncthreads();
-    if (found) break;
-  }
-  int cur = threadIdx.x > 0 ? s_lo[threadIdx.x - 1] : -1;
-  if (cur < 0) cur = s_prev;
-  int nxt = threadIdx.x + 1 < kPrepThreads ? s_hi[threadIdx.x + 1] : L;
-  if (nxt == L) nxt = s_next;
+  if (lo < 0) lo = prev;
+  if (hi >= L) hi = next;
   int lo_of[kPrepPer];
 #pragma unroll
   for (int u = 0; u < kPrepPer; ++u) {
     const int pos = q0 + u;
-    if (pos < p1 && (pos == 0 || rec_child(mg, pos - 1) != rec_child(mg, pos)))
-      cur = pos;
-    lo_of[u] = cur;
+    const int a = (int)(nr[u].aj >> 16);
+    if (pos < p1 && ch[u] != a) lo = pos;
+    lo_of[u] = lo;
   }
+  int hi_of[kPrepPer];
 #pragma unroll
   for (int u = kPrepPer - 1; u >= 0; --u) {
     const int pos = q0 + u;
-    if (pos >= p1) continue;
-    if (pos == L - 1 || rec_child(mg, pos + 1) != rec_child(mg, pos)) nxt = pos;
-    outn[pos].run_lo = lo_of[u];
-    outn[pos].run_hi = nxt;
+    const int a = (int)(nr[u].aj >> 16);
+    if (pos < p1 && ch[u + 2] != a) hi = pos;
+    hi_of[u] = hi;
+  }
+#pragma unroll
+  for (int u = 0; u < kPrepPer; ++u) {
+    const int pos = q0 + u;
+    if (pos >= p1) break;
+    const int a = (int)(nr[u].aj >> 16);
+    // truncating copy; the sweep reads it only when the bounds hold
+    TriElemN n;
+    n.v = (int32_t)nr[u].v;
+    n.kc = ((uint32_t)a << 31) | (uint32_t)(own[u] & 0x7FFFFFFFull);
+    n.mu = (int64_t)(uint64_t)nr[u].mu;
+    n.vm = (int64_t)((uint64_t)nr[u].v * (uint64_t)nr[u].mu);
+    n.run_lo = lo_of[u];
+    n.run_hi = hi_of[u];
+    outn[pos] = n;
   }
 }
 
