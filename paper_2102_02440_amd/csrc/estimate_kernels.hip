@@ -675,11 +675,21 @@ __device__ __forceinline__ u128 *n1_total(const EstBuffers &B, int slot,
   return B.n1tot + ((size_t)slot * B.d + row) * (2 * kN1MaxChunks);
 }
 
+// 128-bit value of lane (lane - off), or 0 below lane off
+__device__ __forceinline__ u128 shfl_up_u128(u128 v, int off) {
+  const int lane = (int)threadIdx.x & 63;
+  u128 r = 0;
+#pragma unroll
+  for (int k = 3; k >= 0; --k)
+    r = (r << 32) | (uint32_t)__shfl_up((int)(uint32_t)(v >> (32 * k)), off);
+  return lane >= off ? r : (u128)0;
+}
+
 __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
     const NodeTask *tasks, EstBuffers B, GridMap gm) {
   const GridPos gp = grid_pos(gm);
   if (!gp.ok) return;
-  __shared__ u128 sh_m[kN1Threads], sh_x[kN1Threads];
+  __shared__ u128 sh_m[kN1Threads / 64], sh_x[kN1Threads / 64];
   const NodeTask &T = tasks[gp.task];
   if (T.m != 1 || !T.guard.on) return;
   const int row = gp.row;
@@ -708,22 +718,29 @@ __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
     tm += pm[u];
     tx += px[u];
   }
-  // inclusive block scans of the thread sums
-  sh_m[threadIdx.x] = tm;
-  sh_x[threadIdx.x] = tx;
-  __syncthreads();
-  for (int off = 1; off < kN1Threads; off <<= 1) {
-    u128 am = 0, ax = 0;
-    if ((int)threadIdx.x >= off) {
-      am = sh_m[threadIdx.x - off];
-      ax = sh_x[threadIdx.x - off];
-    }
-    __syncthreads();
-    sh_m[threadIdx.x] += am;
-    sh_x[threadIdx.x] += ax;
-    __syncthreads();
+  // inclusive block scans of the thread sums: within the waves by
+  // shuffles, then the earlier waves' totals
+  u128 im = tm, ix = tx;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    im += shfl_up_u128(im, off);
+    ix += shfl_up_u128(ix, off);
   }
-  u128 em = sh_m[threadIdx.x] - tm, ex = sh_x[threadIdx.x] - tx;
+  const int wave = (int)threadIdx.x >> 6;
+  if (((int)threadIdx.x & 63) == 63) {
+    sh_m[wave] = im;
+    sh_x[wave] = ix;
+  }
+  __syncthreads();
+  u128 bm = 0, bx = 0;  // the earlier waves' totals, and the block's
+#pragma unroll
+  for (int k = 0; k < kN1Threads / 64; ++k) {
+    if (k < wave) {
+      bm += sh_m[k];
+      bx += sh_x[k];
+    }
+  }
+  u128 em = bm + im - tm, ex = bx + ix - tx;
   u128 *P = n1_prefix(B, T.scratch_slot, row);
   // a tree root (no parent or cut list) needs the chunk totals only
   const bool queries = T.parent_side >= 0 || T.cut_side >= 0;
@@ -739,8 +756,8 @@ __global__ __launch_bounds__(kN1Threads) void node1_prefix_kernel(
   }
   if (threadIdx.x == kN1Threads - 1) {
     u128 *tot = n1_total(B, T.scratch_slot, row);
-    tot[2 * gp.c] = sh_m[threadIdx.x];
-    tot[2 * gp.c + 1] = sh_x[threadIdx.x];
+    tot[2 * gp.c] = bm + im;
+    tot[2 * gp.c + 1] = bx + ix;
   }
 }
 
