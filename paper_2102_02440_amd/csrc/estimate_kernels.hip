@@ -1325,7 +1325,7 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
 __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
     const TriTask *tasks, EstBuffers B) {
   extern __shared__ int32_t s_ps[];  // piece starts (kOrderCap + 1)
-  __shared__ int s_rc[kSegThreads], s_pc[kSegThreads];
+  __shared__ uint32_t s_wt[kSegThreads / 64];
   const TriTask &T = tasks[blockIdx.x];
   if (T.guard.on != 1 + kTriFast) return;  // another rooting, or path
   const int row = blockIdx.y;
@@ -1360,21 +1360,23 @@ __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
     }
   }
   const int rc = __popc(rs), pc = __popc(ps);
-  s_rc[threadIdx.x] = rc;
-  s_pc[threadIdx.x] = pc;
+  // inclusive scans of both counts at once (16-bit fields: at most
+  // kOrderCap each), within the waves, then over the waves' totals
+  const uint32_t mine = (uint32_t)rc | ((uint32_t)pc << 16);
+  const uint32_t incl = wave_scan_incl(mine);
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+  if (lane == 63) s_wt[wave] = incl;
   __syncthreads();
-  for (int off = 1; off < kSegThreads; off <<= 1) {
-    const int a = (int)threadIdx.x >= off ? s_rc[threadIdx.x - off] : 0;
-    const int b = (int)threadIdx.x >= off ? s_pc[threadIdx.x - off] : 0;
-    __syncthreads();
-    s_rc[threadIdx.x] += a;
-    s_pc[threadIdx.x] += b;
-    __syncthreads();
-  }
-  const int R = s_rc[kSegThreads - 1];
-  const int P = s_pc[kSegThreads - 1];
-  int g = s_rc[threadIdx.x] - rc;  // index of my first run start
-  int h = s_pc[threadIdx.x] - pc;  // index of my first piece start
+  const uint32_t wsc = wave_scan_incl(lane < kSegThreads / 64 ? s_wt[lane] : 0u);
+  const uint32_t before =
+      wave > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)wsc, wave - 1) : 0u;
+  const uint32_t all =
+      (uint32_t)__builtin_amdgcn_readlane((int)wsc, kSegThreads / 64 - 1);
+  const uint32_t mine_incl = before + incl;
+  const int R = (int)(all & 0xFFFFu);
+  const int P = (int)(all >> 16);
+  int g = (int)(mine_incl & 0xFFFFu) - rc;  // index of my first run start
+  int h = (int)(mine_incl >> 16) - pc;      // index of my first piece start
   if (threadIdx.x == 0) {
     bounds[0] = z;
     bounds[kFastSegs] = L;
