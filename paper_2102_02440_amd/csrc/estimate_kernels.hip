@@ -426,10 +426,13 @@ __global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
   __syncthreads();
   const bool staged = B.counter_bits == 32 &&
                       (size_t)nl * w * 4 <= (size_t)stage_bytes;
+  // a chunk inside one list needs no rank in that list (its own index)
+  const int own = e_lo / w == (e_hi - 1) / w ? e_lo / w : -1;
   if (staged) {
     for (int a = 0; a < nl; ++a)
-      stage_lds<kMergeThreads, 8>(mags + (size_t)a * w,
-                                  sorted_of(B, s_side[a], row), w, StageMag());
+      if (a != own)
+        stage_lds<kMergeThreads, 8>(mags + (size_t)a * w,
+                                    sorted_of(B, s_side[a], row), w, StageMag());
     __syncthreads();
     // kMergeU elements per lane at a time: their rank searches run in
     // lockstep (uniform trip count), so the LDS probes overlap
@@ -453,6 +456,7 @@ __global__ __launch_bounds__(kMergeThreads) void node_merge_kernel(
         pos[u] = k;
       }
       for (int b = 0; b < nl; ++b) {
+        if (b == own) continue;  // uniform
         const uint32_t *mb = mags + (size_t)b * w;
         const int eb = s_eid[b];
         uint64_t t[kMergeU];
