@@ -793,16 +793,26 @@ __global__ __launch_bounds__(kN1Threads) void node1_emit_kernel(
   const uint64_t *srt = sorted_of(B, cside, row);
   const bool staged = B.counter_bits == 32;
   if (staged) stage_lds<kN1Threads, 8>(smag, srt, w, StageMag());
-  if (threadIdx.x == 0) {
-    u128 am = 0, ax = 0;
-    for (int c = 0; c < nch; ++c) {
-      soff[2 * c] = am;
-      soff[2 * c + 1] = ax;
-      am += tot[2 * c];
-      ax += tot[2 * c + 1];
+  if (threadIdx.x < 64) {
+    // chunk offsets: lane c loads chunk c's totals, an exclusive scan over
+    // the lanes (nch <= kN1MaxChunks <= 64)
+    const int c = (int)threadIdx.x;
+    const u128 tm = c < nch ? tot[2 * c] : (u128)0;
+    const u128 tx = c < nch ? tot[2 * c + 1] : (u128)0;
+    u128 im = tm, ix = tx;
+#pragma unroll
+    for (int off = 1; off < kN1MaxChunks; off <<= 1) {
+      im += shfl_up_u128(im, off);
+      ix += shfl_up_u128(ix, off);
     }
-    soff[2 * nch] = am;  // totals: the prefix at r = w
-    soff[2 * nch + 1] = ax;
+    if (c < nch) {
+      soff[2 * c] = im - tm;
+      soff[2 * c + 1] = ix - tx;
+    }
+    if (c == nch - 1) {
+      soff[2 * nch] = im;  // totals: the prefix at r = w
+      soff[2 * nch + 1] = ix;
+    }
   }
   __syncthreads();
   const u128 *P = n1_prefix(B, T.scratch_slot, row);

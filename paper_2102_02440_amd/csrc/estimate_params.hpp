@@ -20,6 +20,7 @@ constexpr int kN1Threads = 256;   // one-child nodes
 constexpr int kN1Per = 4;
 constexpr int kN1Chunk = kN1Threads * kN1Per;
 constexpr int kN1MaxChunks = (kMaxEstimateW + kN1Chunk - 1) / kN1Chunk;
+static_assert(kN1MaxChunks <= 64, "chunk offsets are scanned by one wave");
 constexpr int kPrepThreads = 256;  // apex preparation
 constexpr int kPrepPer = 4;
 constexpr int kPrepChunk = kPrepThreads * kPrepPer;
