@@ -1418,14 +1418,14 @@ extern "C" compass_status compass_estimate(const compass_join_graph *g,
   const size_t o_tasks = carve(sizeof(NodeTask) * std::max<size_t>(1, flat.size()));
   const size_t o_tris = carve(sizeof(TriTask) * std::max<size_t>(1, pl.tris.size()));
   // two-child sweep groups: triangle tasks of the same apex structure, in
-  // order of first appearance, kFastSegs at most per group
+  // order of first appearance, kTriGroupMax at most per group
   std::vector<TriGroup> tgroups;
   {
     std::map<std::array<int32_t, 9>, int> open;  // key -> group being filled
     for (size_t t = 0; t < pl.tris.size(); ++t) {
       if (pl.tris[t].m != 2) continue;
       auto it = open.find(pl.tri_key[t]);
-      if (it == open.end() || tgroups[it->second].n == kFastSegs) {
+      if (it == open.end() || tgroups[it->second].n == kTriGroupMax) {
         TriGroup gr;
         memset(&gr, 0, sizeof gr);
         tgroups.push_back(gr);

@@ -1454,10 +1454,13 @@ __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
 // threshold) is therefore the same for every member: it is done once, by
 // one slot, and handed to the others through LDS.
 //
-// With nm members running, slot s works for member s % nm on segment
-// s / nm of S = kFastSegs / nm (rounded down to 1, 2 or 4) segments of the
-// sweep; segment g covers tri_seg_kernel's run groups
-// [4 - (g + 1) 4 / S, 4 - g 4 / S).  Cutting the descending sweep into
+// With nm members running (at most kTriGroupMax), slot s works for member
+// s % nm on segment s / nm of S = kFastSegs / nm segments of the sweep (nm
+// = 3 counts as 4: two slots only search); with K = kFastSegs run groups
+// from tri_seg_kernel, segment g covers the groups [K - (g + 1) K / S,
+// K - g K / S).  Many workgroups of few lanes (128 buckets J each) and
+// more segments keep two workgroups on most CUs and shorten each slot's
+// chain of rounds.  Cutting the descending sweep into
 // segments is exact: a segment's runs see the other child's running sum
 // of the earlier segments plus their own, so
 //   G = sum_g [ G_g + A0(before g) * X1_g + A1(before g) * X0_g ]
@@ -1508,10 +1511,10 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   // the members that run (compacted with static indices, so that they stay
   // in scalar registers); slots past nm repeat the first
   const TriGroup &Gr = groups[gp.task];
-  int mem[kFastSegs];
+  int mem[kTriGroupMax];
   int nm = 0;
 #pragma unroll
-  for (int q = 0; q < kFastSegs; ++q) {
+  for (int q = 0; q < kTriGroupMax; ++q) {
     mem[q] = 0;
     if (q >= Gr.n) continue;
     const int t = Gr.member[q];
@@ -1522,7 +1525,7 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     ++nm;
   }
   if (nm == 0) return;  // uniform
-  const int S = nm == 1 ? 4 : (nm == 2 ? 2 : 1);  // segments
+  const int S = kFastSegs / (nm == 3 ? 4 : nm);   // segments
   const int gs = kFastSegs / S;                    // run groups per segment
   const int row = gp.row;
   const int lane = threadIdx.x % kLaneThreads;
@@ -1534,7 +1537,7 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
   const int seg = slot / nm;           // my segment
   int my = mem[0];
 #pragma unroll
-  for (int g = 1; g < kFastSegs; ++g)
+  for (int g = 1; g < kTriGroupMax; ++g)
     if (g == mi) my = mem[g];
   ConstTask &T = *((ConstTask *)tasks + mem[0]);  // the shared structure
   ConstTask &M = *((ConstTask *)tasks + my);      // my member
@@ -1693,7 +1696,7 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
       gather(0, ep);
       if (r + 1 < rounds) search(r + 1);
 #pragma unroll
-      for (int q = 0; q < kFastSegs; ++q) {
+      for (int q = 0; q < kTriGroupMax; ++q) {
         if (q >= nq) break;
         const int i = i0 - q;
         const int info = pcs[i].info;
@@ -1712,7 +1715,7 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
         } else {
           elements(lo, hi, c, rr);
         }
-        if (q + 1 < kFastSegs) gather(q + 1, ep);
+        if (q + 1 < kTriGroupMax) gather(q + 1, ep);
         add_piece(c, rr);
       }
     }
@@ -1759,9 +1762,10 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     }
     if (!active) tot = 0;
   }
-  // lanes: within each wave by shuffles, then the slot's four waves
+  // lanes: within each wave by shuffles, then the slot's waves
   __syncthreads();  // the segment results are read
-  u128 *red = reinterpret_cast<u128 *>(skey);  // [kFastSegs][4]
+  constexpr int kWps = kLaneThreads / 64;        // waves per slot
+  u128 *red = reinterpret_cast<u128 *>(skey);  // [kFastSegs][kWps]
   {
     uint32_t w4[4] = {(uint32_t)tot, (uint32_t)(tot >> 32),
                       (uint32_t)(tot >> 64), (uint32_t)(tot >> 96)};
@@ -1778,12 +1782,13 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
       w4[2] = (uint32_t)(tot >> 64);
       w4[3] = (uint32_t)(tot >> 96);
     }
-    if ((threadIdx.x & 63) == 0) red[slot * 4 + lane / 64] = tot;
+    if ((threadIdx.x & 63) == 0) red[slot * kWps + lane / 64] = tot;
   }
   __syncthreads();
   if (working && seg == 0 && lane == 0) {
-    const u128 sum = red[slot * 4] + red[slot * 4 + 1] + red[slot * 4 + 2] +
-                     red[slot * 4 + 3];
+    u128 sum = 0;
+#pragma unroll
+    for (int k = 0; k < kWps; ++k) sum += red[slot * kWps + k];
     B.partial[((size_t)M.partial_slot + gp.c) * B.d + row] = sum;
   }
 }
@@ -1941,11 +1946,33 @@ __global__ __launch_bounds__(kLaneThreads) void tri_lane_kernel(
 __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
                               const double *approx, uint64_t *row_est,
                               double *est, int32_t *flags, int32_t n_tables) {
-  __shared__ u128 xs[64];
+  __shared__ u128 xs[64], ps[64];
   __shared__ double xd[64];
   const SubplanTask S = sps[blockIdx.x];
   const int d = B.d;
   const int i = threadIdx.x;
+  // partial sums of the sweeps (one per block of cut buckets): every lane
+  // takes one row and every per-th slot, its loads in flight together
+  const bool parts = S.type == kSpTriangle || S.type == kSpGeneric;
+  const int per = (int)blockDim.x / d;  // lanes per row (d <= 32: >= 2)
+  if (parts) {
+    u128 acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < per * d) {
+      const int r = i % d, k = i / d;
+      for (int z0 = k; z0 < S.n_partials; z0 += 8 * per) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int z = z0 + u * per;
+          if (z < S.n_partials) acc[u] += B.partial[((size_t)S.x_slot + z) * d + r];
+        }
+      }
+    }
+    u128 a = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a += acc[u];
+    ps[i] = a;
+    __syncthreads();
+  }
   // the fp64 rows are read only when the 128-bit ones are not certified
   const bool cert = S.type == kSpSingle ||
                     (S.type != kSpUnsupported &&
@@ -1957,19 +1984,8 @@ __global__ void finish_kernel(const SubplanTask *sps, EstBuffers B,
       x = s64_to_u128(B.n_sel[S.single_table]);
     } else if (S.type == kSpTree) {
       x = B.xout[(size_t)S.x_slot * d + i];
-    } else if (S.type == kSpTriangle || S.type == kSpGeneric) {
-      // eight loads in flight (the partials sit in different lines)
-      u128 acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      int z = 0;
-      for (; z + 8 <= S.n_partials; z += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          acc[u] += B.partial[((size_t)S.x_slot + z + u) * d + i];
-      }
-      for (; z < S.n_partials; ++z)
-        acc[0] += B.partial[((size_t)S.x_slot + z) * d + i];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) x += acc[u];
+    } else if (parts) {
+      for (int k = 0; k < per; ++k) x += ps[k * d + i];
     }
     xs[i] = x;
     if (use_approx) {

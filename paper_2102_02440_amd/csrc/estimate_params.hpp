@@ -7,7 +7,7 @@ namespace compass {
 
 constexpr int kMaxChild = 6;
 constexpr int kNodeThreads = 1024;
-constexpr int kLaneThreads = 256;
+constexpr int kLaneThreads = 128;  // cut buckets J per triangle workgroup
 constexpr int kMaxEstimateW = 16384;  // per-(sketch,row) sort held in LDS
 constexpr int kSortThreads = 1024;    // one workgroup sorts a row's keys
 constexpr int kSortKpt = kMaxEstimateW / kSortThreads;  // keys per thread
@@ -27,7 +27,8 @@ constexpr int kPrepChunk = kPrepThreads * kPrepPer;
 constexpr int kOrderThreads = 1024;
 constexpr int kSegThreads = 1024;
 constexpr int kSegPer = 16;
-constexpr int kFastSegs = 4;  // sweep segments per cut bucket
+constexpr int kFastSegs = 8;  // slots of a sweep workgroup (and run groups)
+constexpr int kTriGroupMax = 4;  // triangle tasks swept together
 constexpr int kSearchMin = 8;  // shortest run the sweep sums by search
 constexpr int kOrderTile = 2048;  // positions ordered by one workgroup
 constexpr int kOrderCap = 16384;  // longest two-child apex list run-ordered
@@ -100,7 +101,7 @@ struct TriTask {
 // subtrees below): the two-child sweep searches once for all of them.
 struct TriGroup {
   int32_t n;
-  int32_t member[kFastSegs];
+  int32_t member[kTriGroupMax];
   int32_t pad[3];
 };
 
