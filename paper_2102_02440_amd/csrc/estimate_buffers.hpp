@@ -42,13 +42,10 @@ struct TriPre {
 };
 
 // One piece of the two-child sweep: a maximal same-child run of [z, L)
-// cut at the ordering tiles' starts, with the tile-local prefix sums at its
-// ends (long runs only: the sweep sums those by search).  40 bytes.
+// cut at the ordering tiles' starts.  16 bytes.
 struct TriPiece {
-  int64_t m0, x0;   // prefixes of M and v * M at lo
   int32_t lo, hi;   // positions [lo, hi]
   int32_t info;     // bit 0: child slot; bit 1: summed by search; bits 2..: tile
-  int32_t v0, v1;   // prefixes of v at lo and at hi + 1
   int32_t pad;
 };
 

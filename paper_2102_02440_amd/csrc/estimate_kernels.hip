@@ -1196,11 +1196,26 @@ __device__ __forceinline__ size_t tpre_index(const EstBuffers &B,
   return (slot_row * tiles + tile) * (size_t)(kOrderTile + 1) + q;
 }
 
+// The segment bounds and piece table (tri_seg_block) need the run bounds
+// only, not the ordering: their workgroups ride along as the last
+// n_tri x d workgroups of this launch.
+static_assert(kSegThreads == kOrderThreads, "one launch for both");
+__device__ void tri_seg_block(const TriTask *tasks, const EstBuffers &B,
+                              int task, int row, int32_t *s_ps,
+                              uint32_t *s_wt);
 __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
-    const TriTask *tasks, EstBuffers B, GridMap gm) {
+    const TriTask *tasks, EstBuffers B, GridMap gm, int n_order) {
+  extern __shared__ __align__(16) uint64_t odyn[];  // (kOrderCap + 1) words
+  if ((int)blockIdx.x >= n_order) {
+    __shared__ uint32_t s_wt[kSegThreads / 64];
+    const int b = (int)blockIdx.x - n_order;
+    tri_seg_block(tasks, B, b / B.d, b % B.d, reinterpret_cast<int32_t *>(odyn),
+                  s_wt);
+    return;
+  }
   const GridPos gp = grid_pos(gm);
   if (!gp.ok) return;
-  __shared__ uint64_t okey[kOrderTile];
+  uint64_t *okey = odyn;  // kOrderTile keys
   __shared__ int64_t scm[kOrderThreads / 64], scx[kOrderThreads / 64];
   __shared__ uint32_t scv[kOrderThreads / 64];
   const TriTask &T = tasks[gp.task];
@@ -1336,13 +1351,12 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
 // count, cut at run starts, so that the four sweep segments of a bucket
 // do equal numbers of run pieces.  bounds[k] = first position of group k
 // in ascending position order, bounds[kFastSegs] = L.
-__global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
-    const TriTask *tasks, EstBuffers B) {
-  extern __shared__ int32_t s_ps[];  // piece starts (kOrderCap + 1)
-  __shared__ uint32_t s_wt[kSegThreads / 64];
-  const TriTask &T = tasks[blockIdx.x];
+__device__ void tri_seg_block(const TriTask *tasks, const EstBuffers &B,
+                              int task, int row, int32_t *s_ps,
+                              uint32_t *s_wt) {
+  // s_ps: piece starts (kOrderCap + 1); s_wt: kSegThreads / 64 words
+  const TriTask &T = tasks[task];
   if (T.guard.on != 1 + kTriFast) return;  // another rooting, or path
-  const int row = blockIdx.y;
   const size_t slot_row = (size_t)T.prep_slot * B.d + row;
   const int z = B.prep_z[slot_row];
   const int L = T.L;
@@ -1420,9 +1434,9 @@ __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
   }
   __syncthreads();
   // the pieces: child, summed by search (runs of at least kSearchMin
-  // elements in [z, L)), tile, and the tile-local prefixes at both ends
+  // elements in [z, L)), tile (the sweep reads the prefix sums at a
+  // piece's ends from the ordering's tables, so this needs none of them)
   TriPiece *out = B.tpiece + slot_row * (size_t)B.Pcap;
-  const TriPre *pre0 = B.tpre + tpre_index(B, slot_row, 0, 0);
   for (int i = threadIdx.x; i < P; i += kSegThreads) {
     const int lo = s_ps[i], hi = s_ps[i + 1] - 1;
     const TriElemN e = el[lo];
@@ -1432,16 +1446,7 @@ __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
     o.lo = lo;
     o.hi = hi;
     o.info = (int32_t)((e.kc >> 31) | (lng ? 2u : 0u) | ((uint32_t)tile << 2));
-    o.m0 = o.x0 = 0;
-    o.v0 = o.v1 = o.pad = 0;
-    if (lng) {
-      const int ts = z + tile * kOrderTile;
-      const TriPre a = pre0[(size_t)tile * (kOrderTile + 1) + (lo - ts)];
-      o.m0 = a.m;
-      o.x0 = a.x;
-      o.v0 = a.v;
-      o.v1 = pre0[(size_t)tile * (kOrderTile + 1) + (hi + 1 - ts)].v;
-    }
+    o.pad = 0;
     out[i] = o;
   }
 }
@@ -1457,7 +1462,7 @@ __global__ __launch_bounds__(kSegThreads) void tri_seg_kernel(
 // With nm members running (at most kTriGroupMax), slot s works for member
 // s % nm on segment s / nm of S = kFastSegs / nm segments of the sweep (nm
 // = 3 counts as 4: two slots only search); with K = kFastSegs run groups
-// from tri_seg_kernel, segment g covers the groups [K - (g + 1) K / S,
+// from tri_seg_block, segment g covers the groups [K - (g + 1) K / S,
 // K - g K / S).  Many workgroups of few lanes (128 buckets J each) and
 // more segments keep two workgroups on most CUs and shorten each slot's
 // chain of rounds.  Cutting the descending sweep into
@@ -1659,8 +1664,11 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
     const int pb = __builtin_amdgcn_readfirstlane(sp[kFastSegs - (seg + 1) * gs]);
     const int pe = __builtin_amdgcn_readfirstlane(sp[kFastSegs - seg * gs]);
     ConstPiece *pcs = (ConstPiece *)B.tpiece + slot_row * (size_t)B.Pcap;
-    ConstPiece *mpcs = (ConstPiece *)B.tpiece + my_row * (size_t)B.Pcap;
     const TriPre *mpre = B.tpre + tpre_index(B, my_row, 0, 0);
+    // a piece's ends in the ordering's prefix tables (uniform reads): my
+    // member's sums of M and v M at its start, the sums of v (the same for
+    // every member) at both ends
+    ConstPre *mpre_c = (ConstPre *)B.tpre + tpre_index(B, my_row, 0, 0);
     // my search of round r: piece pe - 1 - (nm r + mi), its lanes' offsets
     // into buffer r & 1
     auto search = [&](int r) {
@@ -1681,19 +1689,34 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
       // during the close of the piece before it
       const int i0 = pe - 1 - nm * r;
       const int nq = working ? min(nm, i0 - pb + 1) : 0;  // my pieces left
-      auto gather = [&](int q, TriPre &e) {
+      // (with them, the uniform prefixes at the piece's ends)
+      struct Ends {
+        int64_t m0, x0;
+        int32_t v0, v1;
+      };
+      auto gather = [&](int q, TriPre &e, Ends &en) {
         e.m = e.x = 0;
         e.v = e.pad = 0;
+        en.m0 = en.x0 = 0;
+        en.v0 = en.v1 = 0;
         if (q >= nq) return;
         const int i = i0 - q;
         const int info = pcs[i].info;
         if (!(info & 2)) return;
         const int tile = info >> 2;
-        const int p = pcs[i].lo + pbuf_at(r & 1, seg * nm + q);
+        const int lo = pcs[i].lo;
+        const int p = lo + pbuf_at(r & 1, seg * nm + q);
         e = mpre[(size_t)tile * (kOrderTile + 1) + (p - z - tile * kOrderTile)];
+        ConstPre *tp = mpre_c + (size_t)tile * (kOrderTile + 1) -
+                       (z + tile * kOrderTile);
+        en.m0 = tp[lo].m;
+        en.x0 = tp[lo].x;
+        en.v0 = tp[lo].v;
+        en.v1 = tp[pcs[i].hi + 1].v;
       };
       TriPre ep;
-      gather(0, ep);
+      Ends en;
+      gather(0, ep, en);
       if (r + 1 < rounds) search(r + 1);
 #pragma unroll
       for (int q = 0; q < kTriGroupMax; ++q) {
@@ -1706,16 +1729,16 @@ __global__ __launch_bounds__(kLaneThreads * kFastSegs, 8) void tri_fast_kernel(
         if (info & 2) {
           const TriPre &e = ep;
           const int p = lo + pbuf_at(r & 1, seg * nm + q);
-          rr.mb = (int64_t)((uint64_t)e.m - (uint64_t)mpcs[i].m0);
-          rr.xb = (int64_t)((uint64_t)e.x - (uint64_t)mpcs[i].x0);
-          rr.vb = (int32_t)((uint32_t)e.v - (uint32_t)pcs[i].v0);
+          rr.mb = (int64_t)((uint64_t)e.m - (uint64_t)en.m0);
+          rr.xb = (int64_t)((uint64_t)e.x - (uint64_t)en.x0);
+          rr.vb = (int32_t)((uint32_t)e.v - (uint32_t)en.v0);
           rr.nb = p - lo;
-          rr.vrun = (int32_t)((uint32_t)pcs[i].v1 - (uint32_t)pcs[i].v0);
+          rr.vrun = (int32_t)((uint32_t)en.v1 - (uint32_t)en.v0);
           rr.nrun = hi - lo + 1;
         } else {
           elements(lo, hi, c, rr);
         }
-        if (q + 1 < kTriGroupMax) gather(q + 1, ep);
+        if (q + 1 < kTriGroupMax) gather(q + 1, ep, en);
         add_piece(c, rr);
       }
     }
@@ -2141,15 +2164,14 @@ hipError_t launch_apex_prep(const NodeTask *tasks, int n, int Lmax_apex,
 hipError_t launch_tri_order(const TriTask *tasks, int n, const EstBuffers &B,
                             hipStream_t st) {
   const int tiles = (std::min(B.Lprep, kOrderCap) + kOrderTile - 1) / kOrderTile;
-  {
-    COMPASS_GRID(tiles, n);
-    hipLaunchKernelGGL(tri_order_kernel, dim3((uint32_t)blocks_),
-                       dim3(kOrderThreads), 0, st, tasks, B, gm_);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(tri_seg_kernel, dim3(n, B.d), dim3(kSegThreads),
-                     (size_t)(kOrderCap + 1) * sizeof(int32_t), st, tasks, B);
+  COMPASS_GRID(tiles, n);
+  // the ordering's keys and the segment blocks' piece starts share the
+  // dynamic LDS
+  static_assert((kOrderCap + 1) * 4 >= kOrderTile * 8, "key stage fits");
+  hipLaunchKernelGGL(tri_order_kernel,
+                     dim3((uint32_t)(blocks_ + (int64_t)n * B.d)),
+                     dim3(kOrderThreads), (size_t)(kOrderCap + 1) * sizeof(int32_t),
+                     st, tasks, B, gm_, (int)blocks_);
   return hipGetLastError();
 }
 
