@@ -825,6 +825,48 @@ def test_approx_when_uncertified_small_values(oracle, shape):
 
 
 @gpu
+@pytest.mark.parametrize("w", [1, 7, 1024, 1025, 8192, 9000, 16384])
+def test_row_sort_extremes(oracle, w):
+    """The per-row radix sort of the estimate path: rows of zeros (no pass),
+    rows with one counter near 2^46 among small ones (12 passes), rows of
+    many equal magnitudes of both signs (ties keep bucket order), ragged
+    row lengths and the largest rows (16 keys a lane).  Sketches are given
+    directly (int64 counters); chain and star sub-plans, plus a triangle at
+    small w, against the oracle."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    rng = np.random.default_rng(4000 + w)
+    n, eu, ev = 4, [0, 1, 2, 0], [1, 2, 0, 3]
+    d = 4
+    sk = []
+    for s in range(2 * len(eu)):
+        x = np.zeros((d, w), dtype=np.int64)
+        x[1] = rng.integers(-50, 51, w)
+        x[1, rng.integers(0, w)] = (1 << 46) - 3
+        x[2] = rng.choice([-3, 3, -2, 2, 0], w)
+        x[3] = rng.integers(-(1 << 20), 1 << 20, w)
+        if s % 3 == 0:
+            x[0] = rng.integers(-5, 6, w)  # one side keeps a live row 0
+        sk.append(x)
+    n_sel = [int(max(np.abs(sk[2 * e + t]).sum(axis=1).max()
+                     for e in range(len(eu)) for t in (0, 1)))] * n
+    dev = [torch.from_numpy(x).cuda() for x in sk]
+    ns = torch.tensor(n_sel, dtype=torch.int64, device="cuda")
+    masks = [0b0011, 0b0110, 0b1001, 0b1011, 0b1101]
+    if w <= 1025:
+        masks += [0b0111, 0b1111]
+    _say("row sort extremes", "w", w, "masks", len(masks))
+    row_est, est, flags = C.estimate(n, eu, ev, d, w, 64, ns, dev, masks)
+    torch.cuda.synchronize()
+    vals_o, est_o, flags_o = oracle.estimate(n, eu, ev, d, w, sk, n_sel, masks)
+    got = C.row_values(row_est)
+    fl = flags.cpu().numpy()
+    for k, m in enumerate(masks):
+        assert not fl[k] & C.FLAG_UNSUPPORTED, hex(m)
+        assert got[k] == [v & ((1 << 128) - 1) for v in vals_o[k]], hex(m)
+
+
+@gpu
 def test_approx_when_values_exceed_128_bits(oracle):
     """Counters of about 2^40 in a four-table chain: row values near 2^160
     wrap modulo 2^128.  The fp64 evaluation's median agrees with the exact
