@@ -19,16 +19,19 @@
 // incident bucket lists merged by kappa and two scans over the merged list.
 //
 // Kernels:
-//  sort_chunk_kernel / sort_merge_kernel
-//                      the w buckets of each (sketch, row) sorted by
-//                      (|v|, j): chunks sorted in LDS, merged by rank.
+//  sort_rows_kernel    the w buckets of each (sketch, row) sorted by
+//                      (|v|, j): an LSD radix sort in LDS, one workgroup a
+//                      row (its trailing workgroups resolve the guards);
 //  node_merge_kernel   k-way merge of a node's sorted lists by rank (binary
 //                      search), many workgroups per (tree node, row);
 //  node_kernel         one workgroup per (tree node, row): block-wide scans
 //                      of 128-bit A and G over the merged records, emitting
 //                      the node's message (or the root's X);
 //  node1_*             nodes with one child (prefix sums + binary search);
-//  tri_lane_kernel     triangles: one lane per bucket J of the cut edge.
+//  apex_prep_kernel, tri_order_kernel (with the segment bounds),
+//  tri_fast_kernel     two-child triangle apexes: run-ordered sweeps by
+//                      binary search, several sub-plans per workgroup;
+//  tri_lane_kernel     other triangles: one lane per bucket J of the cut edge.
 //                      Fixing J turns each cut endpoint's message into
 //                      "M(j) if its parent-edge element ranks below the
 //                      fixed element, else the constant C(J)", so every
