@@ -1190,7 +1190,8 @@ __device__ __forceinline__ void fast_elem(FastRun &r, uint32_t kf, int32_t v,
 // differences of prefix sums.  A run's elements may be reordered freely:
 // within a run the other child's running sum is fixed, so only the run's
 // totals matter.  Keys sort as
-//   (piece start - tile start) << 42 | key << 11 | position - tile start.
+//   (piece start - tile start) << (31 + P) | key << P | position - tile start
+// with P = log2(kOrderTile) bits per position.
 // Lists with L - z > kOrderCap keep the element-wise sweep (its keys would
 // not fit the sweep's LDS stage).
 __device__ __forceinline__ size_t tpre_index(const EstBuffers &B,
@@ -1233,6 +1234,10 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
   if (t0 >= L) return;
   const int nt = min(kOrderTile, L - t0);
   const TriElemN *el = B.prepn + slot_row * (size_t)B.Lprep;
+  constexpr int kPos = __builtin_ctz(kOrderTile);  // position bits
+  constexpr int kR = kOrderTile / kOrderThreads;   // keys a lane sorts
+  constexpr int kMinSort = 64 * kR;                // a wave's key block
+  static_assert(kPos + 31 + kPos <= 64, "sort keys fit 64 bits");
   int n2 = 1;
   while (n2 < nt) n2 <<= 1;
   {
@@ -1249,19 +1254,20 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int q = (int)threadIdx.x + u * kOrderThreads;
-      if (q >= (n2 < 128 ? 128 : n2)) continue;
+      if (q >= (n2 < kMinSort ? kMinSort : n2)) continue;
       uint64_t k = ~0ull;
       if (q < nt) {
         const uint64_t rl = (uint64_t)(max(rlo[u], t0) - t0);
-        k = (rl << 42) | ((uint64_t)(kcs[u] & 0x7FFFFFFFu) << 11) | (uint64_t)q;
+        k = (rl << (31 + kPos)) | ((uint64_t)(kcs[u] & 0x7FFFFFFFu) << kPos) |
+            (uint64_t)q;
       }
       okey[q] = k;
     }
   }
   __syncthreads();
   // padding keys (all ones) sort last
-  bitonic_sort_lds<kOrderThreads, 2>(
-      reinterpret_cast<unsigned long long *>(okey), n2 < 128 ? 128 : n2);
+  bitonic_sort_lds<kOrderThreads, kR>(
+      reinterpret_cast<unsigned long long *>(okey), n2 < kMinSort ? kMinSort : n2);
   // each thread: a consecutive chunk of at most kOrderPer sorted slots;
   // all of its element loads are issued before the sums
   constexpr int kOrderPer = kOrderTile / kOrderThreads;
@@ -1277,11 +1283,11 @@ __global__ __launch_bounds__(kOrderThreads) void tri_order_kernel(
     const int q = q0 + u;
     if (q < q1) {
       const uint64_t k = okey[q];
-      const TriElemN &src = el[t0 + (int)(k & 0x7FF)];
+      const TriElemN &src = el[t0 + (int)(k & (kOrderTile - 1))];
       mu[u] = src.mu;
       vm[u] = src.vm;
       vv[u] = src.v;
-      tk[t0 + q] = (uint32_t)((k >> 11) & 0x7FFFFFFFull);
+      tk[t0 + q] = (uint32_t)((k >> kPos) & 0x7FFFFFFFull);
     }
   }
   uint64_t sm = 0, sx = 0;
