@@ -503,13 +503,39 @@ class DeviceQuery:
         self.n_selected = torch.zeros(len(q.tables), dtype=torch.int64,
                                       device=device)
 
-    def build(self, stream=None):
-        for t, tb in enumerate(self.tables):
-            if not tb["keys"]:
-                continue
-            sketch_build(tb["n"], tb["pred_cols"], tb["preds"], tb["keys"],
-                         tb["seeds"], tb["counters"], self.n_selected[t:t + 1],
-                         self.d, self.w, self.bits, stream=stream)
+    def _build_table(self, t, stream):
+        tb = self.tables[t]
+        sketch_build(tb["n"], tb["pred_cols"], tb["preds"], tb["keys"],
+                     tb["seeds"], tb["counters"], self.n_selected[t:t + 1],
+                     self.d, self.w, self.bits, stream=stream)
+
+    def build(self, stream=None, overlap=True):
+        """Builds every table's sketches on `stream` (the current stream
+        by default); the work is complete on that stream when it returns.
+
+        overlap: tables with predicates (compaction, then hashing of the
+        survivors: short launches bound by their latency) are built on a
+        second stream of the device while the tables without predicates
+        (one fused scan each, bound by the hashing) run on `stream`; the
+        tables share no buffers and the library keeps its scratch per
+        stream.  `stream` then waits for the second stream."""
+        todo = [t for t, tb in enumerate(self.tables) if tb["keys"]]
+        main = stream if stream is not None else torch.cuda.current_stream()
+        side_tabs = [t for t in todo if self.tables[t]["preds"]]
+        if not overlap or not side_tabs or len(side_tabs) == len(todo):
+            for t in todo:
+                self._build_table(t, main)
+            return
+        if getattr(self, "_side", None) is None:
+            self._side = torch.cuda.Stream(device=main.device)  # default priority
+        side = self._side
+        side.wait_stream(main)
+        for t in side_tabs:
+            self._build_table(t, side)
+        for t in todo:
+            if t not in side_tabs:
+                self._build_table(t, main)
+        main.wait_stream(side)
 
     def estimate(self, masks, stream=None):
         return estimate(len(self.q.tables), self.q.edge_u, self.q.edge_v,

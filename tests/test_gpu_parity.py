@@ -108,6 +108,36 @@ def test_job6a_scaled(oracle):
 
 
 @gpu
+def test_build_overlap_matches_one_stream(oracle):
+    """Tables with predicates built on a second stream (the default) give
+    the oracle's counters and selected counts, as every table on one
+    stream does; also on a caller's own stream, and with the counters
+    dirtied between the builds (each build overwrites them)."""
+    torch = _torch()
+    from paper_2102_02440_amd import compass as C
+    q = W.job6a(seed=11, scale=0.01, d=7, w=1024)
+    _say("build overlap", "tables", [tb.n_rows for tb in q.tables])
+    assert any(tb.preds for tb in q.tables) and not all(tb.preds for tb in q.tables)
+    side_sk, n_sel = oracle_query(oracle, q)
+    dq = C.DeviceQuery(q)
+    user = torch.cuda.Stream()
+    for overlap, stream in [(False, None), (True, None), (True, user), (False, user)]:
+        for c in dq.sketch_of_side:
+            c.fill_(7)
+        dq.n_selected.fill_(-1)
+        torch.cuda.synchronize()
+        if stream is None:
+            dq.build(overlap=overlap)
+        else:
+            with torch.cuda.stream(stream):
+                dq.build(stream=stream, overlap=overlap)
+        torch.cuda.synchronize()
+        assert dq.n_selected.cpu().tolist() == n_sel, (overlap, stream)
+        for s, (g, o) in enumerate(zip(dq.sketch_of_side, side_sk)):
+            assert np.array_equal(g.cpu().numpy().astype(np.int64), o), (overlap, s)
+
+
+@gpu
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("cyclic", [False, True])
 def test_random_queries(oracle, seed, cyclic):
